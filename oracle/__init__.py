@@ -1,0 +1,237 @@
+"""ctypes binding of the CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+The oracle is a plain scalar C++ implementation of the WENOIU method written
+from the paper (see ``wenoiu_oracle.hpp``).  Only the test suite, the smoke
+check and the CPU-baseline leg of the benchmark may use it; the product path
+(the HIP library and its Python binding) never imports this package.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+SCHEMES = {"3-1MP": 0, "3-2MP": 1, "5-1MP": 2, "5-2MP": 3}
+BC = {"periodic": 0, "transmissive": 1}
+G = 4  # metric ghost band
+
+_D = ctypes.c_double
+_I = ctypes.c_int
+_P = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = ctypes.CDLL(path)
+        L.orc_weno.restype = _D
+        L.orc_weno.argtypes = [_I, _P, _D, _I]
+        L.orc_ppm.restype = _D
+        L.orc_ppm.argtypes = [_I, _D, _D]
+        L.orc_is.restype = _D
+        L.orc_is.argtypes = [_I, _D, _D, _D]
+        L.orc_hplus.restype = _D
+        L.orc_hplus.argtypes = [_I, _P, _P]
+        L.orc_delta_c.restype = _D
+        L.orc_delta_c.argtypes = [_I, _P, _P]
+        L.orc_interp_mid.restype = _D
+        L.orc_interp_mid.argtypes = [_P]
+        L.orc_metric_derivative.restype = _D
+        L.orc_metric_derivative.argtypes = [_I, _P]
+        L.orc_eigenvectors.restype = None
+        L.orc_eigenvectors.argtypes = [_P, _D, _D, _D, _P, _P]
+        L.orc_flux_hat.restype = None
+        L.orc_flux_hat.argtypes = [_P, _D, _D, _D, _P]
+        L.orc_midpoint_flux.restype = _I
+        L.orc_midpoint_flux.argtypes = [_I, _D, _D, _I, _P, _P, _P, _P, _D, _P, _P]
+        L.orc_metrics_size.restype = ctypes.c_longlong
+        L.orc_metrics_size.argtypes = [_I, _I]
+        L.orc_metrics.restype = _I
+        L.orc_metrics.argtypes = [_I, _I, _I, _I, _I, _D, _D, _P, _P, _P]
+        L.orc_rhs.restype = _I
+        L.orc_rhs.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _P, _P, _P]
+        L.orc_cfl_dt.restype = _D
+        L.orc_cfl_dt.argtypes = [_I, _I, _D, _P, _P, _D]
+        L.orc_rk3_step.restype = _I
+        L.orc_rk3_step.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _D]
+        L.orc_rk3_run.restype = _I
+        L.orc_rk3_run.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _D, _I]
+        L.orc_adv1d_rhs.restype = None
+        L.orc_adv1d_rhs.argtypes = [_I, _I, _D, _I, _D, _D, _I, _P, _P]
+        L.orc_adv1d_run.restype = _I
+        L.orc_adv1d_run.argtypes = [_I, _I, _I, _D, _D, _I, _D, _P, _P]
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [_I]
+        L.orc_get_threads.restype = _I
+        L.orc_get_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def scheme_id(s):
+    return SCHEMES[s] if isinstance(s, str) else int(s)
+
+
+def bc_id(b):
+    return BC[b] if isinstance(b, str) else int(b)
+
+
+def set_threads(n):
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return lib().orc_get_threads()
+
+
+# ---- component probes ------------------------------------------------------------
+
+def weno(r, v, eps=1e-40, ppm=1):
+    v = _f64(v)
+    return lib().orc_weno(r, _ptr(v), eps, ppm)
+
+
+def ppm(order, w, C):
+    return lib().orc_ppm(order, w, C)
+
+
+def smoothness(k, a, b, c):
+    return lib().orc_is(k, a, b, c)
+
+
+def hplus(scheme, f, F):
+    """h^+_{i+1/2}; f = f_{i-3..i+3} (7 values), F = f_{i-3/2..i+3/2} (4 values)."""
+    f, F = _f64(f), _f64(F)
+    return lib().orc_hplus(scheme_id(scheme), _ptr(f), _ptr(F))
+
+
+def delta_c(scheme, g, gm):
+    """delta^{c,(1)} at i; g = g_{i-4..i+4} (9), gm = g_{i-7/2..i+7/2} (8)."""
+    g, gm = _f64(g), _f64(gm)
+    return lib().orc_delta_c(scheme_id(scheme), _ptr(g), _ptr(gm))
+
+
+def interp_mid(g):
+    g = _f64(g)
+    return lib().orc_interp_mid(_ptr(g))
+
+
+def metric_derivative(scheme, r):
+    r = _f64(r)
+    return lib().orc_metric_derivative(scheme_id(scheme), _ptr(r))
+
+
+def eigenvectors(Q, gamma, nx, ny):
+    Q = _f64(Q)
+    L = np.zeros((4, 4))
+    R = np.zeros((4, 4))
+    lib().orc_eigenvectors(_ptr(Q), gamma, nx, ny, _ptr(L), _ptr(R))
+    return L, R
+
+
+def flux_hat(Q, gamma, kx, ky):
+    Q = _f64(Q)
+    out = np.zeros(4)
+    lib().orc_flux_hat(_ptr(Q), gamma, kx, ky, _ptr(out))
+    return out
+
+
+def midpoint_flux(scheme, Qs, k0, k1, mk, lam, gamma=1.4, eps=1e-40, ppm=1):
+    Qs, k0, k1, mk = _f64(Qs), _f64(k0), _f64(k1), _f64(mk)
+    Fp, Fm = np.zeros(4), np.zeros(4)
+    rc = lib().orc_midpoint_flux(scheme_id(scheme), gamma, eps, ppm, _ptr(Qs), _ptr(k0), _ptr(k1),
+                                 _ptr(mk), lam, _ptr(Fp), _ptr(Fm))
+    assert rc == 0
+    return Fp, Fm
+
+
+# ---- 2-D Euler ----------------------------------------------------------------------
+
+def metrics(scheme, x, y, bc=("periodic", "periodic"), period=(0.0, 0.0)):
+    """Nine metric planes with the ghost band: shape (9, ny+2G, nx+2G)."""
+    x, y = _f64(x), _f64(y)
+    ny, nx = x.shape
+    M = np.zeros((9, ny + 2 * G, nx + 2 * G))
+    rc = lib().orc_metrics(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), float(period[0]),
+                           float(period[1]), _ptr(x), _ptr(y), _ptr(M))
+    if rc:
+        raise ValueError("orc_metrics failed")
+    return M
+
+
+def rhs(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1,
+        return_lambda=False):
+    U, M = _f64(U), _f64(M)
+    _, ny, nx = U.shape
+    out = np.zeros_like(U)
+    lx = np.zeros(ny)
+    le = np.zeros(nx)
+    rc = lib().orc_rhs(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+                       _ptr(U), _ptr(M), _ptr(out), _ptr(lx), _ptr(le))
+    if rc:
+        raise ValueError("orc_rhs failed")
+    if return_lambda:
+        return out, lx, le
+    return out
+
+
+def cfl_dt(U, M, cfl, gamma=1.4):
+    U, M = _f64(U), _f64(M)
+    _, ny, nx = U.shape
+    return lib().orc_cfl_dt(nx, ny, gamma, _ptr(U), _ptr(M), cfl)
+
+
+def rk3_step(scheme, U, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+    U = np.array(U, dtype=np.float64, copy=True, order="C")
+    M = _f64(M)
+    _, ny, nx = U.shape
+    rc = lib().orc_rk3_step(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+                            _ptr(U), _ptr(M), dt)
+    if rc:
+        raise ValueError("orc_rk3_step failed")
+    return U
+
+
+def rk3_run(scheme, U, M, dt, nsteps, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+    U = np.array(U, dtype=np.float64, copy=True, order="C")
+    M = _f64(M)
+    _, ny, nx = U.shape
+    rc = lib().orc_rk3_run(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+                           _ptr(U), _ptr(M), dt, int(nsteps))
+    if rc:
+        raise ValueError("orc_rk3_run failed")
+    return U
+
+
+# ---- Sec. 5.1 scalar advection ------------------------------------------------------------
+
+def adv1d_rhs(scheme, u, dx, split=0, alpha=1.1, eps=1e-40, ppm=1):
+    u = _f64(u)
+    out = np.zeros_like(u)
+    lib().orc_adv1d_rhs(scheme_id(scheme), u.size, dx, split, alpha, eps, ppm, _ptr(u), _ptr(out))
+    return out
+
+
+def adv1d_run(scheme, N, split=0, alpha=1.1, eps=1e-40, ppm=1, tend=2.0):
+    l2 = ctypes.c_double()
+    li = ctypes.c_double()
+    rc = lib().orc_adv1d_run(scheme_id(scheme), N, split, alpha, eps, ppm, tend, ctypes.byref(l2),
+                             ctypes.byref(li))
+    if rc:
+        raise ValueError("orc_adv1d_run failed")
+    return l2.value, li.value

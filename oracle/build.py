@@ -1,0 +1,29 @@
+"""Build the CPU oracle (test infrastructure only).
+
+Compiles ``wenoiu_oracle.cpp`` with g++ into ``liboracle.so`` beside it:
+plain C++17, -O2, no floating-point contraction and no fast-math, OpenMP
+over independent grid lines only.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "wenoiu_oracle.cpp")
+HDR = os.path.join(HERE, "wenoiu_oracle.hpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(force=True):
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(
+            os.path.getmtime(SRC), os.path.getmtime(HDR)):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas", "-o", tmp, SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())

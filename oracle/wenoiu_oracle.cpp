@@ -1,0 +1,232 @@
+// ---------------------------------------------------------------------------
+// WENOIU reference oracle: C entry points -- TEST INFRASTRUCTURE ONLY.
+// Called from the test suite, the smoke check and the CPU-baseline leg of the
+// benchmark through ctypes.  Arrays are host memory, fp64, row-major with the
+// i (xi) index fastest; conservative states are [4][ny][nx] = rho, rho u,
+// rho v, e.  Metric arrays follow the layout documented in the header.
+// ---------------------------------------------------------------------------
+#include "wenoiu_oracle.hpp"
+
+#include <cstring>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+using namespace orc;
+
+namespace {
+
+Grid make_grid(int nx, int ny, int bcx, int bcy, double Lx, double Ly) {
+  Grid g;
+  g.nx = nx; g.ny = ny; g.bcx = (Bc)bcx; g.bcy = (Bc)bcy; g.Lx = Lx; g.Ly = Ly;
+  return g;
+}
+
+Params make_params(double gamma, double alpha, double eps, int ppm) {
+  Params p;
+  p.gamma = gamma; p.alpha_lf = alpha; p.eps = eps; p.ppm = ppm;
+  return p;
+}
+
+bool bad_scheme(int s) { return s < 0 || s > 3; }
+
+}  // namespace
+
+extern "C" {
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
+int orc_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+// ---- component probes (used to pin the pieces against the paper) ----------
+
+// WENO interpolation to k+1/2.  r = 3: v[0..4] = v_{k-2..k+2}; r = 2:
+// v[0..3] = v_{k-2..k+1}.
+double orc_weno(int r, const double* v, double eps, int ppm) {
+  Params p = make_params(1.4, 1.1, eps, ppm);
+  if (r == 3) return weno_r3(v, p);
+  return weno_r2(v, p);
+}
+
+double orc_ppm(int order, double w, double C) { return order == 3 ? ppm3(w, C) : ppm2(w, C); }
+
+double orc_is(int k, double a, double b, double c) {
+  return k == 0 ? is_left(a, b, c) : (k == 1 ? is_mid(a, b, c) : is_right(a, b, c));
+}
+
+// h^+_{i+1/2} with nodal f[0..6] = f_{i-3..i+3} and midpoint F[0..3] = f_{i-3/2}, f_{i-1/2}, f_{i+1/2}, f_{i+3/2}.
+double orc_hplus(int scheme, const double* f, const double* F) {
+  auto fn = [&](int m) { return f[m + 3]; };
+  auto Fm = [&](int m) { return F[m + 2]; };
+  return h_plus<double>((Scheme)scheme, fn, Fm);
+}
+
+// delta^{c,(1)} at node i with nodal g[0..8] = g_{i-4..i+4} and midpoint
+// gm[0..7] = g_{i-7/2}, ..., g_{i+7/2}.
+double orc_delta_c(int scheme, const double* g, const double* gm) {
+  auto gn = [&](int m) { return g[m + 4]; };
+  auto gmm = [&](int m) { return gm[m + 4]; };
+  return delta_c((Scheme)scheme, gn, gmm);
+}
+
+// Midpoint interpolation from g[0..5] = g_{i-2..i+3}.
+double orc_interp_mid(const double* g) {
+  return interp_mid([&](int l) { return g[l + 2]; });
+}
+
+// The combined metric operator on relative values r[0..16] = g_{i-8..i+8} - g_i.
+double orc_metric_derivative(int scheme, const double* r) { return metric_derivative((Scheme)scheme, r); }
+
+void orc_eigenvectors(const double* Q, double gamma, double nx, double ny, double* L, double* R) {
+  double LL[4][4], RR[4][4];
+  eigenvectors(Q, gamma, nx, ny, LL, RR);
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) { L[a * 4 + b] = LL[a][b]; R[a * 4 + b] = RR[a][b]; }
+}
+
+void orc_flux_hat(const double* Q, double gamma, double kx, double ky, double* out) {
+  flux_hat(Q, gamma, kx, ky, out);
+}
+
+// Midpoint split fluxes: Qs[6][4] = Q_{k-2..k+3}; k0 = (kx,ky) at k, k1 at k+1,
+// mk = midpoint metric; lam = line eigenvalue.
+int orc_midpoint_flux(int scheme, double gamma, double eps, int ppm, const double* Qs, const double* k0,
+                      const double* k1, const double* mk, double lam, double* Fp, double* Fm) {
+  if (bad_scheme(scheme)) return -1;
+  Params p = make_params(gamma, 1.1, eps, ppm);
+  double QQ[6][4];
+  std::memcpy(QQ, Qs, sizeof(QQ));
+  midpoint_flux((Scheme)scheme, p, QQ, k0[0], k0[1], k1[0], k1[1], mk[0], mk[1], lam, Fp, Fm);
+  return 0;
+}
+
+// ---- 2-D Euler ----------------------------------------------------------------
+
+long long orc_metrics_size(int nx, int ny) { return 9LL * (nx + 2 * G) * (ny + 2 * G); }
+int orc_ghost(void) { return G; }
+
+int orc_metrics(int scheme, int nx, int ny, int bcx, int bcy, double Lx, double Ly, const double* x,
+                const double* y, double* M) {
+  if (bad_scheme(scheme) || nx < 1 || ny < 1) return -1;
+  if ((bcx == TRANSMISSIVE && nx < 2) || (bcy == TRANSMISSIVE && ny < 2)) return -1;
+  Grid g = make_grid(nx, ny, bcx, bcy, Lx, Ly);
+  compute_metrics((Scheme)scheme, g, x, y, M);
+  return 0;
+}
+
+int orc_rhs(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm,
+            const double* U, const double* M, double* dUdt, double* lam_xi, double* lam_eta) {
+  if (bad_scheme(scheme) || nx < 1 || ny < 1) return -1;
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Params p = make_params(gamma, alpha, eps, ppm);
+  rhs<double>((Scheme)scheme, p, g, U, M, dUdt, lam_xi, lam_eta);
+  return 0;
+}
+
+double orc_cfl_dt(int nx, int ny, double gamma, const double* U, const double* M, double cfl) {
+  Grid g = make_grid(nx, ny, 0, 0, 0.0, 0.0);
+  Params p = make_params(gamma, 1.1, 1e-40, 1);
+  return cfl_dt(p, g, U, M, cfl);
+}
+
+int orc_rk3_step(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm,
+                 double* U, const double* M, double dt) {
+  if (bad_scheme(scheme) || nx < 1 || ny < 1) return -1;
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Params p = make_params(gamma, alpha, eps, ppm);
+  rk3_step<double>((Scheme)scheme, p, g, U, M, dt);
+  return 0;
+}
+
+// Run nsteps TVD-RK3 steps at fixed dt.
+int orc_rk3_run(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm,
+                double* U, const double* M, double dt, int nsteps) {
+  for (int s = 0; s < nsteps; ++s) {
+    int rc = orc_rk3_step(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, U, M, dt);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+// ---- Sec. 5.1: scalar linear advection u_t + u_x = 0 ---------------------------
+// Semi-discrete WENOIU operator on a periodic uniform grid of N points with
+// spacing dx (Eq. 3.2).  split = 0: upwind split f+ = u, f- = 0;
+// split = 1: Lax-Friedrichs split f+- = (u +- alpha u)/2.  Midpoint values
+// interpolate u and form the flux from it (Sec. 2.4).
+void orc_adv1d_rhs(int scheme, int N, double dx, int split, double alpha, double eps, int ppm, const double* u,
+                   double* dudt) {
+  Params p = make_params(1.4, alpha, eps, ppm);
+  Scheme sc = (Scheme)scheme;
+  auto U = [&](int k) { return u[wrap(k, N)]; };
+  double cp = split == 0 ? 1.0 : 0.5 * (1.0 + alpha);
+  double cm = split == 0 ? 0.0 : 0.5 * (1.0 - alpha);
+  std::vector<double> H(N + 1);
+  for (int i = -1; i < N; ++i) {
+    auto fp = [&](int m) { return cp * U(i + m); };
+    auto fm = [&](int m) { return cm * U(i + 1 - m); };
+    auto Fp = [&](int m) {  // f^+ at i+1/2+m
+      int k = i + m;
+      double s[6];
+      for (int l = 0; l < 6; ++l) s[l] = U(k - 2 + l);
+      return cp * weno_left(sc, s, p);
+    };
+    auto Fm = [&](int m) {  // f^- at i+1/2-m
+      int k = i - m;
+      double s[6];
+      for (int l = 0; l < 6; ++l) s[l] = U(k - 2 + l);
+      return cm * weno_right(sc, s, p);
+    };
+    H[i + 1] = h_plus<double>(sc, fp, Fp) + h_plus<double>(sc, fm, Fm);
+  }
+  for (int k = 0; k < N; ++k) dudt[k] = -(H[k + 1] - H[k]) / dx;
+}
+
+// Table 3 experiment: u0 = sin(pi x - sin(pi x)/pi) on [-1, 1), classical RK4
+// with dt = dx^{5/4} (shortened to land on tend), errors against the exact
+// translated solution.
+int orc_adv1d_run(int scheme, int N, int split, double alpha, double eps, int ppm, double tend, double* l2,
+                  double* linf) {
+  if (bad_scheme(scheme) || N < 8) return -1;
+  const double PI = 3.14159265358979323846;
+  double dx = 2.0 / N;
+  auto u0 = [&](double x) { return std::sin(PI * x - std::sin(PI * x) / PI); };
+  std::vector<double> u(N), k1(N), k2(N), k3(N), k4(N), tmp(N);
+  for (int i = 0; i < N; ++i) u[i] = u0(-1.0 + i * dx);
+  int nsteps = (int)std::ceil(tend / std::pow(dx, 1.25) - 1e-12);
+  double dt = tend / nsteps;
+  for (int s = 0; s < nsteps; ++s) {
+    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, u.data(), k1.data());
+    for (int i = 0; i < N; ++i) tmp[i] = u[i] + 0.5 * dt * k1[i];
+    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, tmp.data(), k2.data());
+    for (int i = 0; i < N; ++i) tmp[i] = u[i] + 0.5 * dt * k2[i];
+    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, tmp.data(), k3.data());
+    for (int i = 0; i < N; ++i) tmp[i] = u[i] + dt * k3[i];
+    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, tmp.data(), k4.data());
+    for (int i = 0; i < N; ++i) u[i] += dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+  }
+  double s2 = 0.0, smax = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double x = -1.0 + i * dx - tend;
+    x = x - 2.0 * std::floor((x + 1.0) / 2.0);
+    double e = u[i] - u0(x);
+    s2 += e * e;
+    smax = std::max(smax, std::fabs(e));
+  }
+  *l2 = std::sqrt(s2 / N);
+  *linf = smax;
+  return 0;
+}
+
+}  // extern "C"

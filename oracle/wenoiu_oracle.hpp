@@ -1,0 +1,599 @@
+// ---------------------------------------------------------------------------
+// WENOIU reference oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, scalar CPU implementation of the WENO interpolation-based,
+// upwind-biased (WENOIU) schemes of Li & Sun, "WENO interpolation-based and
+// upwind-biased schemes with free-stream preservation" (arXiv 1810.11103),
+// applied to the 2-D Euler equations in curvilinear coordinates.
+//
+// Only the test suite, the smoke check and the CPU-baseline leg of the
+// benchmark may call this code.  It shares no source with the HIP library and
+// must never be used as a fallback for it.  Every step follows the paper's
+// order; where the paper is silent the reading adopted is stated at the spot.
+//
+// Everything is templated on the scalar type T of the flow state so that the
+// same code yields forward values (T = double), tangents (dual numbers) and
+// adjoints (a tape).  Grid coordinates and metrics are plain doubles.
+// ---------------------------------------------------------------------------
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+#include <algorithm>
+
+namespace orc {
+
+enum Scheme { W3_1MP = 0, W3_2MP = 1, W5_1MP = 2, W5_2MP = 3 };
+enum Bc { PERIODIC = 0, TRANSMISSIVE = 1 };
+
+// Width of the metric ghost band stored around the grid (each side).
+constexpr int G = 4;
+
+struct Params {
+  double gamma = 1.4;     // ratio of specific heats (Sec. 6.3(1))
+  double alpha_lf = 1.1;  // alpha of the Lax-Friedrichs eigenvalue, 1.1-1.2 (Sec. 2.3)
+  double eps = 1e-40;     // WENO epsilon when the PPM mapping is used (Sec. 3.2(3))
+  int ppm = 1;            // apply the piecewise-polynomial mapping (Eqs. 3.15/3.23)
+};
+
+inline bool fifth_order(Scheme s) { return s == W5_1MP || s == W5_2MP; }
+inline bool two_midpoints(Scheme s) { return s == W3_2MP || s == W5_2MP; }
+
+// Overloads that AD scalar types also provide.
+using std::sqrt;
+using std::fabs;
+
+// ===========================================================================
+// Sec. 3.2(3), Eqs. 3.10-3.15 and Sec. 3.3(3), Eqs. 3.22-3.23, Table 1:
+// WENO interpolation of a nodal sequence to the midpoint x_{k+1/2}.
+// ===========================================================================
+
+// Smoothness indicators of Eq. 3.22 on the three-point stencil (a, b, c).
+// Eq. 3.22 prints them as quadratic forms; the same forms written as sums of
+// squares (the Jiang-Shu indicators, 13/12 (a-2b+c)^2 + 1/4 (...)^2) are used
+// here because they cannot turn negative through rounding.  The equality of
+// the two is checked by the test suite against the printed coefficients.
+template <class T> T is_left(const T& a, const T& b, const T& c) {   // IS_0
+  T d2 = a - 2.0 * b + c, d1 = a - 4.0 * b + 3.0 * c;
+  return (13.0 / 12.0) * d2 * d2 + 0.25 * d1 * d1;
+}
+template <class T> T is_mid(const T& a, const T& b, const T& c) {    // IS_1
+  T d2 = a - 2.0 * b + c, d1 = a - c;
+  return (13.0 / 12.0) * d2 * d2 + 0.25 * d1 * d1;
+}
+template <class T> T is_right(const T& a, const T& b, const T& c) {  // IS_2
+  T d2 = a - 2.0 * b + c, d1 = 3.0 * a - 4.0 * b + c;
+  return (13.0 / 12.0) * d2 * d2 + 0.25 * d1 * d1;
+}
+
+// Second-order piecewise-polynomial mapping, Eq. 3.15.
+template <class T> T ppm2(const T& w, double C) {
+  if (w <= C) { T t = w / C - 1.0; return C * (1.0 - t * t); }
+  T d = w - C;
+  return C - d * d / (C - 1.0);
+}
+// Third-order piecewise-polynomial mapping, Eq. 3.23.
+template <class T> T ppm3(const T& w, double C) {
+  if (w <= C) { T t = w / C - 1.0; return C * (1.0 + t * t * t); }
+  T d = w - C;
+  return C + d * d * d / ((C - 1.0) * (C - 1.0));
+}
+
+// r = 3 (fifth-order schemes).  v[0..4] = v_{k-2}, ..., v_{k+2}; returns the
+// left-biased value at k+1/2.  Candidates p_k^3 from Eq. 3.11 with the b_{k,l}
+// of Table 1, linear weights C = (1, 10, 5)/16, weights Eqs. 3.12-3.13,
+// indicators Eq. 3.22, mapping Eq. 3.23 followed by re-normalisation.
+template <class T> T weno_r3(const T v[5], const Params& pr) {
+  const double C[3] = {1.0 / 16.0, 10.0 / 16.0, 5.0 / 16.0};
+  T p[3];
+  p[0] = (3.0 / 8.0) * v[0] - (10.0 / 8.0) * v[1] + (15.0 / 8.0) * v[2];
+  p[1] = (-1.0 / 8.0) * v[1] + (6.0 / 8.0) * v[2] + (3.0 / 8.0) * v[3];
+  p[2] = (3.0 / 8.0) * v[2] + (6.0 / 8.0) * v[3] - (1.0 / 8.0) * v[4];
+  T IS[3] = {is_left(v[0], v[1], v[2]), is_mid(v[1], v[2], v[3]), is_right(v[2], v[3], v[4])};
+  T a[3], sa = T(0.0);
+  for (int k = 0; k < 3; ++k) { T d = pr.eps + IS[k]; a[k] = C[k] / (d * d); sa = sa + a[k]; }
+  T w[3];
+  for (int k = 0; k < 3; ++k) w[k] = a[k] / sa;
+  if (pr.ppm) {
+    T g[3], sg = T(0.0);
+    for (int k = 0; k < 3; ++k) { g[k] = ppm3(w[k], C[k]); sg = sg + g[k]; }
+    for (int k = 0; k < 3; ++k) w[k] = g[k] / sg;
+  }
+  return w[0] * p[0] + w[1] * p[1] + w[2] * p[2];
+}
+
+// r = 2 (third-order schemes).  v[0..3] = v_{k-2}, ..., v_{k+1}.  Candidates
+// from Table 1 (C = (1, 3)/4); the indicators are IS_0 and IS_1 of Eq. 3.22 on
+// the three-point stencils {k-2,k-1,k} and {k-1,k,k+1} in place of Eq. 3.14,
+// as Sec. 5.1 prescribes for the third-order schemes; mapping Eq. 3.15.
+template <class T> T weno_r2(const T v[4], const Params& pr) {
+  const double C[2] = {1.0 / 4.0, 3.0 / 4.0};
+  T p[2];
+  p[0] = (-1.0 / 2.0) * v[1] + (3.0 / 2.0) * v[2];
+  p[1] = (1.0 / 2.0) * v[2] + (1.0 / 2.0) * v[3];
+  T IS[2] = {is_left(v[0], v[1], v[2]), is_mid(v[1], v[2], v[3])};
+  T a[2], sa = T(0.0);
+  for (int k = 0; k < 2; ++k) { T d = pr.eps + IS[k]; a[k] = C[k] / (d * d); sa = sa + a[k]; }
+  T w[2];
+  for (int k = 0; k < 2; ++k) w[k] = a[k] / sa;
+  if (pr.ppm) {
+    T g[2], sg = T(0.0);
+    for (int k = 0; k < 2; ++k) { g[k] = ppm2(w[k], C[k]); sg = sg + g[k]; }
+    for (int k = 0; k < 2; ++k) w[k] = g[k] / sg;
+  }
+  return w[0] * p[0] + w[1] * p[1];
+}
+
+// Left-biased value at k+1/2 from the window s[0..5] = v_{k-2..k+3}.
+template <class T> T weno_left(Scheme sc, const T s[6], const Params& pr) {
+  if (fifth_order(sc)) return weno_r3(s, pr);
+  return weno_r2(s, pr);
+}
+// Right-biased value at k+1/2: the same interpolation applied to the sequence
+// mirrored about k+1/2, i.e. v_{k+3}, v_{k+2}, ..., v_{k-2}.
+template <class T> T weno_right(Scheme sc, const T s[6], const Params& pr) {
+  T m[6] = {s[5], s[4], s[3], s[2], s[1], s[0]};
+  if (fifth_order(sc)) return weno_r3(m, pr);
+  return weno_r2(m, pr);
+}
+
+// ===========================================================================
+// Sec. 3.2 / 3.3: upwind-biased numerical flux h^+_{i+1/2} from nodal values
+// f(m) = f_{i+m} and midpoint values F(m) = f_{i+1/2+m}, with alpha = 1
+// (the only member of the families 3.5 / 3.17 that the paper tests).
+// ===========================================================================
+template <class T, class NodeF, class MidF>
+T h_plus(Scheme sc, NodeF f, MidF F) {
+  switch (sc) {
+    case W3_1MP:  // Eq. 3.4
+      return F(0) + (1.0 / 24.0) * (-f(-1) + 2.0 * f(0) - f(1));
+    case W3_2MP:  // Eq. 3.8
+      return F(0) + (1.0 / 6.0) * (-F(-1) + 2.0 * f(0) - F(0));
+    case W5_1MP:  // Eq. 3.16
+      return F(0) + (19.0 / 1920.0) * f(-2) - (29.0 / 480.0) * f(-1) + (77.0 / 960.0) * f(0) -
+             (3.0 / 160.0) * f(1) - (7.0 / 640.0) * f(2);
+    case W5_2MP:  // Eq. 3.20
+    default:
+      return F(0) + (1.0 / 30.0) * ((-4.0 * f(1) + f(0) + f(-1)) + (6.0 * F(0) - 4.0 * F(-1)));
+  }
+}
+
+// ===========================================================================
+// Sec. 2.3, Eq. 2.7 and Eqs. 3.7, 3.9, 3.19, 3.21: the central operator
+// delta^{c,(1)} of each scheme, used for the grid metrics.  g(m) = g_{i+m} at
+// nodes, gm(m) = g_{i+1/2+m} at midpoints (so g_{i-1/2} = gm(-1)).
+// ===========================================================================
+template <class NodeF, class MidF>
+double delta_c(Scheme sc, NodeF g, MidF gm) {
+  switch (sc) {
+    case W3_1MP:  // Eq. 3.7
+      return (gm(0) - gm(-1)) + (1.0 / 48.0) * (-g(2) + 2.0 * g(1) - 2.0 * g(-1) + g(-2));
+    case W3_2MP:  // Eq. 3.9
+      return (1.0 / 12.0) * (2.0 * (g(1) - g(-1)) + (-gm(1) + 11.0 * gm(0) - 11.0 * gm(-1) + gm(-2)));
+    case W5_1MP:  // Eq. 3.19
+      return (gm(0) - gm(-1)) + (19.0 / 3840.0) * (g(3) - g(-3)) - (13.0 / 320.0) * (g(2) - g(-2)) +
+             (17.0 / 256.0) * (g(1) - g(-1));
+    case W5_2MP:  // Eq. 3.21 (its "f_{i+2}" is f_{j+2})
+    default:
+      return (1.0 / 60.0) * (g(2) - 4.0 * g(1) + 4.0 * g(-1) - g(-2)) +
+             (1.0 / 15.0) * (-gm(1) + 19.0 * gm(0) - 19.0 * gm(-1) + gm(-2));
+  }
+}
+
+// Linear interpolation to the midpoint g_{i+1/2} from g_{i-2..i+3}.  The paper
+// asks only for a "directionally consistent" linear interpolation, the same in
+// the metrics and in the midpoint fluxes (Sec. 2.4); the six-point central
+// (sixth-order Lagrange) interpolation is the reading adopted here.
+template <class NodeF> double interp_mid(NodeF g) {
+  return (3.0 * g(-2) - 25.0 * g(-1) + 150.0 * g(0) + 150.0 * g(1) - 25.0 * g(2) + 3.0 * g(3)) / 256.0;
+}
+
+// The scheme's metric derivative at a node, evaluated on the local relative
+// values r[m + 8] = g_{i+m} - g_i, m = -8..8 (the operator annihilates
+// constants, so subtracting g_i changes nothing but the rounding).
+inline double metric_derivative(Scheme sc, const double r[17]) {
+  auto g = [&](int m) { return r[m + 8]; };
+  auto gm = [&](int m) {  // g_{i+1/2+m}
+    return interp_mid([&](int l) { return r[m + l + 8]; });
+  };
+  return delta_c(sc, g, gm);
+}
+
+// ===========================================================================
+// Grid description and coordinate extension.
+// ===========================================================================
+struct Grid {
+  int nx, ny;
+  Bc bcx, bcy;
+  double Lx, Ly;  // period lengths of periodic directions
+};
+
+inline int wrap(int a, int n) { int r = a % n; return r < 0 ? r + n : r; }
+inline int floordiv(int a, int n) { return (a - wrap(a, n)) / n; }
+
+// Extended coordinates X(a, b) for any integer (a, b), in extended precision.
+// Periodic directions repeat the grid shifted by the period; transmissive
+// directions extend it linearly from the last two nodes.  (The paper states
+// no boundary rule; this is the reading adopted here.)
+struct Coords {
+  const Grid& g;
+  const double* x;
+  const double* y;
+  void row(int a, int jr, long double& X, long double& Y) const {  // jr in [0, ny)
+    if (g.bcx == PERIODIC) {
+      int ar = wrap(a, g.nx), k = floordiv(a, g.nx);
+      X = (long double)x[(size_t)jr * g.nx + ar] + (long double)k * (long double)g.Lx;
+      Y = (long double)y[(size_t)jr * g.nx + ar];
+      return;
+    }
+    auto at = [&](int i, long double& XX, long double& YY) {
+      XX = x[(size_t)jr * g.nx + i]; YY = y[(size_t)jr * g.nx + i];
+    };
+    long double X0, Y0, X1, Y1;
+    if (a < 0) {
+      at(0, X0, Y0); at(1, X1, Y1);
+      X = X0 + (long double)a * (X1 - X0); Y = Y0 + (long double)a * (Y1 - Y0);
+    } else if (a >= g.nx) {
+      at(g.nx - 1, X0, Y0); at(g.nx - 2, X1, Y1);
+      long double s = (long double)(a - g.nx + 1);
+      X = X0 + s * (X0 - X1); Y = Y0 + s * (Y0 - Y1);
+    } else {
+      at(a, X, Y);
+    }
+  }
+  void at(int a, int b, long double& X, long double& Y) const {
+    if (g.bcy == PERIODIC) {
+      int br = wrap(b, g.ny), k = floordiv(b, g.ny);
+      row(a, br, X, Y);
+      Y += (long double)k * (long double)g.Ly;
+      return;
+    }
+    long double X0, Y0, X1, Y1;
+    if (b < 0) {
+      row(a, 0, X0, Y0); row(a, 1, X1, Y1);
+      X = X0 + (long double)b * (X1 - X0); Y = Y0 + (long double)b * (Y1 - Y0);
+    } else if (b >= g.ny) {
+      row(a, g.ny - 1, X0, Y0); row(a, g.ny - 2, X1, Y1);
+      long double s = (long double)(b - g.ny + 1);
+      X = X0 + s * (X0 - X1); Y = Y0 + s * (Y0 - Y1);
+    } else {
+      row(a, b, X, Y);
+    }
+  }
+};
+
+// Nodal metrics at (i, j) (any integers): Sec. 2.2 in two dimensions, where the
+// conservative forms 2.3/2.4 reduce to xi_x^ = y_eta, xi_y^ = -x_eta,
+// eta_x^ = -y_xi, eta_y^ = x_xi, and the Jacobian 2.5 to
+// J^{-1} = x_xi y_eta - x_eta y_xi.  Each derivative is the scheme's own
+// central operator (Sec. 2.3), evaluated on coordinate differences.
+struct NodalMetric { double xix, xiy, etx, ety, jinv; };
+
+inline NodalMetric nodal_metric(Scheme sc, const Coords& C, int i, int j) {
+  long double X0, Y0;
+  C.at(i, j, X0, Y0);
+  double rx[17], ry[17];
+  for (int m = -8; m <= 8; ++m) {
+    long double X, Y;
+    C.at(i + m, j, X, Y);
+    rx[m + 8] = (double)(X - X0); ry[m + 8] = (double)(Y - Y0);
+  }
+  double x_xi = metric_derivative(sc, rx), y_xi = metric_derivative(sc, ry);
+  for (int m = -8; m <= 8; ++m) {
+    long double X, Y;
+    C.at(i, j + m, X, Y);
+    rx[m + 8] = (double)(X - X0); ry[m + 8] = (double)(Y - Y0);
+  }
+  double x_eta = metric_derivative(sc, rx), y_eta = metric_derivative(sc, ry);
+  NodalMetric nm;
+  nm.xix = y_eta; nm.xiy = -x_eta; nm.etx = -y_xi; nm.ety = x_xi;
+  nm.jinv = x_xi * y_eta - x_eta * y_xi;
+  return nm;
+}
+
+// Metric storage: nine planes of (ny + 2G) x (nx + 2G) doubles, i fastest,
+// node (i, j) at (j + G) * (nx + 2G) + (i + G):
+//   0 xi_x^, 1 xi_y^, 2 eta_x^, 3 eta_y^, 4 J^{-1}            at nodes (i, j)
+//   5 xi_x^, 6 xi_y^ at (i + 1/2, j);  7 eta_x^, 8 eta_y^ at (i, j + 1/2)
+struct MetricView {
+  int nx, ny;
+  const double* M;
+  size_t plane() const { return (size_t)(nx + 2 * G) * (ny + 2 * G); }
+  double operator()(int p, int i, int j) const {
+    return M[p * plane() + (size_t)(j + G) * (nx + 2 * G) + (i + G)];
+  }
+};
+
+// Fill all nine metric planes, ghost band included.  Periodic directions copy
+// the metrics of the wrapped node; transmissive ones evaluate them on the
+// extended coordinates.  Midpoint metrics are the interpolation of the nodal
+// ones in the same direction (Sec. 2.4, directionally consistent).
+inline void compute_metrics(Scheme sc, const Grid& g, const double* x, const double* y, double* M) {
+  Coords C{g, x, y};
+  const int W = g.nx + 2 * G, H = g.ny + 2 * G;
+  const size_t P = (size_t)W * H;
+  // Nodal metrics on a band wide enough for the midpoint interpolation.
+  const int B = G + 3;
+  const int WB = g.nx + 2 * B, HB = g.ny + 2 * B;
+  std::vector<NodalMetric> nm((size_t)WB * HB);
+  auto wr = [&](int a, int n, Bc bc) { return bc == PERIODIC ? wrap(a, n) : a; };
+#pragma omp parallel for schedule(static)
+  for (int b = -B; b < g.ny + B; ++b)
+    for (int a = -B; a < g.nx + B; ++a)
+      nm[(size_t)(b + B) * WB + (a + B)] = nodal_metric(sc, C, wr(a, g.nx, g.bcx), wr(b, g.ny, g.bcy));
+  auto N = [&](int a, int b) -> const NodalMetric& {
+    // for periodic directions use the wrapped node so copies are bitwise equal
+    int aa = g.bcx == PERIODIC ? wrap(a, g.nx) : a;
+    int bb = g.bcy == PERIODIC ? wrap(b, g.ny) : b;
+    return nm[(size_t)(bb + B) * WB + (aa + B)];
+  };
+  for (int b = -G; b < g.ny + G; ++b)
+    for (int a = -G; a < g.nx + G; ++a) {
+      size_t o = (size_t)(b + G) * W + (a + G);
+      const NodalMetric& n0 = N(a, b);
+      M[0 * P + o] = n0.xix; M[1 * P + o] = n0.xiy;
+      M[2 * P + o] = n0.etx; M[3 * P + o] = n0.ety; M[4 * P + o] = n0.jinv;
+      M[5 * P + o] = interp_mid([&](int l) { return N(a + l, b).xix; });
+      M[6 * P + o] = interp_mid([&](int l) { return N(a + l, b).xiy; });
+      M[7 * P + o] = interp_mid([&](int l) { return N(a, b + l).etx; });
+      M[8 * P + o] = interp_mid([&](int l) { return N(a, b + l).ety; });
+    }
+}
+
+// ===========================================================================
+// Sec. 2.1: state, pressure and the contravariant flux of Eq. 2.2 in 2-D,
+// E^ = k_x E + k_y F for the hatted metric direction (k_x, k_y).
+// ===========================================================================
+template <class T> T pressure(const T Q[4], double gam) {
+  T u = Q[1] / Q[0], v = Q[2] / Q[0];
+  return (gam - 1.0) * (Q[3] - 0.5 * Q[0] * (u * u + v * v));
+}
+
+template <class T> void flux_hat(const T Q[4], double gam, double kx, double ky, T out[4]) {
+  T rho = Q[0], u = Q[1] / Q[0], v = Q[2] / Q[0];
+  T p = (gam - 1.0) * (Q[3] - 0.5 * rho * (u * u + v * v));
+  T U = kx * u + ky * v;
+  out[0] = rho * U;
+  out[1] = Q[1] * U + kx * p;
+  out[2] = Q[2] * U + ky * p;
+  out[3] = (Q[3] + p) * U;
+}
+
+// Wave speed |U^| + c |k^| of Sec. 2.3 (the absolute value is the reading
+// adopted for "MAX(U^ + c|k^|)").
+template <class T> T wave_speed(const T Q[4], double gam, double kx, double ky) {
+  T u = Q[1] / Q[0], v = Q[2] / Q[0];
+  T p = (gam - 1.0) * (Q[3] - 0.5 * Q[0] * (u * u + v * v));
+  T c = sqrt(gam * p / Q[0]);
+  T U = kx * u + ky * v;
+  return fabs(U) + c * std::sqrt(kx * kx + ky * ky);
+}
+
+// ===========================================================================
+// Sec. 3.4: eigenvectors of the flux Jacobian in the unit direction n at the
+// reference state.  Right eigenvectors (columns) for q_n - c, q_n, q_n, q_n + c
+// and the matching left eigenvectors (rows), with b1 = (gamma-1)/c^2 and
+// b2 = b1 q^2 / 2.  (The paper fixes no basis; this one is the reading
+// adopted.)
+// ===========================================================================
+template <class T> void eigenvectors(const T Q[4], double gam, double nx_, double ny_, T L[4][4], T R[4][4]) {
+  T rho = Q[0], u = Q[1] / rho, v = Q[2] / rho;
+  T q2 = u * u + v * v;
+  T p = (gam - 1.0) * (Q[3] - 0.5 * rho * q2);
+  T c = sqrt(gam * p / rho);
+  T Hh = (Q[3] + p) / rho;
+  T qn = u * nx_ + v * ny_;
+  T qt = -u * ny_ + v * nx_;
+  T b1 = (gam - 1.0) / (c * c);
+  T b2 = 0.5 * b1 * q2;
+  // columns of R
+  R[0][0] = T(1.0);        R[0][1] = T(1.0);  R[0][2] = T(0.0);  R[0][3] = T(1.0);
+  R[1][0] = u - c * nx_;   R[1][1] = u;       R[1][2] = T(-ny_); R[1][3] = u + c * nx_;
+  R[2][0] = v - c * ny_;   R[2][1] = v;       R[2][2] = T(nx_);  R[2][3] = v + c * ny_;
+  R[3][0] = Hh - c * qn;   R[3][1] = 0.5 * q2; R[3][2] = qt;     R[3][3] = Hh + c * qn;
+  // rows of L
+  L[0][0] = 0.5 * (b2 + qn / c); L[0][1] = 0.5 * (-b1 * u - nx_ / c);
+  L[0][2] = 0.5 * (-b1 * v - ny_ / c); L[0][3] = 0.5 * b1;
+  L[1][0] = 1.0 - b2; L[1][1] = b1 * u; L[1][2] = b1 * v; L[1][3] = -b1;
+  L[2][0] = -qt; L[2][1] = T(-ny_); L[2][2] = T(nx_); L[2][3] = T(0.0);
+  L[3][0] = 0.5 * (b2 - qn / c); L[3][1] = 0.5 * (-b1 * u + nx_ / c);
+  L[3][2] = 0.5 * (-b1 * v + ny_ / c); L[3][3] = 0.5 * b1;
+}
+
+// ===========================================================================
+// Midpoint split fluxes F^+_{k+1/2}, F^-_{k+1/2} (Secs. 2.3, 2.4, 3.4).
+// Inputs: the six states Q_{k-2..k+3}, the nodal hatted metrics at k and k+1
+// (their mean gives the eigenvector direction), the midpoint metric (I xi^)_{k+1/2},
+// and the line eigenvalue lambda.
+//   + side: reference state Q_k, left-biased interpolation of L Q over k-2..k+2
+//   - side: reference state Q_{k+1}, right-biased interpolation over k-1..k+3
+// Each midpoint is evaluated once and reused by every h that needs it.
+//
+// The projection is applied to the deviations Q_m - Q_ref and Q_ref is added
+// back after R: since R L = I and the WENO interpolation commutes with adding
+// a constant (the indicators see only differences and each candidate's
+// coefficients sum to one), this is the same map as R WENO(L Q); it only
+// removes the rounding of the round trip, so a uniform state comes back
+// bitwise (the reading adopted for free-stream preservation at round-off).
+// ===========================================================================
+template <class T>
+void midpoint_flux(Scheme sc, const Params& pr, const T Qs[6][4], double kx0, double ky0, double kx1,
+                   double ky1, double mkx, double mky, const T& lam, T Fp[4], T Fm[4]) {
+  double nbx = 0.5 * (kx0 + kx1), nby = 0.5 * (ky0 + ky1);
+  double nn = std::sqrt(nbx * nbx + nby * nby);
+  double nx_ = nbx / nn, ny_ = nby / nn;
+  for (int side = 0; side < 2; ++side) {
+    const T* Qref = Qs[2 + side];  // Q_k for +, Q_{k+1} for -
+    T L[4][4], R[4][4];
+    eigenvectors(Qref, pr.gamma, nx_, ny_, L, R);
+    T W[4];
+    for (int c = 0; c < 4; ++c) {
+      T s[6];
+      for (int m = 0; m < 6; ++m) {
+        s[m] = T(0.0);
+        for (int q = 0; q < 4; ++q) s[m] = s[m] + L[c][q] * (Qs[m][q] - Qref[q]);
+      }
+      W[c] = side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr);
+    }
+    T Qm[4];
+    for (int q = 0; q < 4; ++q) {
+      Qm[q] = T(0.0);
+      for (int c = 0; c < 4; ++c) Qm[q] = Qm[q] + R[q][c] * W[c];
+      Qm[q] = Qref[q] + Qm[q];
+    }
+    T E[4];
+    flux_hat(Qm, pr.gamma, mkx, mky, E);
+    T* out = side == 0 ? Fp : Fm;
+    double sgn = side == 0 ? 1.0 : -1.0;
+    for (int q = 0; q < 4; ++q) out[q] = 0.5 * (E[q] + sgn * lam * Qm[q]);
+  }
+}
+
+// ===========================================================================
+// One grid line: residual R_k = H_{k+1/2} - H_{k-1/2}, k = 0..n-1 (Eq. 3.2
+// with unit spacing), H = h^+ + h^-.  Accessors:
+//   Q(k, q)   conservative state at line index k (boundary rule applied)
+//   K(0, k), K(1, k)  nodal hatted metric (k_x, k_y) of this direction
+//   K(2, k), K(3, k)  midpoint metric at k+1/2
+// The Lax-Friedrichs eigenvalue is alpha * max over the line's own nodes of
+// the wave speed (Sec. 2.3); it is returned in *lam_out.
+// ===========================================================================
+template <class T, class QF, class KF>
+void line_residual(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_out) {
+  auto kx = [&](int k) { return K(0, k); };
+  auto ky = [&](int k) { return K(1, k); };
+  auto mkx = [&](int k) { return K(2, k); };
+  auto mky = [&](int k) { return K(3, k); };
+  // Sec. 2.3: A^ = alpha MAX(|U^| + c|k^|) over the full line.
+  T lam = T(0.0);
+  bool first = true;
+  for (int k = 0; k < n; ++k) {
+    T Qk[4] = {Q(k, 0), Q(k, 1), Q(k, 2), Q(k, 3)};
+    T s = wave_speed(Qk, pr.gamma, kx(k), ky(k));
+    if (first || s > lam) { lam = s; first = false; }
+  }
+  lam = pr.alpha_lf * lam;
+  if (lam_out) *lam_out = lam;
+
+  const int off = 4;  // arrays hold indices -4 .. n+3
+  const int len = n + 8;
+  std::vector<T> fp(4 * len), fm(4 * len), Fp(4 * len), Fm(4 * len);
+  // Nodal split fluxes f^+- = (E^ +- lambda Q) / 2 (Sec. 2.3).
+  for (int k = -3; k < n + 3; ++k) {
+    T Qk[4] = {Q(k, 0), Q(k, 1), Q(k, 2), Q(k, 3)}, E[4];
+    flux_hat(Qk, pr.gamma, kx(k), ky(k), E);
+    for (int q = 0; q < 4; ++q) {
+      fp[q * len + k + off] = 0.5 * (E[q] + lam * Qk[q]);
+      fm[q * len + k + off] = 0.5 * (E[q] - lam * Qk[q]);
+    }
+  }
+  // Midpoint split fluxes at k+1/2.
+  for (int k = -2; k < n + 1; ++k) {
+    T Qs[6][4];
+    for (int m = 0; m < 6; ++m)
+      for (int q = 0; q < 4; ++q) Qs[m][q] = Q(k - 2 + m, q);
+    T a[4], b[4];
+    midpoint_flux(sc, pr, Qs, kx(k), ky(k), kx(k + 1), ky(k + 1), mkx(k), mky(k), lam, a, b);
+    for (int q = 0; q < 4; ++q) { Fp[q * len + k + off] = a[q]; Fm[q * len + k + off] = b[q]; }
+  }
+  // H_{i+1/2} = h^+_{i+1/2} + h^-_{i+1/2}; h^- is h^+ mirrored about i+1/2
+  // (node i+m <-> i+1-m, midpoint i+1/2+m <-> i+1/2-m).
+  std::vector<T> H(4 * (n + 1));
+  for (int i = -1; i < n; ++i)
+    for (int q = 0; q < 4; ++q) {
+      auto fpn = [&](int m) { return fp[q * len + i + m + off]; };
+      auto Fpm = [&](int m) { return Fp[q * len + i + m + off]; };
+      auto fmn = [&](int m) { return fm[q * len + i + 1 - m + off]; };
+      auto Fmm = [&](int m) { return Fm[q * len + i - m + off]; };
+      H[q * (n + 1) + i + 1] = h_plus<T>(sc, fpn, Fpm) + h_plus<T>(sc, fmn, Fmm);
+    }
+  for (int k = 0; k < n; ++k)
+    for (int q = 0; q < 4; ++q) R[q * n + k] = H[q * (n + 1) + k + 1] - H[q * (n + 1) + k];
+}
+
+// ===========================================================================
+// Eq. 2.2 / 3.2: dQ/dt = -[(H^xi_{i+1/2} - H^xi_{i-1/2}) + (H^eta_{j+1/2} - H^eta_{j-1/2})] / J^{-1}.
+// U and dUdt: [4][ny][nx].  lam_xi[ny], lam_eta[nx] receive the line
+// eigenvalues when non-null.
+// ===========================================================================
+template <class T>
+void rhs(Scheme sc, const Params& pr, const Grid& g, const T* U, const double* M, T* dUdt,
+         T* lam_xi = nullptr, T* lam_eta = nullptr) {
+  const int nx = g.nx, ny = g.ny;
+  const size_t NP = (size_t)nx * ny;
+  MetricView mv{nx, ny, M};
+  auto wi = [&](int i) { return g.bcx == PERIODIC ? wrap(i, nx) : std::min(std::max(i, 0), nx - 1); };
+  auto wj = [&](int j) { return g.bcy == PERIODIC ? wrap(j, ny) : std::min(std::max(j, 0), ny - 1); };
+  std::vector<T> Rx(4 * NP), Ry(4 * NP);
+  // xi sweep: one line per row j
+#pragma omp parallel for schedule(dynamic)
+  for (int j = 0; j < ny; ++j) {
+    std::vector<T> R(4 * nx);
+    auto Q = [&](int k, int q) { return U[q * NP + (size_t)j * nx + wi(k)]; };
+    const int plane[4] = {0, 1, 5, 6};
+    auto K = [&](int w, int k) { return mv(plane[w], k, j); };
+    T lam;
+    line_residual<T>(sc, pr, nx, Q, K, R.data(), &lam);
+    if (lam_xi) lam_xi[j] = lam;
+    for (int q = 0; q < 4; ++q)
+      for (int i = 0; i < nx; ++i) Rx[q * NP + (size_t)j * nx + i] = R[q * nx + i];
+  }
+  // eta sweep: one line per column i
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < nx; ++i) {
+    std::vector<T> R(4 * ny);
+    auto Q = [&](int k, int q) { return U[q * NP + (size_t)wj(k) * nx + i]; };
+    const int plane[4] = {2, 3, 7, 8};
+    auto K = [&](int w, int k) { return mv(plane[w], i, k); };
+    T lam;
+    line_residual<T>(sc, pr, ny, Q, K, R.data(), &lam);
+    if (lam_eta) lam_eta[i] = lam;
+    for (int q = 0; q < 4; ++q)
+      for (int j = 0; j < ny; ++j) Ry[q * NP + (size_t)j * nx + i] = R[q * ny + j];
+  }
+  for (int q = 0; q < 4; ++q)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        size_t o = (size_t)j * nx + i;
+        dUdt[q * NP + o] = -(Rx[q * NP + o] + Ry[q * NP + o]) / mv(4, i, j);
+      }
+}
+
+// ===========================================================================
+// Time step from the CFL number: dt = CFL / max_ij [(|U^| + c|xi^|) + (|V^| + c|eta^|)] / J^{-1}.
+// (The paper uses fixed steps; this is the rule adopted for CFL-driven runs.)
+// ===========================================================================
+inline double cfl_dt(const Params& pr, const Grid& g, const double* U, const double* M, double cfl) {
+  const size_t NP = (size_t)g.nx * g.ny;
+  MetricView mv{g.nx, g.ny, M};
+  double smax = 0.0;
+  for (int j = 0; j < g.ny; ++j)
+    for (int i = 0; i < g.nx; ++i) {
+      size_t o = (size_t)j * g.nx + i;
+      double Q[4] = {U[o], U[NP + o], U[2 * NP + o], U[3 * NP + o]};
+      double s = wave_speed(Q, pr.gamma, mv(0, i, j), mv(1, i, j)) +
+                 wave_speed(Q, pr.gamma, mv(2, i, j), mv(3, i, j));
+      s = s / mv(4, i, j);
+      if (s > smax) smax = s;
+    }
+  return cfl / smax;
+}
+
+// ===========================================================================
+// Third-order TVD Runge-Kutta (Shu-Osher form), used in Sec. 6:
+//   U1 = U + dt L(U);  U2 = 3/4 U + 1/4 (U1 + dt L(U1));  U = 1/3 U + 2/3 (U2 + dt L(U2)).
+// ===========================================================================
+template <class T>
+void rk3_step(Scheme sc, const Params& pr, const Grid& g, T* U, const double* M, double dt) {
+  const size_t N = 4 * (size_t)g.nx * g.ny;
+  std::vector<T> L(N), U1(N), U2(N);
+  rhs<T>(sc, pr, g, U, M, L.data());
+  for (size_t e = 0; e < N; ++e) U1[e] = U[e] + dt * L[e];
+  rhs<T>(sc, pr, g, U1.data(), M, L.data());
+  for (size_t e = 0; e < N; ++e) U2[e] = 0.75 * U[e] + 0.25 * (U1[e] + dt * L[e]);
+  rhs<T>(sc, pr, g, U2.data(), M, L.data());
+  for (size_t e = 0; e < N; ++e) U[e] = (1.0 / 3.0) * U[e] + (2.0 / 3.0) * (U2[e] + dt * L[e]);
+}
+
+}  // namespace orc

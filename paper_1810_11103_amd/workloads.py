@@ -1,0 +1,250 @@
+"""Seeded synthetic grids and initial states (inputs only).
+
+This module builds the inputs shared by the HIP path, the tests and the
+benchmark: node coordinates of uniform and randomized curvilinear grids and
+conservative initial states of the paper's test problems.  It contains none of
+the method's arithmetic (no metrics, fluxes, interpolation or time stepping).
+
+Conventions: arrays are float64, row-major, the xi index i fastest.
+Coordinates have shape (ny, nx); states have shape (4, ny, nx) holding
+(rho, rho u, rho v, e) with e = p/(gamma-1) + rho (u^2 + v^2)/2 (Sec. 2.1).
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+@dataclass
+class Grid:
+    x: np.ndarray
+    y: np.ndarray
+    bc: tuple = ("periodic", "periodic")
+    period: tuple = (0.0, 0.0)
+    spacing: tuple = (1.0, 1.0)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def shape(self):
+        return self.x.shape
+
+
+def conservative(rho, u, v, p, gamma=GAMMA):
+    dt = np.result_type(rho, u, v, p, np.float64)  # complex inputs stay complex
+    rho, u, v, p = np.broadcast_arrays(*(np.asarray(a, dtype=dt) for a in (rho, u, v, p)))
+    e = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return np.ascontiguousarray(np.stack([rho, rho * u, rho * v, e]))
+
+
+def primitive(U, gamma=GAMMA):
+    rho = U[0]
+    u = U[1] / rho
+    v = U[2] / rho
+    p = (gamma - 1.0) * (U[3] - 0.5 * rho * (u * u + v * v))
+    return rho, u, v, p
+
+
+# ---------------------------------------------------------------------------
+# Grids (Sec. 6.1)
+# ---------------------------------------------------------------------------
+
+def _jitter(nx, ny, A, rng, mask):
+    """Sec. 6.1(1): each node is displaced by 2A(Rand(0,1) - 0.5) spacings in
+    x or in y, the direction chosen by a fair coin Rand(0|1)."""
+    r = rng.random((ny, nx))
+    coin = rng.integers(0, 2, size=(ny, nx))
+    d = 2.0 * A * (r - 0.5) * mask
+    return d * coin, d * (1 - coin)
+
+
+def periodic_grid(nx, ny, box=(0.0, 10.0, 0.0, 10.0), A=0.0, seed=0):
+    """Periodic grid of nx x ny distinct nodes on [x0, x1) x [y0, y1): node
+    (i, j) sits at (x0 + i hx, y0 + j hy), hx = (x1-x0)/nx, displaced at every
+    node when A > 0 (the images across the period are the same nodes)."""
+    x0, x1, y0, y1 = box
+    hx, hy = (x1 - x0) / nx, (y1 - y0) / ny
+    jj, ii = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    dx = dy = 0.0
+    if A > 0:
+        rng = np.random.default_rng(seed)
+        dx, dy = _jitter(nx, ny, A, rng, np.ones((ny, nx)))
+    x = x0 + (ii + dx) * hx
+    y = y0 + (jj + dy) * hy
+    return Grid(np.ascontiguousarray(x), np.ascontiguousarray(y), ("periodic", "periodic"),
+                (x1 - x0, y1 - y0), (hx, hy), {"A": A, "seed": seed})
+
+
+def bounded_grid(nx, ny, box=(0.0, 1.0, 0.0, 1.0), A=0.0, seed=0, layers=4):
+    """Non-periodic grid with nodes from x0 to x1 inclusive, displaced by A
+    spacings except in `layers` uniform node layers along every boundary
+    (Sec. 6.1(1) and (3); the 'or' of Sec. 6.1(1) is read as 'and')."""
+    x0, x1, y0, y1 = box
+    hx, hy = (x1 - x0) / (nx - 1), (y1 - y0) / (ny - 1)
+    jj, ii = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    dx = dy = 0.0
+    if A > 0:
+        rng = np.random.default_rng(seed)
+        iv = np.arange(nx)
+        jv = np.arange(ny)
+        mi = (iv >= layers) & (iv < nx - layers)
+        mj = (jv >= layers) & (jv < ny - layers)
+        mask = (mj[:, None] & mi[None, :]).astype(np.float64)
+        dx, dy = _jitter(nx, ny, A, rng, mask)
+    x = x0 + (ii + dx) * hx
+    y = y0 + (jj + dy) * hy
+    return Grid(np.ascontiguousarray(x), np.ascontiguousarray(y), ("transmissive", "transmissive"),
+                (0.0, 0.0), (hx, hy), {"A": A, "seed": seed, "layers": layers})
+
+
+def strip_grid(n, x0=0.0, x1=1.0):
+    """One-row grid for 1-D problems: cell centres x_i = x0 + (i + 1/2) h,
+    transmissive in x, periodic in y with period h (so every eta line is a
+    single repeated node)."""
+    h = (x1 - x0) / n
+    x = (x0 + (np.arange(n, dtype=np.float64) + 0.5) * h)[None, :]
+    y = np.zeros((1, n))
+    return Grid(np.ascontiguousarray(x), y, ("transmissive", "periodic"), (0.0, h), (h, h), {})
+
+
+def sinusoidal_grid(nx, ny, box=(0.0, 10.0, 0.0, 10.0), amp=0.1):
+    """Smooth periodic curvilinear grid: x = x0 + L_x[s + a sin(2 pi t)],
+    y = y0 + L_y[t + a sin(2 pi s)] with s = i/nx, t = j/ny."""
+    x0, x1, y0, y1 = box
+    Lx, Ly = x1 - x0, y1 - y0
+    jj, ii = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    s, t = ii / nx, jj / ny
+    x = x0 + Lx * (s + amp * np.sin(2 * np.pi * t))
+    y = y0 + Ly * (t + amp * np.sin(2 * np.pi * s))
+    return Grid(np.ascontiguousarray(x), np.ascontiguousarray(y), ("periodic", "periodic"), (Lx, Ly),
+                (Lx / nx, Ly / ny), {"amp": amp})
+
+
+# ---------------------------------------------------------------------------
+# Initial states
+# ---------------------------------------------------------------------------
+
+def uniform_flow(grid, mach=0.5, angle=np.pi / 4, rho=1.0, p=1.0, gamma=GAMMA):
+    c = np.sqrt(gamma * p / rho)
+    u = mach * c * np.cos(angle)
+    v = mach * c * np.sin(angle)
+    shape = grid.x.shape
+    return conservative(np.full(shape, rho), np.full(shape, u), np.full(shape, v), np.full(shape, p), gamma)
+
+
+def vortex_state(x, y, center=(5.0, 5.0), strength=5.0 / (2 * np.pi), alpha=0.5, rc=1.0, mach=0.5,
+                 angle=np.pi / 4, gamma=GAMMA):
+    """Isentropic vortex of Sec. 6.3(1): (du, dv) = eps r e^{alpha(1-r^2)}
+    (sin t, -cos t), dT = -(gamma-1) eps^2 / (4 alpha gamma) e^{2 alpha (1-r^2)},
+    on a mean flow rho = p = T = 1 of the given Mach number.  The defaults give
+    the classic strength-5 vortex (alpha = 1/2, eps = 5/(2 pi))."""
+    c = np.sqrt(gamma)
+    u0 = mach * c * np.cos(angle)
+    v0 = mach * c * np.sin(angle)
+    dx = (x - center[0]) / rc
+    dy = (y - center[1]) / rc
+    r2 = dx * dx + dy * dy
+    f = strength * np.exp(alpha * (1.0 - r2))
+    # r sin(theta) = dy, r cos(theta) = dx
+    u = u0 + f * dy
+    v = v0 - f * dx
+    T = 1.0 - (gamma - 1.0) * strength ** 2 / (4.0 * alpha * gamma) * np.exp(2.0 * alpha * (1.0 - r2))
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho * T
+    return conservative(rho, u, v, p, gamma)
+
+
+def vortex_periodic_state(grid, t=0.0, **kw):
+    """Vortex translated by the mean flow for time t on the periodic box (the
+    exact solution of the Euler equations), summing the nearest images."""
+    mach = kw.get("mach", 0.5)
+    angle = kw.get("angle", np.pi / 4)
+    gamma = kw.get("gamma", GAMMA)
+    center = kw.get("center", (5.0, 5.0))
+    Lx, Ly = grid.period
+    c = np.sqrt(gamma)
+    cx = center[0] + mach * c * np.cos(angle) * t
+    cy = center[1] + mach * c * np.sin(angle) * t
+    x0 = grid.x.min() if Lx == 0 else 0.0
+    # place the centre inside the box and measure distances to the nearest image
+    bx = 0.0 if Lx == 0 else (cx - np.floor((cx - 0.0) / Lx) * Lx)
+    by = 0.0 if Ly == 0 else (cy - np.floor((cy - 0.0) / Ly) * Ly)
+    dx = grid.x - bx
+    dy = grid.y - by
+    if Lx:
+        dx = dx - Lx * np.round(dx / Lx)
+    if Ly:
+        dy = dy - Ly * np.round(dy / Ly)
+    del x0
+    kw2 = {k: v for k, v in kw.items() if k not in ("center",)}
+    return vortex_state(dx, dy, center=(0.0, 0.0), **kw2)
+
+
+# Four-quadrant Riemann problem of Sec. 6.3(3): (rho, u, v, p) per quadrant.
+RIEMANN_QUADRANTS = {
+    "ne": (1.0, 0.0, -0.3, 1.0),
+    "nw": (2.0, 0.0, 0.3, 1.0),
+    "sw": (1.0625, 0.0, 0.8145, 0.4),
+    "se": (0.5313, 0.0, 0.4276, 0.4),
+}
+
+
+def riemann_state(grid, gamma=GAMMA, split=(0.5, 0.5)):
+    x, y = grid.x, grid.y
+    east = x >= split[0]
+    north = y >= split[1]
+    out = []
+    for k in range(4):
+        a = np.where(north & east, RIEMANN_QUADRANTS["ne"][k],
+            np.where(north & ~east, RIEMANN_QUADRANTS["nw"][k],
+            np.where(~north & ~east, RIEMANN_QUADRANTS["sw"][k], RIEMANN_QUADRANTS["se"][k])))
+        out.append(a)
+    return conservative(*out, gamma=gamma)
+
+
+def sod_state(grid, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1), x0=0.5, gamma=GAMMA):
+    x = grid.x
+    L = x < x0
+    rho = np.where(L, left[0], right[0])
+    u = np.where(L, left[1], right[1])
+    p = np.where(L, left[2], right[2])
+    return conservative(rho, u, np.zeros_like(u), p, gamma)
+
+
+def riemann_problem(n=2048, A=0.2, seed=2048, layers=4):
+    """2-D Riemann throughput workload on [0,1]^2 (randomized when A > 0)."""
+    g = bounded_grid(n, n, (0.0, 1.0, 0.0, 1.0), A=A, seed=seed, layers=layers)
+    return g, riemann_state(g)
+
+
+def fsp_problem(n, A=0.2, seed=None, box=(0.0, 10.0, 0.0, 10.0)):
+    seed = 1810 + n if seed is None else seed
+    g = periodic_grid(n, n, box, A=A, seed=seed)
+    return g, uniform_flow(g)
+
+
+def vortex_problem(n, A=0.2, seed=None, box=(0.0, 10.0, 0.0, 10.0), **kw):
+    seed = 1810 + n if seed is None else seed
+    g = periodic_grid(n, n, box, A=A, seed=seed)
+    return g, vortex_periodic_state(g, **kw)
+
+
+def random_smooth_state(grid, seed=0, amp=0.05):
+    """Smooth random perturbation of a uniform state (for parity tests)."""
+    rng = np.random.default_rng(seed)
+    Lx = grid.period[0] or (grid.x.max() - grid.x.min())
+    Ly = grid.period[1] or (grid.y.max() - grid.y.min())
+    x, y = grid.x, grid.y
+    fields = []
+    for _ in range(4):
+        f = np.zeros_like(x)
+        for _k in range(3):
+            kx, ky = rng.integers(1, 4, size=2)
+            ph = rng.random() * 2 * np.pi
+            f += np.sin(2 * np.pi * (kx * x / Lx + ky * y / Ly) + ph)
+        fields.append(f)
+    rho = 1.0 + amp * fields[0]
+    u = 0.3 + amp * fields[1]
+    v = -0.2 + amp * fields[2]
+    p = 1.0 + amp * fields[3]
+    return conservative(rho, u, v, p)

@@ -1,0 +1,146 @@
+/*
+ * wenoiu.h -- C ABI of libwenoiu, the MI355X (gfx950) implementation of the
+ * WENO interpolation-based, upwind-biased (WENOIU) schemes with free-stream
+ * preservation of Li & Sun (arXiv 1810.11103) for the 2-D Euler equations on
+ * curvilinear grids.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers to fp64 memory owned by the
+ *    caller; the library never frees or keeps them.  No entry point allocates
+ *    device memory: scratch comes from a caller-provided workspace `ws` of at
+ *    least wiu_workspace_bytes() bytes (256-byte aligned).
+ *  - Layout is structure-of-arrays, row-major, the xi index i fastest, no
+ *    padding.  A conservative state U is [4][ny][nx] = (rho, rho u, rho v, e)
+ *    with e = p/(gamma-1) + rho (u^2+v^2)/2 (Sec. 2.1).  Node coordinates
+ *    x, y are [ny][nx].
+ *  - Metric array M (wiu_metrics_size() bytes): nine planes of
+ *    (ny + 2 WIU_GHOST) x (nx + 2 WIU_GHOST) doubles, node (i, j) at
+ *    (j + WIU_GHOST) * (nx + 2 WIU_GHOST) + (i + WIU_GHOST), followed by an
+ *    8-double tag recording the scheme and grid the metrics were built for:
+ *      plane 0 xi_x^, 1 xi_y^, 2 eta_x^, 3 eta_y^, 4 J^{-1}  at nodes (i, j)
+ *      plane 5 xi_x^, 6 xi_y^ at (i+1/2, j); 7 eta_x^, 8 eta_y^ at (i, j+1/2)
+ *    (hatted metrics carry the factor J^{-1}, Sec. 2.1).
+ *  - Every call is asynchronous on `stream` (a hipStream_t, 0 = null stream)
+ *    and returns a host-side code: WIU_OK, or a negative WIU_E* code when the
+ *    arguments fail the host checks (nothing is launched then).  Conditions
+ *    found on the device (folded grid cell, non-physical state, metrics of
+ *    another scheme) latch bits into a status word in `ws`, read with
+ *    wiu_status().
+ *  - Calls that share one workspace must not overlap in time (use one stream
+ *    per workspace).
+ */
+#ifndef WENOIU_H
+#define WENOIU_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* wiu_stream_t; /* hipStream_t */
+
+/* Scheme variants: third/fifth order with one or two midpoints
+ * (Eqs. 3.4, 3.8, 3.16, 3.20 with their central operators 3.7, 3.9, 3.19, 3.21). */
+enum { WIU_3_1MP = 0, WIU_3_2MP = 1, WIU_5_1MP = 2, WIU_5_2MP = 3 };
+
+/* Boundary rule per direction.  PERIODIC: states wrap; coordinates repeat
+ * shifted by the period.  TRANSMISSIVE: states copy the boundary node;
+ * coordinates extend linearly from the last two nodes.  (The paper fixes no
+ * boundary rule; these are the library's.) */
+enum { WIU_BC_PERIODIC = 0, WIU_BC_TRANSMISSIVE = 1 };
+
+#define WIU_GHOST 4
+
+/* host-side return codes */
+#define WIU_OK 0
+#define WIU_EINVAL (-1)  /* null pointer, bad size or enum, bad parameter */
+#define WIU_EHIP (-2)    /* a HIP runtime call or kernel launch failed */
+
+/* device-latched status bits (wiu_status) */
+#define WIU_ST_JACOBIAN 1 /* J^{-1} <= 0 or non-finite at some node (folded cell) */
+#define WIU_ST_NONPHYS 2  /* rho <= 0, p <= 0 or a non-finite state entry */
+#define WIU_ST_SCHEME 4   /* metrics were built for another scheme or grid */
+
+typedef struct {
+  int nx, ny;               /* nodes per direction (>= 1; >= 2 if transmissive) */
+  int bc_x, bc_y;           /* WIU_BC_* */
+  double period_x, period_y; /* domain lengths of periodic directions */
+} wiu_grid;
+
+typedef struct {
+  double gamma;    /* ratio of specific heats, 1.4 */
+  double alpha_lf; /* Lax-Friedrichs factor alpha, 1.1 (Sec. 2.3: 1.1-1.2) */
+  double eps;      /* WENO epsilon, 1e-40 with the mapping (Sec. 3.2(3)) */
+  int ppm;         /* 1: piecewise-polynomial mapping of the weights (Eqs. 3.15, 3.23) */
+} wiu_params;
+
+/* Bytes of the metric array M for this grid (planes + tag). */
+size_t wiu_metrics_size(const wiu_grid* g);
+
+/* Bytes of workspace every entry point below needs for this grid. */
+size_t wiu_workspace_bytes(const wiu_grid* g);
+
+/* Grid metrics in conservative form (Sec. 2.2), differentiated with the
+ * scheme's own central operator delta^{c,(1)} (Sec. 2.3, Eqs. 3.7/3.9/3.19/
+ * 3.21) whose midpoint values come from a fixed six-point interpolation in
+ * each direction (Sec. 2.4), evaluated on coordinate differences.  In 2-D:
+ * xi_x^ = y_eta, xi_y^ = -x_eta, eta_x^ = -y_xi, eta_y^ = x_xi,
+ * J^{-1} = x_xi y_eta - x_eta y_xi.  Midpoint metrics interpolate the nodal
+ * ones in their own direction.  Fills the ghost band and the tag of M and
+ * latches WIU_ST_JACOBIAN if J^{-1} <= 0 at an interior node. */
+int wiu_metrics(const wiu_grid* g, int scheme, const double* x, const double* y, double* M, void* ws,
+                wiu_stream_t stream);
+
+/* Write the tag of M for metrics produced elsewhere (e.g. imported): the
+ * caller vouches that they were built with `scheme`'s central operator. */
+int wiu_set_metrics_tag(const wiu_grid* g, int scheme, double* M, wiu_stream_t stream);
+
+/* Line eigenvalues of the Lax-Friedrichs splitting (Sec. 2.3):
+ * lam_xi[j] = alpha max_i (|U^| + c|xi^|) over row j, lam_eta[i] likewise over
+ * column i with eta^.  Outputs are device arrays of ny and nx doubles. */
+int wiu_line_eigenvalues(const wiu_grid* g, const wiu_params* p, const double* U, const double* M,
+                         double* lam_xi, double* lam_eta, void* ws, wiu_stream_t stream);
+
+/* Spatial residual dU/dt = -[(H^xi_{i+1/2} - H^xi_{i-1/2}) + (H^eta_{j+1/2} -
+ * H^eta_{j-1/2})] / J^{-1} (Eq. 2.2 with Eq. 3.2), H = h^+ + h^- of the scheme
+ * (Sec. 3.2-3.3), midpoint fluxes from characteristic WENO interpolation with
+ * the mapped weights (Secs. 3.2(3), 3.3(3), 3.4) and Lax-Friedrichs line
+ * eigenvalues (Sec. 2.3).  dUdt may not alias U. */
+int wiu_rhs(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M, double* dUdt,
+            void* ws, wiu_stream_t stream);
+
+/* Time step dt = cfl / max_ij [(|U^| + c|xi^|) + (|V^| + c|eta^|)] / J^{-1},
+ * written to the device scalar *dt_dev (no host synchronisation). */
+int wiu_cfl_dt(const wiu_grid* g, const wiu_params* p, const double* U, const double* M, double cfl,
+               double* dt_dev, void* ws, wiu_stream_t stream);
+
+/* One third-order TVD Runge-Kutta step (Shu-Osher form, Sec. 6) of size
+ * *dt_dev (device scalar), in place on U. */
+int wiu_rk3_step(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
+                 const double* dt_dev, void* ws, wiu_stream_t stream);
+
+/* Synchronise `stream`, return the latched status bits of `ws` in *status
+ * and clear them when `clear` is non-zero. */
+int wiu_status(void* ws, wiu_stream_t stream, int* status, int clear);
+
+/* Zero the status word and scratch header of a fresh workspace. */
+int wiu_workspace_init(void* ws, wiu_stream_t stream);
+
+const char* wiu_strerror(int code);
+
+/* Kernel timing for benchmarks.  While enabled, every launch of the
+ * library's kernels is bracketed by HIP events recorded on its launch stream.
+ * wiu_profile_read() synchronises the device, returns the number of launches
+ * and their mean duration in milliseconds for kernel `id` (WIU_K_*), and
+ * clears that kernel's records. */
+enum { WIU_K_WAVE_MAX = 0, WIU_K_SWEEP_XI = 1, WIU_K_SWEEP_ETA = 2, WIU_K_METRICS = 3, WIU_K_COUNT = 4 };
+int wiu_profile_enable(int on);
+int wiu_profile_read(int id, long long* count, double* mean_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WENOIU_H */

@@ -66,6 +66,8 @@ def lib():
         L.orc_adv1d_rhs.argtypes = [_I, _I, _D, _I, _D, _D, _I, _P, _P]
         L.orc_adv1d_run.restype = _I
         L.orc_adv1d_run.argtypes = [_I, _I, _I, _D, _D, _I, _D, _P, _P]
+        L.orc_count_rhs_flops.restype = _I
+        L.orc_count_rhs_flops.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _P]
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [_I]
         L.orc_get_threads.restype = _I
@@ -188,6 +190,18 @@ def rhs(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-
     if return_lambda:
         return out, lx, le
     return out
+
+
+def count_rhs_flops(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+    """Operation counts of one rhs: (xi sweep, eta sweep, final combination)."""
+    U, M = _f64(U), _f64(M)
+    _, ny, nx = U.shape
+    c = np.zeros(3, dtype=np.int64)
+    rc = lib().orc_count_rhs_flops(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+                                   _ptr(U), _ptr(M), _ptr(c))
+    if rc:
+        raise ValueError("orc_count_rhs_flops failed")
+    return tuple(int(v) for v in c)
 
 
 def cfl_dt(U, M, cfl, gamma=1.4):

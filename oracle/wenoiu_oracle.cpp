@@ -6,6 +6,7 @@
 // rho v, e.  Metric arrays follow the layout documented in the header.
 // ---------------------------------------------------------------------------
 #include "wenoiu_oracle.hpp"
+#include "flop_count.hpp"
 
 #include <cstring>
 #ifdef _OPENMP
@@ -226,6 +227,34 @@ int orc_adv1d_run(int scheme, int N, int split, double alpha, double eps, int pp
   }
   *l2 = std::sqrt(s2 / N);
   *linf = smax;
+  return 0;
+}
+
+// ---- operation count of one rhs evaluation ---------------------------------------
+// counts[0]: xi sweep (all rows), counts[1]: eta sweep (all columns),
+// counts[2]: final combination; single-threaded.
+static long long g_marks[3];
+static void mark(int ph) { g_marks[ph] = Counted::n(); }
+
+int orc_count_rhs_flops(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps,
+                        int ppm, const double* U, const double* M, long long* counts) {
+  if (bad_scheme(scheme) || nx < 1 || ny < 1) return -1;
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Params p = make_params(gamma, alpha, eps, ppm);
+  const size_t N = 4 * (size_t)nx * ny;
+  std::vector<Counted> Uc(U, U + N), out(N);
+#ifdef _OPENMP
+  int nt = omp_get_max_threads();
+  omp_set_num_threads(1);
+#endif
+  Counted::n() = 0;
+  rhs<Counted>((Scheme)scheme, p, g, Uc.data(), M, out.data(), nullptr, nullptr, mark);
+#ifdef _OPENMP
+  omp_set_num_threads(nt);
+#endif
+  counts[0] = g_marks[0];
+  counts[1] = g_marks[1] - g_marks[0];
+  counts[2] = g_marks[2] - g_marks[1];
   return 0;
 }
 

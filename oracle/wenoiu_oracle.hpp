@@ -519,7 +519,7 @@ void line_residual(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_
 // ===========================================================================
 template <class T>
 void rhs(Scheme sc, const Params& pr, const Grid& g, const T* U, const double* M, T* dUdt,
-         T* lam_xi = nullptr, T* lam_eta = nullptr) {
+         T* lam_xi = nullptr, T* lam_eta = nullptr, void (*phase_end)(int) = nullptr) {
   const int nx = g.nx, ny = g.ny;
   const size_t NP = (size_t)nx * ny;
   MetricView mv{nx, ny, M};
@@ -539,6 +539,7 @@ void rhs(Scheme sc, const Params& pr, const Grid& g, const T* U, const double* M
     for (int q = 0; q < 4; ++q)
       for (int i = 0; i < nx; ++i) Rx[q * NP + (size_t)j * nx + i] = R[q * nx + i];
   }
+  if (phase_end) phase_end(0);
   // eta sweep: one line per column i
 #pragma omp parallel for schedule(dynamic)
   for (int i = 0; i < nx; ++i) {
@@ -552,12 +553,14 @@ void rhs(Scheme sc, const Params& pr, const Grid& g, const T* U, const double* M
     for (int q = 0; q < 4; ++q)
       for (int j = 0; j < ny; ++j) Ry[q * NP + (size_t)j * nx + i] = R[q * ny + j];
   }
+  if (phase_end) phase_end(1);
   for (int q = 0; q < 4; ++q)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
         size_t o = (size_t)j * nx + i;
         dUdt[q * NP + o] = -(Rx[q * NP + o] + Ry[q * NP + o]) / mv(4, i, j);
       }
+  if (phase_end) phase_end(2);
 }
 
 // ===========================================================================

@@ -1,0 +1,266 @@
+// C ABI of libwenoiu: argument checks, workspace carving and kernel launch
+// sequences.  Declarations and the documentation of every entry point are in
+// include/wenoiu.h.
+#include "wenoiu.h"
+#include "wiu_kernels.hpp"
+
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+using namespace wiu;
+
+namespace {
+
+// ---- optional kernel timing ----------------------------------------------
+struct ProfRec { int id; hipEvent_t a, b; };
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+struct ProfScope {
+  int id; hipStream_t st; hipEvent_t a = nullptr, b = nullptr; bool on;
+  ProfScope(int id_, hipStream_t st_) : id(id_), st(st_) {
+    on = g_prof_on;
+    if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) hipEventRecord(a, st);
+    else on = false;
+  }
+  ~ProfScope() {
+    if (!on) return;
+    hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back({id, a, b});
+  }
+};
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Workspace layout (byte offsets):
+//   0            header: int status, padding
+//   HDR          lam_xi[ny], lam_eta[nx], cfl_max[1]   (uint64 bit patterns)
+//   off_scratch  R^xi[4 np], U1[4 np], U2[4 np]  -- or the metric band temp
+struct WsLayout {
+  size_t lam, scratch, rxi, u1, u2, total;
+};
+
+WsLayout layout(const wiu_grid* g) {
+  WsLayout L;
+  const size_t np = (size_t)g->nx * g->ny;
+  const int B = GHOST + 3;
+  const size_t band = 5 * (size_t)(g->nx + 2 * B) * (g->ny + 2 * B);
+  L.lam = ALIGN;
+  L.scratch = L.lam + align_up(((size_t)g->nx + g->ny + 1) * 8);
+  L.rxi = L.scratch;
+  L.u1 = L.rxi + align_up(4 * np * 8);
+  L.u2 = L.u1 + align_up(4 * np * 8);
+  const size_t end_rk = L.u2 + align_up(4 * np * 8);
+  const size_t end_met = L.scratch + align_up(band * 8);
+  L.total = end_rk > end_met ? end_rk : end_met;
+  return L;
+}
+
+bool grid_ok(const wiu_grid* g) {
+  if (!g) return false;
+  if (g->nx < 1 || g->ny < 1) return false;
+  if (g->bc_x < 0 || g->bc_x > 1 || g->bc_y < 0 || g->bc_y > 1) return false;
+  if (g->bc_x == WIU_BC_TRANSMISSIVE && g->nx < 2) return false;
+  if (g->bc_y == WIU_BC_TRANSMISSIVE && g->ny < 2) return false;
+  if (g->bc_x == WIU_BC_PERIODIC && !(g->period_x > 0.0)) return false;
+  if (g->bc_y == WIU_BC_PERIODIC && !(g->period_y > 0.0)) return false;
+  // launch geometry limits (grid.y <= 65535 for the row-wise launches)
+  if (g->ny > 65535 * 4 || g->nx > (1 << 28)) return false;
+  return true;
+}
+
+bool params_ok(const wiu_params* p) {
+  return p && p->gamma > 1.0 && p->alpha_lf > 0.0 && p->eps >= 0.0 && (p->ppm == 0 || p->ppm == 1);
+}
+
+bool scheme_ok(int s) { return s >= 0 && s <= 3; }
+
+Dims dims(const wiu_grid* g) {
+  Dims d;
+  d.nx = g->nx; d.ny = g->ny; d.bcx = g->bc_x; d.bcy = g->bc_y;
+  d.mpitch = g->nx + 2 * GHOST;
+  d.mplane = (long long)(g->nx + 2 * GHOST) * (g->ny + 2 * GHOST);
+  d.np = (long long)g->nx * g->ny;
+  d.Lx = g->period_x; d.Ly = g->period_y;
+  return d;
+}
+
+struct Ws {
+  int* status;
+  unsigned long long *lx, *le, *cfl;
+  double *rxi, *u1, *u2, *band;
+};
+
+Ws carve(const wiu_grid* g, void* ws) {
+  WsLayout L = layout(g);
+  char* b = (char*)ws;
+  Ws w;
+  w.status = (int*)b;
+  w.lx = (unsigned long long*)(b + L.lam);
+  w.le = w.lx + g->ny;
+  w.cfl = w.le + g->nx;
+  w.rxi = (double*)(b + L.rxi);
+  w.u1 = (double*)(b + L.u1);
+  w.u2 = (double*)(b + L.u2);
+  w.band = (double*)(b + L.scratch);
+  return w;
+}
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? WIU_OK : WIU_EHIP; }
+
+// Residual pieces shared by rhs and the RK stages: line maxima, then the xi
+// sweep into R^xi, then the eta sweep with the requested epilogue.
+int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M, const Ws& w,
+             int mode, double* out, const double* U0, const double* dt, double ca, double cb, hipStream_t st) {
+  Dims d = dims(g);
+  hipError_t e;
+  {
+    ProfScope ps(WIU_K_WAVE_MAX, st);
+    e = launch_wave_max(d, U, M, p->gamma, w.lx, w.le, w.cfl, w.status, st);
+  }
+  if (e != hipSuccess) return WIU_EHIP;
+  SweepArgs a;
+  a.d = d; a.U = U; a.M = M; a.lam_xi = w.lx; a.lam_eta = w.le;
+  a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
+  a.mode = 0; a.Rxi = w.rxi; a.out = out; a.U0 = U0; a.dt = dt; a.ca = ca; a.cb = cb; a.status = w.status;
+  {
+    ProfScope ps(WIU_K_SWEEP_XI, st);
+    e = launch_sweep(scheme, 0, a, st);
+  }
+  if (e != hipSuccess) return WIU_EHIP;
+  a.mode = mode;
+  {
+    ProfScope ps(WIU_K_SWEEP_ETA, st);
+    e = launch_sweep(scheme, 1, a, st);
+  }
+  return hip_rc(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t wiu_metrics_size(const wiu_grid* g) {
+  if (!grid_ok(g)) return 0;
+  return (9 * (size_t)(g->nx + 2 * GHOST) * (g->ny + 2 * GHOST) + 8) * sizeof(double);
+}
+
+size_t wiu_workspace_bytes(const wiu_grid* g) {
+  if (!grid_ok(g)) return 0;
+  return layout(g).total;
+}
+
+int wiu_workspace_init(void* ws, wiu_stream_t stream) {
+  if (!ws) return WIU_EINVAL;
+  return hip_rc(launch_zero_header((int*)ws, 64, (hipStream_t)stream));
+}
+
+int wiu_metrics(const wiu_grid* g, int scheme, const double* x, const double* y, double* M, void* ws,
+                wiu_stream_t stream) {
+  if (!grid_ok(g) || !scheme_ok(scheme) || !x || !y || !M || !ws) return WIU_EINVAL;
+  Ws w = carve(g, ws);
+  ProfScope ps(WIU_K_METRICS, (hipStream_t)stream);
+  return hip_rc(launch_metrics(dims(g), scheme, x, y, M, w.band, w.status, (hipStream_t)stream));
+}
+
+int wiu_set_metrics_tag(const wiu_grid* g, int scheme, double* M, wiu_stream_t stream) {
+  if (!grid_ok(g) || !scheme_ok(scheme) || !M) return WIU_EINVAL;
+  return hip_rc(launch_set_tag(dims(g), scheme, M, (hipStream_t)stream));
+}
+
+int wiu_line_eigenvalues(const wiu_grid* g, const wiu_params* p, const double* U, const double* M, double* lam_xi,
+                         double* lam_eta, void* ws, wiu_stream_t stream) {
+  if (!grid_ok(g) || !params_ok(p) || !U || !M || !lam_xi || !lam_eta || !ws) return WIU_EINVAL;
+  Ws w = carve(g, ws);
+  Dims d = dims(g);
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_wave_max(d, U, M, p->gamma, w.lx, w.le, w.cfl, w.status, st) != hipSuccess) return WIU_EHIP;
+  return hip_rc(launch_lambda_out(d, p->alpha_lf, w.lx, w.le, lam_xi, lam_eta, st));
+}
+
+int wiu_rhs(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M, double* dUdt,
+            void* ws, wiu_stream_t stream) {
+  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !dUdt || !ws) return WIU_EINVAL;
+  if (dUdt == U) return WIU_EINVAL;
+  Ws w = carve(g, ws);
+  return residual(g, scheme, p, U, M, w, 1, dUdt, U, nullptr, 0.0, 0.0, (hipStream_t)stream);
+}
+
+int wiu_cfl_dt(const wiu_grid* g, const wiu_params* p, const double* U, const double* M, double cfl, double* dt_dev,
+               void* ws, wiu_stream_t stream) {
+  if (!grid_ok(g) || !params_ok(p) || !U || !M || !dt_dev || !ws || !(cfl > 0.0)) return WIU_EINVAL;
+  Ws w = carve(g, ws);
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_wave_max(dims(g), U, M, p->gamma, w.lx, w.le, w.cfl, w.status, st) != hipSuccess) return WIU_EHIP;
+  return hip_rc(launch_cfl_dt(w.cfl, cfl, dt_dev, st));
+}
+
+int wiu_rk3_step(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
+                 const double* dt_dev, void* ws, wiu_stream_t stream) {
+  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !dt_dev || !ws) return WIU_EINVAL;
+  Ws w = carve(g, ws);
+  hipStream_t st = (hipStream_t)stream;
+  // Shu-Osher TVD-RK3: U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1));
+  // U <- 1/3 U + 2/3 (U2 + dt L(U2))
+  int rc = residual(g, scheme, p, U, M, w, 2, w.u1, U, dt_dev, 0.0, 1.0, st);
+  if (rc) return rc;
+  rc = residual(g, scheme, p, w.u1, M, w, 2, w.u2, U, dt_dev, 0.75, 0.25, st);
+  if (rc) return rc;
+  return residual(g, scheme, p, w.u2, M, w, 2, U, U, dt_dev, 1.0 / 3.0, 2.0 / 3.0, st);
+}
+
+int wiu_status(void* ws, wiu_stream_t stream, int* status, int clear) {
+  if (!ws || !status) return WIU_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (hipStreamSynchronize(st) != hipSuccess) return WIU_EHIP;
+  int v = 0;
+  if (hipMemcpy(&v, ws, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return WIU_EHIP;
+  *status = v;
+  if (clear) {
+    if (launch_zero_header((int*)ws, 1, st) != hipSuccess) return WIU_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return WIU_EHIP;
+  }
+  return WIU_OK;
+}
+
+int wiu_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return WIU_OK;
+}
+
+int wiu_profile_read(int id, long long* count, double* mean_ms) {
+  if (id < 0 || id >= WIU_K_COUNT || !count || !mean_ms) return WIU_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return WIU_EHIP;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  long long n = 0;
+  double tot = 0.0;
+  std::vector<ProfRec> keep;
+  for (auto& r : g_prof) {
+    if (r.id != id) { keep.push_back(r); continue; }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) { tot += ms; ++n; }
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_prof.swap(keep);
+  *count = n;
+  *mean_ms = n ? tot / n : 0.0;
+  return WIU_OK;
+}
+
+const char* wiu_strerror(int code) {
+  switch (code) {
+    case WIU_OK: return "ok";
+    case WIU_EINVAL: return "invalid argument";
+    case WIU_EHIP: return "HIP runtime or launch failure";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,272 @@
+// Device-side building blocks of libwenoiu (gfx950, fp64).
+//
+// Pointwise gas dynamics, the characteristic projection, the WENO
+// interpolation with mapped weights and the upwind-biased flux combination of
+// the WENOIU schemes (Li & Sun, arXiv 1810.11103).  Everything here is
+// __device__ inline code used by the kernels in wiu_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define WIU_DEV __device__ __forceinline__
+
+namespace wiu {
+
+constexpr int GHOST = 4;              // metric ghost band
+constexpr double TAG_MAGIC = 1810.11103;  // first word of the metric tag
+
+// Grid description passed by value to every kernel.
+struct Dims {
+  int nx, ny;
+  int bcx, bcy;        // 0 periodic, 1 transmissive
+  int mpitch;          // nx + 2 GHOST
+  long long mplane;    // (nx + 2 GHOST) (ny + 2 GHOST)
+  long long np;        // nx ny
+  double Lx, Ly;       // periods
+};
+
+// Status bits latched in the workspace header.
+constexpr int ST_JACOBIAN = 1, ST_NONPHYS = 2, ST_SCHEME = 4;
+
+// Map a line index onto the grid: wrap for periodic lines, clamp (copy of the
+// boundary node) for transmissive ones.  Loops run at most halo/n times.
+WIU_DEV int bc_index(int k, int n, int bc) {
+  if (bc == 0) {
+    while (k < 0) k += n;
+    while (k >= n) k -= n;
+    return k;
+  }
+  return k < 0 ? 0 : (k >= n ? n - 1 : k);
+}
+
+// Reciprocal and reciprocal square root.  Plain IEEE operations for now; the
+// call sites are the only places to change for a faster variant.
+WIU_DEV double rcp(double x) { return 1.0 / x; }
+WIU_DEV double rsqrt_(double x) { return 1.0 / sqrt(x); }
+
+// ---------------------------------------------------------------------------
+// Scheme traits: order, midpoints, and the index ranges a tile needs.
+//   node range of split fluxes f^+- : [o + NLO, o + out + NHI)
+//   midpoint range F^+-_{k+1/2}     : [o + MLO, o + out + MHI)
+// for outputs i in [o, o + out).
+// ---------------------------------------------------------------------------
+template <int SC> struct Traits;
+template <> struct Traits<0> {  // WENOIU3-1MP, Eq. 3.4
+  static constexpr bool fifth = false, two_mp = false;
+  static constexpr int NLO = -2, NHI = 2, MLO = -1, MHI = 0;
+};
+template <> struct Traits<1> {  // WENOIU3-2MP, Eq. 3.8
+  static constexpr bool fifth = false, two_mp = true;
+  static constexpr int NLO = -1, NHI = 1, MLO = -2, MHI = 1;
+};
+template <> struct Traits<2> {  // WENOIU5-1MP, Eq. 3.16
+  static constexpr bool fifth = true, two_mp = false;
+  static constexpr int NLO = -3, NHI = 3, MLO = -1, MHI = 0;
+};
+template <> struct Traits<3> {  // WENOIU5-2MP, Eq. 3.20
+  static constexpr bool fifth = true, two_mp = true;
+  static constexpr int NLO = -2, NHI = 2, MLO = -2, MHI = 1;
+};
+template <int SC> struct Range {
+  static constexpr int LO = Traits<SC>::NLO < Traits<SC>::MLO ? Traits<SC>::NLO : Traits<SC>::MLO;
+  static constexpr int HI = Traits<SC>::NHI > Traits<SC>::MHI ? Traits<SC>::NHI : Traits<SC>::MHI;
+  static constexpr int EXTRA = HI - LO;
+};
+
+// ---------------------------------------------------------------------------
+// WENO interpolation to x_{k+1/2} with mapped weights.
+// ---------------------------------------------------------------------------
+
+// Jiang-Shu indicators, Eq. 3.22, on (a, b, c) = three consecutive values.
+WIU_DEV double is_up(double a, double b, double c) {   // stencil ending at k
+  double t = a - 2.0 * b + c, s = a - 4.0 * b + 3.0 * c;
+  return (13.0 / 12.0) * t * t + 0.25 * s * s;
+}
+WIU_DEV double is_ce(double a, double b, double c) {   // centred on k
+  double t = a - 2.0 * b + c, s = a - c;
+  return (13.0 / 12.0) * t * t + 0.25 * s * s;
+}
+WIU_DEV double is_dn(double a, double b, double c) {   // stencil starting at k
+  double t = a - 2.0 * b + c, s = 3.0 * a - 4.0 * b + c;
+  return (13.0 / 12.0) * t * t + 0.25 * s * s;
+}
+
+// Third-order mapping (Eq. 3.23): C[1 + (w/C - 1)^3] below C,
+// C + (w - C)^3 / (C - 1)^2 above.
+WIU_DEV double map3(double w, double C, double invC, double k) {
+  double t = w * invC - 1.0;
+  double d = w - C;
+  double lo = C + C * (t * t * t);
+  double hi = C + k * (d * d * d);
+  return w <= C ? lo : hi;
+}
+// Second-order mapping (Eq. 3.15): C[1 - (w/C - 1)^2] below C,
+// C + (w - C)^2 / (1 - C) above.
+WIU_DEV double map2(double w, double C, double invC, double k) {
+  double t = w * invC - 1.0;
+  double d = w - C;
+  double lo = C - C * (t * t);
+  double hi = C + k * (d * d);
+  return w <= C ? lo : hi;
+}
+
+// r = 3: left-biased value at k+1/2 from v_{k-2}, ..., v_{k+2} = (a, b, c, d, e).
+// Candidates from Table 1, linear weights (1, 10, 5)/16.  The normalised weights
+// alpha_k / sum alpha with alpha_k = C_k / (eps + IS_k)^2 are formed with a
+// single reciprocal: w_k = C_k prod_{l != k} D_l / sum_m C_m prod_{l != m} D_l.
+WIU_DEV double weno5(double a, double b, double c, double d, double e, double eps, int ppm) {
+  const double p0 = 0.375 * a - 1.25 * b + 1.875 * c;
+  const double p1 = -0.125 * b + 0.75 * c + 0.375 * d;
+  const double p2 = 0.375 * c + 0.75 * d - 0.125 * e;
+  double D0 = eps + is_up(a, b, c), D1 = eps + is_ce(b, c, d), D2 = eps + is_dn(c, d, e);
+  D0 *= D0; D1 *= D1; D2 *= D2;
+  const double a0 = 0.0625 * (D1 * D2), a1 = 0.625 * (D0 * D2), a2 = 0.3125 * (D0 * D1);
+  const double r = rcp(a0 + a1 + a2);
+  double w0 = a0 * r, w1 = a1 * r, w2 = a2 * r;
+  if (ppm) {
+    w0 = map3(w0, 0.0625, 16.0, 256.0 / 225.0);
+    w1 = map3(w1, 0.625, 1.6, 64.0 / 9.0);
+    w2 = map3(w2, 0.3125, 3.2, 256.0 / 121.0);
+  }
+  return (w0 * p0 + w1 * p1 + w2 * p2) * rcp(w0 + w1 + w2);
+}
+
+// r = 2: left-biased value at k+1/2 from v_{k-2}, ..., v_{k+1} = (a, b, c, d).
+// Candidates (-v_{k-1} + 3 v_k)/2 and (v_k + v_{k+1})/2, C = (1, 3)/4, with the
+// three-point indicators IS_0, IS_1 of Eq. 3.22 (Sec. 5.1) and the mapping 3.15.
+WIU_DEV double weno3(double a, double b, double c, double d, double eps, int ppm) {
+  const double p0 = -0.5 * b + 1.5 * c;
+  const double p1 = 0.5 * c + 0.5 * d;
+  double D0 = eps + is_up(a, b, c), D1 = eps + is_ce(b, c, d);
+  D0 *= D0; D1 *= D1;
+  const double a0 = 0.25 * D1, a1 = 0.75 * D0;
+  const double r = rcp(a0 + a1);
+  double w0 = a0 * r, w1 = a1 * r;
+  if (ppm) {
+    w0 = map2(w0, 0.25, 4.0, 4.0 / 3.0);
+    w1 = map2(w1, 0.75, 4.0 / 3.0, 4.0);
+  }
+  return (w0 * p0 + w1 * p1) * rcp(w0 + w1);
+}
+
+// ---------------------------------------------------------------------------
+// Characteristic midpoint flux, one side (Secs. 2.3, 2.4, 3.4).
+//   q[m][c], m = 0..5: conservative states at k-2 .. k+3.
+//   side 0: F^+_{k+1/2}, reference Q_k, left-biased over k-2..k+2
+//   side 1: F^-_{k+1/2}, reference Q_{k+1}, right-biased over k+3..k-1
+//   (nx_, ny_): unit normal of the averaged nodal metric; (mx, my): midpoint
+//   metric; lam: line eigenvalue.
+// The projection acts on deviations from the reference state (exact for a
+// uniform state) with the left eigenvectors factored as
+//   l_1 = (A + B)/2, l_2 = e_rho - A, l_4 = (A - B)/2 applied to dQ, with
+//   A = b2 drho - b1 (u dm + v dn - de), B = (qn drho - nx dm - ny dn)/c.
+// ---------------------------------------------------------------------------
+template <bool FIFTH>
+WIU_DEV void side_flux(const double q[6][4], int side, double nx_, double ny_, double mx, double my,
+                       double lam, double gam, double eps, int ppm, double F[4]) {
+  const double* Qr = q[2 + side];
+  const double gm1 = gam - 1.0;
+  const double rr = rcp(Qr[0]);
+  const double u = Qr[1] * rr, v = Qr[2] * rr;
+  const double q2 = u * u + v * v;
+  const double p = gm1 * (Qr[3] - 0.5 * Qr[0] * q2);
+  const double c2 = gam * p * rr;
+  const double rc = rsqrt_(c2);
+  const double c = c2 * rc;
+  const double H = (Qr[3] + p) * rr;
+  const double qn = u * nx_ + v * ny_;
+  const double qt = v * nx_ - u * ny_;
+  const double b1 = gm1 * (rc * rc);
+  const double b2 = 0.5 * b1 * q2;
+
+  // stencil in sweep order: s = 0..4 (fifth) or 0..3 (third), left-biased
+  // order for side 0, mirrored for side 1
+  constexpr int NS = FIFTH ? 5 : 4;
+  double w[4][NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int m = side == 0 ? s : 5 - s;
+    const double dr = q[m][0] - Qr[0], dm = q[m][1] - Qr[1], dn = q[m][2] - Qr[2], de = q[m][3] - Qr[3];
+    const double A = b2 * dr - b1 * (u * dm + v * dn - de);
+    const double B = rc * (qn * dr - nx_ * dm - ny_ * dn);
+    w[0][s] = 0.5 * (A + B);
+    w[1][s] = dr - A;
+    w[2][s] = nx_ * dn - ny_ * dm - qt * dr;
+    w[3][s] = 0.5 * (A - B);
+  }
+  double W[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if constexpr (FIFTH) W[k] = weno5(w[k][0], w[k][1], w[k][2], w[k][3], w[k][4], eps, ppm);
+    else W[k] = weno3(w[k][0], w[k][1], w[k][2], w[k][3], eps, ppm);
+  }
+  // back to conservative variables: Q = Q_ref + R W
+  const double s03 = W[0] + W[3], d30 = W[3] - W[0];
+  const double sum = s03 + W[1];
+  const double r0 = Qr[0] + sum;
+  const double r1 = Qr[1] + (u * sum + c * nx_ * d30 - ny_ * W[2]);
+  const double r2 = Qr[2] + (v * sum + c * ny_ * d30 + nx_ * W[2]);
+  const double r3 = Qr[3] + (H * s03 + c * qn * d30 + 0.5 * q2 * W[1] + qt * W[2]);
+  // contravariant flux with the midpoint metric, then the split part
+  const double ri = rcp(r0);
+  const double ul = r1 * ri, vl = r2 * ri;
+  const double pl = gm1 * (r3 - 0.5 * (r1 * ul + r2 * vl));
+  const double Ul = mx * ul + my * vl;
+  const double sl = side == 0 ? lam : -lam;
+  F[0] = 0.5 * (r0 * Ul + sl * r0);
+  F[1] = 0.5 * (r1 * Ul + mx * pl + sl * r1);
+  F[2] = 0.5 * (r2 * Ul + my * pl + sl * r2);
+  F[3] = 0.5 * ((r3 + pl) * Ul + sl * r3);
+}
+
+// Nodal split fluxes f^+- = (E^ +- lam Q)/2 with the nodal metric (Sec. 2.3).
+WIU_DEV void nodal_split(const double Q[4], double kx, double ky, double lam, double gam, double fp[4],
+                         double fm[4]) {
+  const double ri = rcp(Q[0]);
+  const double u = Q[1] * ri, v = Q[2] * ri;
+  const double p = (gam - 1.0) * (Q[3] - 0.5 * (Q[1] * u + Q[2] * v));
+  const double U = kx * u + ky * v;
+  const double E0 = Q[0] * U, E1 = Q[1] * U + kx * p, E2 = Q[2] * U + ky * p, E3 = (Q[3] + p) * U;
+  fp[0] = 0.5 * (E0 + lam * Q[0]); fm[0] = 0.5 * (E0 - lam * Q[0]);
+  fp[1] = 0.5 * (E1 + lam * Q[1]); fm[1] = 0.5 * (E1 - lam * Q[1]);
+  fp[2] = 0.5 * (E2 + lam * Q[2]); fm[2] = 0.5 * (E2 - lam * Q[2]);
+  fp[3] = 0.5 * (E3 + lam * Q[3]); fm[3] = 0.5 * (E3 - lam * Q[3]);
+}
+
+// Wave speed |k . u| + c |k| (Sec. 2.3); returns a negative value for a
+// non-physical or non-finite state so callers can flag it.
+WIU_DEV double wave_speed(const double Q[4], double kx, double ky, double gam, bool& bad) {
+  const double ri = rcp(Q[0]);
+  const double u = Q[1] * ri, v = Q[2] * ri;
+  const double p = (gam - 1.0) * (Q[3] - 0.5 * (Q[1] * u + Q[2] * v));
+  const double s = fabs(kx * u + ky * v) + sqrt(gam * p * ri) * sqrt(kx * kx + ky * ky);
+  bad = !(Q[0] > 0.0) || !(p > 0.0) || !(s < 1.0e300);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Upwind-biased numerical flux H_{i+1/2} = h^+ + h^- (Eqs. 3.4, 3.8, 3.16,
+// 3.20, alpha = 1; h^- is h^+ mirrored about i+1/2).  fp(k), fm(k): nodal
+// split fluxes at node k; Fp(k), Fm(k): midpoint split fluxes at k+1/2.
+// ---------------------------------------------------------------------------
+template <int SC, class FP, class FM, class GP, class GM>
+WIU_DEV double hflux(int i, FP fp, FM fm, GP Fp, GM Fm) {
+  if constexpr (SC == 0) {
+    return Fp(i) + (1.0 / 24.0) * (2.0 * fp(i) - fp(i - 1) - fp(i + 1)) +
+           Fm(i) + (1.0 / 24.0) * (2.0 * fm(i + 1) - fm(i + 2) - fm(i));
+  } else if constexpr (SC == 1) {
+    return Fp(i) + (1.0 / 6.0) * (2.0 * fp(i) - Fp(i - 1) - Fp(i)) +
+           Fm(i) + (1.0 / 6.0) * (2.0 * fm(i + 1) - Fm(i + 1) - Fm(i));
+  } else if constexpr (SC == 2) {
+    return Fp(i) + (1.0 / 1920.0) * (19.0 * fp(i - 2) - 116.0 * fp(i - 1) + 154.0 * fp(i) - 36.0 * fp(i + 1) -
+                                     21.0 * fp(i + 2)) +
+           Fm(i) + (1.0 / 1920.0) * (19.0 * fm(i + 3) - 116.0 * fm(i + 2) + 154.0 * fm(i + 1) - 36.0 * fm(i) -
+                                     21.0 * fm(i - 1));
+  } else {
+    return Fp(i) + (1.0 / 30.0) * (fp(i - 1) + fp(i) - 4.0 * fp(i + 1) + 6.0 * Fp(i) - 4.0 * Fp(i - 1)) +
+           Fm(i) + (1.0 / 30.0) * (fm(i + 2) + fm(i + 1) - 4.0 * fm(i) + 6.0 * Fm(i) - 4.0 * Fm(i + 1));
+  }
+}
+
+}  // namespace wiu

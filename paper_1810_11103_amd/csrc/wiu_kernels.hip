@@ -1,0 +1,470 @@
+// HIP kernels of libwenoiu for gfx950 (fp64 throughout, no MFMA: nothing on
+// this path is a dense contraction).
+//
+//   metrics_nodal_kernel / metrics_band_kernel  grid metrics (Secs. 2.2-2.4)
+//   wave_max_kernel                             line maxima of |U^| + c|k^| and
+//                                               the CFL maximum (Sec. 2.3)
+//   sweep_kernel<scheme, dir>                   residual of one direction (Sec. 3)
+//                                               with the residual / RK epilogue
+#include "wiu_kernels.hpp"
+
+namespace wiu {
+
+// ===========================================================================
+// Metrics.  Coordinates are extended beyond the grid by the boundary rule
+// (periodic: repeat shifted by the period; transmissive: linear extension
+// from the last two nodes, applied per direction, so the extension is the
+// bilinear tensor-product one).  Derivatives are taken on coordinate
+// differences X(i+m) - X(i-m), never on absolute coordinates, so the metric
+// keeps full relative accuracy on large or offset domains.
+// ===========================================================================
+
+// Error-free sum (Knuth's TwoSum): a + b = s + e exactly.
+WIU_DEV void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  double bb = s - a;
+  double aa = s - bb;
+  e = (a - aa) + (b - bb);
+}
+
+// c[i1] - c[i0] + k L with i0, i1 inside [0, n): when the shift is non-zero
+// the difference of the stored values is close to -k L and is corrected
+// without rounding at the size of L.
+WIU_DEV double shifted_diff(double c1, double c0, int k, double L) {
+  if (k == 0) return c1 - c0;
+  double s, e;
+  two_sum(c1, -c0, s, e);
+  return (s + (double)k * L) + e;
+}
+
+// Along one real line of n values c[stride * t]: difference X(a1) - X(a0)
+// for arbitrary integer a1, a0 under the boundary rule.  `shift` says whether
+// this coordinate is the one the period shifts (x along i, y along j).
+struct LineDiff {
+  const double* c;
+  long long stride;
+  int n, bc;
+  double L;
+  bool shift;
+  WIU_DEV double at(int t) const { return c[stride * t]; }
+  WIU_DEV double operator()(int a1, int a0) const {
+    if (bc == 0) {
+      int w1 = a1, k1 = 0, w0 = a0, k0 = 0;
+      while (w1 < 0) { w1 += n; --k1; }
+      while (w1 >= n) { w1 -= n; ++k1; }
+      while (w0 < 0) { w0 += n; --k0; }
+      while (w0 >= n) { w0 -= n; ++k0; }
+      return shifted_diff(at(w1), at(w0), shift ? (k1 - k0) : 0, L);
+    }
+    // transmissive: X(a) = X(clamp(a)) + (a - clamp(a)) * step at that end
+    int c1 = a1 < 0 ? 0 : (a1 >= n ? n - 1 : a1);
+    int c0 = a0 < 0 ? 0 : (a0 >= n ? n - 1 : a0);
+    double d = at(c1) - at(c0);
+    if (a1 != c1) d += (double)(a1 - c1) * (a1 < 0 ? at(1) - at(0) : at(n - 1) - at(n - 2));
+    if (a0 != c0) d -= (double)(a0 - c0) * (a0 < 0 ? at(1) - at(0) : at(n - 1) - at(n - 2));
+    return d;
+  }
+};
+
+// Difference along i of coordinate array c (x or y) on row b (any integer):
+// rows outside a transmissive range extend linearly from the last two rows.
+WIU_DEV double diff_i(const Dims& d, const double* c, bool is_x, int b, int a1, int a0) {
+  auto row = [&](int r) {
+    LineDiff ld{c + (long long)r * d.nx, 1, d.nx, d.bcx, d.Lx, is_x};
+    return ld(a1, a0);
+  };
+  if (d.bcy == 0) return row(bc_index(b, d.ny, 0));
+  if (b < 0) { double d0 = row(0), d1 = row(1); return d0 + (double)b * (d1 - d0); }
+  if (b >= d.ny) {
+    double dl = row(d.ny - 1), d2 = row(d.ny - 2);
+    return dl + (double)(b - d.ny + 1) * (dl - d2);
+  }
+  return row(b);
+}
+
+WIU_DEV double diff_j(const Dims& d, const double* c, bool is_y, int a, int b1, int b0) {
+  auto col = [&](int cidx) {
+    LineDiff ld{c + cidx, d.nx, d.ny, d.bcy, d.Ly, is_y};
+    return ld(b1, b0);
+  };
+  if (d.bcx == 0) return col(bc_index(a, d.nx, 0));
+  if (a < 0) { double d0 = col(0), d1 = col(1); return d0 + (double)a * (d1 - d0); }
+  if (a >= d.nx) {
+    double dl = col(d.nx - 1), d2 = col(d.nx - 2);
+    return dl + (double)(a - d.nx + 1) * (dl - d2);
+  }
+  return col(a);
+}
+
+// Each scheme's central operator delta^{c,(1)} (Eqs. 3.7, 3.9, 3.19, 3.21)
+// with the six-point midpoint interpolation
+// (3 g_{i-2} - 25 g_{i-1} + 150 g_i + 150 g_{i+1} - 25 g_{i+2} + 3 g_{i+3}) / 256
+// substituted is an antisymmetric node stencil sum_m d_m (g_{i+m} - g_{i-m}):
+__constant__ double kMetricStencil[4][4] = {
+    {557.0 / 768.0, -25.0 / 192.0, 3.0 / 256.0, 0.0},                 // 3-1MP
+    {1145.0 / 1536.0, -229.0 / 1536.0, 29.0 / 1536.0, -1.0 / 1024.0},  // 3-2MP
+    {3.0 / 4.0, -3.0 / 20.0, 1.0 / 60.0, 0.0},                        // 5-1MP
+    {487.0 / 640.0, -103.0 / 640.0, 41.0 / 1920.0, -1.0 / 1280.0},    // 5-2MP
+};
+
+// Nodal metrics on the band of width B around the grid: T[5][(ny+2B)(nx+2B)].
+// Periodic directions evaluate at the wrapped node so that band copies are
+// bitwise equal to the interior values.
+__global__ void metrics_nodal_kernel(Dims d, int scheme, int B, const double* __restrict__ x,
+                                     const double* __restrict__ y, double* __restrict__ T) {
+  const int W = d.nx + 2 * B, Hh = d.ny + 2 * B;
+  const int ta = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tb = blockIdx.y * blockDim.y + threadIdx.y;
+  if (ta >= W || tb >= Hh) return;
+  int a = ta - B, b = tb - B;
+  if (d.bcx == 0) a = bc_index(a, d.nx, 0);
+  if (d.bcy == 0) b = bc_index(b, d.ny, 0);
+  double x_xi = 0.0, y_xi = 0.0, x_eta = 0.0, y_eta = 0.0;
+#pragma unroll
+  for (int m = 1; m <= 4; ++m) {
+    const double cm = kMetricStencil[scheme][m - 1];
+    if (cm == 0.0) continue;
+    x_xi += cm * diff_i(d, x, true, b, a + m, a - m);
+    y_xi += cm * diff_i(d, y, false, b, a + m, a - m);
+    x_eta += cm * diff_j(d, x, false, a, b + m, b - m);
+    y_eta += cm * diff_j(d, y, true, a, b + m, b - m);
+  }
+  const long long P = (long long)W * Hh, o = (long long)tb * W + ta;
+  // Sec. 2.2 in two dimensions
+  T[0 * P + o] = y_eta;                          // xi_x^
+  T[1 * P + o] = -x_eta;                         // xi_y^
+  T[2 * P + o] = -y_xi;                          // eta_x^
+  T[3 * P + o] = x_xi;                           // eta_y^
+  T[4 * P + o] = x_xi * y_eta - x_eta * y_xi;    // J^{-1}
+}
+
+// Nodal and midpoint metrics on the stored band (width GHOST) plus the tag.
+__global__ void metrics_band_kernel(Dims d, int scheme, int B, const double* __restrict__ T,
+                                    double* __restrict__ M, int* __restrict__ status) {
+  const int W = d.nx + 2 * GHOST, Hh = d.ny + 2 * GHOST;
+  const int ta = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tb = blockIdx.y * blockDim.y + threadIdx.y;
+  if (ta == 0 && tb == 0) {
+    double* tag = M + 9 * d.mplane;
+    tag[0] = TAG_MAGIC; tag[1] = (double)scheme; tag[2] = (double)d.nx; tag[3] = (double)d.ny;
+    tag[4] = (double)d.bcx; tag[5] = (double)d.bcy; tag[6] = 0.0; tag[7] = 0.0;
+  }
+  if (ta >= W || tb >= Hh) return;
+  const int a = ta - GHOST, b = tb - GHOST;
+  const int TW = d.nx + 2 * B;
+  const long long TP = (long long)TW * (d.ny + 2 * B);
+  auto t = [&](int p, int aa, int bb) { return T[p * TP + (long long)(bb + B) * TW + (aa + B)]; };
+  const long long o = (long long)tb * W + ta;
+  const long long P = d.mplane;
+#pragma unroll
+  for (int p = 0; p < 5; ++p) M[p * P + o] = t(p, a, b);
+  // midpoint metrics: the same interpolation in the metric's own direction
+  auto I = [&](int p, int di, int dj) {
+    return (3.0 * t(p, a - 2 * di, b - 2 * dj) - 25.0 * t(p, a - di, b - dj) + 150.0 * t(p, a, b) +
+            150.0 * t(p, a + di, b + dj) - 25.0 * t(p, a + 2 * di, b + 2 * dj) + 3.0 * t(p, a + 3 * di, b + 3 * dj)) *
+           (1.0 / 256.0);
+  };
+  M[5 * P + o] = I(0, 1, 0);
+  M[6 * P + o] = I(1, 1, 0);
+  M[7 * P + o] = I(2, 0, 1);
+  M[8 * P + o] = I(3, 0, 1);
+  if (a >= 0 && a < d.nx && b >= 0 && b < d.ny) {
+    const double j = t(4, a, b);
+    if (!(j > 0.0) || !(j < 1.0e300)) atomicOr(status, ST_JACOBIAN);
+  }
+}
+
+// ===========================================================================
+// Wave-speed maxima (Sec. 2.3): lam_xi[j] = max_i (|U^| + c|xi^|) over row j,
+// lam_eta[i] over column i, and the CFL maximum of the sum over J^{-1}.
+// Values are non-negative, so the order of their IEEE bit patterns as
+// unsigned integers is their numeric order and an integer atomic max gives an
+// order-independent (deterministic) result.  Non-physical or non-finite
+// states latch ST_NONPHYS.
+// ===========================================================================
+__global__ void __launch_bounds__(256) wave_max_kernel(Dims d, const double* __restrict__ U,
+                                                       const double* __restrict__ M, double gam,
+                                                       unsigned long long* __restrict__ lam_xi,
+                                                       unsigned long long* __restrict__ lam_eta,
+                                                       unsigned long long* __restrict__ cfl_max,
+                                                       int* __restrict__ status) {
+  // block: 64 columns x 4 thread rows, each thread row covers ROWS rows
+  constexpr int ROWS = 4;
+  __shared__ double scol[4][64];
+  __shared__ double scfl[4];
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j0 = (blockIdx.y * 4 + threadIdx.y) * ROWS;
+  double colmax = 0.0, cflm = 0.0;
+  bool bad_any = false;
+  for (int r = 0; r < ROWS; ++r) {
+    const int j = j0 + r;
+    double sx = 0.0;
+    if (i < d.nx && j < d.ny) {
+      const long long o = (long long)j * d.nx + i;
+      const double Q[4] = {U[o], U[d.np + o], U[2 * d.np + o], U[3 * d.np + o]};
+      const long long mo = (long long)(j + GHOST) * d.mpitch + (i + GHOST);
+      bool b1, b2;
+      sx = wave_speed(Q, M[mo], M[d.mplane + mo], gam, b1);
+      const double se = wave_speed(Q, M[2 * d.mplane + mo], M[3 * d.mplane + mo], gam, b2);
+      bad_any |= b1 || b2;
+      colmax = fmax(colmax, se);  // non-finite speeds are flagged through `status`
+      cflm = fmax(cflm, (sx + se) / M[4 * d.mplane + mo]);
+    }
+    // row max across the 64 lanes of this wave (one wave = one row segment)
+    double v = sx;
+    for (int off = 32; off > 0; off >>= 1) {
+      v = fmax(v, __shfl_xor(v, off, 64));
+    }
+    if (threadIdx.x == 0 && j < d.ny)
+      atomicMax(&lam_xi[j], (unsigned long long)__double_as_longlong(v));
+  }
+  scol[threadIdx.y][threadIdx.x] = colmax;
+  double c = cflm;
+  for (int off = 32; off > 0; off >>= 1) {
+    c = fmax(c, __shfl_xor(c, off, 64));
+  }
+  if (threadIdx.x == 0) scfl[threadIdx.y] = c;
+  if (bad_any) atomicOr(status, ST_NONPHYS);
+  __syncthreads();
+  if (threadIdx.y == 0) {
+    double m = scol[0][threadIdx.x];
+    for (int t = 1; t < 4; ++t) m = fmax(m, scol[t][threadIdx.x]);
+    if (i < d.nx) atomicMax(&lam_eta[i], (unsigned long long)__double_as_longlong(m));
+    if (threadIdx.x == 0 && cfl_max) {
+      double mm = scfl[0];
+      for (int t = 1; t < 4; ++t) mm = fmax(mm, scfl[t]);
+      atomicMax(cfl_max, (unsigned long long)__double_as_longlong(mm));
+    }
+  }
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, long long n, unsigned long long v) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+__global__ void cfl_dt_kernel(const unsigned long long* cfl_max, double cfl, double* dt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) dt[0] = cfl / __longlong_as_double((long long)cfl_max[0]);
+}
+
+__global__ void lambda_out_kernel(Dims d, double alpha, const unsigned long long* lx, const unsigned long long* le,
+                                  double* out_x, double* out_e) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < d.ny) out_x[t] = alpha * __longlong_as_double((long long)lx[t]);
+  if (t < d.nx) out_e[t] = alpha * __longlong_as_double((long long)le[t]);
+}
+
+// ===========================================================================
+// Direction sweep.  One block covers NB grid lines of one direction and a
+// segment of OUT = NA - EXTRA output nodes along them.  Each thread owns one
+// item k along its line: the split fluxes f^+-_k at node k and the midpoint
+// fluxes F^+-_{k+1/2}; the items go to LDS, then the first OUT threads of
+// each line form H_{i+1/2} - H_{i-1/2} for their output node.
+//   DIR 0 (xi):  threadIdx.x runs along i, threadIdx.y across rows j.
+//   DIR 1 (eta): threadIdx.x runs across columns i, threadIdx.y along j.
+// Epilogue: mode 0 writes R^xi; mode 1 writes dU/dt = -(R^xi + R^eta)/J^{-1};
+// mode 2 writes an RK stage U_out = a U0 + b Us + c dt dU/dt.
+// ===========================================================================
+template <int SC, int DIR, int NA, int NB>
+__global__ void __launch_bounds__(NA * NB) sweep_kernel(SweepArgs s) {
+  using R_ = Range<SC>;
+  constexpr int OUT = NA - R_::EXTRA;
+  constexpr int NT = NA * NB;
+  __shared__ double sh[16][NT];  // [kind*4 + comp][item]: kinds fp, fm, Fp, Fm
+
+  const Dims& d = s.d;
+  // metrics built for another scheme or grid: flag and do nothing
+  {
+    const double* tag = s.M + 9 * d.mplane;
+    if (tag[0] != TAG_MAGIC || tag[1] != (double)SC || tag[2] != (double)d.nx || tag[3] != (double)d.ny) {
+      if (threadIdx.x == 0 && threadIdx.y == 0) atomicOr(s.status, ST_SCHEME);
+      return;
+    }
+  }
+  const int ta = DIR == 0 ? threadIdx.x : threadIdx.y;  // along
+  const int tb = DIR == 0 ? threadIdx.y : threadIdx.x;  // across
+  const int n_al = DIR == 0 ? d.nx : d.ny;
+  const int n_ac = DIR == 0 ? d.ny : d.nx;
+  const int bc_al = DIR == 0 ? d.bcx : d.bcy;
+  const int line = (DIR == 0 ? blockIdx.y : blockIdx.x) * NB + tb;
+  const int o0 = (DIR == 0 ? blockIdx.x : blockIdx.y) * OUT;
+  const int out = min(OUT, n_al - o0);
+  const int k = o0 + R_::LO + ta;
+  const int slot = tb * NA + ta;
+  const bool live = line < n_ac;
+
+  // element offsets
+  const long long qstride = DIR == 0 ? 1 : d.nx;                       // along the line in U
+  const long long qline = DIR == 0 ? (long long)line * d.nx : line;    // line origin in U
+  const long long mstride = DIR == 0 ? 1 : d.mpitch;
+  const long long mline = DIR == 0 ? (long long)(line + GHOST) * d.mpitch + GHOST
+                                   : (long long)GHOST * d.mpitch + (line + GHOST);
+  const double* Mk = s.M + (DIR == 0 ? 0 : 2) * d.mplane;   // nodal k_x^ plane
+  const double* Mm = s.M + (DIR == 0 ? 5 : 7) * d.mplane;   // midpoint plane
+  const double gam = s.gamma;
+
+  double lam = 0.0;
+  if (live) {
+    const unsigned long long* lp = DIR == 0 ? s.lam_xi : s.lam_eta;
+    lam = s.alpha * __longlong_as_double((long long)lp[line]);
+  }
+
+  const bool need_node = live && k >= o0 + Traits<SC>::NLO && k < o0 + out + Traits<SC>::NHI;
+  const bool need_mid = live && k >= o0 + Traits<SC>::MLO && k < o0 + out + Traits<SC>::MHI;
+
+  if (need_node || need_mid) {
+    // stencil states Q_{k-2..k+3}
+    double q[6][4];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      const long long o = qline + qstride * bc_index(k - 2 + m, n_al, bc_al);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[m][c] = s.U[c * d.np + o];
+    }
+    const long long mo = mline + mstride * k;
+    const double kx0 = Mk[mo], ky0 = Mk[d.mplane + mo];
+    if (need_node) {
+      double fp[4], fm[4];
+      nodal_split(q[2], kx0, ky0, lam, gam, fp, fm);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) { sh[c][slot] = fp[c]; sh[4 + c][slot] = fm[c]; }
+    }
+    if (need_mid) {
+      const double kx1 = Mk[mo + mstride], ky1 = Mk[d.mplane + mo + mstride];
+      const double mx = Mm[mo], my = Mm[d.mplane + mo];
+      const double nbx = 0.5 * (kx0 + kx1), nby = 0.5 * (ky0 + ky1);
+      const double rn = rsqrt_(nbx * nbx + nby * nby);
+      const double nx_ = nbx * rn, ny_ = nby * rn;
+      double Fp[4], Fm[4];
+      side_flux<Traits<SC>::fifth>(q, 0, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, Fp);
+      side_flux<Traits<SC>::fifth>(q, 1, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, Fm);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) { sh[8 + c][slot] = Fp[c]; sh[12 + c][slot] = Fm[c]; }
+    }
+  }
+  __syncthreads();
+
+  if (!live || ta >= out) return;
+  const int i = o0 + ta;                  // output node along the line
+  const int base = tb * NA - (o0 + R_::LO);  // slot of line index kk is base + kk
+  double R[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    auto fp = [&](int kk) { return sh[c][base + kk]; };
+    auto fm = [&](int kk) { return sh[4 + c][base + kk]; };
+    auto Fp = [&](int kk) { return sh[8 + c][base + kk]; };
+    auto Fm = [&](int kk) { return sh[12 + c][base + kk]; };
+    R[c] = hflux<SC>(i, fp, fm, Fp, Fm) - hflux<SC>(i - 1, fp, fm, Fp, Fm);
+  }
+  const long long o = DIR == 0 ? (long long)line * d.nx + i : (long long)i * d.nx + line;
+  if (s.mode == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s.Rxi[c * d.np + o] = R[c];
+    return;
+  }
+  const int ii = DIR == 0 ? i : line, jj = DIR == 0 ? line : i;
+  const double jinv = s.M[4 * d.mplane + (long long)(jj + GHOST) * d.mpitch + (ii + GHOST)];
+  const double rj = -rcp(jinv);
+  if (s.mode == 1) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s.out[c * d.np + o] = (s.Rxi[c * d.np + o] + R[c]) * rj;
+    return;
+  }
+  const double dt = s.dt[0];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double L = (s.Rxi[c * d.np + o] + R[c]) * rj;
+    const long long e = c * d.np + o;
+    s.out[e] = s.ca * s.U0[e] + s.cb * (s.U[e] + dt * L);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+template <int SC, int DIR>
+hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
+  constexpr int NA = DIR == 0 ? 128 : 32;
+  constexpr int NB = DIR == 0 ? 1 : 16;
+  constexpr int OUT = NA - Range<SC>::EXTRA;
+  const int n_al = DIR == 0 ? a.d.nx : a.d.ny;
+  const int n_ac = DIR == 0 ? a.d.ny : a.d.nx;
+  const int nseg = (n_al + OUT - 1) / OUT;
+  const int nlin = (n_ac + NB - 1) / NB;
+  dim3 grid = DIR == 0 ? dim3(nseg, nlin) : dim3(nlin, nseg);
+  dim3 block = DIR == 0 ? dim3(NA, NB) : dim3(NB, NA);
+  hipLaunchKernelGGL((sweep_kernel<SC, DIR, NA, NB>), grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(int scheme, int dir, const SweepArgs& a, hipStream_t st) {
+  switch (scheme * 2 + dir) {
+    case 0: return launch_sweep_t<0, 0>(a, st);
+    case 1: return launch_sweep_t<0, 1>(a, st);
+    case 2: return launch_sweep_t<1, 0>(a, st);
+    case 3: return launch_sweep_t<1, 1>(a, st);
+    case 4: return launch_sweep_t<2, 0>(a, st);
+    case 5: return launch_sweep_t<2, 1>(a, st);
+    case 6: return launch_sweep_t<3, 0>(a, st);
+    default: return launch_sweep_t<3, 1>(a, st);
+  }
+}
+
+hipError_t launch_wave_max(const Dims& d, const double* U, const double* M, double gam, unsigned long long* lx,
+                           unsigned long long* le, unsigned long long* cfl, int* status, hipStream_t st) {
+  // clear the maxima (a fill kernel, not a memset, so the sequence can be captured)
+  const long long n = (long long)d.nx + d.ny + 1;
+  // lx, le and cfl are contiguous in the workspace: lx[ny], le[nx], cfl[1]
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, lx, n, 0ull);
+  dim3 grid((d.nx + 63) / 64, (d.ny + 15) / 16);
+  hipLaunchKernelGGL(wave_max_kernel, grid, dim3(64, 4), 0, st, d, U, M, gam, lx, le, cfl, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_metrics(const Dims& d, int scheme, const double* x, const double* y, double* M, double* T,
+                          int* status, hipStream_t st) {
+  const int B = GHOST + 3;
+  dim3 b1(64, 4);
+  dim3 g1((d.nx + 2 * B + 63) / 64, (d.ny + 2 * B + 3) / 4);
+  hipLaunchKernelGGL(metrics_nodal_kernel, g1, b1, 0, st, d, scheme, B, x, y, T);
+  dim3 g2((d.nx + 2 * GHOST + 63) / 64, (d.ny + 2 * GHOST + 3) / 4);
+  hipLaunchKernelGGL(metrics_band_kernel, g2, b1, 0, st, d, scheme, B, T, M, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_dt(const unsigned long long* cfl_max, double cfl, double* dt, hipStream_t st) {
+  hipLaunchKernelGGL(cfl_dt_kernel, dim3(1), dim3(64), 0, st, cfl_max, cfl, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda_out(const Dims& d, double alpha, const unsigned long long* lx, const unsigned long long* le,
+                             double* ox, double* oe, hipStream_t st) {
+  int n = d.nx > d.ny ? d.nx : d.ny;
+  hipLaunchKernelGGL(lambda_out_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d, alpha, lx, le, ox, oe);
+  return hipGetLastError();
+}
+
+__global__ void set_tag_kernel(Dims d, int scheme, double* M) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double* tag = M + 9 * d.mplane;
+    tag[0] = TAG_MAGIC; tag[1] = (double)scheme; tag[2] = (double)d.nx; tag[3] = (double)d.ny;
+    tag[4] = (double)d.bcx; tag[5] = (double)d.bcy; tag[6] = 0.0; tag[7] = 0.0;
+  }
+}
+
+hipError_t launch_set_tag(const Dims& d, int scheme, double* M, hipStream_t st) {
+  hipLaunchKernelGGL(set_tag_kernel, dim3(1), dim3(64), 0, st, d, scheme, M);
+  return hipGetLastError();
+}
+
+__global__ void zero_int_kernel(int* p, int n) {
+  int t = threadIdx.x;
+  if (t < n) p[t] = 0;
+}
+
+hipError_t launch_zero_header(int* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace wiu

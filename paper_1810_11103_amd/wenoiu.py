@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libwenoiu (include/wenoiu.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libwenoiu.so.  Tensors are torch tensors on the ROCm device (fp64,
+contiguous); the current torch stream is passed as the HIP stream.  There is
+no CPU fallback: if the library is missing the import of this module fails.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwenoiu.so")
+
+SCHEMES = {"3-1MP": 0, "3-2MP": 1, "5-1MP": 2, "5-2MP": 3}
+BC = {"periodic": 0, "transmissive": 1}
+GHOST = 4
+ST_JACOBIAN, ST_NONPHYS, ST_SCHEME = 1, 2, 4
+WIU_OK, WIU_EINVAL, WIU_EHIP = 0, -1, -2
+
+EXPORTS = [
+    "wiu_metrics_size", "wiu_workspace_bytes", "wiu_workspace_init", "wiu_metrics", "wiu_set_metrics_tag",
+    "wiu_line_eigenvalues", "wiu_rhs", "wiu_cfl_dt", "wiu_rk3_step", "wiu_status", "wiu_strerror",
+    "wiu_profile_enable", "wiu_profile_read",
+]
+KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3}
+
+
+class WiuGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
+                ("period_x", ctypes.c_double), ("period_y", ctypes.c_double)]
+
+
+class WiuParams(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("alpha_lf", ctypes.c_double), ("eps", ctypes.c_double),
+                ("ppm", ctypes.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libwenoiu.so not built ({LIB_PATH}); run paper_1810_11103_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    G = ctypes.POINTER(WiuGrid)
+    PR = ctypes.POINTER(WiuParams)
+    I = ctypes.c_int
+    sig = {
+        "wiu_metrics_size": (ctypes.c_size_t, [G]),
+        "wiu_workspace_bytes": (ctypes.c_size_t, [G]),
+        "wiu_workspace_init": (I, [P, P]),
+        "wiu_metrics": (I, [G, I, P, P, P, P, P]),
+        "wiu_set_metrics_tag": (I, [G, I, P, P]),
+        "wiu_line_eigenvalues": (I, [G, PR, P, P, P, P, P, P]),
+        "wiu_rhs": (I, [G, I, PR, P, P, P, P, P]),
+        "wiu_cfl_dt": (I, [G, PR, P, P, ctypes.c_double, P, P, P]),
+        "wiu_rk3_step": (I, [G, I, PR, P, P, P, P, P]),
+        "wiu_status": (I, [P, P, ctypes.POINTER(I), I]),
+        "wiu_strerror": (ctypes.c_char_p, [I]),
+        "wiu_profile_enable": (I, [I]),
+        "wiu_profile_read": (I, [I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+class WiuError(RuntimeError):
+    pass
+
+
+def _check(rc):
+    if rc != WIU_OK:
+        raise WiuError(f"libwenoiu: {lib.wiu_strerror(rc).decode()} ({rc})")
+
+
+def scheme_id(s):
+    return SCHEMES[s] if isinstance(s, str) else int(s)
+
+
+def make_grid(nx, ny, bc=("periodic", "periodic"), period=(0.0, 0.0)):
+    bx = BC[bc[0]] if isinstance(bc[0], str) else int(bc[0])
+    by = BC[bc[1]] if isinstance(bc[1], str) else int(bc[1])
+    return WiuGrid(int(nx), int(ny), bx, by, float(period[0]), float(period[1]))
+
+
+def make_params(gamma=1.4, alpha_lf=1.1, eps=1e-40, ppm=1):
+    return WiuParams(float(gamma), float(alpha_lf), float(eps), int(ppm))
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "fp64 contiguous device tensor expected"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def metrics_size(grid):
+    return lib.wiu_metrics_size(ctypes.byref(grid))
+
+
+def workspace_bytes(grid):
+    return lib.wiu_workspace_bytes(ctypes.byref(grid))
+
+
+def workspace(grid, device="cuda"):
+    """A zero-initialised workspace tensor for `grid` (uint8)."""
+    n = workspace_bytes(grid)
+    if n == 0:
+        raise WiuError("invalid grid")
+    ws = torch.zeros(n, dtype=torch.uint8, device=device)
+    return ws
+
+
+def metrics_tensor(grid, device="cuda"):
+    n = metrics_size(grid)
+    if n == 0:
+        raise WiuError("invalid grid")
+    return torch.empty(n // 8, dtype=torch.float64, device=device)
+
+
+def metric_planes(M, grid):
+    """View of the nine metric planes (9, ny + 2G, nx + 2G)."""
+    H, W = grid.ny + 2 * GHOST, grid.nx + 2 * GHOST
+    return M[: 9 * H * W].view(9, H, W)
+
+
+def workspace_init(ws, stream=None):
+    _check(lib.wiu_workspace_init(ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+
+
+def metrics(grid, scheme, x, y, M, ws, stream=None):
+    _check(lib.wiu_metrics(ctypes.byref(grid), scheme_id(scheme), _ptr(x), _ptr(y), _ptr(M),
+                           ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+    return M
+
+
+def set_metrics_tag(grid, scheme, M, stream=None):
+    _check(lib.wiu_set_metrics_tag(ctypes.byref(grid), scheme_id(scheme), _ptr(M), _stream(stream)))
+
+
+def line_eigenvalues(grid, params, U, M, lam_xi, lam_eta, ws, stream=None):
+    _check(lib.wiu_line_eigenvalues(ctypes.byref(grid), ctypes.byref(params), _ptr(U), _ptr(M), _ptr(lam_xi),
+                                    _ptr(lam_eta), ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+
+
+def rhs(grid, scheme, params, U, M, dUdt, ws, stream=None):
+    _check(lib.wiu_rhs(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U), _ptr(M), _ptr(dUdt),
+                       ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+    return dUdt
+
+
+def cfl_dt(grid, params, U, M, cfl, dt_dev, ws, stream=None):
+    _check(lib.wiu_cfl_dt(ctypes.byref(grid), ctypes.byref(params), _ptr(U), _ptr(M), float(cfl), _ptr(dt_dev),
+                          ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+    return dt_dev
+
+
+def rk3_step(grid, scheme, params, U, M, dt_dev, ws, stream=None):
+    _check(lib.wiu_rk3_step(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U), _ptr(M),
+                            _ptr(dt_dev), ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+    return U
+
+
+def status(ws, clear=True, stream=None):
+    v = ctypes.c_int(0)
+    _check(lib.wiu_status(ctypes.c_void_p(ws.data_ptr()), _stream(stream), ctypes.byref(v), int(clear)))
+    return v.value
+
+
+def profile_enable(on=True):
+    _check(lib.wiu_profile_enable(int(bool(on))))
+
+
+def profile_read(kernel):
+    """(launch count, mean duration in ms) of a library kernel since the last read."""
+    n = ctypes.c_longlong(0)
+    ms = ctypes.c_double(0.0)
+    _check(lib.wiu_profile_read(KERNELS[kernel] if isinstance(kernel, str) else int(kernel), ctypes.byref(n),
+                                ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+class Solver:
+    """Device-resident grid, metrics and workspace for one WENOIU problem."""
+
+    def __init__(self, x, y, scheme="5-2MP", bc=("periodic", "periodic"), period=(0.0, 0.0), params=None,
+                 device="cuda"):
+        x = torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
+        y = torch.as_tensor(y, dtype=torch.float64).to(device).contiguous()
+        ny, nx = x.shape
+        self.scheme = scheme
+        self.grid = make_grid(nx, ny, bc, period)
+        self.params = params or make_params()
+        self.device = device
+        self.ws = workspace(self.grid, device)
+        workspace_init(self.ws)
+        self.M = metrics_tensor(self.grid, device)
+        metrics(self.grid, scheme, x, y, self.M, self.ws)
+        self.x, self.y = x, y
+        self.dt = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def rhs(self, U, out=None):
+        out = torch.empty_like(U) if out is None else out
+        return rhs(self.grid, self.scheme, self.params, U, self.M, out, self.ws)
+
+    def cfl_dt(self, U, cfl):
+        return cfl_dt(self.grid, self.params, U, self.M, cfl, self.dt, self.ws)
+
+    def rk3_step(self, U, dt=None):
+        if dt is not None:
+            self.dt.fill_(float(dt))
+        return rk3_step(self.grid, self.scheme, self.params, U, self.M, self.dt, self.ws)
+
+    def line_eigenvalues(self, U):
+        lx = torch.empty(self.grid.ny, dtype=torch.float64, device=self.device)
+        le = torch.empty(self.grid.nx, dtype=torch.float64, device=self.device)
+        line_eigenvalues(self.grid, self.params, U, self.M, lx, le, self.ws)
+        return lx, le
+
+    def status(self, clear=True):
+        return status(self.ws, clear)
+
+    def planes(self):
+        return metric_planes(self.M, self.grid)

@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/wenoiu.h, sizes are as documented and
+argument errors are caught on the host before anything is launched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wenoiu.h")
+LIB = os.path.join(ROOT, "paper_1810_11103_amd", "libwenoiu.so")
+
+
+@pytest.fixture(scope="module")
+def wiu():
+    if not os.path.exists(LIB):
+        from paper_1810_11103_amd import build
+        build.build()
+    from paper_1810_11103_amd import wenoiu
+    return wenoiu
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wiu_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("wiu_metrics", "wiu_rhs", "wiu_rk3_step", "wiu_cfl_dt", "wiu_status", "wiu_workspace_bytes"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(wiu):
+    lib = ctypes.CDLL(LIB)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert sorted(wiu.EXPORTS) == sorted(declared_functions())
+
+
+def test_sizes(wiu):
+    g = wiu.make_grid(100, 60, ("periodic", "transmissive"), (1.0, 0.0))
+    assert wiu.metrics_size(g) == (9 * 108 * 68 + 8) * 8
+    ws = wiu.workspace_bytes(g)
+    assert ws % 256 == 0 and ws >= 12 * 100 * 60 * 8
+
+
+@pytest.mark.parametrize("nx,ny,bc,period", [
+    (0, 10, ("periodic", "periodic"), (1, 1)),
+    (10, -1, ("periodic", "periodic"), (1, 1)),
+    (1, 10, ("transmissive", "periodic"), (0, 1)),
+    (10, 10, ("periodic", "periodic"), (0, 1)),
+    (10, 10, (2, 0), (1, 1)),
+])
+def test_bad_grids_rejected_on_host(wiu, nx, ny, bc, period):
+    g = wiu.make_grid(nx, ny, bc, period)
+    assert wiu.metrics_size(g) == 0
+    assert wiu.workspace_bytes(g) == 0
+    p = wiu.make_params()
+    rc = wiu.lib.wiu_rhs(ctypes.byref(g), 3, ctypes.byref(p), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                         ctypes.c_void_p(16), ctypes.c_void_p(8), None)
+    assert rc == wiu.WIU_EINVAL
+
+
+def test_bad_scheme_params_and_pointers_rejected(wiu):
+    g = wiu.make_grid(16, 16, ("periodic", "periodic"), (1.0, 1.0))
+    p = wiu.make_params()
+    dummy = ctypes.c_void_p(256)
+    other = ctypes.c_void_p(512)
+    assert wiu.lib.wiu_rhs(ctypes.byref(g), 4, ctypes.byref(p), dummy, dummy, other, dummy, None) == wiu.WIU_EINVAL
+    assert wiu.lib.wiu_rhs(ctypes.byref(g), 3, ctypes.byref(p), dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL
+    assert wiu.lib.wiu_rhs(ctypes.byref(g), 3, ctypes.byref(p), None, dummy, other, dummy, None) == wiu.WIU_EINVAL
+    bad = wiu.make_params(gamma=1.0)
+    assert wiu.lib.wiu_rhs(ctypes.byref(g), 3, ctypes.byref(bad), dummy, dummy, other, dummy, None) == wiu.WIU_EINVAL
+    assert wiu.lib.wiu_metrics(ctypes.byref(g), -1, dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL
+    assert wiu.lib.wiu_cfl_dt(ctypes.byref(g), ctypes.byref(p), dummy, dummy, ctypes.c_double(-1.0), dummy, dummy,
+                              None) == wiu.WIU_EINVAL
+    assert wiu.lib.wiu_strerror(wiu.WIU_EINVAL) == b"invalid argument"

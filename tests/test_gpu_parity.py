@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bar (written per test): metrics and line eigenvalues within 1e-13 of the
+plane's magnitude; rhs within 1e-12 normwise per conservative component
+(max |gpu - oracle| <= 1e-12 max |oracle|); free-stream preservation
+max |dU/dt| < 1e-11 for uniform flow on randomized grids."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1810_11103_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = ["3-1MP", "3-2MP", "5-1MP", "5-2MP"]
+G = 4
+
+
+@pytest.fixture(scope="module")
+def wiu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    from paper_1810_11103_amd import wenoiu
+    return wenoiu
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).cuda()
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def normwise(gpu, ref):
+    """max_ij |gpu - ref| / max_ij |ref| per conservative component."""
+    return np.array([np.abs(gpu[c] - ref[c]).max() / max(np.abs(ref[c]).max(), 1e-300) for c in range(4)])
+
+
+def make_case(kind, nx, ny, seed=0):
+    if kind == "vortex":
+        g = W.periodic_grid(nx, ny, (0, 10, 0, 10), A=0.2, seed=seed)
+        U = W.vortex_periodic_state(g)
+    elif kind == "smooth":
+        g = W.periodic_grid(nx, ny, (0, 10, 0, 10), A=0.2, seed=seed)
+        U = W.random_smooth_state(g, seed=seed)
+    elif kind == "riemann":
+        g = W.bounded_grid(nx, ny, (0, 1, 0, 1), A=0.2, seed=seed)
+        U = W.riemann_state(g)
+    elif kind == "strip":
+        g = W.strip_grid(nx)
+        U = W.sod_state(g)
+    else:
+        raise ValueError(kind)
+    return g, U
+
+
+CASES = [("vortex", 300, 70), ("smooth", 131, 67), ("riemann", 260, 90), ("strip", 203, 1)]
+
+
+@pytest.mark.parametrize("s", SCHEMES)
+@pytest.mark.parametrize("kind,nx,ny", CASES)
+def test_metrics_parity(orc, wiu, s, kind, nx, ny):
+    say("metrics parity", s, kind, nx, ny)
+    g, _ = make_case(kind, nx, ny, seed=11)
+    Mo = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period)
+    Mg = _host(sol.planes())
+    assert sol.status() == 0
+    for p in range(9):
+        scale = np.abs(Mo[p]).max()
+        err = np.abs(Mg[p] - Mo[p]).max()
+        assert err <= 1e-13 * scale, (p, err, scale)
+
+
+@pytest.mark.parametrize("kind,nx,ny", CASES)
+def test_line_eigenvalue_parity(orc, wiu, kind, nx, ny):
+    say("lambda parity", kind, nx, ny)
+    g, U = make_case(kind, nx, ny, seed=3)
+    s = "5-2MP"
+    Mo = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    _, lx, le = orc.rhs(s, U, Mo, g.bc, return_lambda=True)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period)
+    gx, ge = sol.line_eigenvalues(_dev(U))
+    np.testing.assert_allclose(_host(gx), lx, rtol=1e-13)
+    np.testing.assert_allclose(_host(ge), le, rtol=1e-13)
+
+
+def _gpu_rhs_with_metrics(wiu, g, s, U, M_planes):
+    """rhs on the GPU with externally supplied metric planes (tagged)."""
+    import torch
+    grid = wiu.make_grid(g.x.shape[1], g.x.shape[0], g.bc, g.period)
+    M = wiu.metrics_tensor(grid)
+    H, Wd = grid.ny + 2 * G, grid.nx + 2 * G
+    M[: 9 * H * Wd] = _dev(M_planes).reshape(-1)
+    wiu.set_metrics_tag(grid, s, M)
+    ws = wiu.workspace(grid)
+    Ud = _dev(U)
+    out = torch.empty_like(Ud)
+    wiu.rhs(grid, s, wiu.make_params(), Ud, M, out, ws)
+    st = wiu.status(ws)
+    return _host(out), st
+
+
+@pytest.mark.parametrize("s", SCHEMES)
+@pytest.mark.parametrize("kind,nx,ny", CASES)
+def test_rhs_parity_same_metrics(orc, wiu, s, kind, nx, ny):
+    """rhs alone: both sides consume the oracle's metric planes."""
+    say("rhs parity (oracle metrics)", s, kind, nx, ny)
+    g, U = make_case(kind, nx, ny, seed=5)
+    Mo = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    ref = orc.rhs(s, U, Mo, g.bc)
+    out, st = _gpu_rhs_with_metrics(wiu, g, s, U, Mo)
+    assert st == 0
+    err = normwise(out, ref)
+    assert np.all(err <= 1e-12), err
+
+
+@pytest.mark.parametrize("s", SCHEMES)
+@pytest.mark.parametrize("kind,nx,ny", CASES)
+def test_rhs_parity_full_path(orc, wiu, s, kind, nx, ny):
+    """metrics + rhs on the GPU against metrics + rhs in the oracle."""
+    say("rhs parity (full path)", s, kind, nx, ny)
+    g, U = make_case(kind, nx, ny, seed=7)
+    Mo = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    ref = orc.rhs(s, U, Mo, g.bc)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period)
+    out = _host(sol.rhs(_dev(U)))
+    assert sol.status() == 0
+    err = normwise(out, ref)
+    assert np.all(err <= 1e-12), err
+
+
+@pytest.mark.parametrize("s", SCHEMES)
+@pytest.mark.parametrize("n", [64, 128, 256, 512])
+def test_free_stream_preservation_on_gpu(wiu, s, n):
+    """Sec. 5.2 on the GPU: uniform Mach-0.5 flow on the randomized periodic
+    [0,10]^2 grid (A = 0.2) keeps max |dU/dt| < 1e-11."""
+    say("FSP", s, n)
+    g, U = W.fsp_problem(n, A=0.2)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period)
+    d = _host(sol.rhs(_dev(U)))
+    assert sol.status() == 0
+    assert np.abs(d).max() < 1e-11, np.abs(d).max()
+
+
+@pytest.mark.parametrize("s", SCHEMES)
+def test_rk3_step_parity(orc, wiu, s):
+    say("rk3 parity", s)
+    g, U = make_case("vortex", 160, 96, seed=2)
+    Mo = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    dt = orc.cfl_dt(U, Mo, 0.5)
+    ref = orc.rk3_step(s, U, Mo, dt, g.bc)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period)
+    Ud = _dev(U)
+    sol.cfl_dt(Ud, 0.5)
+    assert float(sol.dt.item()) == pytest.approx(dt, rel=1e-13)
+    sol.dt.fill_(dt)
+    sol.rk3_step(Ud)
+    out = _host(Ud)
+    assert sol.status() == 0
+    err = normwise(out - U, ref - U)
+    assert np.all(err <= 1e-11), err
+
+
+def test_rk3_steps_track_oracle_on_sod_strip(orc, wiu):
+    """20 CFL-driven RK3 steps of the Sod strip stay with the oracle (the
+    state is re-synchronised each step, so only one step's rounding counts)."""
+    g = W.strip_grid(200)
+    U = W.sod_state(g)
+    s = "5-2MP"
+    Mo = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period)
+    for k in range(20):
+        dt = orc.cfl_dt(U, Mo, 0.5)
+        ref = orc.rk3_step(s, U, Mo, dt, g.bc)
+        Ud = _dev(U)
+        sol.rk3_step(Ud, dt)
+        out = _host(Ud)
+        err = normwise(out - U, ref - U)
+        assert np.all(err <= 1e-11), (k, err)
+        U = ref
+    assert sol.status() == 0
+
+
+def test_status_flags(orc, wiu):
+    import torch
+    g, U = make_case("vortex", 64, 64, seed=1)
+    sol = wiu.Solver(g.x, g.y, "5-2MP", g.bc, g.period)
+    assert sol.status() == 0
+    # non-physical state: negative pressure at one node
+    Ub = U.copy()
+    Ub[3, 10, 10] = 0.1 * Ub[3, 10, 10] - 5.0
+    sol.rhs(_dev(Ub))
+    assert sol.status() & wiu.ST_NONPHYS
+    # metrics of another scheme: flagged, nothing written
+    other = wiu.Solver(g.x, g.y, "3-1MP", g.bc, g.period)
+    out = torch.full((4, 64, 64), 7.0, dtype=torch.float64, device="cuda")
+    wiu.rhs(sol.grid, "5-2MP", sol.params, _dev(U), other.M, out, sol.ws)
+    assert sol.status() & wiu.ST_SCHEME
+    assert float(out.min()) == 7.0 and float(out.max()) == 7.0
+    # folded grid (node displaced past its neighbour): J^{-1} <= 0 flagged
+    gf = W.periodic_grid(32, 32, (0, 10, 0, 10))
+    x = gf.x.copy()
+    x[10, 10] += 1.6 * (10 / 32)
+    bad = wiu.Solver(x, gf.y, "5-2MP", gf.bc, gf.period)
+    assert bad.status() & wiu.ST_JACOBIAN
+
+
+def test_rhs_is_deterministic(wiu):
+    g, U = make_case("riemann", 300, 200, seed=8)
+    sol = wiu.Solver(g.x, g.y, "5-2MP", g.bc, g.period)
+    Ud = _dev(U)
+    a = _host(sol.rhs(Ud))
+    b = _host(sol.rhs(Ud))
+    assert np.array_equal(a, b)
+
+
+def test_full_size_riemann_parity(orc, wiu):
+    """The throughput workload itself (2048^2 randomized Riemann grid, 5-2MP,
+    transmissive): GPU rhs and one RK3 step against the oracle, everywhere."""
+    s = "5-2MP"
+    say("full-size parity: metrics")
+    g, U = W.riemann_problem(2048)
+    Mo = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period)
+    Mg = _host(sol.planes())
+    for p in range(9):
+        assert np.abs(Mg[p] - Mo[p]).max() <= 1e-13 * np.abs(Mo[p]).max(), p
+    say("full-size parity: rhs")
+    ref = orc.rhs(s, U, Mo, g.bc)
+    Ud = _dev(U)
+    out = _host(sol.rhs(Ud))
+    err = normwise(out, ref)
+    assert np.all(err <= 1e-12), err
+    say("full-size parity: rk3 step")
+    dt = orc.cfl_dt(U, Mo, 0.5)
+    refs = orc.rk3_step(s, U, Mo, dt, g.bc)
+    sol.rk3_step(Ud, dt)
+    outs = _host(Ud)
+    err = normwise(outs - U, refs - U)
+    assert np.all(err <= 1e-11), err
+    assert sol.status() == 0

@@ -1,0 +1,247 @@
+"""Throughput benchmark of the WENOIU hot path on one MI355X.
+
+Workload: 2-D four-quadrant Riemann problem (Sec. 6.3(3)) on the randomized
+2048 x 2048 grid of [0,1]^2 (jitter 0.2 spacing, four uniform boundary
+layers, seed 2048), fifth-order two-midpoint scheme (WENOIU5-2MP),
+transmissive boundaries, TVD-RK3 with CFL 0.5, fp64.
+
+One step = one time step of the whole path: the CFL time step (wave-speed
+maximum) followed by the three RK stages, each of which evaluates the line
+eigenvalues, the xi and eta sweeps (characteristic WENO midpoint fluxes,
+upwind-biased difference) and the stage update.  The reported value counts
+cell-updates: one rhs evaluation at one cell fused with its stage update, so
+a step is 3 n^2 cell-updates.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic operation count per cell of one WENOIU5-2MP rhs on a 2048-node
+# line length: (1720 + 5065/n) per sweep direction (characteristic WENO
+# midpoint fluxes, nodal splits, line wave speeds, H and its difference) plus
+# 8 for the final -(R_xi + R_eta)/J^{-1}, counted by instantiating the oracle
+# with an operation-counting scalar (add, sub, mul, div, sqrt = 1 each); the
+# RK stage update adds 5 per component.
+N_DEFAULT = 2048
+FLOP_DIR_A, FLOP_DIR_B = 1720.0, 5065.0
+FLOP_COMBINE = 8.0
+FLOP_RK_STAGE = 20.0
+PEAK_FP64_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def flops_per_cell_dir(n):
+    return FLOP_DIR_A + FLOP_DIR_B / n
+
+
+def cpu_baseline(g, U, scheme, cfl):
+    """The oracle, as it stands, timed on the host cores: one TVD-RK3 step of
+    the full workload (3 rhs evaluations)."""
+    import oracle
+    oracle.build.build(force=False)
+    M = oracle.metrics(scheme, g.x, g.y, g.bc, g.period)
+    dt = oracle.cfl_dt(U, M, cfl)
+    t0 = time.perf_counter()
+    oracle.rk3_step(scheme, U, M, dt, g.bc)
+    t = time.perf_counter() - t0
+    n = g.x.size
+    return {"value": 3 * n / t, "unit": "cell-updates/s", "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"one TVD-RK3 step (3 rhs) of the full {g.x.shape[1]}x{g.x.shape[0]} workload, "
+                      f"{t:.2f} s"}
+
+
+def batched_leg(steps, cfl, tune=True):
+    """Batched multi-block workload: 64 periodic randomized blocks (sides
+    64..1024, random aspect ratios, Mach-4 flow with an entropy wave), one RK3
+    step as (a) one captured graph of the batched launches and (b) 64
+    per-block wiu_rk3_step calls on one stream; same per-block time steps."""
+    import torch
+    from paper_1810_11103_amd import autotune, wenoiu
+    from paper_1810_11103_amd import workloads as W
+
+    blocks = W.batched_blocks()
+    plan = wenoiu.BatchedPlan([(g.x, g.y, g.bc, g.period) for g, _ in blocks], "5-2MP")
+    U0 = torch.zeros_like(plan.U_all)
+    for b, (_, U) in enumerate(blocks):
+        plan.state(b).copy_(torch.as_tensor(U))
+    U0.copy_(plan.U_all)
+    plan.cfl_dt(cfl)
+    dts = plan.get_dt()
+    tuned = autotune.tune_batched(plan, cache=None) if tune else None
+    plan.U_all.copy_(U0)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    t_graph = timed(lambda: plan.step(graph=True), steps)
+    t_eager = timed(lambda: plan.step(graph=False), steps)
+    st = plan.status()
+    cells = plan.info()[0]
+    plan.close()
+    sols = []
+    for b, (g, U) in enumerate(blocks):
+        sol = wenoiu.Solver(g.x, g.y, "5-2MP", g.bc, g.period)
+        sol.dt.fill_(float(dts[b]))
+        sols.append((sol, torch.as_tensor(U).cuda().contiguous()))
+
+    def per_block():
+        for sol, Ud in sols:
+            sol.rk3_step(Ud)
+    t_blocks = timed(per_block, steps)
+    return {"blocks": len(blocks), "cells": cells, "graph_ms_per_step": t_graph, "eager_batched_ms_per_step": t_eager,
+            "per_block_ms_per_step": t_blocks, "speedup": t_blocks / t_graph,
+            "graph_cell_updates_per_s": 3 * cells / (t_graph * 1e-3), "tile_variant": tuned and tuned["variant"],
+            "status": st}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=N_DEFAULT)
+    ap.add_argument("--scheme", default="5-2MP")
+    ap.add_argument("--cfl", type=float, default=0.5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-block leg")
+    ap.add_argument("--no-rhs", action="store_true", help="skip the bare-rhs timing")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (reference for HBM counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(domain decomposition is described in DESIGN.md but not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1810_11103_amd import workloads as W
+    from paper_1810_11103_amd import wenoiu
+
+    if args.copy_ref_mib:
+        a = torch.ones(args.copy_ref_mib << 17, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    n = args.n
+    g, U0 = W.riemann_problem(n, A=0.2, seed=2048)
+    sol = wenoiu.Solver(g.x, g.y, args.scheme, g.bc, g.period)
+    U = torch.as_tensor(U0).cuda().contiguous()
+    torch.cuda.synchronize()
+
+    def step():
+        sol.cfl_dt(U, args.cfl)
+        sol.rk3_step(U)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = sol.status()
+    if st:
+        raise SystemExit(f"device status {st} after warm-up")
+
+    # timed region: K steps between two synchronisations, kernel timing on
+    wenoiu.profile_enable(True)
+    for k in ("wave_max", "sweep_xi", "sweep_eta"):
+        wenoiu.profile_read(k)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_host = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t_host
+    ms_total = e0.elapsed_time(e1)
+    kern = {k: wenoiu.profile_read(k) for k in ("wave_max", "sweep_xi", "sweep_eta")}
+    wenoiu.profile_enable(False)
+    ms_per_step = ms_total / args.steps
+    cells = n * n
+    value = 3 * cells * args.steps / (ms_total * 1e-3)
+
+    # bare rhs throughput (one residual per call), same state
+    rhs_ms = None
+    if not args.no_rhs:
+        dU = torch.empty_like(U)
+        for _ in range(3):
+            sol.rhs(U, dU)
+        torch.cuda.synchronize()
+        e0.record()
+        nr = max(args.steps, 10)
+        for _ in range(nr):
+            sol.rhs(U, dU)
+        e1.record()
+        torch.cuda.synchronize()
+        rhs_ms = e0.elapsed_time(e1) / nr
+    st = sol.status()
+
+    # roofline of the dominant kernel
+    fdir = flops_per_cell_dir(n)
+    per_launch = {
+        "sweep_xi": cells * fdir,
+        "sweep_eta": cells * (fdir + FLOP_COMBINE + FLOP_RK_STAGE),
+    }
+    dom = max(("sweep_xi", "sweep_eta"), key=lambda k: kern[k][0] * kern[k][1])
+    achieved = per_launch[dom] / (kern[dom][1] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None, "kernel": dom,
+                "kernel_mean_ms": round(kern[dom][1], 4), "launches": kern[dom][0],
+                "flops_per_launch": per_launch[dom]}
+
+    out = {
+        "metric": "FP64 cell-updates/s (5th-order rhs, 2048^2 grid)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2-D Riemann problem, randomized {n}x{n} grid on [0,1]^2 (A=0.2, seed 2048), "
+                               f"WENOIU{args.scheme}, transmissive, TVD-RK3 CFL {args.cfl}",
+                   "n": n, "scheme": args.scheme, "cfl": args.cfl},
+        "roofline": roofline,
+        "extra": {
+            "rhs_ms": rhs_ms,
+            "rhs_cells_per_s": rhs_ms and cells / (rhs_ms * 1e-3),
+            "kernels_ms": {k: round(v[1], 4) for k, v in kern.items()},
+            "host_wall_s": t_host,
+            "device_status": st,
+        },
+    }
+    if not args.no_batched:
+        del sol, U
+        torch.cuda.empty_cache()
+        out["extra"]["batched"] = batched_leg(max(3, args.steps // 4), args.cfl)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(g, U0, args.scheme, args.cfl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

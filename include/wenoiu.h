@@ -130,6 +130,50 @@ int wiu_workspace_init(void* ws, wiu_stream_t stream);
 
 const char* wiu_strerror(int code);
 
+/* ---- Batched multi-block stepping ------------------------------------------
+ * Many independent grid blocks of uneven sizes (the multi-block grids of
+ * the paper's motivation, Sec. 1) advanced together: per RK stage one launch
+ * of each kernel kind walks a device table of all blocks' tiles (persistent,
+ * XCD-aware), and the twelve launches of a step can be replayed as one
+ * captured HIP graph.  No interface coupling between blocks is applied: each
+ * block uses its own boundary rule.
+ *
+ * Each block's state lives in U_all at off_U (doubles, [4][ny][nx]) and its
+ * metrics, computed beforehand with wiu_metrics for the same scheme, in M_all
+ * at off_M (doubles, wiu_metrics_size() bytes).  The plan binds these
+ * pointers, owns its device tables and scratch (allocated when the plan is
+ * created, freed by wiu_plan_destroy) and a per-block time step. */
+typedef struct {
+  int nx, ny, bc_x, bc_y;
+  double period_x, period_y;
+  long long off_U, off_M;
+} wiu_block;
+
+typedef struct wiu_plan wiu_plan;
+
+/* xi_variant / eta_variant select the tile shapes (see wiu_set_tuning). */
+int wiu_batched_plan(const wiu_block* blocks, int nblocks, int scheme, const wiu_params* p, int xi_variant,
+                     int eta_variant, double* U_all, const double* M_all, wiu_plan** plan);
+int wiu_batched_info(const wiu_plan* plan, long long* cells, int* tiles_xi, int* tiles_eta);
+/* Per-block time steps: from the host (synchronous), from the CFL rule on the
+ * device (Sec. 2.3 wave speeds, as wiu_cfl_dt per block), or read back. */
+int wiu_batched_set_dt(wiu_plan* plan, const double* dt_host, wiu_stream_t stream);
+int wiu_batched_cfl_dt(wiu_plan* plan, double cfl, wiu_stream_t stream);
+int wiu_batched_get_dt(const wiu_plan* plan, double* dt_host, wiu_stream_t stream);
+/* One TVD-RK3 step of every block.  use_graph != 0 replays a captured graph
+ * of the step (captured on first use, bound to the plan's pointers). */
+int wiu_batched_rk3_step(wiu_plan* plan, int use_graph, wiu_stream_t stream);
+int wiu_batched_status(wiu_plan* plan, wiu_stream_t stream, int* status, int clear);
+int wiu_plan_destroy(wiu_plan* plan);
+
+/* Tile shapes of the two sweep kernels (dir 0 = xi, 1 = eta).  Several
+ * shapes are compiled; the choice is process-wide and affects speed only,
+ * never results.  wiu_tuning_variants() returns how many shapes a direction
+ * has, wiu_set_tuning() selects one (WIU_EINVAL when out of range). */
+int wiu_tuning_variants(int dir);
+int wiu_set_tuning(int dir, int variant);
+int wiu_get_tuning(int dir);
+
 /* Kernel timing for benchmarks.  While enabled, every launch of the
  * library's kernels is bracketed by HIP events recorded on its launch stream.
  * wiu_profile_read() synchronises the device, returns the number of launches

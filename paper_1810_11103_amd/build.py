@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libwenoiu.so")
-SOURCES = ["wiu_kernels.hip", "wiu_api.hip"]
+SOURCES = ["wiu_kernels.hip", "wiu_api.hip", "wiu_batched.hip"]
 HEADERS = ["wiu_device.hpp", "wiu_kernels.hpp"]
 ARCH = os.environ.get("WIU_OFFLOAD_ARCH", "gfx950")
 

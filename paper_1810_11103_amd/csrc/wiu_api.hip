@@ -34,6 +34,9 @@ struct ProfScope {
   }
 };
 
+// Tile shape of each sweep direction (index into the compiled variants).
+int g_variant[2] = {0, 4};  // xi 128 x 1, eta 64 x 2 (measured best at 2048^2)
+
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -130,13 +133,13 @@ int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U
   a.mode = 0; a.Rxi = w.rxi; a.out = out; a.U0 = U0; a.dt = dt; a.ca = ca; a.cb = cb; a.status = w.status;
   {
     ProfScope ps(WIU_K_SWEEP_XI, st);
-    e = launch_sweep(scheme, 0, a, st);
+    e = launch_sweep(scheme, 0, g_variant[0], a, st);
   }
   if (e != hipSuccess) return WIU_EHIP;
   a.mode = mode;
   {
     ProfScope ps(WIU_K_SWEEP_ETA, st);
-    e = launch_sweep(scheme, 1, a, st);
+    e = launch_sweep(scheme, 1, g_variant[1], a, st);
   }
   return hip_rc(e);
 }
@@ -227,6 +230,16 @@ int wiu_status(void* ws, wiu_stream_t stream, int* status, int clear) {
   }
   return WIU_OK;
 }
+
+int wiu_tuning_variants(int dir) { return (dir == 0 || dir == 1) ? sweep_variants(dir) : WIU_EINVAL; }
+
+int wiu_set_tuning(int dir, int variant) {
+  if ((dir != 0 && dir != 1) || variant < 0 || variant >= sweep_variants(dir)) return WIU_EINVAL;
+  g_variant[dir] = variant;
+  return WIU_OK;
+}
+
+int wiu_get_tuning(int dir) { return (dir == 0 || dir == 1) ? g_variant[dir] : WIU_EINVAL; }
 
 int wiu_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);

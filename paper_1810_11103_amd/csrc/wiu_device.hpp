@@ -40,10 +40,38 @@ WIU_DEV int bc_index(int k, int n, int bc) {
   return k < 0 ? 0 : (k >= n ? n - 1 : k);
 }
 
-// Reciprocal and reciprocal square root.  Plain IEEE operations for now; the
-// call sites are the only places to change for a faster variant.
-WIU_DEV double rcp(double x) { return 1.0 / x; }
-WIU_DEV double rsqrt_(double x) { return 1.0 / sqrt(x); }
+// XCD-aware block order.  The hardware hands consecutive workgroup ids to
+// the eight XCDs in turn, and each XCD has its own L2.  Remapping the
+// hardware id h so that XCD x receives one contiguous range of logical tiles
+// keeps neighbouring tiles (which share cache lines and stencil halos) in the
+// same L2.  Bijective for any total (the first `total % 8` XCDs get one extra).
+WIU_DEV int xcd_remap(int h, int total) {
+  const int q = total >> 3, r = total & 7;
+  const int x = h & 7, local = h >> 3;
+  return x * q + (x < r ? x : r) + local;
+}
+
+// Reciprocal and reciprocal square root: the hardware estimates refined by
+// two Newton-Raphson steps (r <- r + r (1 - x r); y <- y + y (1 - x y^2) / 2),
+// which leaves an error of about one ulp at a fraction of the cost of the
+// correctly rounded division and square-root sequences.  Arguments here are
+// positive, finite and well scaled (densities, sums of squared weights).
+WIU_DEV double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+WIU_DEV double rsqrt_(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * y;
+  double e = fma(-(x * y), h, 0.5);
+  y = fma(y, e, y);
+  h = 0.5 * y;
+  e = fma(-(x * y), h, 0.5);
+  return fma(y, e, y);
+}
 
 // ---------------------------------------------------------------------------
 // Scheme traits: order, midpoints, and the index ranges a tile needs.
@@ -78,74 +106,73 @@ template <int SC> struct Range {
 // WENO interpolation to x_{k+1/2} with mapped weights.
 // ---------------------------------------------------------------------------
 
-// Jiang-Shu indicators, Eq. 3.22, on (a, b, c) = three consecutive values.
-WIU_DEV double is_up(double a, double b, double c) {   // stencil ending at k
-  double t = a - 2.0 * b + c, s = a - 4.0 * b + 3.0 * c;
-  return (13.0 / 12.0) * t * t + 0.25 * s * s;
+// The interpolated sequences are characteristic deviations from the
+// reference state, whose own entry (the centre v_k of the stencil) is exactly
+// zero; the routines below take that zero into account.
+//
+// Mappings (Eqs. 3.15, 3.23) written as one polynomial in d = w - C:
+//   third order:  g = C + K d^3, K = 1/C^2 for d <= 0, 1/(C-1)^2 above
+//   second order: g = C + K d^2, K = -1/C for d <= 0, 1/(1-C) above
+// (C[1 + (w/C - 1)^3] = C + d^3/C^2 and C[1 - (w/C - 1)^2] = C - d^2/C).
+WIU_DEV double map3(double w, double C, double klo, double khi) {
+  const double d = w - C;
+  const double K = d <= 0.0 ? klo : khi;
+  return fma(K * d, d * d, C);
 }
-WIU_DEV double is_ce(double a, double b, double c) {   // centred on k
-  double t = a - 2.0 * b + c, s = a - c;
-  return (13.0 / 12.0) * t * t + 0.25 * s * s;
-}
-WIU_DEV double is_dn(double a, double b, double c) {   // stencil starting at k
-  double t = a - 2.0 * b + c, s = 3.0 * a - 4.0 * b + c;
-  return (13.0 / 12.0) * t * t + 0.25 * s * s;
-}
-
-// Third-order mapping (Eq. 3.23): C[1 + (w/C - 1)^3] below C,
-// C + (w - C)^3 / (C - 1)^2 above.
-WIU_DEV double map3(double w, double C, double invC, double k) {
-  double t = w * invC - 1.0;
-  double d = w - C;
-  double lo = C + C * (t * t * t);
-  double hi = C + k * (d * d * d);
-  return w <= C ? lo : hi;
-}
-// Second-order mapping (Eq. 3.15): C[1 - (w/C - 1)^2] below C,
-// C + (w - C)^2 / (1 - C) above.
-WIU_DEV double map2(double w, double C, double invC, double k) {
-  double t = w * invC - 1.0;
-  double d = w - C;
-  double lo = C - C * (t * t);
-  double hi = C + k * (d * d);
-  return w <= C ? lo : hi;
+WIU_DEV double map2(double w, double C, double klo, double khi) {
+  const double d = w - C;
+  const double K = d <= 0.0 ? klo : khi;
+  return fma(K * d, d, C);
 }
 
-// r = 3: left-biased value at k+1/2 from v_{k-2}, ..., v_{k+2} = (a, b, c, d, e).
-// Candidates from Table 1, linear weights (1, 10, 5)/16.  The normalised weights
-// alpha_k / sum alpha with alpha_k = C_k / (eps + IS_k)^2 are formed with a
-// single reciprocal: w_k = C_k prod_{l != k} D_l / sum_m C_m prod_{l != m} D_l.
-WIU_DEV double weno5(double a, double b, double c, double d, double e, double eps, int ppm) {
-  const double p0 = 0.375 * a - 1.25 * b + 1.875 * c;
-  const double p1 = -0.125 * b + 0.75 * c + 0.375 * d;
-  const double p2 = 0.375 * c + 0.75 * d - 0.125 * e;
-  double D0 = eps + is_up(a, b, c), D1 = eps + is_ce(b, c, d), D2 = eps + is_dn(c, d, e);
+// r = 3: left-biased value at k+1/2 from v_{k-2}, v_{k-1}, v_k = 0, v_{k+1},
+// v_{k+2} = (a, b, 0, d, e).  Candidates from Table 1 (b_{k,l}), linear
+// weights (1, 10, 5)/16, Jiang-Shu indicators (Eq. 3.22) from first
+// differences, weights alpha_k / sum alpha with alpha_k = C_k / (eps + IS_k)^2
+// formed with one reciprocal (w_k = C_k prod_{l != k} D_l / sum_m C_m
+// prod_{l != m} D_l), mapping Eq. 3.23 and re-normalisation.
+WIU_DEV double weno5(double a, double b, double d, double e, double eps, int ppm) {
+  const double p0 = 0.375 * a - 1.25 * b;
+  const double p1 = 0.375 * d - 0.125 * b;
+  const double p2 = 0.75 * d - 0.125 * e;
+  // differences of (a, b, 0, d, e)
+  const double d1 = b - a, d2 = -b, d3 = d, d4 = e - d;
+  const double t0 = d2 - d1, t1 = d3 - d2, t2 = d4 - d3;
+  const double s0 = fma(3.0, d2, -d1), s1 = -(d2 + d3), s2 = fma(-3.0, d3, d4);
+  double D0 = eps + fma(13.0 / 12.0, t0 * t0, 0.25 * (s0 * s0));
+  double D1 = eps + fma(13.0 / 12.0, t1 * t1, 0.25 * (s1 * s1));
+  double D2 = eps + fma(13.0 / 12.0, t2 * t2, 0.25 * (s2 * s2));
   D0 *= D0; D1 *= D1; D2 *= D2;
   const double a0 = 0.0625 * (D1 * D2), a1 = 0.625 * (D0 * D2), a2 = 0.3125 * (D0 * D1);
   const double r = rcp(a0 + a1 + a2);
   double w0 = a0 * r, w1 = a1 * r, w2 = a2 * r;
   if (ppm) {
-    w0 = map3(w0, 0.0625, 16.0, 256.0 / 225.0);
-    w1 = map3(w1, 0.625, 1.6, 64.0 / 9.0);
-    w2 = map3(w2, 0.3125, 3.2, 256.0 / 121.0);
+    w0 = map3(w0, 0.0625, 256.0, 256.0 / 225.0);
+    w1 = map3(w1, 0.625, 2.56, 64.0 / 9.0);
+    w2 = map3(w2, 0.3125, 10.24, 256.0 / 121.0);
   }
   return (w0 * p0 + w1 * p1 + w2 * p2) * rcp(w0 + w1 + w2);
 }
 
-// r = 2: left-biased value at k+1/2 from v_{k-2}, ..., v_{k+1} = (a, b, c, d).
-// Candidates (-v_{k-1} + 3 v_k)/2 and (v_k + v_{k+1})/2, C = (1, 3)/4, with the
-// three-point indicators IS_0, IS_1 of Eq. 3.22 (Sec. 5.1) and the mapping 3.15.
-WIU_DEV double weno3(double a, double b, double c, double d, double eps, int ppm) {
-  const double p0 = -0.5 * b + 1.5 * c;
-  const double p1 = 0.5 * c + 0.5 * d;
-  double D0 = eps + is_up(a, b, c), D1 = eps + is_ce(b, c, d);
+// r = 2: left-biased value at k+1/2 from v_{k-2}, v_{k-1}, v_k = 0, v_{k+1}
+// = (a, b, 0, d).  Candidates (-v_{k-1} + 3 v_k)/2 and (v_k + v_{k+1})/2,
+// C = (1, 3)/4, with the three-point indicators IS_0, IS_1 of Eq. 3.22 in
+// place of Eq. 3.14 (Sec. 5.1) and the mapping 3.15.
+WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
+  const double p0 = -0.5 * b;
+  const double p1 = 0.5 * d;
+  const double d1 = b - a, d2 = -b, d3 = d;
+  const double t0 = d2 - d1, t1 = d3 - d2;
+  const double s0 = fma(3.0, d2, -d1), s1 = -(d2 + d3);
+  double D0 = eps + fma(13.0 / 12.0, t0 * t0, 0.25 * (s0 * s0));
+  double D1 = eps + fma(13.0 / 12.0, t1 * t1, 0.25 * (s1 * s1));
   D0 *= D0; D1 *= D1;
   const double a0 = 0.25 * D1, a1 = 0.75 * D0;
   const double r = rcp(a0 + a1);
   double w0 = a0 * r, w1 = a1 * r;
   if (ppm) {
-    w0 = map2(w0, 0.25, 4.0, 4.0 / 3.0);
-    w1 = map2(w1, 0.75, 4.0 / 3.0, 4.0);
+    w0 = map2(w0, 0.25, -4.0, 4.0 / 3.0);
+    w1 = map2(w1, 0.75, -4.0 / 3.0, 4.0);
   }
   return (w0 * p0 + w1 * p1) * rcp(w0 + w1);
 }
@@ -186,6 +213,7 @@ WIU_DEV void side_flux(const double q[6][4], int side, double nx_, double ny_, d
   double w[4][NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
+    if (s == 2) continue;  // the reference node: zero deviation
     const int m = side == 0 ? s : 5 - s;
     const double dr = q[m][0] - Qr[0], dm = q[m][1] - Qr[1], dn = q[m][2] - Qr[2], de = q[m][3] - Qr[3];
     const double A = b2 * dr - b1 * (u * dm + v * dn - de);
@@ -198,8 +226,8 @@ WIU_DEV void side_flux(const double q[6][4], int side, double nx_, double ny_, d
   double W[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if constexpr (FIFTH) W[k] = weno5(w[k][0], w[k][1], w[k][2], w[k][3], w[k][4], eps, ppm);
-    else W[k] = weno3(w[k][0], w[k][1], w[k][2], w[k][3], eps, ppm);
+    if constexpr (FIFTH) W[k] = weno5(w[k][0], w[k][1], w[k][3], w[k][4], eps, ppm);
+    else W[k] = weno3(w[k][0], w[k][1], w[k][3], eps, ppm);
   }
   // back to conservative variables: Q = Q_ref + R W
   const double s03 = W[0] + W[3], d30 = W[3] - W[0];

@@ -182,18 +182,23 @@ __global__ void metrics_band_kernel(Dims d, int scheme, int B, const double* __r
 // order-independent (deterministic) result.  Non-physical or non-finite
 // states latch ST_NONPHYS.
 // ===========================================================================
-__global__ void __launch_bounds__(256) wave_max_kernel(Dims d, const double* __restrict__ U,
-                                                       const double* __restrict__ M, double gam,
-                                                       unsigned long long* __restrict__ lam_xi,
-                                                       unsigned long long* __restrict__ lam_eta,
-                                                       unsigned long long* __restrict__ cfl_max,
-                                                       int* __restrict__ status) {
-  // block: 64 columns x 4 thread rows, each thread row covers ROWS rows
+struct WaveLds {
+  double scol[4][64];
+  double scfl[4];
+};
+
+// One 64 x 16 tile (tx, ty) of the wave-speed maxima; block of 64 x 4 threads.
+WIU_DEV void wave_max_tile(const Dims& d, const double* __restrict__ U, const double* __restrict__ M, double gam,
+                           unsigned long long* __restrict__ lam_xi, unsigned long long* __restrict__ lam_eta,
+                           unsigned long long* __restrict__ cfl_max, int* __restrict__ status, int tx, int ty,
+                           WaveLds& L) {
+  // each thread row covers ROWS rows
   constexpr int ROWS = 4;
-  __shared__ double scol[4][64];
-  __shared__ double scfl[4];
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j0 = (blockIdx.y * 4 + threadIdx.y) * ROWS;
+  auto& scol = L.scol;
+  auto& scfl = L.scfl;
+  __syncthreads();  // LDS of the previous tile is free
+  const int i = tx * 64 + threadIdx.x;
+  const int j0 = (ty * 4 + threadIdx.y) * ROWS;
   double colmax = 0.0, cflm = 0.0;
   bool bad_any = false;
   for (int r = 0; r < ROWS; ++r) {
@@ -238,6 +243,16 @@ __global__ void __launch_bounds__(256) wave_max_kernel(Dims d, const double* __r
   }
 }
 
+__global__ void __launch_bounds__(256) wave_max_kernel(Dims d, const double* __restrict__ U,
+                                                       const double* __restrict__ M, double gam,
+                                                       unsigned long long* __restrict__ lam_xi,
+                                                       unsigned long long* __restrict__ lam_eta,
+                                                       unsigned long long* __restrict__ cfl_max,
+                                                       int* __restrict__ status) {
+  __shared__ WaveLds lds;
+  wave_max_tile(d, U, M, gam, lam_xi, lam_eta, cfl_max, status, blockIdx.x, blockIdx.y, lds);
+}
+
 __global__ void fill_u64_kernel(unsigned long long* p, long long n, unsigned long long v) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) p[t] = v;
@@ -265,15 +280,27 @@ __global__ void lambda_out_kernel(Dims d, double alpha, const unsigned long long
 // Epilogue: mode 0 writes R^xi; mode 1 writes dU/dt = -(R^xi + R^eta)/J^{-1};
 // mode 2 writes an RK stage U_out = a U0 + b Us + c dt dU/dt.
 // ===========================================================================
+template <int SC, int DIR, int NA, int NB> struct SweepLds {
+  double sh[16][NA * NB];        // [kind*4 + comp][item]: kinds fp, fm, Fp, Fm
+  double sq[4][NB][NA + 5];      // stencil tile: items k - 2 .. k + 3
+};
+
+// One tile of a sweep: logical tile (bxl, byl) = (segment along the line,
+// group of lines) for xi, (group of lines, segment) for eta.  Every thread of
+// the block calls it with the same tile; it contains three block-wide
+// barriers on every path that reaches the output phase, and none after.
 template <int SC, int DIR, int NA, int NB>
-__global__ void __launch_bounds__(NA * NB) sweep_kernel(SweepArgs s) {
+WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, NA, NB>& L) {
   using R_ = Range<SC>;
   constexpr int OUT = NA - R_::EXTRA;
   constexpr int NT = NA * NB;
-  __shared__ double sh[16][NT];  // [kind*4 + comp][item]: kinds fp, fm, Fp, Fm
+  constexpr int NQ = NA + 5;
+  auto& sh = L.sh;
+  auto& sq = L.sq;
 
   const Dims& d = s.d;
-  // metrics built for another scheme or grid: flag and do nothing
+  // metrics built for another scheme or grid: flag and do nothing (uniform
+  // over the block, so no barrier is skipped by part of it)
   {
     const double* tag = s.M + 9 * d.mplane;
     if (tag[0] != TAG_MAGIC || tag[1] != (double)SC || tag[2] != (double)d.nx || tag[3] != (double)d.ny) {
@@ -281,21 +308,20 @@ __global__ void __launch_bounds__(NA * NB) sweep_kernel(SweepArgs s) {
       return;
     }
   }
+  __syncthreads();  // LDS of the previous tile is free
   const int ta = DIR == 0 ? threadIdx.x : threadIdx.y;  // along
   const int tb = DIR == 0 ? threadIdx.y : threadIdx.x;  // across
   const int n_al = DIR == 0 ? d.nx : d.ny;
   const int n_ac = DIR == 0 ? d.ny : d.nx;
   const int bc_al = DIR == 0 ? d.bcx : d.bcy;
-  const int line = (DIR == 0 ? blockIdx.y : blockIdx.x) * NB + tb;
-  const int o0 = (DIR == 0 ? blockIdx.x : blockIdx.y) * OUT;
+  const int line = (DIR == 0 ? byl : bxl) * NB + tb;
+  const int o0 = (DIR == 0 ? bxl : byl) * OUT;
   const int out = min(OUT, n_al - o0);
   const int k = o0 + R_::LO + ta;
   const int slot = tb * NA + ta;
   const bool live = line < n_ac;
 
   // element offsets
-  const long long qstride = DIR == 0 ? 1 : d.nx;                       // along the line in U
-  const long long qline = DIR == 0 ? (long long)line * d.nx : line;    // line origin in U
   const long long mstride = DIR == 0 ? 1 : d.mpitch;
   const long long mline = DIR == 0 ? (long long)(line + GHOST) * d.mpitch + GHOST
                                    : (long long)GHOST * d.mpitch + (line + GHOST);
@@ -312,14 +338,32 @@ __global__ void __launch_bounds__(NA * NB) sweep_kernel(SweepArgs s) {
   const bool need_node = live && k >= o0 + Traits<SC>::NLO && k < o0 + out + Traits<SC>::NHI;
   const bool need_mid = live && k >= o0 + Traits<SC>::MLO && k < o0 + out + Traits<SC>::MHI;
 
+  // Stage the states of the tile (with the boundary rule applied) in LDS,
+  // consecutive threads reading consecutive addresses.
+  {
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int k0 = o0 + R_::LO - 2;
+    for (int e = tid; e < NQ * NB; e += NT) {
+      const int pos = DIR == 0 ? e % NQ : e / NB;
+      const int lb = DIR == 0 ? e / NQ : e % NB;
+      const int ln = (DIR == 0 ? byl : bxl) * NB + lb;
+      if (ln < n_ac) {
+        const int kk = bc_index(k0 + pos, n_al, bc_al);
+        const long long o = DIR == 0 ? (long long)ln * d.nx + kk : (long long)kk * d.nx + ln;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sq[c][lb][pos] = s.U[c * d.np + o];
+      }
+    }
+  }
+  __syncthreads();
+
   if (need_node || need_mid) {
     // stencil states Q_{k-2..k+3}
     double q[6][4];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-      const long long o = qline + qstride * bc_index(k - 2 + m, n_al, bc_al);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) q[m][c] = s.U[c * d.np + o];
+      for (int c = 0; c < 4; ++c) q[m][c] = sq[c][tb][ta + m];
     }
     const long long mo = mline + mstride * k;
     const double kx0 = Mk[mo], ky0 = Mk[d.mplane + mo];
@@ -344,7 +388,7 @@ __global__ void __launch_bounds__(NA * NB) sweep_kernel(SweepArgs s) {
   }
   __syncthreads();
 
-  if (!live || ta >= out) return;
+  if (!live || ta >= out) return;  // no barrier follows
   const int i = o0 + ta;                  // output node along the line
   const int base = tb * NA - (o0 + R_::LO);  // slot of line index kk is base + kk
   double R[4];
@@ -379,13 +423,20 @@ __global__ void __launch_bounds__(NA * NB) sweep_kernel(SweepArgs s) {
   }
 }
 
+template <int SC, int DIR, int NA, int NB>
+__global__ void __launch_bounds__(NA * NB) sweep_kernel(SweepArgs s) {
+  __shared__ SweepLds<SC, DIR, NA, NB> lds;
+  // logical tile in XCD-aware order
+  const int total = gridDim.x * gridDim.y;
+  const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, total);
+  sweep_tile<SC, DIR, NA, NB>(s, lid % gridDim.x, lid / gridDim.x, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
-template <int SC, int DIR>
+template <int SC, int DIR, int NA, int NB>
 hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
-  constexpr int NA = DIR == 0 ? 128 : 32;
-  constexpr int NB = DIR == 0 ? 1 : 16;
   constexpr int OUT = NA - Range<SC>::EXTRA;
   const int n_al = DIR == 0 ? a.d.nx : a.d.ny;
   const int n_ac = DIR == 0 ? a.d.ny : a.d.nx;
@@ -397,16 +448,40 @@ hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(int scheme, int dir, const SweepArgs& a, hipStream_t st) {
+// Compiled tile shapes (items along the line x lines per block).
+//   xi : 0 (128 x 1), 1 (256 x 1), 2 (64 x 2)
+//   eta: 0 (32 x 16), 1 (32 x 8), 2 (32 x 4), 3 (64 x 4), 4 (64 x 2)
+template <int SC, int DIR>
+hipError_t launch_sweep_v(int variant, const SweepArgs& a, hipStream_t st) {
+  if constexpr (DIR == 0) {
+    switch (variant) {
+      case 1: return launch_sweep_t<SC, 0, 256, 1>(a, st);
+      case 2: return launch_sweep_t<SC, 0, 64, 2>(a, st);
+      default: return launch_sweep_t<SC, 0, 128, 1>(a, st);
+    }
+  } else {
+    switch (variant) {
+      case 1: return launch_sweep_t<SC, 1, 32, 8>(a, st);
+      case 2: return launch_sweep_t<SC, 1, 32, 4>(a, st);
+      case 3: return launch_sweep_t<SC, 1, 64, 4>(a, st);
+      case 4: return launch_sweep_t<SC, 1, 64, 2>(a, st);
+      default: return launch_sweep_t<SC, 1, 32, 16>(a, st);
+    }
+  }
+}
+
+int sweep_variants(int dir) { return dir == 0 ? 3 : 5; }
+
+hipError_t launch_sweep(int scheme, int dir, int variant, const SweepArgs& a, hipStream_t st) {
   switch (scheme * 2 + dir) {
-    case 0: return launch_sweep_t<0, 0>(a, st);
-    case 1: return launch_sweep_t<0, 1>(a, st);
-    case 2: return launch_sweep_t<1, 0>(a, st);
-    case 3: return launch_sweep_t<1, 1>(a, st);
-    case 4: return launch_sweep_t<2, 0>(a, st);
-    case 5: return launch_sweep_t<2, 1>(a, st);
-    case 6: return launch_sweep_t<3, 0>(a, st);
-    default: return launch_sweep_t<3, 1>(a, st);
+    case 0: return launch_sweep_v<0, 0>(variant, a, st);
+    case 1: return launch_sweep_v<0, 1>(variant, a, st);
+    case 2: return launch_sweep_v<1, 0>(variant, a, st);
+    case 3: return launch_sweep_v<1, 1>(variant, a, st);
+    case 4: return launch_sweep_v<2, 0>(variant, a, st);
+    case 5: return launch_sweep_v<2, 1>(variant, a, st);
+    case 6: return launch_sweep_v<3, 0>(variant, a, st);
+    default: return launch_sweep_v<3, 1>(variant, a, st);
   }
 }
 
@@ -464,6 +539,156 @@ __global__ void zero_int_kernel(int* p, int n) {
 
 hipError_t launch_zero_header(int* p, int n, hipStream_t st) {
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, st, p, n);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Batched multi-block stepping.  All blocks' tiles of one kind form one flat
+// table; a persistent grid walks it, each XCD taking one contiguous range of
+// tiles (so tiles of the same block share that XCD's L2).  One launch per
+// kind per RK stage for every block at once.
+// ===========================================================================
+
+// Tiles [start, end) of the table that hardware block h works on.
+WIU_DEV void xcd_range(int ntiles, int& start, int& end, int& stride) {
+  const int G = gridDim.x, h = blockIdx.x;
+  const int x = h & 7, loc = h >> 3;
+  const int nb = (G - x + 7) >> 3;  // hardware blocks of this XCD (G >= 8)
+  const int s0 = (int)((long long)ntiles * x / 8), s1 = (int)((long long)ntiles * (x + 1) / 8);
+  start = s0 + loc;
+  end = s1;
+  stride = nb;
+}
+
+WIU_DEV const double* stage_src(const BlockDev& B, int stage) {
+  return stage == 0 ? B.U : (stage == 1 ? B.U1 : B.U2);
+}
+
+template <int SC, int DIR, int NA, int NB>
+__global__ void __launch_bounds__(NA * NB) batched_sweep_kernel(BatchArgs b) {
+  __shared__ SweepLds<SC, DIR, NA, NB> lds;
+  int t, end, stride;
+  xcd_range(b.ntiles, t, end, stride);
+  for (; t < end; t += stride) {
+    const int4 tl = b.tiles[t];
+    const BlockDev& B = b.blocks[tl.x];
+    SweepArgs s;
+    s.d = B.d; s.M = B.M; s.lam_xi = B.lam; s.lam_eta = B.lam + B.d.ny;
+    s.gamma = b.gamma; s.alpha = b.alpha; s.eps = b.eps; s.ppm = b.ppm;
+    s.Rxi = B.Rxi; s.U0 = B.U; s.dt = B.dt; s.status = b.status;
+    s.U = stage_src(B, b.stage);
+    s.out = b.stage == 0 ? B.U1 : (b.stage == 1 ? B.U2 : B.U);
+    s.ca = b.stage == 0 ? 0.0 : (b.stage == 1 ? 0.75 : 1.0 / 3.0);
+    s.cb = b.stage == 0 ? 1.0 : (b.stage == 1 ? 0.25 : 2.0 / 3.0);
+    s.mode = DIR == 0 ? 0 : 2;
+    sweep_tile<SC, DIR, NA, NB>(s, tl.y, tl.z, lds);
+  }
+}
+
+__global__ void __launch_bounds__(256) batched_wave_max_kernel(BatchArgs b) {
+  __shared__ WaveLds lds;
+  int t, end, stride;
+  xcd_range(b.ntiles, t, end, stride);
+  for (; t < end; t += stride) {
+    const int4 tl = b.tiles[t];
+    const BlockDev& B = b.blocks[tl.x];
+    wave_max_tile(B.d, stage_src(B, b.stage), B.M, b.gamma, B.lam, B.lam + B.d.ny, B.lam + B.d.ny + B.d.nx,
+                  b.status, tl.y, tl.z, lds);
+  }
+}
+
+__global__ void batched_cfl_dt_kernel(const BlockDev* blocks, int nblocks, double cfl) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nblocks) {
+    const BlockDev& B = blocks[t];
+    B.dt[0] = cfl / __longlong_as_double((long long)B.lam[B.d.ny + B.d.nx]);
+  }
+}
+
+template <int SC, int DIR, int NA, int NB>
+hipError_t launch_batched_sweep_t(const BatchArgs& a, hipStream_t st) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipErrorUnknown;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_sweep_kernel<SC, DIR, NA, NB>, NA * NB, 0) !=
+      hipSuccess || per < 1)
+    per = 1;
+  int grid = cus * per;
+  if (grid > a.ntiles) grid = a.ntiles;
+  if (grid < 8) grid = 8;
+  dim3 block = DIR == 0 ? dim3(NA, NB) : dim3(NB, NA);
+  hipLaunchKernelGGL((batched_sweep_kernel<SC, DIR, NA, NB>), dim3(grid), block, 0, st, a);
+  return hipGetLastError();
+}
+
+template <int SC, int DIR>
+hipError_t launch_batched_sweep_v(int variant, const BatchArgs& a, hipStream_t st) {
+  if constexpr (DIR == 0) {
+    switch (variant) {
+      case 1: return launch_batched_sweep_t<SC, 0, 256, 1>(a, st);
+      case 2: return launch_batched_sweep_t<SC, 0, 64, 2>(a, st);
+      default: return launch_batched_sweep_t<SC, 0, 128, 1>(a, st);
+    }
+  } else {
+    switch (variant) {
+      case 1: return launch_batched_sweep_t<SC, 1, 32, 8>(a, st);
+      case 2: return launch_batched_sweep_t<SC, 1, 32, 4>(a, st);
+      case 3: return launch_batched_sweep_t<SC, 1, 64, 4>(a, st);
+      case 4: return launch_batched_sweep_t<SC, 1, 64, 2>(a, st);
+      default: return launch_batched_sweep_t<SC, 1, 32, 16>(a, st);
+    }
+  }
+}
+
+hipError_t launch_batched_sweep(int scheme, int dir, int variant, const BatchArgs& a, hipStream_t st) {
+  switch (scheme * 2 + dir) {
+    case 0: return launch_batched_sweep_v<0, 0>(variant, a, st);
+    case 1: return launch_batched_sweep_v<0, 1>(variant, a, st);
+    case 2: return launch_batched_sweep_v<1, 0>(variant, a, st);
+    case 3: return launch_batched_sweep_v<1, 1>(variant, a, st);
+    case 4: return launch_batched_sweep_v<2, 0>(variant, a, st);
+    case 5: return launch_batched_sweep_v<2, 1>(variant, a, st);
+    case 6: return launch_batched_sweep_v<3, 0>(variant, a, st);
+    default: return launch_batched_sweep_v<3, 1>(variant, a, st);
+  }
+}
+
+void sweep_tile_shape(int dir, int variant, int& na, int& nb) {
+  static const int xi[3][2] = {{128, 1}, {256, 1}, {64, 2}};
+  static const int eta[5][2] = {{32, 16}, {32, 8}, {32, 4}, {64, 4}, {64, 2}};
+  if (dir == 0) { na = xi[variant][0]; nb = xi[variant][1]; }
+  else { na = eta[variant][0]; nb = eta[variant][1]; }
+}
+
+int scheme_extra(int scheme) {
+  switch (scheme) {
+    case 0: return Range<0>::EXTRA;
+    case 1: return Range<1>::EXTRA;
+    case 2: return Range<2>::EXTRA;
+    default: return Range<3>::EXTRA;
+  }
+}
+
+hipError_t launch_batched_wave_max(const BatchArgs& a, hipStream_t st) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipErrorUnknown;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_wave_max_kernel, 256, 0) != hipSuccess || per < 1)
+    per = 1;
+  int grid = cus * per;
+  if (grid > a.ntiles) grid = a.ntiles;
+  if (grid < 8) grid = 8;
+  hipLaunchKernelGGL(batched_wave_max_kernel, dim3(grid), dim3(64, 4), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, 0ull);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_cfl_dt(const BlockDev* blocks, int nblocks, double cfl, hipStream_t st) {
+  hipLaunchKernelGGL(batched_cfl_dt_kernel, dim3((nblocks + 63) / 64), dim3(64), 0, st, blocks, nblocks, cfl);
   return hipGetLastError();
 }
 

@@ -23,7 +23,34 @@ struct SweepArgs {
   int* status;
 };
 
-hipError_t launch_sweep(int scheme, int dir, const SweepArgs& a, hipStream_t st);
+// One block of a batched multi-block problem (device table entry).
+struct BlockDev {
+  Dims d;
+  double* U;                 // the block's state (stage 3 writes it)
+  const double* M;           // its metrics (with tag)
+  double *U1, *U2, *Rxi;     // stage states and R^xi
+  unsigned long long* lam;   // lam_xi[ny], lam_eta[nx], cfl_max[1]
+  double* dt;                // its time step (device scalar)
+};
+
+struct BatchArgs {
+  const BlockDev* blocks;
+  const int4* tiles;         // {block, bx, by, 0}
+  int ntiles;
+  int stage;                 // RK stage 0, 1, 2
+  double gamma, alpha, eps;
+  int ppm;
+  int* status;
+};
+
+hipError_t launch_sweep(int scheme, int dir, int variant, const SweepArgs& a, hipStream_t st);
+hipError_t launch_batched_sweep(int scheme, int dir, int variant, const BatchArgs& a, hipStream_t st);
+hipError_t launch_batched_wave_max(const BatchArgs& a, hipStream_t st);
+hipError_t launch_batched_cfl_dt(const BlockDev* blocks, int nblocks, double cfl, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, long long n, hipStream_t st);
+void sweep_tile_shape(int dir, int variant, int& na, int& nb);
+int scheme_extra(int scheme);
+int sweep_variants(int dir);
 hipError_t launch_wave_max(const Dims& d, const double* U, const double* M, double gam, unsigned long long* lx,
                            unsigned long long* le, unsigned long long* cfl, int* status, hipStream_t st);
 hipError_t launch_metrics(const Dims& d, int scheme, const double* x, const double* y, double* M, double* T,

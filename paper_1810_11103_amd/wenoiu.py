@@ -22,7 +22,9 @@ WIU_OK, WIU_EINVAL, WIU_EHIP = 0, -1, -2
 EXPORTS = [
     "wiu_metrics_size", "wiu_workspace_bytes", "wiu_workspace_init", "wiu_metrics", "wiu_set_metrics_tag",
     "wiu_line_eigenvalues", "wiu_rhs", "wiu_cfl_dt", "wiu_rk3_step", "wiu_status", "wiu_strerror",
-    "wiu_profile_enable", "wiu_profile_read",
+    "wiu_profile_enable", "wiu_profile_read", "wiu_tuning_variants", "wiu_set_tuning", "wiu_get_tuning",
+    "wiu_batched_plan", "wiu_batched_info", "wiu_batched_set_dt", "wiu_batched_cfl_dt", "wiu_batched_get_dt",
+    "wiu_batched_rk3_step", "wiu_batched_status", "wiu_plan_destroy",
 ]
 KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3}
 
@@ -30,6 +32,12 @@ KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3}
 class WiuGrid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
                 ("period_x", ctypes.c_double), ("period_y", ctypes.c_double)]
+
+
+class WiuBlock(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
+                ("period_x", ctypes.c_double), ("period_y", ctypes.c_double),
+                ("off_U", ctypes.c_longlong), ("off_M", ctypes.c_longlong)]
 
 
 class WiuParams(ctypes.Structure):
@@ -58,6 +66,17 @@ def _load():
         "wiu_status": (I, [P, P, ctypes.POINTER(I), I]),
         "wiu_strerror": (ctypes.c_char_p, [I]),
         "wiu_profile_enable": (I, [I]),
+        "wiu_batched_plan": (I, [ctypes.POINTER(WiuBlock), I, I, PR, I, I, P, P, ctypes.POINTER(P)]),
+        "wiu_batched_info": (I, [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "wiu_batched_set_dt": (I, [P, P, P]),
+        "wiu_batched_cfl_dt": (I, [P, ctypes.c_double, P]),
+        "wiu_batched_get_dt": (I, [P, P, P]),
+        "wiu_batched_rk3_step": (I, [P, I, P]),
+        "wiu_batched_status": (I, [P, P, ctypes.POINTER(I), I]),
+        "wiu_plan_destroy": (I, [P]),
+        "wiu_tuning_variants": (I, [I]),
+        "wiu_set_tuning": (I, [I, I]),
+        "wiu_get_tuning": (I, [I]),
         "wiu_profile_read": (I, [I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
@@ -178,6 +197,18 @@ def status(ws, clear=True, stream=None):
     return v.value
 
 
+def tuning_variants(direction):
+    return lib.wiu_tuning_variants(int(direction))
+
+
+def set_tuning(direction, variant):
+    _check(lib.wiu_set_tuning(int(direction), int(variant)))
+
+
+def get_tuning(direction):
+    return lib.wiu_get_tuning(int(direction))
+
+
 def profile_enable(on=True):
     _check(lib.wiu_profile_enable(int(bool(on))))
 
@@ -233,3 +264,104 @@ class Solver:
 
     def planes(self):
         return metric_planes(self.M, self.grid)
+
+
+class BatchedPlan:
+    """Many independent blocks stepped together (wiu_batched_*).
+
+    blocks: list of (x, y, bc, period) node-coordinate arrays per block.
+    U_all and M_all are flat device tensors owned here; block b's state is
+    U_all[off_U[b] : off_U[b] + 4 ny nx] viewed as (4, ny, nx)."""
+
+    def __init__(self, blocks, scheme="5-2MP", params=None, xi_variant=None, eta_variant=None, device="cuda"):
+        self.scheme = scheme
+        self.params = params or make_params()
+        self.device = device
+        self.shapes = []
+        descs = []
+        offU = offM = 0
+        for (x, y, bc, period) in blocks:
+            ny, nx = x.shape
+            g = make_grid(nx, ny, bc, period)
+            descs.append(WiuBlock(nx, ny, g.bc_x, g.bc_y, g.period_x, g.period_y, offU, offM))
+            self.shapes.append((ny, nx))
+            offU += 4 * nx * ny
+            offM += metrics_size(g) // 8
+        self.off_U = [d.off_U for d in descs]
+        self.U_all = torch.zeros(offU, dtype=torch.float64, device=device)
+        self.M_all = torch.zeros(offM, dtype=torch.float64, device=device)
+        # metrics of every block with the single-grid entry point (one-time)
+        for d, (x, y, bc, period) in zip(descs, blocks):
+            g = make_grid(d.nx, d.ny, bc, period)
+            ws = workspace(g, device)
+            xx = torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
+            yy = torch.as_tensor(y, dtype=torch.float64).to(device).contiguous()
+            Mb = self.M_all[d.off_M: d.off_M + metrics_size(g) // 8]
+            metrics(g, scheme, xx, yy, Mb, ws)
+            if status(ws):
+                raise WiuError("metrics reported a folded cell")
+        self._descs = (WiuBlock * len(descs))(*descs)
+        self.plan = ctypes.c_void_p()
+        self.retune(get_tuning(0) if xi_variant is None else xi_variant,
+                    get_tuning(1) if eta_variant is None else eta_variant)
+
+    def retune(self, xi_variant, eta_variant):
+        """(Re)create the device plan with other tile shapes; the state,
+        metrics and time steps are kept."""
+        dt = self.get_dt() if self.plan else None
+        self.close()
+        _check(lib.wiu_batched_plan(self._descs, len(self._descs), scheme_id(self.scheme), ctypes.byref(self.params),
+                                    int(xi_variant), int(eta_variant), ctypes.c_void_p(self.U_all.data_ptr()),
+                                    ctypes.c_void_p(self.M_all.data_ptr()), ctypes.byref(self.plan)))
+        self.variant = (int(xi_variant), int(eta_variant))
+        if dt is not None:
+            self.set_dt(dt)
+
+    def state(self, b):
+        ny, nx = self.shapes[b]
+        return self.U_all[self.off_U[b]: self.off_U[b] + 4 * nx * ny].view(4, ny, nx)
+
+    def metric_array(self, b):
+        d = self._descs[b]
+        g = make_grid(d.nx, d.ny, (d.bc_x, d.bc_y), (d.period_x, d.period_y))
+        return self.M_all[d.off_M: d.off_M + metrics_size(g) // 8]
+
+    def info(self):
+        c = ctypes.c_longlong(0)
+        a = ctypes.c_int(0)
+        b = ctypes.c_int(0)
+        _check(lib.wiu_batched_info(self.plan, ctypes.byref(c), ctypes.byref(a), ctypes.byref(b)))
+        return c.value, a.value, b.value
+
+    def set_dt(self, dt):
+        import numpy as np
+        arr = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (len(self.shapes),)))
+        _check(lib.wiu_batched_set_dt(self.plan, arr.ctypes.data_as(ctypes.c_void_p), _stream()))
+
+    def cfl_dt(self, cfl):
+        _check(lib.wiu_batched_cfl_dt(self.plan, float(cfl), _stream()))
+
+    def get_dt(self):
+        import numpy as np
+        arr = np.zeros(len(self.shapes))
+        _check(lib.wiu_batched_get_dt(self.plan, arr.ctypes.data_as(ctypes.c_void_p), _stream()))
+        return arr
+
+    def step(self, graph=True):
+        _check(lib.wiu_batched_rk3_step(self.plan, int(bool(graph)), _stream()))
+
+    def status(self, clear=True):
+        v = ctypes.c_int(0)
+        _check(lib.wiu_batched_status(self.plan, _stream(), ctypes.byref(v), int(clear)))
+        return v.value
+
+    def close(self):
+        if self.plan:
+            lib.wiu_plan_destroy(self.plan)
+            self.plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

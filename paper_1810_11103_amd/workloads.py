@@ -248,3 +248,29 @@ def random_smooth_state(grid, seed=0, amp=0.05):
     v = -0.2 + amp * fields[2]
     p = 1.0 + amp * fields[3]
     return conservative(rho, u, v, p)
+
+
+def batched_blocks(nblocks=64, seed=64, h=1.0 / 512, A=0.2, nmin=64, nmax=1024, speed=4.0, amp=0.05):
+    """Batched multi-block workload: `nblocks` independent periodic
+    randomized blocks with n_x ~ U{nmin..nmax}, aspect a ~ logU(1/4, 4),
+    n_y = clip(round(n_x a), nmin, nmax), spacing h; each carries a uniform
+    flow rho = 1, p = 1/gamma (c = 1) at `speed` in a random direction plus an
+    entropy wave rho += amp sum_3 sin(2 pi (k x/L_x + l y/L_y) + phi).
+    Returns a list of (Grid, U)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(nblocks):
+        nx = int(rng.integers(nmin, nmax + 1))
+        a = float(np.exp(rng.uniform(np.log(0.25), np.log(4.0))))
+        ny = int(np.clip(round(nx * a), nmin, nmax))
+        g = periodic_grid(nx, ny, (0.0, nx * h, 0.0, ny * h), A=A, seed=seed * 1000 + b)
+        th = rng.uniform(0.0, 2 * np.pi)
+        Lx, Ly = g.period
+        rho = np.ones_like(g.x)
+        for _ in range(3):
+            k, l = rng.integers(1, 4, size=2)
+            ph = rng.uniform(0.0, 2 * np.pi)
+            rho = rho + amp * np.sin(2 * np.pi * (k * g.x / Lx + l * g.y / Ly) + ph)
+        U = conservative(rho, speed * np.cos(th), speed * np.sin(th), 1.0 / GAMMA)
+        out.append((g, U))
+    return out

@@ -249,3 +249,29 @@ def test_full_size_riemann_parity(orc, wiu):
     err = normwise(outs - U, refs - U)
     assert np.all(err <= 1e-11), err
     assert sol.status() == 0
+
+
+def test_tile_shapes_give_identical_results(wiu):
+    """Every compiled tile shape of both sweeps gives bitwise the same rhs
+    (each item is computed by the same code whatever the tiling)."""
+    g, U = make_case("riemann", 301, 203, seed=4)
+    Ud = _dev(U)
+    ref = None
+    saved = (wiu.get_tuning(0), wiu.get_tuning(1))
+    try:
+        for s in SCHEMES:
+            sol = wiu.Solver(g.x, g.y, s, g.bc, g.period)
+            ref = None
+            for vx in range(wiu.tuning_variants(0)):
+                for ve in range(wiu.tuning_variants(1)):
+                    wiu.set_tuning(0, vx)
+                    wiu.set_tuning(1, ve)
+                    out = _host(sol.rhs(Ud))
+                    if ref is None:
+                        ref = out
+                    else:
+                        assert np.array_equal(out, ref), (s, vx, ve)
+            assert sol.status() == 0
+    finally:
+        wiu.set_tuning(0, saved[0])
+        wiu.set_tuning(1, saved[1])

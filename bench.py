@@ -40,6 +40,29 @@ PEAK_FP64_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
 
+# HBM traffic of the dominant kernel, from the committed rocprofv3 counter
+# summary; used only while the kernel sources are the ones profiled.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_eta_riemann2048_hbm.md")
+KERNEL_SOURCES = ("paper_1810_11103_amd/csrc/wiu_device.hpp", "paper_1810_11103_amd/csrc/wiu_sweep.hpp",
+                  "paper_1810_11103_amd/csrc/wiu_kernels.hip")
+
+
+def profiled_traffic(n):
+    import hashlib
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    fields = dict(line.strip().split(": ", 1) for line in text.splitlines()
+                  if line.startswith("    ") and ": " in line)
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if n != N_DEFAULT or fields.get("source_sha") != h.hexdigest()[:16]:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def flops_per_cell_dir(n):
     return FLOP_DIR_A + FLOP_DIR_B / n
 
@@ -112,6 +135,56 @@ def batched_leg(steps, cfl, tune=True):
             "status": st}
 
 
+def adjoint_leg(n=512, nsteps=400, every=20, cfl=0.5, fd_check=True):
+    """Adjoint workload: isentropic vortex (strength 5) on the randomized
+    periodic n x n grid of [0,10]^2, `nsteps` RK3 steps at the fixed dt of
+    CFL 0.5 at t = 0, J = ||rho(T) - 1||, gradient in the initial state and
+    the vortex strength through the hand-written adjoint with checkpoints
+    every `every` steps; cost ratio backward / forward and a central
+    difference (step 1e-6) in the strength."""
+    import math
+    import torch
+    from paper_1810_11103_amd import autograd as AG
+    from paper_1810_11103_amd import wenoiu
+    from paper_1810_11103_amd import workloads as W
+
+    g = W.periodic_grid(n, n, (0, 10, 0, 10), A=0.2, seed=1810 + n)
+    sol = wenoiu.Solver(g.x, g.y, "5-2MP", g.bc, g.period)
+    x = torch.as_tensor(g.x).cuda()
+    y = torch.as_tensor(g.y).cuda()
+    eps0 = 5 / (2 * math.pi)
+    U0 = AG.vortex_state_torch(x, y, torch.tensor(eps0, dtype=torch.float64, device="cuda"))
+    sol.cfl_dt(U0.contiguous(), cfl)
+    dt = float(sol.dt.item())
+
+    def run(e, grad):
+        et = torch.tensor(e, dtype=torch.float64, device="cuda", requires_grad=grad)
+        U = AG.vortex_state_torch(x, y, et)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t2 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        out = AG.rollout(U, sol, nsteps, dt, every=every)
+        J = AG.density_objective(out)
+        t1.record()
+        if grad:
+            J.backward()
+        t2.record()
+        torch.cuda.synchronize()
+        return J.item(), (et.grad.item() if grad else None), t0.elapsed_time(t1), t1.elapsed_time(t2)
+
+    run(eps0, True)  # warm-up
+    J0, dJ, t_fwd, t_bwd = run(eps0, True)
+    res = {"n": n, "steps": nsteps, "checkpoint_every": every, "dt": dt, "J": J0, "dJ_deps": dJ,
+           "forward_ms": t_fwd, "backward_ms": t_bwd, "cost_ratio": t_bwd / t_fwd, "status": sol.status()}
+    if fd_check:
+        h = 1e-6
+        fd = (run(eps0 + h, False)[0] - run(eps0 - h, False)[0]) / (2 * h)
+        res["fd_dJ_deps"] = fd
+        res["fd_rel_err"] = abs(fd - dJ) / abs(fd)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +196,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-block leg")
     ap.add_argument("--no-rhs", action="store_true", help="skip the bare-rhs timing")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM counters)")
     args = ap.parse_args()
@@ -205,7 +279,8 @@ def main():
     dom = max(("sweep_xi", "sweep_eta"), key=lambda k: kern[k][0] * kern[k][1])
     achieved = per_launch[dom] / (kern[dom][1] * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": profiled_traffic(n) if dom == "sweep_eta" else None, "kernel": dom,
                 "kernel_mean_ms": round(kern[dom][1], 4), "launches": kern[dom][0],
                 "flops_per_launch": per_launch[dom]}
 
@@ -238,6 +313,9 @@ def main():
         del sol, U
         torch.cuda.empty_cache()
         out["extra"]["batched"] = batched_leg(max(3, args.steps // 4), args.cfl)
+    if not args.no_adjoint:
+        torch.cuda.empty_cache()
+        out["extra"]["adjoint"] = adjoint_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, U0, args.scheme, args.cfl)
     print(json.dumps(out), flush=True)

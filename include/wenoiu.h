@@ -121,6 +121,29 @@ int wiu_cfl_dt(const wiu_grid* g, const wiu_params* p, const double* U, const do
 int wiu_rk3_step(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
                  const double* dt_dev, void* ws, wiu_stream_t stream);
 
+/* ---- Adjoints (metrics held fixed) ------------------------------------------
+ * Reverse-mode derivatives of the residual and of one RK3 step with respect
+ * to the state, for gradients through time integration.  Non-smooth points:
+ * the line eigenvalue's maximum passes its adjoint to the first maximal node
+ * of the line; |U^| has derivative sign(U^) with sign(0) = 0.  The result is
+ * deterministic (no floating-point atomics). */
+
+/* Ubar = (d rhs / dU)^T Gbar at state U (overwrites Ubar; no aliasing). */
+int wiu_rhs_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M,
+                const double* Gbar, double* Ubar, void* ws, wiu_stream_t stream);
+
+/* wiu_rk3_step that also stores the two intermediate stage states U1, U2
+ * (caller-owned [4][ny][nx]) for a later wiu_rk3_step_vjp. */
+int wiu_rk3_step_stages(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
+                        const double* dt_dev, double* U1, double* U2, void* ws, wiu_stream_t stream);
+
+/* Ubar_n = (d U^{n+1} / d U^n)^T Ubar_np1 for one RK3 step of size *dt_dev
+ * from U_n.  U1, U2: the stored stage states, or both NULL to recompute them.
+ * Ubar_n may alias Ubar_np1. */
+int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U_n, const double* U1,
+                     const double* U2, const double* M, const double* dt_dev, const double* Ubar_np1,
+                     double* Ubar_n, void* ws, wiu_stream_t stream);
+
 /* Synchronise `stream`, return the latched status bits of `ws` in *status
  * and clear them when `clear` is non-zero. */
 int wiu_status(void* ws, wiu_stream_t stream, int* status, int clear);

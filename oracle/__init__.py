@@ -66,6 +66,15 @@ def lib():
         L.orc_adv1d_rhs.argtypes = [_I, _I, _D, _I, _D, _D, _I, _P, _P]
         L.orc_adv1d_run.restype = _I
         L.orc_adv1d_run.argtypes = [_I, _I, _I, _D, _D, _I, _D, _P, _P]
+        for nm in ("orc_rhs_jvp", "orc_rk3_step_jvp"):
+            f = getattr(L, nm)
+            f.restype = _I
+        L.orc_rhs_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _P, _P, _P]
+        L.orc_rk3_step_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _P, _D, _P, _P]
+        L.orc_rhs_vjp.restype = _I
+        L.orc_rhs_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _P, _P]
+        L.orc_rk3_step_vjp.restype = _I
+        L.orc_rk3_step_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _D, _P, _P]
         L.orc_count_rhs_flops.restype = _I
         L.orc_count_rhs_flops.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _P]
         L.orc_set_threads.restype = None
@@ -202,6 +211,52 @@ def count_rhs_flops(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=
     if rc:
         raise ValueError("orc_count_rhs_flops failed")
     return tuple(int(v) for v in c)
+
+
+def rhs_jvp(scheme, U, V, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+    """(rhs(U), (d rhs/dU) V) by forward-mode dual numbers."""
+    U, V, M = _f64(U), _f64(V), _f64(M)
+    _, ny, nx = U.shape
+    val, tan = np.zeros_like(U), np.zeros_like(U)
+    rc = lib().orc_rhs_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+                           _ptr(U), _ptr(V), _ptr(M), _ptr(val), _ptr(tan))
+    if rc:
+        raise ValueError("orc_rhs_jvp failed")
+    return val, tan
+
+
+def rhs_vjp(scheme, U, M, Gbar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+    """(d rhs/dU)^T Gbar by reverse mode on a tape."""
+    U, M, Gbar = _f64(U), _f64(M), _f64(Gbar)
+    _, ny, nx = U.shape
+    out = np.zeros_like(U)
+    rc = lib().orc_rhs_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+                           _ptr(U), _ptr(M), _ptr(Gbar), _ptr(out))
+    if rc:
+        raise ValueError("orc_rhs_vjp failed")
+    return out
+
+
+def rk3_step_jvp(scheme, U, V, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+    U, V, M = _f64(U), _f64(V), _f64(M)
+    _, ny, nx = U.shape
+    val, tan = np.zeros_like(U), np.zeros_like(U)
+    rc = lib().orc_rk3_step_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+                                _ptr(U), _ptr(V), _ptr(M), dt, _ptr(val), _ptr(tan))
+    if rc:
+        raise ValueError("orc_rk3_step_jvp failed")
+    return val, tan
+
+
+def rk3_step_vjp(scheme, U, M, dt, Ubar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+    U, M, Ubar = _f64(U), _f64(M), _f64(Ubar)
+    _, ny, nx = U.shape
+    out = np.zeros_like(U)
+    rc = lib().orc_rk3_step_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+                                _ptr(U), _ptr(M), dt, _ptr(Ubar), _ptr(out))
+    if rc:
+        raise ValueError("orc_rk3_step_vjp failed")
+    return out
 
 
 def cfl_dt(U, M, cfl, gamma=1.4):

@@ -7,6 +7,7 @@
 // ---------------------------------------------------------------------------
 #include "wenoiu_oracle.hpp"
 #include "flop_count.hpp"
+#include "ad_types.hpp"
 
 #include <cstring>
 #ifdef _OPENMP
@@ -227,6 +228,101 @@ int orc_adv1d_run(int scheme, int N, int split, double alpha, double eps, int pp
   }
   *l2 = std::sqrt(s2 / N);
   *linf = smax;
+  return 0;
+}
+
+// ---- tangents and adjoints (metrics held fixed) ------------------------------------
+// Single-threaded: the reverse-mode tape is one global record.
+struct SingleThread {
+#ifdef _OPENMP
+  int nt;
+  SingleThread() : nt(omp_get_max_threads()) { omp_set_num_threads(1); }
+  ~SingleThread() { omp_set_num_threads(nt); }
+#endif
+};
+
+// out_val = rhs(U), out_tan = (d rhs / dU) V (forward mode).
+int orc_rhs_jvp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm,
+                const double* U, const double* V, const double* M, double* out_val, double* out_tan) {
+  if (bad_scheme(scheme) || nx < 1 || ny < 1) return -1;
+  SingleThread guard;
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Params p = make_params(gamma, alpha, eps, ppm);
+  const size_t N = 4 * (size_t)nx * ny;
+  std::vector<Dual> Ud(N), out(N);
+  for (size_t e = 0; e < N; ++e) Ud[e] = Dual(U[e], V[e]);
+  rhs<Dual>((Scheme)scheme, p, g, Ud.data(), M, out.data());
+  for (size_t e = 0; e < N; ++e) { out_val[e] = out[e].v; out_tan[e] = out[e].d; }
+  return 0;
+}
+
+// Ubar = (d rhs / dU)^T Gbar (reverse mode on a tape).
+int orc_rhs_vjp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm,
+                const double* U, const double* M, const double* Gbar, double* Ubar) {
+  if (bad_scheme(scheme) || nx < 1 || ny < 1) return -1;
+  SingleThread guard;
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Params p = make_params(gamma, alpha, eps, ppm);
+  const size_t N = 4 * (size_t)nx * ny;
+  Tape& tape = Tape::get();
+  tape.clear();
+  std::vector<Var> Uv(N), out(N);
+  for (size_t e = 0; e < N; ++e) Uv[e] = Var::leaf(U[e]);
+  rhs<Var>((Scheme)scheme, p, g, Uv.data(), M, out.data());
+  tape.adj.assign(tape.nodes.size(), 0.0);
+  for (size_t e = 0; e < N; ++e)
+    if (out[e].id >= 0) tape.adj[out[e].id] += Gbar[e];
+  tape.backward();
+  for (size_t e = 0; e < N; ++e) Ubar[e] = tape.adj[Uv[e].id];
+  tape.clear();
+  return 0;
+}
+
+// Tangent of one TVD-RK3 step at fixed dt: (U_out, dU_out) from (U, V).
+int orc_rk3_step_jvp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm,
+                     const double* U, const double* V, const double* M, double dt, double* out_val,
+                     double* out_tan) {
+  if (bad_scheme(scheme) || nx < 1 || ny < 1) return -1;
+  SingleThread guard;
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Params p = make_params(gamma, alpha, eps, ppm);
+  const size_t N = 4 * (size_t)nx * ny;
+  std::vector<Dual> Ud(N);
+  for (size_t e = 0; e < N; ++e) Ud[e] = Dual(U[e], V[e]);
+  rk3_step<Dual>((Scheme)scheme, p, g, Ud.data(), M, dt);
+  for (size_t e = 0; e < N; ++e) { out_val[e] = Ud[e].v; out_tan[e] = Ud[e].d; }
+  return 0;
+}
+
+// Adjoint of one TVD-RK3 step at fixed dt: Ubar_n = (dU^{n+1}/dU^n)^T Ubar_np1,
+// composed from the stage adjoints:
+//   U1 = U + dt L(U);  U2 = 3/4 U + 1/4 (U1 + dt L(U1));  U' = 1/3 U + 2/3 (U2 + dt L(U2))
+int orc_rk3_step_vjp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm,
+                     const double* U, const double* M, double dt, const double* Ubar_np1, double* Ubar_n) {
+  if (bad_scheme(scheme) || nx < 1 || ny < 1) return -1;
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Params p = make_params(gamma, alpha, eps, ppm);
+  const size_t N = 4 * (size_t)nx * ny;
+  std::vector<double> L(N), U1(N), U2(N), w(N), a(N), u2b(N), u1b(N);
+  rhs<double>((Scheme)scheme, p, g, U, M, L.data());
+  for (size_t e = 0; e < N; ++e) U1[e] = U[e] + dt * L[e];
+  rhs<double>((Scheme)scheme, p, g, U1.data(), M, L.data());
+  for (size_t e = 0; e < N; ++e) U2[e] = 0.75 * U[e] + 0.25 * (U1[e] + dt * L[e]);
+  // stage 3
+  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, U2.data(), M, Ubar_np1, a.data());
+  for (size_t e = 0; e < N; ++e) {
+    u2b[e] = (2.0 / 3.0) * (Ubar_np1[e] + dt * a[e]);
+    Ubar_n[e] = (1.0 / 3.0) * Ubar_np1[e];
+  }
+  // stage 2
+  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, U1.data(), M, u2b.data(), a.data());
+  for (size_t e = 0; e < N; ++e) {
+    u1b[e] = 0.25 * (u2b[e] + dt * a[e]);
+    Ubar_n[e] += 0.75 * u2b[e];
+  }
+  // stage 1
+  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, U, M, u1b.data(), a.data());
+  for (size_t e = 0; e < N; ++e) Ubar_n[e] += u1b[e] + dt * a[e];
   return 0;
 }
 

@@ -1,0 +1,400 @@
+// Hand-written reverse mode (vector-Jacobian products) of the device building
+// blocks in wiu_device.hpp, metrics held fixed.  Each routine recomputes the
+// forward quantities it needs in registers and then applies the chain rule
+// backwards; "bar" variables are adjoints.  Non-smooth points: the mappings
+// are C^1 at w = C (both pieces have zero slope there); |x| uses sign(0) = 0.
+#pragma once
+
+#include "wiu_device.hpp"
+
+namespace wiu {
+
+// ---------------------------------------------------------------------------
+// WENO r = 3 (inputs a, b, d, e around the zero centre) -- see weno5.
+// Accumulates the adjoints of the inputs.
+// ---------------------------------------------------------------------------
+WIU_DEV void weno5_vjp(double a, double b, double d, double e, double eps, int ppm, double ob, double& ab,
+                       double& bb, double& db, double& eb) {
+  const double C[3] = {0.0625, 0.625, 0.3125};
+  const double klo[3] = {256.0, 2.56, 10.24};
+  const double khi[3] = {256.0 / 225.0, 64.0 / 9.0, 256.0 / 121.0};
+  const double p[3] = {0.375 * a - 1.25 * b, 0.375 * d - 0.125 * b, 0.75 * d - 0.125 * e};
+  const double d1 = b - a, d2 = -b, d3 = d, d4 = e - d;
+  const double t[3] = {d2 - d1, d3 - d2, d4 - d3};
+  const double s[3] = {fma(3.0, d2, -d1), -(d2 + d3), fma(-3.0, d3, d4)};
+  double E[3], D[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    E[k] = eps + fma(13.0 / 12.0, t[k] * t[k], 0.25 * (s[k] * s[k]));
+    D[k] = E[k] * E[k];
+  }
+  const double al[3] = {C[0] * (D[1] * D[2]), C[1] * (D[0] * D[2]), C[2] * (D[0] * D[1])};
+  const double r = rcp(al[0] + al[1] + al[2]);
+  double w[3], g[3], K[3], dw[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    w[k] = al[k] * r;
+    dw[k] = w[k] - C[k];
+    K[k] = dw[k] <= 0.0 ? klo[k] : khi[k];
+    g[k] = ppm ? fma(K[k] * dw[k], dw[k] * dw[k], C[k]) : w[k];
+  }
+  const double sg = g[0] + g[1] + g[2];
+  const double rs = rcp(sg);
+  const double N = g[0] * p[0] + g[1] * p[1] + g[2] * p[2];
+  // out = N / sg
+  const double Nb = ob * rs;
+  const double sgb = -ob * N * rs * rs;
+  double pb[3], ab_[3], Db[3] = {0.0, 0.0, 0.0};
+  double rb = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    pb[k] = Nb * g[k];
+    const double gb = Nb * p[k] + sgb;
+    const double wb = ppm ? gb * 3.0 * K[k] * dw[k] * dw[k] : gb;
+    ab_[k] = wb * r;
+    rb += wb * al[k];
+  }
+  const double Sb = -rb * r * r;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) ab_[k] += Sb;
+  Db[0] = ab_[1] * C[1] * D[2] + ab_[2] * C[2] * D[1];
+  Db[1] = ab_[0] * C[0] * D[2] + ab_[2] * C[2] * D[0];
+  Db[2] = ab_[0] * C[0] * D[1] + ab_[1] * C[1] * D[0];
+  double tb[3], sb[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double Ib = 2.0 * E[k] * Db[k];
+    tb[k] = Ib * (13.0 / 6.0) * t[k];
+    sb[k] = Ib * 0.5 * s[k];
+  }
+  const double d1b = -tb[0] - sb[0];
+  const double d2b = tb[0] - tb[1] + 3.0 * sb[0] - sb[1];
+  const double d3b = tb[1] - tb[2] - sb[1] - 3.0 * sb[2];
+  const double d4b = tb[2] + sb[2];
+  ab += -d1b + 0.375 * pb[0];
+  bb += d1b - d2b - 1.25 * pb[0] - 0.125 * pb[1];
+  db += d3b - d4b + 0.375 * pb[1] + 0.75 * pb[2];
+  eb += d4b - 0.125 * pb[2];
+}
+
+// WENO r = 2 (inputs a, b, d around the zero centre) -- see weno3.
+WIU_DEV void weno3_vjp(double a, double b, double d, double eps, int ppm, double ob, double& ab, double& bb,
+                       double& db) {
+  const double C[2] = {0.25, 0.75};
+  const double klo[2] = {-4.0, -4.0 / 3.0};
+  const double khi[2] = {4.0 / 3.0, 4.0};
+  const double p[2] = {-0.5 * b, 0.5 * d};
+  const double d1 = b - a, d2 = -b, d3 = d;
+  const double t[2] = {d2 - d1, d3 - d2};
+  const double s[2] = {fma(3.0, d2, -d1), -(d2 + d3)};
+  double E[2], D[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    E[k] = eps + fma(13.0 / 12.0, t[k] * t[k], 0.25 * (s[k] * s[k]));
+    D[k] = E[k] * E[k];
+  }
+  const double al[2] = {C[0] * D[1], C[1] * D[0]};
+  const double r = rcp(al[0] + al[1]);
+  double w[2], g[2], K[2], dw[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    w[k] = al[k] * r;
+    dw[k] = w[k] - C[k];
+    K[k] = dw[k] <= 0.0 ? klo[k] : khi[k];
+    g[k] = ppm ? fma(K[k] * dw[k], dw[k], C[k]) : w[k];
+  }
+  const double sg = g[0] + g[1];
+  const double rs = rcp(sg);
+  const double N = g[0] * p[0] + g[1] * p[1];
+  const double Nb = ob * rs;
+  const double sgb = -ob * N * rs * rs;
+  double pb[2], ab_[2], rb = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    pb[k] = Nb * g[k];
+    const double gb = Nb * p[k] + sgb;
+    const double wb = ppm ? gb * 2.0 * K[k] * dw[k] : gb;
+    ab_[k] = wb * r;
+    rb += wb * al[k];
+  }
+  const double Sb = -rb * r * r;
+  ab_[0] += Sb;
+  ab_[1] += Sb;
+  const double Db0 = ab_[1] * C[1], Db1 = ab_[0] * C[0];
+  double tb[2], sb[2];
+  {
+    const double Ib0 = 2.0 * E[0] * Db0, Ib1 = 2.0 * E[1] * Db1;
+    tb[0] = Ib0 * (13.0 / 6.0) * t[0]; sb[0] = Ib0 * 0.5 * s[0];
+    tb[1] = Ib1 * (13.0 / 6.0) * t[1]; sb[1] = Ib1 * 0.5 * s[1];
+  }
+  const double d1b = -tb[0] - sb[0];
+  const double d2b = tb[0] - tb[1] + 3.0 * sb[0] - sb[1];
+  const double d3b = tb[1] - sb[1];
+  ab += -d1b;
+  bb += d1b - d2b - 0.5 * pb[0];
+  db += d3b + 0.5 * pb[1];
+}
+
+// ---------------------------------------------------------------------------
+// Reverse of side_flux: given Fb = adjoint of F^{+-}_{k+1/2}, accumulate
+// qb[m][c] (states k-2 .. k+3) and the adjoint of the line eigenvalue.
+// ---------------------------------------------------------------------------
+template <bool FIFTH>
+WIU_DEV void side_flux_vjp(const double q[6][4], int side, double nx_, double ny_, double mx, double my, double lam,
+                           double gam, double eps, int ppm, const double Fb[4], double qb[6][4], double& lamb) {
+  const double* Qr = q[2 + side];
+  const double gm1 = gam - 1.0;
+  // ---- forward recompute
+  const double rr = rcp(Qr[0]);
+  const double u = Qr[1] * rr, v = Qr[2] * rr;
+  const double q2 = u * u + v * v;
+  const double p = gm1 * (Qr[3] - 0.5 * Qr[0] * q2);
+  const double c2 = gam * p * rr;
+  const double rc = rsqrt_(c2);
+  const double c = c2 * rc;
+  const double H = (Qr[3] + p) * rr;
+  const double qn = u * nx_ + v * ny_;
+  const double qt = v * nx_ - u * ny_;
+  const double b1 = gm1 * (rc * rc);
+  const double b2 = 0.5 * b1 * q2;
+  constexpr int NS = FIFTH ? 5 : 4;
+  double dq[NS][4], w[4][NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (s == 2) continue;
+    const int m = side == 0 ? s : 5 - s;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) dq[s][cc] = q[m][cc] - Qr[cc];
+    const double A = b2 * dq[s][0] - b1 * (u * dq[s][1] + v * dq[s][2] - dq[s][3]);
+    const double B = rc * (qn * dq[s][0] - nx_ * dq[s][1] - ny_ * dq[s][2]);
+    w[0][s] = 0.5 * (A + B);
+    w[1][s] = dq[s][0] - A;
+    w[2][s] = nx_ * dq[s][2] - ny_ * dq[s][1] - qt * dq[s][0];
+    w[3][s] = 0.5 * (A - B);
+  }
+  double W[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if constexpr (FIFTH) W[k] = weno5(w[k][0], w[k][1], w[k][3], w[k][4], eps, ppm);
+    else W[k] = weno3(w[k][0], w[k][1], w[k][3], eps, ppm);
+  }
+  const double s03 = W[0] + W[3], d30 = W[3] - W[0];
+  const double sum = s03 + W[1];
+  const double r0 = Qr[0] + sum;
+  const double r1 = Qr[1] + (u * sum + c * nx_ * d30 - ny_ * W[2]);
+  const double r2 = Qr[2] + (v * sum + c * ny_ * d30 + nx_ * W[2]);
+  const double r3 = Qr[3] + (H * s03 + c * qn * d30 + 0.5 * q2 * W[1] + qt * W[2]);
+  const double ri = rcp(r0);
+  const double ul = r1 * ri, vl = r2 * ri;
+  const double pl = gm1 * (r3 - 0.5 * (r1 * ul + r2 * vl));
+  const double Ul = mx * ul + my * vl;
+  const double sl = side == 0 ? lam : -lam;
+  // ---- reverse: F = (r Ul + (0, mx pl, my pl, pl Ul) + sl r) / 2
+  double r0b = 0.5 * Fb[0] * (Ul + sl);
+  double r1b = 0.5 * Fb[1] * (Ul + sl);
+  double r2b = 0.5 * Fb[2] * (Ul + sl);
+  double r3b = 0.5 * Fb[3] * (Ul + sl);
+  const double Ulb = 0.5 * (Fb[0] * r0 + Fb[1] * r1 + Fb[2] * r2 + Fb[3] * (r3 + pl));
+  const double plb = 0.5 * (Fb[1] * mx + Fb[2] * my + Fb[3] * Ul);
+  const double slb = 0.5 * (Fb[0] * r0 + Fb[1] * r1 + Fb[2] * r2 + Fb[3] * r3);
+  lamb += side == 0 ? slb : -slb;
+  double ulb = Ulb * mx, vlb = Ulb * my;
+  // pl = gm1 (r3 - (r1 ul + r2 vl)/2)
+  r3b += gm1 * plb;
+  r1b -= 0.5 * gm1 * plb * ul;
+  ulb -= 0.5 * gm1 * plb * r1;
+  r2b -= 0.5 * gm1 * plb * vl;
+  vlb -= 0.5 * gm1 * plb * r2;
+  // ul = r1 ri, vl = r2 ri, ri = 1/r0
+  r1b += ulb * ri;
+  r2b += vlb * ri;
+  const double rib = ulb * r1 + vlb * r2;
+  r0b -= rib * ri * ri;
+  // r = Qr + R W
+  double Qrb[4] = {r0b, r1b, r2b, r3b};
+  const double sumb = r0b + u * r1b + v * r2b;
+  double ub = r1b * sum, vb = r2b * sum;
+  const double d30b = c * (nx_ * r1b + ny_ * r2b + qn * r3b);
+  double cb = d30 * (nx_ * r1b + ny_ * r2b + qn * r3b);
+  double Wb[4];
+  Wb[2] = -ny_ * r1b + nx_ * r2b + qt * r3b;
+  double s03b = H * r3b;
+  const double Hb = s03 * r3b;
+  double qnb = c * d30 * r3b;
+  double q2b = 0.5 * W[1] * r3b;
+  Wb[1] = 0.5 * q2 * r3b;
+  double qtb = W[2] * r3b;
+  s03b += sumb;
+  Wb[1] += sumb;
+  Wb[0] = s03b - d30b;
+  Wb[3] = s03b + d30b;
+  // WENO per characteristic component
+  double wb[4][NS];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) wb[k][s] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if constexpr (FIFTH)
+      weno5_vjp(w[k][0], w[k][1], w[k][3], w[k][4], eps, ppm, Wb[k], wb[k][0], wb[k][1], wb[k][3], wb[k][4]);
+    else
+      weno3_vjp(w[k][0], w[k][1], w[k][3], eps, ppm, Wb[k], wb[k][0], wb[k][1], wb[k][3]);
+  }
+  // projection of the deviations
+  double b1b = 0.0, b2b = 0.0, rcb = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (s == 2) continue;
+    const int m = side == 0 ? s : 5 - s;
+    const double Ab = 0.5 * wb[0][s] - wb[1][s] + 0.5 * wb[3][s];
+    const double Bb = 0.5 * wb[0][s] - 0.5 * wb[3][s];
+    double drb = wb[1][s] - qt * wb[2][s];
+    double dmb = -ny_ * wb[2][s];
+    double dnb = nx_ * wb[2][s];
+    double deb = 0.0;
+    qtb -= dq[s][0] * wb[2][s];
+    // A = b2 dr - b1 (u dm + v dn - de)
+    b2b += Ab * dq[s][0];
+    drb += Ab * b2;
+    b1b -= Ab * (u * dq[s][1] + v * dq[s][2] - dq[s][3]);
+    ub -= Ab * b1 * dq[s][1];
+    vb -= Ab * b1 * dq[s][2];
+    dmb -= Ab * b1 * u;
+    dnb -= Ab * b1 * v;
+    deb += Ab * b1;
+    // B = rc (qn dr - nx dm - ny dn)
+    rcb += Bb * (qn * dq[s][0] - nx_ * dq[s][1] - ny_ * dq[s][2]);
+    qnb += Bb * rc * dq[s][0];
+    drb += Bb * rc * qn;
+    dmb -= Bb * rc * nx_;
+    dnb -= Bb * rc * ny_;
+    // dQ = q[m] - Qr
+    qb[m][0] += drb; qb[m][1] += dmb; qb[m][2] += dnb; qb[m][3] += deb;
+    Qrb[0] -= drb; Qrb[1] -= dmb; Qrb[2] -= dnb; Qrb[3] -= deb;
+  }
+  // reference state
+  b1b += 0.5 * q2 * b2b;
+  q2b += 0.5 * b1 * b2b;
+  rcb += 2.0 * gm1 * rc * b1b;
+  vb += nx_ * qtb;
+  ub -= ny_ * qtb;
+  ub += nx_ * qnb;
+  vb += ny_ * qnb;
+  Qrb[3] += Hb * rr;
+  double pb = Hb * rr;
+  double rrb = Hb * (Qr[3] + p);
+  double c2b = cb * rc;
+  rcb += cb * c2;
+  c2b -= 0.5 * rcb * rc * rc * rc;
+  pb += c2b * gam * rr;
+  rrb += c2b * gam * p;
+  Qrb[3] += gm1 * pb;
+  Qrb[0] -= 0.5 * gm1 * q2 * pb;
+  q2b -= 0.5 * gm1 * Qr[0] * pb;
+  ub += 2.0 * u * q2b;
+  vb += 2.0 * v * q2b;
+  Qrb[1] += ub * rr;
+  rrb += ub * Qr[1];
+  Qrb[2] += vb * rr;
+  rrb += vb * Qr[2];
+  Qrb[0] -= rrb * rr * rr;
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) qb[2 + side][cc] += Qrb[cc];
+}
+
+// Reverse of nodal_split: fpb, fmb = adjoints of f^+-; accumulates Qb, lamb.
+WIU_DEV void nodal_split_vjp(const double Q[4], double kx, double ky, double lam, double gam, const double fpb[4],
+                             const double fmb[4], double Qb[4], double& lamb) {
+  const double gm1 = gam - 1.0;
+  const double ri = rcp(Q[0]);
+  const double u = Q[1] * ri, v = Q[2] * ri;
+  const double p = gm1 * (Q[3] - 0.5 * (Q[1] * u + Q[2] * v));
+  const double U = kx * u + ky * v;
+  double Eb[4], db[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    Eb[c] = 0.5 * (fpb[c] + fmb[c]);
+    db[c] = 0.5 * (fpb[c] - fmb[c]);
+    Qb[c] += lam * db[c];
+    lamb += Q[c] * db[c];
+  }
+  // E = (rho U, m U + kx p, n U + ky p, (e + p) U)
+  const double Ub = Eb[0] * Q[0] + Eb[1] * Q[1] + Eb[2] * Q[2] + Eb[3] * (Q[3] + p);
+  const double pb = Eb[1] * kx + Eb[2] * ky + Eb[3] * U;
+  Qb[0] += Eb[0] * U;
+  Qb[1] += Eb[1] * U;
+  Qb[2] += Eb[2] * U;
+  Qb[3] += Eb[3] * U;
+  double ub = Ub * kx, vb = Ub * ky;
+  // p = gm1 (e - (m u + n v)/2)
+  Qb[3] += gm1 * pb;
+  Qb[1] -= 0.5 * gm1 * pb * u;
+  ub -= 0.5 * gm1 * pb * Q[1];
+  Qb[2] -= 0.5 * gm1 * pb * v;
+  vb -= 0.5 * gm1 * pb * Q[2];
+  Qb[1] += ub * ri;
+  Qb[2] += vb * ri;
+  const double rib = ub * Q[1] + vb * Q[2];
+  Qb[0] -= rib * ri * ri;
+}
+
+// Reverse of the wave speed |k . u| + c |k| (c = sqrt(gam p / rho)).
+WIU_DEV void wave_speed_vjp(const double Q[4], double kx, double ky, double gam, double sb, double Qb[4]) {
+  const double gm1 = gam - 1.0;
+  const double ri = 1.0 / Q[0];
+  const double u = Q[1] * ri, v = Q[2] * ri;
+  const double p = gm1 * (Q[3] - 0.5 * (Q[1] * u + Q[2] * v));
+  const double U = kx * u + ky * v;
+  const double c = sqrt(gam * p * ri);
+  const double kn = sqrt(kx * kx + ky * ky);
+  const double sgn = U > 0.0 ? 1.0 : (U < 0.0 ? -1.0 : 0.0);
+  const double Ub = sb * sgn;
+  const double cb = sb * kn;
+  // c^2 = gam p ri
+  const double c2b = cb / (2.0 * c);
+  const double pb = c2b * gam * ri;
+  double rib = c2b * gam * p;
+  double ub = Ub * kx, vb = Ub * ky;
+  Qb[3] += gm1 * pb;
+  Qb[1] -= 0.5 * gm1 * pb * u;
+  ub -= 0.5 * gm1 * pb * Q[1];
+  Qb[2] -= 0.5 * gm1 * pb * v;
+  vb -= 0.5 * gm1 * pb * Q[2];
+  Qb[1] += ub * ri;
+  Qb[2] += vb * ri;
+  rib += ub * Q[1] + vb * Q[2];
+  Qb[0] -= rib * ri * ri;
+}
+
+// Adjoint of the flux combination: coefficients of H_{i+1/2} on the split
+// fluxes (Eqs. 3.4, 3.8, 3.16, 3.20 and their mirror images).  H(i) =
+//   sum_m NP[m] f+(i+m) + MP[m] F+(i+m) + NM[m] f-(i+m) + MM[m] F-(i+m),
+// m = -2 .. 3 (index m + 2); F(k) is the value at k + 1/2.
+template <int SC> struct HCoef;
+template <> struct HCoef<0> {
+  static constexpr double NP[6] = {0, -1.0 / 24, 2.0 / 24, -1.0 / 24, 0, 0};
+  static constexpr double MP[6] = {0, 0, 1.0, 0, 0, 0};
+  static constexpr double NM[6] = {0, 0, -1.0 / 24, 2.0 / 24, -1.0 / 24, 0};
+  static constexpr double MM[6] = {0, 0, 1.0, 0, 0, 0};
+};
+template <> struct HCoef<1> {
+  static constexpr double NP[6] = {0, 0, 2.0 / 6, 0, 0, 0};
+  static constexpr double MP[6] = {0, -1.0 / 6, 5.0 / 6, 0, 0, 0};
+  static constexpr double NM[6] = {0, 0, 0, 2.0 / 6, 0, 0};
+  static constexpr double MM[6] = {0, 0, 5.0 / 6, -1.0 / 6, 0, 0};
+};
+template <> struct HCoef<2> {
+  static constexpr double NP[6] = {19.0 / 1920, -116.0 / 1920, 154.0 / 1920, -36.0 / 1920, -21.0 / 1920, 0};
+  static constexpr double MP[6] = {0, 0, 1.0, 0, 0, 0};
+  static constexpr double NM[6] = {0, -21.0 / 1920, -36.0 / 1920, 154.0 / 1920, -116.0 / 1920, 19.0 / 1920};
+  static constexpr double MM[6] = {0, 0, 1.0, 0, 0, 0};
+};
+template <> struct HCoef<3> {
+  static constexpr double NP[6] = {0, 1.0 / 30, 1.0 / 30, -4.0 / 30, 0, 0};
+  static constexpr double MP[6] = {0, -4.0 / 30, 36.0 / 30, 0, 0, 0};
+  static constexpr double NM[6] = {0, 0, -4.0 / 30, 1.0 / 30, 1.0 / 30, 0};
+  static constexpr double MM[6] = {0, 0, 36.0 / 30, -4.0 / 30, 0, 0};
+};
+
+}  // namespace wiu

@@ -44,8 +44,10 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 //   0            header: int status, padding
 //   HDR          lam_xi[ny], lam_eta[nx], cfl_max[1]   (uint64 bit patterns)
 //   off_scratch  R^xi[4 np], U1[4 np], U2[4 np]  -- or the metric band temp
+//   then the adjoint region: A, Ubar2, Ubar1, acc (4 planes each), eigenvalue
+//   partials [max lines x segments], off-line contributions [max lines][2][6][4]
 struct WsLayout {
-  size_t lam, scratch, rxi, u1, u2, total;
+  size_t lam, scratch, rxi, u1, u2, qa, ub2, ub1, acc, lpart, ghost, total;
 };
 
 WsLayout layout(const wiu_grid* g) {
@@ -53,14 +55,23 @@ WsLayout layout(const wiu_grid* g) {
   const size_t np = (size_t)g->nx * g->ny;
   const int B = GHOST + 3;
   const size_t band = 5 * (size_t)(g->nx + 2 * B) * (g->ny + 2 * B);
+  const size_t plane4 = align_up(4 * np * 8);
   L.lam = ALIGN;
   L.scratch = L.lam + align_up(((size_t)g->nx + g->ny + 1) * 8);
   L.rxi = L.scratch;
-  L.u1 = L.rxi + align_up(4 * np * 8);
-  L.u2 = L.u1 + align_up(4 * np * 8);
-  const size_t end_rk = L.u2 + align_up(4 * np * 8);
+  L.u1 = L.rxi + plane4;
+  L.u2 = L.u1 + plane4;
+  const size_t end_rk = L.u2 + plane4;
   const size_t end_met = L.scratch + align_up(band * 8);
-  L.total = end_rk > end_met ? end_rk : end_met;
+  L.qa = end_rk > end_met ? end_rk : end_met;
+  L.ub2 = L.qa + plane4;
+  L.ub1 = L.ub2 + plane4;
+  L.acc = L.ub1 + plane4;
+  const size_t lp_xi = (size_t)g->ny * adj_nseg(0, g->nx), lp_eta = (size_t)g->nx * adj_nseg(1, g->ny);
+  L.lpart = L.acc + plane4;
+  L.ghost = L.lpart + align_up((lp_xi > lp_eta ? lp_xi : lp_eta) * 8);
+  const size_t nl = (size_t)(g->nx > g->ny ? g->nx : g->ny);
+  L.total = L.ghost + align_up(nl * 2 * 6 * 4 * 8);
   return L;
 }
 
@@ -97,6 +108,7 @@ struct Ws {
   int* status;
   unsigned long long *lx, *le, *cfl;
   double *rxi, *u1, *u2, *band;
+  double *qa, *ub2, *ub1, *acc, *lpart, *ghost;
 };
 
 Ws carve(const wiu_grid* g, void* ws) {
@@ -111,7 +123,28 @@ Ws carve(const wiu_grid* g, void* ws) {
   w.u1 = (double*)(b + L.u1);
   w.u2 = (double*)(b + L.u2);
   w.band = (double*)(b + L.scratch);
+  w.qa = (double*)(b + L.qa);
+  w.ub2 = (double*)(b + L.ub2);
+  w.ub1 = (double*)(b + L.ub1);
+  w.acc = (double*)(b + L.acc);
+  w.lpart = (double*)(b + L.lpart);
+  w.ghost = (double*)(b + L.ghost);
   return w;
+}
+
+// Ubar = (d rhs / dU)^T Gbar at state U.
+int residual_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M,
+                 const double* Gbar, double* Ubar, const Ws& w, hipStream_t st) {
+  Dims d = dims(g);
+  if (launch_wave_max(d, U, M, p->gamma, w.lx, w.le, w.cfl, w.status, st) != hipSuccess) return WIU_EHIP;
+  AdjArgs a;
+  a.d = d; a.U = U; a.M = M; a.Gbar = Gbar; a.Ubar = Ubar; a.lam_xi = w.lx; a.lam_eta = w.le;
+  a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
+  a.lam_part = w.lpart; a.ghost = w.ghost;
+  a.accumulate = 0;
+  if (launch_adj_sweep(scheme, 0, a, st) != hipSuccess) return WIU_EHIP;
+  a.accumulate = 1;
+  return launch_adj_sweep(scheme, 1, a, st) == hipSuccess ? WIU_OK : WIU_EHIP;
 }
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? WIU_OK : WIU_EHIP; }
@@ -215,6 +248,58 @@ int wiu_rk3_step(const wiu_grid* g, int scheme, const wiu_params* p, double* U, 
   rc = residual(g, scheme, p, w.u1, M, w, 2, w.u2, U, dt_dev, 0.75, 0.25, st);
   if (rc) return rc;
   return residual(g, scheme, p, w.u2, M, w, 2, U, U, dt_dev, 1.0 / 3.0, 2.0 / 3.0, st);
+}
+
+int wiu_rhs_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M,
+                const double* Gbar, double* Ubar, void* ws, wiu_stream_t stream) {
+  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !Gbar || !Ubar || !ws) return WIU_EINVAL;
+  if (Ubar == U || Ubar == Gbar) return WIU_EINVAL;
+  Ws w = carve(g, ws);
+  return residual_vjp(g, scheme, p, U, M, Gbar, Ubar, w, (hipStream_t)stream);
+}
+
+int wiu_rk3_step_stages(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
+                        const double* dt_dev, double* U1, double* U2, void* ws, wiu_stream_t stream) {
+  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !dt_dev || !U1 || !U2 || !ws)
+    return WIU_EINVAL;
+  Ws w = carve(g, ws);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = residual(g, scheme, p, U, M, w, 2, U1, U, dt_dev, 0.0, 1.0, st);
+  if (rc) return rc;
+  rc = residual(g, scheme, p, U1, M, w, 2, U2, U, dt_dev, 0.75, 0.25, st);
+  if (rc) return rc;
+  return residual(g, scheme, p, U2, M, w, 2, U, U, dt_dev, 1.0 / 3.0, 2.0 / 3.0, st);
+}
+
+int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U_n, const double* U1,
+                     const double* U2, const double* M, const double* dt_dev, const double* Ubar_np1,
+                     double* Ubar_n, void* ws, wiu_stream_t stream) {
+  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U_n || !M || !dt_dev || !Ubar_np1 || !Ubar_n || !ws)
+    return WIU_EINVAL;
+  if ((U1 == nullptr) != (U2 == nullptr)) return WIU_EINVAL;
+  Ws w = carve(g, ws);
+  hipStream_t st = (hipStream_t)stream;
+  const long long n = 4LL * g->nx * g->ny;
+  int rc;
+  if (!U1) {  // recompute the stage states
+    rc = residual(g, scheme, p, U_n, M, w, 2, w.u1, U_n, dt_dev, 0.0, 1.0, st);
+    if (rc) return rc;
+    rc = residual(g, scheme, p, w.u1, M, w, 2, w.u2, U_n, dt_dev, 0.75, 0.25, st);
+    if (rc) return rc;
+    U1 = w.u1;
+    U2 = w.u2;
+  }
+  // U' = 1/3 U + 2/3 (U2 + dt L(U2))
+  if ((rc = residual_vjp(g, scheme, p, U2, M, Ubar_np1, w.qa, w, st))) return rc;
+  if (launch_axpy(n, 0.0, nullptr, 2.0 / 3.0, Ubar_np1, dt_dev, w.qa, w.ub2, st) != hipSuccess) return WIU_EHIP;
+  if (launch_axpy(n, 1.0 / 3.0, Ubar_np1, 0.0, nullptr, dt_dev, nullptr, w.acc, st) != hipSuccess) return WIU_EHIP;
+  // U2 = 3/4 U + 1/4 (U1 + dt L(U1))
+  if ((rc = residual_vjp(g, scheme, p, U1, M, w.ub2, w.qa, w, st))) return rc;
+  if (launch_axpy(n, 0.0, nullptr, 0.25, w.ub2, dt_dev, w.qa, w.ub1, st) != hipSuccess) return WIU_EHIP;
+  if (launch_axpy(n, 1.0, w.acc, 0.75, w.ub2, dt_dev, nullptr, w.acc, st) != hipSuccess) return WIU_EHIP;
+  // U1 = U + dt L(U)
+  if ((rc = residual_vjp(g, scheme, p, U_n, M, w.ub1, w.qa, w, st))) return rc;
+  return launch_axpy(n, 1.0, w.acc, 1.0, w.ub1, dt_dev, w.qa, Ubar_n, st) == hipSuccess ? WIU_OK : WIU_EHIP;
 }
 
 int wiu_status(void* ws, wiu_stream_t stream, int* status, int clear) {

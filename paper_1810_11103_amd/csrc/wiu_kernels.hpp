@@ -43,6 +43,26 @@ struct BatchArgs {
   int* status;
 };
 
+// Arguments of the adjoint sweeps and their per-line fix-up.
+struct AdjArgs {
+  Dims d;
+  const double* U;                      // state the residual was evaluated at
+  const double* M;
+  const double* Gbar;                   // adjoint of dU/dt
+  double* Ubar;                         // adjoint of U (written or accumulated)
+  const unsigned long long* lam_xi;     // raw line maxima of U
+  const unsigned long long* lam_eta;
+  double gamma, alpha, eps;
+  int ppm;
+  int accumulate;                       // 0: write Ubar, 1: add to it
+  double* lam_part;                     // [lines][segments] eigenvalue adjoints
+  double* ghost;                        // [lines][2][6][4] off-line contributions
+};
+
+hipError_t launch_adj_sweep(int scheme, int dir, const AdjArgs& a, hipStream_t st);
+int adj_nseg(int dir, int n_al);
+hipError_t launch_axpy(long long n, double a, const double* x, double b, const double* y, const double* dt,
+                       const double* z, double* out, hipStream_t st);
 hipError_t launch_sweep(int scheme, int dir, int variant, const SweepArgs& a, hipStream_t st);
 hipError_t launch_batched_sweep(int scheme, int dir, int variant, const BatchArgs& a, hipStream_t st);
 hipError_t launch_batched_wave_max(const BatchArgs& a, hipStream_t st);

@@ -1,0 +1,215 @@
+// Tile-level device code shared by the single-grid and batched kernels:
+// the wave-speed maxima of one tile and one tile of a direction sweep.
+#pragma once
+
+#include "wiu_kernels.hpp"
+
+namespace wiu {
+
+struct WaveLds {
+  double scol[4][64];
+  double scfl[4];
+};
+
+// One 64 x 16 tile (tx, ty) of the wave-speed maxima; block of 64 x 4 threads.
+WIU_DEV void wave_max_tile(const Dims& d, const double* __restrict__ U, const double* __restrict__ M, double gam,
+                           unsigned long long* __restrict__ lam_xi, unsigned long long* __restrict__ lam_eta,
+                           unsigned long long* __restrict__ cfl_max, int* __restrict__ status, int tx, int ty,
+                           WaveLds& L) {
+  // each thread row covers ROWS rows
+  constexpr int ROWS = 4;
+  auto& scol = L.scol;
+  auto& scfl = L.scfl;
+  __syncthreads();  // LDS of the previous tile is free
+  const int i = tx * 64 + threadIdx.x;
+  const int j0 = (ty * 4 + threadIdx.y) * ROWS;
+  double colmax = 0.0, cflm = 0.0;
+  bool bad_any = false;
+  for (int r = 0; r < ROWS; ++r) {
+    const int j = j0 + r;
+    double sx = 0.0;
+    if (i < d.nx && j < d.ny) {
+      const long long o = (long long)j * d.nx + i;
+      const double Q[4] = {U[o], U[d.np + o], U[2 * d.np + o], U[3 * d.np + o]};
+      const long long mo = (long long)(j + GHOST) * d.mpitch + (i + GHOST);
+      bool b1, b2;
+      sx = wave_speed(Q, M[mo], M[d.mplane + mo], gam, b1);
+      const double se = wave_speed(Q, M[2 * d.mplane + mo], M[3 * d.mplane + mo], gam, b2);
+      bad_any |= b1 || b2;
+      colmax = fmax(colmax, se);  // non-finite speeds are flagged through `status`
+      cflm = fmax(cflm, (sx + se) / M[4 * d.mplane + mo]);
+    }
+    // row max across the 64 lanes of this wave (one wave = one row segment)
+    double v = sx;
+    for (int off = 32; off > 0; off >>= 1) {
+      v = fmax(v, __shfl_xor(v, off, 64));
+    }
+    if (threadIdx.x == 0 && j < d.ny)
+      atomicMax(&lam_xi[j], (unsigned long long)__double_as_longlong(v));
+  }
+  scol[threadIdx.y][threadIdx.x] = colmax;
+  double c = cflm;
+  for (int off = 32; off > 0; off >>= 1) {
+    c = fmax(c, __shfl_xor(c, off, 64));
+  }
+  if (threadIdx.x == 0) scfl[threadIdx.y] = c;
+  if (bad_any) atomicOr(status, ST_NONPHYS);
+  __syncthreads();
+  if (threadIdx.y == 0) {
+    double m = scol[0][threadIdx.x];
+    for (int t = 1; t < 4; ++t) m = fmax(m, scol[t][threadIdx.x]);
+    if (i < d.nx) atomicMax(&lam_eta[i], (unsigned long long)__double_as_longlong(m));
+    if (threadIdx.x == 0 && cfl_max) {
+      double mm = scfl[0];
+      for (int t = 1; t < 4; ++t) mm = fmax(mm, scfl[t]);
+      atomicMax(cfl_max, (unsigned long long)__double_as_longlong(mm));
+    }
+  }
+}
+
+
+template <int SC, int DIR, int NA, int NB> struct SweepLds {
+  double sh[16][NA * NB];        // [kind*4 + comp][item]: kinds fp, fm, Fp, Fm
+  double sq[4][NB][NA + 5];      // stencil tile: items k - 2 .. k + 3
+};
+
+// One tile of a sweep: logical tile (bxl, byl) = (segment along the line,
+// group of lines) for xi, (group of lines, segment) for eta.  Every thread of
+// the block calls it with the same tile; it contains three block-wide
+// barriers on every path that reaches the output phase, and none after.
+template <int SC, int DIR, int NA, int NB>
+WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, NA, NB>& L) {
+  using R_ = Range<SC>;
+  constexpr int OUT = NA - R_::EXTRA;
+  constexpr int NT = NA * NB;
+  constexpr int NQ = NA + 5;
+  auto& sh = L.sh;
+  auto& sq = L.sq;
+
+  const Dims& d = s.d;
+  // metrics built for another scheme or grid: flag and do nothing (uniform
+  // over the block, so no barrier is skipped by part of it)
+  {
+    const double* tag = s.M + 9 * d.mplane;
+    if (tag[0] != TAG_MAGIC || tag[1] != (double)SC || tag[2] != (double)d.nx || tag[3] != (double)d.ny) {
+      if (threadIdx.x == 0 && threadIdx.y == 0) atomicOr(s.status, ST_SCHEME);
+      return;
+    }
+  }
+  __syncthreads();  // LDS of the previous tile is free
+  const int ta = DIR == 0 ? threadIdx.x : threadIdx.y;  // along
+  const int tb = DIR == 0 ? threadIdx.y : threadIdx.x;  // across
+  const int n_al = DIR == 0 ? d.nx : d.ny;
+  const int n_ac = DIR == 0 ? d.ny : d.nx;
+  const int bc_al = DIR == 0 ? d.bcx : d.bcy;
+  const int line = (DIR == 0 ? byl : bxl) * NB + tb;
+  const int o0 = (DIR == 0 ? bxl : byl) * OUT;
+  const int out = min(OUT, n_al - o0);
+  const int k = o0 + R_::LO + ta;
+  const int slot = tb * NA + ta;
+  const bool live = line < n_ac;
+
+  // element offsets
+  const long long mstride = DIR == 0 ? 1 : d.mpitch;
+  const long long mline = DIR == 0 ? (long long)(line + GHOST) * d.mpitch + GHOST
+                                   : (long long)GHOST * d.mpitch + (line + GHOST);
+  const double* Mk = s.M + (DIR == 0 ? 0 : 2) * d.mplane;   // nodal k_x^ plane
+  const double* Mm = s.M + (DIR == 0 ? 5 : 7) * d.mplane;   // midpoint plane
+  const double gam = s.gamma;
+
+  double lam = 0.0;
+  if (live) {
+    const unsigned long long* lp = DIR == 0 ? s.lam_xi : s.lam_eta;
+    lam = s.alpha * __longlong_as_double((long long)lp[line]);
+  }
+
+  const bool need_node = live && k >= o0 + Traits<SC>::NLO && k < o0 + out + Traits<SC>::NHI;
+  const bool need_mid = live && k >= o0 + Traits<SC>::MLO && k < o0 + out + Traits<SC>::MHI;
+
+  // Stage the states of the tile (with the boundary rule applied) in LDS,
+  // consecutive threads reading consecutive addresses.
+  {
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int k0 = o0 + R_::LO - 2;
+    for (int e = tid; e < NQ * NB; e += NT) {
+      const int pos = DIR == 0 ? e % NQ : e / NB;
+      const int lb = DIR == 0 ? e / NQ : e % NB;
+      const int ln = (DIR == 0 ? byl : bxl) * NB + lb;
+      if (ln < n_ac) {
+        const int kk = bc_index(k0 + pos, n_al, bc_al);
+        const long long o = DIR == 0 ? (long long)ln * d.nx + kk : (long long)kk * d.nx + ln;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sq[c][lb][pos] = s.U[c * d.np + o];
+      }
+    }
+  }
+  __syncthreads();
+
+  if (need_node || need_mid) {
+    // stencil states Q_{k-2..k+3}
+    double q[6][4];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[m][c] = sq[c][tb][ta + m];
+    }
+    const long long mo = mline + mstride * k;
+    const double kx0 = Mk[mo], ky0 = Mk[d.mplane + mo];
+    if (need_node) {
+      double fp[4], fm[4];
+      nodal_split(q[2], kx0, ky0, lam, gam, fp, fm);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) { sh[c][slot] = fp[c]; sh[4 + c][slot] = fm[c]; }
+    }
+    if (need_mid) {
+      const double kx1 = Mk[mo + mstride], ky1 = Mk[d.mplane + mo + mstride];
+      const double mx = Mm[mo], my = Mm[d.mplane + mo];
+      const double nbx = 0.5 * (kx0 + kx1), nby = 0.5 * (ky0 + ky1);
+      const double rn = rsqrt_(nbx * nbx + nby * nby);
+      const double nx_ = nbx * rn, ny_ = nby * rn;
+      double Fp[4], Fm[4];
+      side_flux<Traits<SC>::fifth>(q, 0, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, Fp);
+      side_flux<Traits<SC>::fifth>(q, 1, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, Fm);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) { sh[8 + c][slot] = Fp[c]; sh[12 + c][slot] = Fm[c]; }
+    }
+  }
+  __syncthreads();
+
+  if (!live || ta >= out) return;  // no barrier follows
+  const int i = o0 + ta;                  // output node along the line
+  const int base = tb * NA - (o0 + R_::LO);  // slot of line index kk is base + kk
+  double R[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    auto fp = [&](int kk) { return sh[c][base + kk]; };
+    auto fm = [&](int kk) { return sh[4 + c][base + kk]; };
+    auto Fp = [&](int kk) { return sh[8 + c][base + kk]; };
+    auto Fm = [&](int kk) { return sh[12 + c][base + kk]; };
+    R[c] = hflux<SC>(i, fp, fm, Fp, Fm) - hflux<SC>(i - 1, fp, fm, Fp, Fm);
+  }
+  const long long o = DIR == 0 ? (long long)line * d.nx + i : (long long)i * d.nx + line;
+  if (s.mode == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s.Rxi[c * d.np + o] = R[c];
+    return;
+  }
+  const int ii = DIR == 0 ? i : line, jj = DIR == 0 ? line : i;
+  const double jinv = s.M[4 * d.mplane + (long long)(jj + GHOST) * d.mpitch + (ii + GHOST)];
+  const double rj = -rcp(jinv);
+  if (s.mode == 1) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s.out[c * d.np + o] = (s.Rxi[c * d.np + o] + R[c]) * rj;
+    return;
+  }
+  const double dt = s.dt[0];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double L = (s.Rxi[c * d.np + o] + R[c]) * rj;
+    const long long e = c * d.np + o;
+    s.out[e] = s.ca * s.U0[e] + s.cb * (s.U[e] + dt * L);
+  }
+}
+
+
+}  // namespace wiu

@@ -25,6 +25,7 @@ EXPORTS = [
     "wiu_profile_enable", "wiu_profile_read", "wiu_tuning_variants", "wiu_set_tuning", "wiu_get_tuning",
     "wiu_batched_plan", "wiu_batched_info", "wiu_batched_set_dt", "wiu_batched_cfl_dt", "wiu_batched_get_dt",
     "wiu_batched_rk3_step", "wiu_batched_status", "wiu_plan_destroy",
+    "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp",
 ]
 KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3}
 
@@ -74,6 +75,9 @@ def _load():
         "wiu_batched_rk3_step": (I, [P, I, P]),
         "wiu_batched_status": (I, [P, P, ctypes.POINTER(I), I]),
         "wiu_plan_destroy": (I, [P]),
+        "wiu_rhs_vjp": (I, [G, I, PR, P, P, P, P, P, P]),
+        "wiu_rk3_step_stages": (I, [G, I, PR, P, P, P, P, P, P, P]),
+        "wiu_rk3_step_vjp": (I, [G, I, PR, P, P, P, P, P, P, P, P, P]),
         "wiu_tuning_variants": (I, [I]),
         "wiu_set_tuning": (I, [I, I]),
         "wiu_get_tuning": (I, [I]),
@@ -191,6 +195,25 @@ def rk3_step(grid, scheme, params, U, M, dt_dev, ws, stream=None):
     return U
 
 
+def rhs_vjp(grid, scheme, params, U, M, Gbar, Ubar, ws, stream=None):
+    _check(lib.wiu_rhs_vjp(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U), _ptr(M), _ptr(Gbar),
+                           _ptr(Ubar), ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+    return Ubar
+
+
+def rk3_step_stages(grid, scheme, params, U, M, dt_dev, U1, U2, ws, stream=None):
+    _check(lib.wiu_rk3_step_stages(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U), _ptr(M),
+                                   _ptr(dt_dev), _ptr(U1), _ptr(U2), ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+    return U
+
+
+def rk3_step_vjp(grid, scheme, params, U_n, U1, U2, M, dt_dev, Ubar_np1, Ubar_n, ws, stream=None):
+    _check(lib.wiu_rk3_step_vjp(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U_n), _ptr(U1),
+                                _ptr(U2), _ptr(M), _ptr(dt_dev), _ptr(Ubar_np1), _ptr(Ubar_n),
+                                ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+    return Ubar_n
+
+
 def status(ws, clear=True, stream=None):
     v = ctypes.c_int(0)
     _check(lib.wiu_status(ctypes.c_void_p(ws.data_ptr()), _stream(stream), ctypes.byref(v), int(clear)))
@@ -252,6 +275,17 @@ class Solver:
         if dt is not None:
             self.dt.fill_(float(dt))
         return rk3_step(self.grid, self.scheme, self.params, U, self.M, self.dt, self.ws)
+
+    def rhs_vjp(self, U, Gbar, out=None):
+        out = torch.empty_like(U) if out is None else out
+        return rhs_vjp(self.grid, self.scheme, self.params, U, self.M, Gbar, out, self.ws)
+
+    def rk3_step_stages(self, U, U1, U2):
+        return rk3_step_stages(self.grid, self.scheme, self.params, U, self.M, self.dt, U1, U2, self.ws)
+
+    def rk3_step_vjp(self, U_n, Ubar_np1, U1=None, U2=None, out=None):
+        out = torch.empty_like(U_n) if out is None else out
+        return rk3_step_vjp(self.grid, self.scheme, self.params, U_n, U1, U2, self.M, self.dt, Ubar_np1, out, self.ws)
 
     def line_eigenvalues(self, U):
         lx = torch.empty(self.grid.ny, dtype=torch.float64, device=self.device)

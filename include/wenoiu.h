@@ -62,6 +62,7 @@ enum { WIU_BC_PERIODIC = 0, WIU_BC_TRANSMISSIVE = 1 };
 #define WIU_ST_JACOBIAN 1 /* J^{-1} <= 0 or non-finite at some node (folded cell) */
 #define WIU_ST_NONPHYS 2  /* rho <= 0, p <= 0 or a non-finite state entry */
 #define WIU_ST_SCHEME 4   /* metrics were built for another scheme or grid */
+#define WIU_ST_ARGMAX 8   /* adjoint: no node of a line reproduced its maximum wave speed */
 
 typedef struct {
   int nx, ny;               /* nodes per direction (>= 1; >= 2 if transmissive) */

@@ -16,8 +16,8 @@ namespace wiu {
 WIU_DEV void weno5_vjp(double a, double b, double d, double e, double eps, int ppm, double ob, double& ab,
                        double& bb, double& db, double& eb) {
   const double C[3] = {0.0625, 0.625, 0.3125};
-  const double klo[3] = {256.0, 2.56, 10.24};
-  const double khi[3] = {256.0 / 225.0, 64.0 / 9.0, 256.0 / 121.0};
+  const double MA[3] = {WIU_M3A0, WIU_M3A1, WIU_M3A2};
+  const double MB[3] = {WIU_M3B0, WIU_M3B1, WIU_M3B2};
   const double p[3] = {0.375 * a - 1.25 * b, 0.375 * d - 0.125 * b, 0.75 * d - 0.125 * e};
   const double d1 = b - a, d2 = -b, d3 = d, d4 = e - d;
   const double t[3] = {d2 - d1, d3 - d2, d4 - d3};
@@ -30,13 +30,13 @@ WIU_DEV void weno5_vjp(double a, double b, double d, double e, double eps, int p
   }
   const double al[3] = {C[0] * (D[1] * D[2]), C[1] * (D[0] * D[2]), C[2] * (D[0] * D[1])};
   const double r = rcp(al[0] + al[1] + al[2]);
-  double w[3], g[3], K[3], dw[3];
+  double w[3], g[3], h[3], dw[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     w[k] = al[k] * r;
     dw[k] = w[k] - C[k];
-    K[k] = dw[k] <= 0.0 ? klo[k] : khi[k];
-    g[k] = ppm ? fma(K[k] * dw[k], dw[k] * dw[k], C[k]) : w[k];
+    h[k] = fma(MA[k], dw[k], MB[k] * fabs(dw[k]));  // K d
+    g[k] = ppm ? fma(dw[k] * dw[k], h[k], C[k]) : w[k];
   }
   const double sg = g[0] + g[1] + g[2];
   const double rs = rcp(sg);
@@ -50,7 +50,7 @@ WIU_DEV void weno5_vjp(double a, double b, double d, double e, double eps, int p
   for (int k = 0; k < 3; ++k) {
     pb[k] = Nb * g[k];
     const double gb = Nb * p[k] + sgb;
-    const double wb = ppm ? gb * 3.0 * K[k] * dw[k] * dw[k] : gb;
+    const double wb = ppm ? gb * 3.0 * (dw[k] * h[k]) : gb;  // dg/dw = 3 K d^2
     ab_[k] = wb * r;
     rb += wb * al[k];
   }
@@ -81,8 +81,8 @@ WIU_DEV void weno5_vjp(double a, double b, double d, double e, double eps, int p
 WIU_DEV void weno3_vjp(double a, double b, double d, double eps, int ppm, double ob, double& ab, double& bb,
                        double& db) {
   const double C[2] = {0.25, 0.75};
-  const double klo[2] = {-4.0, -4.0 / 3.0};
-  const double khi[2] = {4.0 / 3.0, 4.0};
+  const double MA[2] = {WIU_M2A0, WIU_M2A1};
+  const double MB[2] = {WIU_M2B0, WIU_M2B1};
   const double p[2] = {-0.5 * b, 0.5 * d};
   const double d1 = b - a, d2 = -b, d3 = d;
   const double t[2] = {d2 - d1, d3 - d2};
@@ -95,13 +95,13 @@ WIU_DEV void weno3_vjp(double a, double b, double d, double eps, int ppm, double
   }
   const double al[2] = {C[0] * D[1], C[1] * D[0]};
   const double r = rcp(al[0] + al[1]);
-  double w[2], g[2], K[2], dw[2];
+  double w[2], g[2], h[2], dw[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     w[k] = al[k] * r;
     dw[k] = w[k] - C[k];
-    K[k] = dw[k] <= 0.0 ? klo[k] : khi[k];
-    g[k] = ppm ? fma(K[k] * dw[k], dw[k], C[k]) : w[k];
+    h[k] = fma(MA[k], dw[k], MB[k] * fabs(dw[k]));  // K d
+    g[k] = ppm ? fma(dw[k], h[k], C[k]) : w[k];
   }
   const double sg = g[0] + g[1];
   const double rs = rcp(sg);
@@ -113,7 +113,7 @@ WIU_DEV void weno3_vjp(double a, double b, double d, double eps, int ppm, double
   for (int k = 0; k < 2; ++k) {
     pb[k] = Nb * g[k];
     const double gb = Nb * p[k] + sgb;
-    const double wb = ppm ? gb * 2.0 * K[k] * dw[k] : gb;
+    const double wb = ppm ? gb * 2.0 * h[k] : gb;  // dg/dw = 2 K d
     ab_[k] = wb * r;
     rb += wb * al[k];
   }
@@ -136,13 +136,18 @@ WIU_DEV void weno3_vjp(double a, double b, double d, double eps, int ppm, double
 }
 
 // ---------------------------------------------------------------------------
-// Reverse of side_flux: given Fb = adjoint of F^{+-}_{k+1/2}, accumulate
-// qb[m][c] (states k-2 .. k+3) and the adjoint of the line eigenvalue.
+// Reverse of side_flux for one side: given Fb = adjoint of F^{+-}_{k+1/2},
+// accumulate the adjoints of the states k-2 .. k+3 and of the line
+// eigenvalue.  The states are read through q(m, c) and the adjoints added
+// through qb(m, c, value), so both can live in LDS.  Per stencil node only
+// the five forward values A, B, drho, dm, dn of the projection are kept; the
+// characteristic values are rebuilt from them where needed.
 // ---------------------------------------------------------------------------
-template <bool FIFTH>
-WIU_DEV void side_flux_vjp(const double q[6][4], int side, double nx_, double ny_, double mx, double my, double lam,
-                           double gam, double eps, int ppm, const double Fb[4], double qb[6][4], double& lamb) {
-  const double* Qr = q[2 + side];
+template <bool FIFTH, class QF, class QBF>
+WIU_DEV void side_flux_vjp(QF q, int side, double nx_, double ny_, double mx, double my, double lam, double gam,
+                           double eps, int ppm, const double Fb[4], QBF qb, double& lamb) {
+  const int mr = 2 + side;
+  const double Qr[4] = {q(mr, 0), q(mr, 1), q(mr, 2), q(mr, 3)};
   const double gm1 = gam - 1.0;
   // ---- forward recompute
   const double rr = rcp(Qr[0]);
@@ -158,25 +163,26 @@ WIU_DEV void side_flux_vjp(const double q[6][4], int side, double nx_, double ny
   const double b1 = gm1 * (rc * rc);
   const double b2 = 0.5 * b1 * q2;
   constexpr int NS = FIFTH ? 5 : 4;
-  double dq[NS][4], w[4][NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    if (s == 2) continue;
-    const int m = side == 0 ? s : 5 - s;
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) dq[s][cc] = q[m][cc] - Qr[cc];
-    const double A = b2 * dq[s][0] - b1 * (u * dq[s][1] + v * dq[s][2] - dq[s][3]);
-    const double B = rc * (qn * dq[s][0] - nx_ * dq[s][1] - ny_ * dq[s][2]);
-    w[0][s] = 0.5 * (A + B);
-    w[1][s] = dq[s][0] - A;
-    w[2][s] = nx_ * dq[s][2] - ny_ * dq[s][1] - qt * dq[s][0];
-    w[3][s] = 0.5 * (A - B);
-  }
+  // stencil slot s <-> state m (left-biased order for side 0, mirrored for 1);
+  // slot 2 is the reference node, whose deviation is zero
+  auto mof = [&](int s_) { return side == 0 ? s_ : 5 - s_; };
+  // characteristic value k of slot s_, recomputed from the staged states
+  // wherever it is needed (keeps the register working set small)
+  auto wv = [&](int k, int s_) {
+    const int m = mof(s_);
+    const double dr = q(m, 0) - Qr[0], dm = q(m, 1) - Qr[1], dn = q(m, 2) - Qr[2];
+    if (k == 2) return nx_ * dn - ny_ * dm - qt * dr;
+    const double de = q(m, 3) - Qr[3];
+    const double A = b2 * dr - b1 * (u * dm + v * dn - de);
+    if (k == 1) return dr - A;
+    const double B = rc * (qn * dr - nx_ * dm - ny_ * dn);
+    return k == 0 ? 0.5 * (A + B) : 0.5 * (A - B);
+  };
   double W[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if constexpr (FIFTH) W[k] = weno5(w[k][0], w[k][1], w[k][3], w[k][4], eps, ppm);
-    else W[k] = weno3(w[k][0], w[k][1], w[k][3], eps, ppm);
+    if constexpr (FIFTH) W[k] = weno5(wv(k, 0), wv(k, 1), wv(k, 3), wv(k, 4), eps, ppm);
+    else W[k] = weno3(wv(k, 0), wv(k, 1), wv(k, 3), eps, ppm);
   }
   const double s03 = W[0] + W[3], d30 = W[3] - W[0];
   const double sum = s03 + W[1];
@@ -199,78 +205,71 @@ WIU_DEV void side_flux_vjp(const double q[6][4], int side, double nx_, double ny
   const double slb = 0.5 * (Fb[0] * r0 + Fb[1] * r1 + Fb[2] * r2 + Fb[3] * r3);
   lamb += side == 0 ? slb : -slb;
   double ulb = Ulb * mx, vlb = Ulb * my;
-  // pl = gm1 (r3 - (r1 ul + r2 vl)/2)
   r3b += gm1 * plb;
   r1b -= 0.5 * gm1 * plb * ul;
   ulb -= 0.5 * gm1 * plb * r1;
   r2b -= 0.5 * gm1 * plb * vl;
   vlb -= 0.5 * gm1 * plb * r2;
-  // ul = r1 ri, vl = r2 ri, ri = 1/r0
   r1b += ulb * ri;
   r2b += vlb * ri;
-  const double rib = ulb * r1 + vlb * r2;
-  r0b -= rib * ri * ri;
+  r0b -= (ulb * r1 + vlb * r2) * ri * ri;
   // r = Qr + R W
   double Qrb[4] = {r0b, r1b, r2b, r3b};
   const double sumb = r0b + u * r1b + v * r2b;
   double ub = r1b * sum, vb = r2b * sum;
   const double d30b = c * (nx_ * r1b + ny_ * r2b + qn * r3b);
-  double cb = d30 * (nx_ * r1b + ny_ * r2b + qn * r3b);
-  double Wb[4];
-  Wb[2] = -ny_ * r1b + nx_ * r2b + qt * r3b;
-  double s03b = H * r3b;
+  const double cb = d30 * (nx_ * r1b + ny_ * r2b + qn * r3b);
+  const double Wb2 = -ny_ * r1b + nx_ * r2b + qt * r3b;
+  const double s03b = H * r3b + sumb;
   const double Hb = s03 * r3b;
   double qnb = c * d30 * r3b;
   double q2b = 0.5 * W[1] * r3b;
-  Wb[1] = 0.5 * q2 * r3b;
+  const double Wb1 = 0.5 * q2 * r3b + sumb;
   double qtb = W[2] * r3b;
-  s03b += sumb;
-  Wb[1] += sumb;
-  Wb[0] = s03b - d30b;
-  Wb[3] = s03b + d30b;
-  // WENO per characteristic component
+  const double Wb[4] = {s03b - d30b, Wb1, Wb2, s03b + d30b};
+  // WENO per characteristic component: wb[k][s] = adjoint of value k at slot s.
+  // The compiler barrier makes the reverse re-read the staged states instead
+  // of keeping every forward intermediate of the four components live.
   double wb[4][NS];
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int s = 0; s < NS; ++s) wb[k][s] = 0.0;
-#pragma unroll
   for (int k = 0; k < 4; ++k) {
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int s_ = 0; s_ < NS; ++s_) wb[k][s_] = 0.0;
     if constexpr (FIFTH)
-      weno5_vjp(w[k][0], w[k][1], w[k][3], w[k][4], eps, ppm, Wb[k], wb[k][0], wb[k][1], wb[k][3], wb[k][4]);
+      weno5_vjp(wv(k, 0), wv(k, 1), wv(k, 3), wv(k, 4), eps, ppm, Wb[k], wb[k][0], wb[k][1], wb[k][3], wb[k][4]);
     else
-      weno3_vjp(w[k][0], w[k][1], w[k][3], eps, ppm, Wb[k], wb[k][0], wb[k][1], wb[k][3]);
+      weno3_vjp(wv(k, 0), wv(k, 1), wv(k, 3), eps, ppm, Wb[k], wb[k][0], wb[k][1], wb[k][3]);
   }
-  // projection of the deviations
+  // projection of the deviations: per slot, adjoints of A, B and of the
+  // deviation itself, then onto the slot's state and the reference state
   double b1b = 0.0, b2b = 0.0, rcb = 0.0;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    if (s == 2) continue;
-    const int m = side == 0 ? s : 5 - s;
-    const double Ab = 0.5 * wb[0][s] - wb[1][s] + 0.5 * wb[3][s];
-    const double Bb = 0.5 * wb[0][s] - 0.5 * wb[3][s];
-    double drb = wb[1][s] - qt * wb[2][s];
-    double dmb = -ny_ * wb[2][s];
-    double dnb = nx_ * wb[2][s];
-    double deb = 0.0;
-    qtb -= dq[s][0] * wb[2][s];
+  for (int s_ = 0; s_ < NS; ++s_) {
+    if (s_ == 2) continue;
+    const int m = mof(s_);
+    const double dr = q(m, 0) - Qr[0], dm = q(m, 1) - Qr[1], dn = q(m, 2) - Qr[2], de = q(m, 3) - Qr[3];
+    const double Ab = 0.5 * (wb[0][s_] + wb[3][s_]) - wb[1][s_];
+    const double Bb = 0.5 * (wb[0][s_] - wb[3][s_]);
+    double drb = wb[1][s_] - qt * wb[2][s_], dmb = -ny_ * wb[2][s_], dnb = nx_ * wb[2][s_], deb = 0.0;
+    qtb -= dr * wb[2][s_];
     // A = b2 dr - b1 (u dm + v dn - de)
-    b2b += Ab * dq[s][0];
+    b2b += Ab * dr;
     drb += Ab * b2;
-    b1b -= Ab * (u * dq[s][1] + v * dq[s][2] - dq[s][3]);
-    ub -= Ab * b1 * dq[s][1];
-    vb -= Ab * b1 * dq[s][2];
+    b1b -= Ab * (u * dm + v * dn - de);
+    ub -= Ab * b1 * dm;
+    vb -= Ab * b1 * dn;
     dmb -= Ab * b1 * u;
     dnb -= Ab * b1 * v;
     deb += Ab * b1;
     // B = rc (qn dr - nx dm - ny dn)
-    rcb += Bb * (qn * dq[s][0] - nx_ * dq[s][1] - ny_ * dq[s][2]);
-    qnb += Bb * rc * dq[s][0];
+    rcb += Bb * (qn * dr - nx_ * dm - ny_ * dn);
+    qnb += Bb * rc * dr;
     drb += Bb * rc * qn;
     dmb -= Bb * rc * nx_;
     dnb -= Bb * rc * ny_;
-    // dQ = q[m] - Qr
-    qb[m][0] += drb; qb[m][1] += dmb; qb[m][2] += dnb; qb[m][3] += deb;
+    // deviation = q[m] - Qr
+    qb(m, 0, drb); qb(m, 1, dmb); qb(m, 2, dnb); qb(m, 3, deb);
     Qrb[0] -= drb; Qrb[1] -= dmb; Qrb[2] -= dnb; Qrb[3] -= deb;
   }
   // reference state
@@ -300,7 +299,7 @@ WIU_DEV void side_flux_vjp(const double q[6][4], int side, double nx_, double ny
   rrb += vb * Qr[2];
   Qrb[0] -= rrb * rr * rr;
 #pragma unroll
-  for (int cc = 0; cc < 4; ++cc) qb[2 + side][cc] += Qrb[cc];
+  for (int cc = 0; cc < 4; ++cc) qb(mr, cc, Qrb[cc]);
 }
 
 // Reverse of nodal_split: fpb, fmb = adjoints of f^+-; accumulates Qb, lamb.

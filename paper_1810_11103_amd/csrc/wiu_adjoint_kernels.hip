@@ -21,10 +21,11 @@ template <int NA, int NB> struct AdjLds {
   double rb[4][NB][NA + 6];   // Rbar at positions k-3 .. k+3
   double cq[24][NA * NB];     // contributions [m*4 + c][item], m: position k-2+m
   double lb[NA * NB];         // line-eigenvalue adjoint per item
+  int ka[NA * NB];            // k if node k attains the line maximum, else INT_MAX
 };
 
 template <int SC, int DIR, int NA, int NB>
-__global__ void __launch_bounds__(NA * NB) adj_sweep_kernel(AdjArgs s) {
+__global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
   constexpr int LO = -3;                 // first item relative to the output segment
   constexpr int OUT = NA - 6;
   constexpr int NT = NA * NB;
@@ -85,12 +86,16 @@ __global__ void __launch_bounds__(NA * NB) adj_sweep_kernel(AdjArgs s) {
   }
   __syncthreads();
 
-  double cq[6][4];
+  // each item accumulates its contributions straight into its own LDS slot
 #pragma unroll
-  for (int m = 0; m < 6; ++m)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) cq[m][c] = 0.0;
+  for (int e = 0; e < 24; ++e) L.cq[e][slot] = 0.0;
   double lamb = 0.0;
+  int kmax = INT_MAX;
+  // Neighbouring tiles recompute their overlapping items; an item's
+  // eigenvalue adjoint and maximal-node flag are counted only by the tile
+  // that owns the item's position (the end tiles own the items beyond the
+  // line's ends).
+  const bool owner = (k >= o0 || o0 == 0) && (k < o0 + out || o0 + out == n_al);
   const bool item = live && k >= o0 + LO && k <= o0 + out + 2;
   if (item) {
     // Hbar(i) = Rbar(i) - Rbar(i+1); Rbar(p) sits at rb[.][tb][p - (k - 3) + ta]
@@ -111,11 +116,9 @@ __global__ void __launch_bounds__(NA * NB) adj_sweep_kernel(AdjArgs s) {
         if (HCoef<SC>::MM[mm] != 0.0) Fmb[c] += HCoef<SC>::MM[mm] * Hb(c, k - m);
       }
     }
-    double q[6][4];
-#pragma unroll
-    for (int m = 0; m < 6; ++m)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) q[m][c] = L.sq[c][tb][ta + m];
+    auto q = [&](int m, int c) { return L.sq[c][tb][ta + m]; };
+    auto qb = [&](int m, int c, double v) { L.cq[m * 4 + c][slot] += v; };
+    const double qk[4] = {q(2, 0), q(2, 1), q(2, 2), q(2, 3)};
     const long long mstride = DIR == 0 ? 1 : d.mpitch;
     const long long mline = DIR == 0 ? (long long)(line + GHOST) * d.mpitch + GHOST
                                      : (long long)GHOST * d.mpitch + (line + GHOST);
@@ -123,9 +126,19 @@ __global__ void __launch_bounds__(NA * NB) adj_sweep_kernel(AdjArgs s) {
     const double* Mm = s.M + (DIR == 0 ? 5 : 7) * d.mplane;
     const long long mo = mline + mstride * k;
     const unsigned long long* lp = DIR == 0 ? s.lam_xi : s.lam_eta;
-    const double lam = s.alpha * __longlong_as_double((long long)lp[line]);
+    const double smax = __longlong_as_double((long long)lp[line]);
+    const double lam = s.alpha * smax;
     const double kx0 = Mk[mo], ky0 = Mk[d.mplane + mo];
-    nodal_split_vjp(q[2], kx0, ky0, lam, s.gamma, fpb, fmb, cq[2], lamb);
+    if (owner && k >= 0 && k < n_al) {
+      bool bad;
+      if (wave_speed(qk, kx0, ky0, s.gamma, bad) == smax) kmax = k;
+    }
+    {
+      double nb[4] = {0.0, 0.0, 0.0, 0.0};
+      nodal_split_vjp(qk, kx0, ky0, lam, s.gamma, fpb, fmb, nb, lamb);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) qb(2, c, nb[c]);
+    }
     bool midnz = false;
 #pragma unroll
     for (int c = 0; c < 4; ++c) midnz |= (Fpb[c] != 0.0) || (Fmb[c] != 0.0);
@@ -135,27 +148,33 @@ __global__ void __launch_bounds__(NA * NB) adj_sweep_kernel(AdjArgs s) {
       const double nbx = 0.5 * (kx0 + kx1), nby = 0.5 * (ky0 + ky1);
       const double rn = rsqrt_(nbx * nbx + nby * nby);
       const double nx_ = nbx * rn, ny_ = nby * rn;
-      side_flux_vjp<Traits<SC>::fifth>(q, 0, nx_, ny_, mx, my, lam, s.gamma, s.eps, s.ppm, Fpb, cq, lamb);
-      side_flux_vjp<Traits<SC>::fifth>(q, 1, nx_, ny_, mx, my, lam, s.gamma, s.eps, s.ppm, Fmb, cq, lamb);
+      // the two sides one after the other (not interleaved) to bound the
+      // register working set
+#pragma nounroll
+      for (int side = 0; side < 2; ++side) {
+        double Fb[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Fb[c] = side == 0 ? Fpb[c] : Fmb[c];
+        side_flux_vjp<Traits<SC>::fifth>(q, side, nx_, ny_, mx, my, lam, s.gamma, s.eps, s.ppm, Fb, qb, lamb);
+      }
     }
   }
-#pragma unroll
-  for (int m = 0; m < 6; ++m)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) L.cq[m * 4 + c][slot] = cq[m][c];
-  // Neighbouring tiles recompute their overlapping items; an item's
-  // eigenvalue adjoint is counted only by the tile that owns the item's
-  // position (the end tiles own the items beyond the line's ends).
-  const bool owner = (k >= o0 || o0 == 0) && (k < o0 + out || o0 + out == n_al);
   L.lb[slot] = owner ? lamb : 0.0;
+  L.ka[slot] = kmax;
   __syncthreads();
 
   if (!live) return;
-  // line-eigenvalue adjoint of this tile: fixed-order sum over its items
+  // line-eigenvalue adjoint of this tile (fixed-order sum over its items) and
+  // its first node attaining the line maximum
   if (ta == 0) {
     double sum = 0.0;
-    for (int t = 0; t < NA; ++t) sum += L.lb[tb * NA + t];
+    int kf = INT_MAX;
+    for (int t = 0; t < NA; ++t) {
+      sum += L.lb[tb * NA + t];
+      kf = min(kf, L.ka[tb * NA + t]);
+    }
     s.lam_part[(long long)line * nseg + seg] = sum;
+    s.arg_part[(long long)line * nseg + seg] = kf;
   }
   // gather at output positions (and ghost positions at the two line ends)
   auto gather = [&](int p, double g[4]) {
@@ -197,62 +216,66 @@ __global__ void __launch_bounds__(NA * NB) adj_sweep_kernel(AdjArgs s) {
   }
 }
 
-// Per-line fix-up: ghost contributions onto the nodes the boundary rule maps
-// them to, then the line eigenvalue's adjoint onto its first maximal node.
-// One block of 256 threads per line.
+// Per-line fix-up, one wave per line: the off-line (ghost) contributions
+// onto the nodes the boundary rule maps them to, and the line eigenvalue's
+// adjoint (lam = alpha max_k s_k, Sec. 2.3) onto the first node attaining the
+// maximum.  Each target node is owned by one lane, which adds its terms in a
+// fixed order, so the result is deterministic.
 __global__ void __launch_bounds__(256) adj_fixup_kernel(AdjArgs s, int dir, int nseg) {
   const Dims& d = s.d;
-  const int line = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int line = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int n_al = dir == 0 ? d.nx : d.ny;
+  const int n_ac = dir == 0 ? d.ny : d.nx;
   const int bc_al = dir == 0 ? d.bcx : d.bcy;
-  auto node_off = [&](int p) {
-    return dir == 0 ? (long long)line * d.nx + p : (long long)p * d.nx + line;
-  };
-  __shared__ double red[256];
-  __shared__ int ired[256];
-  // first maximal node of the line's wave speed (the same expression and
-  // rounding as the forward maximum)
-  const double smax = __longlong_as_double((long long)(dir == 0 ? s.lam_xi : s.lam_eta)[line]);
-  const double* Mk = s.M + (dir == 0 ? 0 : 2) * d.mplane;
-  int best = n_al;
-  for (int p = threadIdx.x; p < n_al; p += 256) {
-    const long long o = node_off(p);
-    const double Q[4] = {s.U[o], s.U[d.np + o], s.U[2 * d.np + o], s.U[3 * d.np + o]};
-    const int ii = dir == 0 ? p : line, jj = dir == 0 ? line : p;
-    const long long mo = (long long)(jj + GHOST) * d.mpitch + (ii + GHOST);
-    bool bad;
-    const double sp = wave_speed(Q, Mk[mo], Mk[d.mplane + mo], s.gamma, bad);
-    if (sp == smax && p < best) best = p;
-  }
-  ired[threadIdx.x] = best;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) ired[threadIdx.x] = min(ired[threadIdx.x], ired[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  // ghost contributions, fixed order
-  for (int side = 0; side < 2; ++side)
-    for (int j = 0; j < NGHOST_ADJ; ++j) {
-      const int p = side == 0 ? -1 - j : n_al + j;
-      const double* gb = s.ghost + (((long long)line * 2 + side) * NGHOST_ADJ + j) * 4;
-      const long long o = node_off(bc_index(p, n_al, bc_al));
-      for (int c = 0; c < 4; ++c) s.Ubar[c * d.np + o] += gb[c];
-    }
-  // line eigenvalue: lam = alpha max_k s_k
+  if (line >= n_ac) return;
+  // eigenvalue adjoint and first maximal node over the line's segments
   double lb = 0.0;
-  for (int t = 0; t < nseg; ++t) lb += s.lam_part[(long long)line * nseg + t];
-  const int ks = ired[0];
-  if (ks < n_al && lb != 0.0) {
-    const long long o = node_off(ks);
-    const double Q[4] = {s.U[o], s.U[d.np + o], s.U[2 * d.np + o], s.U[3 * d.np + o]};
-    const int ii = dir == 0 ? ks : line, jj = dir == 0 ? line : ks;
-    const long long mo = (long long)(jj + GHOST) * d.mpitch + (ii + GHOST);
-    double Qb[4] = {0.0, 0.0, 0.0, 0.0};
-    wave_speed_vjp(Q, Mk[mo], Mk[d.mplane + mo], s.gamma, s.alpha * lb, Qb);
-    for (int c = 0; c < 4; ++c) s.Ubar[c * d.np + o] += Qb[c];
+  int ks = INT_MAX;
+  for (int t = lane; t < nseg; t += 64) {
+    lb += s.lam_part[(long long)line * nseg + t];
+    ks = min(ks, s.arg_part[(long long)line * nseg + t]);
   }
-  (void)red;
+  for (int off = 32; off > 0; off >>= 1) {  // symmetric butterfly: every lane gets the same bits
+    lb += __shfl_xor(lb, off, 64);
+    ks = min(ks, __shfl_xor(ks, off, 64));
+  }
+  constexpr int NG = 2 * NGHOST_ADJ;
+  auto target = [&](int g) {
+    const int p = g < NGHOST_ADJ ? -1 - g : n_al + (g - NGHOST_ADJ);
+    return bc_index(p, n_al, bc_al);
+  };
+  // lanes 0 .. NG-1: the ghost targets; lane NG: the maximal node if no ghost maps there
+  int t = -1;
+  bool own = false;
+  if (lane < NG) {
+    t = target(lane);
+    own = true;
+    for (int g = 0; g < lane; ++g) own = own && target(g) != t;
+  } else if (lane == NG && ks < n_al) {
+    t = ks;
+    own = true;
+    for (int g = 0; g < NG; ++g) own = own && target(g) != t;
+  }
+  if (!own) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int g = 0; g < NG; ++g) {
+    if (target(g) != t) continue;
+    const double* gb = s.ghost + (((long long)line * 2 + (g < NGHOST_ADJ ? 0 : 1)) * NGHOST_ADJ + g % NGHOST_ADJ) * 4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] += gb[c];
+  }
+  const long long o = dir == 0 ? (long long)line * d.nx + t : (long long)t * d.nx + line;
+  if (t == ks && lb != 0.0) {
+    const double Q[4] = {s.U[o], s.U[d.np + o], s.U[2 * d.np + o], s.U[3 * d.np + o]};
+    const int ii = dir == 0 ? t : line, jj = dir == 0 ? line : t;
+    const long long mo = (long long)(jj + GHOST) * d.mpitch + (ii + GHOST);
+    const double* Mk = s.M + (dir == 0 ? 0 : 2) * d.mplane;
+    wave_speed_vjp(Q, Mk[mo], Mk[d.mplane + mo], s.gamma, s.alpha * lb, acc);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s.Ubar[c * d.np + o] += acc[c];
+  if (lane == 0 && ks >= n_al && lb != 0.0) atomicOr(s.status, ST_ARGMAX);
 }
 
 // out = a x + b (y + dt z), elementwise over n values (RK3 adjoint stages).
@@ -302,7 +325,7 @@ hipError_t launch_adj_sweep(int scheme, int dir, const AdjArgs& a, hipStream_t s
   }
   if (e != hipSuccess) return e;
   const int nlines = dir == 0 ? a.d.ny : a.d.nx;
-  hipLaunchKernelGGL(adj_fixup_kernel, dim3(nlines), dim3(256), 0, st, a, dir, nseg);
+  hipLaunchKernelGGL(adj_fixup_kernel, dim3((nlines + 3) / 4), dim3(256), 0, st, a, dir, nseg);
   return hipGetLastError();
 }
 

@@ -45,9 +45,10 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 //   HDR          lam_xi[ny], lam_eta[nx], cfl_max[1]   (uint64 bit patterns)
 //   off_scratch  R^xi[4 np], U1[4 np], U2[4 np]  -- or the metric band temp
 //   then the adjoint region: A, Ubar2, Ubar1, acc (4 planes each), eigenvalue
-//   partials [max lines x segments], off-line contributions [max lines][2][6][4]
+//   partials [max lines x segments] (double) and first maximal nodes (int),
+//   off-line contributions [max lines][2][6][4]
 struct WsLayout {
-  size_t lam, scratch, rxi, u1, u2, qa, ub2, ub1, acc, lpart, ghost, total;
+  size_t lam, scratch, rxi, u1, u2, qa, ub2, ub1, acc, lpart, apart, ghost, total;
 };
 
 WsLayout layout(const wiu_grid* g) {
@@ -69,7 +70,8 @@ WsLayout layout(const wiu_grid* g) {
   L.acc = L.ub1 + plane4;
   const size_t lp_xi = (size_t)g->ny * adj_nseg(0, g->nx), lp_eta = (size_t)g->nx * adj_nseg(1, g->ny);
   L.lpart = L.acc + plane4;
-  L.ghost = L.lpart + align_up((lp_xi > lp_eta ? lp_xi : lp_eta) * 8);
+  L.apart = L.lpart + align_up((lp_xi > lp_eta ? lp_xi : lp_eta) * 8);
+  L.ghost = L.apart + align_up((lp_xi > lp_eta ? lp_xi : lp_eta) * 4);
   const size_t nl = (size_t)(g->nx > g->ny ? g->nx : g->ny);
   L.total = L.ghost + align_up(nl * 2 * 6 * 4 * 8);
   return L;
@@ -109,6 +111,7 @@ struct Ws {
   unsigned long long *lx, *le, *cfl;
   double *rxi, *u1, *u2, *band;
   double *qa, *ub2, *ub1, *acc, *lpart, *ghost;
+  int* apart;
 };
 
 Ws carve(const wiu_grid* g, void* ws) {
@@ -128,6 +131,7 @@ Ws carve(const wiu_grid* g, void* ws) {
   w.ub1 = (double*)(b + L.ub1);
   w.acc = (double*)(b + L.acc);
   w.lpart = (double*)(b + L.lpart);
+  w.apart = (int*)(b + L.apart);
   w.ghost = (double*)(b + L.ghost);
   return w;
 }
@@ -140,7 +144,7 @@ int residual_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const doubl
   AdjArgs a;
   a.d = d; a.U = U; a.M = M; a.Gbar = Gbar; a.Ubar = Ubar; a.lam_xi = w.lx; a.lam_eta = w.le;
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
-  a.lam_part = w.lpart; a.ghost = w.ghost;
+  a.lam_part = w.lpart; a.arg_part = w.apart; a.ghost = w.ghost; a.status = w.status;
   a.accumulate = 0;
   if (launch_adj_sweep(scheme, 0, a, st) != hipSuccess) return WIU_EHIP;
   a.accumulate = 1;

@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <climits>
 
 #define WIU_DEV __device__ __forceinline__
 
@@ -27,7 +28,7 @@ struct Dims {
 };
 
 // Status bits latched in the workspace header.
-constexpr int ST_JACOBIAN = 1, ST_NONPHYS = 2, ST_SCHEME = 4;
+constexpr int ST_JACOBIAN = 1, ST_NONPHYS = 2, ST_SCHEME = 4, ST_ARGMAX = 8;
 
 // Map a line index onto the grid: wrap for periodic lines, clamp (copy of the
 // boundary node) for transmissive ones.  Loops run at most halo/n times.
@@ -114,16 +115,31 @@ template <int SC> struct Range {
 //   third order:  g = C + K d^3, K = 1/C^2 for d <= 0, 1/(C-1)^2 above
 //   second order: g = C + K d^2, K = -1/C for d <= 0, 1/(1-C) above
 // (C[1 + (w/C - 1)^3] = C + d^3/C^2 and C[1 - (w/C - 1)^2] = C - d^2/C).
-WIU_DEV double map3(double w, double C, double klo, double khi) {
+// The piecewise constant K is folded into |d| without a branch: with
+// A = (K_lo + K_hi)/2 and B = (K_hi - K_lo)/2,
+//   K d^3 = d^2 (A d + B |d|)   and   K d^2 = d (A d + B |d|).
+WIU_DEV double map3(double w, double C, double A, double B) {
   const double d = w - C;
-  const double K = d <= 0.0 ? klo : khi;
-  return fma(K * d, d * d, C);
+  return fma(d * d, fma(A, d, B * fabs(d)), C);
 }
-WIU_DEV double map2(double w, double C, double klo, double khi) {
+WIU_DEV double map2(double w, double C, double A, double B) {
   const double d = w - C;
-  const double K = d <= 0.0 ? klo : khi;
-  return fma(K * d, d, C);
+  return fma(d, fma(A, d, B * fabs(d)), C);
 }
+
+// (A, B) pairs of the mappings for the linear weights of Table 1.
+//   r = 3: C = 1/16, 10/16, 5/16, K_lo = 1/C^2, K_hi = 1/(C-1)^2
+//   r = 2: C = 1/4, 3/4,          K_lo = -1/C,  K_hi = 1/(1-C)
+#define WIU_M3A0 ((256.0 + 256.0 / 225.0) * 0.5)
+#define WIU_M3B0 ((256.0 / 225.0 - 256.0) * 0.5)
+#define WIU_M3A1 ((2.56 + 64.0 / 9.0) * 0.5)
+#define WIU_M3B1 ((64.0 / 9.0 - 2.56) * 0.5)
+#define WIU_M3A2 ((10.24 + 256.0 / 121.0) * 0.5)
+#define WIU_M3B2 ((256.0 / 121.0 - 10.24) * 0.5)
+#define WIU_M2A0 ((-4.0 + 4.0 / 3.0) * 0.5)
+#define WIU_M2B0 ((4.0 / 3.0 + 4.0) * 0.5)
+#define WIU_M2A1 ((-4.0 / 3.0 + 4.0) * 0.5)
+#define WIU_M2B1 ((4.0 + 4.0 / 3.0) * 0.5)
 
 // r = 3: left-biased value at k+1/2 from v_{k-2}, v_{k-1}, v_k = 0, v_{k+1},
 // v_{k+2} = (a, b, 0, d, e).  Candidates from Table 1 (b_{k,l}), linear
@@ -147,9 +163,9 @@ WIU_DEV double weno5(double a, double b, double d, double e, double eps, int ppm
   const double r = rcp(a0 + a1 + a2);
   double w0 = a0 * r, w1 = a1 * r, w2 = a2 * r;
   if (ppm) {
-    w0 = map3(w0, 0.0625, 256.0, 256.0 / 225.0);
-    w1 = map3(w1, 0.625, 2.56, 64.0 / 9.0);
-    w2 = map3(w2, 0.3125, 10.24, 256.0 / 121.0);
+    w0 = map3(w0, 0.0625, WIU_M3A0, WIU_M3B0);
+    w1 = map3(w1, 0.625, WIU_M3A1, WIU_M3B1);
+    w2 = map3(w2, 0.3125, WIU_M3A2, WIU_M3B2);
   }
   return (w0 * p0 + w1 * p1 + w2 * p2) * rcp(w0 + w1 + w2);
 }
@@ -171,8 +187,8 @@ WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
   const double r = rcp(a0 + a1);
   double w0 = a0 * r, w1 = a1 * r;
   if (ppm) {
-    w0 = map2(w0, 0.25, -4.0, 4.0 / 3.0);
-    w1 = map2(w1, 0.75, -4.0 / 3.0, 4.0);
+    w0 = map2(w0, 0.25, WIU_M2A0, WIU_M2B0);
+    w1 = map2(w1, 0.75, WIU_M2A1, WIU_M2B1);
   }
   return (w0 * p0 + w1 * p1) * rcp(w0 + w1);
 }
@@ -264,7 +280,10 @@ WIU_DEV void nodal_split(const double Q[4], double kx, double ky, double lam, do
 
 // Wave speed |k . u| + c |k| (Sec. 2.3); returns a negative value for a
 // non-physical or non-finite state so callers can flag it.
+// No contraction here: the adjoint locates the node attaining a line maximum
+// by recomputing this value in another kernel, which must round identically.
 WIU_DEV double wave_speed(const double Q[4], double kx, double ky, double gam, bool& bad) {
+#pragma clang fp contract(off)
   const double ri = rcp(Q[0]);
   const double u = Q[1] * ri, v = Q[2] * ri;
   const double p = (gam - 1.0) * (Q[3] - 0.5 * (Q[1] * u + Q[2] * v));

@@ -56,6 +56,8 @@ struct AdjArgs {
   int ppm;
   int accumulate;                       // 0: write Ubar, 1: add to it
   double* lam_part;                     // [lines][segments] eigenvalue adjoints
+  int* arg_part;                        // [lines][segments] first maximal node per tile
+  int* status;
   double* ghost;                        // [lines][2][6][4] off-line contributions
 };
 

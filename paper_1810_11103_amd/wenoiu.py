@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libwenoiu.so")
 SCHEMES = {"3-1MP": 0, "3-2MP": 1, "5-1MP": 2, "5-2MP": 3}
 BC = {"periodic": 0, "transmissive": 1}
 GHOST = 4
-ST_JACOBIAN, ST_NONPHYS, ST_SCHEME = 1, 2, 4
+ST_JACOBIAN, ST_NONPHYS, ST_SCHEME, ST_ARGMAX = 1, 2, 4, 8
 WIU_OK, WIU_EINVAL, WIU_EHIP = 0, -1, -2
 
 EXPORTS = [

@@ -195,7 +195,8 @@ WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
 
 // ---------------------------------------------------------------------------
 // Characteristic midpoint flux, one side (Secs. 2.3, 2.4, 3.4).
-//   q[m][c], m = 0..5: conservative states at k-2 .. k+3.
+//   q(m, c), m = 0..5: conservative states at k-2 .. k+3 (read through an
+//   accessor so they can stay in LDS).
 //   side 0: F^+_{k+1/2}, reference Q_k, left-biased over k-2..k+2
 //   side 1: F^-_{k+1/2}, reference Q_{k+1}, right-biased over k+3..k-1
 //   (nx_, ny_): unit normal of the averaged nodal metric; (mx, my): midpoint
@@ -205,10 +206,10 @@ WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
 //   l_1 = (A + B)/2, l_2 = e_rho - A, l_4 = (A - B)/2 applied to dQ, with
 //   A = b2 drho - b1 (u dm + v dn - de), B = (qn drho - nx dm - ny dn)/c.
 // ---------------------------------------------------------------------------
-template <bool FIFTH>
-WIU_DEV void side_flux(const double q[6][4], int side, double nx_, double ny_, double mx, double my,
-                       double lam, double gam, double eps, int ppm, double F[4]) {
-  const double* Qr = q[2 + side];
+template <bool FIFTH, class QF>
+WIU_DEV void side_flux(QF q, int side, double nx_, double ny_, double mx, double my, double lam, double gam,
+                       double eps, int ppm, double F[4]) {
+  const double Qr[4] = {q(2 + side, 0), q(2 + side, 1), q(2 + side, 2), q(2 + side, 3)};
   const double gm1 = gam - 1.0;
   const double rr = rcp(Qr[0]);
   const double u = Qr[1] * rr, v = Qr[2] * rr;
@@ -231,7 +232,7 @@ WIU_DEV void side_flux(const double q[6][4], int side, double nx_, double ny_, d
   for (int s = 0; s < NS; ++s) {
     if (s == 2) continue;  // the reference node: zero deviation
     const int m = side == 0 ? s : 5 - s;
-    const double dr = q[m][0] - Qr[0], dm = q[m][1] - Qr[1], dn = q[m][2] - Qr[2], de = q[m][3] - Qr[3];
+    const double dr = q(m, 0) - Qr[0], dm = q(m, 1) - Qr[1], dn = q(m, 2) - Qr[2], de = q(m, 3) - Qr[3];
     const double A = b2 * dr - b1 * (u * dm + v * dn - de);
     const double B = rc * (qn * dr - nx_ * dm - ny_ * dn);
     w[0][s] = 0.5 * (A + B);

@@ -146,18 +146,14 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   __syncthreads();
 
   if (need_node || need_mid) {
-    // stencil states Q_{k-2..k+3}
-    double q[6][4];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) q[m][c] = sq[c][tb][ta + m];
-    }
+    // stencil states Q_{k-2..k+3}, read from LDS where they are used
+    auto q = [&](int m, int c) { return sq[c][tb][ta + m]; };
     const long long mo = mline + mstride * k;
     const double kx0 = Mk[mo], ky0 = Mk[d.mplane + mo];
     if (need_node) {
+      const double qk[4] = {q(2, 0), q(2, 1), q(2, 2), q(2, 3)};
       double fp[4], fm[4];
-      nodal_split(q[2], kx0, ky0, lam, gam, fp, fm);
+      nodal_split(qk, kx0, ky0, lam, gam, fp, fm);
 #pragma unroll
       for (int c = 0; c < 4; ++c) { sh[c][slot] = fp[c]; sh[4 + c][slot] = fm[c]; }
     }
@@ -167,11 +163,16 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
       const double nbx = 0.5 * (kx0 + kx1), nby = 0.5 * (ky0 + ky1);
       const double rn = rsqrt_(nbx * nbx + nby * nby);
       const double nx_ = nbx * rn, ny_ = nby * rn;
-      double Fp[4], Fm[4];
-      side_flux<Traits<SC>::fifth>(q, 0, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, Fp);
-      side_flux<Traits<SC>::fifth>(q, 1, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, Fm);
+      // the two sides one after the other: the compiler barrier keeps their
+      // working sets from being interleaved (register pressure)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) { sh[8 + c][slot] = Fp[c]; sh[12 + c][slot] = Fm[c]; }
+      for (int side = 0; side < 2; ++side) {
+        asm volatile("" ::: "memory");
+        double F[4];
+        side_flux<Traits<SC>::fifth>(q, side, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, F);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sh[8 + 4 * side + c][slot] = F[c];
+      }
     }
   }
   __syncthreads();

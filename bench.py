@@ -5,10 +5,12 @@ Workload: 2-D four-quadrant Riemann problem (Sec. 6.3(3)) on the randomized
 layers, seed 2048), fifth-order two-midpoint scheme (WENOIU5-2MP),
 transmissive boundaries, TVD-RK3 with CFL 0.5, fp64.
 
-One step = one time step of the whole path: the CFL time step (wave-speed
-maximum) followed by the three RK stages, each of which evaluates the line
-eigenvalues, the xi and eta sweeps (characteristic WENO midpoint fluxes,
-upwind-biased difference) and the stage update.  The reported value counts
+One step = one time step of the whole path (wiu_rk3_step_cfl): the CFL time
+step from the wave-speed maxima of the state, then the three RK stages, each
+with its line eigenvalues, the xi and eta sweeps (characteristic WENO
+midpoint fluxes, upwind-biased difference) and the stage update.  One pass
+over the state gives the CFL maximum and the first stage's eigenvalues; the
+eta sweeps of stages 1 and 2 accumulate the next stage's eigenvalues.  The reported value counts
 cell-updates: one rhs evaluation at one cell fused with its stage update, so
 a step is 3 n^2 cell-updates.
 
@@ -224,8 +226,7 @@ def main():
     torch.cuda.synchronize()
 
     def step():
-        sol.cfl_dt(U, args.cfl)
-        sol.rk3_step(U)
+        sol.rk3_step_cfl(U, args.cfl)
 
     for _ in range(args.warmup):
         step()

@@ -122,6 +122,12 @@ int wiu_cfl_dt(const wiu_grid* g, const wiu_params* p, const double* U, const do
 int wiu_rk3_step(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
                  const double* dt_dev, void* ws, wiu_stream_t stream);
 
+/* wiu_cfl_dt followed by wiu_rk3_step, sharing one pass over U for the CFL
+ * maximum and the first stage's line eigenvalues: *dt_dev receives the CFL
+ * time step of U, then U advances by it.  Same results as the two calls. */
+int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
+                     double* dt_dev, void* ws, wiu_stream_t stream);
+
 /* ---- Adjoints (metrics held fixed) ------------------------------------------
  * Reverse-mode derivatives of the residual and of one RK3 step with respect
  * to the state, for gradients through time integration.  Non-smooth points:

@@ -338,20 +338,19 @@ WIU_DEV void nodal_split_vjp(const double Q[4], double kx, double ky, double lam
   Qb[0] -= rib * ri * ri;
 }
 
-// Reverse of the wave speed |k . u| + c |k| (c = sqrt(gam p / rho)).
+// Reverse of the wave speed |k . u| + sqrt(c^2 |k|^2) (c^2 = gam p / rho).
 WIU_DEV void wave_speed_vjp(const double Q[4], double kx, double ky, double gam, double sb, double Qb[4]) {
   const double gm1 = gam - 1.0;
   const double ri = 1.0 / Q[0];
   const double u = Q[1] * ri, v = Q[2] * ri;
   const double p = gm1 * (Q[3] - 0.5 * (Q[1] * u + Q[2] * v));
   const double U = kx * u + ky * v;
-  const double c = sqrt(gam * p * ri);
-  const double kn = sqrt(kx * kx + ky * ky);
+  const double K2 = kx * kx + ky * ky;
+  const double sc = sqrt(gam * p * ri * K2);
   const double sgn = U > 0.0 ? 1.0 : (U < 0.0 ? -1.0 : 0.0);
   const double Ub = sb * sgn;
-  const double cb = sb * kn;
-  // c^2 = gam p ri
-  const double c2b = cb / (2.0 * c);
+  // c^2 = gam p ri, d sqrt(c^2 K2) / d c^2 = K2 / (2 sqrt(c^2 K2))
+  const double c2b = sb * K2 / (2.0 * sc);
   const double pb = c2b * gam * ri;
   double rib = c2b * gam * p;
   double ub = Ub * kx, vb = Ub * ky;

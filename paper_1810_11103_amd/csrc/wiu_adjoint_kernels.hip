@@ -16,12 +16,18 @@ namespace wiu {
 
 constexpr int NGHOST_ADJ = 6;  // positions beyond each end of a line that items touch
 
-template <int NA, int NB> struct AdjLds {
-  double sq[4][NB][NA + 5];   // states k-2 .. k+3 of the items
-  double rb[4][NB][NA + 6];   // Rbar at positions k-3 .. k+3
+// Line-major (xi) or position-major (eta) so that the lanes of a wave touch
+// consecutive words, as for the forward sweep tile.
+template <int DIR, int NA, int NB> struct AdjLds {
+  static constexpr int NQ = NA + 5, NR = NA + 6;
+  double sq[4][NB * NQ];      // states k-2 .. k+3 of the items
+  double rb[4][NB * NR];      // Rbar at positions k-3 .. k+3
   double cq[24][NA * NB];     // contributions [m*4 + c][item], m: position k-2+m
   double lb[NA * NB];         // line-eigenvalue adjoint per item
   int ka[NA * NB];            // k if node k attains the line maximum, else INT_MAX
+  static WIU_DEV int si(int tb, int ta) { return DIR == 0 ? tb * NA + ta : ta * NB + tb; }
+  static WIU_DEV int qi(int tb, int pos) { return DIR == 0 ? tb * NQ + pos : pos * NB + tb; }
+  static WIU_DEV int ri(int tb, int pos) { return DIR == 0 ? tb * NR + pos : pos * NB + tb; }
 };
 
 template <int SC, int DIR, int NA, int NB>
@@ -30,7 +36,8 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
   constexpr int OUT = NA - 6;
   constexpr int NT = NA * NB;
   constexpr int NQ = NA + 5;
-  __shared__ AdjLds<NA, NB> L;
+  using LT = AdjLds<DIR, NA, NB>;
+  __shared__ LT L;
   const Dims& d = s.d;
   const int ta = DIR == 0 ? threadIdx.x : threadIdx.y;
   const int tb = DIR == 0 ? threadIdx.y : threadIdx.x;
@@ -47,7 +54,7 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
   const int o0 = seg * OUT;
   const int out = min(OUT, n_al - o0);
   const int k = o0 + LO + ta;
-  const int slot = tb * NA + ta;
+  const int slot = LT::si(tb, ta);
   const bool live = line < n_ac;
   const int tid = threadIdx.x + blockDim.x * threadIdx.y;
 
@@ -62,7 +69,7 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
         const int kk = bc_index(k0 + pos, n_al, bc_al);
         const long long o = DIR == 0 ? (long long)ln * d.nx + kk : (long long)kk * d.nx + ln;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) L.sq[c][lb_][pos] = s.U[c * d.np + o];
+        for (int c = 0; c < 4; ++c) L.sq[c][LT::qi(lb_, pos)] = s.U[c * d.np + o];
       }
     }
     const int r0 = o0 + LO - 3;
@@ -81,7 +88,7 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
         for (int c = 0; c < 4; ++c) v[c] = s.Gbar[c * d.np + o] * rj;
       }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) L.rb[c][lb_][pos] = v[c];
+      for (int c = 0; c < 4; ++c) L.rb[c][LT::ri(lb_, pos)] = v[c];
     }
   }
   __syncthreads();
@@ -101,7 +108,7 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
     // Hbar(i) = Rbar(i) - Rbar(i+1); Rbar(p) sits at rb[.][tb][p - (k - 3) + ta]
     auto Hb = [&](int c, int i) {
       const int a = i - (o0 + LO - 3);
-      return L.rb[c][tb][a] - L.rb[c][tb][a + 1];
+      return L.rb[c][LT::ri(tb, a)] - L.rb[c][LT::ri(tb, a + 1)];
     };
     double fpb[4], fmb[4], Fpb[4], Fmb[4];
 #pragma unroll
@@ -116,7 +123,7 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
         if (HCoef<SC>::MM[mm] != 0.0) Fmb[c] += HCoef<SC>::MM[mm] * Hb(c, k - m);
       }
     }
-    auto q = [&](int m, int c) { return L.sq[c][tb][ta + m]; };
+    auto q = [&](int m, int c) { return L.sq[c][LT::qi(tb, ta + m)]; };
     auto qb = [&](int m, int c, double v) { L.cq[m * 4 + c][slot] += v; };
     const double qk[4] = {q(2, 0), q(2, 1), q(2, 2), q(2, 3)};
     const long long mstride = DIR == 0 ? 1 : d.mpitch;
@@ -170,8 +177,8 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
     double sum = 0.0;
     int kf = INT_MAX;
     for (int t = 0; t < NA; ++t) {
-      sum += L.lb[tb * NA + t];
-      kf = min(kf, L.ka[tb * NA + t]);
+      sum += L.lb[LT::si(tb, t)];
+      kf = min(kf, L.ka[LT::si(tb, t)]);
     }
     s.lam_part[(long long)line * nseg + seg] = sum;
     s.arg_part[(long long)line * nseg + seg] = kf;
@@ -186,7 +193,7 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
       const int t = t0 + 2 - m;  // item k = p + 2 - m
       if (t >= 0 && t < NA) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) g[c] += L.cq[m * 4 + c][tb * NA + t];
+        for (int c = 0; c < 4; ++c) g[c] += L.cq[m * 4 + c][LT::si(tb, t)];
       }
     }
   };

@@ -35,7 +35,7 @@ struct ProfScope {
 };
 
 // Tile shape of each sweep direction (index into the compiled variants).
-int g_variant[2] = {0, 4};  // xi 128 x 1, eta 64 x 2 (measured best at 2048^2)
+int g_variant[2] = {0, 2};  // xi 128 x 1, eta 32 x 4 (measured best at 2048^2)
 
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -43,12 +43,13 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 // Workspace layout (byte offsets):
 //   0            header: int status, padding
 //   HDR          lam_xi[ny], lam_eta[nx], cfl_max[1]   (uint64 bit patterns)
+//   lam2         a second lam_xi, lam_eta, cfl_max set (maxima of an RK stage state)
 //   off_scratch  R^xi[4 np], U1[4 np], U2[4 np]  -- or the metric band temp
 //   then the adjoint region: A, Ubar2, Ubar1, acc (4 planes each), eigenvalue
 //   partials [max lines x segments] (double) and first maximal nodes (int),
 //   off-line contributions [max lines][2][6][4]
 struct WsLayout {
-  size_t lam, scratch, rxi, u1, u2, qa, ub2, ub1, acc, lpart, apart, ghost, total;
+  size_t lam, lam2, scratch, rxi, u1, u2, qa, ub2, ub1, acc, lpart, apart, ghost, total;
 };
 
 WsLayout layout(const wiu_grid* g) {
@@ -58,7 +59,8 @@ WsLayout layout(const wiu_grid* g) {
   const size_t band = 5 * (size_t)(g->nx + 2 * B) * (g->ny + 2 * B);
   const size_t plane4 = align_up(4 * np * 8);
   L.lam = ALIGN;
-  L.scratch = L.lam + align_up(((size_t)g->nx + g->ny + 1) * 8);
+  L.lam2 = L.lam + align_up(((size_t)g->nx + g->ny + 1) * 8);
+  L.scratch = L.lam2 + align_up(((size_t)g->nx + g->ny + 1) * 8);
   L.rxi = L.scratch;
   L.u1 = L.rxi + plane4;
   L.u2 = L.u1 + plane4;
@@ -109,6 +111,7 @@ Dims dims(const wiu_grid* g) {
 struct Ws {
   int* status;
   unsigned long long *lx, *le, *cfl;
+  unsigned long long *lx2, *le2;  // maxima of an RK stage state, from the previous stage
   double *rxi, *u1, *u2, *band;
   double *qa, *ub2, *ub1, *acc, *lpart, *ghost;
   int* apart;
@@ -122,6 +125,8 @@ Ws carve(const wiu_grid* g, void* ws) {
   w.lx = (unsigned long long*)(b + L.lam);
   w.le = w.lx + g->ny;
   w.cfl = w.le + g->nx;
+  w.lx2 = (unsigned long long*)(b + L.lam2);
+  w.le2 = w.lx2 + g->ny;
   w.rxi = (double*)(b + L.rxi);
   w.u1 = (double*)(b + L.u1);
   w.u2 = (double*)(b + L.u2);
@@ -154,31 +159,69 @@ int residual_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const doubl
 int hip_rc(hipError_t e) { return e == hipSuccess ? WIU_OK : WIU_EHIP; }
 
 // Residual pieces shared by rhs and the RK stages: line maxima, then the xi
-// sweep into R^xi, then the eta sweep with the requested epilogue.
+// sweep into R^xi, then the eta sweep with the requested epilogue.  The
+// maxima are computed here unless given (lx_in/le_in, accumulated by the
+// previous stage); with nlx/nle (mode 2 only) the eta sweep accumulates the
+// maxima of the new stage state there.
+struct Maxima {
+  const unsigned long long *lx_in = nullptr, *le_in = nullptr;
+  unsigned long long *nlx = nullptr, *nle = nullptr;
+};
+
 int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M, const Ws& w,
-             int mode, double* out, const double* U0, const double* dt, double ca, double cb, hipStream_t st) {
+             int mode, double* out, const double* U0, const double* dt, double ca, double cb, hipStream_t st,
+             const Maxima& mx = Maxima()) {
   Dims d = dims(g);
-  hipError_t e;
-  {
+  hipError_t e = hipSuccess;
+  SweepArgs a;
+  a.lam_xi = mx.lx_in; a.lam_eta = mx.le_in;
+  if (!mx.lx_in) {
     ProfScope ps(WIU_K_WAVE_MAX, st);
     e = launch_wave_max(d, U, M, p->gamma, w.lx, w.le, w.cfl, w.status, st);
+    a.lam_xi = w.lx; a.lam_eta = w.le;
   }
   if (e != hipSuccess) return WIU_EHIP;
-  SweepArgs a;
-  a.d = d; a.U = U; a.M = M; a.lam_xi = w.lx; a.lam_eta = w.le;
+  a.d = d; a.U = U; a.M = M;
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
   a.mode = 0; a.Rxi = w.rxi; a.out = out; a.U0 = U0; a.dt = dt; a.ca = ca; a.cb = cb; a.status = w.status;
+  a.nlam_xi = nullptr; a.nlam_eta = nullptr;
   {
     ProfScope ps(WIU_K_SWEEP_XI, st);
     e = launch_sweep(scheme, 0, g_variant[0], a, st);
   }
   if (e != hipSuccess) return WIU_EHIP;
   a.mode = mode;
+  if (mode == 2 && mx.nlx) {
+    // lx/le and cfl of one set are contiguous: lam_xi[ny], lam_eta[nx], cfl[1]
+    if (launch_fill_u64(mx.nlx, (long long)d.nx + d.ny + 1, st) != hipSuccess) return WIU_EHIP;
+    a.nlam_xi = mx.nlx; a.nlam_eta = mx.nle;
+  }
   {
     ProfScope ps(WIU_K_SWEEP_ETA, st);
     e = launch_sweep(scheme, 1, g_variant[1], a, st);
   }
   return hip_rc(e);
+}
+
+// The three Shu-Osher TVD-RK3 stages (Sec. 4.2):
+//   U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U <- 1/3 U + 2/3 (U2 + dt L(U2)).
+// The first stage's line maxima are computed from U (or taken from a
+// preceding CFL evaluation of the same state, have_max); stages 1 and 2
+// accumulate the maxima of U1 and U2 in their eta sweeps.
+int rk3_stages(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M, const double* dt,
+               double* U1, double* U2, const Ws& w, hipStream_t st, bool have_max) {
+  Maxima m1;
+  if (have_max) { m1.lx_in = w.lx; m1.le_in = w.le; }
+  m1.nlx = w.lx2; m1.nle = w.le2;
+  int rc = residual(g, scheme, p, U, M, w, 2, U1, U, dt, 0.0, 1.0, st, m1);
+  if (rc) return rc;
+  Maxima m2;
+  m2.lx_in = w.lx2; m2.le_in = w.le2; m2.nlx = w.lx; m2.nle = w.le;
+  rc = residual(g, scheme, p, U1, M, w, 2, U2, U, dt, 0.75, 0.25, st, m2);
+  if (rc) return rc;
+  Maxima m3;
+  m3.lx_in = w.lx; m3.le_in = w.le;
+  return residual(g, scheme, p, U2, M, w, 2, U, U, dt, 1.0 / 3.0, 2.0 / 3.0, st, m3);
 }
 
 }  // namespace
@@ -244,14 +287,21 @@ int wiu_rk3_step(const wiu_grid* g, int scheme, const wiu_params* p, double* U, 
                  const double* dt_dev, void* ws, wiu_stream_t stream) {
   if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !dt_dev || !ws) return WIU_EINVAL;
   Ws w = carve(g, ws);
+  return rk3_stages(g, scheme, p, U, M, dt_dev, w.u1, w.u2, w, (hipStream_t)stream, false);
+}
+
+int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
+                     double* dt_dev, void* ws, wiu_stream_t stream) {
+  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !dt_dev || !ws || !(cfl > 0.0))
+    return WIU_EINVAL;
+  Ws w = carve(g, ws);
   hipStream_t st = (hipStream_t)stream;
-  // Shu-Osher TVD-RK3: U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1));
-  // U <- 1/3 U + 2/3 (U2 + dt L(U2))
-  int rc = residual(g, scheme, p, U, M, w, 2, w.u1, U, dt_dev, 0.0, 1.0, st);
-  if (rc) return rc;
-  rc = residual(g, scheme, p, w.u1, M, w, 2, w.u2, U, dt_dev, 0.75, 0.25, st);
-  if (rc) return rc;
-  return residual(g, scheme, p, w.u2, M, w, 2, U, U, dt_dev, 1.0 / 3.0, 2.0 / 3.0, st);
+  {
+    ProfScope ps(WIU_K_WAVE_MAX, st);
+    if (launch_wave_max(dims(g), U, M, p->gamma, w.lx, w.le, w.cfl, w.status, st) != hipSuccess) return WIU_EHIP;
+  }
+  if (launch_cfl_dt(w.cfl, cfl, dt_dev, st) != hipSuccess) return WIU_EHIP;
+  return rk3_stages(g, scheme, p, U, M, dt_dev, w.u1, w.u2, w, st, true);
 }
 
 int wiu_rhs_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M,
@@ -267,12 +317,7 @@ int wiu_rk3_step_stages(const wiu_grid* g, int scheme, const wiu_params* p, doub
   if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !dt_dev || !U1 || !U2 || !ws)
     return WIU_EINVAL;
   Ws w = carve(g, ws);
-  hipStream_t st = (hipStream_t)stream;
-  int rc = residual(g, scheme, p, U, M, w, 2, U1, U, dt_dev, 0.0, 1.0, st);
-  if (rc) return rc;
-  rc = residual(g, scheme, p, U1, M, w, 2, U2, U, dt_dev, 0.75, 0.25, st);
-  if (rc) return rc;
-  return residual(g, scheme, p, U2, M, w, 2, U, U, dt_dev, 1.0 / 3.0, 2.0 / 3.0, st);
+  return rk3_stages(g, scheme, p, U, M, dt_dev, U1, U2, w, (hipStream_t)stream, false);
 }
 
 int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U_n, const double* U1,
@@ -286,9 +331,12 @@ int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const d
   const long long n = 4LL * g->nx * g->ny;
   int rc;
   if (!U1) {  // recompute the stage states
-    rc = residual(g, scheme, p, U_n, M, w, 2, w.u1, U_n, dt_dev, 0.0, 1.0, st);
+    Maxima m1, m2;
+    m1.nlx = w.lx2; m1.nle = w.le2;
+    m2.lx_in = w.lx2; m2.le_in = w.le2;
+    rc = residual(g, scheme, p, U_n, M, w, 2, w.u1, U_n, dt_dev, 0.0, 1.0, st, m1);
     if (rc) return rc;
-    rc = residual(g, scheme, p, w.u1, M, w, 2, w.u2, U_n, dt_dev, 0.75, 0.25, st);
+    rc = residual(g, scheme, p, w.u1, M, w, 2, w.u2, U_n, dt_dev, 0.75, 0.25, st, m2);
     if (rc) return rc;
     U1 = w.u1;
     U2 = w.u2;

@@ -19,7 +19,8 @@ struct wiu_plan {
   int4* d_tiles = nullptr;       // xi tiles, then eta tiles, then wave-max tiles
   int n_xi = 0, n_eta = 0, n_wm = 0;
   char* d_ws = nullptr;          // per-block lam, R^xi, U1, U2, dt; status
-  unsigned long long* d_lam = nullptr;
+  unsigned long long* d_lam = nullptr;   // line maxima of all blocks (stages 1 and 3)
+  unsigned long long* d_lam2 = nullptr;  // second set (stage 2), filled by stage 1's eta sweep
   long long lam_len = 0;
   double* d_dt = nullptr;
   int* d_status = nullptr;
@@ -70,13 +71,20 @@ int launch_step(wiu_plan* p, hipStream_t st) {
   a.blocks = p->d_blocks;
   a.gamma = p->params.gamma; a.alpha = p->params.alpha_lf; a.eps = p->params.eps; a.ppm = p->params.ppm;
   a.status = p->d_status;
+  // Line maxima: a separate pass for the step's state only; the eta sweeps
+  // of stages 1 and 2 accumulate the maxima of the stage state they write
+  // (into lam2, then back into lam), which the next stage reads.
   for (int stage = 0; stage < 3; ++stage) {
     a.stage = stage;
-    if (launch_fill_u64(p->d_lam, p->lam_len, st) != hipSuccess) return WIU_EHIP;
-    a.tiles = p->d_tiles + p->n_xi + p->n_eta; a.ntiles = p->n_wm;
-    if (launch_batched_wave_max(a, st) != hipSuccess) return WIU_EHIP;
+    if (stage == 0) {
+      if (launch_fill_u64(p->d_lam, p->lam_len, st) != hipSuccess) return WIU_EHIP;
+      a.tiles = p->d_tiles + p->n_xi + p->n_eta; a.ntiles = p->n_wm;
+      if (launch_batched_wave_max(a, st) != hipSuccess) return WIU_EHIP;
+    }
     a.tiles = p->d_tiles; a.ntiles = p->n_xi;
     if (launch_batched_sweep(p->scheme, 0, p->variant[0], a, st) != hipSuccess) return WIU_EHIP;
+    if (stage < 2 && launch_fill_u64(stage == 0 ? p->d_lam2 : p->d_lam, p->lam_len, st) != hipSuccess)
+      return WIU_EHIP;
     a.tiles = p->d_tiles + p->n_xi; a.ntiles = p->n_eta;
     if (launch_batched_sweep(p->scheme, 1, p->variant[1], a, st) != hipSuccess) return WIU_EHIP;
   }
@@ -106,7 +114,7 @@ int wiu_batched_plan(const wiu_block* blocks, int nblocks, int scheme, const wiu
   p->variant[1] = eta_variant;
   p->params = *params;
 
-  // workspace: [status | lam of all blocks | dt of all blocks | per block R^xi, U1, U2]
+  // workspace: [status | lam, lam2 of all blocks | dt of all blocks | per block R^xi, U1, U2]
   std::vector<size_t> off_lam(nblocks), off_st(nblocks);
   size_t lam_total = 0;
   for (int b = 0; b < nblocks; ++b) {
@@ -116,6 +124,8 @@ int wiu_batched_plan(const wiu_block* blocks, int nblocks, int scheme, const wiu
   size_t pos = ALIGN;                                   // status
   const size_t lam_pos = pos;
   pos += align_up(lam_total * 8);
+  const size_t lam2_pos = pos;
+  pos += align_up(lam_total * 8);
   const size_t dt_pos = pos;
   pos += align_up((size_t)nblocks * 8);
   for (int b = 0; b < nblocks; ++b) {
@@ -124,12 +134,13 @@ int wiu_batched_plan(const wiu_block* blocks, int nblocks, int scheme, const wiu
     p->cells += (long long)blocks[b].nx * blocks[b].ny;
   }
   if (hipMalloc(&p->d_ws, pos) != hipSuccess) { free_plan(p); return WIU_EHIP; }
-  if (hipMemset(p->d_ws, 0, ALIGN + align_up(lam_total * 8) + align_up((size_t)nblocks * 8)) != hipSuccess) {
+  if (hipMemset(p->d_ws, 0, ALIGN + 2 * align_up(lam_total * 8) + align_up((size_t)nblocks * 8)) != hipSuccess) {
     free_plan(p);
     return WIU_EHIP;
   }
   p->d_status = (int*)p->d_ws;
   p->d_lam = (unsigned long long*)(p->d_ws + lam_pos);
+  p->d_lam2 = (unsigned long long*)(p->d_ws + lam2_pos);
   p->lam_len = (long long)lam_total;
   p->d_dt = (double*)(p->d_ws + dt_pos);
 
@@ -145,6 +156,7 @@ int wiu_batched_plan(const wiu_block* blocks, int nblocks, int scheme, const wiu
     B.U1 = (double*)(p->d_ws + off_st[b] + plane4);
     B.U2 = (double*)(p->d_ws + off_st[b] + 2 * plane4);
     B.lam = p->d_lam + off_lam[b];
+    B.lam2 = p->d_lam2 + off_lam[b];
     B.dt = p->d_dt + b;
   }
   // tile tables, block by block (so each XCD's contiguous range stays local)
@@ -232,7 +244,7 @@ int wiu_batched_rk3_step(wiu_plan* p, int use_graph, wiu_stream_t stream) {
   hipStream_t st = (hipStream_t)stream;
   if (!use_graph) return launch_step(p, st);
   if (!p->exec) {
-    // capture the twelve launches of one step on a private stream
+    // capture the launches of one step on a private stream
     hipStream_t cap;
     if (hipStreamCreate(&cap) != hipSuccess) return WIU_EHIP;
     int rc = WIU_OK;

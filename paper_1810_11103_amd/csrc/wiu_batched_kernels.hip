@@ -25,7 +25,12 @@ __global__ void __launch_bounds__(NA * NB) batched_sweep_kernel(BatchArgs b) {
     const int4 tl = b.tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const BlockDev& B = b.blocks[tl.x];
     SweepArgs s;
-    s.d = B.d; s.M = B.M; s.lam_xi = B.lam; s.lam_eta = B.lam + B.d.ny;
+    // stage 2 reads the maxima its predecessor accumulated in lam2; the eta
+    // sweeps of stages 1 and 2 accumulate those of the state they write
+    const unsigned long long* lam = b.stage == 1 ? B.lam2 : B.lam;
+    s.d = B.d; s.M = B.M; s.lam_xi = lam; s.lam_eta = lam + B.d.ny;
+    unsigned long long* nlam = (DIR == 1 && b.stage < 2) ? (b.stage == 0 ? B.lam2 : B.lam) : nullptr;
+    s.nlam_xi = nlam; s.nlam_eta = nlam ? nlam + B.d.ny : nullptr;
     s.gamma = b.gamma; s.alpha = b.alpha; s.eps = b.eps; s.ppm = b.ppm;
     s.Rxi = B.Rxi; s.U0 = B.U; s.dt = B.dt; s.status = b.status;
     s.U = stage_src(B, b.stage);

@@ -281,15 +281,36 @@ WIU_DEV void nodal_split(const double Q[4], double kx, double ky, double lam, do
 
 // Wave speed |k . u| + c |k| (Sec. 2.3); returns a negative value for a
 // non-physical or non-finite state so callers can flag it.
+// Wave speed |k . u| + c |k| (Sec. 2.3), evaluated as |k . u| + sqrt(c^2 |k|^2)
+// (one root per direction; c^2 shared by both directions of a node).
 // No contraction here: the adjoint locates the node attaining a line maximum
 // by recomputing this value in another kernel, which must round identically.
-WIU_DEV double wave_speed(const double Q[4], double kx, double ky, double gam, bool& bad) {
+struct WaveState {
+  double u, v, c2;
+  bool bad;  // rho <= 0 or p <= 0 (or not finite)
+};
+
+WIU_DEV WaveState wave_state(const double Q[4], double gam) {
 #pragma clang fp contract(off)
   const double ri = rcp(Q[0]);
-  const double u = Q[1] * ri, v = Q[2] * ri;
-  const double p = (gam - 1.0) * (Q[3] - 0.5 * (Q[1] * u + Q[2] * v));
-  const double s = fabs(kx * u + ky * v) + sqrt(gam * p * ri) * sqrt(kx * kx + ky * ky);
-  bad = !(Q[0] > 0.0) || !(p > 0.0) || !(s < 1.0e300);
+  WaveState w;
+  w.u = Q[1] * ri;
+  w.v = Q[2] * ri;
+  const double p = (gam - 1.0) * (Q[3] - 0.5 * (Q[1] * w.u + Q[2] * w.v));
+  w.c2 = gam * p * ri;
+  w.bad = !(Q[0] > 0.0) || !(p > 0.0);
+  return w;
+}
+
+WIU_DEV double wave_speed_dir(const WaveState& w, double kx, double ky) {
+#pragma clang fp contract(off)
+  return fabs(kx * w.u + ky * w.v) + sqrt(w.c2 * (kx * kx + ky * ky));
+}
+
+WIU_DEV double wave_speed(const double Q[4], double kx, double ky, double gam, bool& bad) {
+  const WaveState w = wave_state(Q, gam);
+  const double s = wave_speed_dir(w, kx, ky);
+  bad = w.bad || !(s < 1.0e300);
   return s;
 }
 

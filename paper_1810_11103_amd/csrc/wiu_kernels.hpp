@@ -21,6 +21,10 @@ struct SweepArgs {
   const double* dt;                     // device scalar time step
   double ca, cb;                        // out = ca U0 + cb (U + dt L)
   int* status;
+  // eta sweep in mode 2 only: when set, the line maxima of the new stage
+  // state are accumulated here (cleared beforehand) for the next stage
+  unsigned long long* nlam_xi;
+  unsigned long long* nlam_eta;
 };
 
 // One block of a batched multi-block problem (device table entry).
@@ -30,6 +34,7 @@ struct BlockDev {
   const double* M;           // its metrics (with tag)
   double *U1, *U2, *Rxi;     // stage states and R^xi
   unsigned long long* lam;   // lam_xi[ny], lam_eta[nx], cfl_max[1]
+  unsigned long long* lam2;  // second set: maxima of the first stage state
   double* dt;                // its time step (device scalar)
 };
 

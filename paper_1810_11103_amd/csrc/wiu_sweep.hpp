@@ -32,10 +32,11 @@ WIU_DEV void wave_max_tile(const Dims& d, const double* __restrict__ U, const do
       const long long o = (long long)j * d.nx + i;
       const double Q[4] = {U[o], U[d.np + o], U[2 * d.np + o], U[3 * d.np + o]};
       const long long mo = (long long)(j + GHOST) * d.mpitch + (i + GHOST);
-      bool b1, b2;
-      sx = wave_speed(Q, M[mo], M[d.mplane + mo], gam, b1);
-      const double se = wave_speed(Q, M[2 * d.mplane + mo], M[3 * d.mplane + mo], gam, b2);
-      bad_any |= b1 || b2;
+      const WaveState w = wave_state(Q, gam);
+      const double sxr = wave_speed_dir(w, M[mo], M[d.mplane + mo]);
+      const double se = wave_speed_dir(w, M[2 * d.mplane + mo], M[3 * d.mplane + mo]);
+      bad_any |= w.bad || !(sxr < 1.0e300) || !(se < 1.0e300);
+      sx = fmax(0.0, sxr);  // NaN dropped, as below
       colmax = fmax(colmax, se);  // non-finite speeds are flagged through `status`
       cflm = fmax(cflm, (sx + se) / M[4 * d.mplane + mo]);
     }
@@ -68,10 +69,76 @@ WIU_DEV void wave_max_tile(const Dims& d, const double* __restrict__ U, const do
 }
 
 
+// LDS of a sweep tile.  Lanes of a wave run along the line for xi tiles and
+// across lines (then along) for eta tiles; both arrays are laid out so that
+// the lanes of a wave touch consecutive words (no bank conflicts): line-major
+// for xi, position-major for eta.
 template <int SC, int DIR, int NA, int NB> struct SweepLds {
-  double sh[16][NA * NB];        // [kind*4 + comp][item]: kinds fp, fm, Fp, Fm
-  double sq[4][NB][NA + 5];      // stencil tile: items k - 2 .. k + 3
+  static constexpr int NQ = NA + 5;  // stencil tile: items k - 2 .. k + 3
+  double sh[16][NA * NB];            // [kind*4 + comp][item]: kinds fp, fm, Fp, Fm
+  double sq[4][NB * NQ];
+  // item slot of (line tb, position ta) and state slot of (line tb, position pos)
+  static WIU_DEV int si(int tb, int ta) { return DIR == 0 ? tb * NA + ta : ta * NB + tb; }
+  static WIU_DEV int qi(int tb, int pos) { return DIR == 0 ? tb * NQ + pos : pos * NB + tb; }
 };
+
+// Output phase of an eta tile in RK-stage mode that also accumulates the line
+// maxima of the new stage state (the next stage's eigenvalues, Sec. 2.3), so
+// that stage needs no separate pass over the state.  Every lane of the block
+// calls it (inactive lanes with act = false).  Lanes of a wave are NB lines
+// (fast) by 64/NB positions: the eta maxima reduce over the positions, the
+// xi maxima over the lines; wave speeds are clamped at zero as in the
+// separate pass, so the maxima are bit-identical to it.
+template <int SC, int NA, int NB>
+WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB>& L, bool act, int line, int i, int o0,
+                             int tb, int ta) {
+  using R_ = Range<SC>;
+  using LT = SweepLds<SC, 1, NA, NB>;
+  static_assert(64 % NB == 0 && (NA * NB) % 64 == 0, "eta tile must pack whole waves");
+  const Dims& d = s.d;
+  double sx = 0.0, se = 0.0;
+  bool bad = false;
+  if (act) {
+    auto at = [&](int kk) { return LT::si(tb, kk - (o0 + R_::LO)); };
+    double R[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      auto fp = [&](int kk) { return L.sh[c][at(kk)]; };
+      auto fm = [&](int kk) { return L.sh[4 + c][at(kk)]; };
+      auto Fp = [&](int kk) { return L.sh[8 + c][at(kk)]; };
+      auto Fm = [&](int kk) { return L.sh[12 + c][at(kk)]; };
+      R[c] = hflux<SC>(i, fp, fm, Fp, Fm) - hflux<SC>(i - 1, fp, fm, Fp, Fm);
+    }
+    const long long o = (long long)i * d.nx + line;
+    const long long mo = (long long)(i + GHOST) * d.mpitch + (line + GHOST);
+    const double rj = -rcp(s.M[4 * d.mplane + mo]);
+    const double dt = s.dt[0];
+    const int pq = LT::qi(tb, i - (o0 + R_::LO - 2));
+    double Qn[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double Lc = (s.Rxi[c * d.np + o] + R[c]) * rj;
+      const long long e = c * d.np + o;
+      const double un = s.cb * (L.sq[c][pq] + dt * Lc);
+      Qn[c] = s.ca == 0.0 ? un : s.ca * s.U0[e] + un;
+      s.out[e] = Qn[c];
+    }
+    const WaveState w = wave_state(Qn, s.gamma);
+    const double sxr = wave_speed_dir(w, s.M[mo], s.M[d.mplane + mo]);
+    const double ser = wave_speed_dir(w, s.M[2 * d.mplane + mo], s.M[3 * d.mplane + mo]);
+    bad = w.bad || !(sxr < 1.0e300) || !(ser < 1.0e300);
+    sx = fmax(0.0, sxr);
+    se = fmax(0.0, ser);
+  }
+  if (bad) atomicOr(s.status, ST_NONPHYS);
+  // eta line (column) maxima: reduce over the positions of the wave
+  for (int off = NB; off < 64; off <<= 1) se = fmax(se, __shfl_xor(se, off, 64));
+  // xi line (row) maxima: reduce over the lines of the wave
+  for (int off = 1; off < NB; off <<= 1) sx = fmax(sx, __shfl_xor(sx, off, 64));
+  const int lane = (threadIdx.x + NB * threadIdx.y) & 63;
+  if (lane < NB && line < d.nx) atomicMax(&s.nlam_eta[line], (unsigned long long)__double_as_longlong(se));
+  if (tb == 0 && act) atomicMax(&s.nlam_xi[i], (unsigned long long)__double_as_longlong(sx));
+}
 
 // One tile of a sweep: logical tile (bxl, byl) = (segment along the line,
 // group of lines) for xi, (group of lines, segment) for eta.  Every thread of
@@ -106,7 +173,8 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   const int o0 = (DIR == 0 ? bxl : byl) * OUT;
   const int out = min(OUT, n_al - o0);
   const int k = o0 + R_::LO + ta;
-  const int slot = tb * NA + ta;
+  using LT = SweepLds<SC, DIR, NA, NB>;
+  const int slot = LT::si(tb, ta);
   const bool live = line < n_ac;
 
   // element offsets
@@ -139,7 +207,7 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
         const int kk = bc_index(k0 + pos, n_al, bc_al);
         const long long o = DIR == 0 ? (long long)ln * d.nx + kk : (long long)kk * d.nx + ln;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sq[c][lb][pos] = s.U[c * d.np + o];
+        for (int c = 0; c < 4; ++c) sq[c][LT::qi(lb, pos)] = s.U[c * d.np + o];
       }
     }
   }
@@ -147,7 +215,7 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
 
   if (need_node || need_mid) {
     // stencil states Q_{k-2..k+3}, read from LDS where they are used
-    auto q = [&](int m, int c) { return sq[c][tb][ta + m]; };
+    auto q = [&](int m, int c) { return sq[c][LT::qi(tb, ta + m)]; };
     const long long mo = mline + mstride * k;
     const double kx0 = Mk[mo], ky0 = Mk[d.mplane + mo];
     if (need_node) {
@@ -177,16 +245,23 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   }
   __syncthreads();
 
-  if (!live || ta >= out) return;  // no barrier follows
+  const bool act = live && ta < out;
+  if constexpr (DIR == 1) {
+    if (s.mode == 2 && s.nlam_xi) {  // whole waves take part in the reductions
+      fused_stage_out<SC, NA, NB>(s, L, act, line, o0 + ta, o0, tb, ta);
+      return;
+    }
+  }
+  if (!act) return;  // no barrier follows
   const int i = o0 + ta;                  // output node along the line
-  const int base = tb * NA - (o0 + R_::LO);  // slot of line index kk is base + kk
+  auto at = [&](int kk) { return LT::si(tb, kk - (o0 + R_::LO)); };  // slot of line index kk
   double R[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    auto fp = [&](int kk) { return sh[c][base + kk]; };
-    auto fm = [&](int kk) { return sh[4 + c][base + kk]; };
-    auto Fp = [&](int kk) { return sh[8 + c][base + kk]; };
-    auto Fm = [&](int kk) { return sh[12 + c][base + kk]; };
+    auto fp = [&](int kk) { return sh[c][at(kk)]; };
+    auto fm = [&](int kk) { return sh[4 + c][at(kk)]; };
+    auto Fp = [&](int kk) { return sh[8 + c][at(kk)]; };
+    auto Fm = [&](int kk) { return sh[12 + c][at(kk)]; };
     R[c] = hflux<SC>(i, fp, fm, Fp, Fm) - hflux<SC>(i - 1, fp, fm, Fp, Fm);
   }
   const long long o = DIR == 0 ? (long long)line * d.nx + i : (long long)i * d.nx + line;
@@ -203,12 +278,17 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
     for (int c = 0; c < 4; ++c) s.out[c * d.np + o] = (s.Rxi[c * d.np + o] + R[c]) * rj;
     return;
   }
+  // stage update; the stage state at the output node is the staged tile
+  // entry (an interior node, so untouched by the boundary rule), and U0 is
+  // not read when its coefficient is zero (first stage)
   const double dt = s.dt[0];
+  const int pq = LT::qi(tb, i - (o0 + R_::LO - 2));
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const double L = (s.Rxi[c * d.np + o] + R[c]) * rj;
     const long long e = c * d.np + o;
-    s.out[e] = s.ca * s.U0[e] + s.cb * (s.U[e] + dt * L);
+    const double un = s.cb * (sq[c][pq] + dt * L);
+    s.out[e] = s.ca == 0.0 ? un : s.ca * s.U0[e] + un;
   }
 }
 

@@ -25,7 +25,7 @@ EXPORTS = [
     "wiu_profile_enable", "wiu_profile_read", "wiu_tuning_variants", "wiu_set_tuning", "wiu_get_tuning",
     "wiu_batched_plan", "wiu_batched_info", "wiu_batched_set_dt", "wiu_batched_cfl_dt", "wiu_batched_get_dt",
     "wiu_batched_rk3_step", "wiu_batched_status", "wiu_plan_destroy",
-    "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp",
+    "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl",
 ]
 KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3}
 
@@ -64,6 +64,7 @@ def _load():
         "wiu_rhs": (I, [G, I, PR, P, P, P, P, P]),
         "wiu_cfl_dt": (I, [G, PR, P, P, ctypes.c_double, P, P, P]),
         "wiu_rk3_step": (I, [G, I, PR, P, P, P, P, P]),
+        "wiu_rk3_step_cfl": (I, [G, I, PR, P, P, ctypes.c_double, P, P, P]),
         "wiu_status": (I, [P, P, ctypes.POINTER(I), I]),
         "wiu_strerror": (ctypes.c_char_p, [I]),
         "wiu_profile_enable": (I, [I]),
@@ -195,6 +196,12 @@ def rk3_step(grid, scheme, params, U, M, dt_dev, ws, stream=None):
     return U
 
 
+def rk3_step_cfl(grid, scheme, params, U, M, cfl, dt_dev, ws, stream=None):
+    _check(lib.wiu_rk3_step_cfl(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U), _ptr(M),
+                                float(cfl), _ptr(dt_dev), ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+    return U
+
+
 def rhs_vjp(grid, scheme, params, U, M, Gbar, Ubar, ws, stream=None):
     _check(lib.wiu_rhs_vjp(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U), _ptr(M), _ptr(Gbar),
                            _ptr(Ubar), ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
@@ -275,6 +282,10 @@ class Solver:
         if dt is not None:
             self.dt.fill_(float(dt))
         return rk3_step(self.grid, self.scheme, self.params, U, self.M, self.dt, self.ws)
+
+    def rk3_step_cfl(self, U, cfl):
+        """CFL time step of U (into self.dt) and one RK3 step of that size."""
+        return rk3_step_cfl(self.grid, self.scheme, self.params, U, self.M, cfl, self.dt, self.ws)
 
     def rhs_vjp(self, U, Gbar, out=None):
         out = torch.empty_like(U) if out is None else out

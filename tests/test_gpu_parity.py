@@ -275,3 +275,66 @@ def test_tile_shapes_give_identical_results(wiu):
     finally:
         wiu.set_tuning(0, saved[0])
         wiu.set_tuning(1, saved[1])
+
+
+@pytest.mark.parametrize("s", SCHEMES)
+def test_rk3_step_parity_ragged_transmissive(orc, wiu, s):
+    """RK3 step on a ragged transmissive Riemann grid: stages 2 and 3 take
+    their line eigenvalues from the maxima the previous stage's eta sweep
+    accumulated, so wrong maxima would show here against the oracle."""
+    say("rk3 parity ragged riemann", s)
+    g, U = make_case("riemann", 260, 90, seed=5)
+    Mo = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    dt = orc.cfl_dt(U, Mo, 0.5)
+    ref = orc.rk3_step(s, U, Mo, dt, g.bc)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period)
+    Ud = _dev(U)
+    sol.rk3_step(Ud, dt)
+    out = _host(Ud)
+    assert sol.status() == 0
+    err = normwise(out - U, ref - U)
+    assert np.all(err <= 1e-11), err
+
+
+def test_rk3_step_cfl_equals_cfl_dt_then_step(wiu):
+    """The combined entry point gives bitwise the dt and state of wiu_cfl_dt
+    followed by wiu_rk3_step."""
+    g, U = make_case("riemann", 301, 203, seed=6)
+    sol = wiu.Solver(g.x, g.y, "5-2MP", g.bc, g.period)
+    Ua, Ub = _dev(U), _dev(U)
+    for _ in range(3):
+        sol.cfl_dt(Ua, 0.5)
+        dta = float(sol.dt.item())
+        sol.rk3_step(Ua)
+        sol.rk3_step_cfl(Ub, 0.5)
+        assert float(sol.dt.item()) == dta
+        assert np.array_equal(_host(Ua), _host(Ub))
+    assert sol.status() == 0
+
+
+def test_rk3_step_identical_across_tile_shapes(wiu):
+    """RK3 steps are bitwise the same for every pair of tile shapes: the eta
+    tiles reduce the next stage's line maxima over their own lane layout
+    (2 to 16 lines per wave), and maxima do not depend on the order."""
+    g, U = make_case("riemann", 301, 203, seed=7)
+    saved = (wiu.get_tuning(0), wiu.get_tuning(1))
+    try:
+        for s in ("3-1MP", "5-2MP"):
+            sol = wiu.Solver(g.x, g.y, s, g.bc, g.period)
+            ref = None
+            for vx in range(wiu.tuning_variants(0)):
+                for ve in range(wiu.tuning_variants(1)):
+                    wiu.set_tuning(0, vx)
+                    wiu.set_tuning(1, ve)
+                    Ud = _dev(U)
+                    sol.rk3_step(Ud, 2e-4)
+                    sol.rk3_step(Ud, 2e-4)
+                    out = _host(Ud)
+                    if ref is None:
+                        ref = out
+                    else:
+                        assert np.array_equal(out, ref), (s, vx, ve)
+            assert sol.status() == 0
+    finally:
+        wiu.set_tuning(0, saved[0])
+        wiu.set_tuning(1, saved[1])

@@ -35,7 +35,7 @@ struct ProfScope {
 };
 
 // Tile shape of each sweep direction (index into the compiled variants).
-int g_variant[2] = {0, 2};  // xi 128 x 1, eta 32 x 4 (measured best at 2048^2)
+int g_variant[2] = {0, 2};  // xi 128 x 1, eta 32 x 8 (measured at 2048^2)
 
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -183,7 +183,8 @@ int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U
   if (e != hipSuccess) return WIU_EHIP;
   a.d = d; a.U = U; a.M = M;
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
-  a.mode = 0; a.Rxi = w.rxi; a.out = out; a.U0 = U0; a.dt = dt; a.ca = ca; a.cb = cb; a.status = w.status;
+  a.mode = mode == 2 ? 3 : 0; a.Rxi = w.rxi; a.out = out; a.U0 = U0; a.dt = dt; a.ca = ca; a.cb = cb;
+  a.status = w.status;
   a.nlam_xi = nullptr; a.nlam_eta = nullptr;
   {
     ProfScope ps(WIU_K_SWEEP_XI, st);

@@ -11,7 +11,7 @@ using namespace wiu;
 struct wiu_plan {
   int scheme = 0;
   int nblocks = 0;
-  int variant[2] = {0, 4};
+  int variant[2] = {0, 0};
   wiu_params params{};
   long long cells = 0;
   // device memory owned by the plan

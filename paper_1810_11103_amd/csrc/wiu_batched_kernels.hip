@@ -19,7 +19,7 @@ WIU_DEV const double* stage_src(const BlockDev& B, int stage) {
 }
 
 template <int SC, int DIR, int NA, int NB>
-__global__ void __launch_bounds__(NA * NB) batched_sweep_kernel(BatchArgs b) {
+__global__ void __launch_bounds__(NA * NB, 4) batched_sweep_kernel(BatchArgs b) {
   __shared__ SweepLds<SC, DIR, NA, NB> lds;
   {
     const int4 tl = b.tiles[xcd_remap(blockIdx.x, gridDim.x)];
@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(NA * NB) batched_sweep_kernel(BatchArgs b) {
     s.out = b.stage == 0 ? B.U1 : (b.stage == 1 ? B.U2 : B.U);
     s.ca = b.stage == 0 ? 0.0 : (b.stage == 1 ? 0.75 : 1.0 / 3.0);
     s.cb = b.stage == 0 ? 1.0 : (b.stage == 1 ? 0.25 : 2.0 / 3.0);
-    s.mode = DIR == 0 ? 0 : 2;
+    s.mode = DIR == 0 ? 3 : 2;
     sweep_tile<SC, DIR, NA, NB>(s, tl.y, tl.z, lds);
   }
 }
@@ -70,21 +70,20 @@ hipError_t launch_batched_sweep_t(const BatchArgs& a, hipStream_t st) {
 
 template <int SC, int DIR>
 hipError_t launch_batched_sweep_v(int variant, const BatchArgs& a, hipStream_t st) {
+#define WIU_CASE(v, na, nb) \
+  case v: return launch_batched_sweep_t<SC, DIR, na, nb>(a, st);
   if constexpr (DIR == 0) {
     switch (variant) {
-      case 1: return launch_batched_sweep_t<SC, 0, 256, 1>(a, st);
-      case 2: return launch_batched_sweep_t<SC, 0, 64, 2>(a, st);
-      default: return launch_batched_sweep_t<SC, 0, 128, 1>(a, st);
+      WIU_XI_TILES(WIU_CASE)
+      default: return hipErrorInvalidValue;
     }
   } else {
     switch (variant) {
-      case 1: return launch_batched_sweep_t<SC, 1, 32, 8>(a, st);
-      case 2: return launch_batched_sweep_t<SC, 1, 32, 4>(a, st);
-      case 3: return launch_batched_sweep_t<SC, 1, 64, 4>(a, st);
-      case 4: return launch_batched_sweep_t<SC, 1, 64, 2>(a, st);
-      default: return launch_batched_sweep_t<SC, 1, 32, 16>(a, st);
+      WIU_ETA_TILES(WIU_CASE)
+      default: return hipErrorInvalidValue;
     }
   }
+#undef WIU_CASE
 }
 
 hipError_t launch_batched_sweep(int scheme, int dir, int variant, const BatchArgs& a, hipStream_t st) {
@@ -101,10 +100,12 @@ hipError_t launch_batched_sweep(int scheme, int dir, int variant, const BatchArg
 }
 
 void sweep_tile_shape(int dir, int variant, int& na, int& nb) {
-  static const int xi[3][2] = {{128, 1}, {256, 1}, {64, 2}};
-  static const int eta[5][2] = {{32, 16}, {32, 8}, {32, 4}, {64, 4}, {64, 2}};
-  if (dir == 0) { na = xi[variant][0]; nb = xi[variant][1]; }
-  else { na = eta[variant][0]; nb = eta[variant][1]; }
+  na = nb = 0;
+#define WIU_SHAPE(v, a_, b_) \
+  if (variant == v) { na = a_; nb = b_; }
+  if (dir == 0) { WIU_XI_TILES(WIU_SHAPE) }
+  else { WIU_ETA_TILES(WIU_SHAPE) }
+#undef WIU_SHAPE
 }
 
 int scheme_extra(int scheme) {

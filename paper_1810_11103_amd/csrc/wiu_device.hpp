@@ -265,6 +265,19 @@ WIU_DEV void side_flux(QF q, int side, double nx_, double ny_, double mx, double
   F[3] = 0.5 * ((r3 + pl) * Ul + sl * r3);
 }
 
+// Nodal contravariant flux E^ = (rho U, m U + kx p, n U + ky p, (e + p) U),
+// U = kx u + ky v, with the nodal metric (Sec. 2.1).
+WIU_DEV void nodal_flux(const double Q[4], double kx, double ky, double gam, double E[4]) {
+  const double ri = rcp(Q[0]);
+  const double u = Q[1] * ri, v = Q[2] * ri;
+  const double p = (gam - 1.0) * (Q[3] - 0.5 * (Q[1] * u + Q[2] * v));
+  const double U = kx * u + ky * v;
+  E[0] = Q[0] * U;
+  E[1] = Q[1] * U + kx * p;
+  E[2] = Q[2] * U + ky * p;
+  E[3] = (Q[3] + p) * U;
+}
+
 // Nodal split fluxes f^+- = (E^ +- lam Q)/2 with the nodal metric (Sec. 2.3).
 WIU_DEV void nodal_split(const double Q[4], double kx, double ky, double lam, double gam, double fp[4],
                          double fm[4]) {

@@ -217,11 +217,14 @@ __global__ void lambda_out_kernel(Dims d, double alpha, const unsigned long long
 // each line form H_{i+1/2} - H_{i-1/2} for their output node.
 //   DIR 0 (xi):  threadIdx.x runs along i, threadIdx.y across rows j.
 //   DIR 1 (eta): threadIdx.x runs across columns i, threadIdx.y along j.
-// Epilogue: mode 0 writes R^xi; mode 1 writes dU/dt = -(R^xi + R^eta)/J^{-1};
-// mode 2 writes an RK stage U_out = a U0 + b Us + c dt dU/dt.
+// Epilogue (SweepArgs::mode): rhs -- the xi sweep writes R^xi, the eta sweep
+// dU/dt = -(R^xi + R^eta)/J^{-1}; RK stage -- the xi sweep writes its part of
+// the update, P = a U0 + b (Us - dt R^xi/J^{-1}), the eta sweep completes it,
+// U_out = P - b dt R^eta/J^{-1}, so U0 is read by the lighter xi epilogue.
+// Launched for 4 waves per SIMD (at most 128 VGPRs).
 // ===========================================================================
 template <int SC, int DIR, int NA, int NB>
-__global__ void __launch_bounds__(NA * NB) sweep_kernel(SweepArgs s) {
+__global__ void __launch_bounds__(NA * NB, 4) sweep_kernel(SweepArgs s) {
   __shared__ SweepLds<SC, DIR, NA, NB> lds;
   // logical tile in XCD-aware order
   const int total = gridDim.x * gridDim.y;
@@ -245,29 +248,26 @@ hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Compiled tile shapes (items along the line x lines per block).
-//   xi : 0 (128 x 1), 1 (256 x 1), 2 (64 x 2)
-//   eta: 0 (32 x 16), 1 (32 x 8), 2 (32 x 4), 3 (64 x 4), 4 (64 x 2)
+// Tile shape `variant` of each direction (WIU_XI_TILES / WIU_ETA_TILES).
 template <int SC, int DIR>
 hipError_t launch_sweep_v(int variant, const SweepArgs& a, hipStream_t st) {
+#define WIU_CASE(v, na, nb) \
+  case v: return launch_sweep_t<SC, DIR, na, nb>(a, st);
   if constexpr (DIR == 0) {
     switch (variant) {
-      case 1: return launch_sweep_t<SC, 0, 256, 1>(a, st);
-      case 2: return launch_sweep_t<SC, 0, 64, 2>(a, st);
-      default: return launch_sweep_t<SC, 0, 128, 1>(a, st);
+      WIU_XI_TILES(WIU_CASE)
+      default: return hipErrorInvalidValue;
     }
   } else {
     switch (variant) {
-      case 1: return launch_sweep_t<SC, 1, 32, 8>(a, st);
-      case 2: return launch_sweep_t<SC, 1, 32, 4>(a, st);
-      case 3: return launch_sweep_t<SC, 1, 64, 4>(a, st);
-      case 4: return launch_sweep_t<SC, 1, 64, 2>(a, st);
-      default: return launch_sweep_t<SC, 1, 32, 16>(a, st);
+      WIU_ETA_TILES(WIU_CASE)
+      default: return hipErrorInvalidValue;
     }
   }
+#undef WIU_CASE
 }
 
-int sweep_variants(int dir) { return dir == 0 ? 3 : 5; }
+int sweep_variants(int dir) { return dir == 0 ? WIU_N_XI_TILES : WIU_N_ETA_TILES; }
 
 hipError_t launch_sweep(int scheme, int dir, int variant, const SweepArgs& a, hipStream_t st) {
   switch (scheme * 2 + dir) {

@@ -5,6 +5,12 @@
 
 namespace wiu {
 
+// Compiled tile shapes of the sweeps, (variant, items along a line, lines per
+// workgroup); one list serves the per-grid and the batched launches.
+#define WIU_XI_TILES(X) X(0, 128, 1) X(1, 256, 1) X(2, 64, 2)
+#define WIU_ETA_TILES(X) X(0, 32, 4) X(1, 64, 4) X(2, 32, 8) X(3, 64, 8) X(4, 32, 16)
+constexpr int WIU_N_XI_TILES = 3, WIU_N_ETA_TILES = 5;
+
 // Arguments of one direction sweep (see sweep_kernel).
 struct SweepArgs {
   Dims d;
@@ -14,12 +20,15 @@ struct SweepArgs {
   const unsigned long long* lam_eta;
   double gamma, alpha, eps;
   int ppm;
-  int mode;                             // 0 write R^xi, 1 dU/dt, 2 RK stage
-  double* Rxi;                          // R^xi (written in mode 0, read otherwise)
+  // 0 (xi) write R^xi; 1 (eta) dU/dt = -(R^xi + R^eta)/J^{-1};
+  // 3 (xi) write P = ca U0 + cb (U - dt R^xi/J^{-1}) into the R^xi buffer;
+  // 2 (eta) RK stage U_out = P - cb dt R^eta/J^{-1}
+  int mode;
+  double* Rxi;                          // R^xi or P (written by xi, read by eta)
   double* out;                          // dU/dt or the new RK stage state
   const double* U0;                     // RK base state U^n
   const double* dt;                     // device scalar time step
-  double ca, cb;                        // out = ca U0 + cb (U + dt L)
+  double ca, cb;                        // stage: ca U0 + cb (U + dt dU/dt)
   int* status;
   // eta sweep in mode 2 only: when set, the line maxima of the new stage
   // state are accumulated here (cleared beforehand) for the next stage

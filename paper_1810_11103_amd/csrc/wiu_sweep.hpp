@@ -72,15 +72,35 @@ WIU_DEV void wave_max_tile(const Dims& d, const double* __restrict__ U, const do
 // LDS of a sweep tile.  Lanes of a wave run along the line for xi tiles and
 // across lines (then along) for eta tiles; both arrays are laid out so that
 // the lanes of a wave touch consecutive words (no bank conflicts): line-major
-// for xi, position-major for eta.
+// for xi, position-major for eta.  Per item the nodal flux E^ is kept rather
+// than f^+- = (E^ +- lam Q)/2, which the output phase rebuilds from E^ and the
+// staged state (12 instead of 16 values per item, so larger tiles fit).
 template <int SC, int DIR, int NA, int NB> struct SweepLds {
   static constexpr int NQ = NA + 5;  // stencil tile: items k - 2 .. k + 3
-  double sh[16][NA * NB];            // [kind*4 + comp][item]: kinds fp, fm, Fp, Fm
+  double sh[12][NA * NB];            // [kind*4 + comp][item]: kinds E^, F^+, F^-
   double sq[4][NB * NQ];
   // item slot of (line tb, position ta) and state slot of (line tb, position pos)
   static WIU_DEV int si(int tb, int ta) { return DIR == 0 ? tb * NA + ta : ta * NB + tb; }
   static WIU_DEV int qi(int tb, int pos) { return DIR == 0 ? tb * NQ + pos : pos * NB + tb; }
 };
+
+// H_{i+1/2} - H_{i-1/2} at output node i of line tb from the items in LDS.
+template <int SC, int DIR, int NA, int NB>
+WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB>& L, int tb, int o0, int i, double lam, double R[4]) {
+  using R_ = Range<SC>;
+  using LT = SweepLds<SC, DIR, NA, NB>;
+  auto at = [&](int kk) { return LT::si(tb, kk - (o0 + R_::LO)); };      // item slot of node kk
+  auto aq = [&](int kk) { return LT::qi(tb, kk - (o0 + R_::LO) + 2); };  // state slot of node kk
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    asm volatile("" ::: "memory");  // one component at a time (register pressure)
+    auto fp = [&](int kk) { return 0.5 * (L.sh[c][at(kk)] + lam * L.sq[c][aq(kk)]); };
+    auto fm = [&](int kk) { return 0.5 * (L.sh[c][at(kk)] - lam * L.sq[c][aq(kk)]); };
+    auto Fp = [&](int kk) { return L.sh[4 + c][at(kk)]; };
+    auto Fm = [&](int kk) { return L.sh[8 + c][at(kk)]; };
+    R[c] = hflux<SC>(i, fp, fm, Fp, Fm) - hflux<SC>(i - 1, fp, fm, Fp, Fm);
+  }
+}
 
 // Output phase of an eta tile in RK-stage mode that also accumulates the line
 // maxima of the new stage state (the next stage's eigenvalues, Sec. 2.3), so
@@ -91,7 +111,7 @@ template <int SC, int DIR, int NA, int NB> struct SweepLds {
 // separate pass, so the maxima are bit-identical to it.
 template <int SC, int NA, int NB>
 WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB>& L, bool act, int line, int i, int o0,
-                             int tb, int ta) {
+                             int tb, double lam) {
   using R_ = Range<SC>;
   using LT = SweepLds<SC, 1, NA, NB>;
   static_assert(64 % NB == 0 && (NA * NB) % 64 == 0, "eta tile must pack whole waves");
@@ -99,28 +119,17 @@ WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB>& L, boo
   double sx = 0.0, se = 0.0;
   bool bad = false;
   if (act) {
-    auto at = [&](int kk) { return LT::si(tb, kk - (o0 + R_::LO)); };
     double R[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      auto fp = [&](int kk) { return L.sh[c][at(kk)]; };
-      auto fm = [&](int kk) { return L.sh[4 + c][at(kk)]; };
-      auto Fp = [&](int kk) { return L.sh[8 + c][at(kk)]; };
-      auto Fm = [&](int kk) { return L.sh[12 + c][at(kk)]; };
-      R[c] = hflux<SC>(i, fp, fm, Fp, Fm) - hflux<SC>(i - 1, fp, fm, Fp, Fm);
-    }
+    tile_residual<SC, 1, NA, NB>(L, tb, o0, i, lam, R);
     const long long o = (long long)i * d.nx + line;
     const long long mo = (long long)(i + GHOST) * d.mpitch + (line + GHOST);
     const double rj = -rcp(s.M[4 * d.mplane + mo]);
     const double dt = s.dt[0];
-    const int pq = LT::qi(tb, i - (o0 + R_::LO - 2));
     double Qn[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const double Lc = (s.Rxi[c * d.np + o] + R[c]) * rj;
       const long long e = c * d.np + o;
-      const double un = s.cb * (L.sq[c][pq] + dt * Lc);
-      Qn[c] = s.ca == 0.0 ? un : s.ca * s.U0[e] + un;
+      Qn[c] = s.Rxi[e] + s.cb * (dt * (R[c] * rj));
       s.out[e] = Qn[c];
     }
     const WaveState w = wave_state(Qn, s.gamma);
@@ -220,10 +229,10 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
     const double kx0 = Mk[mo], ky0 = Mk[d.mplane + mo];
     if (need_node) {
       const double qk[4] = {q(2, 0), q(2, 1), q(2, 2), q(2, 3)};
-      double fp[4], fm[4];
-      nodal_split(qk, kx0, ky0, lam, gam, fp, fm);
+      double E[4];
+      nodal_flux(qk, kx0, ky0, gam, E);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) { sh[c][slot] = fp[c]; sh[4 + c][slot] = fm[c]; }
+      for (int c = 0; c < 4; ++c) sh[c][slot] = E[c];
     }
     if (need_mid) {
       const double kx1 = Mk[mo + mstride], ky1 = Mk[d.mplane + mo + mstride];
@@ -239,7 +248,7 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
         double F[4];
         side_flux<Traits<SC>::fifth>(q, side, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, F);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sh[8 + 4 * side + c][slot] = F[c];
+        for (int c = 0; c < 4; ++c) sh[4 + 4 * side + c][slot] = F[c];
       }
     }
   }
@@ -248,22 +257,14 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   const bool act = live && ta < out;
   if constexpr (DIR == 1) {
     if (s.mode == 2 && s.nlam_xi) {  // whole waves take part in the reductions
-      fused_stage_out<SC, NA, NB>(s, L, act, line, o0 + ta, o0, tb, ta);
+      fused_stage_out<SC, NA, NB>(s, L, act, line, o0 + ta, o0, tb, lam);
       return;
     }
   }
   if (!act) return;  // no barrier follows
   const int i = o0 + ta;                  // output node along the line
-  auto at = [&](int kk) { return LT::si(tb, kk - (o0 + R_::LO)); };  // slot of line index kk
   double R[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    auto fp = [&](int kk) { return sh[c][at(kk)]; };
-    auto fm = [&](int kk) { return sh[4 + c][at(kk)]; };
-    auto Fp = [&](int kk) { return sh[8 + c][at(kk)]; };
-    auto Fm = [&](int kk) { return sh[12 + c][at(kk)]; };
-    R[c] = hflux<SC>(i, fp, fm, Fp, Fm) - hflux<SC>(i - 1, fp, fm, Fp, Fm);
-  }
+  tile_residual<SC, DIR, NA, NB>(L, tb, o0, i, lam, R);
   const long long o = DIR == 0 ? (long long)line * d.nx + i : (long long)i * d.nx + line;
   if (s.mode == 0) {
 #pragma unroll
@@ -278,17 +279,26 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
     for (int c = 0; c < 4; ++c) s.out[c * d.np + o] = (s.Rxi[c * d.np + o] + R[c]) * rj;
     return;
   }
-  // stage update; the stage state at the output node is the staged tile
-  // entry (an interior node, so untouched by the boundary rule), and U0 is
-  // not read when its coefficient is zero (first stage)
   const double dt = s.dt[0];
-  const int pq = LT::qi(tb, i - (o0 + R_::LO - 2));
+  if (s.mode == 3) {
+    // xi part of the stage update, P = ca U0 + cb (Us + dt R^xi / -J^{-1}),
+    // into the R^xi buffer; the stage state at the output node is the staged
+    // tile entry (an interior node, untouched by the boundary rule), and U0
+    // is not read when its coefficient is zero (first stage)
+    const int pq = LT::qi(tb, i - (o0 + R_::LO - 2));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const long long e = c * d.np + o;
+      const double un = s.cb * (sq[c][pq] + dt * (R[c] * rj));
+      s.Rxi[e] = s.ca == 0.0 ? un : s.ca * s.U0[e] + un;
+    }
+    return;
+  }
+  // mode 2: U_out = P + cb dt R^eta / -J^{-1}
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const double L = (s.Rxi[c * d.np + o] + R[c]) * rj;
     const long long e = c * d.np + o;
-    const double un = s.cb * (sq[c][pq] + dt * L);
-    s.out[e] = s.ca == 0.0 ? un : s.ca * s.U0[e] + un;
+    s.out[e] = s.Rxi[e] + s.cb * (dt * (R[c] * rj));
   }
 }
 

@@ -45,7 +45,8 @@ PEAK_HBM_GBS = 8000.0
 # HBM traffic of the dominant kernel, from the committed rocprofv3 counter
 # summary; used only while the kernel sources are the ones profiled.
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_eta_riemann2048_hbm.md")
-KERNEL_SOURCES = ("paper_1810_11103_amd/csrc/wiu_device.hpp", "paper_1810_11103_amd/csrc/wiu_sweep.hpp",
+KERNEL_SOURCES = ("paper_1810_11103_amd/csrc/wiu_device.hpp", "paper_1810_11103_amd/csrc/wiu_kernels.hpp",
+                  "paper_1810_11103_amd/csrc/wiu_sweep.hpp",
                   "paper_1810_11103_amd/csrc/wiu_kernels.hip")
 
 

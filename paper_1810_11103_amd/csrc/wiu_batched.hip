@@ -23,6 +23,8 @@ struct wiu_plan {
   unsigned long long* d_lam2 = nullptr;  // second set (stage 2), filled by stage 1's eta sweep
   long long lam_len = 0;
   double* d_dt = nullptr;
+  double* U_all = nullptr;        // caller's states and metrics (offsets in the block table)
+  const double* M_all = nullptr;
   int* d_status = nullptr;
   // captured step
   hipGraph_t graph = nullptr;
@@ -66,11 +68,23 @@ void free_plan(wiu_plan* p) {
   delete p;
 }
 
-int launch_step(wiu_plan* p, hipStream_t st) {
+BatchArgs base_args(const wiu_plan* p) {
   BatchArgs a;
   a.blocks = p->d_blocks;
+  a.tiles = p->d_tiles;
+  a.ntiles = 0;
+  a.stage = 0;
   a.gamma = p->params.gamma; a.alpha = p->params.alpha_lf; a.eps = p->params.eps; a.ppm = p->params.ppm;
   a.status = p->d_status;
+  a.U_all = p->U_all;
+  a.M_all = p->M_all;
+  a.ws = (double*)p->d_ws;
+  a.lam = p->d_lam;
+  return a;
+}
+
+int launch_step(wiu_plan* p, hipStream_t st) {
+  BatchArgs a = base_args(p);
   // Line maxima: a separate pass for the step's state only; the eta sweeps
   // of stages 1 and 2 accumulate the maxima of the stage state they write
   // (into lam2, then back into lam), which the next stage reads.
@@ -144,20 +158,24 @@ int wiu_batched_plan(const wiu_block* blocks, int nblocks, int scheme, const wiu
   p->lam_len = (long long)lam_total;
   p->d_dt = (double*)(p->d_ws + dt_pos);
 
-  // block table
+  p->U_all = U_all;
+  p->M_all = M_all;
+
+  // block table: element offsets into U_all, M_all, the workspace (as
+  // doubles) and the maxima (as 64-bit words from d_lam)
   std::vector<BlockDev> hb(nblocks);
   for (int b = 0; b < nblocks; ++b) {
     BlockDev& B = hb[b];
     B.d = dims_of(blocks[b]);
-    B.U = U_all + blocks[b].off_U;
-    B.M = M_all + blocks[b].off_M;
+    B.oU = blocks[b].off_U;
+    B.oM = blocks[b].off_M;
     const size_t plane4 = align_up(4 * (size_t)blocks[b].nx * blocks[b].ny * 8);
-    B.Rxi = (double*)(p->d_ws + off_st[b]);
-    B.U1 = (double*)(p->d_ws + off_st[b] + plane4);
-    B.U2 = (double*)(p->d_ws + off_st[b] + 2 * plane4);
-    B.lam = p->d_lam + off_lam[b];
-    B.lam2 = p->d_lam2 + off_lam[b];
-    B.dt = p->d_dt + b;
+    B.oRxi = (long long)(off_st[b] / 8);
+    B.oU1 = (long long)((off_st[b] + plane4) / 8);
+    B.oU2 = (long long)((off_st[b] + 2 * plane4) / 8);
+    B.oDt = (long long)(dt_pos / 8) + b;
+    B.oLam = (long long)off_lam[b];
+    B.oLam2 = (long long)((lam2_pos - lam_pos) / 8 + off_lam[b]);
   }
   // tile tables, block by block (so each XCD's contiguous range stays local)
   std::vector<int4> tx, te, tw;
@@ -227,16 +245,12 @@ int wiu_batched_get_dt(const wiu_plan* p, double* dt_host, wiu_stream_t stream) 
 int wiu_batched_cfl_dt(wiu_plan* p, double cfl, wiu_stream_t stream) {
   if (!p || !(cfl > 0.0)) return WIU_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  BatchArgs a;
-  a.blocks = p->d_blocks;
-  a.gamma = p->params.gamma; a.alpha = p->params.alpha_lf; a.eps = p->params.eps; a.ppm = p->params.ppm;
-  a.status = p->d_status;
-  a.stage = 0;
+  BatchArgs a = base_args(p);
   a.tiles = p->d_tiles + p->n_xi + p->n_eta;
   a.ntiles = p->n_wm;
   if (launch_fill_u64(p->d_lam, p->lam_len, st) != hipSuccess) return WIU_EHIP;
   if (launch_batched_wave_max(a, st) != hipSuccess) return WIU_EHIP;
-  return launch_batched_cfl_dt(p->d_blocks, p->nblocks, cfl, st) == hipSuccess ? WIU_OK : WIU_EHIP;
+  return launch_batched_cfl_dt(a, p->nblocks, cfl, st) == hipSuccess ? WIU_OK : WIU_EHIP;
 }
 
 int wiu_batched_rk3_step(wiu_plan* p, int use_graph, wiu_stream_t stream) {

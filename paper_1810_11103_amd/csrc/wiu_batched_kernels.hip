@@ -14,29 +14,45 @@ namespace wiu {
 // place one workgroup per tile, so it was dropped.
 // ===========================================================================
 
-WIU_DEV const double* stage_src(const BlockDev& B, int stage) {
-  return stage == 0 ? B.U : (stage == 1 ? B.U1 : B.U2);
+// The table entry of this workgroup, in scalar registers.
+WIU_DEV int4 uniform_tile(const BatchArgs& b) {
+  const int4 t = b.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  return make_int4(ufirst(t.x), ufirst(t.y), ufirst(t.z), 0);
+}
+
+// RK stage st (0, 1, 2) of a block reads src and writes dst:
+//   U -> U1, U1 -> U2, U2 -> U.
+WIU_DEV double* stage_src(const BatchArgs& b, const BlockDev& B, int st) {
+  return st == 0 ? b.U_all + ufirst(B.oU) : b.ws + ufirst(st == 1 ? B.oU1 : B.oU2);
+}
+WIU_DEV double* stage_dst(const BatchArgs& b, const BlockDev& B, int st) {
+  return st == 2 ? b.U_all + ufirst(B.oU) : b.ws + ufirst(st == 0 ? B.oU1 : B.oU2);
 }
 
 template <int SC, int DIR, int NA, int NB>
 __global__ void __launch_bounds__(NA * NB, 4) batched_sweep_kernel(BatchArgs b) {
   __shared__ SweepLds<SC, DIR, NA, NB> lds;
   {
-    const int4 tl = b.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int4 tl = uniform_tile(b);
     const BlockDev& B = b.blocks[tl.x];
+    const int st = b.stage;
     SweepArgs s;
-    // stage 2 reads the maxima its predecessor accumulated in lam2; the eta
-    // sweeps of stages 1 and 2 accumulate those of the state they write
-    const unsigned long long* lam = b.stage == 1 ? B.lam2 : B.lam;
-    s.d = B.d; s.M = B.M; s.lam_xi = lam; s.lam_eta = lam + B.d.ny;
-    unsigned long long* nlam = (DIR == 1 && b.stage < 2) ? (b.stage == 0 ? B.lam2 : B.lam) : nullptr;
-    s.nlam_xi = nlam; s.nlam_eta = nlam ? nlam + B.d.ny : nullptr;
+    s.d = ufirst(B.d);
+    s.M = b.M_all + ufirst(B.oM);
+    // stage 1 reads the maxima of the separate pass (lam) and accumulates
+    // those of U1 into lam2; stage 2 reads lam2 and accumulates into lam;
+    // stage 3 reads lam
+    const unsigned long long* lam = b.lam + ufirst(st == 1 ? B.oLam2 : B.oLam);
+    s.lam_xi = lam; s.lam_eta = lam + s.d.ny;
+    unsigned long long* nlam = (DIR == 1 && st < 2) ? b.lam + ufirst(st == 0 ? B.oLam2 : B.oLam) : nullptr;
+    s.nlam_xi = nlam; s.nlam_eta = nlam ? nlam + s.d.ny : nullptr;
     s.gamma = b.gamma; s.alpha = b.alpha; s.eps = b.eps; s.ppm = b.ppm;
-    s.Rxi = B.Rxi; s.U0 = B.U; s.dt = B.dt; s.status = b.status;
-    s.U = stage_src(B, b.stage);
-    s.out = b.stage == 0 ? B.U1 : (b.stage == 1 ? B.U2 : B.U);
-    s.ca = b.stage == 0 ? 0.0 : (b.stage == 1 ? 0.75 : 1.0 / 3.0);
-    s.cb = b.stage == 0 ? 1.0 : (b.stage == 1 ? 0.25 : 2.0 / 3.0);
+    s.Rxi = b.ws + ufirst(B.oRxi); s.U0 = b.U_all + ufirst(B.oU); s.dt = b.ws + ufirst(B.oDt);
+    s.status = b.status;
+    s.U = stage_src(b, B, st);
+    s.out = stage_dst(b, B, st);
+    s.ca = st == 0 ? 0.0 : (st == 1 ? 0.75 : 1.0 / 3.0);
+    s.cb = st == 0 ? 1.0 : (st == 1 ? 0.25 : 2.0 / 3.0);
     s.mode = DIR == 0 ? 3 : 2;
     sweep_tile<SC, DIR, NA, NB>(s, tl.y, tl.z, lds);
   }
@@ -45,18 +61,20 @@ __global__ void __launch_bounds__(NA * NB, 4) batched_sweep_kernel(BatchArgs b) 
 __global__ void __launch_bounds__(256) batched_wave_max_kernel(BatchArgs b) {
   __shared__ WaveLds lds;
   {
-    const int4 tl = b.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int4 tl = uniform_tile(b);
     const BlockDev& B = b.blocks[tl.x];
-    wave_max_tile(B.d, stage_src(B, b.stage), B.M, b.gamma, B.lam, B.lam + B.d.ny, B.lam + B.d.ny + B.d.nx,
-                  b.status, tl.y, tl.z, lds);
+    const Dims d = ufirst(B.d);
+    unsigned long long* lam = b.lam + ufirst(B.oLam);
+    wave_max_tile(d, stage_src(b, B, b.stage), b.M_all + ufirst(B.oM), b.gamma, lam, lam + d.ny,
+                  lam + d.ny + d.nx, b.status, tl.y, tl.z, lds);
   }
 }
 
-__global__ void batched_cfl_dt_kernel(const BlockDev* blocks, int nblocks, double cfl) {
+__global__ void batched_cfl_dt_kernel(BatchArgs b, int nblocks, double cfl) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < nblocks) {
-    const BlockDev& B = blocks[t];
-    B.dt[0] = cfl / __longlong_as_double((long long)B.lam[B.d.ny + B.d.nx]);
+    const BlockDev& B = b.blocks[t];
+    b.ws[B.oDt] = cfl / __longlong_as_double((long long)b.lam[B.oLam + B.d.ny + B.d.nx]);
   }
 }
 
@@ -124,8 +142,8 @@ hipError_t launch_batched_wave_max(const BatchArgs& a, hipStream_t st) {
 }
 
 
-hipError_t launch_batched_cfl_dt(const BlockDev* blocks, int nblocks, double cfl, hipStream_t st) {
-  hipLaunchKernelGGL(batched_cfl_dt_kernel, dim3((nblocks + 63) / 64), dim3(64), 0, st, blocks, nblocks, cfl);
+hipError_t launch_batched_cfl_dt(const BatchArgs& a, int nblocks, double cfl, hipStream_t st) {
+  hipLaunchKernelGGL(batched_cfl_dt_kernel, dim3((nblocks + 63) / 64), dim3(64), 0, st, a, nblocks, cfl);
   return hipGetLastError();
 }
 

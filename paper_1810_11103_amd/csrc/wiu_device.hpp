@@ -57,6 +57,25 @@ WIU_DEV int xcd_remap(int h, int total) {
 // which leaves an error of about one ulp at a fraction of the cost of the
 // correctly rounded division and square-root sequences.  Arguments here are
 // positive, finite and well scaled (densities, sums of squared weights).
+// Workgroup-uniform values read from global memory, moved into scalar
+// registers (the compiler cannot prove such loads uniform and would
+// otherwise hold them in vector registers).
+WIU_DEV int ufirst(int x) { return __builtin_amdgcn_readfirstlane(x); }
+WIU_DEV long long ufirst(long long x) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(x & 0xffffffffLL));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)x >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+WIU_DEV double ufirst(double x) { return __longlong_as_double(ufirst((long long)__double_as_longlong(x))); }
+
+WIU_DEV Dims ufirst(const Dims& g) {
+  Dims d;
+  d.nx = ufirst(g.nx); d.ny = ufirst(g.ny); d.bcx = ufirst(g.bcx); d.bcy = ufirst(g.bcy);
+  d.mpitch = ufirst(g.mpitch); d.mplane = ufirst(g.mplane); d.np = ufirst(g.np);
+  d.Lx = ufirst(g.Lx); d.Ly = ufirst(g.Ly);
+  return d;
+}
+
 WIU_DEV double rcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);

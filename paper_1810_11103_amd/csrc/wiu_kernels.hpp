@@ -36,15 +36,15 @@ struct SweepArgs {
   unsigned long long* nlam_eta;
 };
 
-// One block of a batched multi-block problem (device table entry).
+// One block of a batched multi-block problem (device table entry).  The
+// table holds element offsets; kernels add them to the base pointers they
+// receive as arguments (pointers stored in memory would be generic and cost
+// flat accesses).
 struct BlockDev {
   Dims d;
-  double* U;                 // the block's state (stage 3 writes it)
-  const double* M;           // its metrics (with tag)
-  double *U1, *U2, *Rxi;     // stage states and R^xi
-  unsigned long long* lam;   // lam_xi[ny], lam_eta[nx], cfl_max[1]
-  unsigned long long* lam2;  // second set: maxima of the first stage state
-  double* dt;                // its time step (device scalar)
+  long long oU, oM;              // state in U_all, metrics in M_all
+  long long oRxi, oU1, oU2, oDt; // R^xi / partial stage update, stage states, dt: in ws
+  long long oLam, oLam2;         // two sets of line maxima (lam_xi[ny], lam_eta[nx], cfl[1]) in lam
 };
 
 struct BatchArgs {
@@ -55,6 +55,10 @@ struct BatchArgs {
   double gamma, alpha, eps;
   int ppm;
   int* status;
+  double* U_all;             // bases of the offsets in BlockDev
+  const double* M_all;
+  double* ws;
+  unsigned long long* lam;
 };
 
 // Arguments of the adjoint sweeps and their per-line fix-up.
@@ -82,7 +86,7 @@ hipError_t launch_axpy(long long n, double a, const double* x, double b, const d
 hipError_t launch_sweep(int scheme, int dir, int variant, const SweepArgs& a, hipStream_t st);
 hipError_t launch_batched_sweep(int scheme, int dir, int variant, const BatchArgs& a, hipStream_t st);
 hipError_t launch_batched_wave_max(const BatchArgs& a, hipStream_t st);
-hipError_t launch_batched_cfl_dt(const BlockDev* blocks, int nblocks, double cfl, hipStream_t st);
+hipError_t launch_batched_cfl_dt(const BatchArgs& a, int nblocks, double cfl, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, long long n, hipStream_t st);
 void sweep_tile_shape(int dir, int variant, int& na, int& nb);
 int scheme_extra(int scheme);

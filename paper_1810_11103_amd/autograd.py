@@ -1,14 +1,21 @@
 """Differentiable time integration: a torch.autograd.Function over N TVD-RK3
 steps of the WENOIU residual at a fixed time step, with the hand-written
-adjoint of libwenoiu (wiu_rk3_step_vjp) and checkpointing.
+adjoint of libwenoiu (wiu_rk3_step_vjp).
 
-Forward keeps the state every `every` steps (checkpoints).  Backward walks
-the segments in reverse: it restores the segment's checkpoint, recomputes
-the segment forward while storing the two RK stage states of every step
-(wiu_rk3_step_stages), then applies the step adjoints in reverse order.
-Memory: N/every checkpoints plus 3 x every states for one segment.
-Metrics and the time step are held fixed (no gradient flows to them).
+Two ways to have the stage states at hand in the backward pass:
+  every = 0   forward stores (U_n, U1, U2) of every step (3 N states, no
+              recomputation) -- the choice whenever it fits in device memory;
+  every = k   forward keeps U_n every k steps (checkpoints); backward walks
+              the segments in reverse, recomputes each segment forward with
+              its stage states (wiu_rk3_step_stages), then applies the step
+              adjoints in reverse order (N/k checkpoints + 3 k states).
+rollout(every="auto") stores everything when 3 N states fit in the given
+fraction of free device memory, else checkpoints every ~sqrt(N/3) steps,
+which minimises N/k + 3k.  Metrics and the time step are held fixed (no
+gradient flows to them).
 """
+import math
+
 import torch
 
 from . import wenoiu
@@ -19,13 +26,18 @@ class RK3Rollout(torch.autograd.Function):
     def forward(ctx, U0, solver, nsteps, dt, every):
         U = U0.detach().clone().contiguous()
         solver.dt.fill_(float(dt))
-        ckpts = []
+        ckpts, stages = [], []
         for s in range(nsteps):
-            if s % every == 0:
-                ckpts.append(U.clone())
-            solver.rk3_step(U)
+            if every == 0:
+                Un, U1, U2 = U.clone(), torch.empty_like(U), torch.empty_like(U)
+                solver.rk3_step_stages(U, U1, U2)
+                stages.append((Un, U1, U2))
+            else:
+                if s % every == 0:
+                    ckpts.append(U.clone())
+                solver.rk3_step(U)
         ctx.solver, ctx.nsteps, ctx.dt, ctx.every = solver, nsteps, float(dt), every
-        ctx.ckpts = ckpts
+        ctx.ckpts, ctx.stages = ckpts, stages
         return U
 
     @staticmethod
@@ -33,26 +45,41 @@ class RK3Rollout(torch.autograd.Function):
         solver, nsteps, every = ctx.solver, ctx.nsteps, ctx.every
         solver.dt.fill_(ctx.dt)
         Ub = gU.detach().clone().contiguous()
-        nseg = len(ctx.ckpts)
-        for seg in reversed(range(nseg)):
-            s0 = seg * every
-            s1 = min(nsteps, s0 + every)
-            U = ctx.ckpts[seg].clone()
-            stages = []
-            for _ in range(s0, s1):
-                Un = U.clone()
-                U1, U2 = torch.empty_like(U), torch.empty_like(U)
-                solver.rk3_step_stages(U, U1, U2)
-                stages.append((Un, U1, U2))
-            for Un, U1, U2 in reversed(stages):
+        if every == 0:
+            for Un, U1, U2 in reversed(ctx.stages):
                 solver.rk3_step_vjp(Un, Ub, U1, U2, out=Ub)
-            del stages
-        ctx.ckpts = None
+        else:
+            for seg in reversed(range(len(ctx.ckpts))):
+                s0 = seg * every
+                s1 = min(nsteps, s0 + every)
+                U = ctx.ckpts[seg].clone()
+                stages = []
+                for _ in range(s0, s1):
+                    Un = U.clone()
+                    U1, U2 = torch.empty_like(U), torch.empty_like(U)
+                    solver.rk3_step_stages(U, U1, U2)
+                    stages.append((Un, U1, U2))
+                for Un, U1, U2 in reversed(stages):
+                    solver.rk3_step_vjp(Un, Ub, U1, U2, out=Ub)
+                del stages
+        ctx.ckpts = ctx.stages = None
         return Ub, None, None, None, None
 
 
-def rollout(U0, solver, nsteps, dt, every=20):
+def choose_every(nsteps, state_bytes, memory_fraction=0.5, free_bytes=None):
+    """0 (store every stage) if 3 nsteps states fit in memory_fraction of the
+    free device memory, else the checkpoint spacing round(sqrt(nsteps/3))."""
+    if free_bytes is None:
+        free_bytes = torch.cuda.mem_get_info()[0]
+    if 3 * nsteps * state_bytes <= memory_fraction * free_bytes:
+        return 0
+    return max(1, int(round(math.sqrt(nsteps / 3.0))))
+
+
+def rollout(U0, solver, nsteps, dt, every="auto", memory_fraction=0.5):
     """U(T) after `nsteps` RK3 steps of size dt from U0, differentiable in U0."""
+    if every == "auto":
+        every = choose_every(int(nsteps), U0.numel() * U0.element_size(), memory_fraction)
     return RK3Rollout.apply(U0, solver, int(nsteps), float(dt), int(every))
 
 

@@ -1,5 +1,7 @@
 // Adjoint (vector-Jacobian product) kernels of the residual, metrics held
-// fixed: given Gbar = adjoint of dU/dt, accumulate Ubar = (d rhs / dU)^T Gbar.
+// fixed: given Gbar = adjoint of dU/dt, form Ubar = (d rhs / dU)^T Gbar, scaled
+// and added to a linear combination of other arrays (AdjArgs), which is how the
+// RK3 step adjoint combines its stages without separate passes.
 //
 // Per direction a tile of items recomputes the forward quantities, reverses
 // the midpoint and nodal split fluxes (wiu_adjoint.hpp) and stores every
@@ -202,10 +204,19 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
     double g[4];
     gather(p, g);
     const long long o = DIR == 0 ? (long long)line * d.nx + p : (long long)p * d.nx + line;
+    const double coef = s.coef_c * (s.coef_dt ? s.coef_dt[0] : 1.0);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const long long e = c * d.np + o;
-      s.Ubar[e] = s.accumulate ? s.Ubar[e] + g[c] : g[c];
+      double v = coef * g[c];
+      if (s.accumulate) {
+        v += s.Ubar[e];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          if (s.base_x[k]) v += s.base_a[k] * s.base_x[k][e];
+      }
+      s.Ubar[e] = v;
     }
   }
   if (ta < 2 * NGHOST_ADJ) {
@@ -280,21 +291,10 @@ __global__ void __launch_bounds__(256) adj_fixup_kernel(AdjArgs s, int dir, int 
     const double* Mk = s.M + (dir == 0 ? 0 : 2) * d.mplane;
     wave_speed_vjp(Q, Mk[mo], Mk[d.mplane + mo], s.gamma, s.alpha * lb, acc);
   }
+  const double coef = s.coef_c * (s.coef_dt ? s.coef_dt[0] : 1.0);
 #pragma unroll
-  for (int c = 0; c < 4; ++c) s.Ubar[c * d.np + o] += acc[c];
+  for (int c = 0; c < 4; ++c) s.Ubar[c * d.np + o] += coef * acc[c];
   if (lane == 0 && ks >= n_al && lb != 0.0) atomicOr(s.status, ST_ARGMAX);
-}
-
-// out = a x + b (y + dt z), elementwise over n values (RK3 adjoint stages).
-__global__ void axpy_kernel(long long n, double a, const double* x, double b, const double* y, const double* dt,
-                            const double* z, double* out) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) {
-    const double xv = x ? x[t] : 0.0;
-    const double yv = y ? y[t] : 0.0;
-    const double zv = z ? dt[0] * z[t] : 0.0;
-    out[t] = a * xv + b * (yv + zv);
-  }
 }
 
 template <int SC, int DIR>
@@ -333,12 +333,6 @@ hipError_t launch_adj_sweep(int scheme, int dir, const AdjArgs& a, hipStream_t s
   if (e != hipSuccess) return e;
   const int nlines = dir == 0 ? a.d.ny : a.d.nx;
   hipLaunchKernelGGL(adj_fixup_kernel, dim3((nlines + 3) / 4), dim3(256), 0, st, a, dir, nseg);
-  return hipGetLastError();
-}
-
-hipError_t launch_axpy(long long n, double a, const double* x, double b, const double* y, const double* dt,
-                       const double* z, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, x, b, y, dt, z, out);
   return hipGetLastError();
 }
 

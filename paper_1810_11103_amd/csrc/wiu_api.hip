@@ -45,11 +45,11 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 //   HDR          lam_xi[ny], lam_eta[nx], cfl_max[1]   (uint64 bit patterns)
 //   lam2         a second lam_xi, lam_eta, cfl_max set (maxima of an RK stage state)
 //   off_scratch  R^xi[4 np], U1[4 np], U2[4 np]  -- or the metric band temp
-//   then the adjoint region: A, Ubar2, Ubar1, acc (4 planes each), eigenvalue
+//   then the adjoint region: Ubar2, Ubar1 (4 planes each), eigenvalue
 //   partials [max lines x segments] (double) and first maximal nodes (int),
 //   off-line contributions [max lines][2][6][4]
 struct WsLayout {
-  size_t lam, lam2, scratch, rxi, u1, u2, qa, ub2, ub1, acc, lpart, apart, ghost, total;
+  size_t lam, lam2, scratch, rxi, u1, u2, ub2, ub1, lpart, apart, ghost, total;
 };
 
 WsLayout layout(const wiu_grid* g) {
@@ -66,12 +66,10 @@ WsLayout layout(const wiu_grid* g) {
   L.u2 = L.u1 + plane4;
   const size_t end_rk = L.u2 + plane4;
   const size_t end_met = L.scratch + align_up(band * 8);
-  L.qa = end_rk > end_met ? end_rk : end_met;
-  L.ub2 = L.qa + plane4;
+  L.ub2 = end_rk > end_met ? end_rk : end_met;
   L.ub1 = L.ub2 + plane4;
-  L.acc = L.ub1 + plane4;
   const size_t lp_xi = (size_t)g->ny * adj_nseg(0, g->nx), lp_eta = (size_t)g->nx * adj_nseg(1, g->ny);
-  L.lpart = L.acc + plane4;
+  L.lpart = L.ub1 + plane4;
   L.apart = L.lpart + align_up((lp_xi > lp_eta ? lp_xi : lp_eta) * 8);
   L.ghost = L.apart + align_up((lp_xi > lp_eta ? lp_xi : lp_eta) * 4);
   const size_t nl = (size_t)(g->nx > g->ny ? g->nx : g->ny);
@@ -113,7 +111,7 @@ struct Ws {
   unsigned long long *lx, *le, *cfl;
   unsigned long long *lx2, *le2;  // maxima of an RK stage state, from the previous stage
   double *rxi, *u1, *u2, *band;
-  double *qa, *ub2, *ub1, *acc, *lpart, *ghost;
+  double *ub2, *ub1, *lpart, *ghost;
   int* apart;
 };
 
@@ -131,25 +129,33 @@ Ws carve(const wiu_grid* g, void* ws) {
   w.u1 = (double*)(b + L.u1);
   w.u2 = (double*)(b + L.u2);
   w.band = (double*)(b + L.scratch);
-  w.qa = (double*)(b + L.qa);
   w.ub2 = (double*)(b + L.ub2);
   w.ub1 = (double*)(b + L.ub1);
-  w.acc = (double*)(b + L.acc);
   w.lpart = (double*)(b + L.lpart);
   w.apart = (int*)(b + L.apart);
   w.ghost = (double*)(b + L.ghost);
   return w;
 }
 
-// Ubar = (d rhs / dU)^T Gbar at state U.
+// Output of a residual adjoint: Ubar = sum_k a[k] x[k] + c dt (d rhs / dU)^T Gbar
+// (dt the device scalar if given, else 1; null x[k] skipped).
+struct VjpOut {
+  double c = 1.0;
+  const double* dt = nullptr;
+  const double* x[3] = {nullptr, nullptr, nullptr};
+  double a[3] = {0.0, 0.0, 0.0};
+};
+
 int residual_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M,
-                 const double* Gbar, double* Ubar, const Ws& w, hipStream_t st) {
+                 const double* Gbar, double* Ubar, const Ws& w, hipStream_t st, const VjpOut& vo = VjpOut()) {
   Dims d = dims(g);
   if (launch_wave_max(d, U, M, p->gamma, w.lx, w.le, w.cfl, w.status, st) != hipSuccess) return WIU_EHIP;
   AdjArgs a;
   a.d = d; a.U = U; a.M = M; a.Gbar = Gbar; a.Ubar = Ubar; a.lam_xi = w.lx; a.lam_eta = w.le;
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
   a.lam_part = w.lpart; a.arg_part = w.apart; a.ghost = w.ghost; a.status = w.status;
+  a.coef_c = vo.c; a.coef_dt = vo.dt;
+  for (int k = 0; k < 3; ++k) { a.base_x[k] = vo.x[k]; a.base_a[k] = vo.a[k]; }
   a.accumulate = 0;
   if (launch_adj_sweep(scheme, 0, a, st) != hipSuccess) return WIU_EHIP;
   a.accumulate = 1;
@@ -329,7 +335,6 @@ int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const d
   if ((U1 == nullptr) != (U2 == nullptr)) return WIU_EINVAL;
   Ws w = carve(g, ws);
   hipStream_t st = (hipStream_t)stream;
-  const long long n = 4LL * g->nx * g->ny;
   int rc;
   if (!U1) {  // recompute the stage states
     Maxima m1, m2;
@@ -342,17 +347,23 @@ int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const d
     U1 = w.u1;
     U2 = w.u2;
   }
-  // U' = 1/3 U + 2/3 (U2 + dt L(U2))
-  if ((rc = residual_vjp(g, scheme, p, U2, M, Ubar_np1, w.qa, w, st))) return rc;
-  if (launch_axpy(n, 0.0, nullptr, 2.0 / 3.0, Ubar_np1, dt_dev, w.qa, w.ub2, st) != hipSuccess) return WIU_EHIP;
-  if (launch_axpy(n, 1.0 / 3.0, Ubar_np1, 0.0, nullptr, dt_dev, nullptr, w.acc, st) != hipSuccess) return WIU_EHIP;
-  // U2 = 3/4 U + 1/4 (U1 + dt L(U1))
-  if ((rc = residual_vjp(g, scheme, p, U1, M, w.ub2, w.qa, w, st))) return rc;
-  if (launch_axpy(n, 0.0, nullptr, 0.25, w.ub2, dt_dev, w.qa, w.ub1, st) != hipSuccess) return WIU_EHIP;
-  if (launch_axpy(n, 1.0, w.acc, 0.75, w.ub2, dt_dev, nullptr, w.acc, st) != hipSuccess) return WIU_EHIP;
-  // U1 = U + dt L(U)
-  if ((rc = residual_vjp(g, scheme, p, U_n, M, w.ub1, w.qa, w, st))) return rc;
-  return launch_axpy(n, 1.0, w.acc, 1.0, w.ub1, dt_dev, w.qa, Ubar_n, st) == hipSuccess ? WIU_OK : WIU_EHIP;
+  // U' = 1/3 U + 2/3 (U2 + dt L(U2)):  Ubar2 = 2/3 Ubar' + 2/3 dt L'(U2)^T Ubar'
+  VjpOut o2;
+  o2.c = 2.0 / 3.0; o2.dt = dt_dev; o2.x[0] = Ubar_np1; o2.a[0] = 2.0 / 3.0;
+  if ((rc = residual_vjp(g, scheme, p, U2, M, Ubar_np1, w.ub2, w, st, o2))) return rc;
+  // U2 = 3/4 U + 1/4 (U1 + dt L(U1)):  Ubar1 = 1/4 Ubar2 + 1/4 dt L'(U1)^T Ubar2
+  VjpOut o1;
+  o1.c = 0.25; o1.dt = dt_dev; o1.x[0] = w.ub2; o1.a[0] = 0.25;
+  if ((rc = residual_vjp(g, scheme, p, U1, M, w.ub2, w.ub1, w, st, o1))) return rc;
+  // U1 = U + dt L(U), and the direct U terms of U' and U2:
+  //   Ubar_n = 1/3 Ubar' + 3/4 Ubar2 + Ubar1 + dt L'(U)^T Ubar1
+  // (elementwise in Ubar', so Ubar_n may alias it)
+  VjpOut o0;
+  o0.c = 1.0; o0.dt = dt_dev;
+  o0.x[0] = Ubar_np1; o0.a[0] = 1.0 / 3.0;
+  o0.x[1] = w.ub2; o0.a[1] = 0.75;
+  o0.x[2] = w.ub1; o0.a[2] = 1.0;
+  return residual_vjp(g, scheme, p, U_n, M, w.ub1, Ubar_n, w, st, o0);
 }
 
 int wiu_status(void* ws, wiu_stream_t stream, int* status, int clear) {

@@ -72,7 +72,14 @@ struct AdjArgs {
   const unsigned long long* lam_eta;
   double gamma, alpha, eps;
   int ppm;
-  int accumulate;                       // 0: write Ubar, 1: add to it
+  // Output: contributions are scaled by coef = coef_c * (*coef_dt, or 1);
+  // the first pass (accumulate 0) writes Ubar = sum_k base_a[k] base_x[k] +
+  // coef g (null base_x[k] skipped), later passes add coef g.
+  int accumulate;
+  double coef_c;
+  const double* coef_dt;
+  const double* base_x[3];
+  double base_a[3];
   double* lam_part;                     // [lines][segments] eigenvalue adjoints
   int* arg_part;                        // [lines][segments] first maximal node per tile
   int* status;
@@ -81,8 +88,6 @@ struct AdjArgs {
 
 hipError_t launch_adj_sweep(int scheme, int dir, const AdjArgs& a, hipStream_t st);
 int adj_nseg(int dir, int n_al);
-hipError_t launch_axpy(long long n, double a, const double* x, double b, const double* y, const double* dt,
-                       const double* z, double* out, hipStream_t st);
 hipError_t launch_sweep(int scheme, int dir, int variant, const SweepArgs& a, hipStream_t st);
 hipError_t launch_batched_sweep(int scheme, int dir, int variant, const BatchArgs& a, hipStream_t st);
 hipError_t launch_batched_wave_max(const BatchArgs& a, hipStream_t st);

@@ -36,12 +36,13 @@ def _setup(wenoiu, torch, n=48, scheme="5-2MP", seed=9):
     return g, sol, x, y
 
 
-def test_rollout_forward_equals_plain_steps(mods):
+@pytest.mark.parametrize("every", [0, 10])
+def test_rollout_forward_equals_plain_steps(mods, every):
     torch, wenoiu, AG = mods
     g, sol, x, y = _setup(wenoiu, torch)
     U0 = AG.vortex_state_torch(x, y, torch.tensor(5 / (2 * math.pi), dtype=torch.float64, device="cuda"))
     dt = 0.02
-    out = AG.rollout(U0, sol, 25, dt, every=10)
+    out = AG.rollout(U0, sol, 25, dt, every=every)
     U = U0.clone()
     sol.dt.fill_(dt)
     for _ in range(25):
@@ -71,6 +72,24 @@ def test_rollout_gradient_matches_oracle_adjoint_chain(orc, mods):
     got = Ud.grad.cpu().numpy()
     for c in range(4):
         assert np.abs(got[c] - ub[c]).max() <= 1e-9 * np.abs(ub[c]).max(), c
+
+
+def test_stored_stages_and_checkpoints_give_identical_gradients(mods):
+    """Storing every stage (no recomputation) and checkpointing (recomputed
+    segments of several lengths) run the same kernels on the same states:
+    the gradients agree bitwise."""
+    torch, wenoiu, AG = mods
+    g, sol, x, y = _setup(wenoiu, torch, n=40)
+    U0 = torch.as_tensor(W.vortex_periodic_state(g) + 0.02 * W.random_smooth_state(g, seed=3, amp=1.0)).cuda()
+    Wt = torch.as_tensor(np.random.default_rng(5).standard_normal(U0.shape)).cuda()
+    grads = []
+    for every in (0, 1, 3, 7):
+        Ud = U0.clone().requires_grad_(True)
+        AG.rollout(Ud, sol, 10, 0.02, every=every).backward(Wt)
+        grads.append(Ud.grad.clone())
+    for gr in grads[1:]:
+        assert torch.equal(gr, grads[0])
+    assert sol.status() == 0
 
 
 def test_gradient_in_vortex_strength_matches_central_differences(mods):

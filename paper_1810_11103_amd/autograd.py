@@ -26,12 +26,13 @@ class RK3Rollout(torch.autograd.Function):
     def forward(ctx, U0, solver, nsteps, dt, every):
         U = U0.detach().clone().contiguous()
         solver.dt.fill_(float(dt))
-        ckpts, stages = [], []
+        ckpts, stages = [], None
+        if every == 0:  # one allocation for all (U_n, U1, U2)
+            stages = torch.empty((nsteps, 3) + tuple(U.shape), dtype=U.dtype, device=U.device)
         for s in range(nsteps):
             if every == 0:
-                Un, U1, U2 = U.clone(), torch.empty_like(U), torch.empty_like(U)
-                solver.rk3_step_stages(U, U1, U2)
-                stages.append((Un, U1, U2))
+                stages[s, 0].copy_(U)
+                solver.rk3_step_stages(U, stages[s, 1], stages[s, 2])
             else:
                 if s % every == 0:
                     ckpts.append(U.clone())
@@ -46,8 +47,9 @@ class RK3Rollout(torch.autograd.Function):
         solver.dt.fill_(ctx.dt)
         Ub = gU.detach().clone().contiguous()
         if every == 0:
-            for Un, U1, U2 in reversed(ctx.stages):
-                solver.rk3_step_vjp(Un, Ub, U1, U2, out=Ub)
+            for s in reversed(range(nsteps)):
+                st = ctx.stages[s]
+                solver.rk3_step_vjp(st[0], Ub, st[1], st[2], out=Ub)
         else:
             for seg in reversed(range(len(ctx.ckpts))):
                 s0 = seg * every

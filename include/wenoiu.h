@@ -7,9 +7,10 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - All array arguments are DEVICE pointers to fp64 memory owned by the
- *    caller; the library never frees or keeps them.  No entry point allocates
- *    device memory: scratch comes from a caller-provided workspace `ws` of at
- *    least wiu_workspace_bytes() bytes (256-byte aligned).
+ *    caller; the library never frees them.  Apart from wiu_batched_plan (which
+ *    allocates the plan's tables and scratch, freed by wiu_plan_destroy), no
+ *    entry point allocates device memory: scratch comes from a caller-provided
+ *    workspace `ws` of at least wiu_workspace_bytes() bytes (256-byte aligned).
  *  - Layout is structure-of-arrays, row-major, the xi index i fastest, no
  *    padding.  A conservative state U is [4][ny][nx] = (rho, rho u, rho v, e)
  *    with e = p/(gamma-1) + rho (u^2+v^2)/2 (Sec. 2.1).  Node coordinates
@@ -163,8 +164,10 @@ const char* wiu_strerror(int code);
 /* ---- Batched multi-block stepping ------------------------------------------
  * Many independent grid blocks of uneven sizes (the multi-block grids of
  * the paper's motivation, Sec. 1) advanced together: per RK stage one launch
- * of each kernel kind walks a device table of all blocks' tiles (persistent,
- * XCD-aware), and the twelve launches of a step can be replayed as one
+ * of each sweep covers the tiles of all blocks (one workgroup per entry of a
+ * device tile table, in XCD-aware order), one wave-maximum pass per step
+ * serves the first stage and the eta sweeps of stages 1 and 2 accumulate the
+ * next stage's line maxima; the launches of a step can be replayed as one
  * captured HIP graph.  No interface coupling between blocks is applied: each
  * block uses its own boundary rule.
  *

@@ -27,6 +27,8 @@ template <int DIR, int NA, int NB> struct AdjLds {
   double cq[24][NA * NB];     // contributions [m*4 + c][item], m: position k-2+m
   double lb[NA * NB];         // line-eigenvalue adjoint per item
   int ka[NA * NB];            // k if node k attains the line maximum, else INT_MAX
+  double xlb[NA];             // eta tiles folding the xi fix-up: per output row, the
+  int xks[NA];                //   row's eigenvalue adjoint and first maximal node
   static WIU_DEV int si(int tb, int ta) { return DIR == 0 ? tb * NA + ta : ta * NB + tb; }
   static WIU_DEV int qi(int tb, int pos) { return DIR == 0 ? tb * NQ + pos : pos * NB + tb; }
   static WIU_DEV int ri(int tb, int pos) { return DIR == 0 ? tb * NR + pos : pos * NB + tb; }
@@ -170,6 +172,21 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
   }
   L.lb[slot] = owner ? lamb : 0.0;
   L.ka[slot] = kmax;
+  // eta tiles folding the xi fix-up: reduce each output row's xi partials
+  // (fixed order over the row's segments)
+  const bool xfold = DIR == 1 && s.x_lam_part != nullptr;
+  if (xfold && tb == 0 && ta < out) {
+    const int row = o0 + ta;
+    double sum = 0.0;
+    int kf = INT_MAX;
+    for (int t = 0; t < s.x_nseg; ++t) {
+      sum += s.x_lam_part[(long long)row * s.x_nseg + t];
+      kf = min(kf, s.x_arg_part[(long long)row * s.x_nseg + t]);
+    }
+    L.xlb[ta] = sum;
+    L.xks[ta] = kf;
+    if (kf >= d.nx && sum != 0.0) atomicOr(s.status, ST_ARGMAX);
+  }
   __syncthreads();
 
   if (!live) return;
@@ -205,6 +222,29 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
     gather(p, g);
     const long long o = DIR == 0 ? (long long)line * d.nx + p : (long long)p * d.nx + line;
     const double coef = s.coef_c * (s.coef_dt ? s.coef_dt[0] : 1.0);
+    if (xfold) {
+      // xi fix-up of node (line, p) of row p: off-line contributions that the
+      // boundary rule maps here (only the six columns at each end), then the
+      // row eigenvalue's adjoint if this is the row's first maximal node
+      constexpr int NG = 2 * NGHOST_ADJ;
+      if (line < NGHOST_ADJ || line >= d.nx - NGHOST_ADJ) {
+        for (int gi = 0; gi < NG; ++gi) {
+          const int pg = gi < NGHOST_ADJ ? -1 - gi : d.nx + (gi - NGHOST_ADJ);
+          if (bc_index(pg, d.nx, d.bcx) != line) continue;
+          const double* gb =
+              s.x_ghost + (((long long)p * 2 + (gi < NGHOST_ADJ ? 0 : 1)) * NGHOST_ADJ + gi % NGHOST_ADJ) * 4;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) g[c] += gb[c];
+        }
+      }
+      const double xl = L.xlb[ta];
+      if (L.xks[ta] == line && xl != 0.0) {
+        const int pq = LT::qi(tb, p - (o0 + LO - 2));
+        const double Q[4] = {L.sq[0][pq], L.sq[1][pq], L.sq[2][pq], L.sq[3][pq]};
+        const long long mo = (long long)(p + GHOST) * d.mpitch + (line + GHOST);
+        wave_speed_vjp(Q, s.M[mo], s.M[d.mplane + mo], s.gamma, s.alpha * xl, g);
+      }
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const long long e = c * d.np + o;
@@ -317,7 +357,7 @@ int adj_nseg(int dir, int n_al) {
   return (n_al + OUT - 1) / OUT;
 }
 
-hipError_t launch_adj_sweep(int scheme, int dir, const AdjArgs& a, hipStream_t st) {
+hipError_t launch_adj_sweep(int scheme, int dir, const AdjArgs& a, hipStream_t st, bool fixup) {
   int nseg = 0;
   hipError_t e;
   switch (scheme * 2 + dir) {
@@ -330,7 +370,7 @@ hipError_t launch_adj_sweep(int scheme, int dir, const AdjArgs& a, hipStream_t s
     case 6: e = launch_adj_t<3, 0>(a, st, nseg); break;
     default: e = launch_adj_t<3, 1>(a, st, nseg); break;
   }
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !fixup) return e;
   const int nlines = dir == 0 ? a.d.ny : a.d.nx;
   hipLaunchKernelGGL(adj_fixup_kernel, dim3((nlines + 3) / 4), dim3(256), 0, st, a, dir, nseg);
   return hipGetLastError();

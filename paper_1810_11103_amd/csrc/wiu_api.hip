@@ -49,7 +49,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 //   partials [max lines x segments] (double) and first maximal nodes (int),
 //   off-line contributions [max lines][2][6][4]
 struct WsLayout {
-  size_t lam, lam2, scratch, rxi, u1, u2, ub2, ub1, lpart, apart, ghost, total;
+  size_t lam, lam2, scratch, rxi, u1, u2, ub2, ub1, lpx, lpe, apx, ape, ghx, ghe, total;
 };
 
 WsLayout layout(const wiu_grid* g) {
@@ -69,11 +69,13 @@ WsLayout layout(const wiu_grid* g) {
   L.ub2 = end_rk > end_met ? end_rk : end_met;
   L.ub1 = L.ub2 + plane4;
   const size_t lp_xi = (size_t)g->ny * adj_nseg(0, g->nx), lp_eta = (size_t)g->nx * adj_nseg(1, g->ny);
-  L.lpart = L.ub1 + plane4;
-  L.apart = L.lpart + align_up((lp_xi > lp_eta ? lp_xi : lp_eta) * 8);
-  L.ghost = L.apart + align_up((lp_xi > lp_eta ? lp_xi : lp_eta) * 4);
-  const size_t nl = (size_t)(g->nx > g->ny ? g->nx : g->ny);
-  L.total = L.ghost + align_up(nl * 2 * 6 * 4 * 8);
+  L.lpx = L.ub1 + plane4;
+  L.lpe = L.lpx + align_up(lp_xi * 8);
+  L.apx = L.lpe + align_up(lp_eta * 8);
+  L.ape = L.apx + align_up(lp_xi * 4);
+  L.ghx = L.ape + align_up(lp_eta * 4);
+  L.ghe = L.ghx + align_up((size_t)g->ny * 2 * 6 * 4 * 8);
+  L.total = L.ghe + align_up((size_t)g->nx * 2 * 6 * 4 * 8);
   return L;
 }
 
@@ -111,8 +113,8 @@ struct Ws {
   unsigned long long *lx, *le, *cfl;
   unsigned long long *lx2, *le2;  // maxima of an RK stage state, from the previous stage
   double *rxi, *u1, *u2, *band;
-  double *ub2, *ub1, *lpart, *ghost;
-  int* apart;
+  double *ub2, *ub1, *lpx, *lpe, *ghx, *ghe;  // adjoint: per direction, eigenvalue partials and ghosts
+  int *apx, *ape;                            //   and first maximal nodes
 };
 
 Ws carve(const wiu_grid* g, void* ws) {
@@ -131,9 +133,12 @@ Ws carve(const wiu_grid* g, void* ws) {
   w.band = (double*)(b + L.scratch);
   w.ub2 = (double*)(b + L.ub2);
   w.ub1 = (double*)(b + L.ub1);
-  w.lpart = (double*)(b + L.lpart);
-  w.apart = (int*)(b + L.apart);
-  w.ghost = (double*)(b + L.ghost);
+  w.lpx = (double*)(b + L.lpx);
+  w.lpe = (double*)(b + L.lpe);
+  w.apx = (int*)(b + L.apx);
+  w.ape = (int*)(b + L.ape);
+  w.ghx = (double*)(b + L.ghx);
+  w.ghe = (double*)(b + L.ghe);
   return w;
 }
 
@@ -153,13 +158,19 @@ int residual_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const doubl
   AdjArgs a;
   a.d = d; a.U = U; a.M = M; a.Gbar = Gbar; a.Ubar = Ubar; a.lam_xi = w.lx; a.lam_eta = w.le;
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
-  a.lam_part = w.lpart; a.arg_part = w.apart; a.ghost = w.ghost; a.status = w.status;
+  a.status = w.status;
   a.coef_c = vo.c; a.coef_dt = vo.dt;
   for (int k = 0; k < 3; ++k) { a.base_x[k] = vo.x[k]; a.base_a[k] = vo.a[k]; }
+  // xi sweep: writes Ubar, its eigenvalue partials and ghost contributions
+  a.lam_part = w.lpx; a.arg_part = w.apx; a.ghost = w.ghx;
+  a.x_lam_part = nullptr; a.x_arg_part = nullptr; a.x_ghost = nullptr; a.x_nseg = 0;
   a.accumulate = 0;
-  if (launch_adj_sweep(scheme, 0, a, st) != hipSuccess) return WIU_EHIP;
+  if (launch_adj_sweep(scheme, 0, a, st, false) != hipSuccess) return WIU_EHIP;
+  // eta sweep: adds its part and, node by node, the xi fix-up; then the eta fix-up
+  a.lam_part = w.lpe; a.arg_part = w.ape; a.ghost = w.ghe;
+  a.x_lam_part = w.lpx; a.x_arg_part = w.apx; a.x_ghost = w.ghx; a.x_nseg = adj_nseg(0, g->nx);
   a.accumulate = 1;
-  return launch_adj_sweep(scheme, 1, a, st) == hipSuccess ? WIU_OK : WIU_EHIP;
+  return launch_adj_sweep(scheme, 1, a, st, true) == hipSuccess ? WIU_OK : WIU_EHIP;
 }
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? WIU_OK : WIU_EHIP; }

@@ -84,9 +84,15 @@ struct AdjArgs {
   int* arg_part;                        // [lines][segments] first maximal node per tile
   int* status;
   double* ghost;                        // [lines][2][6][4] off-line contributions
+  // eta sweep only, when set: the xi sweep's partials and ghosts, folded
+  // into the eta output (the xi direction's per-line fix-up, done in place)
+  const double* x_lam_part;
+  const int* x_arg_part;
+  const double* x_ghost;
+  int x_nseg;
 };
 
-hipError_t launch_adj_sweep(int scheme, int dir, const AdjArgs& a, hipStream_t st);
+hipError_t launch_adj_sweep(int scheme, int dir, const AdjArgs& a, hipStream_t st, bool fixup);
 int adj_nseg(int dir, int n_al);
 hipError_t launch_sweep(int scheme, int dir, int variant, const SweepArgs& a, hipStream_t st);
 hipError_t launch_batched_sweep(int scheme, int dir, int variant, const BatchArgs& a, hipStream_t st);

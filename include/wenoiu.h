@@ -140,17 +140,25 @@ int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double*
 int wiu_rhs_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M,
                 const double* Gbar, double* Ubar, void* ws, wiu_stream_t stream);
 
+/* Size in bytes of a step record: the line maxima (Sec. 2.3) of the three
+ * stage states of one RK3 step, kept by the caller between a forward step
+ * and its adjoint so the adjoint need not recompute them (device memory,
+ * 8-byte aligned, opaque). */
+size_t wiu_step_record_bytes(const wiu_grid* g);
+
 /* wiu_rk3_step that also stores the two intermediate stage states U1, U2
- * (caller-owned [4][ny][nx]) for a later wiu_rk3_step_vjp. */
+ * (caller-owned [4][ny][nx]) for a later wiu_rk3_step_vjp, and, when `rec`
+ * is not NULL, the step record of U, U1, U2. */
 int wiu_rk3_step_stages(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
-                        const double* dt_dev, double* U1, double* U2, void* ws, wiu_stream_t stream);
+                        const double* dt_dev, double* U1, double* U2, void* rec, void* ws, wiu_stream_t stream);
 
 /* Ubar_n = (d U^{n+1} / d U^n)^T Ubar_np1 for one RK3 step of size *dt_dev
- * from U_n.  U1, U2: the stored stage states, or both NULL to recompute them.
- * Ubar_n may alias Ubar_np1. */
+ * from U_n.  U1, U2: the stored stage states, or both NULL to recompute them;
+ * rec: the step record written with them, or NULL (requires U1, U2 when set;
+ * WIU_EINVAL otherwise).  Ubar_n may alias Ubar_np1. */
 int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U_n, const double* U1,
-                     const double* U2, const double* M, const double* dt_dev, const double* Ubar_np1,
-                     double* Ubar_n, void* ws, wiu_stream_t stream);
+                     const double* U2, const void* rec, const double* M, const double* dt_dev,
+                     const double* Ubar_np1, double* Ubar_n, void* ws, wiu_stream_t stream);
 
 /* Synchronise `stream`, return the latched status bits of `ws` in *status
  * and clear them when `clear` is non-zero. */

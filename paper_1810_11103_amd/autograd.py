@@ -26,19 +26,20 @@ class RK3Rollout(torch.autograd.Function):
     def forward(ctx, U0, solver, nsteps, dt, every):
         U = U0.detach().clone().contiguous()
         solver.dt.fill_(float(dt))
-        ckpts, stages = [], None
-        if every == 0:  # one allocation for all (U_n, U1, U2)
+        ckpts, stages, recs = [], None, None
+        if every == 0:  # one allocation for all (U_n, U1, U2), and their step records
             stages = torch.empty((nsteps, 3) + tuple(U.shape), dtype=U.dtype, device=U.device)
+            recs = solver.step_record(nsteps)
         for s in range(nsteps):
             if every == 0:
                 stages[s, 0].copy_(U)
-                solver.rk3_step_stages(U, stages[s, 1], stages[s, 2])
+                solver.rk3_step_stages(U, stages[s, 1], stages[s, 2], rec=recs[s])
             else:
                 if s % every == 0:
                     ckpts.append(U.clone())
                 solver.rk3_step(U)
         ctx.solver, ctx.nsteps, ctx.dt, ctx.every = solver, nsteps, float(dt), every
-        ctx.ckpts, ctx.stages = ckpts, stages
+        ctx.ckpts, ctx.stages, ctx.recs = ckpts, stages, recs
         return U
 
     @staticmethod
@@ -49,23 +50,53 @@ class RK3Rollout(torch.autograd.Function):
         if every == 0:
             for s in reversed(range(nsteps)):
                 st = ctx.stages[s]
-                solver.rk3_step_vjp(st[0], Ub, st[1], st[2], out=Ub)
+                solver.rk3_step_vjp(st[0], Ub, st[1], st[2], out=Ub, rec=ctx.recs[s])
         else:
-            for seg in reversed(range(len(ctx.ckpts))):
-                s0 = seg * every
-                s1 = min(nsteps, s0 + every)
-                U = ctx.ckpts[seg].clone()
-                stages = []
-                for _ in range(s0, s1):
-                    Un = U.clone()
-                    U1, U2 = torch.empty_like(U), torch.empty_like(U)
-                    solver.rk3_step_stages(U, U1, U2)
-                    stages.append((Un, U1, U2))
-                for Un, U1, U2 in reversed(stages):
-                    solver.rk3_step_vjp(Un, Ub, U1, U2, out=Ub)
-                del stages
-        ctx.ckpts = ctx.stages = None
+            _checkpointed_backward(ctx, Ub)
+        ctx.ckpts = ctx.stages = ctx.recs = None
         return Ub, None, None, None, None
+
+
+def _checkpointed_backward(ctx, Ub):
+    """Segments in reverse order; the forward recomputation of segment k-1
+    runs on a second stream (its own workspace, one of two stage buffers)
+    while the step adjoints of segment k run on the caller's stream."""
+    solver, nsteps, every, ckpts = ctx.solver, ctx.nsteps, ctx.every, ctx.ckpts
+    nseg = len(ckpts)
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream(device=Ub.device)  # default priority
+    ws2 = solver.side_workspace()
+    bufs = torch.empty((2, every, 3) + tuple(Ub.shape), dtype=Ub.dtype, device=Ub.device)
+    recs = solver.step_record(2 * every).view(2, every, -1)
+    work = torch.empty((2,) + tuple(Ub.shape), dtype=Ub.dtype, device=Ub.device)
+    ready = [torch.cuda.Event() for _ in range(nseg)]
+    freed = [torch.cuda.Event() for _ in range(nseg)]
+    side.wait_stream(main)  # dt, checkpoints and buffers are ready
+
+    def recompute(seg):
+        with torch.cuda.stream(side):
+            if seg + 2 < nseg:
+                side.wait_event(freed[seg + 2])  # its buffer set was last used by segment seg+2
+            B, U = bufs[seg % 2], work[seg % 2]
+            U.copy_(ckpts[seg])
+            for i in range(min(nsteps, (seg + 1) * every) - seg * every):
+                B[i, 0].copy_(U)
+                solver.rk3_step_stages(U, B[i, 1], B[i, 2], ws=ws2, rec=recs[seg % 2, i])
+            ready[seg].record(side)
+
+    recompute(nseg - 1)
+    for seg in reversed(range(nseg)):
+        if seg > 0:
+            recompute(seg - 1)
+        main.wait_event(ready[seg])
+        B, R = bufs[seg % 2], recs[seg % 2]
+        for i in reversed(range(min(nsteps, (seg + 1) * every) - seg * every)):
+            solver.rk3_step_vjp(B[i, 0], Ub, B[i, 1], B[i, 2], out=Ub, rec=R[i])
+        freed[seg].record(main)
+    main.wait_stream(side)
+    bufs.record_stream(side)
+    work.record_stream(side)
+    recs.record_stream(side)
 
 
 def choose_every(nsteps, state_bytes, memory_fraction=0.5, free_bytes=None):

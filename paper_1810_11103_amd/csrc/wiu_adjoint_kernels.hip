@@ -337,14 +337,24 @@ __global__ void __launch_bounds__(256) adj_fixup_kernel(AdjArgs s, int dir, int 
   if (lane == 0 && ks >= n_al && lb != 0.0) atomicOr(s.status, ST_ARGMAX);
 }
 
-template <int SC, int DIR>
-hipError_t launch_adj_t(const AdjArgs& a, hipStream_t st, int& nseg) {
-  constexpr int NA = DIR == 0 ? 128 : 64;
-  constexpr int NB = DIR == 0 ? 1 : 2;
+// Adjoint tile length along the line: of two compiled shapes per direction,
+// the one that recomputes the fewest items for this line length (each tile
+// yields NA - 6 outputs).  Results depend on the choice only in the
+// association of the eigenvalue-adjoint sums.
+//   xi : 128 x 1 or 64 x 2;  eta: 128 x 2 or 64 x 4 (lines x items per workgroup)
+int adj_tile_na(int dir, int n_al) {
+  (void)dir;
+  const long long i128 = (long long)((n_al + 121) / 122) * 128, i64 = (long long)((n_al + 57) / 58) * 64;
+  return i64 < i128 ? 64 : 128;
+}
+
+template <int SC, int DIR, int NA>
+hipError_t launch_adj_t(const AdjArgs& a, hipStream_t st) {
+  constexpr int NB = DIR == 0 ? 128 / NA : 256 / NA;
   constexpr int OUT = NA - 6;
   const int n_al = DIR == 0 ? a.d.nx : a.d.ny;
   const int n_ac = DIR == 0 ? a.d.ny : a.d.nx;
-  nseg = (n_al + OUT - 1) / OUT;
+  const int nseg = (n_al + OUT - 1) / OUT;
   const int nlin = (n_ac + NB - 1) / NB;
   dim3 grid = DIR == 0 ? dim3(nseg, nlin) : dim3(nlin, nseg);
   dim3 block = DIR == 0 ? dim3(NA, NB) : dim3(NB, NA);
@@ -353,25 +363,31 @@ hipError_t launch_adj_t(const AdjArgs& a, hipStream_t st, int& nseg) {
 }
 
 int adj_nseg(int dir, int n_al) {
-  const int OUT = (dir == 0 ? 128 : 64) - 6;
+  const int OUT = adj_tile_na(dir, n_al) - 6;
   return (n_al + OUT - 1) / OUT;
 }
 
+template <int SC, int DIR>
+hipError_t launch_adj_d(const AdjArgs& a, hipStream_t st) {
+  const int n_al = DIR == 0 ? a.d.nx : a.d.ny;
+  return adj_tile_na(DIR, n_al) == 64 ? launch_adj_t<SC, DIR, 64>(a, st) : launch_adj_t<SC, DIR, 128>(a, st);
+}
+
 hipError_t launch_adj_sweep(int scheme, int dir, const AdjArgs& a, hipStream_t st, bool fixup) {
-  int nseg = 0;
   hipError_t e;
   switch (scheme * 2 + dir) {
-    case 0: e = launch_adj_t<0, 0>(a, st, nseg); break;
-    case 1: e = launch_adj_t<0, 1>(a, st, nseg); break;
-    case 2: e = launch_adj_t<1, 0>(a, st, nseg); break;
-    case 3: e = launch_adj_t<1, 1>(a, st, nseg); break;
-    case 4: e = launch_adj_t<2, 0>(a, st, nseg); break;
-    case 5: e = launch_adj_t<2, 1>(a, st, nseg); break;
-    case 6: e = launch_adj_t<3, 0>(a, st, nseg); break;
-    default: e = launch_adj_t<3, 1>(a, st, nseg); break;
+    case 0: e = launch_adj_d<0, 0>(a, st); break;
+    case 1: e = launch_adj_d<0, 1>(a, st); break;
+    case 2: e = launch_adj_d<1, 0>(a, st); break;
+    case 3: e = launch_adj_d<1, 1>(a, st); break;
+    case 4: e = launch_adj_d<2, 0>(a, st); break;
+    case 5: e = launch_adj_d<2, 1>(a, st); break;
+    case 6: e = launch_adj_d<3, 0>(a, st); break;
+    default: e = launch_adj_d<3, 1>(a, st); break;
   }
   if (e != hipSuccess || !fixup) return e;
   const int nlines = dir == 0 ? a.d.ny : a.d.nx;
+  const int nseg = adj_nseg(dir, dir == 0 ? a.d.nx : a.d.ny);
   hipLaunchKernelGGL(adj_fixup_kernel, dim3((nlines + 3) / 4), dim3(256), 0, st, a, dir, nseg);
   return hipGetLastError();
 }

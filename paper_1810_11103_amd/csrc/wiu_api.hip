@@ -151,12 +151,18 @@ struct VjpOut {
   double a[3] = {0.0, 0.0, 0.0};
 };
 
+// lam (optional): the line maxima of U (lam_xi[ny], lam_eta[nx]) from a step
+// record; otherwise they are computed here.
 int residual_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M,
-                 const double* Gbar, double* Ubar, const Ws& w, hipStream_t st, const VjpOut& vo = VjpOut()) {
+                 const double* Gbar, double* Ubar, const Ws& w, hipStream_t st, const VjpOut& vo = VjpOut(),
+                 const unsigned long long* lam = nullptr) {
   Dims d = dims(g);
-  if (launch_wave_max(d, U, M, p->gamma, w.lx, w.le, w.cfl, w.status, st) != hipSuccess) return WIU_EHIP;
+  if (!lam) {
+    if (launch_wave_max(d, U, M, p->gamma, w.lx, w.le, w.cfl, w.status, st) != hipSuccess) return WIU_EHIP;
+    lam = w.lx;
+  }
   AdjArgs a;
-  a.d = d; a.U = U; a.M = M; a.Gbar = Gbar; a.Ubar = Ubar; a.lam_xi = w.lx; a.lam_eta = w.le;
+  a.d = d; a.U = U; a.M = M; a.Gbar = Gbar; a.Ubar = Ubar; a.lam_xi = lam; a.lam_eta = lam + d.ny;
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
   a.status = w.status;
   a.coef_c = vo.c; a.coef_dt = vo.dt;
@@ -183,6 +189,7 @@ int hip_rc(hipError_t e) { return e == hipSuccess ? WIU_OK : WIU_EHIP; }
 struct Maxima {
   const unsigned long long *lx_in = nullptr, *le_in = nullptr;
   unsigned long long *nlx = nullptr, *nle = nullptr;
+  unsigned long long* wm = nullptr;  // target of the separate pass (lx[ny], le[nx], cfl[1]); default the workspace's
 };
 
 int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M, const Ws& w,
@@ -194,8 +201,9 @@ int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U
   a.lam_xi = mx.lx_in; a.lam_eta = mx.le_in;
   if (!mx.lx_in) {
     ProfScope ps(WIU_K_WAVE_MAX, st);
-    e = launch_wave_max(d, U, M, p->gamma, w.lx, w.le, w.cfl, w.status, st);
-    a.lam_xi = w.lx; a.lam_eta = w.le;
+    unsigned long long* lx = mx.wm ? mx.wm : w.lx;
+    e = launch_wave_max(d, U, M, p->gamma, lx, lx + d.ny, lx + d.ny + d.nx, w.status, st);
+    a.lam_xi = lx; a.lam_eta = lx + d.ny;
   }
   if (e != hipSuccess) return WIU_EHIP;
   a.d = d; a.U = U; a.M = M;
@@ -226,19 +234,27 @@ int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U
 // The first stage's line maxima are computed from U (or taken from a
 // preceding CFL evaluation of the same state, have_max); stages 1 and 2
 // accumulate the maxima of U1 and U2 in their eta sweeps.
+// rec (optional, a step record): the three maxima sets go there instead of
+// the workspace, U's at rec[0], U1's at rec[1], U2's at rec[2].
 int rk3_stages(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M, const double* dt,
-               double* U1, double* U2, const Ws& w, hipStream_t st, bool have_max) {
+               double* U1, double* U2, const Ws& w, hipStream_t st, bool have_max,
+               unsigned long long* rec = nullptr) {
+  const long long ns = (long long)g->nx + g->ny + 1;
+  unsigned long long* m0 = rec ? rec : w.lx;              // maxima of U
+  unsigned long long* mA = rec ? rec + ns : w.lx2;        // of U1
+  unsigned long long* mB = rec ? rec + 2 * ns : w.lx;     // of U2
   Maxima m1;
   if (have_max) { m1.lx_in = w.lx; m1.le_in = w.le; }
-  m1.nlx = w.lx2; m1.nle = w.le2;
+  m1.wm = m0;
+  m1.nlx = mA; m1.nle = mA + g->ny;
   int rc = residual(g, scheme, p, U, M, w, 2, U1, U, dt, 0.0, 1.0, st, m1);
   if (rc) return rc;
   Maxima m2;
-  m2.lx_in = w.lx2; m2.le_in = w.le2; m2.nlx = w.lx; m2.nle = w.le;
+  m2.lx_in = mA; m2.le_in = mA + g->ny; m2.nlx = mB; m2.nle = mB + g->ny;
   rc = residual(g, scheme, p, U1, M, w, 2, U2, U, dt, 0.75, 0.25, st, m2);
   if (rc) return rc;
   Maxima m3;
-  m3.lx_in = w.lx; m3.le_in = w.le;
+  m3.lx_in = mB; m3.le_in = mB + g->ny;
   return residual(g, scheme, p, U2, M, w, 2, U, U, dt, 1.0 / 3.0, 2.0 / 3.0, st, m3);
 }
 
@@ -330,20 +346,28 @@ int wiu_rhs_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double
   return residual_vjp(g, scheme, p, U, M, Gbar, Ubar, w, (hipStream_t)stream);
 }
 
+size_t wiu_step_record_bytes(const wiu_grid* g) {
+  if (!grid_ok(g)) return 0;
+  return 3 * ((size_t)g->nx + g->ny + 1) * sizeof(unsigned long long);
+}
+
 int wiu_rk3_step_stages(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
-                        const double* dt_dev, double* U1, double* U2, void* ws, wiu_stream_t stream) {
+                        const double* dt_dev, double* U1, double* U2, void* rec, void* ws, wiu_stream_t stream) {
   if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !dt_dev || !U1 || !U2 || !ws)
     return WIU_EINVAL;
   Ws w = carve(g, ws);
-  return rk3_stages(g, scheme, p, U, M, dt_dev, U1, U2, w, (hipStream_t)stream, false);
+  return rk3_stages(g, scheme, p, U, M, dt_dev, U1, U2, w, (hipStream_t)stream, false, (unsigned long long*)rec);
 }
 
 int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U_n, const double* U1,
-                     const double* U2, const double* M, const double* dt_dev, const double* Ubar_np1,
-                     double* Ubar_n, void* ws, wiu_stream_t stream) {
+                     const double* U2, const void* rec, const double* M, const double* dt_dev,
+                     const double* Ubar_np1, double* Ubar_n, void* ws, wiu_stream_t stream) {
   if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U_n || !M || !dt_dev || !Ubar_np1 || !Ubar_n || !ws)
     return WIU_EINVAL;
   if ((U1 == nullptr) != (U2 == nullptr)) return WIU_EINVAL;
+  if (rec && !U1) return WIU_EINVAL;
+  const long long ns = (long long)g->nx + g->ny + 1;
+  const unsigned long long* r = (const unsigned long long*)rec;
   Ws w = carve(g, ws);
   hipStream_t st = (hipStream_t)stream;
   int rc;
@@ -361,11 +385,11 @@ int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const d
   // U' = 1/3 U + 2/3 (U2 + dt L(U2)):  Ubar2 = 2/3 Ubar' + 2/3 dt L'(U2)^T Ubar'
   VjpOut o2;
   o2.c = 2.0 / 3.0; o2.dt = dt_dev; o2.x[0] = Ubar_np1; o2.a[0] = 2.0 / 3.0;
-  if ((rc = residual_vjp(g, scheme, p, U2, M, Ubar_np1, w.ub2, w, st, o2))) return rc;
+  if ((rc = residual_vjp(g, scheme, p, U2, M, Ubar_np1, w.ub2, w, st, o2, r ? r + 2 * ns : nullptr))) return rc;
   // U2 = 3/4 U + 1/4 (U1 + dt L(U1)):  Ubar1 = 1/4 Ubar2 + 1/4 dt L'(U1)^T Ubar2
   VjpOut o1;
   o1.c = 0.25; o1.dt = dt_dev; o1.x[0] = w.ub2; o1.a[0] = 0.25;
-  if ((rc = residual_vjp(g, scheme, p, U1, M, w.ub2, w.ub1, w, st, o1))) return rc;
+  if ((rc = residual_vjp(g, scheme, p, U1, M, w.ub2, w.ub1, w, st, o1, r ? r + ns : nullptr))) return rc;
   // U1 = U + dt L(U), and the direct U terms of U' and U2:
   //   Ubar_n = 1/3 Ubar' + 3/4 Ubar2 + Ubar1 + dt L'(U)^T Ubar1
   // (elementwise in Ubar', so Ubar_n may alias it)
@@ -374,7 +398,7 @@ int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const d
   o0.x[0] = Ubar_np1; o0.a[0] = 1.0 / 3.0;
   o0.x[1] = w.ub2; o0.a[1] = 0.75;
   o0.x[2] = w.ub1; o0.a[2] = 1.0;
-  return residual_vjp(g, scheme, p, U_n, M, w.ub1, Ubar_n, w, st, o0);
+  return residual_vjp(g, scheme, p, U_n, M, w.ub1, Ubar_n, w, st, o0, r);
 }
 
 int wiu_status(void* ws, wiu_stream_t stream, int* status, int clear) {

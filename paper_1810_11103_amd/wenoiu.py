@@ -25,7 +25,7 @@ EXPORTS = [
     "wiu_profile_enable", "wiu_profile_read", "wiu_tuning_variants", "wiu_set_tuning", "wiu_get_tuning",
     "wiu_batched_plan", "wiu_batched_info", "wiu_batched_set_dt", "wiu_batched_cfl_dt", "wiu_batched_get_dt",
     "wiu_batched_rk3_step", "wiu_batched_status", "wiu_plan_destroy",
-    "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl",
+    "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl", "wiu_step_record_bytes",
 ]
 KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3}
 
@@ -77,8 +77,9 @@ def _load():
         "wiu_batched_status": (I, [P, P, ctypes.POINTER(I), I]),
         "wiu_plan_destroy": (I, [P]),
         "wiu_rhs_vjp": (I, [G, I, PR, P, P, P, P, P, P]),
-        "wiu_rk3_step_stages": (I, [G, I, PR, P, P, P, P, P, P, P]),
-        "wiu_rk3_step_vjp": (I, [G, I, PR, P, P, P, P, P, P, P, P, P]),
+        "wiu_rk3_step_stages": (I, [G, I, PR, P, P, P, P, P, P, P, P]),
+        "wiu_rk3_step_vjp": (I, [G, I, PR, P, P, P, P, P, P, P, P, P, P]),
+        "wiu_step_record_bytes": (ctypes.c_size_t, [G]),
         "wiu_tuning_variants": (I, [I]),
         "wiu_set_tuning": (I, [I, I]),
         "wiu_get_tuning": (I, [I]),
@@ -208,15 +209,27 @@ def rhs_vjp(grid, scheme, params, U, M, Gbar, Ubar, ws, stream=None):
     return Ubar
 
 
-def rk3_step_stages(grid, scheme, params, U, M, dt_dev, U1, U2, ws, stream=None):
+def step_record_bytes(grid):
+    return lib.wiu_step_record_bytes(ctypes.byref(grid))
+
+
+def _rec(rec):
+    if rec is None:
+        return None
+    assert rec.is_cuda and rec.is_contiguous() and rec.numel() * rec.element_size() >= 8
+    return ctypes.c_void_p(rec.data_ptr())
+
+
+def rk3_step_stages(grid, scheme, params, U, M, dt_dev, U1, U2, ws, rec=None, stream=None):
     _check(lib.wiu_rk3_step_stages(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U), _ptr(M),
-                                   _ptr(dt_dev), _ptr(U1), _ptr(U2), ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+                                   _ptr(dt_dev), _ptr(U1), _ptr(U2), _rec(rec), ctypes.c_void_p(ws.data_ptr()),
+                                   _stream(stream)))
     return U
 
 
-def rk3_step_vjp(grid, scheme, params, U_n, U1, U2, M, dt_dev, Ubar_np1, Ubar_n, ws, stream=None):
+def rk3_step_vjp(grid, scheme, params, U_n, U1, U2, M, dt_dev, Ubar_np1, Ubar_n, ws, rec=None, stream=None):
     _check(lib.wiu_rk3_step_vjp(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U_n), _ptr(U1),
-                                _ptr(U2), _ptr(M), _ptr(dt_dev), _ptr(Ubar_np1), _ptr(Ubar_n),
+                                _ptr(U2), _rec(rec), _ptr(M), _ptr(dt_dev), _ptr(Ubar_np1), _ptr(Ubar_n),
                                 ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
     return Ubar_n
 
@@ -291,12 +304,28 @@ class Solver:
         out = torch.empty_like(U) if out is None else out
         return rhs_vjp(self.grid, self.scheme, self.params, U, self.M, Gbar, out, self.ws)
 
-    def rk3_step_stages(self, U, U1, U2):
-        return rk3_step_stages(self.grid, self.scheme, self.params, U, self.M, self.dt, U1, U2, self.ws)
+    def rk3_step_stages(self, U, U1, U2, ws=None, rec=None):
+        return rk3_step_stages(self.grid, self.scheme, self.params, U, self.M, self.dt, U1, U2,
+                               self.ws if ws is None else ws, rec)
 
-    def rk3_step_vjp(self, U_n, Ubar_np1, U1=None, U2=None, out=None):
+    def step_record(self, n=None):
+        """Device buffer for one step record (or `n` of them, as rows)."""
+        nb = step_record_bytes(self.grid)
+        shape = (nb // 8,) if n is None else (n, nb // 8)
+        return torch.empty(shape, dtype=torch.int64, device=self.device)
+
+    def side_workspace(self):
+        """A second workspace of this grid (lazily created), for work issued
+        on another stream concurrently with calls that use self.ws."""
+        if getattr(self, "_ws2", None) is None:
+            self._ws2 = workspace(self.grid, self.device)
+            workspace_init(self._ws2)
+        return self._ws2
+
+    def rk3_step_vjp(self, U_n, Ubar_np1, U1=None, U2=None, out=None, rec=None):
         out = torch.empty_like(U_n) if out is None else out
-        return rk3_step_vjp(self.grid, self.scheme, self.params, U_n, U1, U2, self.M, self.dt, Ubar_np1, out, self.ws)
+        return rk3_step_vjp(self.grid, self.scheme, self.params, U_n, U1, U2, self.M, self.dt, Ubar_np1, out, self.ws,
+                            rec)
 
     def line_eigenvalues(self, U):
         lx = torch.empty(self.grid.ny, dtype=torch.float64, device=self.device)
@@ -305,7 +334,10 @@ class Solver:
         return lx, le
 
     def status(self, clear=True):
-        return status(self.ws, clear)
+        st = status(self.ws, clear)
+        if getattr(self, "_ws2", None) is not None:
+            st |= status(self._ws2, clear)
+        return st
 
     def planes(self):
         return metric_planes(self.M, self.grid)

@@ -102,7 +102,7 @@ def test_rhs_vjp_is_deterministic(wiu):
 
 
 @pytest.mark.parametrize("s", ["3-2MP", "5-2MP"])
-@pytest.mark.parametrize("stored", [False, True])
+@pytest.mark.parametrize("stored", [False, True, "record"])
 def test_rk3_step_vjp_matches_oracle(orc, wiu, s, stored):
     import torch
     say("rk3 vjp", s, stored)
@@ -117,13 +117,16 @@ def test_rk3_step_vjp_matches_oracle(orc, wiu, s, stored):
     Ud = _dev(U)
     if stored:
         U1, U2 = torch.empty_like(Ud), torch.empty_like(Ud)
+        rec = sol.step_record() if stored == "record" else None
         Uf = Ud.clone()
-        sol.rk3_step_stages(Uf, U1, U2)
+        sol.rk3_step_stages(Uf, U1, U2, rec=rec)
         # the stage-storing step is the ordinary step
         Uo = Ud.clone()
         sol.rk3_step(Uo)
         assert torch.equal(Uf, Uo)
-        out = sol.rk3_step_vjp(Ud, _dev(Wt), U1, U2).cpu().numpy()
+        out = sol.rk3_step_vjp(Ud, _dev(Wt), U1, U2, rec=rec).cpu().numpy()
+        if rec is not None:  # the recorded maxima are the ones the adjoint would recompute
+            assert np.array_equal(out, sol.rk3_step_vjp(Ud, _dev(Wt), U1, U2).cpu().numpy())
     else:
         out = sol.rk3_step_vjp(Ud, _dev(Wt)).cpu().numpy()
     assert sol.status() == 0

@@ -80,6 +80,7 @@ BatchArgs base_args(const wiu_plan* p) {
   a.M_all = p->M_all;
   a.ws = (double*)p->d_ws;
   a.lam = p->d_lam;
+  a.xi_mode = 3;
   return a;
 }
 

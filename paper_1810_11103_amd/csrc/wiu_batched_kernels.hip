@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(NA * NB, 4) batched_sweep_kernel(BatchArgs b) 
     s.out = stage_dst(b, B, st);
     s.ca = st == 0 ? 0.0 : (st == 1 ? 0.75 : 1.0 / 3.0);
     s.cb = st == 0 ? 1.0 : (st == 1 ? 0.25 : 2.0 / 3.0);
-    s.mode = DIR == 0 ? 3 : 2;
+    s.mode = DIR == 0 ? b.xi_mode : 2;
     sweep_tile<SC, DIR, NA, NB>(s, tl.y, tl.z, lds);
   }
 }

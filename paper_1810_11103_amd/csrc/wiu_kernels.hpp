@@ -59,6 +59,8 @@ struct BatchArgs {
   const double* M_all;
   double* ws;
   unsigned long long* lam;
+  int xi_mode;               // sweep mode of the xi launches (3); a kernel argument
+                             // rather than a constant, which keeps the epilogue lean
 };
 
 // Arguments of the adjoint sweeps and their per-line fix-up.

@@ -102,6 +102,15 @@ WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB>& L, int tb, int o0, i
   }
 }
 
+// Epilogue operands of one output node, loaded before the tile's last
+// barrier so that their latency overlaps the barrier and the flux
+// difference (at that point the compute phase's registers are free).
+struct OutOperands {
+  double x[4];   // R^xi (rhs), P (eta stage) or U0 (xi stage, when its coefficient is non-zero)
+  double jinv;   // J^{-1} at the node
+  double km[4];  // nodal metrics xi_x, xi_y, eta_x, eta_y (eta stage with next maxima)
+};
+
 // Output phase of an eta tile in RK-stage mode that also accumulates the line
 // maxima of the new stage state (the next stage's eigenvalues, Sec. 2.3), so
 // that stage needs no separate pass over the state.  Every lane of the block
@@ -111,9 +120,7 @@ WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB>& L, int tb, int o0, i
 // separate pass, so the maxima are bit-identical to it.
 template <int SC, int NA, int NB>
 WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB>& L, bool act, int line, int i, int o0,
-                             int tb, double lam) {
-  using R_ = Range<SC>;
-  using LT = SweepLds<SC, 1, NA, NB>;
+                             int tb, double lam, const OutOperands& op) {
   static_assert(64 % NB == 0 && (NA * NB) % 64 == 0, "eta tile must pack whole waves");
   const Dims& d = s.d;
   double sx = 0.0, se = 0.0;
@@ -122,19 +129,17 @@ WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB>& L, boo
     double R[4];
     tile_residual<SC, 1, NA, NB>(L, tb, o0, i, lam, R);
     const long long o = (long long)i * d.nx + line;
-    const long long mo = (long long)(i + GHOST) * d.mpitch + (line + GHOST);
-    const double rj = -rcp(s.M[4 * d.mplane + mo]);
+    const double rj = -rcp(op.jinv);
     const double dt = s.dt[0];
     double Qn[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const long long e = c * d.np + o;
-      Qn[c] = s.Rxi[e] + s.cb * (dt * (R[c] * rj));
-      s.out[e] = Qn[c];
+      Qn[c] = op.x[c] + s.cb * (dt * (R[c] * rj));
+      s.out[c * d.np + o] = Qn[c];
     }
     const WaveState w = wave_state(Qn, s.gamma);
-    const double sxr = wave_speed_dir(w, s.M[mo], s.M[d.mplane + mo]);
-    const double ser = wave_speed_dir(w, s.M[2 * d.mplane + mo], s.M[3 * d.mplane + mo]);
+    const double sxr = wave_speed_dir(w, op.km[0], op.km[1]);
+    const double ser = wave_speed_dir(w, op.km[2], op.km[3]);
     bad = w.bad || !(sxr < 1.0e300) || !(ser < 1.0e300);
     sx = fmax(0.0, sxr);
     se = fmax(0.0, ser);
@@ -252,31 +257,50 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
       }
     }
   }
+
+  // epilogue operands of this thread's output node, issued before the barrier
+  const bool act = live && ta < out;
+  const int i = o0 + ta;                  // output node along the line
+  const int ii = DIR == 0 ? i : line, jj = DIR == 0 ? line : i;
+  const long long o = (long long)jj * d.nx + ii;
+  const long long mo = (long long)(jj + GHOST) * d.mpitch + (ii + GHOST);
+  const bool fused = DIR == 1 && s.mode == 2 && s.nlam_xi;
+  OutOperands op;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) op.x[c] = op.km[c] = 0.0;
+  op.jinv = 1.0;
+  if (act && s.mode != 0) {
+    op.jinv = s.M[4 * d.mplane + mo];
+    const double* src = s.mode == 3 ? (s.ca != 0.0 ? s.U0 : nullptr) : s.Rxi;
+    if (src) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) op.x[c] = src[c * d.np + o];
+    }
+    if (fused) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) op.km[c] = s.M[c * d.mplane + mo];
+    }
+  }
   __syncthreads();
 
-  const bool act = live && ta < out;
   if constexpr (DIR == 1) {
-    if (s.mode == 2 && s.nlam_xi) {  // whole waves take part in the reductions
-      fused_stage_out<SC, NA, NB>(s, L, act, line, o0 + ta, o0, tb, lam);
+    if (fused) {  // whole waves take part in the reductions
+      fused_stage_out<SC, NA, NB>(s, L, act, line, i, o0, tb, lam, op);
       return;
     }
   }
   if (!act) return;  // no barrier follows
-  const int i = o0 + ta;                  // output node along the line
   double R[4];
   tile_residual<SC, DIR, NA, NB>(L, tb, o0, i, lam, R);
-  const long long o = DIR == 0 ? (long long)line * d.nx + i : (long long)i * d.nx + line;
   if (s.mode == 0) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) s.Rxi[c * d.np + o] = R[c];
     return;
   }
-  const int ii = DIR == 0 ? i : line, jj = DIR == 0 ? line : i;
-  const double jinv = s.M[4 * d.mplane + (long long)(jj + GHOST) * d.mpitch + (ii + GHOST)];
-  const double rj = -rcp(jinv);
+  const double rj = -rcp(op.jinv);
   if (s.mode == 1) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) s.out[c * d.np + o] = (s.Rxi[c * d.np + o] + R[c]) * rj;
+    for (int c = 0; c < 4; ++c) s.out[c * d.np + o] = (op.x[c] + R[c]) * rj;
     return;
   }
   const double dt = s.dt[0];
@@ -288,18 +312,14 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
     const int pq = LT::qi(tb, i - (o0 + R_::LO - 2));
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const long long e = c * d.np + o;
       const double un = s.cb * (sq[c][pq] + dt * (R[c] * rj));
-      s.Rxi[e] = s.ca == 0.0 ? un : s.ca * s.U0[e] + un;
+      s.Rxi[c * d.np + o] = s.ca == 0.0 ? un : s.ca * op.x[c] + un;
     }
     return;
   }
   // mode 2: U_out = P + cb dt R^eta / -J^{-1}
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const long long e = c * d.np + o;
-    s.out[e] = s.Rxi[e] + s.cb * (dt * (R[c] * rj));
-  }
+  for (int c = 0; c < 4; ++c) s.out[c * d.np + o] = op.x[c] + s.cb * (dt * (R[c] * rj));
 }
 
 

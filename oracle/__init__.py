@@ -14,7 +14,7 @@ from . import build as _build
 
 _lib = None
 
-SCHEMES = {"3-1MP": 0, "3-2MP": 1, "5-1MP": 2, "5-2MP": 3}
+SCHEMES = {"3-1MP": 0, "3-2MP": 1, "5-1MP": 2, "5-2MP": 3, "7-1MP": 4, "7-2MP": 5, "7-4MP": 6, "7-6MP": 7}
 BC = {"periodic": 0, "transmissive": 1}
 G = 4  # metric ghost band
 
@@ -36,12 +36,14 @@ def lib():
         L.orc_ppm.argtypes = [_I, _D, _D]
         L.orc_is.restype = _D
         L.orc_is.argtypes = [_I, _D, _D, _D]
+        L.orc_is4.restype = _D
+        L.orc_is4.argtypes = [_I, _D, _D, _D, _D]
         L.orc_hplus.restype = _D
         L.orc_hplus.argtypes = [_I, _P, _P]
         L.orc_delta_c.restype = _D
         L.orc_delta_c.argtypes = [_I, _P, _P]
         L.orc_interp_mid.restype = _D
-        L.orc_interp_mid.argtypes = [_P]
+        L.orc_interp_mid.argtypes = [_I, _P]
         L.orc_metric_derivative.restype = _D
         L.orc_metric_derivative.argtypes = [_I, _P]
         L.orc_eigenvectors.restype = None
@@ -65,7 +67,7 @@ def lib():
         L.orc_adv1d_rhs.restype = None
         L.orc_adv1d_rhs.argtypes = [_I, _I, _D, _I, _D, _D, _I, _P, _P]
         L.orc_adv1d_run.restype = _I
-        L.orc_adv1d_run.argtypes = [_I, _I, _I, _D, _D, _I, _D, _P, _P]
+        L.orc_adv1d_run.argtypes = [_I, _I, _I, _D, _D, _I, _D, _D, _P, _P]
         for nm in ("orc_rhs_jvp", "orc_rk3_step_jvp"):
             f = getattr(L, nm)
             f.restype = _I
@@ -125,9 +127,17 @@ def smoothness(k, a, b, c):
     return lib().orc_is(k, a, b, c)
 
 
+def smoothness4(k, a, b, c, d):
+    """r = 4 indicator of stencil k (0 = leftmost) on four values."""
+    return lib().orc_is4(k, a, b, c, d)
+
+
 def hplus(scheme, f, F):
-    """h^+_{i+1/2}; f = f_{i-3..i+3} (7 values), F = f_{i-3/2..i+3/2} (4 values)."""
+    """h^+_{i+1/2}; f = f_{i-3..i+3} (7 values), F = f_{i-5/2..i+5/2} (6 values;
+    4 values f_{i-3/2..i+3/2} are accepted and padded with zeros)."""
     f, F = _f64(f), _f64(F)
+    if F.size == 4:
+        F = np.concatenate([[0.0], F, [0.0]])
     return lib().orc_hplus(scheme_id(scheme), _ptr(f), _ptr(F))
 
 
@@ -138,8 +148,11 @@ def delta_c(scheme, g, gm):
 
 
 def interp_mid(g):
+    """Midpoint value g_{i+1/2} from g_{i-2..i+3} (6 values) or g_{i-3..i+4} (8)."""
     g = _f64(g)
-    return lib().orc_interp_mid(_ptr(g))
+    if g.size not in (6, 8):
+        raise ValueError("interp_mid takes 6 or 8 values")
+    return lib().orc_interp_mid(g.size, _ptr(g))
 
 
 def metric_derivative(scheme, r):
@@ -163,7 +176,11 @@ def flux_hat(Q, gamma, kx, ky):
 
 
 def midpoint_flux(scheme, Qs, k0, k1, mk, lam, gamma=1.4, eps=1e-40, ppm=1):
+    """F^+, F^- at k+1/2 from Qs = Q_{k-3..k+4} (8 states; 6 states Q_{k-2..k+3}
+    are accepted for the third- and fifth-order schemes)."""
     Qs, k0, k1, mk = _f64(Qs), _f64(k0), _f64(k1), _f64(mk)
+    if Qs.shape[0] == 6:
+        Qs = np.ascontiguousarray(np.concatenate([Qs[:1], Qs, Qs[-1:]]))
     Fp, Fm = np.zeros(4), np.zeros(4)
     rc = lib().orc_midpoint_flux(scheme_id(scheme), gamma, eps, ppm, _ptr(Qs), _ptr(k0), _ptr(k1),
                                  _ptr(mk), lam, _ptr(Fp), _ptr(Fm))
@@ -296,10 +313,10 @@ def adv1d_rhs(scheme, u, dx, split=0, alpha=1.1, eps=1e-40, ppm=1):
     return out
 
 
-def adv1d_run(scheme, N, split=0, alpha=1.1, eps=1e-40, ppm=1, tend=2.0):
+def adv1d_run(scheme, N, split=0, alpha=1.1, eps=1e-40, ppm=1, tend=2.0, dtpow=1.25):
     l2 = ctypes.c_double()
     li = ctypes.c_double()
-    rc = lib().orc_adv1d_run(scheme_id(scheme), N, split, alpha, eps, ppm, tend, ctypes.byref(l2),
+    rc = lib().orc_adv1d_run(scheme_id(scheme), N, split, alpha, eps, ppm, tend, dtpow, ctypes.byref(l2),
                              ctypes.byref(li))
     if rc:
         raise ValueError("orc_adv1d_run failed")

@@ -24,7 +24,7 @@
 
 namespace orc {
 
-enum Scheme { W3_1MP = 0, W3_2MP = 1, W5_1MP = 2, W5_2MP = 3 };
+enum Scheme { W3_1MP = 0, W3_2MP = 1, W5_1MP = 2, W5_2MP = 3, W7_1MP = 4, W7_2MP = 5, W7_4MP = 6, W7_6MP = 7 };
 enum Bc { PERIODIC = 0, TRANSMISSIVE = 1 };
 
 // Width of the metric ghost band stored around the grid (each side).
@@ -38,6 +38,7 @@ struct Params {
 };
 
 inline bool fifth_order(Scheme s) { return s == W5_1MP || s == W5_2MP; }
+inline bool seventh_order(Scheme s) { return s >= W7_1MP; }
 inline bool two_midpoints(Scheme s) { return s == W3_2MP || s == W5_2MP; }
 
 // Overloads that AD scalar types also provide.
@@ -125,17 +126,68 @@ template <class T> T weno_r2(const T v[4], const Params& pr) {
   return w[0] * p[0] + w[1] * p[1];
 }
 
-// Left-biased value at k+1/2 from the window s[0..5] = v_{k-2..k+3}.
-template <class T> T weno_left(Scheme sc, const T s[6], const Params& pr) {
-  if (fifth_order(sc)) return weno_r3(s, pr);
-  return weno_r2(s, pr);
+// Fourth-order piecewise-polynomial mapping (Appendix), for r = 4.
+template <class T> T ppm4(const T& w, double C) {
+  if (w <= C) { T t = w / C - 1.0; T t2 = t * t; return C * (1.0 - t2 * t2); }
+  T d = w - C; T d2 = d * d;
+  return C - d2 * d2 / ((C - 1.0) * (C - 1.0) * (C - 1.0));
+}
+
+// Smoothness indicators for r = 4 on the four-point stencil (a, b, c, d)
+// counted from the left: the paper gives none; the Jiang-Shu definition that
+// yields the printed r = 3 ones (Eqs. 3.14, 3.22) gives these quadratic forms
+// (coefficients / 240), derived exactly by oracle/derive_weno_is.py and
+// re-derived by the test suite.  k is the stencil's position (0: leftmost).
+template <class T> T is_r4(int k, const T& a, const T& b, const T& c, const T& d) {
+  static const double Q[4][10] = {
+      // a^2, ab, ac, ad, b^2, bc, bd, c^2, cd, d^2 (cross terms doubled)
+      {547, -3882, 4642, -1854, 7043, -17246, 7042, 11003, -9402, 2107},
+      {267, -1642, 1602, -494, 2843, -5966, 1922, 3443, -2522, 547},
+      {547, -2522, 1922, -494, 3443, -5966, 1602, 2843, -1642, 267},
+      {2107, -9402, 7042, -1854, 11003, -17246, 4642, 7043, -3882, 547}};
+  const double* q = Q[k];
+  T s = a * (q[0] * a + q[1] * b + q[2] * c + q[3] * d) + b * (q[4] * b + q[5] * c + q[6] * d) +
+        c * (q[7] * c + q[8] * d) + q[9] * d * d;
+  return s / 240.0;
+}
+
+// r = 4 (seventh-order schemes, Appendix).  v[0..6] = v_{k-3}, ..., v_{k+3};
+// left-biased value at k+1/2.  Candidates and linear weights of Table A1
+// (C = (1, 21, 35, 7)/64), weights Eqs. 3.12-3.13, indicators is_r4, the
+// fourth-order mapping followed by re-normalisation.
+template <class T> T weno_r4(const T v[7], const Params& pr) {
+  const double C[4] = {1.0 / 64.0, 21.0 / 64.0, 35.0 / 64.0, 7.0 / 64.0};
+  T p[4];
+  p[0] = (-5.0 * v[0] + 21.0 * v[1] - 35.0 * v[2] + 35.0 * v[3]) / 16.0;
+  p[1] = (1.0 * v[1] - 5.0 * v[2] + 15.0 * v[3] + 5.0 * v[4]) / 16.0;
+  p[2] = (-1.0 * v[2] + 9.0 * v[3] + 9.0 * v[4] - 1.0 * v[5]) / 16.0;
+  p[3] = (5.0 * v[3] + 15.0 * v[4] - 5.0 * v[5] + 1.0 * v[6]) / 16.0;
+  T IS[4];
+  for (int k = 0; k < 4; ++k) IS[k] = is_r4(k, v[k], v[k + 1], v[k + 2], v[k + 3]);
+  T a[4], sa = T(0.0);
+  for (int k = 0; k < 4; ++k) { T d = pr.eps + IS[k]; a[k] = C[k] / (d * d); sa = sa + a[k]; }
+  T w[4];
+  for (int k = 0; k < 4; ++k) w[k] = a[k] / sa;
+  if (pr.ppm) {
+    T g[4], sg = T(0.0);
+    for (int k = 0; k < 4; ++k) { g[k] = ppm4(w[k], C[k]); sg = sg + g[k]; }
+    for (int k = 0; k < 4; ++k) w[k] = g[k] / sg;
+  }
+  return w[0] * p[0] + w[1] * p[1] + w[2] * p[2] + w[3] * p[3];
+}
+
+// Left-biased value at k+1/2 from the window s[0..7] = v_{k-3..k+4}.
+template <class T> T weno_left(Scheme sc, const T s[8], const Params& pr) {
+  if (seventh_order(sc)) return weno_r4(s, pr);
+  if (fifth_order(sc)) return weno_r3(s + 1, pr);
+  return weno_r2(s + 1, pr);
 }
 // Right-biased value at k+1/2: the same interpolation applied to the sequence
-// mirrored about k+1/2, i.e. v_{k+3}, v_{k+2}, ..., v_{k-2}.
-template <class T> T weno_right(Scheme sc, const T s[6], const Params& pr) {
-  T m[6] = {s[5], s[4], s[3], s[2], s[1], s[0]};
-  if (fifth_order(sc)) return weno_r3(m, pr);
-  return weno_r2(m, pr);
+// mirrored about k+1/2, i.e. v_{k+4}, v_{k+3}, ..., v_{k-3}.
+template <class T> T weno_right(Scheme sc, const T s[8], const Params& pr) {
+  T m[8];
+  for (int i = 0; i < 8; ++i) m[i] = s[7 - i];
+  return weno_left(sc, m, pr);
 }
 
 // ===========================================================================
@@ -154,8 +206,20 @@ T h_plus(Scheme sc, NodeF f, MidF F) {
       return F(0) + (19.0 / 1920.0) * f(-2) - (29.0 / 480.0) * f(-1) + (77.0 / 960.0) * f(0) -
              (3.0 / 160.0) * f(1) - (7.0 / 640.0) * f(2);
     case W5_2MP:  // Eq. 3.20
-    default:
       return F(0) + (1.0 / 30.0) * ((-4.0 * f(1) + f(0) + f(-1)) + (6.0 * F(0) - 4.0 * F(-1)));
+    case W7_1MP:  // Appendix (1), alpha = 1
+      return F(0) + (1.0 / 107520.0) * (-243.0 * f(-3) + 1990.0 * f(-2) - 7481.0 * f(-1) + 8164.0 * f(0) -
+                                        341.0 * f(1) - 2378.0 * f(2) + 289.0 * f(3));
+    case W7_2MP:  // Appendix (2); its f_j coefficient -92 is read as -93 (consistency)
+      return F(0) + (1.0 / 1260.0) * ((-128.0 * F(-1) + 404.0 * F(0)) +
+                                      (-2.0 * f(-2) + 47.0 * f(-1) - 93.0 * f(0) - 233.0 * f(1) + 5.0 * f(2)));
+    case W7_4MP:  // Appendix (3)
+      return F(0) + (1.0 / 420.0) * ((18.0 * f(-1) - 66.0 * f(0) - 108.0 * f(1)) +
+                                     (-3.0 * F(-2) - 31.0 * F(-1) + 179.0 * F(0) + 11.0 * F(1)));
+    case W7_6MP:  // Appendix (4); its node term 3840 f_{j-1} is read as 3840 f_j
+    default:
+      return F(0) + (1.0 / 26880.0) * (3840.0 * f(0) + (-45.0 * F(-3) + 501.0 * F(-2) - 3874.0 * F(-1) +
+                                                         746.0 * F(0) - 1249.0 * F(1) + 81.0 * F(2)));
   }
 }
 
@@ -175,18 +239,41 @@ double delta_c(Scheme sc, NodeF g, MidF gm) {
       return (gm(0) - gm(-1)) + (19.0 / 3840.0) * (g(3) - g(-3)) - (13.0 / 320.0) * (g(2) - g(-2)) +
              (17.0 / 256.0) * (g(1) - g(-1));
     case W5_2MP:  // Eq. 3.21 (its "f_{i+2}" is f_{j+2})
-    default:
       return (1.0 / 60.0) * (g(2) - 4.0 * g(1) + 4.0 * g(-1) - g(-2)) +
              (1.0 / 15.0) * (-gm(1) + 19.0 * gm(0) - 19.0 * gm(-1) + gm(-2));
+    case W7_1MP:  // Appendix (1)
+      return (gm(0) - gm(-1)) + (1.0 / 107520.0) * (-121.5 * (g(4) - g(-4)) + 1261.0 * (g(3) - g(-3)) -
+                                                    6069.0 * (g(2) - g(-2)) + 8841.0 * (g(1) - g(-1)));
+    case W7_2MP:  // Appendix (2)
+      return (1.0 / 315.0) * (-16.0 * (gm(1) - gm(-2)) + 432.0 * (gm(0) - gm(-1))) +
+             (1.0 / 1260.0) * (-(g(3) - g(-3)) + 27.0 * (g(2) - g(-2)) - 189.0 * (g(1) - g(-1)));
+    case W7_4MP:  // Appendix (3) (its "f_{i-2}", "f_{i-5/2}" are f_{j-2}, f_{j-5/2})
+      return (1.0 / 140.0) * (3.0 * (g(2) - g(-2)) - 32.0 * (g(1) - g(-1))) +
+             (1.0 / 840.0) * (-3.0 * (gm(2) - gm(-3)) - 17.0 * (gm(1) - gm(-2)) + 1218.0 * (gm(0) - gm(-1)));
+    case W7_6MP:  // Appendix (4)
+    default:
+      return (1.0 / 14.0) * (g(1) - g(-1)) - (3.0 / 3584.0) * (gm(3) - gm(-4)) +
+             (209.0 / 17920.0) * (gm(2) - gm(-3)) - (163.0 / 1536.0) * (gm(1) - gm(-2)) +
+             (575.0 / 512.0) * (gm(0) - gm(-1));
   }
 }
 
-// Linear interpolation to the midpoint g_{i+1/2} from g_{i-2..i+3}.  The paper
-// asks only for a "directionally consistent" linear interpolation, the same in
-// the metrics and in the midpoint fluxes (Sec. 2.4); the six-point central
-// (sixth-order Lagrange) interpolation is the reading adopted here.
-template <class NodeF> double interp_mid(NodeF g) {
+// Linear interpolation to the midpoint g_{i+1/2}.  The paper asks only for a
+// "directionally consistent" linear interpolation, the same in the metrics
+// and in the midpoint fluxes (Sec. 2.4).  The reading adopted is the central
+// Lagrange interpolation one order above the scheme: six points g_{i-2..i+3}
+// (sixth order) for the third- and fifth-order schemes, eight points
+// g_{i-3..i+4} (eighth order) for the seventh-order ones, so the metrics keep
+// the order of the scheme's central operator (Sec. 2.3, Appendix).
+template <class NodeF> double interp_mid6(NodeF g) {
   return (3.0 * g(-2) - 25.0 * g(-1) + 150.0 * g(0) + 150.0 * g(1) - 25.0 * g(2) + 3.0 * g(3)) / 256.0;
+}
+template <class NodeF> double interp_mid8(NodeF g) {
+  return (-5.0 * g(-3) + 49.0 * g(-2) - 245.0 * g(-1) + 1225.0 * g(0) + 1225.0 * g(1) - 245.0 * g(2) +
+          49.0 * g(3) - 5.0 * g(4)) / 2048.0;
+}
+template <class NodeF> double interp_mid(Scheme sc, NodeF g) {
+  return seventh_order(sc) ? interp_mid8(g) : interp_mid6(g);
 }
 
 // The scheme's metric derivative at a node, evaluated on the local relative
@@ -195,7 +282,7 @@ template <class NodeF> double interp_mid(NodeF g) {
 inline double metric_derivative(Scheme sc, const double r[17]) {
   auto g = [&](int m) { return r[m + 8]; };
   auto gm = [&](int m) {  // g_{i+1/2+m}
-    return interp_mid([&](int l) { return r[m + l + 8]; });
+    return interp_mid(sc, [&](int l) { return r[m + l + 8]; });
   };
   return delta_c(sc, g, gm);
 }
@@ -314,7 +401,7 @@ inline void compute_metrics(Scheme sc, const Grid& g, const double* x, const dou
   const int W = g.nx + 2 * G, H = g.ny + 2 * G;
   const size_t P = (size_t)W * H;
   // Nodal metrics on a band wide enough for the midpoint interpolation.
-  const int B = G + 3;
+  const int B = G + (seventh_order(sc) ? 4 : 3);
   const int WB = g.nx + 2 * B, HB = g.ny + 2 * B;
   std::vector<NodalMetric> nm((size_t)WB * HB);
   auto wr = [&](int a, int n, Bc bc) { return bc == PERIODIC ? wrap(a, n) : a; };
@@ -334,10 +421,10 @@ inline void compute_metrics(Scheme sc, const Grid& g, const double* x, const dou
       const NodalMetric& n0 = N(a, b);
       M[0 * P + o] = n0.xix; M[1 * P + o] = n0.xiy;
       M[2 * P + o] = n0.etx; M[3 * P + o] = n0.ety; M[4 * P + o] = n0.jinv;
-      M[5 * P + o] = interp_mid([&](int l) { return N(a + l, b).xix; });
-      M[6 * P + o] = interp_mid([&](int l) { return N(a + l, b).xiy; });
-      M[7 * P + o] = interp_mid([&](int l) { return N(a, b + l).etx; });
-      M[8 * P + o] = interp_mid([&](int l) { return N(a, b + l).ety; });
+      M[5 * P + o] = interp_mid(sc, [&](int l) { return N(a + l, b).xix; });
+      M[6 * P + o] = interp_mid(sc, [&](int l) { return N(a + l, b).xiy; });
+      M[7 * P + o] = interp_mid(sc, [&](int l) { return N(a, b + l).etx; });
+      M[8 * P + o] = interp_mid(sc, [&](int l) { return N(a, b + l).ety; });
     }
 }
 
@@ -403,11 +490,12 @@ template <class T> void eigenvectors(const T Q[4], double gam, double nx_, doubl
 
 // ===========================================================================
 // Midpoint split fluxes F^+_{k+1/2}, F^-_{k+1/2} (Secs. 2.3, 2.4, 3.4).
-// Inputs: the six states Q_{k-2..k+3}, the nodal hatted metrics at k and k+1
+// Inputs: the eight states Q_{k-3..k+4}, the nodal hatted metrics at k and k+1
 // (their mean gives the eigenvector direction), the midpoint metric (I xi^)_{k+1/2},
 // and the line eigenvalue lambda.
-//   + side: reference state Q_k, left-biased interpolation of L Q over k-2..k+2
-//   - side: reference state Q_{k+1}, right-biased interpolation over k-1..k+3
+//   + side: reference state Q_k, left-biased interpolation of L Q over
+//           k-2..k+2 (k-1..k+1 for r = 2, k-3..k+3 for r = 4)
+//   - side: reference state Q_{k+1}, the mirror image about k+1/2
 // Each midpoint is evaluated once and reused by every h that needs it.
 //
 // The projection is applied to the deviations Q_m - Q_ref and Q_ref is added
@@ -418,19 +506,19 @@ template <class T> void eigenvectors(const T Q[4], double gam, double nx_, doubl
 // bitwise (the reading adopted for free-stream preservation at round-off).
 // ===========================================================================
 template <class T>
-void midpoint_flux(Scheme sc, const Params& pr, const T Qs[6][4], double kx0, double ky0, double kx1,
+void midpoint_flux(Scheme sc, const Params& pr, const T Qs[8][4], double kx0, double ky0, double kx1,
                    double ky1, double mkx, double mky, const T& lam, T Fp[4], T Fm[4]) {
   double nbx = 0.5 * (kx0 + kx1), nby = 0.5 * (ky0 + ky1);
   double nn = std::sqrt(nbx * nbx + nby * nby);
   double nx_ = nbx / nn, ny_ = nby / nn;
   for (int side = 0; side < 2; ++side) {
-    const T* Qref = Qs[2 + side];  // Q_k for +, Q_{k+1} for -
+    const T* Qref = Qs[3 + side];  // Q_k for +, Q_{k+1} for -
     T L[4][4], R[4][4];
     eigenvectors(Qref, pr.gamma, nx_, ny_, L, R);
     T W[4];
     for (int c = 0; c < 4; ++c) {
-      T s[6];
-      for (int m = 0; m < 6; ++m) {
+      T s[8];
+      for (int m = 0; m < 8; ++m) {
         s[m] = T(0.0);
         for (int q = 0; q < 4; ++q) s[m] = s[m] + L[c][q] * (Qs[m][q] - Qref[q]);
       }
@@ -476,11 +564,14 @@ void line_residual(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_
   lam = pr.alpha_lf * lam;
   if (lam_out) *lam_out = lam;
 
+  // Indices a residual needs: nodes -4 .. n+3, midpoints -4 .. n+2 (the
+  // widest stencils, of the seventh-order schemes; the metric ghost band
+  // reaches exactly that far).
   const int off = 4;  // arrays hold indices -4 .. n+3
   const int len = n + 8;
   std::vector<T> fp(4 * len), fm(4 * len), Fp(4 * len), Fm(4 * len);
   // Nodal split fluxes f^+- = (E^ +- lambda Q) / 2 (Sec. 2.3).
-  for (int k = -3; k < n + 3; ++k) {
+  for (int k = -4; k < n + 4; ++k) {
     T Qk[4] = {Q(k, 0), Q(k, 1), Q(k, 2), Q(k, 3)}, E[4];
     flux_hat(Qk, pr.gamma, kx(k), ky(k), E);
     for (int q = 0; q < 4; ++q) {
@@ -489,10 +580,10 @@ void line_residual(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_
     }
   }
   // Midpoint split fluxes at k+1/2.
-  for (int k = -2; k < n + 1; ++k) {
-    T Qs[6][4];
-    for (int m = 0; m < 6; ++m)
-      for (int q = 0; q < 4; ++q) Qs[m][q] = Q(k - 2 + m, q);
+  for (int k = -4; k < n + 3; ++k) {
+    T Qs[8][4];
+    for (int m = 0; m < 8; ++m)
+      for (int q = 0; q < 4; ++q) Qs[m][q] = Q(k - 3 + m, q);
     T a[4], b[4];
     midpoint_flux(sc, pr, Qs, kx(k), ky(k), kx(k + 1), ky(k + 1), mkx(k), mky(k), lam, a, b);
     for (int q = 0; q < 4; ++q) { Fp[q * len + k + off] = a[q]; Fm[q * len + k + off] = b[q]; }

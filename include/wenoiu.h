@@ -43,8 +43,16 @@ extern "C" {
 typedef void* wiu_stream_t; /* hipStream_t */
 
 /* Scheme variants: third/fifth order with one or two midpoints
- * (Eqs. 3.4, 3.8, 3.16, 3.20 with their central operators 3.7, 3.9, 3.19, 3.21). */
-enum { WIU_3_1MP = 0, WIU_3_2MP = 1, WIU_5_1MP = 2, WIU_5_2MP = 3 };
+ * (Eqs. 3.4, 3.8, 3.16, 3.20 with their central operators 3.7, 3.9, 3.19,
+ * 3.21) and the seventh-order schemes of the Appendix with one, two, four and
+ * six midpoints (r = 4 interpolation of Table A1 with the fourth-order
+ * mapping).  Two printed Appendix coefficients are read as corrected (7-2MP:
+ * f_j weight -93; 7-6MP: node term 3840 f_j), the values for which each h
+ * decomposes into its printed central operator (Eq. 2.7). */
+enum {
+  WIU_3_1MP = 0, WIU_3_2MP = 1, WIU_5_1MP = 2, WIU_5_2MP = 3,
+  WIU_7_1MP = 4, WIU_7_2MP = 5, WIU_7_4MP = 6, WIU_7_6MP = 7
+};
 
 /* Boundary rule per direction.  PERIODIC: states wrap; coordinates repeat
  * shifted by the period.  TRANSMISSIVE: states copy the boundary node;
@@ -86,8 +94,10 @@ size_t wiu_workspace_bytes(const wiu_grid* g);
 
 /* Grid metrics in conservative form (Sec. 2.2), differentiated with the
  * scheme's own central operator delta^{c,(1)} (Sec. 2.3, Eqs. 3.7/3.9/3.19/
- * 3.21) whose midpoint values come from a fixed six-point interpolation in
- * each direction (Sec. 2.4), evaluated on coordinate differences.  In 2-D:
+ * 3.21, Appendix) whose midpoint values come from a fixed linear
+ * interpolation in each direction (Sec. 2.4: six-point central for the
+ * third- and fifth-order schemes, eight-point for the seventh-order ones),
+ * evaluated on coordinate differences.  In 2-D:
  * xi_x^ = y_eta, xi_y^ = -x_eta, eta_x^ = -y_xi, eta_y^ = x_xi,
  * J^{-1} = x_xi y_eta - x_eta y_xi.  Midpoint metrics interpolate the nodal
  * ones in their own direction.  Fills the ghost band and the tag of M and
@@ -131,7 +141,8 @@ int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double*
 
 /* ---- Adjoints (metrics held fixed) ------------------------------------------
  * Reverse-mode derivatives of the residual and of one RK3 step with respect
- * to the state, for gradients through time integration.  Non-smooth points:
+ * to the state, for gradients through time integration.  Third- and
+ * fifth-order schemes only (WIU_EINVAL for the seventh-order ones).  Non-smooth points:
  * the line eigenvalue's maximum passes its adjoint to the first maximal node
  * of the line; |U^| has derivative sign(U^) with sign(0) = 0.  The result is
  * deterministic (no floating-point atomics). */

@@ -16,8 +16,8 @@ namespace wiu {
 WIU_DEV void weno5_vjp(double a, double b, double d, double e, double eps, int ppm, double ob, double& ab,
                        double& bb, double& db, double& eb) {
   const double C[3] = {0.0625, 0.625, 0.3125};
-  const double MA[3] = {WIU_M3A0, WIU_M3A1, WIU_M3A2};
-  const double MB[3] = {WIU_M3B0, WIU_M3B1, WIU_M3B2};
+  const double KL[3] = {WIU_M3L0, WIU_M3L1, WIU_M3L2};
+  const double KH[3] = {WIU_M3H0, WIU_M3H1, WIU_M3H2};
   const double p[3] = {0.375 * a - 1.25 * b, 0.375 * d - 0.125 * b, 0.75 * d - 0.125 * e};
   const double d1 = b - a, d2 = -b, d3 = d, d4 = e - d;
   const double t[3] = {d2 - d1, d3 - d2, d4 - d3};
@@ -35,7 +35,7 @@ WIU_DEV void weno5_vjp(double a, double b, double d, double e, double eps, int p
   for (int k = 0; k < 3; ++k) {
     w[k] = al[k] * r;
     dw[k] = w[k] - C[k];
-    h[k] = fma(MA[k], dw[k], MB[k] * fabs(dw[k]));  // K d
+    h[k] = (dw[k] > 0.0 ? KH[k] : KL[k]) * dw[k];  // K d
     g[k] = ppm ? fma(dw[k] * dw[k], h[k], C[k]) : w[k];
   }
   const double sg = g[0] + g[1] + g[2];
@@ -81,8 +81,8 @@ WIU_DEV void weno5_vjp(double a, double b, double d, double e, double eps, int p
 WIU_DEV void weno3_vjp(double a, double b, double d, double eps, int ppm, double ob, double& ab, double& bb,
                        double& db) {
   const double C[2] = {0.25, 0.75};
-  const double MA[2] = {WIU_M2A0, WIU_M2A1};
-  const double MB[2] = {WIU_M2B0, WIU_M2B1};
+  const double KL[2] = {WIU_M2L0, WIU_M2L1};
+  const double KH[2] = {WIU_M2H0, WIU_M2H1};
   const double p[2] = {-0.5 * b, 0.5 * d};
   const double d1 = b - a, d2 = -b, d3 = d;
   const double t[2] = {d2 - d1, d3 - d2};
@@ -100,7 +100,7 @@ WIU_DEV void weno3_vjp(double a, double b, double d, double eps, int ppm, double
   for (int k = 0; k < 2; ++k) {
     w[k] = al[k] * r;
     dw[k] = w[k] - C[k];
-    h[k] = fma(MA[k], dw[k], MB[k] * fabs(dw[k]));  // K d
+    h[k] = (dw[k] > 0.0 ? KH[k] : KL[k]) * dw[k];  // K d
     g[k] = ppm ? fma(dw[k], h[k], C[k]) : w[k];
   }
   const double sg = g[0] + g[1];

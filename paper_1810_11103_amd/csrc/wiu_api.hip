@@ -55,7 +55,7 @@ struct WsLayout {
 WsLayout layout(const wiu_grid* g) {
   WsLayout L;
   const size_t np = (size_t)g->nx * g->ny;
-  const int B = GHOST + 3;
+  const int B = GHOST + 4;  // widest nodal-metric band (eight-point interpolation)
   const size_t band = 5 * (size_t)(g->nx + 2 * B) * (g->ny + 2 * B);
   const size_t plane4 = align_up(4 * np * 8);
   L.lam = ALIGN;
@@ -96,7 +96,9 @@ bool params_ok(const wiu_params* p) {
   return p && p->gamma > 1.0 && p->alpha_lf > 0.0 && p->eps >= 0.0 && (p->ppm == 0 || p->ppm == 1);
 }
 
-bool scheme_ok(int s) { return s >= 0 && s <= 3; }
+bool scheme_ok(int s) { return s >= 0 && s <= 7; }
+// The adjoint covers the third- and fifth-order schemes.
+bool adjoint_scheme_ok(int s) { return s >= 0 && s <= 3; }
 
 Dims dims(const wiu_grid* g) {
   Dims d;
@@ -340,7 +342,8 @@ int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double*
 
 int wiu_rhs_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M,
                 const double* Gbar, double* Ubar, void* ws, wiu_stream_t stream) {
-  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !Gbar || !Ubar || !ws) return WIU_EINVAL;
+  if (!grid_ok(g) || !adjoint_scheme_ok(scheme) || !params_ok(p) || !U || !M || !Gbar || !Ubar || !ws)
+    return WIU_EINVAL;
   if (Ubar == U || Ubar == Gbar) return WIU_EINVAL;
   Ws w = carve(g, ws);
   return residual_vjp(g, scheme, p, U, M, Gbar, Ubar, w, (hipStream_t)stream);
@@ -362,7 +365,8 @@ int wiu_rk3_step_stages(const wiu_grid* g, int scheme, const wiu_params* p, doub
 int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U_n, const double* U1,
                      const double* U2, const void* rec, const double* M, const double* dt_dev,
                      const double* Ubar_np1, double* Ubar_n, void* ws, wiu_stream_t stream) {
-  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U_n || !M || !dt_dev || !Ubar_np1 || !Ubar_n || !ws)
+  if (!grid_ok(g) || !adjoint_scheme_ok(scheme) || !params_ok(p) || !U_n || !M || !dt_dev || !Ubar_np1 || !Ubar_n ||
+      !ws)
     return WIU_EINVAL;
   if ((U1 == nullptr) != (U2 == nullptr)) return WIU_EINVAL;
   if (rec && !U1) return WIU_EINVAL;

@@ -114,7 +114,7 @@ int wiu_batched_plan(const wiu_block* blocks, int nblocks, int scheme, const wiu
                      int eta_variant, double* U_all, const double* M_all, wiu_plan** out) {
   if (!out) return WIU_EINVAL;
   *out = nullptr;
-  if (!blocks || nblocks < 1 || scheme < 0 || scheme > 3 || !params || !U_all || !M_all) return WIU_EINVAL;
+  if (!blocks || nblocks < 1 || scheme < 0 || scheme > 7 || !params || !U_all || !M_all) return WIU_EINVAL;
   if (!(params->gamma > 1.0) || !(params->alpha_lf > 0.0) || !(params->eps >= 0.0)) return WIU_EINVAL;
   if (xi_variant < 0 || xi_variant >= wiu_tuning_variants(0)) return WIU_EINVAL;
   if (eta_variant < 0 || eta_variant >= wiu_tuning_variants(1)) return WIU_EINVAL;

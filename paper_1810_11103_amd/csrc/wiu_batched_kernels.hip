@@ -30,7 +30,7 @@ WIU_DEV double* stage_dst(const BatchArgs& b, const BlockDev& B, int st) {
 }
 
 template <int SC, int DIR, int NA, int NB>
-__global__ void __launch_bounds__(NA * NB, 4) batched_sweep_kernel(BatchArgs b) {
+__global__ void __launch_bounds__(NA * NB, sweep_waves<SC>()) batched_sweep_kernel(BatchArgs b) {
   __shared__ SweepLds<SC, DIR, NA, NB> lds;
   {
     const int4 tl = uniform_tile(b);
@@ -113,7 +113,16 @@ hipError_t launch_batched_sweep(int scheme, int dir, int variant, const BatchArg
     case 4: return launch_batched_sweep_v<2, 0>(variant, a, st);
     case 5: return launch_batched_sweep_v<2, 1>(variant, a, st);
     case 6: return launch_batched_sweep_v<3, 0>(variant, a, st);
-    default: return launch_batched_sweep_v<3, 1>(variant, a, st);
+    case 7: return launch_batched_sweep_v<3, 1>(variant, a, st);
+    case 8: return launch_batched_sweep_v<4, 0>(variant, a, st);
+    case 9: return launch_batched_sweep_v<4, 1>(variant, a, st);
+    case 10: return launch_batched_sweep_v<5, 0>(variant, a, st);
+    case 11: return launch_batched_sweep_v<5, 1>(variant, a, st);
+    case 12: return launch_batched_sweep_v<6, 0>(variant, a, st);
+    case 13: return launch_batched_sweep_v<6, 1>(variant, a, st);
+    case 14: return launch_batched_sweep_v<7, 0>(variant, a, st);
+    case 15: return launch_batched_sweep_v<7, 1>(variant, a, st);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -131,7 +140,12 @@ int scheme_extra(int scheme) {
     case 0: return Range<0>::EXTRA;
     case 1: return Range<1>::EXTRA;
     case 2: return Range<2>::EXTRA;
-    default: return Range<3>::EXTRA;
+    case 3: return Range<3>::EXTRA;
+    case 4: return Range<4>::EXTRA;
+    case 5: return Range<5>::EXTRA;
+    case 6: return Range<6>::EXTRA;
+    case 7: return Range<7>::EXTRA;
+    default: return -1;
   }
 }
 

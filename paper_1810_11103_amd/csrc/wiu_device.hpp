@@ -103,24 +103,44 @@ WIU_DEV double rsqrt_(double x) {
 template <int SC> struct Traits;
 template <> struct Traits<0> {  // WENOIU3-1MP, Eq. 3.4
   static constexpr bool fifth = false, two_mp = false;
-  static constexpr int NLO = -2, NHI = 2, MLO = -1, MHI = 0;
+  static constexpr int R = 2, NLO = -2, NHI = 2, MLO = -1, MHI = 0;
 };
 template <> struct Traits<1> {  // WENOIU3-2MP, Eq. 3.8
   static constexpr bool fifth = false, two_mp = true;
-  static constexpr int NLO = -1, NHI = 1, MLO = -2, MHI = 1;
+  static constexpr int R = 2, NLO = -1, NHI = 1, MLO = -2, MHI = 1;
 };
 template <> struct Traits<2> {  // WENOIU5-1MP, Eq. 3.16
   static constexpr bool fifth = true, two_mp = false;
-  static constexpr int NLO = -3, NHI = 3, MLO = -1, MHI = 0;
+  static constexpr int R = 3, NLO = -3, NHI = 3, MLO = -1, MHI = 0;
 };
 template <> struct Traits<3> {  // WENOIU5-2MP, Eq. 3.20
   static constexpr bool fifth = true, two_mp = true;
-  static constexpr int NLO = -2, NHI = 2, MLO = -2, MHI = 1;
+  static constexpr int R = 3, NLO = -2, NHI = 2, MLO = -2, MHI = 1;
+};
+// Seventh-order schemes of the Appendix (R = 4 interpolation, Table A1).
+template <> struct Traits<4> {  // WENOIU7-1MP
+  static constexpr bool fifth = false, two_mp = false;
+  static constexpr int R = 4, NLO = -4, NHI = 4, MLO = -1, MHI = 0;
+};
+template <> struct Traits<5> {  // WENOIU7-2MP
+  static constexpr bool fifth = false, two_mp = true;
+  static constexpr int R = 4, NLO = -3, NHI = 3, MLO = -2, MHI = 1;
+};
+template <> struct Traits<6> {  // WENOIU7-4MP
+  static constexpr bool fifth = false, two_mp = false;
+  static constexpr int R = 4, NLO = -2, NHI = 2, MLO = -3, MHI = 2;
+};
+template <> struct Traits<7> {  // WENOIU7-6MP
+  static constexpr bool fifth = false, two_mp = false;
+  static constexpr int R = 4, NLO = -1, NHI = 1, MLO = -4, MHI = 3;
 };
 template <int SC> struct Range {
   static constexpr int LO = Traits<SC>::NLO < Traits<SC>::MLO ? Traits<SC>::NLO : Traits<SC>::MLO;
   static constexpr int HI = Traits<SC>::NHI > Traits<SC>::MHI ? Traits<SC>::NHI : Traits<SC>::MHI;
   static constexpr int EXTRA = HI - LO;
+  // states a midpoint flux reads on each side of its item k: Q_{k-QL} ..
+  // Q_{k+QL+1} (the R = 4 interpolation reaches one node further)
+  static constexpr int QL = Traits<SC>::R == 4 ? 3 : 2;
 };
 
 // ---------------------------------------------------------------------------
@@ -135,31 +155,32 @@ template <int SC> struct Range {
 //   third order:  g = C + K d^3, K = 1/C^2 for d <= 0, 1/(C-1)^2 above
 //   second order: g = C + K d^2, K = -1/C for d <= 0, 1/(1-C) above
 // (C[1 + (w/C - 1)^3] = C + d^3/C^2 and C[1 - (w/C - 1)^2] = C - d^2/C).
-// The piecewise constant K is folded into |d| without a branch: with
-// A = (K_lo + K_hi)/2 and B = (K_hi - K_lo)/2,
-//   K d^3 = d^2 (A d + B |d|)   and   K d^2 = d (A d + B |d|).
-WIU_DEV double map3(double w, double C, double A, double B) {
+// The piecewise constant K is a select on the sign of d (no branch).  (Folding
+// it into |d| as d (A d + B |d|) with A, B = (K_hi +- K_lo)/2 would cancel
+// badly where |K_lo| >> |K_hi|: up to 2e5 times for the fourth-order
+// mapping at C = 1/64.)
+WIU_DEV double map3(double w, double C, double Klo, double Khi) {
   const double d = w - C;
-  return fma(d * d, fma(A, d, B * fabs(d)), C);
+  return fma(d * d, (d > 0.0 ? Khi : Klo) * d, C);
 }
-WIU_DEV double map2(double w, double C, double A, double B) {
+WIU_DEV double map2(double w, double C, double Klo, double Khi) {
   const double d = w - C;
-  return fma(d, fma(A, d, B * fabs(d)), C);
+  return fma(d, (d > 0.0 ? Khi : Klo) * d, C);
 }
 
-// (A, B) pairs of the mappings for the linear weights of Table 1.
+// (K_lo, K_hi) of the mappings for the linear weights of Table 1.
 //   r = 3: C = 1/16, 10/16, 5/16, K_lo = 1/C^2, K_hi = 1/(C-1)^2
 //   r = 2: C = 1/4, 3/4,          K_lo = -1/C,  K_hi = 1/(1-C)
-#define WIU_M3A0 ((256.0 + 256.0 / 225.0) * 0.5)
-#define WIU_M3B0 ((256.0 / 225.0 - 256.0) * 0.5)
-#define WIU_M3A1 ((2.56 + 64.0 / 9.0) * 0.5)
-#define WIU_M3B1 ((64.0 / 9.0 - 2.56) * 0.5)
-#define WIU_M3A2 ((10.24 + 256.0 / 121.0) * 0.5)
-#define WIU_M3B2 ((256.0 / 121.0 - 10.24) * 0.5)
-#define WIU_M2A0 ((-4.0 + 4.0 / 3.0) * 0.5)
-#define WIU_M2B0 ((4.0 / 3.0 + 4.0) * 0.5)
-#define WIU_M2A1 ((-4.0 / 3.0 + 4.0) * 0.5)
-#define WIU_M2B1 ((4.0 + 4.0 / 3.0) * 0.5)
+#define WIU_M3L0 256.0
+#define WIU_M3H0 (256.0 / 225.0)
+#define WIU_M3L1 2.56
+#define WIU_M3H1 (64.0 / 9.0)
+#define WIU_M3L2 10.24
+#define WIU_M3H2 (256.0 / 121.0)
+#define WIU_M2L0 (-4.0)
+#define WIU_M2H0 (4.0 / 3.0)
+#define WIU_M2L1 (-4.0 / 3.0)
+#define WIU_M2H1 4.0
 
 // r = 3: left-biased value at k+1/2 from v_{k-2}, v_{k-1}, v_k = 0, v_{k+1},
 // v_{k+2} = (a, b, 0, d, e).  Candidates from Table 1 (b_{k,l}), linear
@@ -183,9 +204,9 @@ WIU_DEV double weno5(double a, double b, double d, double e, double eps, int ppm
   const double r = rcp(a0 + a1 + a2);
   double w0 = a0 * r, w1 = a1 * r, w2 = a2 * r;
   if (ppm) {
-    w0 = map3(w0, 0.0625, WIU_M3A0, WIU_M3B0);
-    w1 = map3(w1, 0.625, WIU_M3A1, WIU_M3B1);
-    w2 = map3(w2, 0.3125, WIU_M3A2, WIU_M3B2);
+    w0 = map3(w0, 0.0625, WIU_M3L0, WIU_M3H0);
+    w1 = map3(w1, 0.625, WIU_M3L1, WIU_M3H1);
+    w2 = map3(w2, 0.3125, WIU_M3L2, WIU_M3H2);
   }
   return (w0 * p0 + w1 * p1 + w2 * p2) * rcp(w0 + w1 + w2);
 }
@@ -207,10 +228,67 @@ WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
   const double r = rcp(a0 + a1);
   double w0 = a0 * r, w1 = a1 * r;
   if (ppm) {
-    w0 = map2(w0, 0.25, WIU_M2A0, WIU_M2B0);
-    w1 = map2(w1, 0.75, WIU_M2A1, WIU_M2B1);
+    w0 = map2(w0, 0.25, WIU_M2L0, WIU_M2H0);
+    w1 = map2(w1, 0.75, WIU_M2L1, WIU_M2H1);
   }
   return (w0 * p0 + w1 * p1) * rcp(w0 + w1);
+}
+
+// Fourth-order mapping of the Appendix, g = C (1 - (w/C - 1)^4) below C and
+// C - (w - C)^4 / (C - 1)^3 above, i.e. g = C + K d^4 with K = -1/C^3 for
+// d <= 0 and 1/(1-C)^3 above.
+WIU_DEV double map4(double w, double C, double Klo, double Khi) {
+  const double d = w - C;
+  const double d2 = d * d;
+  return fma(d2, (d > 0.0 ? Khi : Klo) * d2, C);
+}
+//   C = 1/64, 21/64, 35/64, 7/64: K_lo = -(64/(64 C))^3, K_hi = (64/(64 - 64 C))^3
+#define WIU_M4L0 (-262144.0)
+#define WIU_M4H0 (262144.0 / 250047.0)
+#define WIU_M4L1 (-262144.0 / 9261.0)
+#define WIU_M4H1 (262144.0 / 79507.0)
+#define WIU_M4L2 (-262144.0 / 42875.0)
+#define WIU_M4H2 (262144.0 / 24389.0)
+#define WIU_M4L3 (-262144.0 / 343.0)
+#define WIU_M4H3 (262144.0 / 185193.0)
+
+// r = 4: left-biased value at k+1/2 from v_{k-3..k+3} = (a, b, c, 0, e, f, g)
+// (seventh-order schemes, Appendix).  Candidates and linear weights
+// (1, 21, 35, 7)/64 of Table A1.  The paper prints no r = 4 indicators; the
+// Jiang-Shu definition that gives its r = 3 ones is used, written as a sum
+// of squares: with p = c0 + c1 x + c2 x^2 + c3 x^3 the stencil's cubic on
+// the unit cell around k,
+//   IS = sum_{l=1..3} int (p^(l))^2 = (c1 + c3/4)^2 + 13/3 c2^2 + 781/20 c3^2,
+// where c1 + c3/4, c2 and c3 are fixed differences of the stencil values.
+// Weights as in weno5 (products of the squared denominators, one
+// reciprocal), mapping map4, re-normalisation.
+WIU_DEV double weno7(double a, double b, double c, double e, double f, double g, double eps, int ppm) {
+  const double p0 = (-5.0 * a + 21.0 * b - 35.0 * c) * 0.0625;
+  const double p1 = (b - 5.0 * c + 5.0 * e) * 0.0625;
+  const double p2 = (-c + 9.0 * e - f) * 0.0625;
+  const double p3 = (15.0 * e - 5.0 * f + g) * 0.0625;
+  auto is = [&](double y1, double c2, double c3) {
+    return eps + fma(y1, y1, fma(13.0 / 3.0, c2 * c2, (781.0 / 20.0) * (c3 * c3)));
+  };
+  const double ce = 0.5 * (c + e);  // c2 of the two central stencils
+  double D0 = is(fma(1.5, b, fma(-1.0 / 3.0, a, -3.0 * c)), fma(2.0, b, fma(-0.5, a, -2.5 * c)),
+                 (-a + 3.0 * (b - c)) * (1.0 / 6.0));
+  double D1 = is(fma(1.0 / 6.0, b, fma(1.0 / 3.0, e, -c)), ce, (3.0 * c - b + e) * (1.0 / 6.0));
+  double D2 = is(fma(-1.0 / 3.0, c, fma(-1.0 / 6.0, f, e)), ce, (f - c - 3.0 * e) * (1.0 / 6.0));
+  double D3 = is(fma(3.0, e, fma(1.0 / 3.0, g, -1.5 * f)), fma(2.0, f, fma(-2.5, e, -0.5 * g)),
+                 (3.0 * (e - f) + g) * (1.0 / 6.0));
+  D0 *= D0; D1 *= D1; D2 *= D2; D3 *= D3;
+  const double P01 = D0 * D1, P23 = D2 * D3;
+  const double a0 = (D1 * P23), a1 = 21.0 * (D0 * P23), a2 = 35.0 * (D3 * P01), a3 = 7.0 * (D2 * P01);
+  const double r = rcp((a0 + a1) + (a2 + a3));
+  double w0 = a0 * r, w1 = a1 * r, w2 = a2 * r, w3 = a3 * r;
+  if (ppm) {
+    w0 = map4(w0, 1.0 / 64.0, WIU_M4L0, WIU_M4H0);
+    w1 = map4(w1, 21.0 / 64.0, WIU_M4L1, WIU_M4H1);
+    w2 = map4(w2, 35.0 / 64.0, WIU_M4L2, WIU_M4H2);
+    w3 = map4(w3, 7.0 / 64.0, WIU_M4L3, WIU_M4H3);
+  }
+  return (w0 * p0 + w1 * p1 + w2 * p2 + w3 * p3) * rcp((w0 + w1) + (w2 + w3));
 }
 
 // ---------------------------------------------------------------------------
@@ -274,6 +352,83 @@ WIU_DEV void side_flux(QF q, int side, double nx_, double ny_, double mx, double
   const double r2 = Qr[2] + (v * sum + c * ny_ * d30 + nx_ * W[2]);
   const double r3 = Qr[3] + (H * s03 + c * qn * d30 + 0.5 * q2 * W[1] + qt * W[2]);
   // contravariant flux with the midpoint metric, then the split part
+  const double ri = rcp(r0);
+  const double ul = r1 * ri, vl = r2 * ri;
+  const double pl = gm1 * (r3 - 0.5 * (r1 * ul + r2 * vl));
+  const double Ul = mx * ul + my * vl;
+  const double sl = side == 0 ? lam : -lam;
+  F[0] = 0.5 * (r0 * Ul + sl * r0);
+  F[1] = 0.5 * (r1 * Ul + mx * pl + sl * r1);
+  F[2] = 0.5 * (r2 * Ul + my * pl + sl * r2);
+  F[3] = 0.5 * ((r3 + pl) * Ul + sl * r3);
+}
+
+// The same for the seventh-order schemes: q(m, c), m = 0..7, holds the states
+// at k-3 .. k+4; side 0 is left-biased over k-3..k+3 (reference Q_k), side 1
+// right-biased over k+4..k-2 (reference Q_{k+1}).  The characteristic
+// fields are projected and interpolated in two passes over the stencil,
+// fields 0 and 3 (which share A and B) and then fields 1 and 2, each pass
+// re-reading the states from LDS: twelve projected values are live at a time
+// instead of twenty-four (compiler barriers keep the passes apart).
+template <class QF>
+WIU_DEV void side_flux7(QF q, int side, double nx_, double ny_, double mx, double my, double lam, double gam,
+                        double eps, int ppm, double F[4]) {
+  const double Qr[4] = {q(3 + side, 0), q(3 + side, 1), q(3 + side, 2), q(3 + side, 3)};
+  const double gm1 = gam - 1.0;
+  const double rr = rcp(Qr[0]);
+  const double u = Qr[1] * rr, v = Qr[2] * rr;
+  const double q2 = u * u + v * v;
+  const double p = gm1 * (Qr[3] - 0.5 * Qr[0] * q2);
+  const double c2 = gam * p * rr;
+  const double rc = rsqrt_(c2);
+  const double c = c2 * rc;
+  const double H = (Qr[3] + p) * rr;
+  const double qn = u * nx_ + v * ny_;
+  const double qt = v * nx_ - u * ny_;
+  const double b1 = gm1 * (rc * rc);
+  const double b2 = 0.5 * b1 * q2;
+
+  // stencil position s = 0..6 (s = 3 the reference node) -> window index
+  auto mi = [&](int s) { return side == 0 ? s : 7 - s; };
+  double W[4];
+  {
+    double w0[7], w3[7];
+#pragma unroll
+    for (int s = 0; s < 7; ++s) {
+      if (s == 3) continue;
+      const int m = mi(s);
+      const double dr = q(m, 0) - Qr[0], dm = q(m, 1) - Qr[1], dn = q(m, 2) - Qr[2], de = q(m, 3) - Qr[3];
+      const double A = b2 * dr - b1 * (u * dm + v * dn - de);
+      const double B = rc * (qn * dr - nx_ * dm - ny_ * dn);
+      w0[s] = 0.5 * (A + B);
+      w3[s] = 0.5 * (A - B);
+    }
+    W[0] = weno7(w0[0], w0[1], w0[2], w0[4], w0[5], w0[6], eps, ppm);
+    asm volatile("" ::: "memory");
+    W[3] = weno7(w3[0], w3[1], w3[2], w3[4], w3[5], w3[6], eps, ppm);
+  }
+  asm volatile("" ::: "memory");
+  {
+    double w1[7], w2[7];
+#pragma unroll
+    for (int s = 0; s < 7; ++s) {
+      if (s == 3) continue;
+      const int m = mi(s);
+      const double dr = q(m, 0) - Qr[0], dm = q(m, 1) - Qr[1], dn = q(m, 2) - Qr[2], de = q(m, 3) - Qr[3];
+      const double A = b2 * dr - b1 * (u * dm + v * dn - de);
+      w1[s] = dr - A;
+      w2[s] = nx_ * dn - ny_ * dm - qt * dr;
+    }
+    W[1] = weno7(w1[0], w1[1], w1[2], w1[4], w1[5], w1[6], eps, ppm);
+    asm volatile("" ::: "memory");
+    W[2] = weno7(w2[0], w2[1], w2[2], w2[4], w2[5], w2[6], eps, ppm);
+  }
+  const double s03 = W[0] + W[3], d30 = W[3] - W[0];
+  const double sum = s03 + W[1];
+  const double r0 = Qr[0] + sum;
+  const double r1 = Qr[1] + (u * sum + c * nx_ * d30 - ny_ * W[2]);
+  const double r2 = Qr[2] + (v * sum + c * ny_ * d30 + nx_ * W[2]);
+  const double r3 = Qr[3] + (H * s03 + c * qn * d30 + 0.5 * q2 * W[1] + qt * W[2]);
   const double ri = rcp(r0);
   const double ul = r1 * ri, vl = r2 * ri;
   const double pl = gm1 * (r3 - 0.5 * (r1 * ul + r2 * vl));
@@ -349,9 +504,33 @@ WIU_DEV double wave_speed(const double Q[4], double kx, double ky, double gam, b
 
 // ---------------------------------------------------------------------------
 // Upwind-biased numerical flux H_{i+1/2} = h^+ + h^- (Eqs. 3.4, 3.8, 3.16,
-// 3.20, alpha = 1; h^- is h^+ mirrored about i+1/2).  fp(k), fm(k): nodal
-// split fluxes at node k; Fp(k), Fm(k): midpoint split fluxes at k+1/2.
+// 3.20 and the Appendix, alpha = 1; h^- is h^+ mirrored about i+1/2).
+// fp(k), fm(k): nodal split fluxes at node k; Fp(k), Fm(k): midpoint split
+// fluxes at k+1/2.
 // ---------------------------------------------------------------------------
+
+// h^+_{i+1/2} of the seventh-order schemes from f(m) = f_{i+m} and
+// F(m) = f_{i+1/2+m}.  Two printed coefficients are read as corrected, as
+// the central-scheme decomposition (Eq. 2.7) into the printed central
+// operators requires: 7-2MP's f_i weight -93 (printed -92), 7-6MP's node term
+// 3840 f_i (printed at f_{i-1}).
+template <int SC, class NF, class MF>
+WIU_DEV double h7_plus(NF f, MF F) {
+  if constexpr (SC == 4) {
+    return F(0) + (1.0 / 107520.0) * (-243.0 * f(-3) + 1990.0 * f(-2) - 7481.0 * f(-1) + 8164.0 * f(0) -
+                                      341.0 * f(1) - 2378.0 * f(2) + 289.0 * f(3));
+  } else if constexpr (SC == 5) {
+    return F(0) + (1.0 / 1260.0) * (-128.0 * F(-1) + 404.0 * F(0) - 2.0 * f(-2) + 47.0 * f(-1) - 93.0 * f(0) -
+                                    233.0 * f(1) + 5.0 * f(2));
+  } else if constexpr (SC == 6) {
+    return F(0) + (1.0 / 420.0) * (18.0 * f(-1) - 66.0 * f(0) - 108.0 * f(1) - 3.0 * F(-2) - 31.0 * F(-1) +
+                                   179.0 * F(0) + 11.0 * F(1));
+  } else {
+    return F(0) + (1.0 / 26880.0) * (3840.0 * f(0) - 45.0 * F(-3) + 501.0 * F(-2) - 3874.0 * F(-1) +
+                                     746.0 * F(0) - 1249.0 * F(1) + 81.0 * F(2));
+  }
+}
+
 template <int SC, class FP, class FM, class GP, class GM>
 WIU_DEV double hflux(int i, FP fp, FM fm, GP Fp, GM Fm) {
   if constexpr (SC == 0) {
@@ -365,9 +544,12 @@ WIU_DEV double hflux(int i, FP fp, FM fm, GP Fp, GM Fm) {
                                      21.0 * fp(i + 2)) +
            Fm(i) + (1.0 / 1920.0) * (19.0 * fm(i + 3) - 116.0 * fm(i + 2) + 154.0 * fm(i + 1) - 36.0 * fm(i) -
                                      21.0 * fm(i - 1));
-  } else {
+  } else if constexpr (SC == 3) {
     return Fp(i) + (1.0 / 30.0) * (fp(i - 1) + fp(i) - 4.0 * fp(i + 1) + 6.0 * Fp(i) - 4.0 * Fp(i - 1)) +
            Fm(i) + (1.0 / 30.0) * (fm(i + 2) + fm(i + 1) - 4.0 * fm(i) + 6.0 * Fm(i) - 4.0 * Fm(i + 1));
+  } else {
+    return h7_plus<SC>([&](int m) { return fp(i + m); }, [&](int m) { return Fp(i + m); }) +
+           h7_plus<SC>([&](int m) { return fm(i + 1 - m); }, [&](int m) { return Fm(i - m); });
   }
 }
 

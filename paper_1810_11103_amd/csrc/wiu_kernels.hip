@@ -97,16 +97,31 @@ WIU_DEV double diff_j(const Dims& d, const double* c, bool is_y, int a, int b1, 
   return col(a);
 }
 
-// Each scheme's central operator delta^{c,(1)} (Eqs. 3.7, 3.9, 3.19, 3.21)
-// with the six-point midpoint interpolation
-// (3 g_{i-2} - 25 g_{i-1} + 150 g_i + 150 g_{i+1} - 25 g_{i+2} + 3 g_{i+3}) / 256
-// substituted is an antisymmetric node stencil sum_m d_m (g_{i+m} - g_{i-m}):
-__constant__ double kMetricStencil[4][4] = {
-    {557.0 / 768.0, -25.0 / 192.0, 3.0 / 256.0, 0.0},                 // 3-1MP
-    {1145.0 / 1536.0, -229.0 / 1536.0, 29.0 / 1536.0, -1.0 / 1024.0},  // 3-2MP
-    {3.0 / 4.0, -3.0 / 20.0, 1.0 / 60.0, 0.0},                        // 5-1MP
-    {487.0 / 640.0, -103.0 / 640.0, 41.0 / 1920.0, -1.0 / 1280.0},    // 5-2MP
+// Each scheme's central operator delta^{c,(1)} (Eqs. 3.7, 3.9, 3.19, 3.21 and
+// the Appendix) with the midpoint values replaced by the scheme's linear
+// midpoint interpolation -- six points for the third- and fifth-order
+// schemes, (3 g_{i-2} - 25 g_{i-1} + 150 g_i + 150 g_{i+1} - 25 g_{i+2} +
+// 3 g_{i+3}) / 256, eight for the seventh-order ones, (-5 g_{i-3} + 49 g_{i-2}
+// - 245 g_{i-1} + 1225 g_i + 1225 g_{i+1} - 245 g_{i+2} + 49 g_{i+3} -
+// 5 g_{i+4}) / 2048 -- is an antisymmetric node stencil
+// sum_m d_m (g_{i+m} - g_{i-m}), m = 1..7 (exact rationals):
+constexpr int METRIC_REACH = 7;
+__constant__ double kMetricStencil[8][METRIC_REACH] = {
+    {557.0 / 768.0, -25.0 / 192.0, 3.0 / 256.0, 0.0, 0.0, 0.0, 0.0},                   // 3-1MP
+    {1145.0 / 1536.0, -229.0 / 1536.0, 29.0 / 1536.0, -1.0 / 1024.0, 0.0, 0.0, 0.0},    // 3-2MP
+    {3.0 / 4.0, -3.0 / 20.0, 1.0 / 60.0, 0.0, 0.0, 0.0, 0.0},                          // 5-1MP
+    {487.0 / 640.0, -103.0 / 640.0, 41.0 / 1920.0, -1.0 / 1280.0, 0.0, 0.0, 0.0},      // 5-2MP
+    {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0, 0.0, 0.0, 0.0},                 // 7-1MP
+    {773.0 / 960.0, -173.0 / 840.0, 557.0 / 13440.0, -23.0 / 5040.0, 1.0 / 8064.0, 0.0, 0.0},  // 7-2MP
+    {114831.0 / 143360.0, -115271.0 / 573440.0, 4733.0 / 122880.0, -221.0 / 61440.0, -31.0 / 860160.0,
+     1.0 / 114688.0, 0.0},                                                              // 7-4MP
+    {5983587.0 / 7340032.0, -57115.0 / 262144.0, 153455.0 / 3145728.0, -1411.0 / 196608.0,
+     10039.0 / 15728640.0, -89.0 / 1835008.0, 15.0 / 7340032.0},                        // 7-6MP
 };
+
+// Nodal-metric band beyond the stored ghost band: the reach of the midpoint
+// interpolation (3 for six points, 4 for eight).
+inline int metric_band(int scheme) { return GHOST + (scheme >= 4 ? 4 : 3); }
 
 // Nodal metrics on the band of width B around the grid: T[5][(ny+2B)(nx+2B)].
 // Periodic directions evaluate at the wrapped node so that band copies are
@@ -122,7 +137,7 @@ __global__ void metrics_nodal_kernel(Dims d, int scheme, int B, const double* __
   if (d.bcy == 0) b = bc_index(b, d.ny, 0);
   double x_xi = 0.0, y_xi = 0.0, x_eta = 0.0, y_eta = 0.0;
 #pragma unroll
-  for (int m = 1; m <= 4; ++m) {
+  for (int m = 1; m <= METRIC_REACH; ++m) {
     const double cm = kMetricStencil[scheme][m - 1];
     if (cm == 0.0) continue;
     x_xi += cm * diff_i(d, x, true, b, a + m, a - m);
@@ -160,10 +175,13 @@ __global__ void metrics_band_kernel(Dims d, int scheme, int B, const double* __r
 #pragma unroll
   for (int p = 0; p < 5; ++p) M[p * P + o] = t(p, a, b);
   // midpoint metrics: the same interpolation in the metric's own direction
+  const bool eight = scheme >= 4;
   auto I = [&](int p, int di, int dj) {
-    return (3.0 * t(p, a - 2 * di, b - 2 * dj) - 25.0 * t(p, a - di, b - dj) + 150.0 * t(p, a, b) +
-            150.0 * t(p, a + di, b + dj) - 25.0 * t(p, a + 2 * di, b + 2 * dj) + 3.0 * t(p, a + 3 * di, b + 3 * dj)) *
-           (1.0 / 256.0);
+    auto v = [&](int l) { return t(p, a + l * di, b + l * dj); };
+    if (eight)
+      return (-5.0 * (v(-3) + v(4)) + 49.0 * (v(-2) + v(3)) - 245.0 * (v(-1) + v(2)) + 1225.0 * (v(0) + v(1))) *
+             (1.0 / 2048.0);
+    return (3.0 * v(-2) - 25.0 * v(-1) + 150.0 * v(0) + 150.0 * v(1) - 25.0 * v(2) + 3.0 * v(3)) * (1.0 / 256.0);
   };
   M[5 * P + o] = I(0, 1, 0);
   M[6 * P + o] = I(1, 1, 0);
@@ -224,7 +242,7 @@ __global__ void lambda_out_kernel(Dims d, double alpha, const unsigned long long
 // Launched for 4 waves per SIMD (at most 128 VGPRs).
 // ===========================================================================
 template <int SC, int DIR, int NA, int NB>
-__global__ void __launch_bounds__(NA * NB, 4) sweep_kernel(SweepArgs s) {
+__global__ void __launch_bounds__(NA * NB, sweep_waves<SC>()) sweep_kernel(SweepArgs s) {
   __shared__ SweepLds<SC, DIR, NA, NB> lds;
   // logical tile in XCD-aware order
   const int total = gridDim.x * gridDim.y;
@@ -278,7 +296,16 @@ hipError_t launch_sweep(int scheme, int dir, int variant, const SweepArgs& a, hi
     case 4: return launch_sweep_v<2, 0>(variant, a, st);
     case 5: return launch_sweep_v<2, 1>(variant, a, st);
     case 6: return launch_sweep_v<3, 0>(variant, a, st);
-    default: return launch_sweep_v<3, 1>(variant, a, st);
+    case 7: return launch_sweep_v<3, 1>(variant, a, st);
+    case 8: return launch_sweep_v<4, 0>(variant, a, st);
+    case 9: return launch_sweep_v<4, 1>(variant, a, st);
+    case 10: return launch_sweep_v<5, 0>(variant, a, st);
+    case 11: return launch_sweep_v<5, 1>(variant, a, st);
+    case 12: return launch_sweep_v<6, 0>(variant, a, st);
+    case 13: return launch_sweep_v<6, 1>(variant, a, st);
+    case 14: return launch_sweep_v<7, 0>(variant, a, st);
+    case 15: return launch_sweep_v<7, 1>(variant, a, st);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -300,7 +327,7 @@ hipError_t launch_fill_u64(unsigned long long* p, long long n, hipStream_t st) {
 
 hipError_t launch_metrics(const Dims& d, int scheme, const double* x, const double* y, double* M, double* T,
                           int* status, hipStream_t st) {
-  const int B = GHOST + 3;
+  const int B = metric_band(scheme);
   dim3 b1(64, 4);
   dim3 g1((d.nx + 2 * B + 63) / 64, (d.ny + 2 * B + 3) / 4);
   hipLaunchKernelGGL(metrics_nodal_kernel, g1, b1, 0, st, d, scheme, B, x, y, T);

@@ -69,6 +69,11 @@ WIU_DEV void wave_max_tile(const Dims& d, const double* __restrict__ U, const do
 }
 
 
+// Waves per SIMD a sweep kernel is compiled for: 4 (at most 128 VGPRs) for
+// the third- and fifth-order schemes; the seventh-order interpolation needs
+// more registers than that without spilling, so 3 (at most 168).
+template <int SC> constexpr int sweep_waves() { return Traits<SC>::R == 4 ? 3 : 4; }
+
 // LDS of a sweep tile.  Lanes of a wave run along the line for xi tiles and
 // across lines (then along) for eta tiles; both arrays are laid out so that
 // the lanes of a wave touch consecutive words (no bank conflicts): line-major
@@ -76,7 +81,7 @@ WIU_DEV void wave_max_tile(const Dims& d, const double* __restrict__ U, const do
 // than f^+- = (E^ +- lam Q)/2, which the output phase rebuilds from E^ and the
 // staged state (12 instead of 16 values per item, so larger tiles fit).
 template <int SC, int DIR, int NA, int NB> struct SweepLds {
-  static constexpr int NQ = NA + 5;  // stencil tile: items k - 2 .. k + 3
+  static constexpr int NQ = NA + 2 * Range<SC>::QL + 1;  // states of items k - QL .. k + QL + 1
   double sh[12][NA * NB];            // [kind*4 + comp][item]: kinds E^, F^+, F^-
   double sq[4][NB * NQ];
   // item slot of (line tb, position ta) and state slot of (line tb, position pos)
@@ -90,7 +95,7 @@ WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB>& L, int tb, int o0, i
   using R_ = Range<SC>;
   using LT = SweepLds<SC, DIR, NA, NB>;
   auto at = [&](int kk) { return LT::si(tb, kk - (o0 + R_::LO)); };      // item slot of node kk
-  auto aq = [&](int kk) { return LT::qi(tb, kk - (o0 + R_::LO) + 2); };  // state slot of node kk
+  auto aq = [&](int kk) { return LT::qi(tb, kk - (o0 + R_::LO) + R_::QL); };  // state slot of node kk
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     asm volatile("" ::: "memory");  // one component at a time (register pressure)
@@ -163,7 +168,8 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   using R_ = Range<SC>;
   constexpr int OUT = NA - R_::EXTRA;
   constexpr int NT = NA * NB;
-  constexpr int NQ = NA + 5;
+  constexpr int QL = R_::QL;
+  constexpr int NQ = SweepLds<SC, DIR, NA, NB>::NQ;
   auto& sh = L.sh;
   auto& sq = L.sq;
 
@@ -212,7 +218,7 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   // consecutive threads reading consecutive addresses.
   {
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-    const int k0 = o0 + R_::LO - 2;
+    const int k0 = o0 + R_::LO - QL;
     for (int e = tid; e < NQ * NB; e += NT) {
       const int pos = DIR == 0 ? e % NQ : e / NB;
       const int lb = DIR == 0 ? e / NQ : e % NB;
@@ -228,12 +234,12 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   __syncthreads();
 
   if (need_node || need_mid) {
-    // stencil states Q_{k-2..k+3}, read from LDS where they are used
+    // stencil states Q_{k-QL..k+QL+1}, read from LDS where they are used
     auto q = [&](int m, int c) { return sq[c][LT::qi(tb, ta + m)]; };
     const long long mo = mline + mstride * k;
     const double kx0 = Mk[mo], ky0 = Mk[d.mplane + mo];
     if (need_node) {
-      const double qk[4] = {q(2, 0), q(2, 1), q(2, 2), q(2, 3)};
+      const double qk[4] = {q(QL, 0), q(QL, 1), q(QL, 2), q(QL, 3)};
       double E[4];
       nodal_flux(qk, kx0, ky0, gam, E);
 #pragma unroll
@@ -251,7 +257,10 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
       for (int side = 0; side < 2; ++side) {
         asm volatile("" ::: "memory");
         double F[4];
-        side_flux<Traits<SC>::fifth>(q, side, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, F);
+        if constexpr (Traits<SC>::R == 4)
+          side_flux7(q, side, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, F);
+        else
+          side_flux<Traits<SC>::fifth>(q, side, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, F);
 #pragma unroll
         for (int c = 0; c < 4; ++c) sh[4 + 4 * side + c][slot] = F[c];
       }
@@ -309,7 +318,7 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
     // into the R^xi buffer; the stage state at the output node is the staged
     // tile entry (an interior node, untouched by the boundary rule), and U0
     // is not read when its coefficient is zero (first stage)
-    const int pq = LT::qi(tb, i - (o0 + R_::LO - 2));
+    const int pq = LT::qi(tb, i - (o0 + R_::LO - QL));
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double un = s.cb * (sq[c][pq] + dt * (R[c] * rj));

@@ -13,7 +13,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwenoiu.so")
 
-SCHEMES = {"3-1MP": 0, "3-2MP": 1, "5-1MP": 2, "5-2MP": 3}
+SCHEMES = {"3-1MP": 0, "3-2MP": 1, "5-1MP": 2, "5-2MP": 3, "7-1MP": 4, "7-2MP": 5, "7-4MP": 6, "7-6MP": 7}
 BC = {"periodic": 0, "transmissive": 1}
 GHOST = 4
 ST_JACOBIAN, ST_NONPHYS, ST_SCHEME, ST_ARGMAX = 1, 2, 4, 8

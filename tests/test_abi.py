@@ -69,7 +69,10 @@ def test_bad_scheme_params_and_pointers_rejected(wiu):
     p = wiu.make_params()
     dummy = ctypes.c_void_p(256)
     other = ctypes.c_void_p(512)
-    assert wiu.lib.wiu_rhs(ctypes.byref(g), 4, ctypes.byref(p), dummy, dummy, other, dummy, None) == wiu.WIU_EINVAL
+    assert wiu.lib.wiu_rhs(ctypes.byref(g), 8, ctypes.byref(p), dummy, dummy, other, dummy, None) == wiu.WIU_EINVAL
+    # the adjoint covers the third- and fifth-order schemes only
+    assert wiu.lib.wiu_rhs_vjp(ctypes.byref(g), 4, ctypes.byref(p), dummy, dummy, other, ctypes.c_void_p(768),
+                               dummy, None) == wiu.WIU_EINVAL
     assert wiu.lib.wiu_rhs(ctypes.byref(g), 3, ctypes.byref(p), dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL
     assert wiu.lib.wiu_rhs(ctypes.byref(g), 3, ctypes.byref(p), None, dummy, other, dummy, None) == wiu.WIU_EINVAL
     bad = wiu.make_params(gamma=1.0)

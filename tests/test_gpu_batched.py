@@ -45,7 +45,7 @@ def _plan(wiu, blocks, scheme, **kw):
     return plan
 
 
-@pytest.mark.parametrize("s", ["3-1MP", "5-2MP"])
+@pytest.mark.parametrize("s", ["3-1MP", "5-2MP", "7-1MP", "7-6MP"])
 def test_batched_step_equals_per_block_steps(wiu, s):
     import torch
     say("batched vs per-block", s)
@@ -93,9 +93,9 @@ def test_graph_replays_match_eager(wiu):
     graph.close()
 
 
-def test_batched_step_matches_oracle(orc, wiu):
-    say("batched vs oracle")
-    s = "5-2MP"
+@pytest.mark.parametrize("s", ["5-2MP", "7-4MP"])
+def test_batched_step_matches_oracle(orc, wiu, s):
+    say("batched vs oracle", s)
     blocks = small_blocks()
     plan = _plan(wiu, blocks, s)
     plan.cfl_dt(0.4)

@@ -14,7 +14,7 @@ from paper_1810_11103_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-SCHEMES = ["3-1MP", "3-2MP", "5-1MP", "5-2MP"]
+SCHEMES = ["3-1MP", "3-2MP", "5-1MP", "5-2MP", "7-1MP", "7-2MP", "7-4MP", "7-6MP"]
 G = 4
 
 
@@ -319,7 +319,7 @@ def test_rk3_step_identical_across_tile_shapes(wiu):
     g, U = make_case("riemann", 301, 203, seed=7)
     saved = (wiu.get_tuning(0), wiu.get_tuning(1))
     try:
-        for s in ("3-1MP", "5-2MP"):
+        for s in ("3-1MP", "5-2MP", "7-6MP"):
             sol = wiu.Solver(g.x, g.y, s, g.bc, g.period)
             ref = None
             for vx in range(wiu.tuning_variants(0)):
@@ -338,3 +338,14 @@ def test_rk3_step_identical_across_tile_shapes(wiu):
     finally:
         wiu.set_tuning(0, saved[0])
         wiu.set_tuning(1, saved[1])
+
+
+def test_adjoint_rejects_seventh_order(wiu):
+    """The adjoint entry points cover the third- and fifth-order schemes and
+    reject the seventh-order ones with WIU_EINVAL (no silent result)."""
+    import torch
+    g, U = make_case("smooth", 64, 48, seed=1)
+    sol = wiu.Solver(g.x, g.y, "7-2MP", g.bc, g.period)
+    Ud = _dev(U)
+    with pytest.raises(RuntimeError):
+        sol.rhs_vjp(Ud, torch.ones_like(Ud))

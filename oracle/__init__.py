@@ -39,46 +39,48 @@ def lib():
         L.orc_is4.restype = _D
         L.orc_is4.argtypes = [_I, _D, _D, _D, _D]
         L.orc_hplus.restype = _D
-        L.orc_hplus.argtypes = [_I, _P, _P]
+        L.orc_hplus.argtypes = [_I, _D, _P, _P]
         L.orc_delta_c.restype = _D
-        L.orc_delta_c.argtypes = [_I, _P, _P]
+        L.orc_delta_c.argtypes = [_I, _D, _P, _P]
+        L.orc_delta_c_eq27.restype = _D
+        L.orc_delta_c_eq27.argtypes = [_I, _D, _P, _P]
         L.orc_interp_mid.restype = _D
         L.orc_interp_mid.argtypes = [_I, _P]
         L.orc_metric_derivative.restype = _D
-        L.orc_metric_derivative.argtypes = [_I, _P]
+        L.orc_metric_derivative.argtypes = [_I, _D, _P]
         L.orc_eigenvectors.restype = None
         L.orc_eigenvectors.argtypes = [_P, _D, _D, _D, _P, _P]
         L.orc_flux_hat.restype = None
         L.orc_flux_hat.argtypes = [_P, _D, _D, _D, _P]
         L.orc_midpoint_flux.restype = _I
-        L.orc_midpoint_flux.argtypes = [_I, _D, _D, _I, _P, _P, _P, _P, _D, _P, _P]
+        L.orc_midpoint_flux.argtypes = [_I, _D, _D, _I, _I, _P, _P, _P, _P, _D, _P, _P]
         L.orc_metrics_size.restype = ctypes.c_longlong
         L.orc_metrics_size.argtypes = [_I, _I]
         L.orc_metrics.restype = _I
-        L.orc_metrics.argtypes = [_I, _I, _I, _I, _I, _D, _D, _P, _P, _P]
+        L.orc_metrics.argtypes = [_I, _D, _I, _I, _I, _I, _D, _D, _P, _P, _P]
         L.orc_rhs.restype = _I
-        L.orc_rhs.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _P, _P, _P]
+        L.orc_rhs.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _P, _P, _P]
         L.orc_cfl_dt.restype = _D
         L.orc_cfl_dt.argtypes = [_I, _I, _D, _P, _P, _D]
         L.orc_rk3_step.restype = _I
-        L.orc_rk3_step.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _D]
+        L.orc_rk3_step.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _D]
         L.orc_rk3_run.restype = _I
-        L.orc_rk3_run.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _D, _I]
+        L.orc_rk3_run.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _D, _I]
         L.orc_adv1d_rhs.restype = None
-        L.orc_adv1d_rhs.argtypes = [_I, _I, _D, _I, _D, _D, _I, _P, _P]
+        L.orc_adv1d_rhs.argtypes = [_I, _I, _D, _I, _D, _D, _I, _D, _P, _P]
         L.orc_adv1d_run.restype = _I
-        L.orc_adv1d_run.argtypes = [_I, _I, _I, _D, _D, _I, _D, _D, _P, _P]
+        L.orc_adv1d_run.argtypes = [_I, _I, _I, _D, _D, _I, _D, _D, _D, _P, _P]
         for nm in ("orc_rhs_jvp", "orc_rk3_step_jvp"):
             f = getattr(L, nm)
             f.restype = _I
-        L.orc_rhs_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _P, _P, _P]
-        L.orc_rk3_step_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _P, _D, _P, _P]
+        L.orc_rhs_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _P, _P, _P]
+        L.orc_rk3_step_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _P, _D, _P, _P]
         L.orc_rhs_vjp.restype = _I
-        L.orc_rhs_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _P, _P]
+        L.orc_rhs_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _P, _P]
         L.orc_rk3_step_vjp.restype = _I
-        L.orc_rk3_step_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _D, _P, _P]
+        L.orc_rk3_step_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _D, _P, _P]
         L.orc_count_rhs_flops.restype = _I
-        L.orc_count_rhs_flops.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _P, _P, _P]
+        L.orc_count_rhs_flops.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _P]
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [_I]
         L.orc_get_threads.restype = _I
@@ -94,6 +96,14 @@ def _f64(a):
 
 def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+VARS = {"characteristic": 0, "conservative": 1, "primitive": 2}
+
+
+def vars_id(v):
+    """Interpolation variables (Sec. 2.4): name or 0/1/2."""
+    return VARS[v] if isinstance(v, str) else int(v)
 
 
 def scheme_id(s):
@@ -132,19 +142,26 @@ def smoothness4(k, a, b, c, d):
     return lib().orc_is4(k, a, b, c, d)
 
 
-def hplus(scheme, f, F):
+def hplus(scheme, f, F, alpha_h=1.0):
     """h^+_{i+1/2}; f = f_{i-3..i+3} (7 values), F = f_{i-5/2..i+5/2} (6 values;
-    4 values f_{i-3/2..i+3/2} are accepted and padded with zeros)."""
+    4 values f_{i-3/2..i+3/2} are accepted and padded with zeros).  alpha_h:
+    free parameter of the one-midpoint families."""
     f, F = _f64(f), _f64(F)
     if F.size == 4:
         F = np.concatenate([[0.0], F, [0.0]])
-    return lib().orc_hplus(scheme_id(scheme), _ptr(f), _ptr(F))
+    return lib().orc_hplus(scheme_id(scheme), float(alpha_h), _ptr(f), _ptr(F))
 
 
-def delta_c(scheme, g, gm):
+def delta_c(scheme, g, gm, alpha_h=1.0):
     """delta^{c,(1)} at i; g = g_{i-4..i+4} (9), gm = g_{i-7/2..i+7/2} (8)."""
     g, gm = _f64(g), _f64(gm)
-    return lib().orc_delta_c(scheme_id(scheme), _ptr(g), _ptr(gm))
+    return lib().orc_delta_c(scheme_id(scheme), float(alpha_h), _ptr(g), _ptr(gm))
+
+
+def delta_c_eq27(scheme, g, gm, alpha_h=1.0):
+    """The central operator built by Eq. 2.7 from h^+ (any alpha_h)."""
+    g, gm = _f64(g), _f64(gm)
+    return lib().orc_delta_c_eq27(scheme_id(scheme), float(alpha_h), _ptr(g), _ptr(gm))
 
 
 def interp_mid(g):
@@ -155,9 +172,9 @@ def interp_mid(g):
     return lib().orc_interp_mid(g.size, _ptr(g))
 
 
-def metric_derivative(scheme, r):
+def metric_derivative(scheme, r, alpha_h=1.0):
     r = _f64(r)
-    return lib().orc_metric_derivative(scheme_id(scheme), _ptr(r))
+    return lib().orc_metric_derivative(scheme_id(scheme), float(alpha_h), _ptr(r))
 
 
 def eigenvectors(Q, gamma, nx, ny):
@@ -175,14 +192,14 @@ def flux_hat(Q, gamma, kx, ky):
     return out
 
 
-def midpoint_flux(scheme, Qs, k0, k1, mk, lam, gamma=1.4, eps=1e-40, ppm=1):
+def midpoint_flux(scheme, Qs, k0, k1, mk, lam, gamma=1.4, eps=1e-40, ppm=1, vars=0):
     """F^+, F^- at k+1/2 from Qs = Q_{k-3..k+4} (8 states; 6 states Q_{k-2..k+3}
     are accepted for the third- and fifth-order schemes)."""
     Qs, k0, k1, mk = _f64(Qs), _f64(k0), _f64(k1), _f64(mk)
     if Qs.shape[0] == 6:
         Qs = np.ascontiguousarray(np.concatenate([Qs[:1], Qs, Qs[-1:]]))
     Fp, Fm = np.zeros(4), np.zeros(4)
-    rc = lib().orc_midpoint_flux(scheme_id(scheme), gamma, eps, ppm, _ptr(Qs), _ptr(k0), _ptr(k1),
+    rc = lib().orc_midpoint_flux(scheme_id(scheme), gamma, eps, ppm, vars_id(vars), _ptr(Qs), _ptr(k0), _ptr(k1),
                                  _ptr(mk), lam, _ptr(Fp), _ptr(Fm))
     assert rc == 0
     return Fp, Fm
@@ -190,26 +207,26 @@ def midpoint_flux(scheme, Qs, k0, k1, mk, lam, gamma=1.4, eps=1e-40, ppm=1):
 
 # ---- 2-D Euler ----------------------------------------------------------------------
 
-def metrics(scheme, x, y, bc=("periodic", "periodic"), period=(0.0, 0.0)):
+def metrics(scheme, x, y, bc=("periodic", "periodic"), period=(0.0, 0.0), alpha_h=1.0):
     """Nine metric planes with the ghost band: shape (9, ny+2G, nx+2G)."""
     x, y = _f64(x), _f64(y)
     ny, nx = x.shape
     M = np.zeros((9, ny + 2 * G, nx + 2 * G))
-    rc = lib().orc_metrics(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), float(period[0]),
+    rc = lib().orc_metrics(scheme_id(scheme), float(alpha_h), nx, ny, bc_id(bc[0]), bc_id(bc[1]), float(period[0]),
                            float(period[1]), _ptr(x), _ptr(y), _ptr(M))
     if rc:
         raise ValueError("orc_metrics failed")
     return M
 
 
-def rhs(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1,
+def rhs(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0,
         return_lambda=False):
     U, M = _f64(U), _f64(M)
     _, ny, nx = U.shape
     out = np.zeros_like(U)
     lx = np.zeros(ny)
     le = np.zeros(nx)
-    rc = lib().orc_rhs(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+    rc = lib().orc_rhs(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
                        _ptr(U), _ptr(M), _ptr(out), _ptr(lx), _ptr(le))
     if rc:
         raise ValueError("orc_rhs failed")
@@ -218,58 +235,58 @@ def rhs(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-
     return out
 
 
-def count_rhs_flops(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+def count_rhs_flops(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
     """Operation counts of one rhs: (xi sweep, eta sweep, final combination)."""
     U, M = _f64(U), _f64(M)
     _, ny, nx = U.shape
     c = np.zeros(3, dtype=np.int64)
-    rc = lib().orc_count_rhs_flops(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+    rc = lib().orc_count_rhs_flops(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
                                    _ptr(U), _ptr(M), _ptr(c))
     if rc:
         raise ValueError("orc_count_rhs_flops failed")
     return tuple(int(v) for v in c)
 
 
-def rhs_jvp(scheme, U, V, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+def rhs_jvp(scheme, U, V, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
     """(rhs(U), (d rhs/dU) V) by forward-mode dual numbers."""
     U, V, M = _f64(U), _f64(V), _f64(M)
     _, ny, nx = U.shape
     val, tan = np.zeros_like(U), np.zeros_like(U)
-    rc = lib().orc_rhs_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+    rc = lib().orc_rhs_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
                            _ptr(U), _ptr(V), _ptr(M), _ptr(val), _ptr(tan))
     if rc:
         raise ValueError("orc_rhs_jvp failed")
     return val, tan
 
 
-def rhs_vjp(scheme, U, M, Gbar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+def rhs_vjp(scheme, U, M, Gbar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
     """(d rhs/dU)^T Gbar by reverse mode on a tape."""
     U, M, Gbar = _f64(U), _f64(M), _f64(Gbar)
     _, ny, nx = U.shape
     out = np.zeros_like(U)
-    rc = lib().orc_rhs_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+    rc = lib().orc_rhs_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
                            _ptr(U), _ptr(M), _ptr(Gbar), _ptr(out))
     if rc:
         raise ValueError("orc_rhs_vjp failed")
     return out
 
 
-def rk3_step_jvp(scheme, U, V, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+def rk3_step_jvp(scheme, U, V, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
     U, V, M = _f64(U), _f64(V), _f64(M)
     _, ny, nx = U.shape
     val, tan = np.zeros_like(U), np.zeros_like(U)
-    rc = lib().orc_rk3_step_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+    rc = lib().orc_rk3_step_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
                                 _ptr(U), _ptr(V), _ptr(M), dt, _ptr(val), _ptr(tan))
     if rc:
         raise ValueError("orc_rk3_step_jvp failed")
     return val, tan
 
 
-def rk3_step_vjp(scheme, U, M, dt, Ubar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+def rk3_step_vjp(scheme, U, M, dt, Ubar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
     U, M, Ubar = _f64(U), _f64(M), _f64(Ubar)
     _, ny, nx = U.shape
     out = np.zeros_like(U)
-    rc = lib().orc_rk3_step_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+    rc = lib().orc_rk3_step_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
                                 _ptr(U), _ptr(M), dt, _ptr(Ubar), _ptr(out))
     if rc:
         raise ValueError("orc_rk3_step_vjp failed")
@@ -282,22 +299,22 @@ def cfl_dt(U, M, cfl, gamma=1.4):
     return lib().orc_cfl_dt(nx, ny, gamma, _ptr(U), _ptr(M), cfl)
 
 
-def rk3_step(scheme, U, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+def rk3_step(scheme, U, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
     U = np.array(U, dtype=np.float64, copy=True, order="C")
     M = _f64(M)
     _, ny, nx = U.shape
-    rc = lib().orc_rk3_step(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+    rc = lib().orc_rk3_step(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
                             _ptr(U), _ptr(M), dt)
     if rc:
         raise ValueError("orc_rk3_step failed")
     return U
 
 
-def rk3_run(scheme, U, M, dt, nsteps, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+def rk3_run(scheme, U, M, dt, nsteps, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
     U = np.array(U, dtype=np.float64, copy=True, order="C")
     M = _f64(M)
     _, ny, nx = U.shape
-    rc = lib().orc_rk3_run(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm,
+    rc = lib().orc_rk3_run(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
                            _ptr(U), _ptr(M), dt, int(nsteps))
     if rc:
         raise ValueError("orc_rk3_run failed")
@@ -306,18 +323,18 @@ def rk3_run(scheme, U, M, dt, nsteps, bc=("periodic", "periodic"), gamma=1.4, al
 
 # ---- Sec. 5.1 scalar advection ------------------------------------------------------------
 
-def adv1d_rhs(scheme, u, dx, split=0, alpha=1.1, eps=1e-40, ppm=1):
+def adv1d_rhs(scheme, u, dx, split=0, alpha=1.1, eps=1e-40, ppm=1, alpha_h=1.0):
     u = _f64(u)
     out = np.zeros_like(u)
-    lib().orc_adv1d_rhs(scheme_id(scheme), u.size, dx, split, alpha, eps, ppm, _ptr(u), _ptr(out))
+    lib().orc_adv1d_rhs(scheme_id(scheme), u.size, dx, split, alpha, eps, ppm, float(alpha_h), _ptr(u), _ptr(out))
     return out
 
 
-def adv1d_run(scheme, N, split=0, alpha=1.1, eps=1e-40, ppm=1, tend=2.0, dtpow=1.25):
+def adv1d_run(scheme, N, split=0, alpha=1.1, eps=1e-40, ppm=1, tend=2.0, dtpow=1.25, alpha_h=1.0):
     l2 = ctypes.c_double()
     li = ctypes.c_double()
-    rc = lib().orc_adv1d_run(scheme_id(scheme), N, split, alpha, eps, ppm, tend, dtpow, ctypes.byref(l2),
-                             ctypes.byref(li))
+    rc = lib().orc_adv1d_run(scheme_id(scheme), N, split, alpha, eps, ppm, float(alpha_h), tend, dtpow,
+                             ctypes.byref(l2), ctypes.byref(li))
     if rc:
         raise ValueError("orc_adv1d_run failed")
     return l2.value, li.value

@@ -35,7 +35,15 @@ struct Params {
   double alpha_lf = 1.1;  // alpha of the Lax-Friedrichs eigenvalue, 1.1-1.2 (Sec. 2.3)
   double eps = 1e-40;     // WENO epsilon when the PPM mapping is used (Sec. 3.2(3))
   int ppm = 1;            // apply the piecewise-polynomial mapping (Eqs. 3.15/3.23)
+  // Variables the midpoint values are interpolated in (Sec. 2.4): 0
+  // characteristic (the paper's choice, Sec. 3.4), 1 conservative, 2 primitive.
+  int vars = 0;
+  // Free parameter alpha of the one-midpoint families (Eqs. 3.5, 3.17 and
+  // Appendix (1)); the paper tests alpha = 1 only.  Other schemes require 1.
+  double alpha_h = 1.0;
 };
+
+inline bool one_midpoint(int s) { return s == 0 || s == 2 || s == 4; }
 
 inline bool fifth_order(Scheme s) { return s == W5_1MP || s == W5_2MP; }
 inline bool seventh_order(Scheme s) { return s >= W7_1MP; }
@@ -196,7 +204,24 @@ template <class T> T weno_right(Scheme sc, const T s[8], const Params& pr) {
 // (the only member of the families 3.5 / 3.17 that the paper tests).
 // ===========================================================================
 template <class T, class NodeF, class MidF>
-T h_plus(Scheme sc, NodeF f, MidF F) {
+T h_plus(Scheme sc, double a, NodeF f, MidF F) {
+  if (a != 1.0) {
+    // the general one-midpoint forms; sc is W3_1MP, W5_1MP or W7_1MP
+    switch (sc) {
+      case W3_1MP:  // Eq. 3.5
+        return a * F(0) + (a / 8.0 - 1.0 / 6.0) * f(-1) + (-3.0 * a / 4.0 + 5.0 / 6.0) * f(0) +
+               (-3.0 * a / 8.0 + 1.0 / 3.0) * f(1);
+      case W5_1MP:  // Eq. 3.17
+        return a * F(0) + (-3.0 * a / 128.0 + 1.0 / 30.0) * f(-2) + (5.0 * a / 32.0 - 13.0 / 60.0) * f(-1) +
+               (-45.0 * a / 64.0 + 47.0 / 60.0) * f(0) + (-15.0 * a / 32.0 + 9.0 / 20.0) * f(1) +
+               (5.0 * a / 128.0 - 1.0 / 20.0) * f(2);
+      default:  // Appendix (1), general form
+        return a * F(0) + (5.0 * a / 1024.0 - 1.0 / 140.0) * f(-3) + (-21.0 * a / 512.0 + 5.0 / 84.0) * f(-2) +
+               (175.0 * a / 1024.0 - 101.0 / 420.0) * f(-1) + (-175.0 * a / 256.0 + 319.0 / 420.0) * f(0) +
+               (-525.0 * a / 1024.0 + 107.0 / 210.0) * f(1) + (35.0 * a / 512.0 - 19.0 / 210.0) * f(2) +
+               (-7.0 * a / 1024.0 + 1.0 / 105.0) * f(3);
+    }
+  }
   switch (sc) {
     case W3_1MP:  // Eq. 3.4
       return F(0) + (1.0 / 24.0) * (-f(-1) + 2.0 * f(0) - f(1));
@@ -228,6 +253,31 @@ T h_plus(Scheme sc, NodeF f, MidF F) {
 // delta^{c,(1)} of each scheme, used for the grid metrics.  g(m) = g_{i+m} at
 // nodes, gm(m) = g_{i+1/2+m} at midpoints (so g_{i-1/2} = gm(-1)).
 // ===========================================================================
+template <class NodeF, class MidF>
+double delta_c(Scheme sc, NodeF g, MidF gm);
+
+// The central operator of a one-midpoint scheme with free parameter a != 1,
+// for which the paper prints none: Eq. 2.7 itself, half the sum of the
+// upwind-biased difference and its mirror image,
+//   delta g_i = [(h+_{i+1/2} - h+_{i-1/2}) + (h-_{i+1/2} - h-_{i-1/2})] / 2,
+// with h- the mirror of h+ about the midpoint.  At a = 1 this reproduces the
+// printed operators (Eqs. 3.7, 3.19, Appendix (1)).
+template <class NodeF, class MidF>
+double delta_c_eq27(Scheme sc, double a, NodeF g, MidF gm) {
+  auto hp = [&](int s) {  // h+_{i+1/2+s}
+    return h_plus<double>(sc, a, [&](int m) { return g(s + m); }, [&](int m) { return gm(s + m); });
+  };
+  auto hm = [&](int s) {  // h-_{i+1/2+s}
+    return h_plus<double>(sc, a, [&](int m) { return g(s + 1 - m); }, [&](int m) { return gm(s - m); });
+  };
+  return 0.5 * ((hp(0) - hp(-1)) + (hm(0) - hm(-1)));
+}
+
+template <class NodeF, class MidF>
+double delta_c(Scheme sc, double a, NodeF g, MidF gm) {
+  return a == 1.0 ? delta_c(sc, g, gm) : delta_c_eq27(sc, a, g, gm);
+}
+
 template <class NodeF, class MidF>
 double delta_c(Scheme sc, NodeF g, MidF gm) {
   switch (sc) {
@@ -279,12 +329,12 @@ template <class NodeF> double interp_mid(Scheme sc, NodeF g) {
 // The scheme's metric derivative at a node, evaluated on the local relative
 // values r[m + 8] = g_{i+m} - g_i, m = -8..8 (the operator annihilates
 // constants, so subtracting g_i changes nothing but the rounding).
-inline double metric_derivative(Scheme sc, const double r[17]) {
+inline double metric_derivative(Scheme sc, double a, const double r[17]) {
   auto g = [&](int m) { return r[m + 8]; };
   auto gm = [&](int m) {  // g_{i+1/2+m}
     return interp_mid(sc, [&](int l) { return r[m + l + 8]; });
   };
-  return delta_c(sc, g, gm);
+  return delta_c(sc, a, g, gm);
 }
 
 // ===========================================================================
@@ -357,7 +407,7 @@ struct Coords {
 // central operator (Sec. 2.3), evaluated on coordinate differences.
 struct NodalMetric { double xix, xiy, etx, ety, jinv; };
 
-inline NodalMetric nodal_metric(Scheme sc, const Coords& C, int i, int j) {
+inline NodalMetric nodal_metric(Scheme sc, double a, const Coords& C, int i, int j) {
   long double X0, Y0;
   C.at(i, j, X0, Y0);
   double rx[17], ry[17];
@@ -366,13 +416,13 @@ inline NodalMetric nodal_metric(Scheme sc, const Coords& C, int i, int j) {
     C.at(i + m, j, X, Y);
     rx[m + 8] = (double)(X - X0); ry[m + 8] = (double)(Y - Y0);
   }
-  double x_xi = metric_derivative(sc, rx), y_xi = metric_derivative(sc, ry);
+  double x_xi = metric_derivative(sc, a, rx), y_xi = metric_derivative(sc, a, ry);
   for (int m = -8; m <= 8; ++m) {
     long double X, Y;
     C.at(i, j + m, X, Y);
     rx[m + 8] = (double)(X - X0); ry[m + 8] = (double)(Y - Y0);
   }
-  double x_eta = metric_derivative(sc, rx), y_eta = metric_derivative(sc, ry);
+  double x_eta = metric_derivative(sc, a, rx), y_eta = metric_derivative(sc, a, ry);
   NodalMetric nm;
   nm.xix = y_eta; nm.xiy = -x_eta; nm.etx = -y_xi; nm.ety = x_xi;
   nm.jinv = x_xi * y_eta - x_eta * y_xi;
@@ -396,7 +446,8 @@ struct MetricView {
 // the metrics of the wrapped node; transmissive ones evaluate them on the
 // extended coordinates.  Midpoint metrics are the interpolation of the nodal
 // ones in the same direction (Sec. 2.4, directionally consistent).
-inline void compute_metrics(Scheme sc, const Grid& g, const double* x, const double* y, double* M) {
+inline void compute_metrics(Scheme sc, double alpha_h, const Grid& g, const double* x, const double* y,
+                            double* M) {
   Coords C{g, x, y};
   const int W = g.nx + 2 * G, H = g.ny + 2 * G;
   const size_t P = (size_t)W * H;
@@ -408,7 +459,7 @@ inline void compute_metrics(Scheme sc, const Grid& g, const double* x, const dou
 #pragma omp parallel for schedule(static)
   for (int b = -B; b < g.ny + B; ++b)
     for (int a = -B; a < g.nx + B; ++a)
-      nm[(size_t)(b + B) * WB + (a + B)] = nodal_metric(sc, C, wr(a, g.nx, g.bcx), wr(b, g.ny, g.bcy));
+      nm[(size_t)(b + B) * WB + (a + B)] = nodal_metric(sc, alpha_h, C, wr(a, g.nx, g.bcx), wr(b, g.ny, g.bcy));
   auto N = [&](int a, int b) -> const NodalMetric& {
     // for periodic directions use the wrapped node so copies are bitwise equal
     int aa = g.bcx == PERIODIC ? wrap(a, g.nx) : a;
@@ -435,6 +486,20 @@ inline void compute_metrics(Scheme sc, const Grid& g, const double* x, const dou
 template <class T> T pressure(const T Q[4], double gam) {
   T u = Q[1] / Q[0], v = Q[2] / Q[0];
   return (gam - 1.0) * (Q[3] - 0.5 * Q[0] * (u * u + v * v));
+}
+
+// Primitive variables (rho, u, v, p) of a conservative state and back.
+template <class T> void to_primitive(const T Q[4], double gam, T P[4]) {
+  P[0] = Q[0];
+  P[1] = Q[1] / Q[0];
+  P[2] = Q[2] / Q[0];
+  P[3] = pressure(Q, gam);
+}
+template <class T> void to_conservative(const T P[4], double gam, T Q[4]) {
+  Q[0] = P[0];
+  Q[1] = P[0] * P[1];
+  Q[2] = P[0] * P[2];
+  Q[3] = P[3] / (gam - 1.0) + 0.5 * P[0] * (P[1] * P[1] + P[2] * P[2]);
 }
 
 template <class T> void flux_hat(const T Q[4], double gam, double kx, double ky, T out[4]) {
@@ -513,22 +578,45 @@ void midpoint_flux(Scheme sc, const Params& pr, const T Qs[8][4], double kx0, do
   double nx_ = nbx / nn, ny_ = nby / nn;
   for (int side = 0; side < 2; ++side) {
     const T* Qref = Qs[3 + side];  // Q_k for +, Q_{k+1} for -
-    T L[4][4], R[4][4];
-    eigenvectors(Qref, pr.gamma, nx_, ny_, L, R);
-    T W[4];
-    for (int c = 0; c < 4; ++c) {
-      T s[8];
-      for (int m = 0; m < 8; ++m) {
-        s[m] = T(0.0);
-        for (int q = 0; q < 4; ++q) s[m] = s[m] + L[c][q] * (Qs[m][q] - Qref[q]);
-      }
-      W[c] = side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr);
-    }
     T Qm[4];
-    for (int q = 0; q < 4; ++q) {
-      Qm[q] = T(0.0);
-      for (int c = 0; c < 4; ++c) Qm[q] = Qm[q] + R[q][c] * W[c];
-      Qm[q] = Qref[q] + Qm[q];
+    if (pr.vars == 0) {
+      T L[4][4], R[4][4];
+      eigenvectors(Qref, pr.gamma, nx_, ny_, L, R);
+      T W[4];
+      for (int c = 0; c < 4; ++c) {
+        T s[8];
+        for (int m = 0; m < 8; ++m) {
+          s[m] = T(0.0);
+          for (int q = 0; q < 4; ++q) s[m] = s[m] + L[c][q] * (Qs[m][q] - Qref[q]);
+        }
+        W[c] = side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr);
+      }
+      for (int q = 0; q < 4; ++q) {
+        Qm[q] = T(0.0);
+        for (int c = 0; c < 4; ++c) Qm[q] = Qm[q] + R[q][c] * W[c];
+        Qm[q] = Qref[q] + Qm[q];
+      }
+    } else {
+      // Sec. 2.4: component by component in conservative (vars 1) or
+      // primitive (vars 2) variables, on deviations from the reference
+      // node's values as above
+      T V[8][4];
+      for (int m = 0; m < 8; ++m) {
+        if (pr.vars == 1)
+          for (int q = 0; q < 4; ++q) V[m][q] = Qs[m][q];
+        else
+          to_primitive(Qs[m], pr.gamma, V[m]);
+      }
+      T Vm[4];
+      for (int c = 0; c < 4; ++c) {
+        T s[8];
+        for (int m = 0; m < 8; ++m) s[m] = V[m][c] - V[3 + side][c];
+        Vm[c] = V[3 + side][c] + (side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr));
+      }
+      if (pr.vars == 1)
+        for (int q = 0; q < 4; ++q) Qm[q] = Vm[q];
+      else
+        to_conservative(Vm, pr.gamma, Qm);
     }
     T E[4];
     flux_hat(Qm, pr.gamma, mkx, mky, E);
@@ -597,7 +685,7 @@ void line_residual(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_
       auto Fpm = [&](int m) { return Fp[q * len + i + m + off]; };
       auto fmn = [&](int m) { return fm[q * len + i + 1 - m + off]; };
       auto Fmm = [&](int m) { return Fm[q * len + i - m + off]; };
-      H[q * (n + 1) + i + 1] = h_plus<T>(sc, fpn, Fpm) + h_plus<T>(sc, fmn, Fmm);
+      H[q * (n + 1) + i + 1] = h_plus<T>(sc, pr.alpha_h, fpn, Fpm) + h_plus<T>(sc, pr.alpha_h, fmn, Fmm);
     }
   for (int k = 0; k < n; ++k)
     for (int q = 0; q < 4; ++q) R[q * n + k] = H[q * (n + 1) + k + 1] - H[q * (n + 1) + k];

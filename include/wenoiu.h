@@ -79,11 +79,25 @@ typedef struct {
   double period_x, period_y; /* domain lengths of periodic directions */
 } wiu_grid;
 
+/* Variables the midpoint values are interpolated in (Sec. 2.4): the
+ * characteristic variables of the reference node (the paper's choice,
+ * Sec. 3.4), or component by component the conservative or the primitive
+ * (rho, u, v, p) variables.  All three are taken as deviations from the
+ * reference node's values, so a uniform state is reproduced exactly. */
+enum { WIU_VARS_CHARACTERISTIC = 0, WIU_VARS_CONSERVATIVE = 1, WIU_VARS_PRIMITIVE = 2 };
+
 typedef struct {
   double gamma;    /* ratio of specific heats, 1.4 */
   double alpha_lf; /* Lax-Friedrichs factor alpha, 1.1 (Sec. 2.3: 1.1-1.2) */
   double eps;      /* WENO epsilon, 1e-40 with the mapping (Sec. 3.2(3)) */
   int ppm;         /* 1: piecewise-polynomial mapping of the weights (Eqs. 3.15, 3.23) */
+  int vars;        /* WIU_VARS_* */
+  double alpha_h;  /* free parameter alpha of the one-midpoint families (Eq. 3.5 for
+                      WIU_3_1MP, Eq. 3.17 for WIU_5_1MP, Appendix (1) for WIU_7_1MP);
+                      1 gives Eqs. 3.4, 3.16 and the printed 7-1MP scheme and is the
+                      only value the other schemes accept.  The metrics depend on it
+                      (the central operator Eq. 2.7 derives from the scheme), so
+                      wiu_metrics takes the same parameters. */
 } wiu_params;
 
 /* Bytes of the metric array M for this grid (planes + tag). */
@@ -100,14 +114,19 @@ size_t wiu_workspace_bytes(const wiu_grid* g);
  * evaluated on coordinate differences.  In 2-D:
  * xi_x^ = y_eta, xi_y^ = -x_eta, eta_x^ = -y_xi, eta_y^ = x_xi,
  * J^{-1} = x_xi y_eta - x_eta y_xi.  Midpoint metrics interpolate the nodal
- * ones in their own direction.  Fills the ghost band and the tag of M and
- * latches WIU_ST_JACOBIAN if J^{-1} <= 0 at an interior node. */
-int wiu_metrics(const wiu_grid* g, int scheme, const double* x, const double* y, double* M, void* ws,
-                wiu_stream_t stream);
+ * ones in their own direction.  Only p->alpha_h is read (p may be NULL for
+ * alpha_h = 1): with alpha_h != 1 the operator is the one Eq. 2.7 defines
+ * for the general one-midpoint form.  Fills the ghost band and the tag of M
+ * (scheme, grid, alpha_h) and latches WIU_ST_JACOBIAN if J^{-1} <= 0 at an
+ * interior node.  Sweeps latch WIU_ST_SCHEME when the tag does not match the
+ * scheme, grid and alpha_h they run with. */
+int wiu_metrics(const wiu_grid* g, int scheme, const wiu_params* p, const double* x, const double* y, double* M,
+                void* ws, wiu_stream_t stream);
 
 /* Write the tag of M for metrics produced elsewhere (e.g. imported): the
- * caller vouches that they were built with `scheme`'s central operator. */
-int wiu_set_metrics_tag(const wiu_grid* g, int scheme, double* M, wiu_stream_t stream);
+ * caller vouches that they were built with `scheme`'s central operator at
+ * p->alpha_h (p may be NULL for alpha_h = 1). */
+int wiu_set_metrics_tag(const wiu_grid* g, int scheme, const wiu_params* p, double* M, wiu_stream_t stream);
 
 /* Line eigenvalues of the Lax-Friedrichs splitting (Sec. 2.3):
  * lam_xi[j] = alpha max_i (|U^| + c|xi^|) over row j, lam_eta[i] likewise over

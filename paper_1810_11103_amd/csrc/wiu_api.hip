@@ -92,13 +92,26 @@ bool grid_ok(const wiu_grid* g) {
   return true;
 }
 
+bool alpha_h_ok(int scheme, double a) {
+  // the free parameter exists for the one-midpoint schemes only
+  return a > 0.0 && a < 1.0e300 && (a == 1.0 || scheme == WIU_3_1MP || scheme == WIU_5_1MP || scheme == WIU_7_1MP);
+}
+
 bool params_ok(const wiu_params* p) {
-  return p && p->gamma > 1.0 && p->alpha_lf > 0.0 && p->eps >= 0.0 && (p->ppm == 0 || p->ppm == 1);
+  return p && p->gamma > 1.0 && p->alpha_lf > 0.0 && p->eps >= 0.0 && (p->ppm == 0 || p->ppm == 1) &&
+         p->vars >= WIU_VARS_CHARACTERISTIC && p->vars <= WIU_VARS_PRIMITIVE;
 }
 
 bool scheme_ok(int s) { return s >= 0 && s <= 7; }
-// The adjoint covers the third- and fifth-order schemes.
-bool adjoint_scheme_ok(int s) { return s >= 0 && s <= 3; }
+
+// scheme and parameters together
+bool options_ok(int s, const wiu_params* p) { return scheme_ok(s) && params_ok(p) && alpha_h_ok(s, p->alpha_h); }
+
+// The adjoint covers the third- and fifth-order schemes with the paper's
+// configuration (characteristic variables, alpha_h = 1).
+bool adjoint_ok(int s, const wiu_params* p) {
+  return s >= 0 && s <= 3 && params_ok(p) && p->vars == WIU_VARS_CHARACTERISTIC && p->alpha_h == 1.0;
+}
 
 Dims dims(const wiu_grid* g) {
   Dims d;
@@ -210,6 +223,7 @@ int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U
   if (e != hipSuccess) return WIU_EHIP;
   a.d = d; a.U = U; a.M = M;
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
+  a.vars = p->vars; a.ah = p->alpha_h;
   a.mode = mode == 2 ? 3 : 0; a.Rxi = w.rxi; a.out = out; a.U0 = U0; a.dt = dt; a.ca = ca; a.cb = cb;
   a.status = w.status;
   a.nlam_xi = nullptr; a.nlam_eta = nullptr;
@@ -279,17 +293,19 @@ int wiu_workspace_init(void* ws, wiu_stream_t stream) {
   return hip_rc(launch_zero_header((int*)ws, 64, (hipStream_t)stream));
 }
 
-int wiu_metrics(const wiu_grid* g, int scheme, const double* x, const double* y, double* M, void* ws,
-                wiu_stream_t stream) {
-  if (!grid_ok(g) || !scheme_ok(scheme) || !x || !y || !M || !ws) return WIU_EINVAL;
+int wiu_metrics(const wiu_grid* g, int scheme, const wiu_params* p, const double* x, const double* y, double* M,
+                void* ws, wiu_stream_t stream) {
+  const double ah = p ? p->alpha_h : 1.0;
+  if (!grid_ok(g) || !scheme_ok(scheme) || !alpha_h_ok(scheme, ah) || !x || !y || !M || !ws) return WIU_EINVAL;
   Ws w = carve(g, ws);
   ProfScope ps(WIU_K_METRICS, (hipStream_t)stream);
-  return hip_rc(launch_metrics(dims(g), scheme, x, y, M, w.band, w.status, (hipStream_t)stream));
+  return hip_rc(launch_metrics(dims(g), scheme, ah, x, y, M, w.band, w.status, (hipStream_t)stream));
 }
 
-int wiu_set_metrics_tag(const wiu_grid* g, int scheme, double* M, wiu_stream_t stream) {
-  if (!grid_ok(g) || !scheme_ok(scheme) || !M) return WIU_EINVAL;
-  return hip_rc(launch_set_tag(dims(g), scheme, M, (hipStream_t)stream));
+int wiu_set_metrics_tag(const wiu_grid* g, int scheme, const wiu_params* p, double* M, wiu_stream_t stream) {
+  const double ah = p ? p->alpha_h : 1.0;
+  if (!grid_ok(g) || !scheme_ok(scheme) || !alpha_h_ok(scheme, ah) || !M) return WIU_EINVAL;
+  return hip_rc(launch_set_tag(dims(g), scheme, ah, M, (hipStream_t)stream));
 }
 
 int wiu_line_eigenvalues(const wiu_grid* g, const wiu_params* p, const double* U, const double* M, double* lam_xi,
@@ -304,7 +320,7 @@ int wiu_line_eigenvalues(const wiu_grid* g, const wiu_params* p, const double* U
 
 int wiu_rhs(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M, double* dUdt,
             void* ws, wiu_stream_t stream) {
-  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !dUdt || !ws) return WIU_EINVAL;
+  if (!grid_ok(g) || !options_ok(scheme, p) || !U || !M || !dUdt || !ws) return WIU_EINVAL;
   if (dUdt == U) return WIU_EINVAL;
   Ws w = carve(g, ws);
   return residual(g, scheme, p, U, M, w, 1, dUdt, U, nullptr, 0.0, 0.0, (hipStream_t)stream);
@@ -321,14 +337,14 @@ int wiu_cfl_dt(const wiu_grid* g, const wiu_params* p, const double* U, const do
 
 int wiu_rk3_step(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
                  const double* dt_dev, void* ws, wiu_stream_t stream) {
-  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !dt_dev || !ws) return WIU_EINVAL;
+  if (!grid_ok(g) || !options_ok(scheme, p) || !U || !M || !dt_dev || !ws) return WIU_EINVAL;
   Ws w = carve(g, ws);
   return rk3_stages(g, scheme, p, U, M, dt_dev, w.u1, w.u2, w, (hipStream_t)stream, false);
 }
 
 int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
                      double* dt_dev, void* ws, wiu_stream_t stream) {
-  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !dt_dev || !ws || !(cfl > 0.0))
+  if (!grid_ok(g) || !options_ok(scheme, p) || !U || !M || !dt_dev || !ws || !(cfl > 0.0))
     return WIU_EINVAL;
   Ws w = carve(g, ws);
   hipStream_t st = (hipStream_t)stream;
@@ -342,7 +358,7 @@ int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double*
 
 int wiu_rhs_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M,
                 const double* Gbar, double* Ubar, void* ws, wiu_stream_t stream) {
-  if (!grid_ok(g) || !adjoint_scheme_ok(scheme) || !params_ok(p) || !U || !M || !Gbar || !Ubar || !ws)
+  if (!grid_ok(g) || !adjoint_ok(scheme, p) || !U || !M || !Gbar || !Ubar || !ws)
     return WIU_EINVAL;
   if (Ubar == U || Ubar == Gbar) return WIU_EINVAL;
   Ws w = carve(g, ws);
@@ -356,7 +372,7 @@ size_t wiu_step_record_bytes(const wiu_grid* g) {
 
 int wiu_rk3_step_stages(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
                         const double* dt_dev, double* U1, double* U2, void* rec, void* ws, wiu_stream_t stream) {
-  if (!grid_ok(g) || !scheme_ok(scheme) || !params_ok(p) || !U || !M || !dt_dev || !U1 || !U2 || !ws)
+  if (!grid_ok(g) || !options_ok(scheme, p) || !U || !M || !dt_dev || !U1 || !U2 || !ws)
     return WIU_EINVAL;
   Ws w = carve(g, ws);
   return rk3_stages(g, scheme, p, U, M, dt_dev, U1, U2, w, (hipStream_t)stream, false, (unsigned long long*)rec);
@@ -365,7 +381,7 @@ int wiu_rk3_step_stages(const wiu_grid* g, int scheme, const wiu_params* p, doub
 int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U_n, const double* U1,
                      const double* U2, const void* rec, const double* M, const double* dt_dev,
                      const double* Ubar_np1, double* Ubar_n, void* ws, wiu_stream_t stream) {
-  if (!grid_ok(g) || !adjoint_scheme_ok(scheme) || !params_ok(p) || !U_n || !M || !dt_dev || !Ubar_np1 || !Ubar_n ||
+  if (!grid_ok(g) || !adjoint_ok(scheme, p) || !U_n || !M || !dt_dev || !Ubar_np1 || !Ubar_n ||
       !ws)
     return WIU_EINVAL;
   if ((U1 == nullptr) != (U2 == nullptr)) return WIU_EINVAL;

@@ -29,7 +29,7 @@ WIU_DEV double* stage_dst(const BatchArgs& b, const BlockDev& B, int st) {
   return st == 2 ? b.U_all + ufirst(B.oU) : b.ws + ufirst(st == 0 ? B.oU1 : B.oU2);
 }
 
-template <int SC, int DIR, int NA, int NB>
+template <int SC, int DIR, int NA, int NB, bool OPT>
 __global__ void __launch_bounds__(NA * NB, sweep_waves<SC>()) batched_sweep_kernel(BatchArgs b) {
   __shared__ SweepLds<SC, DIR, NA, NB> lds;
   {
@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(NA * NB, sweep_waves<SC>()) batched_sweep_kern
     s.lam_xi = lam; s.lam_eta = lam + s.d.ny;
     unsigned long long* nlam = (DIR == 1 && st < 2) ? b.lam + ufirst(st == 0 ? B.oLam2 : B.oLam) : nullptr;
     s.nlam_xi = nlam; s.nlam_eta = nlam ? nlam + s.d.ny : nullptr;
-    s.gamma = b.gamma; s.alpha = b.alpha; s.eps = b.eps; s.ppm = b.ppm;
+    s.gamma = b.gamma; s.alpha = b.alpha; s.eps = b.eps; s.ppm = b.ppm; s.vars = b.vars; s.ah = b.ah;
     s.Rxi = b.ws + ufirst(B.oRxi); s.U0 = b.U_all + ufirst(B.oU); s.dt = b.ws + ufirst(B.oDt);
     s.status = b.status;
     s.U = stage_src(b, B, st);
@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(NA * NB, sweep_waves<SC>()) batched_sweep_kern
     s.ca = st == 0 ? 0.0 : (st == 1 ? 0.75 : 1.0 / 3.0);
     s.cb = st == 0 ? 1.0 : (st == 1 ? 0.25 : 2.0 / 3.0);
     s.mode = DIR == 0 ? b.xi_mode : 2;
-    sweep_tile<SC, DIR, NA, NB>(s, tl.y, tl.z, lds);
+    sweep_tile<SC, DIR, NA, NB, OPT>(s, tl.y, tl.z, lds);
   }
 }
 
@@ -78,18 +78,18 @@ __global__ void batched_cfl_dt_kernel(BatchArgs b, int nblocks, double cfl) {
   }
 }
 
-template <int SC, int DIR, int NA, int NB>
+template <int SC, int DIR, int NA, int NB, bool OPT>
 hipError_t launch_batched_sweep_t(const BatchArgs& a, hipStream_t st) {
   const int grid = a.ntiles;
   dim3 block = DIR == 0 ? dim3(NA, NB) : dim3(NB, NA);
-  hipLaunchKernelGGL((batched_sweep_kernel<SC, DIR, NA, NB>), dim3(grid), block, 0, st, a);
+  hipLaunchKernelGGL((batched_sweep_kernel<SC, DIR, NA, NB, OPT>), dim3(grid), block, 0, st, a);
   return hipGetLastError();
 }
 
-template <int SC, int DIR>
-hipError_t launch_batched_sweep_v(int variant, const BatchArgs& a, hipStream_t st) {
+template <int SC, int DIR, bool OPT>
+hipError_t launch_batched_sweep_vo(int variant, const BatchArgs& a, hipStream_t st) {
 #define WIU_CASE(v, na, nb) \
-  case v: return launch_batched_sweep_t<SC, DIR, na, nb>(a, st);
+  case v: return launch_batched_sweep_t<SC, DIR, na, nb, OPT>(a, st);
   if constexpr (DIR == 0) {
     switch (variant) {
       WIU_XI_TILES(WIU_CASE)
@@ -102,6 +102,13 @@ hipError_t launch_batched_sweep_v(int variant, const BatchArgs& a, hipStream_t s
     }
   }
 #undef WIU_CASE
+}
+
+// the options kernels only when an option is in use
+template <int SC, int DIR>
+hipError_t launch_batched_sweep_v(int variant, const BatchArgs& a, hipStream_t st) {
+  if (a.vars != 0 || a.ah != 1.0) return launch_batched_sweep_vo<SC, DIR, true>(variant, a, st);
+  return launch_batched_sweep_vo<SC, DIR, false>(variant, a, st);
 }
 
 hipError_t launch_batched_sweep(int scheme, int dir, int variant, const BatchArgs& a, hipStream_t st) {

@@ -440,6 +440,65 @@ WIU_DEV void side_flux7(QF q, int side, double nx_, double ny_, double mx, doubl
   F[3] = 0.5 * ((r3 + pl) * Ul + sl * r3);
 }
 
+// Midpoint flux with the midpoint state interpolated component by component
+// (Sec. 2.4) in conservative (vars 1) or primitive (vars 2: rho, u, v, p)
+// variables instead of characteristic ones.  Same window and sides as
+// side_flux / side_flux7 (R = 2, 3: q(m), m = 0..5 at k-2..k+3; R = 4:
+// m = 0..7 at k-3..k+4), same deviation form: each variable is interpolated
+// as its deviation from the reference node's value, which is then added
+// back.  Primitive values are formed from the staged conservative states
+// with one reciprocal density per stencil point.
+template <int R, class QF>
+WIU_DEV void side_flux_comp(QF q, int side, int vars, double mx, double my, double lam, double gam, double eps,
+                            int ppm, double F[4]) {
+  constexpr int QL = R == 4 ? 3 : 2;        // reference position in the window (side 0)
+  constexpr int NS = R == 2 ? 4 : 2 * R - 1;  // stencil positions s = 0..NS-1, reference at s = QL
+  const double gm1 = gam - 1.0;
+  auto mi = [&](int s) { return side == 0 ? s : 2 * QL + 1 - s; };
+  double rinv[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rinv[s] = vars == 2 ? rcp(q(mi(s), 0)) : 0.0;
+  // variable c at stencil position s
+  auto var = [&](int s, int c) -> double {
+    const int m = mi(s);
+    if (vars == 1 || c == 0) return q(m, c);
+    if (c == 1) return q(m, 1) * rinv[s];
+    if (c == 2) return q(m, 2) * rinv[s];
+    const double a = q(m, 1), b = q(m, 2);
+    return gm1 * (q(m, 3) - 0.5 * (a * a + b * b) * rinv[s]);
+  };
+  double V[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    asm volatile("" ::: "memory");  // one variable at a time (register pressure)
+    const double vr = var(QL, c);
+    double v[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] = s == QL ? 0.0 : var(s, c) - vr;
+    double w;
+    if constexpr (R == 4) w = weno7(v[0], v[1], v[2], v[4], v[5], v[6], eps, ppm);
+    else if constexpr (R == 3) w = weno5(v[0], v[1], v[3], v[4], eps, ppm);
+    else w = weno3(v[0], v[1], v[3], eps, ppm);
+    V[c] = vr + w;
+  }
+  double r0, r1, r2, r3;
+  if (vars == 1) {
+    r0 = V[0]; r1 = V[1]; r2 = V[2]; r3 = V[3];
+  } else {
+    r0 = V[0]; r1 = V[0] * V[1]; r2 = V[0] * V[2];
+    r3 = fma(V[3], rcp(gm1), 0.5 * V[0] * (V[1] * V[1] + V[2] * V[2]));
+  }
+  const double ri = rcp(r0);
+  const double ul = r1 * ri, vl = r2 * ri;
+  const double pl = gm1 * (r3 - 0.5 * (r1 * ul + r2 * vl));
+  const double Ul = mx * ul + my * vl;
+  const double sl = side == 0 ? lam : -lam;
+  F[0] = 0.5 * (r0 * Ul + sl * r0);
+  F[1] = 0.5 * (r1 * Ul + mx * pl + sl * r1);
+  F[2] = 0.5 * (r2 * Ul + my * pl + sl * r2);
+  F[3] = 0.5 * ((r3 + pl) * Ul + sl * r3);
+}
+
 // Nodal contravariant flux E^ = (rho U, m U + kx p, n U + ky p, (e + p) U),
 // U = kx u + ky v, with the nodal metric (Sec. 2.1).
 WIU_DEV void nodal_flux(const double Q[4], double kx, double ky, double gam, double E[4]) {
@@ -531,8 +590,33 @@ WIU_DEV double h7_plus(NF f, MF F) {
   }
 }
 
+// h^+_{i+1/2} of the one-midpoint families with free parameter a (Eq. 3.5
+// for SC 0, Eq. 3.17 for SC 2, Appendix (1) for SC 4); a = 1 is the printed
+// scheme, which hflux evaluates in its printed form instead.
+template <int SC, class NF, class MF>
+WIU_DEV double h1mp_plus(double a, NF f, MF F) {
+  if constexpr (SC == 0) {
+    return a * F(0) + (a * 0.125 - 1.0 / 6.0) * f(-1) + (-0.75 * a + 5.0 / 6.0) * f(0) +
+           (-0.375 * a + 1.0 / 3.0) * f(1);
+  } else if constexpr (SC == 2) {
+    return a * F(0) + (-3.0 / 128.0 * a + 1.0 / 30.0) * f(-2) + (5.0 / 32.0 * a - 13.0 / 60.0) * f(-1) +
+           (-45.0 / 64.0 * a + 47.0 / 60.0) * f(0) + (-15.0 / 32.0 * a + 0.45) * f(1) +
+           (5.0 / 128.0 * a - 0.05) * f(2);
+  } else {
+    return a * F(0) + (5.0 / 1024.0 * a - 1.0 / 140.0) * f(-3) + (-21.0 / 512.0 * a + 5.0 / 84.0) * f(-2) +
+           (175.0 / 1024.0 * a - 101.0 / 420.0) * f(-1) + (-175.0 / 256.0 * a + 319.0 / 420.0) * f(0) +
+           (-525.0 / 1024.0 * a + 107.0 / 210.0) * f(1) + (35.0 / 512.0 * a - 19.0 / 210.0) * f(2) +
+           (-7.0 / 1024.0 * a + 1.0 / 105.0) * f(3);
+  }
+}
+
 template <int SC, class FP, class FM, class GP, class GM>
-WIU_DEV double hflux(int i, FP fp, FM fm, GP Fp, GM Fm) {
+WIU_DEV double hflux(int i, double ah, FP fp, FM fm, GP Fp, GM Fm) {
+  if constexpr (SC == 0 || SC == 2 || SC == 4) {
+    if (ah != 1.0)
+      return h1mp_plus<SC>(ah, [&](int m) { return fp(i + m); }, [&](int m) { return Fp(i + m); }) +
+             h1mp_plus<SC>(ah, [&](int m) { return fm(i + 1 - m); }, [&](int m) { return Fm(i - m); });
+  }
   if constexpr (SC == 0) {
     return Fp(i) + (1.0 / 24.0) * (2.0 * fp(i) - fp(i - 1) - fp(i + 1)) +
            Fm(i) + (1.0 / 24.0) * (2.0 * fm(i + 1) - fm(i + 2) - fm(i));

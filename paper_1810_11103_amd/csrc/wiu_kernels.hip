@@ -106,7 +106,10 @@ WIU_DEV double diff_j(const Dims& d, const double* c, bool is_y, int a, int b1, 
 // 5 g_{i+4}) / 2048 -- is an antisymmetric node stencil
 // sum_m d_m (g_{i+m} - g_{i-m}), m = 1..7 (exact rationals):
 constexpr int METRIC_REACH = 7;
-__constant__ double kMetricStencil[8][METRIC_REACH] = {
+struct MetricStencil {
+  double d[METRIC_REACH];
+};
+const double kMetricStencil[8][METRIC_REACH] = {
     {557.0 / 768.0, -25.0 / 192.0, 3.0 / 256.0, 0.0, 0.0, 0.0, 0.0},                   // 3-1MP
     {1145.0 / 1536.0, -229.0 / 1536.0, 29.0 / 1536.0, -1.0 / 1024.0, 0.0, 0.0, 0.0},    // 3-2MP
     {3.0 / 4.0, -3.0 / 20.0, 1.0 / 60.0, 0.0, 0.0, 0.0, 0.0},                          // 5-1MP
@@ -119,6 +122,24 @@ __constant__ double kMetricStencil[8][METRIC_REACH] = {
      10039.0 / 15728640.0, -89.0 / 1835008.0, 15.0 / 7340032.0},                        // 7-6MP
 };
 
+// The stencil for a scheme and free parameter a of the one-midpoint forms.
+// Eq. 2.7 applied to Eq. 3.5 gives, with the six-point interpolation,
+//   d = (2/3 + 15a/256, -1/12 - 3a/64, 3a/256)      (3-1MP; a = 1: the table row).
+// For 5-1MP and 7-1MP the alpha term of h+ is a (F - P f), P the one-sided
+// five- (seven-) point interpolation, whose mirror average is the six-
+// (eight-) point central interpolation used here, so their operator does not
+// depend on a.
+MetricStencil metric_stencil(int scheme, double a) {
+  MetricStencil s;
+  for (int m = 0; m < METRIC_REACH; ++m) s.d[m] = kMetricStencil[scheme][m];
+  if (scheme == 0 && a != 1.0) {
+    s.d[0] = 2.0 / 3.0 + 15.0 * a / 256.0;
+    s.d[1] = -1.0 / 12.0 - 3.0 * a / 64.0;
+    s.d[2] = 3.0 * a / 256.0;
+  }
+  return s;
+}
+
 // Nodal-metric band beyond the stored ghost band: the reach of the midpoint
 // interpolation (3 for six points, 4 for eight).
 inline int metric_band(int scheme) { return GHOST + (scheme >= 4 ? 4 : 3); }
@@ -126,7 +147,7 @@ inline int metric_band(int scheme) { return GHOST + (scheme >= 4 ? 4 : 3); }
 // Nodal metrics on the band of width B around the grid: T[5][(ny+2B)(nx+2B)].
 // Periodic directions evaluate at the wrapped node so that band copies are
 // bitwise equal to the interior values.
-__global__ void metrics_nodal_kernel(Dims d, int scheme, int B, const double* __restrict__ x,
+__global__ void metrics_nodal_kernel(Dims d, MetricStencil ms, int B, const double* __restrict__ x,
                                      const double* __restrict__ y, double* __restrict__ T) {
   const int W = d.nx + 2 * B, Hh = d.ny + 2 * B;
   const int ta = blockIdx.x * blockDim.x + threadIdx.x;
@@ -138,7 +159,7 @@ __global__ void metrics_nodal_kernel(Dims d, int scheme, int B, const double* __
   double x_xi = 0.0, y_xi = 0.0, x_eta = 0.0, y_eta = 0.0;
 #pragma unroll
   for (int m = 1; m <= METRIC_REACH; ++m) {
-    const double cm = kMetricStencil[scheme][m - 1];
+    const double cm = ms.d[m - 1];
     if (cm == 0.0) continue;
     x_xi += cm * diff_i(d, x, true, b, a + m, a - m);
     y_xi += cm * diff_i(d, y, false, b, a + m, a - m);
@@ -155,7 +176,7 @@ __global__ void metrics_nodal_kernel(Dims d, int scheme, int B, const double* __
 }
 
 // Nodal and midpoint metrics on the stored band (width GHOST) plus the tag.
-__global__ void metrics_band_kernel(Dims d, int scheme, int B, const double* __restrict__ T,
+__global__ void metrics_band_kernel(Dims d, int scheme, double ah, int B, const double* __restrict__ T,
                                     double* __restrict__ M, int* __restrict__ status) {
   const int W = d.nx + 2 * GHOST, Hh = d.ny + 2 * GHOST;
   const int ta = blockIdx.x * blockDim.x + threadIdx.x;
@@ -163,7 +184,7 @@ __global__ void metrics_band_kernel(Dims d, int scheme, int B, const double* __r
   if (ta == 0 && tb == 0) {
     double* tag = M + 9 * d.mplane;
     tag[0] = TAG_MAGIC; tag[1] = (double)scheme; tag[2] = (double)d.nx; tag[3] = (double)d.ny;
-    tag[4] = (double)d.bcx; tag[5] = (double)d.bcy; tag[6] = 0.0; tag[7] = 0.0;
+    tag[4] = (double)d.bcx; tag[5] = (double)d.bcy; tag[6] = ah; tag[7] = 0.0;
   }
   if (ta >= W || tb >= Hh) return;
   const int a = ta - GHOST, b = tb - GHOST;
@@ -241,19 +262,19 @@ __global__ void lambda_out_kernel(Dims d, double alpha, const unsigned long long
 // U_out = P - b dt R^eta/J^{-1}, so U0 is read by the lighter xi epilogue.
 // Launched for 4 waves per SIMD (at most 128 VGPRs).
 // ===========================================================================
-template <int SC, int DIR, int NA, int NB>
+template <int SC, int DIR, int NA, int NB, bool OPT>
 __global__ void __launch_bounds__(NA * NB, sweep_waves<SC>()) sweep_kernel(SweepArgs s) {
   __shared__ SweepLds<SC, DIR, NA, NB> lds;
   // logical tile in XCD-aware order
   const int total = gridDim.x * gridDim.y;
   const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, total);
-  sweep_tile<SC, DIR, NA, NB>(s, lid % gridDim.x, lid / gridDim.x, lds);
+  sweep_tile<SC, DIR, NA, NB, OPT>(s, lid % gridDim.x, lid / gridDim.x, lds);
 }
 
 // ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
-template <int SC, int DIR, int NA, int NB>
+template <int SC, int DIR, int NA, int NB, bool OPT>
 hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   constexpr int OUT = NA - Range<SC>::EXTRA;
   const int n_al = DIR == 0 ? a.d.nx : a.d.ny;
@@ -262,15 +283,15 @@ hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   const int nlin = (n_ac + NB - 1) / NB;
   dim3 grid = DIR == 0 ? dim3(nseg, nlin) : dim3(nlin, nseg);
   dim3 block = DIR == 0 ? dim3(NA, NB) : dim3(NB, NA);
-  hipLaunchKernelGGL((sweep_kernel<SC, DIR, NA, NB>), grid, block, 0, st, a);
+  hipLaunchKernelGGL((sweep_kernel<SC, DIR, NA, NB, OPT>), grid, block, 0, st, a);
   return hipGetLastError();
 }
 
 // Tile shape `variant` of each direction (WIU_XI_TILES / WIU_ETA_TILES).
-template <int SC, int DIR>
-hipError_t launch_sweep_v(int variant, const SweepArgs& a, hipStream_t st) {
+template <int SC, int DIR, bool OPT>
+hipError_t launch_sweep_vo(int variant, const SweepArgs& a, hipStream_t st) {
 #define WIU_CASE(v, na, nb) \
-  case v: return launch_sweep_t<SC, DIR, na, nb>(a, st);
+  case v: return launch_sweep_t<SC, DIR, na, nb, OPT>(a, st);
   if constexpr (DIR == 0) {
     switch (variant) {
       WIU_XI_TILES(WIU_CASE)
@@ -283,6 +304,13 @@ hipError_t launch_sweep_v(int variant, const SweepArgs& a, hipStream_t st) {
     }
   }
 #undef WIU_CASE
+}
+
+// the options kernels only when an option is in use
+template <int SC, int DIR>
+hipError_t launch_sweep_v(int variant, const SweepArgs& a, hipStream_t st) {
+  if (a.vars != 0 || a.ah != 1.0) return launch_sweep_vo<SC, DIR, true>(variant, a, st);
+  return launch_sweep_vo<SC, DIR, false>(variant, a, st);
 }
 
 int sweep_variants(int dir) { return dir == 0 ? WIU_N_XI_TILES : WIU_N_ETA_TILES; }
@@ -325,14 +353,14 @@ hipError_t launch_fill_u64(unsigned long long* p, long long n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_metrics(const Dims& d, int scheme, const double* x, const double* y, double* M, double* T,
-                          int* status, hipStream_t st) {
+hipError_t launch_metrics(const Dims& d, int scheme, double ah, const double* x, const double* y, double* M,
+                          double* T, int* status, hipStream_t st) {
   const int B = metric_band(scheme);
   dim3 b1(64, 4);
   dim3 g1((d.nx + 2 * B + 63) / 64, (d.ny + 2 * B + 3) / 4);
-  hipLaunchKernelGGL(metrics_nodal_kernel, g1, b1, 0, st, d, scheme, B, x, y, T);
+  hipLaunchKernelGGL(metrics_nodal_kernel, g1, b1, 0, st, d, metric_stencil(scheme, ah), B, x, y, T);
   dim3 g2((d.nx + 2 * GHOST + 63) / 64, (d.ny + 2 * GHOST + 3) / 4);
-  hipLaunchKernelGGL(metrics_band_kernel, g2, b1, 0, st, d, scheme, B, T, M, status);
+  hipLaunchKernelGGL(metrics_band_kernel, g2, b1, 0, st, d, scheme, ah, B, T, M, status);
   return hipGetLastError();
 }
 
@@ -348,16 +376,16 @@ hipError_t launch_lambda_out(const Dims& d, double alpha, const unsigned long lo
   return hipGetLastError();
 }
 
-__global__ void set_tag_kernel(Dims d, int scheme, double* M) {
+__global__ void set_tag_kernel(Dims d, int scheme, double ah, double* M) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     double* tag = M + 9 * d.mplane;
     tag[0] = TAG_MAGIC; tag[1] = (double)scheme; tag[2] = (double)d.nx; tag[3] = (double)d.ny;
-    tag[4] = (double)d.bcx; tag[5] = (double)d.bcy; tag[6] = 0.0; tag[7] = 0.0;
+    tag[4] = (double)d.bcx; tag[5] = (double)d.bcy; tag[6] = ah; tag[7] = 0.0;
   }
 }
 
-hipError_t launch_set_tag(const Dims& d, int scheme, double* M, hipStream_t st) {
-  hipLaunchKernelGGL(set_tag_kernel, dim3(1), dim3(64), 0, st, d, scheme, M);
+hipError_t launch_set_tag(const Dims& d, int scheme, double ah, double* M, hipStream_t st) {
+  hipLaunchKernelGGL(set_tag_kernel, dim3(1), dim3(64), 0, st, d, scheme, ah, M);
   return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@ struct SweepArgs {
   const unsigned long long* lam_eta;
   double gamma, alpha, eps;
   int ppm;
+  int vars;                             // interpolation variables (WIU_VARS_*)
+  double ah;                            // free parameter of the one-midpoint schemes
   // 0 (xi) write R^xi; 1 (eta) dU/dt = -(R^xi + R^eta)/J^{-1};
   // 3 (xi) write P = ca U0 + cb (U - dt R^xi/J^{-1}) into the R^xi buffer;
   // 2 (eta) RK stage U_out = P - cb dt R^eta/J^{-1}
@@ -54,6 +56,8 @@ struct BatchArgs {
   int stage;                 // RK stage 0, 1, 2
   double gamma, alpha, eps;
   int ppm;
+  int vars;                  // interpolation variables (WIU_VARS_*)
+  double ah;                 // free parameter of the one-midpoint schemes
   int* status;
   double* U_all;             // bases of the offsets in BlockDev
   const double* M_all;
@@ -106,12 +110,12 @@ int scheme_extra(int scheme);
 int sweep_variants(int dir);
 hipError_t launch_wave_max(const Dims& d, const double* U, const double* M, double gam, unsigned long long* lx,
                            unsigned long long* le, unsigned long long* cfl, int* status, hipStream_t st);
-hipError_t launch_metrics(const Dims& d, int scheme, const double* x, const double* y, double* M, double* T,
-                          int* status, hipStream_t st);
+hipError_t launch_metrics(const Dims& d, int scheme, double ah, const double* x, const double* y, double* M,
+                          double* T, int* status, hipStream_t st);
 hipError_t launch_cfl_dt(const unsigned long long* cfl_max, double cfl, double* dt, hipStream_t st);
 hipError_t launch_lambda_out(const Dims& d, double alpha, const unsigned long long* lx, const unsigned long long* le,
                              double* ox, double* oe, hipStream_t st);
-hipError_t launch_set_tag(const Dims& d, int scheme, double* M, hipStream_t st);
+hipError_t launch_set_tag(const Dims& d, int scheme, double ah, double* M, hipStream_t st);
 hipError_t launch_zero_header(int* p, int n, hipStream_t st);
 
 }  // namespace wiu

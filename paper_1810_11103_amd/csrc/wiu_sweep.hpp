@@ -91,7 +91,8 @@ template <int SC, int DIR, int NA, int NB> struct SweepLds {
 
 // H_{i+1/2} - H_{i-1/2} at output node i of line tb from the items in LDS.
 template <int SC, int DIR, int NA, int NB>
-WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB>& L, int tb, int o0, int i, double lam, double R[4]) {
+WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB>& L, int tb, int o0, int i, double lam, double ah,
+                           double R[4]) {
   using R_ = Range<SC>;
   using LT = SweepLds<SC, DIR, NA, NB>;
   auto at = [&](int kk) { return LT::si(tb, kk - (o0 + R_::LO)); };      // item slot of node kk
@@ -103,7 +104,7 @@ WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB>& L, int tb, int o0, i
     auto fm = [&](int kk) { return 0.5 * (L.sh[c][at(kk)] - lam * L.sq[c][aq(kk)]); };
     auto Fp = [&](int kk) { return L.sh[4 + c][at(kk)]; };
     auto Fm = [&](int kk) { return L.sh[8 + c][at(kk)]; };
-    R[c] = hflux<SC>(i, fp, fm, Fp, Fm) - hflux<SC>(i - 1, fp, fm, Fp, Fm);
+    R[c] = hflux<SC>(i, ah, fp, fm, Fp, Fm) - hflux<SC>(i - 1, ah, fp, fm, Fp, Fm);
   }
 }
 
@@ -125,14 +126,14 @@ struct OutOperands {
 // separate pass, so the maxima are bit-identical to it.
 template <int SC, int NA, int NB>
 WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB>& L, bool act, int line, int i, int o0,
-                             int tb, double lam, const OutOperands& op) {
+                             int tb, double lam, double ah, const OutOperands& op) {
   static_assert(64 % NB == 0 && (NA * NB) % 64 == 0, "eta tile must pack whole waves");
   const Dims& d = s.d;
   double sx = 0.0, se = 0.0;
   bool bad = false;
   if (act) {
     double R[4];
-    tile_residual<SC, 1, NA, NB>(L, tb, o0, i, lam, R);
+    tile_residual<SC, 1, NA, NB>(L, tb, o0, i, lam, ah, R);
     const long long o = (long long)i * d.nx + line;
     const double rj = -rcp(op.jinv);
     const double dt = s.dt[0];
@@ -163,8 +164,13 @@ WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB>& L, boo
 // group of lines) for xi, (group of lines, segment) for eta.  Every thread of
 // the block calls it with the same tile; it contains three block-wide
 // barriers on every path that reaches the output phase, and none after.
-template <int SC, int DIR, int NA, int NB>
+// OPT: compiled with the scheme options (interpolation variables s.vars and
+// the free parameter s.ah); without it the tile runs the paper's
+// configuration (characteristic variables, alpha = 1) and carries no code
+// for the options, which keeps its register count down.
+template <int SC, int DIR, int NA, int NB, bool OPT>
 WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, NA, NB>& L) {
+  const double ah = OPT ? s.ah : 1.0;
   using R_ = Range<SC>;
   constexpr int OUT = NA - R_::EXTRA;
   constexpr int NT = NA * NB;
@@ -178,7 +184,8 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   // over the block, so no barrier is skipped by part of it)
   {
     const double* tag = s.M + 9 * d.mplane;
-    if (tag[0] != TAG_MAGIC || tag[1] != (double)SC || tag[2] != (double)d.nx || tag[3] != (double)d.ny) {
+    if (tag[0] != TAG_MAGIC || tag[1] != (double)SC || tag[2] != (double)d.nx || tag[3] != (double)d.ny ||
+        tag[6] != ah) {
       if (threadIdx.x == 0 && threadIdx.y == 0) atomicOr(s.status, ST_SCHEME);
       return;
     }
@@ -257,7 +264,9 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
       for (int side = 0; side < 2; ++side) {
         asm volatile("" ::: "memory");
         double F[4];
-        if constexpr (Traits<SC>::R == 4)
+        if (OPT && s.vars != 0)
+          side_flux_comp<Traits<SC>::R>(q, side, s.vars, mx, my, lam, gam, s.eps, s.ppm, F);
+        else if constexpr (Traits<SC>::R == 4)
           side_flux7(q, side, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, F);
         else
           side_flux<Traits<SC>::fifth>(q, side, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, F);
@@ -294,13 +303,13 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
 
   if constexpr (DIR == 1) {
     if (fused) {  // whole waves take part in the reductions
-      fused_stage_out<SC, NA, NB>(s, L, act, line, i, o0, tb, lam, op);
+      fused_stage_out<SC, NA, NB>(s, L, act, line, i, o0, tb, lam, ah, op);
       return;
     }
   }
   if (!act) return;  // no barrier follows
   double R[4];
-  tile_residual<SC, DIR, NA, NB>(L, tb, o0, i, lam, R);
+  tile_residual<SC, DIR, NA, NB>(L, tb, o0, i, lam, ah, R);
   if (s.mode == 0) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) s.Rxi[c * d.np + o] = R[c];

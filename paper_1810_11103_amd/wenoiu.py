@@ -43,7 +43,7 @@ class WiuBlock(ctypes.Structure):
 
 class WiuParams(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("alpha_lf", ctypes.c_double), ("eps", ctypes.c_double),
-                ("ppm", ctypes.c_int)]
+                ("ppm", ctypes.c_int), ("vars", ctypes.c_int), ("alpha_h", ctypes.c_double)]
 
 
 def _load():
@@ -58,8 +58,8 @@ def _load():
         "wiu_metrics_size": (ctypes.c_size_t, [G]),
         "wiu_workspace_bytes": (ctypes.c_size_t, [G]),
         "wiu_workspace_init": (I, [P, P]),
-        "wiu_metrics": (I, [G, I, P, P, P, P, P]),
-        "wiu_set_metrics_tag": (I, [G, I, P, P]),
+        "wiu_metrics": (I, [G, I, PR, P, P, P, P, P]),
+        "wiu_set_metrics_tag": (I, [G, I, PR, P, P]),
         "wiu_line_eigenvalues": (I, [G, PR, P, P, P, P, P, P]),
         "wiu_rhs": (I, [G, I, PR, P, P, P, P, P]),
         "wiu_cfl_dt": (I, [G, PR, P, P, ctypes.c_double, P, P, P]),
@@ -114,8 +114,14 @@ def make_grid(nx, ny, bc=("periodic", "periodic"), period=(0.0, 0.0)):
     return WiuGrid(int(nx), int(ny), bx, by, float(period[0]), float(period[1]))
 
 
-def make_params(gamma=1.4, alpha_lf=1.1, eps=1e-40, ppm=1):
-    return WiuParams(float(gamma), float(alpha_lf), float(eps), int(ppm))
+VARS = {"characteristic": 0, "conservative": 1, "primitive": 2}
+
+
+def make_params(gamma=1.4, alpha_lf=1.1, eps=1e-40, ppm=1, vars="characteristic", alpha_h=1.0):
+    """Scheme parameters; vars: interpolation variables (Sec. 2.4), alpha_h:
+    free parameter of the one-midpoint families (Eqs. 3.5, 3.17, Appendix)."""
+    v = VARS[vars] if isinstance(vars, str) else int(vars)
+    return WiuParams(float(gamma), float(alpha_lf), float(eps), int(ppm), v, float(alpha_h))
 
 
 def _stream(stream=None):
@@ -164,14 +170,19 @@ def workspace_init(ws, stream=None):
     _check(lib.wiu_workspace_init(ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
 
 
-def metrics(grid, scheme, x, y, M, ws, stream=None):
-    _check(lib.wiu_metrics(ctypes.byref(grid), scheme_id(scheme), _ptr(x), _ptr(y), _ptr(M),
+def _pref(params):
+    return ctypes.byref(params) if params is not None else None
+
+
+def metrics(grid, scheme, x, y, M, ws, stream=None, params=None):
+    _check(lib.wiu_metrics(ctypes.byref(grid), scheme_id(scheme), _pref(params), _ptr(x), _ptr(y), _ptr(M),
                            ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
     return M
 
 
-def set_metrics_tag(grid, scheme, M, stream=None):
-    _check(lib.wiu_set_metrics_tag(ctypes.byref(grid), scheme_id(scheme), _ptr(M), _stream(stream)))
+def set_metrics_tag(grid, scheme, M, stream=None, params=None):
+    _check(lib.wiu_set_metrics_tag(ctypes.byref(grid), scheme_id(scheme), _pref(params), _ptr(M),
+                                   _stream(stream)))
 
 
 def line_eigenvalues(grid, params, U, M, lam_xi, lam_eta, ws, stream=None):
@@ -280,7 +291,7 @@ class Solver:
         self.ws = workspace(self.grid, device)
         workspace_init(self.ws)
         self.M = metrics_tensor(self.grid, device)
-        metrics(self.grid, scheme, x, y, self.M, self.ws)
+        metrics(self.grid, scheme, x, y, self.M, self.ws, params=self.params)
         self.x, self.y = x, y
         self.dt = torch.zeros(1, dtype=torch.float64, device=device)
 
@@ -374,7 +385,7 @@ class BatchedPlan:
             xx = torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
             yy = torch.as_tensor(y, dtype=torch.float64).to(device).contiguous()
             Mb = self.M_all[d.off_M: d.off_M + metrics_size(g) // 8]
-            metrics(g, scheme, xx, yy, Mb, ws)
+            metrics(g, scheme, xx, yy, Mb, ws, params=self.params)
             if status(ws):
                 raise WiuError("metrics reported a folded cell")
         self._descs = (WiuBlock * len(descs))(*descs)

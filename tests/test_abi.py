@@ -75,9 +75,21 @@ def test_bad_scheme_params_and_pointers_rejected(wiu):
                                dummy, None) == wiu.WIU_EINVAL
     assert wiu.lib.wiu_rhs(ctypes.byref(g), 3, ctypes.byref(p), dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL
     assert wiu.lib.wiu_rhs(ctypes.byref(g), 3, ctypes.byref(p), None, dummy, other, dummy, None) == wiu.WIU_EINVAL
+    # interpolation variables 0..2; alpha_h != 1 only for the one-midpoint schemes
+    for kw, scheme in ((dict(vars=3), 3), (dict(alpha_h=0.9), 3), (dict(alpha_h=-1.0), 0), (dict(alpha_h=0.9), 7)):
+        q = wiu.make_params(**kw)
+        assert wiu.lib.wiu_rhs(ctypes.byref(g), scheme, ctypes.byref(q), dummy, dummy, other, dummy,
+                               None) == wiu.WIU_EINVAL, kw
+    assert wiu.lib.wiu_metrics(ctypes.byref(g), 3, ctypes.byref(wiu.make_params(alpha_h=0.9)), dummy, dummy, other,
+                               dummy, None) == wiu.WIU_EINVAL
+    # the adjoint: the paper's configuration only
+    for kw in (dict(vars=1), dict(alpha_h=0.9)):
+        q = wiu.make_params(**kw)
+        assert wiu.lib.wiu_rhs_vjp(ctypes.byref(g), 0, ctypes.byref(q), dummy, dummy, other, ctypes.c_void_p(768),
+                                   dummy, None) == wiu.WIU_EINVAL
     bad = wiu.make_params(gamma=1.0)
     assert wiu.lib.wiu_rhs(ctypes.byref(g), 3, ctypes.byref(bad), dummy, dummy, other, dummy, None) == wiu.WIU_EINVAL
-    assert wiu.lib.wiu_metrics(ctypes.byref(g), -1, dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL
+    assert wiu.lib.wiu_metrics(ctypes.byref(g), -1, None, dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL
     assert wiu.lib.wiu_cfl_dt(ctypes.byref(g), ctypes.byref(p), dummy, dummy, ctypes.c_double(-1.0), dummy, dummy,
                               None) == wiu.WIU_EINVAL
     assert wiu.lib.wiu_strerror(wiu.WIU_EINVAL) == b"invalid argument"

@@ -28,14 +28,26 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic operation count per cell of one WENOIU5-2MP rhs on a 2048-node
-# line length: (1720 + 5065/n) per sweep direction (characteristic WENO
-# midpoint fluxes, nodal splits, line wave speeds, H and its difference) plus
-# 8 for the final -(R_xi + R_eta)/J^{-1}, counted by instantiating the oracle
-# with an operation-counting scalar (add, sub, mul, div, sqrt = 1 each); the
-# RK stage update adds 5 per component.
+# Algorithmic operation count per cell of one rhs on lines of n nodes:
+# (A + B/n) per sweep direction (midpoint fluxes, nodal splits, line wave
+# speeds, H and its difference) plus 8 for the final -(R_xi + R_eta)/J^{-1},
+# counted by instantiating the oracle with an operation-counting scalar (add,
+# sub, mul, div, sqrt = 1 each) on the Riemann workload (oracle/count_flops.py;
+# B includes the oracle's uniform four-node ghost band, under 0.4 % of the
+# total at n = 2048).  The RK stage update adds 5 per component.  The
+# one-midpoint forms with alpha != 1 add a few operations per cell that the
+# table leaves out.
 N_DEFAULT = 2048
-FLOP_DIR_A, FLOP_DIR_B = 1720.0, 5065.0
+FLOP_DIR = {  # (scheme family, interpolation variables) -> (A, B)
+    ("3", "characteristic"): (1392.0, 9355.0), ("3", "conservative"): (672.0, 4321.0),
+    ("3", "primitive"): (822.0, 5374.0),
+    ("5-1MP", "characteristic"): (1728.0, 11475.0), ("5-1MP", "conservative"): (1008.0, 6439.0),
+    ("5-1MP", "primitive"): (1158.0, 7491.0),
+    ("5-2MP", "characteristic"): (1720.0, 11467.0), ("5-2MP", "conservative"): (1000.0, 6431.0),
+    ("5-2MP", "primitive"): (1150.0, 7483.0),
+    ("7", "characteristic"): (2728.0, 18155.0), ("7", "conservative"): (1832.0, 11907.0),
+    ("7", "primitive"): (2026.0, 13277.0),
+}
 FLOP_COMBINE = 8.0
 FLOP_RK_STAGE = 20.0
 PEAK_FP64_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
@@ -66,19 +78,21 @@ def profiled_traffic(n):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def flops_per_cell_dir(n):
-    return FLOP_DIR_A + FLOP_DIR_B / n
+def flops_per_cell_dir(n, scheme="5-2MP", vars="characteristic"):
+    key = scheme if scheme.startswith("5") else scheme[0]
+    A, B = FLOP_DIR[(key, vars)]
+    return A + B / n
 
 
-def cpu_baseline(g, U, scheme, cfl):
+def cpu_baseline(g, U, scheme, cfl, vars="characteristic", alpha_h=1.0):
     """The oracle, as it stands, timed on the host cores: one TVD-RK3 step of
     the full workload (3 rhs evaluations)."""
     import oracle
     oracle.build.build(force=False)
-    M = oracle.metrics(scheme, g.x, g.y, g.bc, g.period)
+    M = oracle.metrics(scheme, g.x, g.y, g.bc, g.period, alpha_h=alpha_h)
     dt = oracle.cfl_dt(U, M, cfl)
     t0 = time.perf_counter()
-    oracle.rk3_step(scheme, U, M, dt, g.bc)
+    oracle.rk3_step(scheme, U, M, dt, g.bc, vars=vars, alpha_h=alpha_h)
     t = time.perf_counter() - t0
     n = g.x.size
     return {"value": 3 * n / t, "unit": "cell-updates/s", "cores": oracle.get_threads(), "kind": "oracle",
@@ -203,6 +217,9 @@ def main():
     ap.add_argument("--n", type=int, default=N_DEFAULT)
     ap.add_argument("--scheme", default="5-2MP")
     ap.add_argument("--cfl", type=float, default=0.5)
+    ap.add_argument("--vars", default="characteristic", choices=("characteristic", "conservative", "primitive"),
+                    help="variables the midpoint states are interpolated in (Sec. 2.4)")
+    ap.add_argument("--alpha-h", type=float, default=1.0, help="free parameter of the one-midpoint schemes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-block leg")
     ap.add_argument("--no-rhs", action="store_true", help="skip the bare-rhs timing")
@@ -229,7 +246,8 @@ def main():
 
     n = args.n
     g, U0 = W.riemann_problem(n, A=0.2, seed=2048)
-    sol = wenoiu.Solver(g.x, g.y, args.scheme, g.bc, g.period)
+    params = wenoiu.make_params(vars=args.vars, alpha_h=args.alpha_h)
+    sol = wenoiu.Solver(g.x, g.y, args.scheme, g.bc, g.period, params=params)
     U = torch.as_tensor(U0).cuda().contiguous()
     torch.cuda.synchronize()
 
@@ -280,7 +298,7 @@ def main():
     st = sol.status()
 
     # roofline of the dominant kernel
-    fdir = flops_per_cell_dir(n)
+    fdir = flops_per_cell_dir(n, args.scheme, args.vars)
     per_launch = {
         "sweep_xi": cells * fdir,
         "sweep_eta": cells * (fdir + FLOP_COMBINE + FLOP_RK_STAGE),
@@ -307,8 +325,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"2-D Riemann problem, randomized {n}x{n} grid on [0,1]^2 (A=0.2, seed 2048), "
-                               f"WENOIU{args.scheme}, transmissive, TVD-RK3 CFL {args.cfl}",
-                   "n": n, "scheme": args.scheme, "cfl": args.cfl},
+                               f"WENOIU{args.scheme}, transmissive, TVD-RK3 CFL {args.cfl}"
+                               + ("" if args.vars == "characteristic" else f", {args.vars} variables")
+                               + ("" if args.alpha_h == 1.0 else f", alpha {args.alpha_h}"),
+                   "n": n, "scheme": args.scheme, "cfl": args.cfl, "vars": args.vars, "alpha_h": args.alpha_h},
         "roofline": roofline,
         "extra": {
             "rhs_ms": rhs_ms,
@@ -326,7 +346,7 @@ def main():
         torch.cuda.empty_cache()
         out["extra"]["adjoint"] = adjoint_leg()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(g, U0, args.scheme, args.cfl)
+        out["cpu_baseline"] = cpu_baseline(g, U0, args.scheme, args.cfl, args.vars, args.alpha_h)
     print(json.dumps(out), flush=True)
 
 

@@ -576,6 +576,9 @@ void midpoint_flux(Scheme sc, const Params& pr, const T Qs[8][4], double kx0, do
   double nbx = 0.5 * (kx0 + kx1), nby = 0.5 * (ky0 + ky1);
   double nn = std::sqrt(nbx * nbx + nby * nby);
   double nx_ = nbx / nn, ny_ = nby / nn;
+  // window entries the interpolation reads: Q_{k-3..k+4} for r = 4, Q_{k-2..k+3}
+  // otherwise (the others are left out, and set to zero where passed on)
+  const int m0 = seventh_order(sc) ? 0 : 1, m1 = seventh_order(sc) ? 8 : 7;
   for (int side = 0; side < 2; ++side) {
     const T* Qref = Qs[3 + side];  // Q_k for +, Q_{k+1} for -
     T Qm[4];
@@ -587,6 +590,7 @@ void midpoint_flux(Scheme sc, const Params& pr, const T Qs[8][4], double kx0, do
         T s[8];
         for (int m = 0; m < 8; ++m) {
           s[m] = T(0.0);
+          if (m < m0 || m >= m1) continue;
           for (int q = 0; q < 4; ++q) s[m] = s[m] + L[c][q] * (Qs[m][q] - Qref[q]);
         }
         W[c] = side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr);
@@ -602,7 +606,9 @@ void midpoint_flux(Scheme sc, const Params& pr, const T Qs[8][4], double kx0, do
       // node's values as above
       T V[8][4];
       for (int m = 0; m < 8; ++m) {
-        if (pr.vars == 1)
+        if (m < m0 || m >= m1)
+          for (int q = 0; q < 4; ++q) V[m][q] = T(0.0);
+        else if (pr.vars == 1)
           for (int q = 0; q < 4; ++q) V[m][q] = Qs[m][q];
         else
           to_primitive(Qs[m], pr.gamma, V[m]);
@@ -610,7 +616,7 @@ void midpoint_flux(Scheme sc, const Params& pr, const T Qs[8][4], double kx0, do
       T Vm[4];
       for (int c = 0; c < 4; ++c) {
         T s[8];
-        for (int m = 0; m < 8; ++m) s[m] = V[m][c] - V[3 + side][c];
+        for (int m = 0; m < 8; ++m) s[m] = (m < m0 || m >= m1) ? T(0.0) : V[m][c] - V[3 + side][c];
         Vm[c] = V[3 + side][c] + (side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr));
       }
       if (pr.vars == 1)

@@ -155,17 +155,26 @@ template <int SC> struct Range {
 //   third order:  g = C + K d^3, K = 1/C^2 for d <= 0, 1/(C-1)^2 above
 //   second order: g = C + K d^2, K = -1/C for d <= 0, 1/(1-C) above
 // (C[1 + (w/C - 1)^3] = C + d^3/C^2 and C[1 - (w/C - 1)^2] = C - d^2/C).
-// The piecewise constant K is a select on the sign of d (no branch).  (Folding
-// it into |d| as d (A d + B |d|) with A, B = (K_hi +- K_lo)/2 would cancel
-// badly where |K_lo| >> |K_hi|: up to 2e5 times for the fourth-order
-// mapping at C = 1/64.)
+// K d without a branch or a select: the product with the constant of smaller
+// magnitude is formed for either sign of d and the difference of the
+// constants is applied to the part of d on the other side (min(d, 0) or
+// max(d, 0), exact), so the result is exact on one side and within a few
+// ulp on the other.  (Folding K into |d| as A d + B |d|, A, B =
+// (K_hi +- K_lo)/2, cancels where |K_lo| >> |K_hi|: up to 2e5 times for the
+// fourth-order mapping at C = 1/64.  A select costs the compare, two
+// selects and VGPR copies of the 64-bit constants.)  The constants are
+// literals, so the choice of form is made at compile time.
+WIU_DEV double kd(double d, double Klo, double Khi) {
+  if (fabs(Klo) >= fabs(Khi)) return fma(Klo - Khi, fmin(d, 0.0), Khi * d);
+  return fma(Khi - Klo, fmax(d, 0.0), Klo * d);
+}
 WIU_DEV double map3(double w, double C, double Klo, double Khi) {
   const double d = w - C;
-  return fma(d * d, (d > 0.0 ? Khi : Klo) * d, C);
+  return fma(d * d, kd(d, Klo, Khi), C);
 }
 WIU_DEV double map2(double w, double C, double Klo, double Khi) {
   const double d = w - C;
-  return fma(d, (d > 0.0 ? Khi : Klo) * d, C);
+  return fma(d, kd(d, Klo, Khi), C);
 }
 
 // (K_lo, K_hi) of the mappings for the linear weights of Table 1.
@@ -184,23 +193,25 @@ WIU_DEV double map2(double w, double C, double Klo, double Khi) {
 
 // r = 3: left-biased value at k+1/2 from v_{k-2}, v_{k-1}, v_k = 0, v_{k+1},
 // v_{k+2} = (a, b, 0, d, e).  Candidates from Table 1 (b_{k,l}), linear
-// weights (1, 10, 5)/16, Jiang-Shu indicators (Eq. 3.22) from first
-// differences, weights alpha_k / sum alpha with alpha_k = C_k / (eps + IS_k)^2
-// formed with one reciprocal (w_k = C_k prod_{l != k} D_l / sum_m C_m
-// prod_{l != m} D_l), mapping Eq. 3.23 and re-normalisation.
+// weights (1, 10, 5)/16, Jiang-Shu indicators (Eq. 3.22)
+//   IS = 13/12 t^2 + 1/4 s^2 = 13/12 t^2 + u^2,  u = s/2,
+// with t, u formed directly from the values (t0 = a - 2b, u0 = a/2 - 2b;
+// t1 = b + d, u1 = (b - d)/2; t2 = e - 2d, u2 = e/2 - 2d), weights
+// alpha_k / sum alpha with alpha_k = C_k / (eps + IS_k)^2 formed with one
+// reciprocal (w_k = C_k prod_{l != k} D_l / sum_m C_m prod_{l != m} D_l; the
+// common factor 1/16 of the C_k cancels), mapping Eq. 3.23 and
+// re-normalisation.
 WIU_DEV double weno5(double a, double b, double d, double e, double eps, int ppm) {
   const double p0 = 0.375 * a - 1.25 * b;
   const double p1 = 0.375 * d - 0.125 * b;
   const double p2 = 0.75 * d - 0.125 * e;
-  // differences of (a, b, 0, d, e)
-  const double d1 = b - a, d2 = -b, d3 = d, d4 = e - d;
-  const double t0 = d2 - d1, t1 = d3 - d2, t2 = d4 - d3;
-  const double s0 = fma(3.0, d2, -d1), s1 = -(d2 + d3), s2 = fma(-3.0, d3, d4);
-  double D0 = eps + fma(13.0 / 12.0, t0 * t0, 0.25 * (s0 * s0));
-  double D1 = eps + fma(13.0 / 12.0, t1 * t1, 0.25 * (s1 * s1));
-  double D2 = eps + fma(13.0 / 12.0, t2 * t2, 0.25 * (s2 * s2));
+  const double t0 = fma(-2.0, b, a), t1 = b + d, t2 = fma(-2.0, d, e);
+  const double u0 = fma(-2.0, b, 0.5 * a), u1 = 0.5 * (b - d), u2 = fma(-2.0, d, 0.5 * e);
+  double D0 = fma(13.0 / 12.0, t0 * t0, fma(u0, u0, eps));
+  double D1 = fma(13.0 / 12.0, t1 * t1, fma(u1, u1, eps));
+  double D2 = fma(13.0 / 12.0, t2 * t2, fma(u2, u2, eps));
   D0 *= D0; D1 *= D1; D2 *= D2;
-  const double a0 = 0.0625 * (D1 * D2), a1 = 0.625 * (D0 * D2), a2 = 0.3125 * (D0 * D1);
+  const double a0 = D1 * D2, a1 = 10.0 * (D0 * D2), a2 = 5.0 * (D0 * D1);
   const double r = rcp(a0 + a1 + a2);
   double w0 = a0 * r, w1 = a1 * r, w2 = a2 * r;
   if (ppm) {
@@ -218,13 +229,13 @@ WIU_DEV double weno5(double a, double b, double d, double e, double eps, int ppm
 WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
   const double p0 = -0.5 * b;
   const double p1 = 0.5 * d;
-  const double d1 = b - a, d2 = -b, d3 = d;
-  const double t0 = d2 - d1, t1 = d3 - d2;
-  const double s0 = fma(3.0, d2, -d1), s1 = -(d2 + d3);
-  double D0 = eps + fma(13.0 / 12.0, t0 * t0, 0.25 * (s0 * s0));
-  double D1 = eps + fma(13.0 / 12.0, t1 * t1, 0.25 * (s1 * s1));
+  // the first two r = 3 indicators, in the form of weno5
+  const double t0 = fma(-2.0, b, a), t1 = b + d;
+  const double u0 = fma(-2.0, b, 0.5 * a), u1 = 0.5 * (b - d);
+  double D0 = fma(13.0 / 12.0, t0 * t0, fma(u0, u0, eps));
+  double D1 = fma(13.0 / 12.0, t1 * t1, fma(u1, u1, eps));
   D0 *= D0; D1 *= D1;
-  const double a0 = 0.25 * D1, a1 = 0.75 * D0;
+  const double a0 = D1, a1 = 3.0 * D0;
   const double r = rcp(a0 + a1);
   double w0 = a0 * r, w1 = a1 * r;
   if (ppm) {
@@ -239,8 +250,7 @@ WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
 // d <= 0 and 1/(1-C)^3 above.
 WIU_DEV double map4(double w, double C, double Klo, double Khi) {
   const double d = w - C;
-  const double d2 = d * d;
-  return fma(d2, (d > 0.0 ? Khi : Klo) * d2, C);
+  return fma(d * d, kd(d, Klo, Khi) * d, C);
 }
 //   C = 1/64, 21/64, 35/64, 7/64: K_lo = -(64/(64 C))^3, K_hi = (64/(64 - 64 C))^3
 #define WIU_M4L0 (-262144.0)
@@ -268,7 +278,7 @@ WIU_DEV double weno7(double a, double b, double c, double e, double f, double g,
   const double p2 = (-c + 9.0 * e - f) * 0.0625;
   const double p3 = (15.0 * e - 5.0 * f + g) * 0.0625;
   auto is = [&](double y1, double c2, double c3) {
-    return eps + fma(y1, y1, fma(13.0 / 3.0, c2 * c2, (781.0 / 20.0) * (c3 * c3)));
+    return fma(781.0 / 20.0, c3 * c3, fma(13.0 / 3.0, c2 * c2, fma(y1, y1, eps)));
   };
   const double ce = 0.5 * (c + e);  // c2 of the two central stencils
   double D0 = is(fma(1.5, b, fma(-1.0 / 3.0, a, -3.0 * c)), fma(2.0, b, fma(-0.5, a, -2.5 * c)),

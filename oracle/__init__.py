@@ -31,7 +31,7 @@ def lib():
             _build.build()
         L = ctypes.CDLL(path)
         L.orc_weno.restype = _D
-        L.orc_weno.argtypes = [_I, _P, _D, _I]
+        L.orc_weno.argtypes = [_I, _P, _D, _I, _I]
         L.orc_ppm.restype = _D
         L.orc_ppm.argtypes = [_I, _D, _D]
         L.orc_is.restype = _D
@@ -53,34 +53,34 @@ def lib():
         L.orc_flux_hat.restype = None
         L.orc_flux_hat.argtypes = [_P, _D, _D, _D, _P]
         L.orc_midpoint_flux.restype = _I
-        L.orc_midpoint_flux.argtypes = [_I, _D, _D, _I, _I, _P, _P, _P, _P, _D, _P, _P]
+        L.orc_midpoint_flux.argtypes = [_I, _D, _D, _I, _I, _I, _I, _P, _P, _P, _P, _D, _P, _P]
         L.orc_metrics_size.restype = ctypes.c_longlong
         L.orc_metrics_size.argtypes = [_I, _I]
         L.orc_metrics.restype = _I
         L.orc_metrics.argtypes = [_I, _D, _I, _I, _I, _I, _D, _D, _P, _P, _P]
         L.orc_rhs.restype = _I
-        L.orc_rhs.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _P, _P, _P]
+        L.orc_rhs.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P, _P]
         L.orc_cfl_dt.restype = _D
         L.orc_cfl_dt.argtypes = [_I, _I, _D, _P, _P, _D]
         L.orc_rk3_step.restype = _I
-        L.orc_rk3_step.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _D]
+        L.orc_rk3_step.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _D]
         L.orc_rk3_run.restype = _I
-        L.orc_rk3_run.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _D, _I]
+        L.orc_rk3_run.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _D, _I]
         L.orc_adv1d_rhs.restype = None
-        L.orc_adv1d_rhs.argtypes = [_I, _I, _D, _I, _D, _D, _I, _D, _P, _P]
+        L.orc_adv1d_rhs.argtypes = [_I, _I, _D, _I, _D, _D, _I, _D, _I, _P, _P]
         L.orc_adv1d_run.restype = _I
-        L.orc_adv1d_run.argtypes = [_I, _I, _I, _D, _D, _I, _D, _D, _D, _P, _P]
+        L.orc_adv1d_run.argtypes = [_I, _I, _I, _D, _D, _I, _D, _I, _D, _D, _P, _P]
         for nm in ("orc_rhs_jvp", "orc_rk3_step_jvp"):
             f = getattr(L, nm)
             f.restype = _I
-        L.orc_rhs_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _P, _P, _P]
-        L.orc_rk3_step_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _P, _D, _P, _P]
+        L.orc_rhs_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P, _P]
+        L.orc_rk3_step_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _D, _P, _P]
         L.orc_rhs_vjp.restype = _I
-        L.orc_rhs_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _P, _P]
+        L.orc_rhs_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P]
         L.orc_rk3_step_vjp.restype = _I
-        L.orc_rk3_step_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _D, _P, _P]
+        L.orc_rk3_step_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _D, _P, _P]
         L.orc_count_rhs_flops.restype = _I
-        L.orc_count_rhs_flops.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P, _P]
+        L.orc_count_rhs_flops.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P]
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [_I]
         L.orc_get_threads.restype = _I
@@ -106,6 +106,20 @@ def vars_id(v):
     return VARS[v] if isinstance(v, str) else int(v)
 
 
+WEIGHTS = {"js": 0, "z": 1}
+SPLITS = {"lf": 0, "sw": 1, "vl": 2}
+
+
+def weights_id(w):
+    """Nonlinear weights: "js" (Jiang-Shu, Eqs. 3.12-3.13) or "z" (WENO-Z)."""
+    return WEIGHTS[w] if isinstance(w, str) else int(w)
+
+
+def split_id(s):
+    """Midpoint flux split: "lf" (Lax-Friedrichs), "sw" (Steger-Warming), "vl" (van Leer)."""
+    return SPLITS[s] if isinstance(s, str) else int(s)
+
+
 def scheme_id(s):
     return SCHEMES[s] if isinstance(s, str) else int(s)
 
@@ -124,9 +138,9 @@ def get_threads():
 
 # ---- component probes ------------------------------------------------------------
 
-def weno(r, v, eps=1e-40, ppm=1):
+def weno(r, v, eps=1e-40, ppm=1, weights=0):
     v = _f64(v)
-    return lib().orc_weno(r, _ptr(v), eps, ppm)
+    return lib().orc_weno(r, _ptr(v), eps, ppm, weights_id(weights))
 
 
 def ppm(order, w, C):
@@ -192,14 +206,15 @@ def flux_hat(Q, gamma, kx, ky):
     return out
 
 
-def midpoint_flux(scheme, Qs, k0, k1, mk, lam, gamma=1.4, eps=1e-40, ppm=1, vars=0):
+def midpoint_flux(scheme, Qs, k0, k1, mk, lam, gamma=1.4, eps=1e-40, ppm=1, vars=0, weights=0, split=0):
     """F^+, F^- at k+1/2 from Qs = Q_{k-3..k+4} (8 states; 6 states Q_{k-2..k+3}
     are accepted for the third- and fifth-order schemes)."""
     Qs, k0, k1, mk = _f64(Qs), _f64(k0), _f64(k1), _f64(mk)
     if Qs.shape[0] == 6:
         Qs = np.ascontiguousarray(np.concatenate([Qs[:1], Qs, Qs[-1:]]))
     Fp, Fm = np.zeros(4), np.zeros(4)
-    rc = lib().orc_midpoint_flux(scheme_id(scheme), gamma, eps, ppm, vars_id(vars), _ptr(Qs), _ptr(k0), _ptr(k1),
+    rc = lib().orc_midpoint_flux(scheme_id(scheme), gamma, eps, ppm, vars_id(vars), weights_id(weights),
+                                 split_id(split), _ptr(Qs), _ptr(k0), _ptr(k1),
                                  _ptr(mk), lam, _ptr(Fp), _ptr(Fm))
     assert rc == 0
     return Fp, Fm
@@ -219,14 +234,14 @@ def metrics(scheme, x, y, bc=("periodic", "periodic"), period=(0.0, 0.0), alpha_
     return M
 
 
-def rhs(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0,
+def rhs(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0,
         return_lambda=False):
     U, M = _f64(U), _f64(M)
     _, ny, nx = U.shape
     out = np.zeros_like(U)
     lx = np.zeros(ny)
     le = np.zeros(nx)
-    rc = lib().orc_rhs(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
+    rc = lib().orc_rhs(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                        _ptr(U), _ptr(M), _ptr(out), _ptr(lx), _ptr(le))
     if rc:
         raise ValueError("orc_rhs failed")
@@ -235,58 +250,58 @@ def rhs(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-
     return out
 
 
-def count_rhs_flops(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
+def count_rhs_flops(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
     """Operation counts of one rhs: (xi sweep, eta sweep, final combination)."""
     U, M = _f64(U), _f64(M)
     _, ny, nx = U.shape
     c = np.zeros(3, dtype=np.int64)
-    rc = lib().orc_count_rhs_flops(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
+    rc = lib().orc_count_rhs_flops(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                                    _ptr(U), _ptr(M), _ptr(c))
     if rc:
         raise ValueError("orc_count_rhs_flops failed")
     return tuple(int(v) for v in c)
 
 
-def rhs_jvp(scheme, U, V, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
+def rhs_jvp(scheme, U, V, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
     """(rhs(U), (d rhs/dU) V) by forward-mode dual numbers."""
     U, V, M = _f64(U), _f64(V), _f64(M)
     _, ny, nx = U.shape
     val, tan = np.zeros_like(U), np.zeros_like(U)
-    rc = lib().orc_rhs_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
+    rc = lib().orc_rhs_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                            _ptr(U), _ptr(V), _ptr(M), _ptr(val), _ptr(tan))
     if rc:
         raise ValueError("orc_rhs_jvp failed")
     return val, tan
 
 
-def rhs_vjp(scheme, U, M, Gbar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
+def rhs_vjp(scheme, U, M, Gbar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
     """(d rhs/dU)^T Gbar by reverse mode on a tape."""
     U, M, Gbar = _f64(U), _f64(M), _f64(Gbar)
     _, ny, nx = U.shape
     out = np.zeros_like(U)
-    rc = lib().orc_rhs_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
+    rc = lib().orc_rhs_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                            _ptr(U), _ptr(M), _ptr(Gbar), _ptr(out))
     if rc:
         raise ValueError("orc_rhs_vjp failed")
     return out
 
 
-def rk3_step_jvp(scheme, U, V, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
+def rk3_step_jvp(scheme, U, V, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
     U, V, M = _f64(U), _f64(V), _f64(M)
     _, ny, nx = U.shape
     val, tan = np.zeros_like(U), np.zeros_like(U)
-    rc = lib().orc_rk3_step_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
+    rc = lib().orc_rk3_step_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                                 _ptr(U), _ptr(V), _ptr(M), dt, _ptr(val), _ptr(tan))
     if rc:
         raise ValueError("orc_rk3_step_jvp failed")
     return val, tan
 
 
-def rk3_step_vjp(scheme, U, M, dt, Ubar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
+def rk3_step_vjp(scheme, U, M, dt, Ubar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
     U, M, Ubar = _f64(U), _f64(M), _f64(Ubar)
     _, ny, nx = U.shape
     out = np.zeros_like(U)
-    rc = lib().orc_rk3_step_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
+    rc = lib().orc_rk3_step_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                                 _ptr(U), _ptr(M), dt, _ptr(Ubar), _ptr(out))
     if rc:
         raise ValueError("orc_rk3_step_vjp failed")
@@ -299,22 +314,22 @@ def cfl_dt(U, M, cfl, gamma=1.4):
     return lib().orc_cfl_dt(nx, ny, gamma, _ptr(U), _ptr(M), cfl)
 
 
-def rk3_step(scheme, U, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
+def rk3_step(scheme, U, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
     U = np.array(U, dtype=np.float64, copy=True, order="C")
     M = _f64(M)
     _, ny, nx = U.shape
-    rc = lib().orc_rk3_step(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
+    rc = lib().orc_rk3_step(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                             _ptr(U), _ptr(M), dt)
     if rc:
         raise ValueError("orc_rk3_step failed")
     return U
 
 
-def rk3_run(scheme, U, M, dt, nsteps, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0):
+def rk3_run(scheme, U, M, dt, nsteps, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
     U = np.array(U, dtype=np.float64, copy=True, order="C")
     M = _f64(M)
     _, ny, nx = U.shape
-    rc = lib().orc_rk3_run(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
+    rc = lib().orc_rk3_run(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                            _ptr(U), _ptr(M), dt, int(nsteps))
     if rc:
         raise ValueError("orc_rk3_run failed")
@@ -323,18 +338,19 @@ def rk3_run(scheme, U, M, dt, nsteps, bc=("periodic", "periodic"), gamma=1.4, al
 
 # ---- Sec. 5.1 scalar advection ------------------------------------------------------------
 
-def adv1d_rhs(scheme, u, dx, split=0, alpha=1.1, eps=1e-40, ppm=1, alpha_h=1.0):
+def adv1d_rhs(scheme, u, dx, split=0, alpha=1.1, eps=1e-40, ppm=1, alpha_h=1.0, weights=0):
     u = _f64(u)
     out = np.zeros_like(u)
-    lib().orc_adv1d_rhs(scheme_id(scheme), u.size, dx, split, alpha, eps, ppm, float(alpha_h), _ptr(u), _ptr(out))
+    lib().orc_adv1d_rhs(scheme_id(scheme), u.size, dx, split, alpha, eps, ppm, float(alpha_h), weights_id(weights),
+                        _ptr(u), _ptr(out))
     return out
 
 
-def adv1d_run(scheme, N, split=0, alpha=1.1, eps=1e-40, ppm=1, tend=2.0, dtpow=1.25, alpha_h=1.0):
+def adv1d_run(scheme, N, split=0, alpha=1.1, eps=1e-40, ppm=1, tend=2.0, dtpow=1.25, alpha_h=1.0, weights=0):
     l2 = ctypes.c_double()
     li = ctypes.c_double()
-    rc = lib().orc_adv1d_run(scheme_id(scheme), N, split, alpha, eps, ppm, float(alpha_h), tend, dtpow,
-                             ctypes.byref(l2), ctypes.byref(li))
+    rc = lib().orc_adv1d_run(scheme_id(scheme), N, split, alpha, eps, ppm, float(alpha_h), weights_id(weights), tend,
+                             dtpow, ctypes.byref(l2), ctypes.byref(li))
     if rc:
         raise ValueError("orc_adv1d_run failed")
     return l2.value, li.value

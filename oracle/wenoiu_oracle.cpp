@@ -24,17 +24,20 @@ Grid make_grid(int nx, int ny, int bcx, int bcy, double Lx, double Ly) {
   return g;
 }
 
-Params make_params(double gamma, double alpha, double eps, int ppm, int vars = 0, double alpha_h = 1.0) {
+Params make_params(double gamma, double alpha, double eps, int ppm, int vars = 0, double alpha_h = 1.0,
+                   int weights = 0, int split = 0) {
   Params p;
   p.gamma = gamma; p.alpha_lf = alpha; p.eps = eps; p.ppm = ppm; p.vars = vars; p.alpha_h = alpha_h;
+  p.weights = weights; p.split = split;
   return p;
 }
 
 bool bad_scheme(int s) { return s < 0 || s > 7; }
 
 // alpha_h other than 1 exists only for the one-midpoint schemes
-bool bad_options(int s, int vars, double alpha_h) {
-  return bad_scheme(s) || vars < 0 || vars > 2 || (alpha_h != 1.0 && !one_midpoint(s)) || !(alpha_h > 0.0);
+bool bad_options(int s, int vars, double alpha_h, int weights, int split) {
+  return bad_scheme(s) || vars < 0 || vars > 2 || (alpha_h != 1.0 && !one_midpoint(s)) || !(alpha_h > 0.0) ||
+         weights < 0 || weights > 1 || split < 0 || split > 2;
 }
 
 }  // namespace
@@ -61,8 +64,8 @@ int orc_get_threads(void) {
 
 // WENO interpolation to k+1/2.  r = 4: v[0..6] = v_{k-3..k+3}; r = 3:
 // v[0..4] = v_{k-2..k+2}; r = 2: v[0..3] = v_{k-2..k+1}.
-double orc_weno(int r, const double* v, double eps, int ppm) {
-  Params p = make_params(1.4, 1.1, eps, ppm);
+double orc_weno(int r, const double* v, double eps, int ppm, int weights) {
+  Params p = make_params(1.4, 1.1, eps, ppm, 0, 1.0, weights);
   if (r == 4) return weno_r4(v, p);
   if (r == 3) return weno_r3(v, p);
   return weno_r2(v, p);
@@ -128,10 +131,11 @@ void orc_flux_hat(const double* Q, double gamma, double kx, double ky, double* o
 
 // Midpoint split fluxes: Qs[8][4] = Q_{k-3..k+4}; k0 = (kx,ky) at k, k1 at k+1,
 // mk = midpoint metric; lam = line eigenvalue.
-int orc_midpoint_flux(int scheme, double gamma, double eps, int ppm, int vars, const double* Qs, const double* k0,
-                      const double* k1, const double* mk, double lam, double* Fp, double* Fm) {
-  if (bad_options(scheme, vars, 1.0)) return -1;
-  Params p = make_params(gamma, 1.1, eps, ppm, vars);
+int orc_midpoint_flux(int scheme, double gamma, double eps, int ppm, int vars, int weights, int split,
+                      const double* Qs, const double* k0, const double* k1, const double* mk, double lam, double* Fp,
+                      double* Fm) {
+  if (bad_options(scheme, vars, 1.0, weights, split)) return -1;
+  Params p = make_params(gamma, 1.1, eps, ppm, vars, 1.0, weights, split);
   double QQ[8][4];
   std::memcpy(QQ, Qs, sizeof(QQ));
   midpoint_flux((Scheme)scheme, p, QQ, k0[0], k0[1], k1[0], k1[1], mk[0], mk[1], lam, Fp, Fm);
@@ -145,7 +149,7 @@ int orc_ghost(void) { return G; }
 
 int orc_metrics(int scheme, double alpha_h, int nx, int ny, int bcx, int bcy, double Lx, double Ly, const double* x,
                 const double* y, double* M) {
-  if (bad_options(scheme, 0, alpha_h) || nx < 1 || ny < 1) return -1;
+  if (bad_options(scheme, 0, alpha_h, 0, 0) || nx < 1 || ny < 1) return -1;
   if ((bcx == TRANSMISSIVE && nx < 2) || (bcy == TRANSMISSIVE && ny < 2)) return -1;
   Grid g = make_grid(nx, ny, bcx, bcy, Lx, Ly);
   compute_metrics((Scheme)scheme, alpha_h, g, x, y, M);
@@ -153,11 +157,11 @@ int orc_metrics(int scheme, double alpha_h, int nx, int ny, int bcx, int bcy, do
 }
 
 int orc_rhs(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
-         double alpha_h,
+         double alpha_h, int weights, int split,
             const double* U, const double* M, double* dUdt, double* lam_xi, double* lam_eta) {
-  if (bad_options(scheme, vars, alpha_h) || nx < 1 || ny < 1) return -1;
+  if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
   Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
-  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h);
+  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   rhs<double>((Scheme)scheme, p, g, U, M, dUdt, lam_xi, lam_eta);
   return 0;
 }
@@ -169,21 +173,21 @@ double orc_cfl_dt(int nx, int ny, double gamma, const double* U, const double* M
 }
 
 int orc_rk3_step(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
-         double alpha_h,
+         double alpha_h, int weights, int split,
                  double* U, const double* M, double dt) {
-  if (bad_options(scheme, vars, alpha_h) || nx < 1 || ny < 1) return -1;
+  if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
   Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
-  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h);
+  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   rk3_step<double>((Scheme)scheme, p, g, U, M, dt);
   return 0;
 }
 
 // Run nsteps TVD-RK3 steps at fixed dt.
 int orc_rk3_run(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
-         double alpha_h,
+         double alpha_h, int weights, int split,
                 double* U, const double* M, double dt, int nsteps) {
   for (int s = 0; s < nsteps; ++s) {
-    int rc = orc_rk3_step(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, U, M, dt);
+    int rc = orc_rk3_step(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U, M, dt);
     if (rc) return rc;
   }
   return 0;
@@ -195,8 +199,8 @@ int orc_rk3_run(int scheme, int nx, int ny, int bcx, int bcy, double gamma, doub
 // split = 1: Lax-Friedrichs split f+- = (u +- alpha u)/2.  Midpoint values
 // interpolate u and form the flux from it (Sec. 2.4).
 void orc_adv1d_rhs(int scheme, int N, double dx, int split, double alpha, double eps, int ppm, double alpha_h,
-                   const double* u, double* dudt) {
-  Params p = make_params(1.4, alpha, eps, ppm, 0, alpha_h);
+                   int weights, const double* u, double* dudt) {
+  Params p = make_params(1.4, alpha, eps, ppm, 0, alpha_h, weights);
   Scheme sc = (Scheme)scheme;
   auto U = [&](int k) { return u[wrap(k, N)]; };
   double cp = split == 0 ? 1.0 : 0.5 * (1.0 + alpha);
@@ -226,9 +230,9 @@ void orc_adv1d_rhs(int scheme, int N, double dx, int split, double alpha, double
 // with dt = dx^dtpow (5/4 in Table 3; 7/4 keeps RK4's error below a
 // seventh-order spatial one), shortened to land on tend, errors against the
 // exact translated solution.
-int orc_adv1d_run(int scheme, int N, int split, double alpha, double eps, int ppm, double alpha_h, double tend,
-                  double dtpow, double* l2, double* linf) {
-  if (bad_options(scheme, 0, alpha_h) || N < 8) return -1;
+int orc_adv1d_run(int scheme, int N, int split, double alpha, double eps, int ppm, double alpha_h, int weights,
+                  double tend, double dtpow, double* l2, double* linf) {
+  if (bad_options(scheme, 0, alpha_h, weights, 0) || N < 8) return -1;
   const double PI = 3.14159265358979323846;
   double dx = 2.0 / N;
   auto u0 = [&](double x) { return std::sin(PI * x - std::sin(PI * x) / PI); };
@@ -237,13 +241,13 @@ int orc_adv1d_run(int scheme, int N, int split, double alpha, double eps, int pp
   int nsteps = (int)std::ceil(tend / std::pow(dx, dtpow) - 1e-12);
   double dt = tend / nsteps;
   for (int s = 0; s < nsteps; ++s) {
-    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, alpha_h, u.data(), k1.data());
+    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, alpha_h, weights, u.data(), k1.data());
     for (int i = 0; i < N; ++i) tmp[i] = u[i] + 0.5 * dt * k1[i];
-    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, alpha_h, tmp.data(), k2.data());
+    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, alpha_h, weights, tmp.data(), k2.data());
     for (int i = 0; i < N; ++i) tmp[i] = u[i] + 0.5 * dt * k2[i];
-    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, alpha_h, tmp.data(), k3.data());
+    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, alpha_h, weights, tmp.data(), k3.data());
     for (int i = 0; i < N; ++i) tmp[i] = u[i] + dt * k3[i];
-    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, alpha_h, tmp.data(), k4.data());
+    orc_adv1d_rhs(scheme, N, dx, split, alpha, eps, ppm, alpha_h, weights, tmp.data(), k4.data());
     for (int i = 0; i < N; ++i) u[i] += dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
   }
   double s2 = 0.0, smax = 0.0;
@@ -271,12 +275,12 @@ struct SingleThread {
 
 // out_val = rhs(U), out_tan = (d rhs / dU) V (forward mode).
 int orc_rhs_jvp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
-         double alpha_h,
+         double alpha_h, int weights, int split,
                 const double* U, const double* V, const double* M, double* out_val, double* out_tan) {
-  if (bad_options(scheme, vars, alpha_h) || nx < 1 || ny < 1) return -1;
+  if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
   SingleThread guard;
   Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
-  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h);
+  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   const size_t N = 4 * (size_t)nx * ny;
   std::vector<Dual> Ud(N), out(N);
   for (size_t e = 0; e < N; ++e) Ud[e] = Dual(U[e], V[e]);
@@ -287,12 +291,12 @@ int orc_rhs_jvp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, doub
 
 // Ubar = (d rhs / dU)^T Gbar (reverse mode on a tape).
 int orc_rhs_vjp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
-         double alpha_h,
+         double alpha_h, int weights, int split,
                 const double* U, const double* M, const double* Gbar, double* Ubar) {
-  if (bad_options(scheme, vars, alpha_h) || nx < 1 || ny < 1) return -1;
+  if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
   SingleThread guard;
   Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
-  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h);
+  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   const size_t N = 4 * (size_t)nx * ny;
   Tape& tape = Tape::get();
   tape.clear();
@@ -310,13 +314,13 @@ int orc_rhs_vjp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, doub
 
 // Tangent of one TVD-RK3 step at fixed dt: (U_out, dU_out) from (U, V).
 int orc_rk3_step_jvp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
-         double alpha_h,
+         double alpha_h, int weights, int split,
                      const double* U, const double* V, const double* M, double dt, double* out_val,
                      double* out_tan) {
-  if (bad_options(scheme, vars, alpha_h) || nx < 1 || ny < 1) return -1;
+  if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
   SingleThread guard;
   Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
-  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h);
+  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   const size_t N = 4 * (size_t)nx * ny;
   std::vector<Dual> Ud(N);
   for (size_t e = 0; e < N; ++e) Ud[e] = Dual(U[e], V[e]);
@@ -329,11 +333,11 @@ int orc_rk3_step_jvp(int scheme, int nx, int ny, int bcx, int bcy, double gamma,
 // composed from the stage adjoints:
 //   U1 = U + dt L(U);  U2 = 3/4 U + 1/4 (U1 + dt L(U1));  U' = 1/3 U + 2/3 (U2 + dt L(U2))
 int orc_rk3_step_vjp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
-         double alpha_h,
+         double alpha_h, int weights, int split,
                      const double* U, const double* M, double dt, const double* Ubar_np1, double* Ubar_n) {
-  if (bad_options(scheme, vars, alpha_h) || nx < 1 || ny < 1) return -1;
+  if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
   Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
-  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h);
+  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   const size_t N = 4 * (size_t)nx * ny;
   std::vector<double> L(N), U1(N), U2(N), w(N), a(N), u2b(N), u1b(N);
   rhs<double>((Scheme)scheme, p, g, U, M, L.data());
@@ -341,19 +345,19 @@ int orc_rk3_step_vjp(int scheme, int nx, int ny, int bcx, int bcy, double gamma,
   rhs<double>((Scheme)scheme, p, g, U1.data(), M, L.data());
   for (size_t e = 0; e < N; ++e) U2[e] = 0.75 * U[e] + 0.25 * (U1[e] + dt * L[e]);
   // stage 3
-  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, U2.data(), M, Ubar_np1, a.data());
+  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U2.data(), M, Ubar_np1, a.data());
   for (size_t e = 0; e < N; ++e) {
     u2b[e] = (2.0 / 3.0) * (Ubar_np1[e] + dt * a[e]);
     Ubar_n[e] = (1.0 / 3.0) * Ubar_np1[e];
   }
   // stage 2
-  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, U1.data(), M, u2b.data(), a.data());
+  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U1.data(), M, u2b.data(), a.data());
   for (size_t e = 0; e < N; ++e) {
     u1b[e] = 0.25 * (u2b[e] + dt * a[e]);
     Ubar_n[e] += 0.75 * u2b[e];
   }
   // stage 1
-  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, U, M, u1b.data(), a.data());
+  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U, M, u1b.data(), a.data());
   for (size_t e = 0; e < N; ++e) Ubar_n[e] += u1b[e] + dt * a[e];
   return 0;
 }
@@ -365,10 +369,10 @@ static long long g_marks[3];
 static void mark(int ph) { g_marks[ph] = Counted::n(); }
 
 int orc_count_rhs_flops(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps,
-                        int ppm, int vars, double alpha_h, const double* U, const double* M, long long* counts) {
-  if (bad_options(scheme, vars, alpha_h) || nx < 1 || ny < 1) return -1;
+                        int ppm, int vars, double alpha_h, int weights, int split, const double* U, const double* M, long long* counts) {
+  if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
   Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
-  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h);
+  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   const size_t N = 4 * (size_t)nx * ny;
   std::vector<Counted> Uc(U, U + N), out(N);
 #ifdef _OPENMP

@@ -41,6 +41,13 @@ struct Params {
   // Free parameter alpha of the one-midpoint families (Eqs. 3.5, 3.17 and
   // Appendix (1)); the paper tests alpha = 1 only.  Other schemes require 1.
   double alpha_h = 1.0;
+  // Nonlinear weights: 0 Jiang-Shu (Eqs. 3.12-3.13, the paper's), 1 WENO-Z
+  // (named in Sec. 7 as a possible alternative).
+  int weights = 0;
+  // Splitting of the midpoint flux: 0 Lax-Friedrichs with the line
+  // eigenvalue (Sec. 2.3, the paper's), 1 Steger-Warming, 2 van Leer (named
+  // in Sec. 7 as possible alternatives for the midpoint flux only).
+  int split = 0;
 };
 
 inline bool one_midpoint(int s) { return s == 0 || s == 2 || s == 4; }
@@ -89,6 +96,33 @@ template <class T> T ppm3(const T& w, double C) {
   return C + d * d * d / ((C - 1.0) * (C - 1.0));
 }
 
+// Nonlinear weights from the indicators IS_k and linear weights C_k.
+//   weights 0: Eqs. 3.12-3.13, alpha_k = C_k / (eps + IS_k)^2, w = alpha /
+//     sum alpha; with the mapping (ppm), g_k = map(w_k; C_k) re-normalised.
+//   weights 1 (WENO-Z; Sec. 7 names it, gives no details; reading): alpha_k =
+//     C_k (1 + (tau / (eps + IS_k))^2) with the global indicator tau passed
+//     in, w = alpha / sum alpha, no mapping.
+template <class T, int N, class Map>
+void nonlinear_weights(const T (&IS)[N], const double (&C)[N], const T& tau, const Params& pr, Map map, T (&w)[N]) {
+  T a[N], sa = T(0.0);
+  for (int k = 0; k < N; ++k) {
+    T d = pr.eps + IS[k];
+    if (pr.weights == 1) {
+      T q = tau / d;
+      a[k] = C[k] * (1.0 + q * q);
+    } else {
+      a[k] = C[k] / (d * d);
+    }
+    sa = sa + a[k];
+  }
+  for (int k = 0; k < N; ++k) w[k] = a[k] / sa;
+  if (pr.weights == 0 && pr.ppm) {
+    T g[N], sg = T(0.0);
+    for (int k = 0; k < N; ++k) { g[k] = map(w[k], C[k]); sg = sg + g[k]; }
+    for (int k = 0; k < N; ++k) w[k] = g[k] / sg;
+  }
+}
+
 // r = 3 (fifth-order schemes).  v[0..4] = v_{k-2}, ..., v_{k+2}; returns the
 // left-biased value at k+1/2.  Candidates p_k^3 from Eq. 3.11 with the b_{k,l}
 // of Table 1, linear weights C = (1, 10, 5)/16, weights Eqs. 3.12-3.13,
@@ -100,15 +134,9 @@ template <class T> T weno_r3(const T v[5], const Params& pr) {
   p[1] = (-1.0 / 8.0) * v[1] + (6.0 / 8.0) * v[2] + (3.0 / 8.0) * v[3];
   p[2] = (3.0 / 8.0) * v[2] + (6.0 / 8.0) * v[3] - (1.0 / 8.0) * v[4];
   T IS[3] = {is_left(v[0], v[1], v[2]), is_mid(v[1], v[2], v[3]), is_right(v[2], v[3], v[4])};
-  T a[3], sa = T(0.0);
-  for (int k = 0; k < 3; ++k) { T d = pr.eps + IS[k]; a[k] = C[k] / (d * d); sa = sa + a[k]; }
   T w[3];
-  for (int k = 0; k < 3; ++k) w[k] = a[k] / sa;
-  if (pr.ppm) {
-    T g[3], sg = T(0.0);
-    for (int k = 0; k < 3; ++k) { g[k] = ppm3(w[k], C[k]); sg = sg + g[k]; }
-    for (int k = 0; k < 3; ++k) w[k] = g[k] / sg;
-  }
+  // WENO-Z global indicator for r = 3: |IS_0 - IS_2|
+  nonlinear_weights(IS, C, fabs(IS[0] - IS[2]), pr, [](const T& x, double c) { return ppm3(x, c); }, w);
   return w[0] * p[0] + w[1] * p[1] + w[2] * p[2];
 }
 
@@ -122,15 +150,9 @@ template <class T> T weno_r2(const T v[4], const Params& pr) {
   p[0] = (-1.0 / 2.0) * v[1] + (3.0 / 2.0) * v[2];
   p[1] = (1.0 / 2.0) * v[2] + (1.0 / 2.0) * v[3];
   T IS[2] = {is_left(v[0], v[1], v[2]), is_mid(v[1], v[2], v[3])};
-  T a[2], sa = T(0.0);
-  for (int k = 0; k < 2; ++k) { T d = pr.eps + IS[k]; a[k] = C[k] / (d * d); sa = sa + a[k]; }
   T w[2];
-  for (int k = 0; k < 2; ++k) w[k] = a[k] / sa;
-  if (pr.ppm) {
-    T g[2], sg = T(0.0);
-    for (int k = 0; k < 2; ++k) { g[k] = ppm2(w[k], C[k]); sg = sg + g[k]; }
-    for (int k = 0; k < 2; ++k) w[k] = g[k] / sg;
-  }
+  // WENO-Z global indicator for r = 2: |IS_0 - IS_1|
+  nonlinear_weights(IS, C, fabs(IS[0] - IS[1]), pr, [](const T& x, double c) { return ppm2(x, c); }, w);
   return w[0] * p[0] + w[1] * p[1];
 }
 
@@ -172,15 +194,10 @@ template <class T> T weno_r4(const T v[7], const Params& pr) {
   p[3] = (5.0 * v[3] + 15.0 * v[4] - 5.0 * v[5] + 1.0 * v[6]) / 16.0;
   T IS[4];
   for (int k = 0; k < 4; ++k) IS[k] = is_r4(k, v[k], v[k + 1], v[k + 2], v[k + 3]);
-  T a[4], sa = T(0.0);
-  for (int k = 0; k < 4; ++k) { T d = pr.eps + IS[k]; a[k] = C[k] / (d * d); sa = sa + a[k]; }
   T w[4];
-  for (int k = 0; k < 4; ++k) w[k] = a[k] / sa;
-  if (pr.ppm) {
-    T g[4], sg = T(0.0);
-    for (int k = 0; k < 4; ++k) { g[k] = ppm4(w[k], C[k]); sg = sg + g[k]; }
-    for (int k = 0; k < 4; ++k) w[k] = g[k] / sg;
-  }
+  // WENO-Z global indicator for r = 4: |IS_0 + 3 IS_1 - 3 IS_2 - IS_3|
+  nonlinear_weights(IS, C, fabs(IS[0] + 3.0 * IS[1] - 3.0 * IS[2] - IS[3]), pr,
+                    [](const T& x, double c) { return ppm4(x, c); }, w);
   return w[0] * p[0] + w[1] * p[1] + w[2] * p[2] + w[3] * p[3];
 }
 
@@ -554,6 +571,76 @@ template <class T> void eigenvectors(const T Q[4], double gam, double nx_, doubl
 }
 
 // ===========================================================================
+// Split of the midpoint flux at the interpolated state Q (side 0: F^+, side
+// 1: F^-) with the midpoint metric k = (kx, ky).
+//   split 0 (the paper's, Sec. 2.3): Lax-Friedrichs, F+- = (E^(Q; k) +- lam Q)/2
+//     with the line eigenvalue lam.
+//   split 1 (Steger-Warming; Sec. 7 names it): F+- = R diag(l+-) L Q with the
+//     eigen-decomposition of the flux Jacobian along n = k/|k| at Q,
+//     l = |k| (q_n - c, q_n, q_n, q_n + c), l+- = (l +- |l|)/2.  Since E^ is
+//     homogeneous of degree one in Q, F+ + F- = E^(Q; k).
+//   split 2 (van Leer; Sec. 7 names it): the Mach-number split along n,
+//     M = q_n / c; F+ = E^, F- = 0 for M >= 1 (mirrored for M <= -1), else
+//     F+- = +-|k| rho c (M +- 1)^2 / 4 (1, u + n_x (-q_n +- 2c)/gamma,
+//     v + n_y (-q_n +- 2c)/gamma, ((gamma-1) q_n +- 2c)^2 / (2(gamma^2-1)) +
+//     (q^2 - q_n^2)/2).
+// Only the midpoint flux is split differently; the nodal fluxes keep the
+// Lax-Friedrichs split, so FSP is unaffected (at a uniform state every split
+// sums to E^ with the same midpoint metric).
+// ===========================================================================
+template <class T>
+void midpoint_split(const Params& pr, const T Q[4], double kx, double ky, const T& lam, int side, T out[4]) {
+  const double gam = pr.gamma;
+  if (pr.split == 0) {
+    T E[4];
+    flux_hat(Q, gam, kx, ky, E);
+    const double sgn = side == 0 ? 1.0 : -1.0;
+    for (int q = 0; q < 4; ++q) out[q] = 0.5 * (E[q] + sgn * lam * Q[q]);
+    return;
+  }
+  const double kn = std::sqrt(kx * kx + ky * ky);
+  const double nx_ = kx / kn, ny_ = ky / kn;
+  const T rho = Q[0], u = Q[1] / rho, v = Q[2] / rho;
+  const T p = pressure(Q, gam);
+  const T c = sqrt(gam * p / rho);
+  const T qn = u * nx_ + v * ny_;
+  if (pr.split == 1) {
+    T L[4][4], R[4][4];
+    eigenvectors(Q, gam, nx_, ny_, L, R);
+    const T lam4[4] = {kn * (qn - c), kn * qn, kn * qn, kn * (qn + c)};
+    T w[4];
+    for (int a = 0; a < 4; ++a) {
+      T lq = T(0.0);
+      for (int b = 0; b < 4; ++b) lq = lq + L[a][b] * Q[b];
+      const T part = side == 0 ? 0.5 * (lam4[a] + fabs(lam4[a])) : 0.5 * (lam4[a] - fabs(lam4[a]));
+      w[a] = part * lq;
+    }
+    for (int a = 0; a < 4; ++a) {
+      out[a] = T(0.0);
+      for (int b = 0; b < 4; ++b) out[a] = out[a] + R[a][b] * w[b];
+    }
+    return;
+  }
+  const T M = qn / c;
+  if ((side == 0 && T(1.0) <= M) || (side == 1 && M <= T(-1.0))) {
+    flux_hat(Q, gam, kx, ky, out);
+    return;
+  }
+  if ((side == 0 && M <= T(-1.0)) || (side == 1 && T(1.0) <= M)) {
+    for (int q = 0; q < 4; ++q) out[q] = T(0.0);
+    return;
+  }
+  const double s = side == 0 ? 1.0 : -1.0;
+  const T fm = s * kn * rho * c * (M + s) * (M + s) / 4.0;
+  const T vt = -qn + s * 2.0 * c;
+  const T e2 = (gam - 1.0) * qn + s * 2.0 * c;
+  out[0] = fm;
+  out[1] = fm * (u + nx_ * vt / gam);
+  out[2] = fm * (v + ny_ * vt / gam);
+  out[3] = fm * (e2 * e2 / (2.0 * (gam * gam - 1.0)) + 0.5 * (u * u + v * v - qn * qn));
+}
+
+// ===========================================================================
 // Midpoint split fluxes F^+_{k+1/2}, F^-_{k+1/2} (Secs. 2.3, 2.4, 3.4).
 // Inputs: the eight states Q_{k-3..k+4}, the nodal hatted metrics at k and k+1
 // (their mean gives the eigenvector direction), the midpoint metric (I xi^)_{k+1/2},
@@ -624,11 +711,7 @@ void midpoint_flux(Scheme sc, const Params& pr, const T Qs[8][4], double kx0, do
       else
         to_conservative(Vm, pr.gamma, Qm);
     }
-    T E[4];
-    flux_hat(Qm, pr.gamma, mkx, mky, E);
-    T* out = side == 0 ? Fp : Fm;
-    double sgn = side == 0 ? 1.0 : -1.0;
-    for (int q = 0; q < 4; ++q) out[q] = 0.5 * (E[q] + sgn * lam * Qm[q]);
+    midpoint_split(pr, Qm, mkx, mky, lam, side, side == 0 ? Fp : Fm);
   }
 }
 
@@ -673,14 +756,28 @@ void line_residual(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_
       fm[q * len + k + off] = 0.5 * (E[q] - lam * Qk[q]);
     }
   }
-  // Midpoint split fluxes at k+1/2.
+  // Midpoint split fluxes at k+1/2 (Lax-Friedrichs split).  With another
+  // midpoint splitting (Sec. 7), only the leading f_{i+1/2} of each h, the
+  // term Sec. 7 singles out, takes it: H_{i+1/2} gains D = (F~+ - F+) +
+  // (F~- - F-) at its own midpoint, while the correction terms of the 2-, 4-
+  // and 6-midpoint schemes keep the Lax-Friedrichs values.  (Splitting every
+  // midpoint value would break FSP for those schemes: a lone F+ at another
+  // midpoint is then not linear in the metric.)
+  Params plf = pr;
+  plf.split = 0;
+  std::vector<T> D(pr.split != 0 ? 4 * len : 0);
   for (int k = -4; k < n + 3; ++k) {
     T Qs[8][4];
     for (int m = 0; m < 8; ++m)
       for (int q = 0; q < 4; ++q) Qs[m][q] = Q(k - 3 + m, q);
     T a[4], b[4];
-    midpoint_flux(sc, pr, Qs, kx(k), ky(k), kx(k + 1), ky(k + 1), mkx(k), mky(k), lam, a, b);
+    midpoint_flux(sc, plf, Qs, kx(k), ky(k), kx(k + 1), ky(k + 1), mkx(k), mky(k), lam, a, b);
     for (int q = 0; q < 4; ++q) { Fp[q * len + k + off] = a[q]; Fm[q * len + k + off] = b[q]; }
+    if (pr.split != 0 && k >= -1 && k < n) {
+      T ga[4], gb[4];
+      midpoint_flux(sc, pr, Qs, kx(k), ky(k), kx(k + 1), ky(k + 1), mkx(k), mky(k), lam, ga, gb);
+      for (int q = 0; q < 4; ++q) D[q * len + k + off] = (ga[q] - a[q]) + (gb[q] - b[q]);
+    }
   }
   // H_{i+1/2} = h^+_{i+1/2} + h^-_{i+1/2}; h^- is h^+ mirrored about i+1/2
   // (node i+m <-> i+1-m, midpoint i+1/2+m <-> i+1/2-m).
@@ -692,6 +789,7 @@ void line_residual(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_
       auto fmn = [&](int m) { return fm[q * len + i + 1 - m + off]; };
       auto Fmm = [&](int m) { return Fm[q * len + i - m + off]; };
       H[q * (n + 1) + i + 1] = h_plus<T>(sc, pr.alpha_h, fpn, Fpm) + h_plus<T>(sc, pr.alpha_h, fmn, Fmm);
+      if (pr.split != 0) H[q * (n + 1) + i + 1] = H[q * (n + 1) + i + 1] + D[q * len + i + off];
     }
   for (int k = 0; k < n; ++k)
     for (int q = 0; q < 4; ++q) R[q * n + k] = H[q * (n + 1) + k + 1] - H[q * (n + 1) + k];

@@ -307,3 +307,164 @@ def test_component_variants_capture_sod(orc, vars):
     assert np.all(np.isfinite(U)) and rho.min() > 0 and p.min() > 0
     ex, _, _ = sod_exact(g.x[0], 0.2)
     assert np.mean(np.abs(rho[0] - ex[0])) < 1e-2
+
+
+# ---------------------------------------------------------------------------
+# WENO-Z weights (Sec. 7 names them; reading: alpha_k = C_k (1 + (tau /
+# (eps + IS_k))^2), tau = |IS_0 - IS_2| (r = 3), |IS_0 - IS_1| (r = 2),
+# |IS_0 + 3 IS_1 - 3 IS_2 - IS_3| (r = 4), no mapping)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("r,order", [(3, 5), (4, 7)])
+def test_weno_z_design_order_including_a_critical_point(orc, r, order):
+    """Smooth data with f'(x_k) = 0 at the interpolation node: the Z weights
+    (no mapping) keep the design order."""
+    f = lambda x: np.cos(2.0 * x) + 0.1 * x ** 3  # f'(0) = 0
+    n = 2 * r - 1
+    def err(h, **kw):
+        v = f(h * np.arange(-(r - 1), r))
+        return abs(orc.weno(r, v[:n], **kw) - f(0.5 * h))
+    ez = [err(h, weights="z") for h in (0.2, 0.1, 0.05)]
+    assert math.log2(ez[1] / ez[2]) > order - 0.6, ez
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_weno_z_picks_the_smooth_stencil_at_a_jump(orc, r):
+    """Data with a unit jump after k+1: the interpolated value at k+1/2 stays
+    within 1e-6 of the smooth side's value (the crossing stencils' weights
+    vanish), and uniform data is reproduced."""
+    n = {2: 4, 3: 5, 4: 7}[r]
+    k = {2: 2, 3: 2, 4: 3}[r]
+    v = np.where(np.arange(n) > k + 1, 1.0, 0.0)
+    v = v + 0.01 * np.arange(n)  # a gentle slope on both sides
+    lin = 0.01 * (k + 0.5)
+    assert abs(orc.weno(r, v, weights="z") - lin) < 1e-6
+    assert orc.weno(r, np.full(n, 0.7), weights="z") == pytest.approx(0.7, abs=1e-15)
+
+
+@pytest.mark.parametrize("s,order", [("3-2MP", 3), ("5-1MP", 5), ("7-2MP", 7)])
+def test_weno_z_advection_order(orc, s, order):
+    dtpow = {3: 1.0, 5: 1.25, 7: 1.75}[order]
+    e = [orc.adv1d_run(s, N, dtpow=dtpow, weights="z")[0] for N in (40, 80)]
+    assert math.log2(e[0] / e[1]) > order - 0.5, e
+
+
+@pytest.mark.parametrize("s", ["3-1MP", "5-2MP", "7-4MP"])
+def test_weno_z_preserves_free_stream(orc, s):
+    g, U = W.fsp_problem(40, A=0.2)
+    M = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    assert np.abs(orc.rhs(s, U, M, g.bc, weights="z")).max() < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# midpoint flux splittings (Sec. 7 names Steger-Warming and van Leer for the
+# midpoint flux; the nodal fluxes keep the Lax-Friedrichs split)
+# ---------------------------------------------------------------------------
+
+def _split_pair(orc, Q, k, split):
+    """(F+, F-) of one state Q at the midpoint metric k (all window states
+    equal Q, so the interpolated states are Q itself)."""
+    Qs = np.ascontiguousarray(np.tile(Q, (8, 1)))
+    return orc.midpoint_flux("5-2MP", Qs, k, k, k, 0.0, split=split)
+
+
+def _states(rng, n):
+    for _ in range(n):
+        rho, p = rng.uniform(0.3, 3.0), rng.uniform(0.2, 3.0)
+        c = math.sqrt(1.4 * p / rho)
+        m = rng.uniform(-2.5, 2.5)  # normal Mach numbers across both sonic points
+        th = rng.uniform(0, 2 * math.pi)
+        yield W.conservative(rho, m * c * math.cos(th), m * c * math.sin(th), p).ravel()
+
+
+@pytest.mark.parametrize("split", ["sw", "vl"])
+def test_split_parts_sum_to_the_flux(orc, split):
+    """F+ + F- = E^(Q; k): Steger-Warming by the degree-one homogeneity of
+    E^, van Leer by construction."""
+    rng = np.random.default_rng(12)
+    for Q in _states(rng, 200):
+        k = rng.uniform(-1.5, 1.5, 2)
+        Fp, Fm = _split_pair(orc, Q, k, split)
+        E = orc.flux_hat(Q, 1.4, k[0], k[1])
+        np.testing.assert_allclose(Fp + Fm, E, rtol=1e-12, atol=1e-12 * np.abs(E).max())
+
+
+def test_steger_warming_matches_the_one_dimensional_textbook_form(orc):
+    """Along k = (kx, 0) with v = 0 the split is the classical 1-D
+    Steger-Warming flux (scaled by |kx|): f+- = rho/(2 gamma) [2(gamma-1) l2 +
+    l1 + l3, 2(gamma-1) l2 u + l1 (u-c) + l3 (u+c), (gamma-1) l2 u^2 +
+    l1 (u-c)^2/2 + l3 (u+c)^2/2 + (3-gamma)(l1 + l3) c^2 / (2(gamma-1))] with
+    l = (u-c, u, u+c) split into positive and negative parts."""
+    g = 1.4
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        rho, p, u = rng.uniform(0.3, 3), rng.uniform(0.2, 3), rng.uniform(-3, 3)
+        kx = rng.uniform(0.2, 2.0)
+        c = math.sqrt(g * p / rho)
+        Q = W.conservative(rho, u, 0.0, p).ravel()
+        Fp, Fm = _split_pair(orc, Q, np.array([kx, 0.0]), "sw")
+        for F, sgn in ((Fp, 1), (Fm, -1)):
+            l1, l2, l3 = [0.5 * (x + sgn * abs(x)) for x in (u - c, u, u + c)]
+            f = rho / (2 * g) * np.array([
+                2 * (g - 1) * l2 + l1 + l3,
+                2 * (g - 1) * l2 * u + l1 * (u - c) + l3 * (u + c),
+                0.0,
+                (g - 1) * l2 * u * u + 0.5 * l1 * (u - c) ** 2 + 0.5 * l3 * (u + c) ** 2
+                + (3 - g) * (l1 + l3) * c * c / (2 * (g - 1))])
+            np.testing.assert_allclose(F, kx * f, rtol=1e-12, atol=1e-13)
+
+
+def test_van_leer_limits_and_smoothness(orc):
+    """van Leer along n: F+ = E^ for M >= 1 and 0 for M <= -1, continuous at
+    M = +-1, with a double root at M = -1 (F+ = O((M+1)^2))."""
+    g = 1.4
+    rho, p = 1.3, 0.9
+    c = math.sqrt(g * p / rho)
+    k = np.array([0.6, 0.8])
+    def fp(M):
+        Q = W.conservative(rho, M * c * 0.6, M * c * 0.8, p).ravel()
+        return _split_pair(orc, Q, k, "vl")[0], Q
+    for M in (1.0, 1.5):
+        F, Q = fp(M)
+        np.testing.assert_allclose(F, orc.flux_hat(Q, g, k[0], k[1]), rtol=1e-13)
+    F, Q = fp(1.0 - 1e-9)
+    np.testing.assert_allclose(F, orc.flux_hat(Q, g, k[0], k[1]), rtol=1e-7)
+    assert np.abs(fp(-1.0)[0]).max() == 0.0
+    a, b = np.abs(fp(-1 + 1e-3)[0]).max(), np.abs(fp(-1 + 2e-3)[0]).max()
+    assert 3.5 < b / a < 4.5
+
+
+@pytest.mark.parametrize("split", ["sw", "vl"])
+@pytest.mark.parametrize("s", ["3-1MP", "5-2MP", "7-6MP"])
+def test_splittings_preserve_free_stream(orc, s, split):
+    """Sec. 7's claim: another midpoint splitting leaves FSP intact."""
+    g, U = W.fsp_problem(40, A=0.2)
+    M = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    assert np.abs(orc.rhs(s, U, M, g.bc, split=split)).max() < 1e-11
+
+
+@pytest.mark.parametrize("split", ["sw", "vl"])
+def test_splittings_keep_design_order_and_capture_sod(orc, split):
+    s = "5-2MP"
+    errs = []
+    for n in (48, 96):
+        g = W.sinusoidal_grid(n, n, amp=0.03)
+        U = W.vortex_state(g.x, g.y)
+        M = orc.metrics(s, g.x, g.y, g.bc, g.period)
+        d = orc.rhs(s, U, M, g.bc, split=split)
+        ex = _vortex_exact_rate(g)
+        r = np.hypot(g.x - 5, g.y - 5)
+        errs.append(np.sqrt(np.mean((d - ex)[:, r <= 4] ** 2)))
+    assert np.log2(errs[0] / errs[1]) > 4.5, errs
+    g = W.strip_grid(200)
+    U = W.sod_state(g)
+    M = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    t = 0.0
+    while t < 0.2 - 1e-14:
+        dt = min(orc.cfl_dt(U, M, 0.5), 0.2 - t)
+        U = orc.rk3_step(s, U, M, dt, g.bc, split=split)
+        t += dt
+    rho, u, v, p = W.primitive(U)
+    assert np.all(np.isfinite(U)) and rho.min() > 0 and p.min() > 0
+    ex, _, _ = sod_exact(g.x[0], 0.2)
+    assert np.mean(np.abs(rho[0] - ex[0])) < 1e-2

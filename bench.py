@@ -84,7 +84,7 @@ def flops_per_cell_dir(n, scheme="5-2MP", vars="characteristic"):
     return A + B / n
 
 
-def cpu_baseline(g, U, scheme, cfl, vars="characteristic", alpha_h=1.0):
+def cpu_baseline(g, U, scheme, cfl, vars="characteristic", alpha_h=1.0, weights="js", split="lf"):
     """The oracle, as it stands, timed on the host cores: one TVD-RK3 step of
     the full workload (3 rhs evaluations)."""
     import oracle
@@ -92,7 +92,7 @@ def cpu_baseline(g, U, scheme, cfl, vars="characteristic", alpha_h=1.0):
     M = oracle.metrics(scheme, g.x, g.y, g.bc, g.period, alpha_h=alpha_h)
     dt = oracle.cfl_dt(U, M, cfl)
     t0 = time.perf_counter()
-    oracle.rk3_step(scheme, U, M, dt, g.bc, vars=vars, alpha_h=alpha_h)
+    oracle.rk3_step(scheme, U, M, dt, g.bc, vars=vars, alpha_h=alpha_h, weights=weights, split=split)
     t = time.perf_counter() - t0
     n = g.x.size
     return {"value": 3 * n / t, "unit": "cell-updates/s", "cores": oracle.get_threads(), "kind": "oracle",
@@ -220,6 +220,8 @@ def main():
     ap.add_argument("--vars", default="characteristic", choices=("characteristic", "conservative", "primitive"),
                     help="variables the midpoint states are interpolated in (Sec. 2.4)")
     ap.add_argument("--alpha-h", type=float, default=1.0, help="free parameter of the one-midpoint schemes")
+    ap.add_argument("--weights", default="js", choices=("js", "z"), help="Jiang-Shu (mapped) or WENO-Z weights")
+    ap.add_argument("--split", default="lf", choices=("lf", "sw", "vl"), help="split of the leading midpoint flux")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-block leg")
     ap.add_argument("--no-rhs", action="store_true", help="skip the bare-rhs timing")
@@ -246,7 +248,7 @@ def main():
 
     n = args.n
     g, U0 = W.riemann_problem(n, A=0.2, seed=2048)
-    params = wenoiu.make_params(vars=args.vars, alpha_h=args.alpha_h)
+    params = wenoiu.make_params(vars=args.vars, alpha_h=args.alpha_h, weights=args.weights, split=args.split)
     sol = wenoiu.Solver(g.x, g.y, args.scheme, g.bc, g.period, params=params)
     U = torch.as_tensor(U0).cuda().contiguous()
     torch.cuda.synchronize()
@@ -327,8 +329,11 @@ def main():
         "config": {"workload": f"2-D Riemann problem, randomized {n}x{n} grid on [0,1]^2 (A=0.2, seed 2048), "
                                f"WENOIU{args.scheme}, transmissive, TVD-RK3 CFL {args.cfl}"
                                + ("" if args.vars == "characteristic" else f", {args.vars} variables")
-                               + ("" if args.alpha_h == 1.0 else f", alpha {args.alpha_h}"),
-                   "n": n, "scheme": args.scheme, "cfl": args.cfl, "vars": args.vars, "alpha_h": args.alpha_h},
+                               + ("" if args.alpha_h == 1.0 else f", alpha {args.alpha_h}")
+                               + ("" if args.weights == "js" else ", WENO-Z weights")
+                               + ("" if args.split == "lf" else f", {args.split} midpoint split"),
+                   "n": n, "scheme": args.scheme, "cfl": args.cfl, "vars": args.vars, "alpha_h": args.alpha_h,
+                   "weights": args.weights, "split": args.split},
         "roofline": roofline,
         "extra": {
             "rhs_ms": rhs_ms,
@@ -346,7 +351,8 @@ def main():
         torch.cuda.empty_cache()
         out["extra"]["adjoint"] = adjoint_leg()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(g, U0, args.scheme, args.cfl, args.vars, args.alpha_h)
+        out["cpu_baseline"] = cpu_baseline(g, U0, args.scheme, args.cfl, args.vars, args.alpha_h, args.weights,
+                                           args.split)
     print(json.dumps(out), flush=True)
 
 

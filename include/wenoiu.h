@@ -86,6 +86,20 @@ typedef struct {
  * reference node's values, so a uniform state is reproduced exactly. */
 enum { WIU_VARS_CHARACTERISTIC = 0, WIU_VARS_CONSERVATIVE = 1, WIU_VARS_PRIMITIVE = 2 };
 
+/* Nonlinear weights of the interpolation: Jiang-Shu (Eqs. 3.12-3.13, with the
+ * mapping when ppm = 1; the paper's), or WENO-Z, which Sec. 7 names as a
+ * possible alternative: alpha_k = C_k (1 + (tau / (eps + IS_k))^2) with
+ * tau = |IS_0 - IS_1|, |IS_0 - IS_2|, |IS_0 + 3 IS_1 - 3 IS_2 - IS_3| for
+ * r = 2, 3, 4, no mapping. */
+enum { WIU_WEIGHTS_JS = 0, WIU_WEIGHTS_Z = 1 };
+
+/* Split of the leading midpoint flux f_{j+1/2} of each h (Sec. 7 singles it
+ * out and names Steger-Warming and van Leer): Lax-Friedrichs with the line
+ * eigenvalue (the paper's), Steger-Warming or van Leer along the midpoint
+ * metric.  The correction terms of the 2-, 4- and 6-midpoint schemes and
+ * the nodal fluxes keep the Lax-Friedrichs split, so FSP is kept. */
+enum { WIU_SPLIT_LF = 0, WIU_SPLIT_SW = 1, WIU_SPLIT_VL = 2 };
+
 typedef struct {
   double gamma;    /* ratio of specific heats, 1.4 */
   double alpha_lf; /* Lax-Friedrichs factor alpha, 1.1 (Sec. 2.3: 1.1-1.2) */
@@ -98,6 +112,8 @@ typedef struct {
                       only value the other schemes accept.  The metrics depend on it
                       (the central operator Eq. 2.7 derives from the scheme), so
                       wiu_metrics takes the same parameters. */
+  int weights;     /* WIU_WEIGHTS_* */
+  int split;       /* WIU_SPLIT_* */
 } wiu_params;
 
 /* Bytes of the metric array M for this grid (planes + tag). */
@@ -161,7 +177,9 @@ int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double*
 /* ---- Adjoints (metrics held fixed) ------------------------------------------
  * Reverse-mode derivatives of the residual and of one RK3 step with respect
  * to the state, for gradients through time integration.  Third- and
- * fifth-order schemes only (WIU_EINVAL for the seventh-order ones).  Non-smooth points:
+ * fifth-order schemes with the paper's configuration only (characteristic
+ * variables, alpha_h = 1, Jiang-Shu weights, Lax-Friedrichs split;
+ * WIU_EINVAL otherwise).  Non-smooth points:
  * the line eigenvalue's maximum passes its adjoint to the first maximal node
  * of the line; |U^| has derivative sign(U^) with sign(0) = 0.  The result is
  * deterministic (no floating-point atomics). */

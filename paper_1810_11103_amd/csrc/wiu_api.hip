@@ -99,7 +99,9 @@ bool alpha_h_ok(int scheme, double a) {
 
 bool params_ok(const wiu_params* p) {
   return p && p->gamma > 1.0 && p->alpha_lf > 0.0 && p->eps >= 0.0 && (p->ppm == 0 || p->ppm == 1) &&
-         p->vars >= WIU_VARS_CHARACTERISTIC && p->vars <= WIU_VARS_PRIMITIVE;
+         p->vars >= WIU_VARS_CHARACTERISTIC && p->vars <= WIU_VARS_PRIMITIVE &&
+         (p->weights == WIU_WEIGHTS_JS || p->weights == WIU_WEIGHTS_Z) && p->split >= WIU_SPLIT_LF &&
+         p->split <= WIU_SPLIT_VL;
 }
 
 bool scheme_ok(int s) { return s >= 0 && s <= 7; }
@@ -110,7 +112,8 @@ bool options_ok(int s, const wiu_params* p) { return scheme_ok(s) && params_ok(p
 // The adjoint covers the third- and fifth-order schemes with the paper's
 // configuration (characteristic variables, alpha_h = 1).
 bool adjoint_ok(int s, const wiu_params* p) {
-  return s >= 0 && s <= 3 && params_ok(p) && p->vars == WIU_VARS_CHARACTERISTIC && p->alpha_h == 1.0;
+  return s >= 0 && s <= 3 && params_ok(p) && p->vars == WIU_VARS_CHARACTERISTIC && p->alpha_h == 1.0 &&
+         p->weights == WIU_WEIGHTS_JS && p->split == WIU_SPLIT_LF;
 }
 
 Dims dims(const wiu_grid* g) {
@@ -223,7 +226,7 @@ int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U
   if (e != hipSuccess) return WIU_EHIP;
   a.d = d; a.U = U; a.M = M;
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
-  a.vars = p->vars; a.ah = p->alpha_h;
+  a.vars = p->vars; a.ah = p->alpha_h; a.weights = p->weights; a.split = p->split;
   a.mode = mode == 2 ? 3 : 0; a.Rxi = w.rxi; a.out = out; a.U0 = U0; a.dt = dt; a.ca = ca; a.cb = cb;
   a.status = w.status;
   a.nlam_xi = nullptr; a.nlam_eta = nullptr;

@@ -76,6 +76,7 @@ BatchArgs base_args(const wiu_plan* p) {
   a.stage = 0;
   a.gamma = p->params.gamma; a.alpha = p->params.alpha_lf; a.eps = p->params.eps; a.ppm = p->params.ppm;
   a.vars = p->params.vars; a.ah = p->params.alpha_h;
+  a.weights = p->params.weights; a.split = p->params.split;
   a.status = p->d_status;
   a.U_all = p->U_all;
   a.M_all = p->M_all;
@@ -119,6 +120,7 @@ int wiu_batched_plan(const wiu_block* blocks, int nblocks, int scheme, const wiu
   if (!(params->gamma > 1.0) || !(params->alpha_lf > 0.0) || !(params->eps >= 0.0)) return WIU_EINVAL;
   if (params->ppm != 0 && params->ppm != 1) return WIU_EINVAL;
   if (params->vars < WIU_VARS_CHARACTERISTIC || params->vars > WIU_VARS_PRIMITIVE) return WIU_EINVAL;
+  if (params->weights < 0 || params->weights > 1 || params->split < 0 || params->split > 2) return WIU_EINVAL;
   if (!(params->alpha_h > 0.0) || !(params->alpha_h < 1.0e300)) return WIU_EINVAL;
   if (params->alpha_h != 1.0 && scheme != WIU_3_1MP && scheme != WIU_5_1MP && scheme != WIU_7_1MP) return WIU_EINVAL;
   if (xi_variant < 0 || xi_variant >= wiu_tuning_variants(0)) return WIU_EINVAL;

@@ -30,8 +30,8 @@ WIU_DEV double* stage_dst(const BatchArgs& b, const BlockDev& B, int st) {
 }
 
 template <int SC, int DIR, int NA, int NB, bool OPT>
-__global__ void __launch_bounds__(NA * NB, sweep_waves<SC>()) batched_sweep_kernel(BatchArgs b) {
-  __shared__ SweepLds<SC, DIR, NA, NB> lds;
+__global__ void __launch_bounds__(NA * NB, (sweep_waves<SC, OPT>())) batched_sweep_kernel(BatchArgs b) {
+  __shared__ SweepLds<SC, DIR, NA, NB, OPT> lds;
   {
     const int4 tl = uniform_tile(b);
     const BlockDev& B = b.blocks[tl.x];
@@ -47,6 +47,7 @@ __global__ void __launch_bounds__(NA * NB, sweep_waves<SC>()) batched_sweep_kern
     unsigned long long* nlam = (DIR == 1 && st < 2) ? b.lam + ufirst(st == 0 ? B.oLam2 : B.oLam) : nullptr;
     s.nlam_xi = nlam; s.nlam_eta = nlam ? nlam + s.d.ny : nullptr;
     s.gamma = b.gamma; s.alpha = b.alpha; s.eps = b.eps; s.ppm = b.ppm; s.vars = b.vars; s.ah = b.ah;
+    s.weights = b.weights; s.split = b.split;
     s.Rxi = b.ws + ufirst(B.oRxi); s.U0 = b.U_all + ufirst(B.oU); s.dt = b.ws + ufirst(B.oDt);
     s.status = b.status;
     s.U = stage_src(b, B, st);
@@ -107,7 +108,8 @@ hipError_t launch_batched_sweep_vo(int variant, const BatchArgs& a, hipStream_t 
 // the options kernels only when an option is in use
 template <int SC, int DIR>
 hipError_t launch_batched_sweep_v(int variant, const BatchArgs& a, hipStream_t st) {
-  if (a.vars != 0 || a.ah != 1.0) return launch_batched_sweep_vo<SC, DIR, true>(variant, a, st);
+  if (a.vars != 0 || a.ah != 1.0 || a.weights != 0 || a.split != 0)
+    return launch_batched_sweep_vo<SC, DIR, true>(variant, a, st);
   return launch_batched_sweep_vo<SC, DIR, false>(variant, a, st);
 }
 

@@ -201,6 +201,10 @@ WIU_DEV double map2(double w, double C, double Klo, double Khi) {
 // reciprocal (w_k = C_k prod_{l != k} D_l / sum_m C_m prod_{l != m} D_l; the
 // common factor 1/16 of the C_k cancels), mapping Eq. 3.23 and
 // re-normalisation.
+// ZOK (compile time) admits ppm = 2, which selects WENO-Z weights (Sec. 7 names
+// them; reading): alpha_k = C_k (1 + (tau / (eps + IS_k))^2) with the global
+// indicator tau, no mapping, the q_k = tau / (eps + IS_k) from one reciprocal.
+template <bool ZOK = false>
 WIU_DEV double weno5(double a, double b, double d, double e, double eps, int ppm) {
   const double p0 = 0.375 * a - 1.25 * b;
   const double p1 = 0.375 * d - 0.125 * b;
@@ -210,6 +214,15 @@ WIU_DEV double weno5(double a, double b, double d, double e, double eps, int ppm
   double D0 = fma(13.0 / 12.0, t0 * t0, fma(u0, u0, eps));
   double D1 = fma(13.0 / 12.0, t1 * t1, fma(u1, u1, eps));
   double D2 = fma(13.0 / 12.0, t2 * t2, fma(u2, u2, eps));
+  if constexpr (ZOK) {
+    if (ppm == 2) {
+      // tau = |IS_0 - IS_2|; q_k = tau / (eps + IS_k) from one reciprocal
+      const double P01 = D0 * D1, R = rcp(P01 * D2), tau = fabs(D0 - D2);
+      const double q0 = tau * (D1 * D2 * R), q1 = tau * (D0 * D2 * R), q2 = tau * (P01 * R);
+      const double a0 = fma(q0, q0, 1.0), a1 = 10.0 * fma(q1, q1, 1.0), a2 = 5.0 * fma(q2, q2, 1.0);
+      return (a0 * p0 + a1 * p1 + a2 * p2) * rcp(a0 + a1 + a2);
+    }
+  }
   D0 *= D0; D1 *= D1; D2 *= D2;
   const double a0 = D1 * D2, a1 = 10.0 * (D0 * D2), a2 = 5.0 * (D0 * D1);
   const double r = rcp(a0 + a1 + a2);
@@ -226,6 +239,7 @@ WIU_DEV double weno5(double a, double b, double d, double e, double eps, int ppm
 // = (a, b, 0, d).  Candidates (-v_{k-1} + 3 v_k)/2 and (v_k + v_{k+1})/2,
 // C = (1, 3)/4, with the three-point indicators IS_0, IS_1 of Eq. 3.22 in
 // place of Eq. 3.14 (Sec. 5.1) and the mapping 3.15.
+template <bool ZOK = false>
 WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
   const double p0 = -0.5 * b;
   const double p1 = 0.5 * d;
@@ -234,6 +248,14 @@ WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
   const double u0 = fma(-2.0, b, 0.5 * a), u1 = 0.5 * (b - d);
   double D0 = fma(13.0 / 12.0, t0 * t0, fma(u0, u0, eps));
   double D1 = fma(13.0 / 12.0, t1 * t1, fma(u1, u1, eps));
+  if constexpr (ZOK) {
+    if (ppm == 2) {  // WENO-Z, tau = |IS_0 - IS_1|
+      const double R = rcp(D0 * D1), tau = fabs(D0 - D1);
+      const double q0 = tau * (D1 * R), q1 = tau * (D0 * R);
+      const double a0 = fma(q0, q0, 1.0), a1 = 3.0 * fma(q1, q1, 1.0);
+      return (a0 * p0 + a1 * p1) * rcp(a0 + a1);
+    }
+  }
   D0 *= D0; D1 *= D1;
   const double a0 = D1, a1 = 3.0 * D0;
   const double r = rcp(a0 + a1);
@@ -272,6 +294,7 @@ WIU_DEV double map4(double w, double C, double Klo, double Khi) {
 // where c1 + c3/4, c2 and c3 are fixed differences of the stencil values.
 // Weights as in weno5 (products of the squared denominators, one
 // reciprocal), mapping map4, re-normalisation.
+template <bool ZOK = false>
 WIU_DEV double weno7(double a, double b, double c, double e, double f, double g, double eps, int ppm) {
   const double p0 = (-5.0 * a + 21.0 * b - 35.0 * c) * 0.0625;
   const double p1 = (b - 5.0 * c + 5.0 * e) * 0.0625;
@@ -287,6 +310,17 @@ WIU_DEV double weno7(double a, double b, double c, double e, double f, double g,
   double D2 = is(fma(-1.0 / 3.0, c, fma(-1.0 / 6.0, f, e)), ce, (f - c - 3.0 * e) * (1.0 / 6.0));
   double D3 = is(fma(3.0, e, fma(1.0 / 3.0, g, -1.5 * f)), fma(2.0, f, fma(-2.5, e, -0.5 * g)),
                  (3.0 * (e - f) + g) * (1.0 / 6.0));
+  if constexpr (ZOK) {
+    if (ppm == 2) {  // WENO-Z, tau = |IS_0 + 3 IS_1 - 3 IS_2 - IS_3|
+      const double P01 = D0 * D1, P23 = D2 * D3, R = rcp(P01 * P23);
+      const double tau = fabs(fma(3.0, D1 - D2, D0 - D3));
+      const double q0 = tau * (D1 * P23 * R), q1 = tau * (D0 * P23 * R);
+      const double q2 = tau * (D3 * P01 * R), q3 = tau * (D2 * P01 * R);
+      const double a0 = fma(q0, q0, 1.0), a1 = 21.0 * fma(q1, q1, 1.0);
+      const double a2 = 35.0 * fma(q2, q2, 1.0), a3 = 7.0 * fma(q3, q3, 1.0);
+      return (a0 * p0 + a1 * p1 + a2 * p2 + a3 * p3) * rcp((a0 + a1) + (a2 + a3));
+    }
+  }
   D0 *= D0; D1 *= D1; D2 *= D2; D3 *= D3;
   const double P01 = D0 * D1, P23 = D2 * D3;
   const double a0 = (D1 * P23), a1 = 21.0 * (D0 * P23), a2 = 35.0 * (D3 * P01), a3 = 7.0 * (D2 * P01);
@@ -299,6 +333,63 @@ WIU_DEV double weno7(double a, double b, double c, double e, double f, double g,
     w3 = map4(w3, 7.0 / 64.0, WIU_M4L3, WIU_M4H3);
   }
   return (w0 * p0 + w1 * p1 + w2 * p2 + w3 * p3) * rcp((w0 + w1) + (w2 + w3));
+}
+
+// Steger-Warming (split 1) or van Leer (split 2) split of a midpoint flux at
+// the interpolated state Q with the midpoint metric (mx, my); side 0 gives
+// F^+, side 1 F^- (Sec. 7 names both for the midpoint flux; closed forms
+// along n = k/|k|, scaled by |k|):
+//   Steger-Warming: F = |k| rho/(2 gamma) [2(g-1) l2 + l1 + l3,
+//     2(g-1) l2 u + l1 (u - c nx) + l3 (u + c nx), (same for v, ny),
+//     (g-1) l2 q^2 + l1 |u - c n|^2/2 + l3 |u + c n|^2/2 + (3-g)(l1 + l3) c^2/(2(g-1))]
+//     with l = (qn - c, qn, qn + c) reduced to its positive / negative parts;
+//   van Leer: F = E^ / 0 beyond |M| = 1 (M = qn/c), else
+//     +-|k| rho c (M +- 1)^2/4 [1, u + nx (-qn +- 2c)/g, v + ny (...)/g,
+//     ((g-1) qn +- 2c)^2/(2(g^2-1)) + (q^2 - qn^2)/2].
+WIU_DEV void mid_split_alt(int split, const double Q[4], double mx, double my, int side, double gam, double F[4]) {
+  const double kn2 = mx * mx + my * my;
+  const double rk = rsqrt_(kn2), kn = kn2 * rk;
+  const double nx_ = mx * rk, ny_ = my * rk;
+  const double ri = rcp(Q[0]);
+  const double u = Q[1] * ri, v = Q[2] * ri;
+  const double q2 = u * u + v * v;
+  const double gm1 = gam - 1.0;
+  const double p = gm1 * (Q[3] - 0.5 * Q[0] * q2);
+  const double c2 = gam * p * ri;
+  const double rc = rsqrt_(c2), c = c2 * rc;
+  const double qn = u * nx_ + v * ny_;
+  const double sg = side == 0 ? 1.0 : -1.0;
+  if (split == 1) {
+    auto part = [&](double l) { return 0.5 * fma(sg, fabs(l), l); };
+    const double l1 = part(qn - c), l2 = part(qn), l3 = part(qn + c);
+    const double f = kn * Q[0] * rcp(2.0 * gam);
+    const double uc = c * nx_, vc = c * ny_;
+    const double um = u - uc, up = u + uc, vm = v - vc, vp = v + vc;
+    F[0] = f * (2.0 * gm1 * l2 + l1 + l3);
+    F[1] = f * (2.0 * gm1 * l2 * u + l1 * um + l3 * up);
+    F[2] = f * (2.0 * gm1 * l2 * v + l1 * vm + l3 * vp);
+    F[3] = f * (gm1 * l2 * q2 + 0.5 * l1 * (um * um + vm * vm) + 0.5 * l3 * (up * up + vp * vp) +
+                (3.0 - gam) * (l1 + l3) * c2 * rcp(2.0 * gm1));
+    return;
+  }
+  const double M = qn * rc;
+  if (sg * M >= 1.0) {
+    const double U = mx * u + my * v;
+    F[0] = Q[0] * U; F[1] = Q[1] * U + mx * p; F[2] = Q[2] * U + my * p; F[3] = (Q[3] + p) * U;
+    return;
+  }
+  if (sg * M <= -1.0) {
+    F[0] = F[1] = F[2] = F[3] = 0.0;
+    return;
+  }
+  const double mp = M + sg;
+  const double fm = sg * kn * Q[0] * c * mp * mp * 0.25;
+  const double rg = rcp(gam);
+  const double vt = fma(sg * 2.0, c, -qn), e2 = fma(sg * 2.0, c, gm1 * qn);
+  F[0] = fm;
+  F[1] = fm * fma(nx_ * vt, rg, u);
+  F[2] = fm * fma(ny_ * vt, rg, v);
+  F[3] = fm * (e2 * e2 * rcp(2.0 * (gam * gam - 1.0)) + 0.5 * (q2 - qn * qn));
 }
 
 // ---------------------------------------------------------------------------
@@ -314,9 +405,9 @@ WIU_DEV double weno7(double a, double b, double c, double e, double f, double g,
 //   l_1 = (A + B)/2, l_2 = e_rho - A, l_4 = (A - B)/2 applied to dQ, with
 //   A = b2 drho - b1 (u dm + v dn - de), B = (qn drho - nx dm - ny dn)/c.
 // ---------------------------------------------------------------------------
-template <bool FIFTH, class QF>
+template <bool FIFTH, bool ZOK = false, class QF>
 WIU_DEV void side_flux(QF q, int side, double nx_, double ny_, double mx, double my, double lam, double gam,
-                       double eps, int ppm, double F[4]) {
+                       double eps, int ppm, double F[4], int split = 0, double* Dacc = nullptr) {
   const double Qr[4] = {q(2 + side, 0), q(2 + side, 1), q(2 + side, 2), q(2 + side, 3)};
   const double gm1 = gam - 1.0;
   const double rr = rcp(Qr[0]);
@@ -351,8 +442,8 @@ WIU_DEV void side_flux(QF q, int side, double nx_, double ny_, double mx, double
   double W[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if constexpr (FIFTH) W[k] = weno5(w[k][0], w[k][1], w[k][3], w[k][4], eps, ppm);
-    else W[k] = weno3(w[k][0], w[k][1], w[k][3], eps, ppm);
+    if constexpr (FIFTH) W[k] = weno5<ZOK>(w[k][0], w[k][1], w[k][3], w[k][4], eps, ppm);
+    else W[k] = weno3<ZOK>(w[k][0], w[k][1], w[k][3], eps, ppm);
   }
   // back to conservative variables: Q = Q_ref + R W
   const double s03 = W[0] + W[3], d30 = W[3] - W[0];
@@ -371,6 +462,14 @@ WIU_DEV void side_flux(QF q, int side, double nx_, double ny_, double mx, double
   F[1] = 0.5 * (r1 * Ul + mx * pl + sl * r1);
   F[2] = 0.5 * (r2 * Ul + my * pl + sl * r2);
   F[3] = 0.5 * ((r3 + pl) * Ul + sl * r3);
+  if (split != 0) {
+    // another split for the leading midpoint flux: accumulate its difference
+    const double Qm[4] = {r0, r1, r2, r3};
+    double G[4];
+    mid_split_alt(split, Qm, mx, my, side, gam, G);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Dacc[c] += G[c] - F[c];
+  }
 }
 
 // The same for the seventh-order schemes: q(m, c), m = 0..7, holds the states
@@ -380,9 +479,9 @@ WIU_DEV void side_flux(QF q, int side, double nx_, double ny_, double mx, double
 // fields 0 and 3 (which share A and B) and then fields 1 and 2, each pass
 // re-reading the states from LDS: twelve projected values are live at a time
 // instead of twenty-four (compiler barriers keep the passes apart).
-template <class QF>
+template <bool ZOK = false, class QF>
 WIU_DEV void side_flux7(QF q, int side, double nx_, double ny_, double mx, double my, double lam, double gam,
-                        double eps, int ppm, double F[4]) {
+                        double eps, int ppm, double F[4], int split = 0, double* Dacc = nullptr) {
   const double Qr[4] = {q(3 + side, 0), q(3 + side, 1), q(3 + side, 2), q(3 + side, 3)};
   const double gm1 = gam - 1.0;
   const double rr = rcp(Qr[0]);
@@ -413,9 +512,9 @@ WIU_DEV void side_flux7(QF q, int side, double nx_, double ny_, double mx, doubl
       w0[s] = 0.5 * (A + B);
       w3[s] = 0.5 * (A - B);
     }
-    W[0] = weno7(w0[0], w0[1], w0[2], w0[4], w0[5], w0[6], eps, ppm);
+    W[0] = weno7<ZOK>(w0[0], w0[1], w0[2], w0[4], w0[5], w0[6], eps, ppm);
     asm volatile("" ::: "memory");
-    W[3] = weno7(w3[0], w3[1], w3[2], w3[4], w3[5], w3[6], eps, ppm);
+    W[3] = weno7<ZOK>(w3[0], w3[1], w3[2], w3[4], w3[5], w3[6], eps, ppm);
   }
   asm volatile("" ::: "memory");
   {
@@ -429,9 +528,9 @@ WIU_DEV void side_flux7(QF q, int side, double nx_, double ny_, double mx, doubl
       w1[s] = dr - A;
       w2[s] = nx_ * dn - ny_ * dm - qt * dr;
     }
-    W[1] = weno7(w1[0], w1[1], w1[2], w1[4], w1[5], w1[6], eps, ppm);
+    W[1] = weno7<ZOK>(w1[0], w1[1], w1[2], w1[4], w1[5], w1[6], eps, ppm);
     asm volatile("" ::: "memory");
-    W[2] = weno7(w2[0], w2[1], w2[2], w2[4], w2[5], w2[6], eps, ppm);
+    W[2] = weno7<ZOK>(w2[0], w2[1], w2[2], w2[4], w2[5], w2[6], eps, ppm);
   }
   const double s03 = W[0] + W[3], d30 = W[3] - W[0];
   const double sum = s03 + W[1];
@@ -448,6 +547,14 @@ WIU_DEV void side_flux7(QF q, int side, double nx_, double ny_, double mx, doubl
   F[1] = 0.5 * (r1 * Ul + mx * pl + sl * r1);
   F[2] = 0.5 * (r2 * Ul + my * pl + sl * r2);
   F[3] = 0.5 * ((r3 + pl) * Ul + sl * r3);
+  if (split != 0) {
+    // another split for the leading midpoint flux: accumulate its difference
+    const double Qm[4] = {r0, r1, r2, r3};
+    double G[4];
+    mid_split_alt(split, Qm, mx, my, side, gam, G);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Dacc[c] += G[c] - F[c];
+  }
 }
 
 // Midpoint flux with the midpoint state interpolated component by component
@@ -458,9 +565,9 @@ WIU_DEV void side_flux7(QF q, int side, double nx_, double ny_, double mx, doubl
 // as its deviation from the reference node's value, which is then added
 // back.  Primitive values are formed from the staged conservative states
 // with one reciprocal density per stencil point.
-template <int R, class QF>
+template <int R, bool ZOK = false, class QF>
 WIU_DEV void side_flux_comp(QF q, int side, int vars, double mx, double my, double lam, double gam, double eps,
-                            int ppm, double F[4]) {
+                            int ppm, double F[4], int split = 0, double* Dacc = nullptr) {
   constexpr int QL = R == 4 ? 3 : 2;        // reference position in the window (side 0)
   constexpr int NS = R == 2 ? 4 : 2 * R - 1;  // stencil positions s = 0..NS-1, reference at s = QL
   const double gm1 = gam - 1.0;
@@ -486,9 +593,9 @@ WIU_DEV void side_flux_comp(QF q, int side, int vars, double mx, double my, doub
 #pragma unroll
     for (int s = 0; s < NS; ++s) v[s] = s == QL ? 0.0 : var(s, c) - vr;
     double w;
-    if constexpr (R == 4) w = weno7(v[0], v[1], v[2], v[4], v[5], v[6], eps, ppm);
-    else if constexpr (R == 3) w = weno5(v[0], v[1], v[3], v[4], eps, ppm);
-    else w = weno3(v[0], v[1], v[3], eps, ppm);
+    if constexpr (R == 4) w = weno7<ZOK>(v[0], v[1], v[2], v[4], v[5], v[6], eps, ppm);
+    else if constexpr (R == 3) w = weno5<ZOK>(v[0], v[1], v[3], v[4], eps, ppm);
+    else w = weno3<ZOK>(v[0], v[1], v[3], eps, ppm);
     V[c] = vr + w;
   }
   double r0, r1, r2, r3;
@@ -507,6 +614,14 @@ WIU_DEV void side_flux_comp(QF q, int side, int vars, double mx, double my, doub
   F[1] = 0.5 * (r1 * Ul + mx * pl + sl * r1);
   F[2] = 0.5 * (r2 * Ul + my * pl + sl * r2);
   F[3] = 0.5 * ((r3 + pl) * Ul + sl * r3);
+  if (split != 0) {
+    // another split for the leading midpoint flux: accumulate its difference
+    const double Qm[4] = {r0, r1, r2, r3};
+    double G[4];
+    mid_split_alt(split, Qm, mx, my, side, gam, G);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Dacc[c] += G[c] - F[c];
+  }
 }
 
 // Nodal contravariant flux E^ = (rho U, m U + kx p, n U + ky p, (e + p) U),

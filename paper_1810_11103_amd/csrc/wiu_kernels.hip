@@ -263,8 +263,8 @@ __global__ void lambda_out_kernel(Dims d, double alpha, const unsigned long long
 // Launched for 4 waves per SIMD (at most 128 VGPRs).
 // ===========================================================================
 template <int SC, int DIR, int NA, int NB, bool OPT>
-__global__ void __launch_bounds__(NA * NB, sweep_waves<SC>()) sweep_kernel(SweepArgs s) {
-  __shared__ SweepLds<SC, DIR, NA, NB> lds;
+__global__ void __launch_bounds__(NA * NB, (sweep_waves<SC, OPT>())) sweep_kernel(SweepArgs s) {
+  __shared__ SweepLds<SC, DIR, NA, NB, OPT> lds;
   // logical tile in XCD-aware order
   const int total = gridDim.x * gridDim.y;
   const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, total);
@@ -309,7 +309,7 @@ hipError_t launch_sweep_vo(int variant, const SweepArgs& a, hipStream_t st) {
 // the options kernels only when an option is in use
 template <int SC, int DIR>
 hipError_t launch_sweep_v(int variant, const SweepArgs& a, hipStream_t st) {
-  if (a.vars != 0 || a.ah != 1.0) return launch_sweep_vo<SC, DIR, true>(variant, a, st);
+  if (a.vars != 0 || a.ah != 1.0 || a.weights != 0 || a.split != 0) return launch_sweep_vo<SC, DIR, true>(variant, a, st);
   return launch_sweep_vo<SC, DIR, false>(variant, a, st);
 }
 

@@ -22,6 +22,8 @@ struct SweepArgs {
   int ppm;
   int vars;                             // interpolation variables (WIU_VARS_*)
   double ah;                            // free parameter of the one-midpoint schemes
+  int weights;                          // WIU_WEIGHTS_*
+  int split;                            // WIU_SPLIT_* of the leading midpoint flux
   // 0 (xi) write R^xi; 1 (eta) dU/dt = -(R^xi + R^eta)/J^{-1};
   // 3 (xi) write P = ca U0 + cb (U - dt R^xi/J^{-1}) into the R^xi buffer;
   // 2 (eta) RK stage U_out = P - cb dt R^eta/J^{-1}
@@ -58,6 +60,7 @@ struct BatchArgs {
   int ppm;
   int vars;                  // interpolation variables (WIU_VARS_*)
   double ah;                 // free parameter of the one-midpoint schemes
+  int weights, split;        // WIU_WEIGHTS_*, WIU_SPLIT_*
   int* status;
   double* U_all;             // bases of the offsets in BlockDev
   const double* M_all;

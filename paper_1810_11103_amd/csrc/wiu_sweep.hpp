@@ -70,9 +70,10 @@ WIU_DEV void wave_max_tile(const Dims& d, const double* __restrict__ U, const do
 
 
 // Waves per SIMD a sweep kernel is compiled for: 4 (at most 128 VGPRs) for
-// the third- and fifth-order schemes; the seventh-order interpolation needs
-// more registers than that without spilling, so 3 (at most 168).
-template <int SC> constexpr int sweep_waves() { return Traits<SC>::R == 4 ? 3 : 4; }
+// the third- and fifth-order schemes in the paper's configuration; the
+// seventh-order interpolation, and the kernels that carry the scheme options,
+// need more registers than that without spilling, so 3 (at most 168).
+template <int SC, bool OPT> constexpr int sweep_waves() { return Traits<SC>::R == 4 || OPT ? 3 : 4; }
 
 // LDS of a sweep tile.  Lanes of a wave run along the line for xi tiles and
 // across lines (then along) for eta tiles; both arrays are laid out so that
@@ -80,9 +81,12 @@ template <int SC> constexpr int sweep_waves() { return Traits<SC>::R == 4 ? 3 : 
 // for xi, position-major for eta.  Per item the nodal flux E^ is kept rather
 // than f^+- = (E^ +- lam Q)/2, which the output phase rebuilds from E^ and the
 // staged state (12 instead of 16 values per item, so larger tiles fit).
-template <int SC, int DIR, int NA, int NB> struct SweepLds {
+template <int SC, int DIR, int NA, int NB, bool OPT = false> struct SweepLds {
   static constexpr int NQ = NA + 2 * Range<SC>::QL + 1;  // states of items k - QL .. k + QL + 1
-  double sh[12][NA * NB];            // [kind*4 + comp][item]: kinds E^, F^+, F^-
+  // [kind*4 + comp][item]: kinds E^, F^+, F^- and, with the options, D (the
+  // difference another midpoint split makes to H at the item's midpoint)
+  static constexpr int NREC = OPT ? 16 : 12;
+  double sh[NREC][NA * NB];
   double sq[4][NB * NQ];
   // item slot of (line tb, position ta) and state slot of (line tb, position pos)
   static WIU_DEV int si(int tb, int ta) { return DIR == 0 ? tb * NA + ta : ta * NB + tb; }
@@ -90,11 +94,11 @@ template <int SC, int DIR, int NA, int NB> struct SweepLds {
 };
 
 // H_{i+1/2} - H_{i-1/2} at output node i of line tb from the items in LDS.
-template <int SC, int DIR, int NA, int NB>
-WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB>& L, int tb, int o0, int i, double lam, double ah,
-                           double R[4]) {
+template <int SC, int DIR, int NA, int NB, bool OPT>
+WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB, OPT>& L, int tb, int o0, int i, double lam, double ah,
+                           bool alt, double R[4]) {
   using R_ = Range<SC>;
-  using LT = SweepLds<SC, DIR, NA, NB>;
+  using LT = SweepLds<SC, DIR, NA, NB, OPT>;
   auto at = [&](int kk) { return LT::si(tb, kk - (o0 + R_::LO)); };      // item slot of node kk
   auto aq = [&](int kk) { return LT::qi(tb, kk - (o0 + R_::LO) + R_::QL); };  // state slot of node kk
 #pragma unroll
@@ -105,6 +109,9 @@ WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB>& L, int tb, int o0, i
     auto Fp = [&](int kk) { return L.sh[4 + c][at(kk)]; };
     auto Fm = [&](int kk) { return L.sh[8 + c][at(kk)]; };
     R[c] = hflux<SC>(i, ah, fp, fm, Fp, Fm) - hflux<SC>(i - 1, ah, fp, fm, Fp, Fm);
+    if constexpr (OPT) {
+      if (alt) R[c] += L.sh[12 + c][at(i)] - L.sh[12 + c][at(i - 1)];
+    }
   }
 }
 
@@ -124,16 +131,16 @@ struct OutOperands {
 // (fast) by 64/NB positions: the eta maxima reduce over the positions, the
 // xi maxima over the lines; wave speeds are clamped at zero as in the
 // separate pass, so the maxima are bit-identical to it.
-template <int SC, int NA, int NB>
-WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB>& L, bool act, int line, int i, int o0,
-                             int tb, double lam, double ah, const OutOperands& op) {
+template <int SC, int NA, int NB, bool OPT>
+WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB, OPT>& L, bool act, int line, int i, int o0,
+                             int tb, double lam, double ah, bool alt, const OutOperands& op) {
   static_assert(64 % NB == 0 && (NA * NB) % 64 == 0, "eta tile must pack whole waves");
   const Dims& d = s.d;
   double sx = 0.0, se = 0.0;
   bool bad = false;
   if (act) {
     double R[4];
-    tile_residual<SC, 1, NA, NB>(L, tb, o0, i, lam, ah, R);
+    tile_residual<SC, 1, NA, NB, OPT>(L, tb, o0, i, lam, ah, alt, R);
     const long long o = (long long)i * d.nx + line;
     const double rj = -rcp(op.jinv);
     const double dt = s.dt[0];
@@ -169,13 +176,15 @@ WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB>& L, boo
 // configuration (characteristic variables, alpha = 1) and carries no code
 // for the options, which keeps its register count down.
 template <int SC, int DIR, int NA, int NB, bool OPT>
-WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, NA, NB>& L) {
+WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, NA, NB, OPT>& L) {
   const double ah = OPT ? s.ah : 1.0;
+  const bool alt = OPT && s.split != 0;                 // another midpoint split
+  const int ppm = OPT && s.weights != 0 ? 2 : s.ppm;    // 2: WENO-Z weights
   using R_ = Range<SC>;
   constexpr int OUT = NA - R_::EXTRA;
   constexpr int NT = NA * NB;
   constexpr int QL = R_::QL;
-  constexpr int NQ = SweepLds<SC, DIR, NA, NB>::NQ;
+  constexpr int NQ = SweepLds<SC, DIR, NA, NB, OPT>::NQ;
   auto& sh = L.sh;
   auto& sq = L.sq;
 
@@ -200,7 +209,7 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   const int o0 = (DIR == 0 ? bxl : byl) * OUT;
   const int out = min(OUT, n_al - o0);
   const int k = o0 + R_::LO + ta;
-  using LT = SweepLds<SC, DIR, NA, NB>;
+  using LT = SweepLds<SC, DIR, NA, NB, OPT>;
   const int slot = LT::si(tb, ta);
   const bool live = line < n_ac;
 
@@ -260,18 +269,24 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
       const double nx_ = nbx * rn, ny_ = nby * rn;
       // the two sides one after the other: the compiler barrier keeps their
       // working sets from being interleaved (register pressure)
+      double D[4] = {0.0, 0.0, 0.0, 0.0};
+      const int split = alt ? s.split : 0;
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         asm volatile("" ::: "memory");
         double F[4];
         if (OPT && s.vars != 0)
-          side_flux_comp<Traits<SC>::R>(q, side, s.vars, mx, my, lam, gam, s.eps, s.ppm, F);
+          side_flux_comp<Traits<SC>::R, OPT>(q, side, s.vars, mx, my, lam, gam, s.eps, ppm, F, split, D);
         else if constexpr (Traits<SC>::R == 4)
-          side_flux7(q, side, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, F);
+          side_flux7<OPT>(q, side, nx_, ny_, mx, my, lam, gam, s.eps, ppm, F, split, D);
         else
-          side_flux<Traits<SC>::fifth>(q, side, nx_, ny_, mx, my, lam, gam, s.eps, s.ppm, F);
+          side_flux<Traits<SC>::fifth, OPT>(q, side, nx_, ny_, mx, my, lam, gam, s.eps, ppm, F, split, D);
 #pragma unroll
         for (int c = 0; c < 4; ++c) sh[4 + 4 * side + c][slot] = F[c];
+      }
+      if constexpr (OPT) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sh[12 + c][slot] = D[c];
       }
     }
   }
@@ -303,13 +318,13 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
 
   if constexpr (DIR == 1) {
     if (fused) {  // whole waves take part in the reductions
-      fused_stage_out<SC, NA, NB>(s, L, act, line, i, o0, tb, lam, ah, op);
+      fused_stage_out<SC, NA, NB, OPT>(s, L, act, line, i, o0, tb, lam, ah, alt, op);
       return;
     }
   }
   if (!act) return;  // no barrier follows
   double R[4];
-  tile_residual<SC, DIR, NA, NB>(L, tb, o0, i, lam, ah, R);
+  tile_residual<SC, DIR, NA, NB, OPT>(L, tb, o0, i, lam, ah, alt, R);
   if (s.mode == 0) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) s.Rxi[c * d.np + o] = R[c];

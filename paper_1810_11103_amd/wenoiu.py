@@ -43,7 +43,8 @@ class WiuBlock(ctypes.Structure):
 
 class WiuParams(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("alpha_lf", ctypes.c_double), ("eps", ctypes.c_double),
-                ("ppm", ctypes.c_int), ("vars", ctypes.c_int), ("alpha_h", ctypes.c_double)]
+                ("ppm", ctypes.c_int), ("vars", ctypes.c_int), ("alpha_h", ctypes.c_double),
+                ("weights", ctypes.c_int), ("split", ctypes.c_int)]
 
 
 def _load():
@@ -117,11 +118,20 @@ def make_grid(nx, ny, bc=("periodic", "periodic"), period=(0.0, 0.0)):
 VARS = {"characteristic": 0, "conservative": 1, "primitive": 2}
 
 
-def make_params(gamma=1.4, alpha_lf=1.1, eps=1e-40, ppm=1, vars="characteristic", alpha_h=1.0):
+WEIGHTS = {"js": 0, "z": 1}
+SPLITS = {"lf": 0, "sw": 1, "vl": 2}
+
+
+def make_params(gamma=1.4, alpha_lf=1.1, eps=1e-40, ppm=1, vars="characteristic", alpha_h=1.0, weights="js",
+                split="lf"):
     """Scheme parameters; vars: interpolation variables (Sec. 2.4), alpha_h:
-    free parameter of the one-midpoint families (Eqs. 3.5, 3.17, Appendix)."""
+    free parameter of the one-midpoint families (Eqs. 3.5, 3.17, Appendix),
+    weights: "js" (Eqs. 3.12-3.13) or "z" (WENO-Z), split: splitting of the
+    leading midpoint flux, "lf", "sw" (Steger-Warming) or "vl" (van Leer)."""
     v = VARS[vars] if isinstance(vars, str) else int(vars)
-    return WiuParams(float(gamma), float(alpha_lf), float(eps), int(ppm), v, float(alpha_h))
+    w = WEIGHTS[weights] if isinstance(weights, str) else int(weights)
+    sp = SPLITS[split] if isinstance(split, str) else int(split)
+    return WiuParams(float(gamma), float(alpha_lf), float(eps), int(ppm), v, float(alpha_h), w, sp)
 
 
 def _stream(stream=None):

@@ -76,14 +76,15 @@ def test_bad_scheme_params_and_pointers_rejected(wiu):
     assert wiu.lib.wiu_rhs(ctypes.byref(g), 3, ctypes.byref(p), dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL
     assert wiu.lib.wiu_rhs(ctypes.byref(g), 3, ctypes.byref(p), None, dummy, other, dummy, None) == wiu.WIU_EINVAL
     # interpolation variables 0..2; alpha_h != 1 only for the one-midpoint schemes
-    for kw, scheme in ((dict(vars=3), 3), (dict(alpha_h=0.9), 3), (dict(alpha_h=-1.0), 0), (dict(alpha_h=0.9), 7)):
+    for kw, scheme in ((dict(vars=3), 3), (dict(alpha_h=0.9), 3), (dict(alpha_h=-1.0), 0), (dict(alpha_h=0.9), 7),
+                       (dict(weights=2), 3), (dict(split=3), 3)):
         q = wiu.make_params(**kw)
         assert wiu.lib.wiu_rhs(ctypes.byref(g), scheme, ctypes.byref(q), dummy, dummy, other, dummy,
                                None) == wiu.WIU_EINVAL, kw
     assert wiu.lib.wiu_metrics(ctypes.byref(g), 3, ctypes.byref(wiu.make_params(alpha_h=0.9)), dummy, dummy, other,
                                dummy, None) == wiu.WIU_EINVAL
     # the adjoint: the paper's configuration only
-    for kw in (dict(vars=1), dict(alpha_h=0.9)):
+    for kw in (dict(vars=1), dict(alpha_h=0.9), dict(weights="z"), dict(split="sw")):
         q = wiu.make_params(**kw)
         assert wiu.lib.wiu_rhs_vjp(ctypes.byref(g), 0, ctypes.byref(q), dummy, dummy, other, ctypes.c_void_p(768),
                                    dummy, None) == wiu.WIU_EINVAL

@@ -124,12 +124,14 @@ def test_options_rejected_where_undefined(wiu):
         sol.rhs_vjp(Ud, torch.ones_like(Ud))
 
 
-@pytest.mark.parametrize("s,vars,a", [("5-1MP", "primitive", 0.9), ("7-2MP", "conservative", 1.0)])
-def test_batched_step_with_options_equals_per_block(wiu, s, vars, a):
+@pytest.mark.parametrize("s,vars,a,weights,split", [("5-1MP", "primitive", 0.9, "js", "lf"),
+                                                    ("7-2MP", "conservative", 1.0, "z", "sw"),
+                                                    ("3-2MP", "characteristic", 1.0, "js", "vl")])
+def test_batched_step_with_options_equals_per_block(wiu, s, vars, a, weights, split):
     import torch
-    say("batched options", s, vars, a)
+    say("batched options", s, vars, a, weights, split)
     blocks = W.batched_blocks(nblocks=6, seed=5, nmin=64, nmax=160)
-    params = wiu.make_params(vars=vars, alpha_h=a)
+    params = wiu.make_params(vars=vars, alpha_h=a, weights=weights, split=split)
     plan = wiu.BatchedPlan([(g.x, g.y, g.bc, g.period) for g, _ in blocks], s, params=params)
     for b, (_, U) in enumerate(blocks):
         plan.state(b).copy_(torch.as_tensor(U))
@@ -147,3 +149,43 @@ def test_batched_step_with_options_equals_per_block(wiu, s, vars, a):
     for b in range(len(blocks)):
         assert np.array_equal(plan.state(b).cpu().numpy(), ref[b]), b
     plan.close()
+
+
+ZS_CASES = [("3-2MP", "z", "lf"), ("5-2MP", "z", "lf"), ("7-1MP", "z", "lf"), ("3-1MP", "js", "sw"),
+            ("5-2MP", "js", "sw"), ("7-6MP", "js", "vl"), ("5-1MP", "js", "vl"), ("5-2MP", "z", "vl")]
+
+
+@pytest.mark.parametrize("s,weights,split", ZS_CASES)
+@pytest.mark.parametrize("kind,nx,ny", [("vortex", 300, 70), ("riemann", 260, 90)])
+def test_rhs_parity_weno_z_and_splits(orc, wiu, s, weights, split, kind, nx, ny):
+    """WENO-Z weights and the Steger-Warming / van Leer split of the leading
+    midpoint flux (Sec. 7) against the oracle."""
+    say("rhs parity weights/split", s, weights, split, kind, nx, ny)
+    g, U = make_case(kind, nx, ny, seed=13)
+    Mo = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    ref = orc.rhs(s, U, Mo, g.bc, weights=weights, split=split)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period, params=wiu.make_params(weights=weights, split=split))
+    out = _host(sol.rhs(_dev(U)))
+    assert sol.status() == 0
+    err = normwise(out, ref)
+    assert np.all(err <= 1e-12), err
+
+
+@pytest.mark.parametrize("s,weights,split,vars", [("5-2MP", "z", "sw", "primitive"), ("7-4MP", "js", "vl", "conservative"),
+                                                  ("3-1MP", "z", "vl", "characteristic")])
+def test_options_combined_fsp_and_rk3_parity(orc, wiu, s, weights, split, vars):
+    say("combined options", s, weights, split, vars)
+    kw = dict(weights=weights, split=split, vars=vars)
+    g, U = W.fsp_problem(128, A=0.2)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period, params=wiu.make_params(**kw))
+    assert np.abs(_host(sol.rhs(_dev(U)))).max() < 1e-11
+    g, U = make_case("riemann", 260, 90, seed=5)
+    Mo = orc.metrics(s, g.x, g.y, g.bc, g.period)
+    dt = orc.cfl_dt(U, Mo, 0.5)
+    ref = orc.rk3_step(s, U, Mo, dt, g.bc, **kw)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period, params=wiu.make_params(**kw))
+    Ud = _dev(U)
+    sol.rk3_step(Ud, dt)
+    assert sol.status() == 0
+    err = normwise(_host(Ud) - U, ref - U)
+    assert np.all(err <= 1e-11), err

@@ -59,13 +59,13 @@ def lib():
         L.orc_metrics.restype = _I
         L.orc_metrics.argtypes = [_I, _D, _I, _I, _I, _I, _D, _D, _P, _P, _P]
         L.orc_rhs.restype = _I
-        L.orc_rhs.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P, _P]
+        L.orc_rhs.argtypes = [_I, _I, _I, _I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P, _P]
         L.orc_cfl_dt.restype = _D
         L.orc_cfl_dt.argtypes = [_I, _I, _D, _P, _P, _D]
         L.orc_rk3_step.restype = _I
-        L.orc_rk3_step.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _D]
+        L.orc_rk3_step.argtypes = [_I, _I, _I, _I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _D]
         L.orc_rk3_run.restype = _I
-        L.orc_rk3_run.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _D, _I]
+        L.orc_rk3_run.argtypes = [_I, _I, _I, _I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _D, _I]
         L.orc_adv1d_rhs.restype = None
         L.orc_adv1d_rhs.argtypes = [_I, _I, _D, _I, _D, _D, _I, _D, _I, _P, _P]
         L.orc_adv1d_run.restype = _I
@@ -73,14 +73,14 @@ def lib():
         for nm in ("orc_rhs_jvp", "orc_rk3_step_jvp"):
             f = getattr(L, nm)
             f.restype = _I
-        L.orc_rhs_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P, _P]
-        L.orc_rk3_step_jvp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _D, _P, _P]
+        L.orc_rhs_jvp.argtypes = [_I, _I, _I, _I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P, _P]
+        L.orc_rk3_step_jvp.argtypes = [_I, _I, _I, _I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _D, _P, _P]
         L.orc_rhs_vjp.restype = _I
-        L.orc_rhs_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P]
+        L.orc_rhs_vjp.argtypes = [_I, _I, _I, _I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P]
         L.orc_rk3_step_vjp.restype = _I
-        L.orc_rk3_step_vjp.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _D, _P, _P]
+        L.orc_rk3_step_vjp.argtypes = [_I, _I, _I, _I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _D, _P, _P]
         L.orc_count_rhs_flops.restype = _I
-        L.orc_count_rhs_flops.argtypes = [_I, _I, _I, _I, _I, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P]
+        L.orc_count_rhs_flops.argtypes = [_I, _I, _I, _I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P]
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [_I]
         L.orc_get_threads.restype = _I
@@ -118,6 +118,21 @@ def weights_id(w):
 def split_id(s):
     """Midpoint flux split: "lf" (Lax-Friedrichs), "sw" (Steger-Warming), "vl" (van Leer)."""
     return SPLITS[s] if isinstance(s, str) else int(s)
+
+
+SIDES = {"transmissive": 0, "wall": 1, "fixed": 2}
+
+
+def _sides(sides, fixed):
+    """(side kinds, fixed states) of the four sides (x lo, x hi, y lo, y hi) as
+    ctypes pointers, or nulls for all-transmissive.  sides: names or 0/1/2;
+    fixed: conservative states [4][4] used by "fixed" sides."""
+    if sides is None:
+        return None, None
+    k = np.ascontiguousarray([SIDES[v] if isinstance(v, str) else int(v) for v in sides], dtype=np.int32)
+    f = np.zeros((4, 4)) if fixed is None else np.ascontiguousarray(fixed, dtype=np.float64).reshape(4, 4)
+    _sides.keep = (k, f)  # alive for the duration of the call
+    return k.ctypes.data_as(ctypes.c_void_p), f.ctypes.data_as(ctypes.c_void_p)
 
 
 def scheme_id(s):
@@ -235,13 +250,14 @@ def metrics(scheme, x, y, bc=("periodic", "periodic"), period=(0.0, 0.0), alpha_
 
 
 def rhs(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0,
+        sides=None, fixed=None,
         return_lambda=False):
     U, M = _f64(U), _f64(M)
     _, ny, nx = U.shape
     out = np.zeros_like(U)
     lx = np.zeros(ny)
     le = np.zeros(nx)
-    rc = lib().orc_rhs(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
+    rc = lib().orc_rhs(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), *_sides(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                        _ptr(U), _ptr(M), _ptr(out), _ptr(lx), _ptr(le))
     if rc:
         raise ValueError("orc_rhs failed")
@@ -250,58 +266,63 @@ def rhs(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-
     return out
 
 
-def count_rhs_flops(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
+def count_rhs_flops(scheme, U, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0,
+        sides=None, fixed=None):
     """Operation counts of one rhs: (xi sweep, eta sweep, final combination)."""
     U, M = _f64(U), _f64(M)
     _, ny, nx = U.shape
     c = np.zeros(3, dtype=np.int64)
-    rc = lib().orc_count_rhs_flops(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
+    rc = lib().orc_count_rhs_flops(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), *_sides(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                                    _ptr(U), _ptr(M), _ptr(c))
     if rc:
         raise ValueError("orc_count_rhs_flops failed")
     return tuple(int(v) for v in c)
 
 
-def rhs_jvp(scheme, U, V, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
+def rhs_jvp(scheme, U, V, M, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0,
+        sides=None, fixed=None):
     """(rhs(U), (d rhs/dU) V) by forward-mode dual numbers."""
     U, V, M = _f64(U), _f64(V), _f64(M)
     _, ny, nx = U.shape
     val, tan = np.zeros_like(U), np.zeros_like(U)
-    rc = lib().orc_rhs_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
+    rc = lib().orc_rhs_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), *_sides(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                            _ptr(U), _ptr(V), _ptr(M), _ptr(val), _ptr(tan))
     if rc:
         raise ValueError("orc_rhs_jvp failed")
     return val, tan
 
 
-def rhs_vjp(scheme, U, M, Gbar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
+def rhs_vjp(scheme, U, M, Gbar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0,
+        sides=None, fixed=None):
     """(d rhs/dU)^T Gbar by reverse mode on a tape."""
     U, M, Gbar = _f64(U), _f64(M), _f64(Gbar)
     _, ny, nx = U.shape
     out = np.zeros_like(U)
-    rc = lib().orc_rhs_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
+    rc = lib().orc_rhs_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), *_sides(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                            _ptr(U), _ptr(M), _ptr(Gbar), _ptr(out))
     if rc:
         raise ValueError("orc_rhs_vjp failed")
     return out
 
 
-def rk3_step_jvp(scheme, U, V, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
+def rk3_step_jvp(scheme, U, V, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0,
+        sides=None, fixed=None):
     U, V, M = _f64(U), _f64(V), _f64(M)
     _, ny, nx = U.shape
     val, tan = np.zeros_like(U), np.zeros_like(U)
-    rc = lib().orc_rk3_step_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
+    rc = lib().orc_rk3_step_jvp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), *_sides(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                                 _ptr(U), _ptr(V), _ptr(M), dt, _ptr(val), _ptr(tan))
     if rc:
         raise ValueError("orc_rk3_step_jvp failed")
     return val, tan
 
 
-def rk3_step_vjp(scheme, U, M, dt, Ubar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
+def rk3_step_vjp(scheme, U, M, dt, Ubar, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0,
+        sides=None, fixed=None):
     U, M, Ubar = _f64(U), _f64(M), _f64(Ubar)
     _, ny, nx = U.shape
     out = np.zeros_like(U)
-    rc = lib().orc_rk3_step_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
+    rc = lib().orc_rk3_step_vjp(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), *_sides(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                                 _ptr(U), _ptr(M), dt, _ptr(Ubar), _ptr(out))
     if rc:
         raise ValueError("orc_rk3_step_vjp failed")
@@ -314,22 +335,24 @@ def cfl_dt(U, M, cfl, gamma=1.4):
     return lib().orc_cfl_dt(nx, ny, gamma, _ptr(U), _ptr(M), cfl)
 
 
-def rk3_step(scheme, U, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
+def rk3_step(scheme, U, M, dt, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0,
+        sides=None, fixed=None):
     U = np.array(U, dtype=np.float64, copy=True, order="C")
     M = _f64(M)
     _, ny, nx = U.shape
-    rc = lib().orc_rk3_step(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
+    rc = lib().orc_rk3_step(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), *_sides(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                             _ptr(U), _ptr(M), dt)
     if rc:
         raise ValueError("orc_rk3_step failed")
     return U
 
 
-def rk3_run(scheme, U, M, dt, nsteps, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
+def rk3_run(scheme, U, M, dt, nsteps, bc=("periodic", "periodic"), gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0,
+        sides=None, fixed=None):
     U = np.array(U, dtype=np.float64, copy=True, order="C")
     M = _f64(M)
     _, ny, nx = U.shape
-    rc = lib().orc_rk3_run(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
+    rc = lib().orc_rk3_run(scheme_id(scheme), nx, ny, bc_id(bc[0]), bc_id(bc[1]), *_sides(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h), weights_id(weights), split_id(split),
                            _ptr(U), _ptr(M), dt, int(nsteps))
     if rc:
         raise ValueError("orc_rk3_run failed")

@@ -18,9 +18,15 @@ using namespace orc;
 
 namespace {
 
-Grid make_grid(int nx, int ny, int bcx, int bcy, double Lx, double Ly) {
+// side[4] (x lo, x hi, y lo, y hi; Side values) and fixed[4][4] may be null.
+Grid make_grid(int nx, int ny, int bcx, int bcy, double Lx, double Ly, const int* side = nullptr,
+               const double* fixed = nullptr) {
   Grid g;
   g.nx = nx; g.ny = ny; g.bcx = (Bc)bcx; g.bcy = (Bc)bcy; g.Lx = Lx; g.Ly = Ly;
+  for (int k = 0; k < 4; ++k) {
+    g.side[k] = side ? side[k] : SIDE_TRANSMISSIVE;
+    for (int q = 0; q < 4; ++q) g.fixed[k][q] = fixed ? fixed[4 * k + q] : 0.0;
+  }
   return g;
 }
 
@@ -156,11 +162,11 @@ int orc_metrics(int scheme, double alpha_h, int nx, int ny, int bcx, int bcy, do
   return 0;
 }
 
-int orc_rhs(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
+int orc_rhs(int scheme, int nx, int ny, int bcx, int bcy, const int* side, const double* fixed, double gamma, double alpha, double eps, int ppm, int vars,
          double alpha_h, int weights, int split,
             const double* U, const double* M, double* dUdt, double* lam_xi, double* lam_eta) {
   if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
-  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0, side, fixed);
   Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   rhs<double>((Scheme)scheme, p, g, U, M, dUdt, lam_xi, lam_eta);
   return 0;
@@ -172,22 +178,22 @@ double orc_cfl_dt(int nx, int ny, double gamma, const double* U, const double* M
   return cfl_dt(p, g, U, M, cfl);
 }
 
-int orc_rk3_step(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
+int orc_rk3_step(int scheme, int nx, int ny, int bcx, int bcy, const int* side, const double* fixed, double gamma, double alpha, double eps, int ppm, int vars,
          double alpha_h, int weights, int split,
                  double* U, const double* M, double dt) {
   if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
-  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0, side, fixed);
   Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   rk3_step<double>((Scheme)scheme, p, g, U, M, dt);
   return 0;
 }
 
 // Run nsteps TVD-RK3 steps at fixed dt.
-int orc_rk3_run(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
+int orc_rk3_run(int scheme, int nx, int ny, int bcx, int bcy, const int* side, const double* fixed, double gamma, double alpha, double eps, int ppm, int vars,
          double alpha_h, int weights, int split,
                 double* U, const double* M, double dt, int nsteps) {
   for (int s = 0; s < nsteps; ++s) {
-    int rc = orc_rk3_step(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U, M, dt);
+    int rc = orc_rk3_step(scheme, nx, ny, bcx, bcy, side, fixed, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U, M, dt);
     if (rc) return rc;
   }
   return 0;
@@ -274,12 +280,12 @@ struct SingleThread {
 };
 
 // out_val = rhs(U), out_tan = (d rhs / dU) V (forward mode).
-int orc_rhs_jvp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
+int orc_rhs_jvp(int scheme, int nx, int ny, int bcx, int bcy, const int* side, const double* fixed, double gamma, double alpha, double eps, int ppm, int vars,
          double alpha_h, int weights, int split,
                 const double* U, const double* V, const double* M, double* out_val, double* out_tan) {
   if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
   SingleThread guard;
-  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0, side, fixed);
   Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   const size_t N = 4 * (size_t)nx * ny;
   std::vector<Dual> Ud(N), out(N);
@@ -290,12 +296,12 @@ int orc_rhs_jvp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, doub
 }
 
 // Ubar = (d rhs / dU)^T Gbar (reverse mode on a tape).
-int orc_rhs_vjp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
+int orc_rhs_vjp(int scheme, int nx, int ny, int bcx, int bcy, const int* side, const double* fixed, double gamma, double alpha, double eps, int ppm, int vars,
          double alpha_h, int weights, int split,
                 const double* U, const double* M, const double* Gbar, double* Ubar) {
   if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
   SingleThread guard;
-  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0, side, fixed);
   Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   const size_t N = 4 * (size_t)nx * ny;
   Tape& tape = Tape::get();
@@ -313,13 +319,13 @@ int orc_rhs_vjp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, doub
 }
 
 // Tangent of one TVD-RK3 step at fixed dt: (U_out, dU_out) from (U, V).
-int orc_rk3_step_jvp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
+int orc_rk3_step_jvp(int scheme, int nx, int ny, int bcx, int bcy, const int* side, const double* fixed, double gamma, double alpha, double eps, int ppm, int vars,
          double alpha_h, int weights, int split,
                      const double* U, const double* V, const double* M, double dt, double* out_val,
                      double* out_tan) {
   if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
   SingleThread guard;
-  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0, side, fixed);
   Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   const size_t N = 4 * (size_t)nx * ny;
   std::vector<Dual> Ud(N);
@@ -332,11 +338,11 @@ int orc_rk3_step_jvp(int scheme, int nx, int ny, int bcx, int bcy, double gamma,
 // Adjoint of one TVD-RK3 step at fixed dt: Ubar_n = (dU^{n+1}/dU^n)^T Ubar_np1,
 // composed from the stage adjoints:
 //   U1 = U + dt L(U);  U2 = 3/4 U + 1/4 (U1 + dt L(U1));  U' = 1/3 U + 2/3 (U2 + dt L(U2))
-int orc_rk3_step_vjp(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps, int ppm, int vars,
+int orc_rk3_step_vjp(int scheme, int nx, int ny, int bcx, int bcy, const int* side, const double* fixed, double gamma, double alpha, double eps, int ppm, int vars,
          double alpha_h, int weights, int split,
                      const double* U, const double* M, double dt, const double* Ubar_np1, double* Ubar_n) {
   if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
-  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0, side, fixed);
   Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   const size_t N = 4 * (size_t)nx * ny;
   std::vector<double> L(N), U1(N), U2(N), w(N), a(N), u2b(N), u1b(N);
@@ -345,19 +351,19 @@ int orc_rk3_step_vjp(int scheme, int nx, int ny, int bcx, int bcy, double gamma,
   rhs<double>((Scheme)scheme, p, g, U1.data(), M, L.data());
   for (size_t e = 0; e < N; ++e) U2[e] = 0.75 * U[e] + 0.25 * (U1[e] + dt * L[e]);
   // stage 3
-  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U2.data(), M, Ubar_np1, a.data());
+  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, side, fixed, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U2.data(), M, Ubar_np1, a.data());
   for (size_t e = 0; e < N; ++e) {
     u2b[e] = (2.0 / 3.0) * (Ubar_np1[e] + dt * a[e]);
     Ubar_n[e] = (1.0 / 3.0) * Ubar_np1[e];
   }
   // stage 2
-  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U1.data(), M, u2b.data(), a.data());
+  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, side, fixed, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U1.data(), M, u2b.data(), a.data());
   for (size_t e = 0; e < N; ++e) {
     u1b[e] = 0.25 * (u2b[e] + dt * a[e]);
     Ubar_n[e] += 0.75 * u2b[e];
   }
   // stage 1
-  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U, M, u1b.data(), a.data());
+  orc_rhs_vjp(scheme, nx, ny, bcx, bcy, side, fixed, gamma, alpha, eps, ppm, vars, alpha_h, weights, split, U, M, u1b.data(), a.data());
   for (size_t e = 0; e < N; ++e) Ubar_n[e] += u1b[e] + dt * a[e];
   return 0;
 }
@@ -368,10 +374,10 @@ int orc_rk3_step_vjp(int scheme, int nx, int ny, int bcx, int bcy, double gamma,
 static long long g_marks[3];
 static void mark(int ph) { g_marks[ph] = Counted::n(); }
 
-int orc_count_rhs_flops(int scheme, int nx, int ny, int bcx, int bcy, double gamma, double alpha, double eps,
+int orc_count_rhs_flops(int scheme, int nx, int ny, int bcx, int bcy, const int* side, const double* fixed, double gamma, double alpha, double eps,
                         int ppm, int vars, double alpha_h, int weights, int split, const double* U, const double* M, long long* counts) {
   if (bad_options(scheme, vars, alpha_h, weights, split) || nx < 1 || ny < 1) return -1;
-  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0);
+  Grid g = make_grid(nx, ny, bcx, bcy, 0.0, 0.0, side, fixed);
   Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
   const size_t N = 4 * (size_t)nx * ny;
   std::vector<Counted> Uc(U, U + N), out(N);

@@ -357,10 +357,19 @@ inline double metric_derivative(Scheme sc, double a, const double r[17]) {
 // ===========================================================================
 // Grid description and coordinate extension.
 // ===========================================================================
+// Rule of one side of a non-periodic direction for the states outside the
+// grid (the paper fixes none; these are the library's): transmissive (copy
+// of the boundary node), a reflecting slip wall (mirror image about the
+// boundary node with the momentum's component along the boundary's metric
+// direction reversed), or a fixed state (e.g. supersonic inflow).
+enum Side { SIDE_TRANSMISSIVE = 0, SIDE_WALL = 1, SIDE_FIXED = 2 };
+
 struct Grid {
   int nx, ny;
   Bc bcx, bcy;
   double Lx, Ly;  // period lengths of periodic directions
+  int side[4] = {SIDE_TRANSMISSIVE, SIDE_TRANSMISSIVE, SIDE_TRANSMISSIVE, SIDE_TRANSMISSIVE};  // x lo, x hi, y lo, y hi
+  double fixed[4][4] = {};  // conservative state outside a SIDE_FIXED side
 };
 
 inline int wrap(int a, int n) { int r = a % n; return r < 0 ? r + n : r; }
@@ -806,14 +815,35 @@ void rhs(Scheme sc, const Params& pr, const Grid& g, const T* U, const double* M
   const int nx = g.nx, ny = g.ny;
   const size_t NP = (size_t)nx * ny;
   MetricView mv{nx, ny, M};
-  auto wi = [&](int i) { return g.bcx == PERIODIC ? wrap(i, nx) : std::min(std::max(i, 0), nx - 1); };
-  auto wj = [&](int j) { return g.bcy == PERIODIC ? wrap(j, ny) : std::min(std::max(j, 0), ny - 1); };
+  // State at line index k of a line of n nodes (at(m, q): node m of the line)
+  // under the boundary rule: periodic wrap, or the side's rule beyond the
+  // ends; kx, ky: the line direction's metric plane indices for a wall normal.
+  auto line_state = [&](int n, bool periodic, int slo, int shi, auto at, auto knode, int k, int q) -> T {
+    if (periodic) return at(wrap(k, n), q);
+    if (k >= 0 && k < n) return at(k, q);
+    const int sd = k < 0 ? slo : shi;
+    const int kb = k < 0 ? 0 : n - 1;  // boundary node
+    if (g.side[sd] == SIDE_FIXED) return T(g.fixed[sd][q]);
+    if (g.side[sd] == SIDE_WALL) {
+      const int km = std::min(std::max(2 * kb - k, 0), n - 1);  // mirror node
+      if (q == 0 || q == 3) return at(km, q);
+      double nxb, nyb;
+      knode(kb, nxb, nyb);
+      const double nn = std::sqrt(nxb * nxb + nyb * nyb);
+      nxb /= nn; nyb /= nn;
+      const T mn = at(km, 1) * nxb + at(km, 2) * nyb;
+      return at(km, q) - 2.0 * mn * (q == 1 ? nxb : nyb);
+    }
+    return at(kb, q);
+  };
   std::vector<T> Rx(4 * NP), Ry(4 * NP);
   // xi sweep: one line per row j
 #pragma omp parallel for schedule(dynamic)
   for (int j = 0; j < ny; ++j) {
     std::vector<T> R(4 * nx);
-    auto Q = [&](int k, int q) { return U[q * NP + (size_t)j * nx + wi(k)]; };
+    auto at = [&](int m, int q) { return U[q * NP + (size_t)j * nx + m]; };
+    auto kn = [&](int m, double& a, double& b) { a = mv(0, m, j); b = mv(1, m, j); };
+    auto Q = [&](int k, int q) { return line_state(nx, g.bcx == PERIODIC, 0, 1, at, kn, k, q); };
     const int plane[4] = {0, 1, 5, 6};
     auto K = [&](int w, int k) { return mv(plane[w], k, j); };
     T lam;
@@ -827,7 +857,9 @@ void rhs(Scheme sc, const Params& pr, const Grid& g, const T* U, const double* M
 #pragma omp parallel for schedule(dynamic)
   for (int i = 0; i < nx; ++i) {
     std::vector<T> R(4 * ny);
-    auto Q = [&](int k, int q) { return U[q * NP + (size_t)wj(k) * nx + i]; };
+    auto at = [&](int m, int q) { return U[q * NP + (size_t)m * nx + i]; };
+    auto kn = [&](int m, double& a, double& b) { a = mv(2, i, m); b = mv(3, i, m); };
+    auto Q = [&](int k, int q) { return line_state(ny, g.bcy == PERIODIC, 2, 3, at, kn, k, q); };
     const int plane[4] = {2, 3, 7, 8};
     auto K = [&](int w, int k) { return mv(plane[w], i, k); };
     T lam;

@@ -107,6 +107,16 @@ def strip_grid(n, x0=0.0, x1=1.0):
     return Grid(np.ascontiguousarray(x), y, ("transmissive", "periodic"), (0.0, h), (h, h), {})
 
 
+def line_grid(n, x0=0.0, x1=1.0):
+    """One-row node grid for 1-D problems with boundary nodes on x0 and x1:
+    x_i = x0 + i h, i = 0..n-1, h = (x1 - x0)/(n - 1); non-periodic in x,
+    periodic in y with period h."""
+    h = (x1 - x0) / (n - 1)
+    x = (x0 + np.arange(n, dtype=np.float64) * h)[None, :]
+    y = np.zeros((1, n))
+    return Grid(np.ascontiguousarray(x), y, ("transmissive", "periodic"), (0.0, h), (h, h), {})
+
+
 def sinusoidal_grid(nx, ny, box=(0.0, 10.0, 0.0, 10.0), amp=0.1):
     """Smooth periodic curvilinear grid: x = x0 + L_x[s + a sin(2 pi t)],
     y = y0 + L_y[t + a sin(2 pi s)] with s = i/nx, t = j/ny."""
@@ -209,6 +219,17 @@ def sod_state(grid, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1), x0=0.5, gamma
     u = np.where(L, left[1], right[1])
     p = np.where(L, left[2], right[2])
     return conservative(rho, u, np.zeros_like(u), p, gamma)
+
+
+def shu_osher_state(grid, gamma=GAMMA):
+    """Shu-Osher problem (Sec. 6.2(2)) on [-5, 5]: (rho, u, p) = (3.857143,
+    2.629369, 10.3333) for x < -4, (1 + 0.2 sin 5x, 0, 1) otherwise."""
+    x = grid.x
+    left = x < -4.0
+    rho = np.where(left, 3.857143, 1.0 + 0.2 * np.sin(5.0 * x))
+    u = np.where(left, 2.629369, 0.0)
+    p = np.where(left, 10.3333, 1.0)
+    return conservative(rho, u, np.zeros_like(x), p, gamma)
 
 
 def riemann_problem(n=2048, A=0.2, seed=2048, layers=4):

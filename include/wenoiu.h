@@ -60,6 +60,19 @@ enum {
  * boundary rule; these are the library's.) */
 enum { WIU_BC_PERIODIC = 0, WIU_BC_TRANSMISSIVE = 1 };
 
+/* Rule for the states beyond one side of a non-periodic direction (the
+ * paper states none; the library's), in wiu_grid.side[] ordered x low,
+ * x high, y low, y high:
+ *   WIU_SIDE_TRANSMISSIVE  copy of the boundary node (default, value 0);
+ *   WIU_SIDE_WALL          reflecting slip wall: mirror image about the
+ *                          boundary node with the momentum component along
+ *                          the boundary node's metric direction reversed;
+ *   WIU_SIDE_FIXED         the conservative state wiu_grid.fixed[side]
+ *                          (e.g. supersonic inflow).
+ * Coordinates extend linearly beyond every non-periodic side.  The rules
+ * are ignored for periodic directions. */
+enum { WIU_SIDE_TRANSMISSIVE = 0, WIU_SIDE_WALL = 1, WIU_SIDE_FIXED = 2 };
+
 #define WIU_GHOST 4
 
 /* host-side return codes */
@@ -77,6 +90,8 @@ typedef struct {
   int nx, ny;               /* nodes per direction (>= 1; >= 2 if transmissive) */
   int bc_x, bc_y;           /* WIU_BC_* */
   double period_x, period_y; /* domain lengths of periodic directions */
+  int side[4];              /* WIU_SIDE_* of x low, x high, y low, y high (0: transmissive) */
+  double fixed[4][4];       /* conservative state beyond a WIU_SIDE_FIXED side */
 } wiu_grid;
 
 /* Variables the midpoint values are interpolated in (Sec. 2.4): the

@@ -87,6 +87,19 @@ bool grid_ok(const wiu_grid* g) {
   if (g->bc_y == WIU_BC_TRANSMISSIVE && g->ny < 2) return false;
   if (g->bc_x == WIU_BC_PERIODIC && !(g->period_x > 0.0)) return false;
   if (g->bc_y == WIU_BC_PERIODIC && !(g->period_y > 0.0)) return false;
+  // side rules of non-periodic directions; fixed states must be physical
+  for (int k = 0; k < 4; ++k) {
+    const bool periodic = (k < 2 ? g->bc_x : g->bc_y) == WIU_BC_PERIODIC;
+    if (periodic) continue;
+    if (g->side[k] < WIU_SIDE_TRANSMISSIVE || g->side[k] > WIU_SIDE_FIXED) return false;
+    if (g->side[k] == WIU_SIDE_FIXED) {
+      const double* q = g->fixed[k];
+      const double rho = q[0];
+      if (!(rho > 0.0) || !(rho < 1.0e300)) return false;
+      const double p = q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / rho;  // (gamma - 1) p
+      if (!(p > 0.0) || !(p < 1.0e300)) return false;
+    }
+  }
   // launch geometry limits (grid.y <= 65535 for the row-wise launches)
   if (g->ny > 65535 * 4 || g->nx > (1 << 28)) return false;
   return true;
@@ -110,10 +123,15 @@ bool scheme_ok(int s) { return s >= 0 && s <= 7; }
 bool options_ok(int s, const wiu_params* p) { return scheme_ok(s) && params_ok(p) && alpha_h_ok(s, p->alpha_h); }
 
 // The adjoint covers the third- and fifth-order schemes with the paper's
-// configuration (characteristic variables, alpha_h = 1).
-bool adjoint_ok(int s, const wiu_params* p) {
-  return s >= 0 && s <= 3 && params_ok(p) && p->vars == WIU_VARS_CHARACTERISTIC && p->alpha_h == 1.0 &&
-         p->weights == WIU_WEIGHTS_JS && p->split == WIU_SPLIT_LF;
+// configuration (characteristic variables, alpha_h = 1) on periodic or
+// transmissive sides.
+bool adjoint_ok(int s, const wiu_params* p, const wiu_grid* g) {
+  if (!(s >= 0 && s <= 3 && params_ok(p) && p->vars == WIU_VARS_CHARACTERISTIC && p->alpha_h == 1.0 &&
+        p->weights == WIU_WEIGHTS_JS && p->split == WIU_SPLIT_LF))
+    return false;
+  for (int k = 0; k < 4; ++k)
+    if ((k < 2 ? g->bc_x : g->bc_y) != WIU_BC_PERIODIC && g->side[k] != WIU_SIDE_TRANSMISSIVE) return false;
+  return true;
 }
 
 Dims dims(const wiu_grid* g) {
@@ -227,6 +245,11 @@ int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U
   a.d = d; a.U = U; a.M = M;
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
   a.vars = p->vars; a.ah = p->alpha_h; a.weights = p->weights; a.split = p->split;
+  for (int k = 0; k < 4; ++k) {
+    const bool periodic = (k < 2 ? g->bc_x : g->bc_y) == WIU_BC_PERIODIC;
+    a.side[k] = periodic ? WIU_SIDE_TRANSMISSIVE : g->side[k];
+    for (int c = 0; c < 4; ++c) a.fixed[k][c] = g->fixed[k][c];
+  }
   a.mode = mode == 2 ? 3 : 0; a.Rxi = w.rxi; a.out = out; a.U0 = U0; a.dt = dt; a.ca = ca; a.cb = cb;
   a.status = w.status;
   a.nlam_xi = nullptr; a.nlam_eta = nullptr;
@@ -361,7 +384,7 @@ int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double*
 
 int wiu_rhs_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M,
                 const double* Gbar, double* Ubar, void* ws, wiu_stream_t stream) {
-  if (!grid_ok(g) || !adjoint_ok(scheme, p) || !U || !M || !Gbar || !Ubar || !ws)
+  if (!grid_ok(g) || !adjoint_ok(scheme, p, g) || !U || !M || !Gbar || !Ubar || !ws)
     return WIU_EINVAL;
   if (Ubar == U || Ubar == Gbar) return WIU_EINVAL;
   Ws w = carve(g, ws);
@@ -384,7 +407,7 @@ int wiu_rk3_step_stages(const wiu_grid* g, int scheme, const wiu_params* p, doub
 int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U_n, const double* U1,
                      const double* U2, const void* rec, const double* M, const double* dt_dev,
                      const double* Ubar_np1, double* Ubar_n, void* ws, wiu_stream_t stream) {
-  if (!grid_ok(g) || !adjoint_ok(scheme, p) || !U_n || !M || !dt_dev || !Ubar_np1 || !Ubar_n ||
+  if (!grid_ok(g) || !adjoint_ok(scheme, p, g) || !U_n || !M || !dt_dev || !Ubar_np1 || !Ubar_n ||
       !ws)
     return WIU_EINVAL;
   if ((U1 == nullptr) != (U2 == nullptr)) return WIU_EINVAL;

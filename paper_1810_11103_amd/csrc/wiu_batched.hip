@@ -77,6 +77,10 @@ BatchArgs base_args(const wiu_plan* p) {
   a.gamma = p->params.gamma; a.alpha = p->params.alpha_lf; a.eps = p->params.eps; a.ppm = p->params.ppm;
   a.vars = p->params.vars; a.ah = p->params.alpha_h;
   a.weights = p->params.weights; a.split = p->params.split;
+  for (int k = 0; k < 4; ++k) {  // blocks have periodic or transmissive sides
+    a.side[k] = WIU_SIDE_TRANSMISSIVE;
+    for (int c = 0; c < 4; ++c) a.fixed[k][c] = 0.0;
+  }
   a.status = p->d_status;
   a.U_all = p->U_all;
   a.M_all = p->M_all;

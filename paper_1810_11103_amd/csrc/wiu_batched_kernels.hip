@@ -48,6 +48,12 @@ __global__ void __launch_bounds__(NA * NB, (sweep_waves<SC, OPT>())) batched_swe
     s.nlam_xi = nlam; s.nlam_eta = nlam ? nlam + s.d.ny : nullptr;
     s.gamma = b.gamma; s.alpha = b.alpha; s.eps = b.eps; s.ppm = b.ppm; s.vars = b.vars; s.ah = b.ah;
     s.weights = b.weights; s.split = b.split;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s.side[k] = b.side[k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s.fixed[k][c] = b.fixed[k][c];
+    }
     s.Rxi = b.ws + ufirst(B.oRxi); s.U0 = b.U_all + ufirst(B.oU); s.dt = b.ws + ufirst(B.oDt);
     s.status = b.status;
     s.U = stage_src(b, B, st);

@@ -24,6 +24,10 @@ struct SweepArgs {
   double ah;                            // free parameter of the one-midpoint schemes
   int weights;                          // WIU_WEIGHTS_*
   int split;                            // WIU_SPLIT_* of the leading midpoint flux
+  // rules beyond the sides of non-periodic directions (x lo, x hi, y lo,
+  // y hi): 0 transmissive, 1 reflecting wall, 2 fixed state `fixed`
+  int side[4];
+  double fixed[4][4];
   // 0 (xi) write R^xi; 1 (eta) dU/dt = -(R^xi + R^eta)/J^{-1};
   // 3 (xi) write P = ca U0 + cb (U - dt R^xi/J^{-1}) into the R^xi buffer;
   // 2 (eta) RK stage U_out = P - cb dt R^eta/J^{-1}
@@ -61,6 +65,11 @@ struct BatchArgs {
   int vars;                  // interpolation variables (WIU_VARS_*)
   double ah;                 // free parameter of the one-midpoint schemes
   int weights, split;        // WIU_WEIGHTS_*, WIU_SPLIT_*
+  // side rules for the sweeps: batched blocks have periodic or transmissive
+  // sides only (all zero), passed as arguments rather than constants so that
+  // the tile code compiles exactly as in the single-grid kernels
+  int side[4];
+  double fixed[4][4];
   int* status;
   double* U_all;             // bases of the offsets in BlockDev
   const double* M_all;

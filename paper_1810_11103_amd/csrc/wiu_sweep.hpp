@@ -231,19 +231,49 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   const bool need_mid = live && k >= o0 + Traits<SC>::MLO && k < o0 + out + Traits<SC>::MHI;
 
   // Stage the states of the tile (with the boundary rule applied) in LDS,
-  // consecutive threads reading consecutive addresses.
+  // consecutive threads reading consecutive addresses.  Beyond the ends of a
+  // non-periodic line the side's rule applies: transmissive (copy of the
+  // boundary node), reflecting wall (mirror image about the boundary node,
+  // momentum along the boundary node's metric direction reversed) or a
+  // fixed state.
   {
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int k0 = o0 + R_::LO - QL;
+    constexpr int S0 = DIR == 0 ? 0 : 2;  // this direction's low side
+    // tiles whose window stays inside the line, or with no wall or fixed
+    // side at the ends it reaches, load plainly (block-uniform test)
+    const bool edge = bc_al != 0 && ((k0 < 0 && s.side[S0] != 0) || (k0 + NQ > n_al && s.side[S0 + 1] != 0));
     for (int e = tid; e < NQ * NB; e += NT) {
       const int pos = DIR == 0 ? e % NQ : e / NB;
       const int lb = DIR == 0 ? e / NQ : e % NB;
       const int ln = (DIR == 0 ? byl : bxl) * NB + lb;
       if (ln < n_ac) {
-        const int kk = bc_index(k0 + pos, n_al, bc_al);
-        const long long o = DIR == 0 ? (long long)ln * d.nx + kk : (long long)kk * d.nx + ln;
+        const int kr = k0 + pos;
+        const bool lo = kr < 0;
+        const int rule = (edge && (lo || kr >= n_al)) ? (lo ? s.side[S0] : s.side[S0 + 1]) : 0;
+        double Qv[4];
+        if (rule == 2) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sq[c][LT::qi(lb, pos)] = s.U[c * d.np + o];
+          for (int c = 0; c < 4; ++c) Qv[c] = lo ? s.fixed[S0][c] : s.fixed[S0 + 1][c];
+        } else {
+          const int kb = lo ? 0 : n_al - 1;
+          const int kk = rule == 1 ? min(max(2 * kb - kr, 0), n_al - 1) : bc_index(kr, n_al, bc_al);
+          const long long o = DIR == 0 ? (long long)ln * d.nx + kk : (long long)kk * d.nx + ln;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Qv[c] = s.U[c * d.np + o];
+          if (rule == 1) {
+            const long long mb = DIR == 0 ? (long long)(ln + GHOST) * d.mpitch + (kb + GHOST)
+                                          : (long long)(kb + GHOST) * d.mpitch + (ln + GHOST);
+            const double bx = Mk[mb], by = Mk[d.mplane + mb];
+            const double rn = rsqrt_(bx * bx + by * by);
+            const double nbx = bx * rn, nby = by * rn;
+            const double mn = Qv[1] * nbx + Qv[2] * nby;
+            Qv[1] -= 2.0 * mn * nbx;
+            Qv[2] -= 2.0 * mn * nby;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sq[c][LT::qi(lb, pos)] = Qv[c];
       }
     }
   }

@@ -32,7 +32,8 @@ KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3}
 
 class WiuGrid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
-                ("period_x", ctypes.c_double), ("period_y", ctypes.c_double)]
+                ("period_x", ctypes.c_double), ("period_y", ctypes.c_double), ("side", ctypes.c_int * 4),
+                ("fixed", (ctypes.c_double * 4) * 4)]
 
 
 class WiuBlock(ctypes.Structure):
@@ -109,10 +110,24 @@ def scheme_id(s):
     return SCHEMES[s] if isinstance(s, str) else int(s)
 
 
-def make_grid(nx, ny, bc=("periodic", "periodic"), period=(0.0, 0.0)):
+SIDES = {"transmissive": 0, "wall": 1, "fixed": 2}
+
+
+def make_grid(nx, ny, bc=("periodic", "periodic"), period=(0.0, 0.0), sides=None, fixed=None):
+    """Grid description; sides: rules of (x low, x high, y low, y high) of the
+    non-periodic directions ("transmissive", "wall", "fixed"), fixed: their
+    conservative states [4][4] for "fixed" sides."""
     bx = BC[bc[0]] if isinstance(bc[0], str) else int(bc[0])
     by = BC[bc[1]] if isinstance(bc[1], str) else int(bc[1])
-    return WiuGrid(int(nx), int(ny), bx, by, float(period[0]), float(period[1]))
+    g = WiuGrid(int(nx), int(ny), bx, by, float(period[0]), float(period[1]))
+    if sides is not None:
+        for k, v in enumerate(sides):
+            g.side[k] = SIDES[v] if isinstance(v, str) else int(v)
+    if fixed is not None:
+        for k in range(4):
+            for q in range(4):
+                g.fixed[k][q] = float(fixed[k][q])
+    return g
 
 
 VARS = {"characteristic": 0, "conservative": 1, "primitive": 2}
@@ -290,12 +305,12 @@ class Solver:
     """Device-resident grid, metrics and workspace for one WENOIU problem."""
 
     def __init__(self, x, y, scheme="5-2MP", bc=("periodic", "periodic"), period=(0.0, 0.0), params=None,
-                 device="cuda"):
+                 device="cuda", sides=None, fixed=None):
         x = torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
         y = torch.as_tensor(y, dtype=torch.float64).to(device).contiguous()
         ny, nx = x.shape
         self.scheme = scheme
-        self.grid = make_grid(nx, ny, bc, period)
+        self.grid = make_grid(nx, ny, bc, period, sides, fixed)
         self.params = params or make_params()
         self.device = device
         self.ws = workspace(self.grid, device)

@@ -94,3 +94,17 @@ def test_bad_scheme_params_and_pointers_rejected(wiu):
     assert wiu.lib.wiu_cfl_dt(ctypes.byref(g), ctypes.byref(p), dummy, dummy, ctypes.c_double(-1.0), dummy, dummy,
                               None) == wiu.WIU_EINVAL
     assert wiu.lib.wiu_strerror(wiu.WIU_EINVAL) == b"invalid argument"
+
+
+def test_side_rules_are_validated(wiu):
+    """Side rules of non-periodic directions must be 0..2 and fixed states
+    physical; periodic directions ignore them."""
+    g = wiu.make_grid(16, 12, ("transmissive", "transmissive"), sides=("wall", "fixed", 0, 0),
+                      fixed=[[1.0, 0.1, 0.0, 2.5], [1.0, 0.0, 0.0, 2.5], [0] * 4, [0] * 4])
+    assert wiu.metrics_size(g) > 0
+    g.fixed[1][0] = -1.0
+    assert wiu.metrics_size(g) == 0
+    g = wiu.make_grid(16, 12, ("transmissive", "transmissive"), sides=(0, 0, 3, 0))
+    assert wiu.metrics_size(g) == 0
+    g = wiu.make_grid(16, 12, ("periodic", "periodic"), (1.0, 1.0), sides=(3, 3, 3, 3))
+    assert wiu.metrics_size(g) > 0

@@ -67,7 +67,11 @@ def test_batched_step_equals_per_block_steps(wiu, s):
         plan.step(graph=False)
     assert plan.status() == 0
     for b in range(len(blocks)):
-        assert np.array_equal(plan.state(b).cpu().numpy(), ref[b]), b
+        # same arithmetic in two kernel families (batched and single-grid), whose
+        # compilations may contract different products into FMAs: agreement to
+        # round-off, not bit for bit
+        out = plan.state(b).cpu().numpy()
+        assert np.abs(out - ref[b]).max() <= 1e-13 * np.abs(ref[b]).max(), b
     plan.close()
 
 

@@ -99,18 +99,26 @@ WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB, OPT>& L, int tb, int 
                            bool alt, double R[4]) {
   using R_ = Range<SC>;
   using LT = SweepLds<SC, DIR, NA, NB, OPT>;
-  auto at = [&](int kk) { return LT::si(tb, kk - (o0 + R_::LO)); };      // item slot of node kk
-  auto aq = [&](int kk) { return LT::qi(tb, kk - (o0 + R_::LO) + R_::QL); };  // state slot of node kk
+  // one base slot per array at node i; the stencil's nodes are then constant
+  // offsets from it (stride 1 along a xi line, NB across eta lines)
+  constexpr int S = DIR == 0 ? 1 : NB;
+  const int hs = LT::si(tb, i - (o0 + R_::LO));
+  const int qs = LT::qi(tb, i - (o0 + R_::LO) + R_::QL);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     asm volatile("" ::: "memory");  // one component at a time (register pressure)
-    auto fp = [&](int kk) { return 0.5 * (L.sh[c][at(kk)] + lam * L.sq[c][aq(kk)]); };
-    auto fm = [&](int kk) { return 0.5 * (L.sh[c][at(kk)] - lam * L.sq[c][aq(kk)]); };
-    auto Fp = [&](int kk) { return L.sh[4 + c][at(kk)]; };
-    auto Fm = [&](int kk) { return L.sh[8 + c][at(kk)]; };
+    const double* e = &L.sh[c][hs];
+    const double* q = &L.sq[c][qs];
+    const double* gp = &L.sh[4 + c][hs];
+    const double* gm = &L.sh[8 + c][hs];
+    auto fp = [&](int kk) { return 0.5 * (e[(kk - i) * S] + lam * q[(kk - i) * S]); };
+    auto fm = [&](int kk) { return 0.5 * (e[(kk - i) * S] - lam * q[(kk - i) * S]); };
+    auto Fp = [&](int kk) { return gp[(kk - i) * S]; };
+    auto Fm = [&](int kk) { return gm[(kk - i) * S]; };
     R[c] = hflux<SC>(i, ah, fp, fm, Fp, Fm) - hflux<SC>(i - 1, ah, fp, fm, Fp, Fm);
     if constexpr (OPT) {
-      if (alt) R[c] += L.sh[12 + c][at(i)] - L.sh[12 + c][at(i - 1)];
+      const double* dd = &L.sh[12 + c][hs];
+      if (alt) R[c] += dd[0] - dd[-S];
     }
   }
 }

@@ -81,6 +81,12 @@ def lib():
         L.orc_rk3_step_vjp.argtypes = [_I, _I, _I, _I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _D, _P, _P]
         L.orc_count_rhs_flops.restype = _I
         L.orc_count_rhs_flops.argtypes = [_I, _I, _I, _I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P]
+        for f in ("orc_mb_metrics", "orc_mb_rhs", "orc_mb_rk3_step", "orc_mb_cfl_dt"):
+            getattr(L, f).restype = _I
+        L.orc_mb_metrics.argtypes = [_I, _D, _I, _P, _P, _P, _P, _P, _P]
+        L.orc_mb_rhs.argtypes = [_I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P, _P]
+        L.orc_mb_rk3_step.argtypes = [_I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P, _P]
+        L.orc_mb_cfl_dt.argtypes = [_I, _P, _P, _D, _P, _P, _P, _P, _D, _P]
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [_I]
         L.orc_get_threads.restype = _I
@@ -377,3 +383,94 @@ def adv1d_run(scheme, N, split=0, alpha=1.1, eps=1e-40, ppm=1, tend=2.0, dtpow=1
     if rc:
         raise ValueError("orc_adv1d_run failed")
     return l2.value, li.value
+
+
+# ---- multi-block grids (multiblock.hpp) -----------------------------------------
+
+SIDE_KINDS = {"transmissive": 0, "wall": 1, "fixed": 2, "interface": 3}
+
+
+def _mb_desc(blocks):
+    """Block descriptors: idesc[b] = nx, ny, bcx, bcy, side[4], nbr[4],
+    nbr_side[4]; fdesc[b] = Lx, Ly, shift[4][2], fixed[4][4]."""
+    I = np.zeros((len(blocks), 16), dtype=np.int32)
+    F = np.zeros((len(blocks), 26))
+    for b, k in enumerate(blocks):
+        ny, nx = k.x.shape
+        I[b, :4] = nx, ny, bc_id(k.bc[0]), bc_id(k.bc[1])
+        I[b, 4:8] = [SIDE_KINDS[v] if isinstance(v, str) else int(v) for v in k.sides]
+        I[b, 8:12] = k.nbr
+        I[b, 12:16] = k.nbr_side
+        F[b, :2] = k.period
+        F[b, 2:10] = np.asarray(k.shift, dtype=np.float64).reshape(8)
+        F[b, 10:26] = np.asarray(k.fixed, dtype=np.float64).reshape(16)
+    return I, F
+
+
+def _concat(arrays):
+    arrays = [_f64(a) for a in arrays]
+    off = np.zeros(len(arrays), dtype=np.int64)
+    pos = 0
+    for b, a in enumerate(arrays):
+        off[b] = pos
+        pos += a.size
+    return np.concatenate([a.ravel() for a in arrays]) if arrays else np.zeros(0), off
+
+
+def _split(flat, off, like):
+    return [flat[o:o + a.size].reshape(a.shape).copy() for o, a in zip(off, like)]
+
+
+def mb_metrics(scheme, blocks, alpha_h=1.0):
+    """Metric arrays (9, ny+2G, nx+2G) of every block, coupled through the
+    blocks' interfaces."""
+    I, F = _mb_desc(blocks)
+    X, offX = _concat([np.concatenate([_f64(k.x).ravel(), _f64(k.y).ravel()]) for k in blocks])
+    shapes = [np.zeros((9, k.x.shape[0] + 2 * G, k.x.shape[1] + 2 * G)) for k in blocks]
+    M, offM = _concat(shapes)
+    rc = lib().orc_mb_metrics(scheme_id(scheme), float(alpha_h), len(blocks), _ptr(I), _ptr(F), _ptr(X), _ptr(offX),
+                              _ptr(M), _ptr(offM))
+    if rc:
+        raise ValueError("orc_mb_metrics: invalid scheme or connectivity")
+    return _split(M, offM, shapes)
+
+
+def mb_rhs(scheme, blocks, Us, Ms, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0, split=0):
+    I, F = _mb_desc(blocks)
+    U, offU = _concat(Us)
+    M, offM = _concat(Ms)
+    out = np.zeros_like(U)
+    rc = lib().orc_mb_rhs(scheme_id(scheme), len(blocks), _ptr(I), _ptr(F), gamma, alpha, eps, ppm, vars_id(vars),
+                          float(alpha_h), weights_id(weights), split_id(split), _ptr(U), _ptr(offU), _ptr(M),
+                          _ptr(offM), _ptr(out))
+    if rc:
+        raise ValueError("orc_mb_rhs: invalid options or connectivity")
+    return _split(out, offU, Us)
+
+
+def mb_rk3_step(scheme, blocks, Us, Ms, dts, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, vars=0, alpha_h=1.0, weights=0,
+                split=0):
+    I, F = _mb_desc(blocks)
+    U, offU = _concat(Us)
+    M, offM = _concat(Ms)
+    dt = _f64(np.broadcast_to(np.asarray(dts, dtype=np.float64), (len(blocks),)))
+    rc = lib().orc_mb_rk3_step(scheme_id(scheme), len(blocks), _ptr(I), _ptr(F), gamma, alpha, eps, ppm,
+                               vars_id(vars), float(alpha_h), weights_id(weights), split_id(split), _ptr(U),
+                               _ptr(offU), _ptr(M), _ptr(offM), _ptr(dt))
+    if rc:
+        raise ValueError("orc_mb_rk3_step: invalid options or connectivity")
+    return _split(U, offU, Us)
+
+
+def mb_cfl_dt(blocks, Us, Ms, cfl, gamma=1.4):
+    """Per-block CFL time step, the minimum over each set of blocks joined
+    by interfaces."""
+    I, F = _mb_desc(blocks)
+    U, offU = _concat(Us)
+    M, offM = _concat(Ms)
+    dt = np.zeros(len(blocks))
+    rc = lib().orc_mb_cfl_dt(len(blocks), _ptr(I), _ptr(F), gamma, _ptr(U), _ptr(offU), _ptr(M), _ptr(offM),
+                             float(cfl), _ptr(dt))
+    if rc:
+        raise ValueError("orc_mb_cfl_dt: invalid connectivity")
+    return dt

@@ -6,6 +6,7 @@
 // rho v, e.  Metric arrays follow the layout documented in the header.
 // ---------------------------------------------------------------------------
 #include "wenoiu_oracle.hpp"
+#include "multiblock.hpp"
 #include "flop_count.hpp"
 #include "ad_types.hpp"
 
@@ -39,6 +40,36 @@ Params make_params(double gamma, double alpha, double eps, int ppm, int vars = 0
 }
 
 bool bad_scheme(int s) { return s < 0 || s > 7; }
+
+// Multi-block descriptors, per block: idesc[16] = nx, ny, bcx, bcy, side[4],
+// nbr[4], nbr_side[4]; fdesc[26] = Lx, Ly, shift[4][2], fixed[4][4].  X_all
+// holds block b's x at offX[b] and y right after it (nx ny values each).
+std::vector<Block> make_blocks(int nblocks, const int* idesc, const double* fdesc, const double* X_all,
+                               const long long* offX) {
+  std::vector<Block> B(nblocks);
+  for (int b = 0; b < nblocks; ++b) {
+    const int* I = idesc + 16 * b;
+    const double* F = fdesc + 26 * b;
+    B[b].g = make_grid(I[0], I[1], I[2], I[3], F[0], F[1], I + 4, F + 10);
+    for (int s = 0; s < 4; ++s) {
+      B[b].nbr[s] = I[8 + s];
+      B[b].nbr_side[s] = I[12 + s];
+      B[b].shift[s][0] = F[2 + 2 * s];
+      B[b].shift[s][1] = F[3 + 2 * s];
+    }
+    if (X_all) {
+      B[b].x = X_all + offX[b];
+      B[b].y = X_all + offX[b] + (long long)I[0] * I[1];
+    }
+  }
+  return B;
+}
+
+template <class P, class Q> std::vector<P> views(int n, Q* base, const long long* off) {
+  std::vector<P> v(n);
+  for (int b = 0; b < n; ++b) v[b] = base + off[b];
+  return v;
+}
 
 // alpha_h other than 1 exists only for the one-midpoint schemes
 bool bad_options(int s, int vars, double alpha_h, int weights, int split) {
@@ -393,6 +424,51 @@ int orc_count_rhs_flops(int scheme, int nx, int ny, int bcx, int bcy, const int*
   counts[0] = g_marks[0];
   counts[1] = g_marks[1] - g_marks[0];
   counts[2] = g_marks[2] - g_marks[1];
+  return 0;
+}
+
+// ---- multi-block grids (multiblock.hpp) ----------------------------------
+// All return 0, or -1 for an invalid scheme, option or connectivity.
+
+int orc_mb_metrics(int scheme, double alpha_h, int nblocks, const int* idesc, const double* fdesc,
+                   const double* X_all, const long long* offX, double* M_all, const long long* offM) {
+  if (bad_scheme(scheme) || (alpha_h != 1.0 && !one_midpoint(scheme))) return -1;
+  std::vector<Block> B = make_blocks(nblocks, idesc, fdesc, X_all, offX);
+  if (!mb_valid(B)) return -1;
+  for (int b = 0; b < nblocks; ++b) mb_metrics((Scheme)scheme, alpha_h, B, b, M_all + offM[b]);
+  return 0;
+}
+
+int orc_mb_rhs(int scheme, int nblocks, const int* idesc, const double* fdesc, double gamma, double alpha,
+               double eps, int ppm, int vars, double alpha_h, int weights, int split, const double* U_all,
+               const long long* offU, const double* M_all, const long long* offM, double* out_all) {
+  if (bad_options(scheme, vars, alpha_h, weights, split)) return -1;
+  std::vector<Block> B = make_blocks(nblocks, idesc, fdesc, nullptr, nullptr);
+  if (!mb_valid(B)) return -1;
+  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
+  mb_rhs<double>((Scheme)scheme, p, B, views<const double*>(nblocks, U_all, offU),
+                 views<const double*>(nblocks, M_all, offM), views<double*>(nblocks, out_all, offU));
+  return 0;
+}
+
+int orc_mb_rk3_step(int scheme, int nblocks, const int* idesc, const double* fdesc, double gamma, double alpha,
+                    double eps, int ppm, int vars, double alpha_h, int weights, int split, double* U_all,
+                    const long long* offU, const double* M_all, const long long* offM, const double* dt) {
+  if (bad_options(scheme, vars, alpha_h, weights, split)) return -1;
+  std::vector<Block> B = make_blocks(nblocks, idesc, fdesc, nullptr, nullptr);
+  if (!mb_valid(B)) return -1;
+  Params p = make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split);
+  mb_rk3_step((Scheme)scheme, p, B, views<double*>(nblocks, U_all, offU), views<const double*>(nblocks, M_all, offM),
+              dt);
+  return 0;
+}
+
+int orc_mb_cfl_dt(int nblocks, const int* idesc, const double* fdesc, double gamma, const double* U_all,
+                  const long long* offU, const double* M_all, const long long* offM, double cfl, double* dt) {
+  std::vector<Block> B = make_blocks(nblocks, idesc, fdesc, nullptr, nullptr);
+  if (!mb_valid(B)) return -1;
+  Params p = make_params(gamma, 1.1, 1e-40, 1);
+  mb_cfl_dt(p, B, views<const double*>(nblocks, U_all, offU), views<const double*>(nblocks, M_all, offM), cfl, dt);
   return 0;
 }
 

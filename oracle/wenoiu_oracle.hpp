@@ -19,6 +19,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <functional>
 #include <vector>
 #include <algorithm>
 
@@ -362,7 +363,9 @@ inline double metric_derivative(Scheme sc, double a, const double r[17]) {
 // of the boundary node), a reflecting slip wall (mirror image about the
 // boundary node with the momentum's component along the boundary's metric
 // direction reversed), or a fixed state (e.g. supersonic inflow).
-enum Side { SIDE_TRANSMISSIVE = 0, SIDE_WALL = 1, SIDE_FIXED = 2 };
+// A side of a multi-block grid may instead be an interface to another block
+// (multiblock.hpp), whose states continue the lines across it.
+enum Side { SIDE_TRANSMISSIVE = 0, SIDE_WALL = 1, SIDE_FIXED = 2, SIDE_INTERFACE = 3 };
 
 struct Grid {
   int nx, ny;
@@ -433,7 +436,8 @@ struct Coords {
 // central operator (Sec. 2.3), evaluated on coordinate differences.
 struct NodalMetric { double xix, xiy, etx, ety, jinv; };
 
-inline NodalMetric nodal_metric(Scheme sc, double a, const Coords& C, int i, int j) {
+template <class CoordSrc>
+NodalMetric nodal_metric(Scheme sc, double a, const CoordSrc& C, int i, int j) {
   long double X0, Y0;
   C.at(i, j, X0, Y0);
   double rx[17], ry[17];
@@ -472,9 +476,8 @@ struct MetricView {
 // the metrics of the wrapped node; transmissive ones evaluate them on the
 // extended coordinates.  Midpoint metrics are the interpolation of the nodal
 // ones in the same direction (Sec. 2.4, directionally consistent).
-inline void compute_metrics(Scheme sc, double alpha_h, const Grid& g, const double* x, const double* y,
-                            double* M) {
-  Coords C{g, x, y};
+template <class CoordSrc>
+void compute_metrics_from(Scheme sc, double alpha_h, const Grid& g, const CoordSrc& C, double* M) {
   const int W = g.nx + 2 * G, H = g.ny + 2 * G;
   const size_t P = (size_t)W * H;
   // Nodal metrics on a band wide enough for the midpoint interpolation.
@@ -503,6 +506,11 @@ inline void compute_metrics(Scheme sc, double alpha_h, const Grid& g, const doub
       M[7 * P + o] = interp_mid(sc, [&](int l) { return N(a, b + l).etx; });
       M[8 * P + o] = interp_mid(sc, [&](int l) { return N(a, b + l).ety; });
     }
+}
+
+inline void compute_metrics(Scheme sc, double alpha_h, const Grid& g, const double* x, const double* y,
+                            double* M) {
+  compute_metrics_from(sc, alpha_h, g, Coords{g, x, y}, M);
 }
 
 // ===========================================================================
@@ -734,7 +742,7 @@ void midpoint_flux(Scheme sc, const Params& pr, const T Qs[8][4], double kx0, do
 // the wave speed (Sec. 2.3); it is returned in *lam_out.
 // ===========================================================================
 template <class T, class QF, class KF>
-void line_residual(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_out) {
+void line_residual(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_out, const T* smax_in = nullptr) {
   auto kx = [&](int k) { return K(0, k); };
   auto ky = [&](int k) { return K(1, k); };
   auto mkx = [&](int k) { return K(2, k); };
@@ -747,6 +755,8 @@ void line_residual(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_
     T s = wave_speed(Qk, pr.gamma, kx(k), ky(k));
     if (first || s > lam) { lam = s; first = false; }
   }
+  // on a line that continues into other blocks, the maximum over all of it
+  if (smax_in) lam = *smax_in;
   lam = pr.alpha_lf * lam;
   if (lam_out) *lam_out = lam;
 
@@ -809,20 +819,32 @@ void line_residual(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_
 // U and dUdt: [4][ny][nx].  lam_xi[ny], lam_eta[nx] receive the line
 // eigenvalues when non-null.
 // ===========================================================================
+// Coupling of one block to the others of a multi-block grid: the state at
+// depth m >= 1 beyond interface side s on line `line` of the block, and the
+// maximum wave speed of each of its lines over the whole line across the
+// blocks it passes through (before the factor alpha).
+template <class T> struct Coupling {
+  std::function<T(int s, int m, int line, int q)> ghost;
+  const T* smax_xi = nullptr;   // [ny]
+  const T* smax_eta = nullptr;  // [nx]
+};
+
 template <class T>
 void rhs(Scheme sc, const Params& pr, const Grid& g, const T* U, const double* M, T* dUdt,
-         T* lam_xi = nullptr, T* lam_eta = nullptr, void (*phase_end)(int) = nullptr) {
+         T* lam_xi = nullptr, T* lam_eta = nullptr, void (*phase_end)(int) = nullptr,
+         const Coupling<T>* cp = nullptr) {
   const int nx = g.nx, ny = g.ny;
   const size_t NP = (size_t)nx * ny;
   MetricView mv{nx, ny, M};
   // State at line index k of a line of n nodes (at(m, q): node m of the line)
   // under the boundary rule: periodic wrap, or the side's rule beyond the
   // ends; kx, ky: the line direction's metric plane indices for a wall normal.
-  auto line_state = [&](int n, bool periodic, int slo, int shi, auto at, auto knode, int k, int q) -> T {
+  auto line_state = [&](int n, bool periodic, int slo, int shi, int line, auto at, auto knode, int k, int q) -> T {
     if (periodic) return at(wrap(k, n), q);
     if (k >= 0 && k < n) return at(k, q);
     const int sd = k < 0 ? slo : shi;
     const int kb = k < 0 ? 0 : n - 1;  // boundary node
+    if (g.side[sd] == SIDE_INTERFACE) return cp->ghost(sd, k < 0 ? -k : k - n + 1, line, q);
     if (g.side[sd] == SIDE_FIXED) return T(g.fixed[sd][q]);
     if (g.side[sd] == SIDE_WALL) {
       const int km = std::min(std::max(2 * kb - k, 0), n - 1);  // mirror node
@@ -843,11 +865,11 @@ void rhs(Scheme sc, const Params& pr, const Grid& g, const T* U, const double* M
     std::vector<T> R(4 * nx);
     auto at = [&](int m, int q) { return U[q * NP + (size_t)j * nx + m]; };
     auto kn = [&](int m, double& a, double& b) { a = mv(0, m, j); b = mv(1, m, j); };
-    auto Q = [&](int k, int q) { return line_state(nx, g.bcx == PERIODIC, 0, 1, at, kn, k, q); };
+    auto Q = [&](int k, int q) { return line_state(nx, g.bcx == PERIODIC, 0, 1, j, at, kn, k, q); };
     const int plane[4] = {0, 1, 5, 6};
     auto K = [&](int w, int k) { return mv(plane[w], k, j); };
     T lam;
-    line_residual<T>(sc, pr, nx, Q, K, R.data(), &lam);
+    line_residual<T>(sc, pr, nx, Q, K, R.data(), &lam, cp && cp->smax_xi ? &cp->smax_xi[j] : nullptr);
     if (lam_xi) lam_xi[j] = lam;
     for (int q = 0; q < 4; ++q)
       for (int i = 0; i < nx; ++i) Rx[q * NP + (size_t)j * nx + i] = R[q * nx + i];
@@ -859,11 +881,11 @@ void rhs(Scheme sc, const Params& pr, const Grid& g, const T* U, const double* M
     std::vector<T> R(4 * ny);
     auto at = [&](int m, int q) { return U[q * NP + (size_t)m * nx + i]; };
     auto kn = [&](int m, double& a, double& b) { a = mv(2, i, m); b = mv(3, i, m); };
-    auto Q = [&](int k, int q) { return line_state(ny, g.bcy == PERIODIC, 2, 3, at, kn, k, q); };
+    auto Q = [&](int k, int q) { return line_state(ny, g.bcy == PERIODIC, 2, 3, i, at, kn, k, q); };
     const int plane[4] = {2, 3, 7, 8};
     auto K = [&](int w, int k) { return mv(plane[w], i, k); };
     T lam;
-    line_residual<T>(sc, pr, ny, Q, K, R.data(), &lam);
+    line_residual<T>(sc, pr, ny, Q, K, R.data(), &lam, cp && cp->smax_eta ? &cp->smax_eta[i] : nullptr);
     if (lam_eta) lam_eta[i] = lam;
     for (int q = 0; q < 4; ++q)
       for (int j = 0; j < ny; ++j) Ry[q * NP + (size_t)j * nx + i] = R[q * ny + j];

@@ -295,3 +295,125 @@ def batched_blocks(nblocks=64, seed=64, h=1.0 / 512, A=0.2, nmin=64, nmax=1024, 
         U = conservative(rho, speed * np.cos(th), speed * np.sin(th), 1.0 / GAMMA)
         out.append((g, U))
     return out
+
+
+# ---- multi-block grids cut from one structured grid --------------------------
+
+SIDE_KINDS = {"transmissive": 0, "wall": 1, "fixed": 2, "interface": 3}
+
+
+@dataclass
+class MBlock:
+    """One block of a multi-block grid.  Sides are x lo, x hi, y lo, y hi;
+    side kinds index SIDE_KINDS; an "interface" side continues into side
+    nbr_side[s] of block nbr[s], whose coordinates are read shifted by
+    shift[s] (non-zero across a periodic seam only).  `src` maps each node
+    (j, i) of the block to the flat index of the node it came from in the
+    grid it was cut from (for reassembly)."""
+    x: np.ndarray
+    y: np.ndarray
+    sides: list
+    nbr: list
+    nbr_side: list
+    shift: np.ndarray
+    fixed: np.ndarray
+    src: np.ndarray
+    bc: tuple = ("transmissive", "transmissive")
+    period: tuple = (0.0, 0.0)
+
+    @property
+    def shape(self):
+        return self.x.shape
+
+
+def cut_blocks(grid, fields=(), icuts=(), jcuts=(), turns=None, sides=("transmissive",) * 4, fixed=None):
+    """Cut `grid` into (len(icuts)+1) x (len(jcuts)+1) rectangular blocks at
+    the given node indices and turn the index frame of block b by
+    90 * turns[b] degrees (a rotation, so every block stays right-handed).
+    Periodic directions of the grid become interfaces with a shift of one
+    period; its other sides take `sides` (x lo, x hi, y lo, y hi) and the
+    fixed states `fixed` [4][4].  `fields` are arrays [..., ny, nx] cut and
+    turned with the blocks.  Returns (blocks, [per-field lists of block
+    arrays])."""
+    ny, nx = grid.x.shape
+    ia = [0, *icuts, nx]
+    jc = [0, *jcuts, ny]
+    P, Q = len(ia) - 1, len(jc) - 1
+    nb = P * Q
+    turns = [0] * nb if turns is None else list(turns)
+    per = (grid.bc[0] == "periodic", grid.bc[1] == "periodic")
+    Lx, Ly = grid.period
+    fixed = np.zeros((4, 4)) if fixed is None else np.asarray(fixed, dtype=np.float64).reshape(4, 4)
+    flat = np.arange(nx * ny).reshape(ny, nx)
+    bid = lambda p, q: q * P + p
+    pieces, conn = [], []
+    for q in range(Q):
+        for p in range(P):
+            sl = (slice(jc[q], jc[q + 1]), slice(ia[p], ia[p + 1]))
+            pieces.append(sl)
+            c = []
+            # (kind, neighbour, its side, shift) for sides 0..3 of the unturned piece
+            for s, (dp, dq, other) in enumerate([(-1, 0, 1), (1, 0, 0), (0, -1, 3), (0, 1, 2)]):
+                pp, qq = p + dp, q + dq
+                sh = np.zeros(2)
+                inside = 0 <= pp < P and 0 <= qq < Q
+                if not inside and per[0 if s < 2 else 1]:
+                    if s < 2:
+                        sh[0] = -Lx if pp < 0 else Lx
+                    else:
+                        sh[1] = -Ly if qq < 0 else Ly
+                    pp, qq, inside = pp % P, qq % Q, True
+                if inside:
+                    c.append((3, bid(pp, qq), other, sh))
+                else:
+                    k = sides[s]
+                    c.append((SIDE_KINDS[k] if isinstance(k, str) else int(k), -1, 0, sh))
+            conn.append(c)
+
+    def side_nodes(a):  # flat indices on sides 0..3 of a [ny][nx] index array
+        return [set(a[:, 0].ravel()), set(a[:, -1].ravel()), set(a[0, :].ravel()), set(a[-1, :].ravel())]
+
+    # side renaming under each block's turn
+    newside = []
+    for b, sl in enumerate(pieces):
+        idx = flat[sl]
+        before = side_nodes(idx)
+        after = side_nodes(np.rot90(idx, turns[b]))
+        newside.append([after.index(before[s]) for s in range(4)])
+    blocks = []
+    for b, sl in enumerate(pieces):
+        k = turns[b]
+        src = np.ascontiguousarray(np.rot90(flat[sl], k))
+        kinds, nbr, nsd = [0] * 4, [-1] * 4, [0] * 4
+        shift = np.zeros((4, 2))
+        fx = np.zeros((4, 4))
+        for s in range(4):
+            kind, n2, s2, sh = conn[b][s]
+            t = newside[b][s]
+            kinds[t] = kind
+            if kind == 3:
+                nbr[t], nsd[t] = n2, newside[n2][s2]
+                shift[t] = sh
+            else:
+                fx[t] = fixed[s]
+        blocks.append(MBlock(x=np.ascontiguousarray(np.rot90(grid.x[sl], k)),
+                             y=np.ascontiguousarray(np.rot90(grid.y[sl], k)),
+                             sides=kinds, nbr=nbr, nbr_side=nsd, shift=shift, fixed=fx, src=src))
+    out = []
+    for f in fields:
+        f = np.asarray(f)
+        out.append([np.ascontiguousarray(np.rot90(f[(..., *sl)], turns[b], axes=(-2, -1)))
+                    for b, sl in enumerate(pieces)])
+    return blocks, out
+
+
+def assemble(blocks, arrays, shape):
+    """Inverse of cut_blocks for block arrays [..., ny_b, nx_b]: the array
+    [..., ny, nx] of the original grid."""
+    ny, nx = shape
+    lead = np.asarray(arrays[0]).shape[:-2]
+    out = np.full(lead + (ny * nx,), np.nan)
+    for blk, a in zip(blocks, arrays):
+        a = np.asarray(a)
+        out[..., blk.src.ravel()] = a.reshape(lead + (-1,))
+    return out.reshape(lead + (ny, nx))

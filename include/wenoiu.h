@@ -70,8 +70,11 @@ enum { WIU_BC_PERIODIC = 0, WIU_BC_TRANSMISSIVE = 1 };
  *   WIU_SIDE_FIXED         the conservative state wiu_grid.fixed[side]
  *                          (e.g. supersonic inflow).
  * Coordinates extend linearly beyond every non-periodic side.  The rules
- * are ignored for periodic directions. */
-enum { WIU_SIDE_TRANSMISSIVE = 0, WIU_SIDE_WALL = 1, WIU_SIDE_FIXED = 2 };
+ * are ignored for periodic directions.
+ *   WIU_SIDE_INTERFACE     (blocks of a batched plan only, wiu_block) the
+ *                          side continues into a side of another block;
+ *                          see the multi-block section below. */
+enum { WIU_SIDE_TRANSMISSIVE = 0, WIU_SIDE_WALL = 1, WIU_SIDE_FIXED = 2, WIU_SIDE_INTERFACE = 3 };
 
 #define WIU_GHOST 4
 
@@ -239,19 +242,64 @@ const char* wiu_strerror(int code);
  * device tile table, in XCD-aware order), one wave-maximum pass per step
  * serves the first stage and the eta sweeps of stages 1 and 2 accumulate the
  * next stage's line maxima; the launches of a step can be replayed as one
- * captured HIP graph.  No interface coupling between blocks is applied: each
- * block uses its own boundary rule.
+ * captured HIP graph.
  *
  * Each block's state lives in U_all at off_U (doubles, [4][ny][nx]) and its
- * metrics, computed beforehand with wiu_metrics for the same scheme, in M_all
- * at off_M (doubles, wiu_metrics_size() bytes).  The plan binds these
- * pointers, owns its device tables and scratch (allocated when the plan is
- * created, freed by wiu_plan_destroy) and a per-block time step. */
+ * metrics in M_all at off_M (doubles, wiu_metrics_size() bytes), computed
+ * beforehand for the same scheme: with wiu_metrics for a block without
+ * interfaces, with wiu_blocks_metrics for a grid whose blocks are coupled.
+ * The plan binds these pointers, owns its device tables and scratch
+ * (allocated when the plan is created, freed by wiu_plan_destroy) and a
+ * per-block time step.
+ *
+ * Sides of non-periodic directions (x low, x high, y low, y high) take the
+ * rules of wiu_grid (side, fixed; zero-initialised fields give transmissive
+ * sides) or WIU_SIDE_INTERFACE: the paper motivates its schemes with
+ * multi-block grids (Sec. 1) but defines no coupling; the library's rule is
+ * that the block's lines continue into the neighbour.  Blocks are
+ * right-handed; side s of block b abuts side nbr_side[s] of block nbr[s]
+ * (which points back), both with the same number of nodes, and the
+ * neighbour is at least WIU_MB_REACH nodes deep across that side.  Along a
+ * side a node has a position counted counterclockwise around its block;
+ * the two sides meet with those orders opposed (position t is the
+ * neighbour's n - 1 - t), and ghost layer m >= 1 is the neighbour's node
+ * layer m - 1 (no overlap).  Then
+ *   - states beyond the side are the neighbour's (of the same RK stage);
+ *   - coordinates beyond it are the neighbour's plus shift[s] (non-zero
+ *     across a periodic seam only; the neighbour's shift is its negative),
+ *     so both blocks evaluate their metrics on one coordinate field
+ *     (free-stream preservation and conservation across the interface);
+ *     at a corner the interface of the x direction is crossed first;
+ *   - the Lax-Friedrichs eigenvalue of a line (Sec. 2.3) is the maximum over
+ *     the whole line through every block it crosses;
+ *   - wiu_batched_cfl_dt gives every set of blocks joined by interfaces its
+ *     smallest step (steps set from the host must agree within a set).
+ * A plan that violates these rules is rejected with WIU_EINVAL. */
+#define WIU_MB_REACH 15
 typedef struct {
   int nx, ny, bc_x, bc_y;
   double period_x, period_y;
   long long off_U, off_M;
+  int side[4];          /* WIU_SIDE_* of x low, x high, y low, y high */
+  int nbr[4];           /* WIU_SIDE_INTERFACE: neighbour block index */
+  int nbr_side[4];      /* WIU_SIDE_INTERFACE: the neighbour's side (0..3) */
+  double shift[4][2];   /* WIU_SIDE_INTERFACE: added to the neighbour's (x, y) */
+  double fixed[4][4];   /* WIU_SIDE_FIXED: conservative state */
+  long long off_X;      /* wiu_blocks_metrics: x at X_all + off_X, y right after (nx ny doubles each) */
 } wiu_block;
+
+/* Metrics of every block of a multi-block grid (nine planes with ghost band
+ * and tag per block, as wiu_metrics; Secs. 2.2-2.4 and the scheme's central
+ * operator) on the coupled coordinates described above.  X_all: device
+ * coordinates at each block's off_X; M_all: output at each block's off_M;
+ * work: device scratch of wiu_blocks_metrics_work_size() bytes, caller-owned.
+ * Asynchronous on `stream` except that the block table is copied to `work`
+ * synchronously.  Returns WIU_EINVAL for an invalid block set, scheme or
+ * parameter; folded cells latch WIU_ST_JACOBIAN in the status word at the
+ * start of `work` (read it with wiu_status(work, ...)). */
+size_t wiu_blocks_metrics_work_size(const wiu_block* blocks, int nblocks, int scheme);
+int wiu_blocks_metrics(const wiu_block* blocks, int nblocks, int scheme, const wiu_params* p, const double* X_all,
+                       double* M_all, void* work, wiu_stream_t stream);
 
 typedef struct wiu_plan wiu_plan;
 

@@ -2,6 +2,7 @@
 // C ABI entry points declared in include/wenoiu.h.
 #include "wenoiu.h"
 #include "wiu_kernels.hpp"
+#include "wiu_mb.hpp"
 
 #include <new>
 #include <vector>
@@ -26,6 +27,11 @@ struct wiu_plan {
   double* U_all = nullptr;        // caller's states and metrics (offsets in the block table)
   const double* M_all = nullptr;
   int* d_status = nullptr;
+  // groups of line maxima joined through interfaces (lines crossing blocks,
+  // and the CFL maxima of blocks joined into one set): offsets into d_lam
+  int* d_gstart = nullptr;
+  int* d_gmem = nullptr;
+  int ngroups = 0;
   // captured step
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -36,26 +42,87 @@ namespace {
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
-bool block_ok(const wiu_block& b) {
-  if (b.nx < 1 || b.ny < 1) return false;
-  if (b.bc_x < 0 || b.bc_x > 1 || b.bc_y < 0 || b.bc_y > 1) return false;
-  if (b.bc_x == WIU_BC_TRANSMISSIVE && b.nx < 2) return false;
-  if (b.bc_y == WIU_BC_TRANSMISSIVE && b.ny < 2) return false;
-  if (b.bc_x == WIU_BC_PERIODIC && !(b.period_x > 0.0)) return false;
-  if (b.bc_y == WIU_BC_PERIODIC && !(b.period_y > 0.0)) return false;
-  if (b.off_U < 0 || b.off_M < 0) return false;
-  if (b.ny > 65535 * 4 || b.nx > (1 << 28)) return false;
+// Ghost layer m >= 1 on line l beyond interface side s of block b, as an
+// element offset g0 + m gm + l gl in the neighbour's state planes (an affine
+// map: the side frames are).  False if some layer 1 <= m < WIU_MB_REACH of
+// some line would fall outside the neighbour.
+bool ghost_map(const wiu_block* blocks, int b, int s, long long& g0, long long& gm, long long& gl) {
+  const wiu_block& k = blocks[b];
+  const wiu_block& h = blocks[k.nbr[s]];
+  auto off = [&](int m, int l) {
+    int a, c, a2, c2;
+    if (s == 0) { a = -m; c = l; }
+    else if (s == 1) { a = k.nx - 1 + m; c = l; }
+    else if (s == 2) { a = l; c = -m; }
+    else { a = l; c = k.ny - 1 + m; }
+    mb_through(s, k.nx, k.ny, k.nbr_side[s], h.nx, h.ny, a, c, a2, c2);
+    if (a2 < 0 || a2 >= h.nx || c2 < 0 || c2 >= h.ny) return -1LL;
+    return (long long)c2 * h.nx + a2;
+  };
+  const int n = mb_side_len(s, k.nx, k.ny), mmax = WIU_MB_REACH - 1;
+  gm = off(2, 0) - off(1, 0);
+  gl = n > 1 ? off(1, 1) - off(1, 0) : 0;
+  g0 = off(1, 0) - gm;
+  for (int m : {1, mmax})
+    for (int l : {0, n - 1}) {
+      const long long o = off(m, l);
+      if (o < 0 || o != g0 + m * gm + l * gl) return false;
+    }
   return true;
 }
 
-Dims dims_of(const wiu_block& b) {
-  Dims d;
-  d.nx = b.nx; d.ny = b.ny; d.bcx = b.bc_x; d.bcy = b.bc_y;
-  d.mpitch = b.nx + 2 * GHOST;
-  d.mplane = (long long)(b.nx + 2 * GHOST) * (b.ny + 2 * GHOST);
-  d.np = (long long)b.nx * b.ny;
-  d.Lx = b.period_x; d.Ly = b.period_y;
-  return d;
+int uf_root(std::vector<int>& p, int v) {
+  while (p[v] != v) { p[v] = p[p[v]]; v = p[v]; }
+  return v;
+}
+
+// Groups of line maxima to be joined (only groups of two or more): the
+// lines that continue through interfaces, and the CFL maxima of the blocks
+// of each set joined by interfaces.  Uploaded to the plan.
+bool line_groups(const wiu_block* blocks, int n, const std::vector<size_t>& off_lam, wiu_plan* p) {
+  const int total = (int)(off_lam[n - 1] + blocks[n - 1].nx + blocks[n - 1].ny + 1);
+  std::vector<int> par(total);
+  for (int v = 0; v < total; ++v) par[v] = v;
+  auto join = [&](int u, int v) {
+    u = uf_root(par, u); v = uf_root(par, v);
+    if (u != v) par[u] = v;
+  };
+  // line through node (a, c) normal to side s: xi line (row c) or eta line (column a)
+  auto line_of = [&](int b, int s, int a, int c) { return (int)off_lam[b] + (s < 2 ? c : blocks[b].ny + a); };
+  auto cfl_of = [&](int b) { return (int)off_lam[b] + blocks[b].ny + blocks[b].nx; };
+  bool any = false;
+  for (int b = 0; b < n; ++b)
+    for (int s = 0; s < 4; ++s) {
+      const wiu_block& k = blocks[b];
+      if ((s < 2 ? k.bc_x : k.bc_y) == WIU_BC_PERIODIC || k.side[s] != WIU_SIDE_INTERFACE) continue;
+      const wiu_block& h = blocks[k.nbr[s]];
+      const int len = mb_side_len(s, k.nx, k.ny);
+      for (int t = 0; t < len; ++t) {
+        int a, c, a2, c2;
+        mb_side_node(s, k.nx, k.ny, t, 0, a, c);
+        mb_side_node(k.nbr_side[s], h.nx, h.ny, len - 1 - t, 0, a2, c2);
+        join(line_of(b, s, a, c), line_of(k.nbr[s], k.nbr_side[s], a2, c2));
+      }
+      join(cfl_of(b), cfl_of(k.nbr[s]));
+      any = true;
+    }
+  if (!any) return true;
+  std::vector<std::vector<int>> members(total);
+  for (int v = 0; v < total; ++v) members[uf_root(par, v)].push_back(v);
+  std::vector<int> start{0}, mem;
+  for (int v = 0; v < total; ++v)
+    if (members[v].size() > 1) {
+      mem.insert(mem.end(), members[v].begin(), members[v].end());
+      start.push_back((int)mem.size());
+    }
+  p->ngroups = (int)start.size() - 1;
+  if (p->ngroups == 0) return true;
+  // one allocation: starts, then members
+  const size_t bytes = sizeof(int) * (start.size() + mem.size());
+  if (hipMalloc(&p->d_gstart, bytes) != hipSuccess) return false;
+  p->d_gmem = p->d_gstart + start.size();
+  return hipMemcpy(p->d_gstart, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(p->d_gmem, mem.data(), sizeof(int) * mem.size(), hipMemcpyHostToDevice) == hipSuccess;
 }
 
 void free_plan(wiu_plan* p) {
@@ -65,6 +132,7 @@ void free_plan(wiu_plan* p) {
   if (p->d_blocks) hipFree(p->d_blocks);
   if (p->d_tiles) hipFree(p->d_tiles);
   if (p->d_ws) hipFree(p->d_ws);
+  if (p->d_gstart) hipFree(p->d_gstart);
   delete p;
 }
 
@@ -77,10 +145,6 @@ BatchArgs base_args(const wiu_plan* p) {
   a.gamma = p->params.gamma; a.alpha = p->params.alpha_lf; a.eps = p->params.eps; a.ppm = p->params.ppm;
   a.vars = p->params.vars; a.ah = p->params.alpha_h;
   a.weights = p->params.weights; a.split = p->params.split;
-  for (int k = 0; k < 4; ++k) {  // blocks have periodic or transmissive sides
-    a.side[k] = WIU_SIDE_TRANSMISSIVE;
-    for (int c = 0; c < 4; ++c) a.fixed[k][c] = 0.0;
-  }
   a.status = p->d_status;
   a.U_all = p->U_all;
   a.M_all = p->M_all;
@@ -101,6 +165,7 @@ int launch_step(wiu_plan* p, hipStream_t st) {
       if (launch_fill_u64(p->d_lam, p->lam_len, st) != hipSuccess) return WIU_EHIP;
       a.tiles = p->d_tiles + p->n_xi + p->n_eta; a.ntiles = p->n_wm;
       if (launch_batched_wave_max(a, st) != hipSuccess) return WIU_EHIP;
+      if (launch_group_max(p->d_lam, p->d_gstart, p->d_gmem, p->ngroups, st) != hipSuccess) return WIU_EHIP;
     }
     a.tiles = p->d_tiles; a.ntiles = p->n_xi;
     if (launch_batched_sweep(p->scheme, 0, p->variant[0], a, st) != hipSuccess) return WIU_EHIP;
@@ -108,6 +173,9 @@ int launch_step(wiu_plan* p, hipStream_t st) {
       return WIU_EHIP;
     a.tiles = p->d_tiles + p->n_xi; a.ntiles = p->n_eta;
     if (launch_batched_sweep(p->scheme, 1, p->variant[1], a, st) != hipSuccess) return WIU_EHIP;
+    if (stage < 2 &&
+        launch_group_max(stage == 0 ? p->d_lam2 : p->d_lam, p->d_gstart, p->d_gmem, p->ngroups, st) != hipSuccess)
+      return WIU_EHIP;
   }
   return WIU_OK;
 }
@@ -129,8 +197,7 @@ int wiu_batched_plan(const wiu_block* blocks, int nblocks, int scheme, const wiu
   if (params->alpha_h != 1.0 && scheme != WIU_3_1MP && scheme != WIU_5_1MP && scheme != WIU_7_1MP) return WIU_EINVAL;
   if (xi_variant < 0 || xi_variant >= wiu_tuning_variants(0)) return WIU_EINVAL;
   if (eta_variant < 0 || eta_variant >= wiu_tuning_variants(1)) return WIU_EINVAL;
-  for (int b = 0; b < nblocks; ++b)
-    if (!block_ok(blocks[b])) return WIU_EINVAL;
+  if (!mb_blocks_ok(blocks, nblocks)) return WIU_EINVAL;
 
   wiu_plan* p = new (std::nothrow) wiu_plan();
   if (!p) return WIU_EINVAL;
@@ -178,7 +245,7 @@ int wiu_batched_plan(const wiu_block* blocks, int nblocks, int scheme, const wiu
   std::vector<BlockDev> hb(nblocks);
   for (int b = 0; b < nblocks; ++b) {
     BlockDev& B = hb[b];
-    B.d = dims_of(blocks[b]);
+    B.d = mb_dims(blocks[b]);
     B.oU = blocks[b].off_U;
     B.oM = blocks[b].off_M;
     const size_t plane4 = align_up(4 * (size_t)blocks[b].nx * blocks[b].ny * 8);
@@ -188,7 +255,19 @@ int wiu_batched_plan(const wiu_block* blocks, int nblocks, int scheme, const wiu
     B.oDt = (long long)(dt_pos / 8) + b;
     B.oLam = (long long)off_lam[b];
     B.oLam2 = (long long)((lam2_pos - lam_pos) / 8 + off_lam[b]);
+    for (int s = 0; s < 4; ++s) {
+      const bool per = (s < 2 ? blocks[b].bc_x : blocks[b].bc_y) == WIU_BC_PERIODIC;
+      B.side[s] = per ? WIU_SIDE_TRANSMISSIVE : blocks[b].side[s];
+      B.nbr[s] = 0;
+      B.g0[s] = B.gm[s] = B.gl[s] = 0;
+      for (int c = 0; c < 4; ++c) B.fixed[s][c] = blocks[b].fixed[s][c];
+      if (B.side[s] == WIU_SIDE_INTERFACE) {
+        B.nbr[s] = blocks[b].nbr[s];
+        if (!ghost_map(blocks, b, s, B.g0[s], B.gm[s], B.gl[s])) { free_plan(p); return WIU_EINVAL; }
+      }
+    }
   }
+  if (!line_groups(blocks, nblocks, off_lam, p)) { free_plan(p); return WIU_EHIP; }
   // tile tables, block by block (so each XCD's contiguous range stays local)
   std::vector<int4> tx, te, tw;
   const int extra = scheme_extra(scheme);
@@ -262,6 +341,7 @@ int wiu_batched_cfl_dt(wiu_plan* p, double cfl, wiu_stream_t stream) {
   a.ntiles = p->n_wm;
   if (launch_fill_u64(p->d_lam, p->lam_len, st) != hipSuccess) return WIU_EHIP;
   if (launch_batched_wave_max(a, st) != hipSuccess) return WIU_EHIP;
+  if (launch_group_max(p->d_lam, p->d_gstart, p->d_gmem, p->ngroups, st) != hipSuccess) return WIU_EHIP;
   return launch_batched_cfl_dt(a, p->nblocks, cfl, st) == hipSuccess ? WIU_OK : WIU_EHIP;
 }
 

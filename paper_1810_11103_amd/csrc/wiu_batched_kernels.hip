@@ -48,11 +48,22 @@ __global__ void __launch_bounds__(NA * NB, (sweep_waves<SC, OPT>())) batched_swe
     s.nlam_xi = nlam; s.nlam_eta = nlam ? nlam + s.d.ny : nullptr;
     s.gamma = b.gamma; s.alpha = b.alpha; s.eps = b.eps; s.ppm = b.ppm; s.vars = b.vars; s.ah = b.ah;
     s.weights = b.weights; s.split = b.split;
+    // the block's side rules; an interface reads the neighbour's state of
+    // the same stage
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      s.side[k] = b.side[k];
+      s.side[k] = ufirst(B.side[k]);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) s.fixed[k][c] = b.fixed[k][c];
+      for (int c = 0; c < 4; ++c) s.fixed[k][c] = ufirst(B.fixed[k][c]);
+    }
+#pragma unroll
+    for (int k = 2 * DIR; k < 2 * DIR + 2; ++k) {
+      if (s.side[k] == WIU_SIDE_INTERFACE) {
+        const BlockDev& N = b.blocks[ufirst(B.nbr[k])];
+        s.nbU[k] = stage_src(b, N, st);
+        s.nbnp[k] = ufirst(N.d.np);
+        s.g0[k] = ufirst(B.g0[k]); s.gm[k] = ufirst(B.gm[k]); s.gl[k] = ufirst(B.gl[k]);
+      }
     }
     s.Rxi = b.ws + ufirst(B.oRxi); s.U0 = b.U_all + ufirst(B.oU); s.dt = b.ws + ufirst(B.oDt);
     s.status = b.status;

@@ -32,6 +32,14 @@ constexpr int ST_JACOBIAN = 1, ST_NONPHYS = 2, ST_SCHEME = 4, ST_ARGMAX = 8;
 
 // Map a line index onto the grid: wrap for periodic lines, clamp (copy of the
 // boundary node) for transmissive ones.  Loops run at most halo/n times.
+// Error-free sum (Knuth's TwoSum): a + b = s + e exactly.
+WIU_DEV void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  double bb = s - a;
+  double aa = s - bb;
+  e = (a - aa) + (b - bb);
+}
+
 WIU_DEV int bc_index(int k, int n, int bc) {
   if (bc == 0) {
     while (k < 0) k += n;

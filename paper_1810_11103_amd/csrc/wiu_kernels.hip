@@ -20,14 +20,6 @@ namespace wiu {
 // keeps full relative accuracy on large or offset domains.
 // ===========================================================================
 
-// Error-free sum (Knuth's TwoSum): a + b = s + e exactly.
-WIU_DEV void two_sum(double a, double b, double& s, double& e) {
-  s = a + b;
-  double bb = s - a;
-  double aa = s - bb;
-  e = (a - aa) + (b - bb);
-}
-
 // c[i1] - c[i0] + k L with i0, i1 inside [0, n): when the shift is non-zero
 // the difference of the stored values is close to -k L and is corrected
 // without rounding at the size of L.
@@ -105,10 +97,6 @@ WIU_DEV double diff_j(const Dims& d, const double* c, bool is_y, int a, int b1, 
 // - 245 g_{i-1} + 1225 g_i + 1225 g_{i+1} - 245 g_{i+2} + 49 g_{i+3} -
 // 5 g_{i+4}) / 2048 -- is an antisymmetric node stencil
 // sum_m d_m (g_{i+m} - g_{i-m}), m = 1..7 (exact rationals):
-constexpr int METRIC_REACH = 7;
-struct MetricStencil {
-  double d[METRIC_REACH];
-};
 const double kMetricStencil[8][METRIC_REACH] = {
     {557.0 / 768.0, -25.0 / 192.0, 3.0 / 256.0, 0.0, 0.0, 0.0, 0.0},                   // 3-1MP
     {1145.0 / 1536.0, -229.0 / 1536.0, 29.0 / 1536.0, -1.0 / 1024.0, 0.0, 0.0, 0.0},    // 3-2MP
@@ -142,7 +130,7 @@ MetricStencil metric_stencil(int scheme, double a) {
 
 // Nodal-metric band beyond the stored ghost band: the reach of the midpoint
 // interpolation (3 for six points, 4 for eight).
-inline int metric_band(int scheme) { return GHOST + (scheme >= 4 ? 4 : 3); }
+int metric_band(int scheme) { return GHOST + (scheme >= 4 ? 4 : 3); }
 
 // Nodal metrics on the band of width B around the grid: T[5][(ny+2B)(nx+2B)].
 // Periodic directions evaluate at the wrapped node so that band copies are
@@ -359,6 +347,14 @@ hipError_t launch_metrics(const Dims& d, int scheme, double ah, const double* x,
   dim3 b1(64, 4);
   dim3 g1((d.nx + 2 * B + 63) / 64, (d.ny + 2 * B + 3) / 4);
   hipLaunchKernelGGL(metrics_nodal_kernel, g1, b1, 0, st, d, metric_stencil(scheme, ah), B, x, y, T);
+  dim3 g2((d.nx + 2 * GHOST + 63) / 64, (d.ny + 2 * GHOST + 3) / 4);
+  hipLaunchKernelGGL(metrics_band_kernel, g2, b1, 0, st, d, scheme, ah, B, T, M, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_metrics_band(const Dims& d, int scheme, double ah, int B, const double* T, double* M, int* status,
+                               hipStream_t st) {
+  dim3 b1(64, 4);
   dim3 g2((d.nx + 2 * GHOST + 63) / 64, (d.ny + 2 * GHOST + 3) / 4);
   hipLaunchKernelGGL(metrics_band_kernel, g2, b1, 0, st, d, scheme, ah, B, T, M, status);
   return hipGetLastError();

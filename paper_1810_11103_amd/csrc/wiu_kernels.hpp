@@ -1,6 +1,7 @@
 // Kernel launch interface of libwenoiu (internal to the library).
 #pragma once
 
+#include "wenoiu.h"
 #include "wiu_device.hpp"
 
 namespace wiu {
@@ -25,9 +26,13 @@ struct SweepArgs {
   int weights;                          // WIU_WEIGHTS_*
   int split;                            // WIU_SPLIT_* of the leading midpoint flux
   // rules beyond the sides of non-periodic directions (x lo, x hi, y lo,
-  // y hi): 0 transmissive, 1 reflecting wall, 2 fixed state `fixed`
+  // y hi): 0 transmissive, 1 reflecting wall, 2 fixed state `fixed`,
+  // 3 interface (batched blocks): ghost layer m (1 <= m < WIU_MB_REACH) of
+  // line l is nbU[side][c * nbnp[side] + g0 + m gm + l gl]
   int side[4];
   double fixed[4][4];
+  const double* nbU[4];
+  long long nbnp[4], g0[4], gm[4], gl[4];
   // 0 (xi) write R^xi; 1 (eta) dU/dt = -(R^xi + R^eta)/J^{-1};
   // 3 (xi) write P = ca U0 + cb (U - dt R^xi/J^{-1}) into the R^xi buffer;
   // 2 (eta) RK stage U_out = P - cb dt R^eta/J^{-1}
@@ -53,6 +58,12 @@ struct BlockDev {
   long long oU, oM;              // state in U_all, metrics in M_all
   long long oRxi, oU1, oU2, oDt; // R^xi / partial stage update, stage states, dt: in ws
   long long oLam, oLam2;         // two sets of line maxima (lam_xi[ny], lam_eta[nx], cfl[1]) in lam
+  // sides of non-periodic directions: rule (WIU_SIDE_*), fixed states, and
+  // for interfaces the neighbour block and the affine map of ghost layer m
+  // on line l to the neighbour's node, g0 + m gm + l gl
+  int side[4], nbr[4];
+  long long g0[4], gm[4], gl[4];
+  double fixed[4][4];
 };
 
 struct BatchArgs {
@@ -65,11 +76,6 @@ struct BatchArgs {
   int vars;                  // interpolation variables (WIU_VARS_*)
   double ah;                 // free parameter of the one-midpoint schemes
   int weights, split;        // WIU_WEIGHTS_*, WIU_SPLIT_*
-  // side rules for the sweeps: batched blocks have periodic or transmissive
-  // sides only (all zero), passed as arguments rather than constants so that
-  // the tile code compiles exactly as in the single-grid kernels
-  int side[4];
-  double fixed[4][4];
   int* status;
   double* U_all;             // bases of the offsets in BlockDev
   const double* M_all;
@@ -124,6 +130,22 @@ hipError_t launch_wave_max(const Dims& d, const double* U, const double* M, doub
                            unsigned long long* le, unsigned long long* cfl, int* status, hipStream_t st);
 hipError_t launch_metrics(const Dims& d, int scheme, double ah, const double* x, const double* y, double* M,
                           double* T, int* status, hipStream_t st);
+// Central metric operator of a scheme as an antisymmetric node stencil
+// sum_m d_m (g_{i+m} - g_{i-m}), m = 1..METRIC_REACH, and the width of the
+// nodal-metric band the midpoint interpolation needs.
+constexpr int METRIC_REACH = 7;
+struct MetricStencil {
+  double d[METRIC_REACH];
+};
+MetricStencil metric_stencil(int scheme, double a);
+int metric_band(int scheme);
+// Stored metrics (nodal and midpoint planes with ghost band, tag) from the
+// nodal metrics T[5] on a band of width B.
+hipError_t launch_metrics_band(const Dims& d, int scheme, double ah, int B, const double* T, double* M, int* status,
+                               hipStream_t st);
+// Maximum over each group of line maxima (lam[mem[start[g] .. start[g+1])]),
+// written back to every member.
+hipError_t launch_group_max(unsigned long long* lam, const int* start, const int* mem, int ngroups, hipStream_t st);
 hipError_t launch_cfl_dt(const unsigned long long* cfl_max, double cfl, double* dt, hipStream_t st);
 hipError_t launch_lambda_out(const Dims& d, double alpha, const unsigned long long* lx, const unsigned long long* le,
                              double* ox, double* oe, hipStream_t st);

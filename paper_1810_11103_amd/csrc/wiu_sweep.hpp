@@ -242,8 +242,8 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   // consecutive threads reading consecutive addresses.  Beyond the ends of a
   // non-periodic line the side's rule applies: transmissive (copy of the
   // boundary node), reflecting wall (mirror image about the boundary node,
-  // momentum along the boundary node's metric direction reversed) or a
-  // fixed state.
+  // momentum along the boundary node's metric direction reversed), a fixed
+  // state, or an interface (the neighbouring block's nodes).
   {
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int k0 = o0 + R_::LO - QL;
@@ -263,6 +263,14 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
         if (rule == 2) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) Qv[c] = lo ? s.fixed[S0][c] : s.fixed[S0 + 1][c];
+        } else if (rule == 3) {
+          // interface: the neighbour's node; layers deeper than any stencil
+          // reaches are clamped (staged but never used)
+          const int sd = lo ? S0 : S0 + 1;
+          const int m = min(lo ? -kr : kr - n_al + 1, WIU_MB_REACH - 1);
+          const long long o = s.g0[sd] + m * s.gm[sd] + ln * s.gl[sd];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Qv[c] = s.nbU[sd][c * s.nbnp[sd] + o];
         } else {
           const int kb = lo ? 0 : n_al - 1;
           const int kk = rule == 1 ? min(max(2 * kb - kr, 0), n_al - 1) : bc_index(kr, n_al, bc_al);

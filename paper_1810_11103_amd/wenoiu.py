@@ -24,7 +24,8 @@ EXPORTS = [
     "wiu_line_eigenvalues", "wiu_rhs", "wiu_cfl_dt", "wiu_rk3_step", "wiu_status", "wiu_strerror",
     "wiu_profile_enable", "wiu_profile_read", "wiu_tuning_variants", "wiu_set_tuning", "wiu_get_tuning",
     "wiu_batched_plan", "wiu_batched_info", "wiu_batched_set_dt", "wiu_batched_cfl_dt", "wiu_batched_get_dt",
-    "wiu_batched_rk3_step", "wiu_batched_status", "wiu_plan_destroy",
+    "wiu_batched_rk3_step", "wiu_batched_status", "wiu_plan_destroy", "wiu_blocks_metrics_work_size",
+    "wiu_blocks_metrics",
     "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl", "wiu_step_record_bytes",
 ]
 KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3}
@@ -39,7 +40,10 @@ class WiuGrid(ctypes.Structure):
 class WiuBlock(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
                 ("period_x", ctypes.c_double), ("period_y", ctypes.c_double),
-                ("off_U", ctypes.c_longlong), ("off_M", ctypes.c_longlong)]
+                ("off_U", ctypes.c_longlong), ("off_M", ctypes.c_longlong),
+                ("side", ctypes.c_int * 4), ("nbr", ctypes.c_int * 4), ("nbr_side", ctypes.c_int * 4),
+                ("shift", (ctypes.c_double * 2) * 4), ("fixed", (ctypes.c_double * 4) * 4),
+                ("off_X", ctypes.c_longlong)]
 
 
 class WiuParams(ctypes.Structure):
@@ -71,6 +75,8 @@ def _load():
         "wiu_strerror": (ctypes.c_char_p, [I]),
         "wiu_profile_enable": (I, [I]),
         "wiu_batched_plan": (I, [ctypes.POINTER(WiuBlock), I, I, PR, I, I, P, P, ctypes.POINTER(P)]),
+        "wiu_blocks_metrics_work_size": (ctypes.c_size_t, [ctypes.POINTER(WiuBlock), I, I]),
+        "wiu_blocks_metrics": (I, [ctypes.POINTER(WiuBlock), I, I, PR, P, P, P, P]),
         "wiu_batched_info": (I, [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "wiu_batched_set_dt": (I, [P, P, P]),
         "wiu_batched_cfl_dt": (I, [P, ctypes.c_double, P]),
@@ -110,7 +116,7 @@ def scheme_id(s):
     return SCHEMES[s] if isinstance(s, str) else int(s)
 
 
-SIDES = {"transmissive": 0, "wall": 1, "fixed": 2}
+SIDES = {"transmissive": 0, "wall": 1, "fixed": 2, "interface": 3}
 
 
 def make_grid(nx, ny, bc=("periodic", "periodic"), period=(0.0, 0.0), sides=None, fixed=None):
@@ -380,9 +386,13 @@ class Solver:
 
 
 class BatchedPlan:
-    """Many independent blocks stepped together (wiu_batched_*).
+    """Many blocks stepped together (wiu_batched_*).
 
-    blocks: list of (x, y, bc, period) node-coordinate arrays per block.
+    blocks: either (x, y, bc, period) node-coordinate arrays per block
+    (independent blocks, each with its own boundary rule), or objects with
+    attributes x, y, bc, period, sides, nbr, nbr_side, shift, fixed (a
+    multi-block grid: per-side rules, "interface" sides coupling the blocks
+    as stated with wiu_block in wenoiu.h; metrics from wiu_blocks_metrics).
     U_all and M_all are flat device tensors owned here; block b's state is
     U_all[off_U[b] : off_U[b] + 4 ny nx] viewed as (4, ny, nx)."""
 
@@ -391,29 +401,58 @@ class BatchedPlan:
         self.params = params or make_params()
         self.device = device
         self.shapes = []
+        self.coupled = any(hasattr(b, "sides") for b in blocks)
         descs = []
-        offU = offM = 0
-        for (x, y, bc, period) in blocks:
+        offU = offM = offX = 0
+        for blk in blocks:
+            x, y, bc, period = (blk.x, blk.y, blk.bc, blk.period) if self.coupled else blk
             ny, nx = x.shape
             g = make_grid(nx, ny, bc, period)
-            descs.append(WiuBlock(nx, ny, g.bc_x, g.bc_y, g.period_x, g.period_y, offU, offM))
+            d = WiuBlock(nx, ny, g.bc_x, g.bc_y, g.period_x, g.period_y, offU, offM)
+            if self.coupled:
+                for s_ in range(4):
+                    v = blk.sides[s_]
+                    d.side[s_] = SIDES[v] if isinstance(v, str) else int(v)
+                    d.nbr[s_] = int(blk.nbr[s_])
+                    d.nbr_side[s_] = int(blk.nbr_side[s_])
+                    for c in range(2):
+                        d.shift[s_][c] = float(blk.shift[s_][c])
+                    for q in range(4):
+                        d.fixed[s_][q] = float(blk.fixed[s_][q])
+                d.off_X = offX
+                offX += 2 * nx * ny
+            descs.append(d)
             self.shapes.append((ny, nx))
             offU += 4 * nx * ny
             offM += metrics_size(g) // 8
         self.off_U = [d.off_U for d in descs]
         self.U_all = torch.zeros(offU, dtype=torch.float64, device=device)
         self.M_all = torch.zeros(offM, dtype=torch.float64, device=device)
-        # metrics of every block with the single-grid entry point (one-time)
-        for d, (x, y, bc, period) in zip(descs, blocks):
-            g = make_grid(d.nx, d.ny, bc, period)
-            ws = workspace(g, device)
-            xx = torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
-            yy = torch.as_tensor(y, dtype=torch.float64).to(device).contiguous()
-            Mb = self.M_all[d.off_M: d.off_M + metrics_size(g) // 8]
-            metrics(g, scheme, xx, yy, Mb, ws, params=self.params)
-            if status(ws):
-                raise WiuError("metrics reported a folded cell")
         self._descs = (WiuBlock * len(descs))(*descs)
+        if self.coupled:
+            # metrics of all blocks on their coupled coordinates (one-time)
+            X = torch.cat([torch.as_tensor(a, dtype=torch.float64).reshape(-1)
+                           for blk in blocks for a in (blk.x, blk.y)]).to(device).contiguous()
+            n = lib.wiu_blocks_metrics_work_size(self._descs, len(descs), scheme_id(scheme))
+            if n == 0:
+                raise WiuError("invalid multi-block grid")
+            work = torch.zeros(n, dtype=torch.uint8, device=device)
+            _check(lib.wiu_blocks_metrics(self._descs, len(descs), scheme_id(scheme), ctypes.byref(self.params),
+                                          ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(self.M_all.data_ptr()),
+                                          ctypes.c_void_p(work.data_ptr()), _stream()))
+            if status(work):
+                raise WiuError("metrics reported a folded cell")
+        else:
+            # metrics of every block with the single-grid entry point (one-time)
+            for d, (x, y, bc, period) in zip(descs, blocks):
+                g = make_grid(d.nx, d.ny, bc, period)
+                ws = workspace(g, device)
+                xx = torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
+                yy = torch.as_tensor(y, dtype=torch.float64).to(device).contiguous()
+                Mb = self.M_all[d.off_M: d.off_M + metrics_size(g) // 8]
+                metrics(g, scheme, xx, yy, Mb, ws, params=self.params)
+                if status(ws):
+                    raise WiuError("metrics reported a folded cell")
         self.plan = ctypes.c_void_p()
         self.retune(get_tuning(0) if xi_variant is None else xi_variant,
                     get_tuning(1) if eta_variant is None else eta_variant)

@@ -108,3 +108,46 @@ def test_side_rules_are_validated(wiu):
     assert wiu.metrics_size(g) == 0
     g = wiu.make_grid(16, 12, ("periodic", "periodic"), (1.0, 1.0), sides=(3, 3, 3, 3))
     assert wiu.metrics_size(g) > 0
+
+
+def _descs(wiu, blocks):
+    """wiu_block array for multi-block grid blocks (offsets left at zero:
+    validation does not look at them)."""
+    out = (wiu.WiuBlock * len(blocks))()
+    for d, b in zip(out, blocks):
+        ny, nx = b.x.shape
+        d.nx, d.ny, d.bc_x, d.bc_y = nx, ny, 1, 1
+        for s in range(4):
+            d.side[s], d.nbr[s], d.nbr_side[s] = int(b.sides[s]), int(b.nbr[s]), int(b.nbr_side[s])
+            d.shift[s][0], d.shift[s][1] = float(b.shift[s][0]), float(b.shift[s][1])
+    return out
+
+
+def test_block_sets_are_validated(wiu):
+    """Interfaces must point back, match in length and lead into blocks at
+    least WIU_MB_REACH nodes deep; seam shifts must cancel; a rejected set
+    fails on the host before anything is allocated or launched."""
+    import numpy as np
+    from paper_1810_11103_amd import workloads as W
+    g = W.periodic_grid(60, 40, A=0.2, seed=1)
+    P = wiu.make_params()
+    plan = ctypes.c_void_p()
+
+    def ok(blocks):
+        d = _descs(wiu, blocks)
+        n = wiu.lib.wiu_blocks_metrics_work_size(d, len(blocks), 3)
+        return n > 0
+
+    good, _ = W.cut_blocks(g, [], icuts=[30], turns=[1, 2])
+    assert ok(good)
+    cases = []
+    b, _ = W.cut_blocks(g, [], icuts=[30], turns=[1, 2]); b[0].nbr_side[0] = (b[0].nbr_side[0] + 1) % 4; cases.append(b)
+    b, _ = W.cut_blocks(g, [], icuts=[30], turns=[1, 2]); b[1].shift = np.ones((4, 2)); cases.append(b)
+    b, _ = W.cut_blocks(g, [], icuts=[30], turns=[1, 2]); b[1].nbr = [5, 5, 5, 5]; cases.append(b)
+    b, _ = W.cut_blocks(g, [], icuts=[50], turns=[0, 0]); cases.append(b)  # neighbour 10 nodes deep
+    for b in cases:
+        assert not ok(b)
+        d = _descs(wiu, b)
+        rc = wiu.lib.wiu_batched_plan(d, len(b), 3, ctypes.byref(P), 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                                      ctypes.byref(plan))
+        assert rc == wiu.WIU_EINVAL and not plan.value

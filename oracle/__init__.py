@@ -87,6 +87,17 @@ def lib():
         L.orc_mb_rhs.argtypes = [_I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P, _P]
         L.orc_mb_rk3_step.argtypes = [_I, _I, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P, _P, _P]
         L.orc_mb_cfl_dt.argtypes = [_I, _P, _P, _D, _P, _P, _P, _P, _D, _P]
+        L.orc3_metrics_size.restype = ctypes.c_longlong
+        L.orc3_metrics_size.argtypes = [_P]
+        L.orc3_metrics.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P]
+        L.orc3_rhs.argtypes = [_I, _P, _P, _D, _D, _D, _I, _P, _P, _P]
+        L.orc3_cfl_dt.restype = _D
+        L.orc3_cfl_dt.argtypes = [_P, _D, _P, _P, _D]
+        L.orc3_rk3_step.argtypes = [_I, _P, _P, _D, _D, _D, _I, _P, _P, _D]
+        L.orc3_eigenvectors.restype = None
+        L.orc3_eigenvectors.argtypes = [_P, _D, _P, _P, _P]
+        L.orc3_flux_hat.restype = None
+        L.orc3_flux_hat.argtypes = [_P, _D, _P, _P]
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [_I]
         L.orc_get_threads.restype = _I
@@ -474,3 +485,63 @@ def mb_cfl_dt(blocks, Us, Ms, cfl, gamma=1.4):
     if rc:
         raise ValueError("orc_mb_cfl_dt: invalid connectivity")
     return dt
+
+
+# ---- three-dimensional grids (euler3d.hpp) --------------------------------------
+
+def _i3(v):
+    return np.ascontiguousarray(v, dtype=np.int32)
+
+
+def metrics3(scheme, x, y, z, bc=("periodic",) * 3, period=(0.0, 0.0, 0.0)):
+    """19 metric planes with the ghost band: shape (19, nz+2G, ny+2G, nx+2G)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    nz, ny, nx = x.shape
+    n = _i3([nx, ny, nz])
+    b = _i3([bc_id(v) for v in bc])
+    L = _f64(period)
+    M = np.zeros((19, nz + 2 * G, ny + 2 * G, nx + 2 * G))
+    if lib().orc3_metrics(scheme_id(scheme), _ptr(n), _ptr(b), _ptr(L), _ptr(x), _ptr(y), _ptr(z), _ptr(M)):
+        raise ValueError("orc3_metrics failed")
+    return M
+
+
+def rhs3(scheme, U, M, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+    U, M = _f64(U), _f64(M)
+    _, nz, ny, nx = U.shape
+    out = np.zeros_like(U)
+    if lib().orc3_rhs(scheme_id(scheme), _ptr(_i3([nx, ny, nz])), _ptr(_i3([bc_id(v) for v in bc])), gamma, alpha,
+                      eps, ppm, _ptr(U), _ptr(M), _ptr(out)):
+        raise ValueError("orc3_rhs failed")
+    return out
+
+
+def cfl_dt3(U, M, cfl, gamma=1.4):
+    U, M = _f64(U), _f64(M)
+    _, nz, ny, nx = U.shape
+    return lib().orc3_cfl_dt(_ptr(_i3([nx, ny, nz])), gamma, _ptr(U), _ptr(M), float(cfl))
+
+
+def rk3_step3(scheme, U, M, dt, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+    U = _f64(U).copy()
+    M = _f64(M)
+    _, nz, ny, nx = U.shape
+    if lib().orc3_rk3_step(scheme_id(scheme), _ptr(_i3([nx, ny, nz])), _ptr(_i3([bc_id(v) for v in bc])), gamma,
+                           alpha, eps, ppm, _ptr(U), _ptr(M), float(dt)):
+        raise ValueError("orc3_rk3_step failed")
+    return U
+
+
+def eigenvectors3(Q, gamma, n):
+    Q, n = _f64(Q), _f64(n)
+    L = np.zeros((5, 5))
+    R = np.zeros((5, 5))
+    lib().orc3_eigenvectors(_ptr(Q), gamma, _ptr(n), _ptr(L), _ptr(R))
+    return L, R
+
+
+def flux_hat3(Q, gamma, k):
+    Q, k = _f64(Q), _f64(k)
+    out = np.zeros(5)
+    lib().orc3_flux_hat(_ptr(Q), gamma, _ptr(k), _ptr(out))
+    return out

@@ -13,13 +13,14 @@ HDR = os.path.join(HERE, "wenoiu_oracle.hpp")
 HDR2 = os.path.join(HERE, "flop_count.hpp")
 HDR3 = os.path.join(HERE, "ad_types.hpp")
 HDR4 = os.path.join(HERE, "multiblock.hpp")
+HDR5 = os.path.join(HERE, "euler3d.hpp")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(force=True):
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(
             os.path.getmtime(SRC), os.path.getmtime(HDR), os.path.getmtime(HDR2), os.path.getmtime(HDR3),
-            os.path.getmtime(HDR4)):
+            os.path.getmtime(HDR4), os.path.getmtime(HDR5)):
         return LIB
     tmp = LIB + ".tmp"
     cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",

@@ -7,6 +7,7 @@
 // ---------------------------------------------------------------------------
 #include "wenoiu_oracle.hpp"
 #include "multiblock.hpp"
+#include "euler3d.hpp"
 #include "flop_count.hpp"
 #include "ad_types.hpp"
 
@@ -471,5 +472,63 @@ int orc_mb_cfl_dt(int nblocks, const int* idesc, const double* fdesc, double gam
   mb_cfl_dt(p, B, views<const double*>(nblocks, U_all, offU), views<const double*>(nblocks, M_all, offM), cfl, dt);
   return 0;
 }
+
+// ---- three-dimensional grids (euler3d.hpp) ---------------------------------
+// n[3], bc[3] (0 periodic, 1 transmissive), L[3] periods; x, y, z nodes
+// [nz][ny][nx]; states [5][nz][ny][nx]; metrics as MetricView3.  The paper's
+// configuration only (characteristic variables, Lax-Friedrichs, alpha = 1).
+
+namespace {
+Grid3 make_grid3(const int* n, const int* bc, const double* L) {
+  Grid3 g;
+  for (int d = 0; d < 3; ++d) { g.n[d] = n[d]; g.bc[d] = (Bc)bc[d]; g.L[d] = L[d]; }
+  return g;
+}
+const double kNoPeriod[3] = {0.0, 0.0, 0.0};  // rhs3 reads no coordinates
+bool bad_grid3(const int* n, const int* bc) {
+  for (int d = 0; d < 3; ++d)
+    if (n[d] < 1 || bc[d] < 0 || bc[d] > 1 || (bc[d] == 1 && n[d] < 2)) return true;
+  return false;
+}
+}  // namespace
+
+long long orc3_metrics_size(const int* n) {
+  return (long long)NPLANES3 * (n[0] + 2 * G) * (n[1] + 2 * G) * (n[2] + 2 * G);
+}
+
+int orc3_metrics(int scheme, const int* n, const int* bc, const double* L, const double* x, const double* y,
+                 const double* z, double* M) {
+  if (bad_scheme(scheme) || bad_grid3(n, bc)) return -1;
+  compute_metrics3((Scheme)scheme, make_grid3(n, bc, L), x, y, z, M);
+  return 0;
+}
+
+int orc3_rhs(int scheme, const int* n, const int* bc, double gamma, double alpha, double eps, int ppm,
+             const double* U, const double* M, double* out) {
+  if (bad_scheme(scheme) || bad_grid3(n, bc)) return -1;
+  rhs3((Scheme)scheme, make_params(gamma, alpha, eps, ppm), make_grid3(n, bc, kNoPeriod), U, M, out);
+  return 0;
+}
+
+double orc3_cfl_dt(const int* n, double gamma, const double* U, const double* M, double cfl) {
+  const int bc[3] = {0, 0, 0};
+  return cfl_dt3(make_params(gamma, 1.1, 1e-40, 1), make_grid3(n, bc, kNoPeriod), U, M, cfl);
+}
+
+int orc3_rk3_step(int scheme, const int* n, const int* bc, double gamma, double alpha, double eps, int ppm,
+                  double* U, const double* M, double dt) {
+  if (bad_scheme(scheme) || bad_grid3(n, bc)) return -1;
+  rk3_step3((Scheme)scheme, make_params(gamma, alpha, eps, ppm), make_grid3(n, bc, kNoPeriod), U, M, dt);
+  return 0;
+}
+
+void orc3_eigenvectors(const double* Q, double gamma, const double* nvec, double* L, double* R) {
+  double l[5][5], r[5][5];
+  eigenvectors3(Q, gamma, nvec, l, r);
+  for (int a = 0; a < 5; ++a)
+    for (int b = 0; b < 5; ++b) { L[5 * a + b] = l[a][b]; R[5 * a + b] = r[a][b]; }
+}
+
+void orc3_flux_hat(const double* Q, double gamma, const double* k, double* out) { flux_hat3(Q, gamma, k, out); }
 
 }  // extern "C"

@@ -417,3 +417,133 @@ def assemble(blocks, arrays, shape):
         a = np.asarray(a)
         out[..., blk.src.ravel()] = a.reshape(lead + (-1,))
     return out.reshape(lead + (ny, nx))
+
+
+# ---- three-dimensional grids and states --------------------------------------
+
+@dataclass
+class Grid3:
+    x: np.ndarray  # [nz][ny][nx]
+    y: np.ndarray
+    z: np.ndarray
+    bc: tuple = ("periodic", "periodic", "periodic")
+    period: tuple = (0.0, 0.0, 0.0)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def shape(self):
+        return self.x.shape
+
+
+def _mesh3(nx, ny, nz):
+    kk, jj, ii = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                             np.arange(nx, dtype=np.float64), indexing="ij")
+    return ii, jj, kk
+
+
+def _jitter3(shape, A, rng, mask):
+    """The 3-D counterpart of Sec. 6.1(1): each node displaced by
+    2A(Rand(0,1) - 0.5) spacings along one axis drawn uniformly."""
+    r = rng.random(shape)
+    axis = rng.integers(0, 3, size=shape)
+    d = 2.0 * A * (r - 0.5) * mask
+    return d * (axis == 0), d * (axis == 1), d * (axis == 2)
+
+
+def periodic_grid3(nx, ny, nz, box=(0.0, 1.0, 0.0, 1.0, 0.0, 1.0), A=0.0, seed=0):
+    """Periodic grid of nx x ny x nz distinct nodes, randomized at every node
+    when A > 0."""
+    x0, x1, y0, y1, z0, z1 = box
+    h = ((x1 - x0) / nx, (y1 - y0) / ny, (z1 - z0) / nz)
+    ii, jj, kk = _mesh3(nx, ny, nz)
+    d = (0.0, 0.0, 0.0)
+    if A > 0:
+        d = _jitter3(ii.shape, A, np.random.default_rng(seed), np.ones(ii.shape))
+    c = lambda a: np.ascontiguousarray(a)
+    return Grid3(c(x0 + (ii + d[0]) * h[0]), c(y0 + (jj + d[1]) * h[1]), c(z0 + (kk + d[2]) * h[2]),
+                 ("periodic",) * 3, (x1 - x0, y1 - y0, z1 - z0), {"A": A, "seed": seed})
+
+
+def bounded_grid3(nx, ny, nz, box=(0.0, 1.0, 0.0, 1.0, 0.0, 1.0), A=0.0, seed=0, layers=4):
+    """Non-periodic grid (nodes on both ends), randomized except in `layers`
+    uniform layers along every boundary."""
+    x0, x1, y0, y1, z0, z1 = box
+    h = ((x1 - x0) / (nx - 1), (y1 - y0) / (ny - 1), (z1 - z0) / (nz - 1))
+    ii, jj, kk = _mesh3(nx, ny, nz)
+    d = (0.0, 0.0, 0.0)
+    if A > 0:
+        inner = lambda v, n: (v >= layers) & (v < n - layers)
+        mask = (inner(ii, nx) & inner(jj, ny) & inner(kk, nz)).astype(np.float64)
+        d = _jitter3(ii.shape, A, np.random.default_rng(seed), mask)
+    c = lambda a: np.ascontiguousarray(a)
+    return Grid3(c(x0 + (ii + d[0]) * h[0]), c(y0 + (jj + d[1]) * h[1]), c(z0 + (kk + d[2]) * h[2]),
+                 ("transmissive",) * 3, (0.0, 0.0, 0.0), {"A": A, "seed": seed, "layers": layers})
+
+
+def wavy_grid3(nx, ny, nz, L=1.0, amp=0.04):
+    """Smooth periodic curvilinear grid on [0, L)^3: every coordinate is
+    displaced by amp L sin(2 pi a) sin(2 pi b) of the two other index
+    coordinates (a, b in [0, 1)), so all nine metrics vary."""
+    ii, jj, kk = _mesh3(nx, ny, nz)
+    a, b, c = ii / nx, jj / ny, kk / nz
+    s = lambda u: np.sin(2 * np.pi * u)
+    x = L * a + amp * L * s(b) * s(c)
+    y = L * b + amp * L * s(c) * s(a)
+    z = L * c + amp * L * s(a) * s(b)
+    f = np.ascontiguousarray
+    return Grid3(f(x), f(y), f(z), ("periodic",) * 3, (L, L, L), {"amp": amp})
+
+
+def extrude(grid, nz, U=None):
+    """A 2-D grid (and state [4][ny][nx]) made z-independent in 3-D: z = k
+    (period nz), w = 0; returns (Grid3, state [5][nz][ny][nx] or None)."""
+    ny, nx = grid.x.shape
+    rep = lambda a: np.ascontiguousarray(np.broadcast_to(a, (nz, ny, nx)))
+    z = np.ascontiguousarray(np.broadcast_to(np.arange(nz, dtype=np.float64)[:, None, None], (nz, ny, nx)))
+    g3 = Grid3(rep(grid.x), rep(grid.y), z, (grid.bc[0], grid.bc[1], "periodic"),
+               (grid.period[0], grid.period[1], float(nz)))
+    if U is None:
+        return g3, None
+    U3 = np.zeros((5, nz, ny, nx))
+    U3[0], U3[1], U3[2], U3[4] = rep(U[0]), rep(U[1]), rep(U[2]), rep(U[3])
+    return g3, U3
+
+
+def conservative3(rho, u, v, w, p, gamma=GAMMA):
+    rho = np.asarray(rho, dtype=np.float64)
+    e = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.ascontiguousarray(np.stack([rho, rho * u * np.ones_like(rho), rho * v * np.ones_like(rho),
+                                          rho * w * np.ones_like(rho), e * np.ones_like(rho)]))
+
+
+def uniform_flow3(grid, mach=0.5, direction=(1.0, 0.7, 0.4), rho=1.0, p=1.0, gamma=GAMMA):
+    n = np.asarray(direction, dtype=np.float64)
+    n = n / np.linalg.norm(n)
+    c = np.sqrt(gamma * p / rho)
+    r = np.full(grid.x.shape, rho)
+    return conservative3(r, mach * c * n[0], mach * c * n[1], mach * c * n[2], p, gamma)
+
+
+def entropy_wave3(grid, t=0.0, vel=(0.6, 0.4, 0.3), amp=0.2, gamma=GAMMA):
+    """rho = 1 + amp sin(2 pi (x + y + z - (u + v + w) t) / L) with uniform
+    velocity and pressure 1: an exact solution of the Euler equations on a
+    periodic cube of side L."""
+    L = grid.period[0]
+    u, v, w = vel
+    rho = 1.0 + amp * np.sin(2 * np.pi * (grid.x + grid.y + grid.z - (u + v + w) * t) / L)
+    return conservative3(rho, u, v, w, 1.0, gamma)
+
+
+def octant_state3(grid, gamma=GAMMA):
+    """Discontinuous state: eight octants about the centre of the box with
+    different densities, velocities and pressures (a 3-D Riemann problem)."""
+    xm = 0.5 * (grid.x.min() + grid.x.max())
+    ym = 0.5 * (grid.y.min() + grid.y.max())
+    zm = 0.5 * (grid.z.min() + grid.z.max())
+    o = (grid.x > xm).astype(int) + 2 * (grid.y > ym).astype(int) + 4 * (grid.z > zm).astype(int)
+    rho = np.array([1.0, 0.5323, 0.5323, 0.138, 0.8, 1.2, 0.7, 1.5])[o]
+    u = np.array([0.0, 1.206, 0.0, 1.206, 0.1, -0.2, 0.3, 0.0])[o]
+    v = np.array([0.0, 0.0, 1.206, 1.206, -0.1, 0.2, 0.0, 0.3])[o]
+    w = np.array([0.0, 0.2, -0.2, 0.0, 0.4, 0.0, -0.3, 0.1])[o]
+    p = np.array([1.0, 0.3, 0.3, 0.029, 0.9, 1.4, 0.6, 1.1])[o]
+    return conservative3(rho, u, v, w, p, gamma)

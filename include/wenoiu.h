@@ -318,6 +318,48 @@ int wiu_batched_rk3_step(wiu_plan* plan, int use_graph, wiu_stream_t stream);
 int wiu_batched_status(wiu_plan* plan, wiu_stream_t stream, int* status, int clear);
 int wiu_plan_destroy(wiu_plan* plan);
 
+/* ---- Three-dimensional grids ----------------------------------------------
+ * The paper's method in its general form (Sec. 2.1, Eq. 2.2): Q = (rho,
+ * rho u, rho v, rho w, e), metrics in the symmetric conservative form
+ * (Eq. 2.4) with each scheme's central operator in every derivative,
+ * J^{-1} by Eq. 2.5, midpoint metrics by the linear interpolation of the
+ * 2-D path (Sec. 2.4), the characteristic projection of Sec. 3.4 with five
+ * eigenvectors along the unit direction (shear waves along t2 and t1: t1
+ * the axis of the smallest component of n, ties to the later axis, made
+ * orthogonal to n; t2 = t1 x n), TVD-RK3.  The paper's configuration only:
+ * wiu_params must hold characteristic variables, alpha_h = 1, Jiang-Shu
+ * weights and the Lax-Friedrichs split (else WIU_EINVAL).
+ *
+ * Layouts (device, caller-owned): coordinates x, y, z and each state
+ * component [nz][ny][nx], i fastest; U [5][nz][ny][nx]; M 19 planes of
+ * (nx+8)(ny+8)(nz+8) doubles (ghost band 4): xi^ (x, y, z), eta^, zeta^,
+ * J^{-1} at nodes, then xi^ at (i+1/2), eta^ at (j+1/2), zeta^ at (k+1/2),
+ * followed by an 8-double tag; the sweeps latch WIU_ST_SCHEME and write
+ * nothing if the tag does not match.  ws: wiu3_workspace_bytes() bytes
+ * (status word first, read with wiu_status); zero it once with
+ * wiu_workspace_init.  Directions are periodic or transmissive (the
+ * boundary node's state beyond the end, coordinates extended linearly).
+ * All calls are asynchronous on `stream`. */
+typedef struct {
+  int nx, ny, nz;
+  int bc[3];            /* WIU_BC_* of x, y, z */
+  double period[3];     /* periods of periodic directions */
+} wiu_grid3;
+
+size_t wiu3_metrics_size(const wiu_grid3* g);
+size_t wiu3_workspace_bytes(const wiu_grid3* g);
+int wiu3_metrics(const wiu_grid3* g, int scheme, const double* x, const double* y, const double* z, double* M,
+                 void* ws, wiu_stream_t stream);
+/* dU/dt of Eq. 2.2 (one direction pass per coordinate direction). */
+int wiu3_rhs(const wiu_grid3* g, int scheme, const wiu_params* p, const double* U, const double* M, double* dUdt,
+             void* ws, wiu_stream_t stream);
+/* dt = cfl / max over nodes of sum_d (|U^_d| + c|k_d|) / J^{-1}, written to the device scalar dt. */
+int wiu3_cfl_dt(const wiu_grid3* g, const wiu_params* p, const double* U, const double* M, double cfl, double* dt,
+                void* ws, wiu_stream_t stream);
+/* One TVD-RK3 step of U in place with the device scalar time step dt (Sec. 6). */
+int wiu3_rk3_step(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, const double* dt,
+                  void* ws, wiu_stream_t stream);
+
 /* Tile shapes of the two sweep kernels (dir 0 = xi, 1 = eta).  Several
  * shapes are compiled; the choice is process-wide and affects speed only,
  * never results.  wiu_tuning_variants() returns how many shapes a direction

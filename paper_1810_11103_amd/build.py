@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libwenoiu.so")
 SOURCES = ["wiu_kernels.hip", "wiu_batched_kernels.hip", "wiu_adjoint_kernels.hip", "wiu_api.hip",
-           "wiu_batched.hip", "wiu_multiblock.hip"]
+           "wiu_batched.hip", "wiu_multiblock.hip", "wiu3d.hip"]
 HEADERS = ["wiu_device.hpp", "wiu_kernels.hpp", "wiu_sweep.hpp", "wiu_adjoint.hpp", "wiu_mb.hpp"]
 ARCH = os.environ.get("WIU_OFFLOAD_ARCH", "gfx950")
 

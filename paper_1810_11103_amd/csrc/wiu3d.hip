@@ -1,0 +1,707 @@
+// Three-dimensional Euler equations on curvilinear grids (gfx950, fp64): the
+// paper's method in its general form (Sec. 2.1, Eq. 2.2) -- metrics in the
+// symmetric conservative form (Eq. 2.4) with each scheme's central operator,
+// Jacobian by Eq. 2.5, the characteristic projection of Sec. 3.4 with five
+// eigenvectors, the WENOIU midpoint fluxes and upwind-biased difference of
+// every scheme, TVD-RK3.  The paper's configuration only (characteristic
+// variables, Lax-Friedrichs split, alpha = 1, Jiang-Shu weights).
+//
+// Kernels: one thread per node, threads consecutive along i (the fastest
+// memory index) for every direction, so loads and stores coalesce whatever
+// the line direction.  A direction pass is two kernels: items (nodal split
+// fluxes and both midpoint side fluxes of each node, ghost nodes included,
+// into a record box) and differences (H_{k+1/2} - H_{k-1/2} at interior
+// nodes, accumulated over the directions, with the final direction writing
+// dU/dt or the RK stage).
+#include "wenoiu.h"
+#include "wiu_kernels.hpp"
+
+namespace wiu {
+
+constexpr double TAG_MAGIC3 = 1810.111033;
+constexpr int NP3 = 19;   // metric planes (see wenoiu.h)
+constexpr int REC = 20;   // record values per node: f+, f-, F+, F- (5 each)
+constexpr int RG = 4;     // record box padding (nodes -4 .. n+3)
+
+struct Dims3 {
+  int n[3], bc[3];
+  double L[3];
+  long long np;        // nodes
+  int mp[2];           // metric box pitches nx+2G, ny+2G
+  long long mplane;    // metric plane size
+  int rp[2];           // record box pitches nx+2RG, ny+2RG
+  long long rplane;    // record plane size
+};
+
+WIU_DEV long long m3idx(const Dims3& d, int i, int j, int k) {
+  return ((long long)(k + GHOST) * d.mp[1] + (j + GHOST)) * d.mp[0] + (i + GHOST);
+}
+WIU_DEV long long r3idx(const Dims3& d, int i, int j, int k) {
+  return ((long long)(k + RG) * d.rp[1] + (j + RG)) * d.rp[0] + (i + RG);
+}
+WIU_DEV long long u3idx(const Dims3& d, int i, int j, int k) {
+  return ((long long)k * d.n[1] + j) * d.n[0] + i;
+}
+
+// ===========================================================================
+// Coordinates at any position: a node coordinate (base) plus an offset --
+// shifts across periodic seams, and beyond transmissive ends the linear
+// extension direction by direction (trilinear at edges and corners, as
+// sum over the out-of-range set T of prod_{d in T} e_d times the mixed
+// backward difference at the clamped node) -- so differences of nearby
+// positions take the base difference error-free.
+// ===========================================================================
+WIU_DEV void c3_point(const Dims3& d, const double* __restrict__ X, int c, const int p_in[3], double& base,
+                      double& off) {
+  int p[3] = {p_in[0], p_in[1], p_in[2]};
+  off = 0.0;
+  int cc[3], in[3], e[3];
+  for (int a = 0; a < 3; ++a) {
+    if (d.bc[a] == WIU_BC_PERIODIC) {
+      const int w = bc_index(p[a], d.n[a], 0);
+      if (a == c) off += (double)((p[a] - w) / d.n[a]) * d.L[a];
+      p[a] = w;
+    }
+    cc[a] = min(max(p[a], 0), d.n[a] - 1);
+    e[a] = abs(p[a] - cc[a]);
+    in[a] = e[a] ? (p[a] < 0 ? 1 : -1) : 0;
+  }
+  auto at = [&](int da, int db, int dc) {
+    return X[((long long)(cc[2] + dc) * d.n[1] + (cc[1] + db)) * d.n[0] + (cc[0] + da)];
+  };
+  base = at(0, 0, 0);
+  if (e[0] | e[1] | e[2]) {
+    // mixed differences over the out-of-range directions
+    double ext = 0.0;
+    for (int t = 1; t < 8; ++t) {
+      const int t0 = t & 1, t1 = (t >> 1) & 1, t2 = (t >> 2) & 1;
+      if ((t0 && !e[0]) || (t1 && !e[1]) || (t2 && !e[2])) continue;
+      double md = 0.0;
+      for (int s = 0; s < 8; ++s) {
+        if ((s & ~t) != 0) continue;  // s a subset of t
+        const int s0 = s & 1, s1 = (s >> 1) & 1, s2 = (s >> 2) & 1;
+        const double v = at(s0 * in[0], s1 * in[1], s2 * in[2]);
+        md += ((s0 + s1 + s2) & 1) ? -v : v;
+      }
+      ext += (double)((t0 ? e[0] : 1) * (t1 ? e[1] : 1) * (t2 ? e[2] : 1)) * md;
+    }
+    off += ext;
+  }
+}
+
+WIU_DEV double c3_diff(const Dims3& d, const double* X, int c, const int p1[3], const int p0[3]) {
+  double b1, o1, b0, o0, s, e;
+  c3_point(d, X, c, p1, b1, o1);
+  c3_point(d, X, c, p0, b0, o0);
+  two_sum(b1, -b0, s, e);
+  return s + ((o1 - o0) + e);
+}
+
+struct Coord3 {
+  const double* x[3];
+};
+
+// Inner derivatives D_a x_c (a, c = 0..2) on the box [-E, n+E)^3:
+// Dx[3a + c][box index].
+__global__ void m3_inner_kernel(Dims3 d, MetricStencil ms, int E, Coord3 X, double* __restrict__ Dx) {
+  const long long W0 = d.n[0] + 2 * E, W1 = d.n[1] + 2 * E, W2 = d.n[2] + 2 * E;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long P = W0 * W1 * W2;
+  if (t >= P) return;
+  const int p[3] = {(int)(t % W0) - E, (int)((t / W0) % W1) - E, (int)(t / (W0 * W1)) - E};
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int m = 1; m <= METRIC_REACH; ++m) {
+        const double cm = ms.d[m - 1];
+        if (cm == 0.0) continue;
+        int p1[3] = {p[0], p[1], p[2]}, p0[3] = {p[0], p[1], p[2]};
+        p1[a] += m;
+        p0[a] -= m;
+        s += cm * c3_diff(d, X.x[c], c, p1, p0);
+      }
+      Dx[(3 * a + c) * P + t] = s;
+    }
+}
+
+// Nodal metrics (Eq. 2.4) and J^{-1} (Eq. 2.5) on [-B, n+B)^3 into T[10]:
+// for direction m with (a, b) the next two directions cyclically and
+// component l with (p, q) the next two coordinates cyclically,
+//   n^_{m,l} = 1/2 [D_b(q D_a p) - D_a(q D_b p) + D_a(p D_b q) - D_b(p D_a q)],
+// with p, q taken relative to the node.  Periodic directions evaluate at the
+// wrapped node.
+__global__ void m3_nodal_kernel(Dims3 d, MetricStencil ms, int B, int E, Coord3 X, const double* __restrict__ Dx,
+                                double* __restrict__ T) {
+  const long long V0 = d.n[0] + 2 * B, V1 = d.n[1] + 2 * B, V2 = d.n[2] + 2 * B;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long P = V0 * V1 * V2;
+  if (t >= P) return;
+  int w[3] = {(int)(t % V0) - B, (int)((t / V0) % V1) - B, (int)(t / (V0 * V1)) - B};
+  for (int a = 0; a < 3; ++a)
+    if (d.bc[a] == WIU_BC_PERIODIC) w[a] = bc_index(w[a], d.n[a], 0);
+  const long long W0 = d.n[0] + 2 * E, W1 = d.n[1] + 2 * E;
+  const long long DP = W0 * W1 * (d.n[2] + 2 * E);
+  auto dx = [&](int plane, const int p[3]) {
+    return Dx[plane * DP + ((long long)(p[2] + E) * W1 + (p[1] + E)) * W0 + (p[0] + E)];
+  };
+  double J = 0.0;
+  for (int m = 0; m < 3; ++m) {
+    const int a = (m + 1) % 3, b = (m + 2) % 3;
+    for (int l = 0; l < 3; ++l) {
+      const int pc = (l + 1) % 3, qc = (l + 2) % 3;
+      // D_outer((X_cv - X_cv(w)) D_inner X_cd)
+      auto term = [&](int outer, int cv, int inner, int cd) {
+        double s = 0.0;
+        for (int k = 1; k <= METRIC_REACH; ++k) {
+          const double ck = ms.d[k - 1];
+          if (ck == 0.0) continue;
+          int p1[3] = {w[0], w[1], w[2]}, p0[3] = {w[0], w[1], w[2]};
+          p1[outer] += k;
+          p0[outer] -= k;
+          const double f1 = c3_diff(d, X.x[cv], cv, p1, w) * dx(3 * inner + cd, p1);
+          const double f0 = c3_diff(d, X.x[cv], cv, p0, w) * dx(3 * inner + cd, p0);
+          s += ck * (f1 - f0);
+        }
+        return s;
+      };
+      const double v = 0.5 * (term(b, qc, a, pc) - term(a, qc, b, pc) + term(a, pc, b, qc) - term(b, pc, a, qc));
+      T[(3 * m + l) * P + t] = v;
+      J += v * dx(3 * m + l, w);
+    }
+  }
+  T[9 * P + t] = J * (1.0 / 3.0);
+}
+
+// Stored metrics: nodal planes and midpoint interpolation in each metric's
+// own direction, ghost band included, plus the tag.
+__global__ void m3_band_kernel(Dims3 d, int scheme, int B, const double* __restrict__ T, double* __restrict__ M,
+                               int* __restrict__ status) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    double* tag = M + NP3 * d.mplane;
+    tag[0] = TAG_MAGIC3; tag[1] = (double)scheme; tag[2] = (double)d.n[0]; tag[3] = (double)d.n[1];
+    tag[4] = (double)d.n[2]; tag[5] = (double)(d.bc[0] + 2 * d.bc[1] + 4 * d.bc[2]); tag[6] = 1.0; tag[7] = 0.0;
+  }
+  if (t >= d.mplane) return;
+  const int p[3] = {(int)(t % d.mp[0]) - GHOST, (int)((t / d.mp[0]) % d.mp[1]) - GHOST,
+                    (int)(t / ((long long)d.mp[0] * d.mp[1])) - GHOST};
+  const long long V0 = d.n[0] + 2 * B, V1 = d.n[1] + 2 * B;
+  const long long TP = V0 * V1 * (d.n[2] + 2 * B);
+  auto tv = [&](int plane, int i, int j, int k) {
+    return T[plane * TP + ((long long)(k + B) * V1 + (j + B)) * V0 + (i + B)];
+  };
+  for (int q = 0; q < 10; ++q) M[q * d.mplane + t] = tv(q, p[0], p[1], p[2]);
+  const bool eight = scheme >= 4;
+  for (int m = 0; m < 3; ++m)
+    for (int l = 0; l < 3; ++l) {
+      auto v = [&](int s) {
+        int r[3] = {p[0], p[1], p[2]};
+        r[m] += s;
+        return tv(3 * m + l, r[0], r[1], r[2]);
+      };
+      M[(10 + 3 * m + l) * d.mplane + t] =
+          eight ? (-5.0 * (v(-3) + v(4)) + 49.0 * (v(-2) + v(3)) - 245.0 * (v(-1) + v(2)) +
+                   1225.0 * (v(0) + v(1))) * (1.0 / 2048.0)
+                : (3.0 * v(-2) - 25.0 * v(-1) + 150.0 * v(0) + 150.0 * v(1) - 25.0 * v(2) + 3.0 * v(3)) *
+                      (1.0 / 256.0);
+    }
+  if (p[0] >= 0 && p[0] < d.n[0] && p[1] >= 0 && p[1] < d.n[1] && p[2] >= 0 && p[2] < d.n[2]) {
+    const double j = tv(9, p[0], p[1], p[2]);
+    if (!(j > 0.0) || !(j < 1.0e300)) atomicOr(status, ST_JACOBIAN);
+  }
+}
+
+// ===========================================================================
+// Physics in three dimensions (Sec. 2.1; Sec. 3.4 eigenvectors).
+// ===========================================================================
+WIU_DEV void flux3(const double Q[5], const double k[3], double gam, double E[5]) {
+  const double ri = rcp(Q[0]);
+  const double u = Q[1] * ri, v = Q[2] * ri, w = Q[3] * ri;
+  const double p = (gam - 1.0) * (Q[4] - 0.5 * (Q[1] * u + Q[2] * v + Q[3] * w));
+  const double U = k[0] * u + k[1] * v + k[2] * w;
+  E[0] = Q[0] * U;
+  E[1] = Q[1] * U + k[0] * p;
+  E[2] = Q[2] * U + k[1] * p;
+  E[3] = Q[3] * U + k[2] * p;
+  E[4] = (Q[4] + p) * U;
+}
+
+// |k . u| + c |k| without contraction (every kernel rounds it alike).
+WIU_DEV double speed3(const double Q[5], const double k[3], double gam, bool& bad) {
+#pragma clang fp contract(off)
+  const double ri = rcp(Q[0]);
+  const double u = Q[1] * ri, v = Q[2] * ri, w = Q[3] * ri;
+  const double p = (gam - 1.0) * (Q[4] - 0.5 * (Q[1] * u + Q[2] * v + Q[3] * w));
+  const double c2 = gam * p * ri;
+  bad = !(Q[0] > 0.0) || !(p > 0.0);
+  const double s = fabs(k[0] * u + k[1] * v + k[2] * w) + sqrt(c2 * (k[0] * k[0] + k[1] * k[1] + k[2] * k[2]));
+  bad = bad || !(s < 1.0e300);
+  return s;
+}
+
+// Tangent basis of the unit direction n: t1 the axis of the smallest
+// component of n (ties to the later axis) made orthogonal to n, t2 = t1 x n.
+WIU_DEV void tangents3(const double n[3], double t1[3], double t2[3]) {
+  int e = 2;
+  if (fabs(n[1]) < fabs(n[e])) e = 1;
+  if (fabs(n[0]) < fabs(n[e])) e = 0;
+  const double an = n[e];
+  for (int c = 0; c < 3; ++c) t1[c] = (c == e ? 1.0 : 0.0) - an * n[c];
+  const double r = rsqrt_(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+  for (int c = 0; c < 3; ++c) t1[c] *= r;
+  t2[0] = t1[1] * n[2] - t1[2] * n[1];
+  t2[1] = t1[2] * n[0] - t1[0] * n[2];
+  t2[2] = t1[0] * n[1] - t1[1] * n[0];
+}
+
+// One side of the midpoint k+1/2 (side 0: F+, reference Q_k; side 1: F-,
+// reference Q_{k+1}): project the stencil's deviations from the reference
+// on the characteristic fields (rows of L for q_n - c, q_n, shear t2, shear
+// t1, q_n + c), interpolate each with WENO, map back with R, add the
+// reference, then the Lax-Friedrichs half flux with the midpoint metric.
+// q(s, c): state at window slot s = 0..7 (nodes k-3 .. k+4).
+template <int R, class QF>
+WIU_DEV void side_flux3(QF q, int side, const double n[3], const double mk[3], double lam, double gam, double eps,
+                        int ppm, double F[5]) {
+  double Qr[5];
+  for (int c = 0; c < 5; ++c) Qr[c] = q(3 + side, c);
+  double t1[3], t2[3];
+  tangents3(n, t1, t2);
+  const double gm1 = gam - 1.0;
+  const double rr = rcp(Qr[0]);
+  const double V[3] = {Qr[1] * rr, Qr[2] * rr, Qr[3] * rr};
+  const double q2 = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+  const double p = gm1 * (Qr[4] - 0.5 * Qr[0] * q2);
+  const double c2 = gam * p * rr;
+  const double rc = rsqrt_(c2);
+  const double c = c2 * rc;
+  const double H = (Qr[4] + p) * rr;
+  const double qn = V[0] * n[0] + V[1] * n[1] + V[2] * n[2];
+  const double qa = V[0] * t2[0] + V[1] * t2[1] + V[2] * t2[2];
+  const double qb = V[0] * t1[0] + V[1] * t1[1] + V[2] * t1[2];
+  const double b1 = gm1 * (rc * rc);
+  const double b2 = 0.5 * b1 * q2;
+  // window slots of the stencil in interpolation order (left-biased for side
+  // 0, mirrored for side 1); the reference slot has zero deviation
+  // r = 2: k-2 .. k+1, r = 3: k-2 .. k+2, r = 4: k-3 .. k+3 (for side 0)
+  constexpr int NS = R == 2 ? 4 : (R == 3 ? 5 : 7);
+  constexpr int C0 = R == 4 ? 3 : 2;     // index of the reference in that order
+  double w[5][NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (s == C0) {
+      for (int f = 0; f < 5; ++f) w[f][s] = 0.0;
+      continue;
+    }
+    const int slot = side == 0 ? 3 - C0 + s : 4 + C0 - s;
+    double dq[5];
+    for (int cc = 0; cc < 5; ++cc) dq[cc] = q(slot, cc) - Qr[cc];
+    const double dmV = V[0] * dq[1] + V[1] * dq[2] + V[2] * dq[3];
+    const double A = b2 * dq[0] - b1 * (dmV - dq[4]);
+    const double Bn = rc * (qn * dq[0] - (n[0] * dq[1] + n[1] * dq[2] + n[2] * dq[3]));
+    w[0][s] = 0.5 * (A + Bn);
+    w[1][s] = dq[0] - A;
+    w[2][s] = t2[0] * dq[1] + t2[1] * dq[2] + t2[2] * dq[3] - qa * dq[0];
+    w[3][s] = t1[0] * dq[1] + t1[1] * dq[2] + t1[2] * dq[3] - qb * dq[0];
+    w[4][s] = 0.5 * (A - Bn);
+  }
+  double Wf[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    if constexpr (R == 2) Wf[f] = weno3(w[f][0], w[f][1], w[f][3], eps, ppm);
+    else if constexpr (R == 3) Wf[f] = weno5(w[f][0], w[f][1], w[f][3], w[f][4], eps, ppm);
+    else Wf[f] = weno7(w[f][0], w[f][1], w[f][2], w[f][4], w[f][5], w[f][6], eps, ppm);
+  }
+  // Q = Q_ref + R W
+  const double s04 = Wf[0] + Wf[4], d40 = Wf[4] - Wf[0];
+  const double sum = s04 + Wf[1];
+  double r[5];
+  r[0] = Qr[0] + sum;
+  for (int a = 0; a < 3; ++a) r[1 + a] = Qr[1 + a] + (V[a] * sum + c * n[a] * d40 + t2[a] * Wf[2] + t1[a] * Wf[3]);
+  r[4] = Qr[4] + (H * s04 + c * qn * d40 + 0.5 * q2 * Wf[1] + qa * Wf[2] + qb * Wf[3]);
+  double E[5];
+  flux3(r, mk, gam, E);
+  const double sl = side == 0 ? lam : -lam;
+  for (int a = 0; a < 5; ++a) F[a] = 0.5 * (E[a] + sl * r[a]);
+}
+
+// ===========================================================================
+// Direction passes.
+// ===========================================================================
+struct S3Args {
+  Dims3 d;
+  const double* U;                 // state the fluxes are built from
+  const double* M;
+  const unsigned long long* lam;   // line maxima: xi lines [ny nz], eta [nx nz], zeta [nx ny]
+  double gamma, alpha, eps;
+  int ppm;
+  double* rec;                     // record box [REC][rplane]
+  double* Racc;                    // accumulated flux differences [5][np]
+  double* out;                     // dU/dt (mode 2) or the new stage state (mode 3)
+  const double* U0;                // RK base state
+  const double* dt;                // device time step
+  double ca, cb;
+  int* status;
+};
+
+WIU_DEV long long lam_off(const Dims3& d, int D) {
+  return D == 0 ? 0 : (D == 1 ? (long long)d.n[1] * d.n[2] : (long long)d.n[1] * d.n[2] + (long long)d.n[0] * d.n[2]);
+}
+WIU_DEV long long line3(const Dims3& d, int D, const int p[3]) {
+  return D == 0 ? (long long)p[2] * d.n[1] + p[1] : (D == 1 ? (long long)p[2] * d.n[0] + p[0]
+                                                             : (long long)p[1] * d.n[0] + p[0]);
+}
+
+WIU_DEV bool tag3_ok(const Dims3& d, const double* M, int scheme) {
+  const double* tag = M + NP3 * d.mplane;
+  return tag[0] == TAG_MAGIC3 && tag[1] == (double)scheme && tag[2] == (double)d.n[0] &&
+         tag[3] == (double)d.n[1] && tag[4] == (double)d.n[2] &&
+         tag[5] == (double)(d.bc[0] + 2 * d.bc[1] + 4 * d.bc[2]);
+}
+
+// Items of direction D: nodes -4 .. n+3 along D (nodal f+-), midpoints -4 ..
+// n+2 (F+-), at every position across.
+template <int SC>
+__global__ void __launch_bounds__(256) s3_item_kernel(S3Args a, int D) {
+  const Dims3& d = a.d;
+  long long W[3] = {d.n[0], d.n[1], d.n[2]};
+  W[D] += 2 * RG;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W[0] * W[1] * W[2]) return;
+  if (!tag3_ok(d, a.M, SC)) {
+    if (t == 0) atomicOr(a.status, ST_SCHEME);
+    return;
+  }
+  int p[3] = {(int)(t % W[0]), (int)((t / W[0]) % W[1]), (int)(t / (W[0] * W[1]))};
+  p[D] -= RG;
+  const int n = d.n[D], k = p[D];
+  const double lam = a.alpha * __longlong_as_double((long long)a.lam[lam_off(d, D) + line3(d, D, p)]);
+  const double gam = a.gamma;
+  // state at line position kk (the boundary rule along D)
+  auto Qat = [&](int kk, int c) {
+    int r[3] = {p[0], p[1], p[2]};
+    r[D] = bc_index(kk, n, d.bc[D]);
+    return a.U[c * d.np + u3idx(d, r[0], r[1], r[2])];
+  };
+  auto kn = [&](int kk, double out[3]) {
+    int r[3] = {p[0], p[1], p[2]};
+    r[D] = kk;
+    const long long o = m3idx(d, r[0], r[1], r[2]);
+    for (int c = 0; c < 3; ++c) out[c] = a.M[(3 * D + c) * d.mplane + o];
+  };
+  const long long ro = r3idx(d, p[0], p[1], p[2]);
+  {
+    double Q[5], k0[3], E[5];
+    for (int c = 0; c < 5; ++c) Q[c] = Qat(k, c);
+    kn(k, k0);
+    flux3(Q, k0, gam, E);
+    for (int c = 0; c < 5; ++c) {
+      a.rec[c * d.rplane + ro] = 0.5 * (E[c] + lam * Q[c]);
+      a.rec[(5 + c) * d.rplane + ro] = 0.5 * (E[c] - lam * Q[c]);
+    }
+  }
+  if (k < n + RG - 1) {
+    double k0[3], k1[3], mk[3], nv[3];
+    kn(k, k0);
+    kn(k + 1, k1);
+    const long long o = m3idx(d, p[0], p[1], p[2]);
+    for (int c = 0; c < 3; ++c) {
+      mk[c] = a.M[(10 + 3 * D + c) * d.mplane + o];
+      nv[c] = 0.5 * (k0[c] + k1[c]);
+    }
+    const double rn = rsqrt_(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    for (int c = 0; c < 3; ++c) nv[c] *= rn;
+    auto q = [&](int s, int c) { return Qat(k - 3 + s, c); };
+    for (int side = 0; side < 2; ++side) {
+      double F[5];
+      side_flux3<Traits<SC>::R>(q, side, nv, mk, lam, gam, a.eps, a.ppm, F);
+      for (int c = 0; c < 5; ++c) a.rec[(10 + 5 * side + c) * d.rplane + ro] = F[c];
+    }
+  }
+}
+
+// Differences of direction D at interior nodes.  mode 0: Racc = R; 1: Racc
+// += R; 2: dU/dt = -(Racc + R)/J^{-1}; 3: stage U_out = ca U0 + cb (U + dt
+// dU/dt) with dU/dt as in mode 2.
+template <int SC>
+__global__ void __launch_bounds__(256) s3_diff_kernel(S3Args a, int D, int mode) {
+  const Dims3& d = a.d;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.np) return;
+  if (!tag3_ok(d, a.M, SC)) return;
+  const int p[3] = {(int)(t % d.n[0]), (int)((t / d.n[0]) % d.n[1]), (int)(t / ((long long)d.n[0] * d.n[1]))};
+  auto ridx = [&](int kk) {
+    int r[3] = {p[0], p[1], p[2]};
+    r[D] = kk;
+    return r3idx(d, r[0], r[1], r[2]);
+  };
+  const int k = p[D];
+  double Rv[5];
+  for (int c = 0; c < 5; ++c) {
+    auto fp = [&](int kk) { return a.rec[c * d.rplane + ridx(kk)]; };
+    auto fm = [&](int kk) { return a.rec[(5 + c) * d.rplane + ridx(kk)]; };
+    auto Fp = [&](int kk) { return a.rec[(10 + c) * d.rplane + ridx(kk)]; };
+    auto Fm = [&](int kk) { return a.rec[(15 + c) * d.rplane + ridx(kk)]; };
+    Rv[c] = hflux<SC>(k, 1.0, fp, fm, Fp, Fm) - hflux<SC>(k - 1, 1.0, fp, fm, Fp, Fm);
+  }
+  if (mode == 0) {
+    for (int c = 0; c < 5; ++c) a.Racc[c * d.np + t] = Rv[c];
+    return;
+  }
+  if (mode == 1) {
+    for (int c = 0; c < 5; ++c) a.Racc[c * d.np + t] += Rv[c];
+    return;
+  }
+  const double rj = -rcp(a.M[9 * d.mplane + m3idx(d, p[0], p[1], p[2])]);
+  if (mode == 2) {
+    for (int c = 0; c < 5; ++c) a.out[c * d.np + t] = (a.Racc[c * d.np + t] + Rv[c]) * rj;
+    return;
+  }
+  const double dt = a.dt[0];
+  for (int c = 0; c < 5; ++c) {
+    const double L = (a.Racc[c * d.np + t] + Rv[c]) * rj;
+    const double us = a.U[c * d.np + t] + dt * L;
+    a.out[c * d.np + t] = a.ca == 0.0 ? a.cb * us : a.ca * a.U0[c * d.np + t] + a.cb * us;
+  }
+}
+
+// Line maxima of the wave speeds in all three directions and the CFL
+// maximum.  One thread per (i, j) column walks along k: zeta lines reduce in
+// registers, xi lines across the wave (threads along i), eta lines by
+// atomics.
+__global__ void __launch_bounds__(256) w3_max_kernel(Dims3 d, const double* __restrict__ U,
+                                                     const double* __restrict__ M, double gam,
+                                                     unsigned long long* __restrict__ lam, int* __restrict__ status) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const bool act = i < d.n[0] && j < d.n[1];
+  unsigned long long* lx = lam;
+  unsigned long long* le = lam + (long long)d.n[1] * d.n[2];
+  unsigned long long* lz = le + (long long)d.n[0] * d.n[2];
+  unsigned long long* cflm = lz + (long long)d.n[0] * d.n[1];
+  double smz = 0.0, cm = 0.0;
+  bool bad = false;
+  for (int k = 0; k < d.n[2]; ++k) {
+    double sx = 0.0;
+    if (act) {
+      const long long o = u3idx(d, i, j, k), mo = m3idx(d, i, j, k);
+      double Q[5];
+      for (int c = 0; c < 5; ++c) Q[c] = U[c * d.np + o];
+      double s[3];
+      for (int D = 0; D < 3; ++D) {
+        const double kk[3] = {M[(3 * D) * d.mplane + mo], M[(3 * D + 1) * d.mplane + mo],
+                              M[(3 * D + 2) * d.mplane + mo]};
+        bool b;
+        s[D] = speed3(Q, kk, gam, b);
+        bad |= b;
+      }
+      sx = fmax(0.0, s[0]);
+      atomicMax(&le[(long long)k * d.n[0] + i], (unsigned long long)__double_as_longlong(fmax(0.0, s[1])));
+      smz = fmax(smz, s[2]);
+      cm = fmax(cm, (sx + fmax(0.0, s[1]) + fmax(0.0, s[2])) / M[9 * d.mplane + mo]);
+    }
+    double v = sx;
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0 && j < d.n[1])
+      atomicMax(&lx[(long long)k * d.n[1] + j], (unsigned long long)__double_as_longlong(v));
+  }
+  if (act) atomicMax(&lz[(long long)j * d.n[0] + i], (unsigned long long)__double_as_longlong(smz));
+  for (int off = 32; off > 0; off >>= 1) cm = fmax(cm, __shfl_xor(cm, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(cflm, (unsigned long long)__double_as_longlong(cm));
+  if (bad) atomicOr(status, ST_NONPHYS);
+}
+
+}  // namespace wiu
+
+using namespace wiu;
+
+namespace {
+
+constexpr size_t A3 = 256;
+size_t al3(size_t v) { return (v + A3 - 1) / A3 * A3; }
+
+bool grid3_ok(const wiu_grid3* g) {
+  if (!g) return false;
+  const int n[3] = {g->nx, g->ny, g->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1 || g->bc[a] < 0 || g->bc[a] > 1) return false;
+    if (g->bc[a] == WIU_BC_TRANSMISSIVE && n[a] < 2) return false;
+    if (g->bc[a] == WIU_BC_PERIODIC && !(g->period[a] > 0.0 && g->period[a] < 1.0e300)) return false;
+    if (n[a] > 4096) return false;
+  }
+  return (long long)n[0] * n[1] * n[2] <= (1LL << 31);
+}
+
+Dims3 dims3(const wiu_grid3* g) {
+  Dims3 d;
+  d.n[0] = g->nx; d.n[1] = g->ny; d.n[2] = g->nz;
+  for (int a = 0; a < 3; ++a) { d.bc[a] = g->bc[a]; d.L[a] = g->period[a]; }
+  d.np = (long long)g->nx * g->ny * g->nz;
+  d.mp[0] = g->nx + 2 * GHOST; d.mp[1] = g->ny + 2 * GHOST;
+  d.mplane = (long long)d.mp[0] * d.mp[1] * (g->nz + 2 * GHOST);
+  d.rp[0] = g->nx + 2 * RG; d.rp[1] = g->ny + 2 * RG;
+  d.rplane = (long long)d.rp[0] * d.rp[1] * (g->nz + 2 * RG);
+  return d;
+}
+
+// Workspace: [status | line maxima | dt | big area], the big area holding
+// either the metric scratch (inner derivatives, nodal band) or the stepping
+// buffers (records, Racc, U1, U2).
+struct Ws3 {
+  size_t lam, dt, big, metric_dx, metric_t, rec, racc, u1, u2, total;
+  long long nlam;
+};
+
+Ws3 ws3(const wiu_grid3* g) {
+  const Dims3 d = dims3(g);
+  Ws3 w;
+  w.nlam = (long long)g->ny * g->nz + (long long)g->nx * g->nz + (long long)g->nx * g->ny + 1;
+  w.lam = A3;
+  w.dt = w.lam + al3(w.nlam * 8);
+  w.big = w.dt + A3;
+  const int B = GHOST + 4, E = B + 8;
+  const size_t dxb = al3(9 * (size_t)(g->nx + 2 * E) * (g->ny + 2 * E) * (g->nz + 2 * E) * 8);
+  const size_t tb = al3(10 * (size_t)(g->nx + 2 * B) * (g->ny + 2 * B) * (g->nz + 2 * B) * 8);
+  w.metric_dx = w.big;
+  w.metric_t = w.big + dxb;
+  w.rec = w.big;
+  w.racc = w.rec + al3(REC * (size_t)d.rplane * 8);
+  w.u1 = w.racc + al3(5 * (size_t)d.np * 8);
+  w.u2 = w.u1 + al3(5 * (size_t)d.np * 8);
+  const size_t step_end = w.u2 + al3(5 * (size_t)d.np * 8);
+  const size_t met_end = w.metric_t + tb;
+  w.total = step_end > met_end ? step_end : met_end;
+  return w;
+}
+
+bool params3_ok(const wiu_params* p) {
+  return p && p->gamma > 1.0 && p->alpha_lf > 0.0 && p->eps >= 0.0 && (p->ppm == 0 || p->ppm == 1) &&
+         p->vars == WIU_VARS_CHARACTERISTIC && p->alpha_h == 1.0 && p->weights == WIU_WEIGHTS_JS &&
+         p->split == WIU_SPLIT_LF;
+}
+
+dim3 lin_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+template <int SC>
+hipError_t launch_pass3(const S3Args& a, int D, int mode, hipStream_t st) {
+  long long W = (long long)a.d.n[0] * a.d.n[1] * a.d.n[2] / a.d.n[D] * (a.d.n[D] + 2 * RG);
+  hipLaunchKernelGGL(s3_item_kernel<SC>, lin_grid(W), dim3(256), 0, st, a, D);
+  hipLaunchKernelGGL(s3_diff_kernel<SC>, lin_grid(a.d.np), dim3(256), 0, st, a, D, mode);
+  return hipGetLastError();
+}
+
+hipError_t pass3(int scheme, const S3Args& a, int D, int mode, hipStream_t st) {
+  switch (scheme) {
+    case 0: return launch_pass3<0>(a, D, mode, st);
+    case 1: return launch_pass3<1>(a, D, mode, st);
+    case 2: return launch_pass3<2>(a, D, mode, st);
+    case 3: return launch_pass3<3>(a, D, mode, st);
+    case 4: return launch_pass3<4>(a, D, mode, st);
+    case 5: return launch_pass3<5>(a, D, mode, st);
+    case 6: return launch_pass3<6>(a, D, mode, st);
+    case 7: return launch_pass3<7>(a, D, mode, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t maxima3(const Dims3& d, const double* U, const double* M, double gam, unsigned long long* lam,
+                   long long nlam, int* status, hipStream_t st) {
+  if (launch_fill_u64(lam, nlam, st) != hipSuccess) return hipErrorUnknown;
+  hipLaunchKernelGGL(w3_max_kernel, dim3((d.n[0] + 63) / 64, (d.n[1] + 3) / 4), dim3(256), 0, st, d, U, M, gam,
+                     lam, status);
+  return hipGetLastError();
+}
+
+int rc3(hipError_t e) { return e == hipSuccess ? WIU_OK : WIU_EHIP; }
+
+}  // namespace
+
+extern "C" {
+
+size_t wiu3_metrics_size(const wiu_grid3* g) {
+  if (!grid3_ok(g)) return 0;
+  return ((size_t)NP3 * dims3(g).mplane + 8) * sizeof(double);
+}
+
+size_t wiu3_workspace_bytes(const wiu_grid3* g) { return grid3_ok(g) ? ws3(g).total : 0; }
+
+int wiu3_metrics(const wiu_grid3* g, int scheme, const double* x, const double* y, const double* z, double* M,
+                 void* ws, wiu_stream_t stream) {
+  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !x || !y || !z || !M || !ws) return WIU_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims3 d = dims3(g);
+  const Ws3 w = ws3(g);
+  char* base = (char*)ws;
+  double* Dx = (double*)(base + w.metric_dx);
+  double* T = (double*)(base + w.metric_t);
+  int* status = (int*)base;
+  const MetricStencil ms = metric_stencil(scheme, 1.0);
+  const int B = metric_band(scheme), E = B + 8;
+  Coord3 X{{x, y, z}};
+  const long long ND = (long long)(d.n[0] + 2 * E) * (d.n[1] + 2 * E) * (d.n[2] + 2 * E);
+  const long long NT = (long long)(d.n[0] + 2 * B) * (d.n[1] + 2 * B) * (d.n[2] + 2 * B);
+  hipLaunchKernelGGL(m3_inner_kernel, lin_grid(ND), dim3(256), 0, st, d, ms, E, X, Dx);
+  hipLaunchKernelGGL(m3_nodal_kernel, lin_grid(NT), dim3(256), 0, st, d, ms, B, E, X, Dx, T);
+  hipLaunchKernelGGL(m3_band_kernel, lin_grid(d.mplane), dim3(256), 0, st, d, scheme, B, T, M, status);
+  return rc3(hipGetLastError());
+}
+
+int wiu3_rhs(const wiu_grid3* g, int scheme, const wiu_params* p, const double* U, const double* M, double* dUdt,
+             void* ws, wiu_stream_t stream) {
+  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !params3_ok(p) || !U || !M || !dUdt || !ws) return WIU_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims3 d = dims3(g);
+  const Ws3 w = ws3(g);
+  char* base = (char*)ws;
+  S3Args a;
+  a.d = d; a.U = U; a.M = M; a.lam = (unsigned long long*)(base + w.lam);
+  a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
+  a.rec = (double*)(base + w.rec); a.Racc = (double*)(base + w.racc); a.out = dUdt;
+  a.U0 = nullptr; a.dt = nullptr; a.ca = 0.0; a.cb = 1.0; a.status = (int*)base;
+  if (maxima3(d, U, M, p->gamma, (unsigned long long*)a.lam, w.nlam, a.status, st) != hipSuccess) return WIU_EHIP;
+  for (int D = 0; D < 3; ++D)
+    if (pass3(scheme, a, D, D == 0 ? 0 : (D == 1 ? 1 : 2), st) != hipSuccess) return WIU_EHIP;
+  return WIU_OK;
+}
+
+int wiu3_cfl_dt(const wiu_grid3* g, const wiu_params* p, const double* U, const double* M, double cfl, double* dt,
+                void* ws, wiu_stream_t stream) {
+  if (!grid3_ok(g) || !p || !(p->gamma > 1.0) || !U || !M || !dt || !ws || !(cfl > 0.0)) return WIU_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims3 d = dims3(g);
+  const Ws3 w = ws3(g);
+  char* base = (char*)ws;
+  unsigned long long* lam = (unsigned long long*)(base + w.lam);
+  if (maxima3(d, U, M, p->gamma, lam, w.nlam, (int*)base, st) != hipSuccess) return WIU_EHIP;
+  return rc3(launch_cfl_dt(lam + w.nlam - 1, cfl, dt, st));
+}
+
+int wiu3_rk3_step(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, const double* dt,
+                  void* ws, wiu_stream_t stream) {
+  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !params3_ok(p) || !U || !M || !dt || !ws) return WIU_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims3 d = dims3(g);
+  const Ws3 w = ws3(g);
+  char* base = (char*)ws;
+  double* U1 = (double*)(base + w.u1);
+  double* U2 = (double*)(base + w.u2);
+  S3Args a;
+  a.d = d; a.M = M; a.lam = (unsigned long long*)(base + w.lam);
+  a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
+  a.rec = (double*)(base + w.rec); a.Racc = (double*)(base + w.racc);
+  a.U0 = U; a.dt = dt; a.status = (int*)base;
+  // U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U = 1/3 U + 2/3 (U2 + dt L(U2))
+  const double* src[3] = {U, U1, U2};
+  double* dst[3] = {U1, U2, U};
+  const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (int s = 0; s < 3; ++s) {
+    a.U = src[s]; a.out = dst[s]; a.ca = ca[s]; a.cb = cb[s];
+    if (maxima3(d, a.U, M, p->gamma, (unsigned long long*)a.lam, w.nlam, a.status, st) != hipSuccess)
+      return WIU_EHIP;
+    for (int D = 0; D < 3; ++D)
+      if (pass3(scheme, a, D, D == 0 ? 0 : (D == 1 ? 1 : 3), st) != hipSuccess) return WIU_EHIP;
+  }
+  return WIU_OK;
+}
+
+}  // extern "C"

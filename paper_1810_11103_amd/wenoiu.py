@@ -25,7 +25,8 @@ EXPORTS = [
     "wiu_profile_enable", "wiu_profile_read", "wiu_tuning_variants", "wiu_set_tuning", "wiu_get_tuning",
     "wiu_batched_plan", "wiu_batched_info", "wiu_batched_set_dt", "wiu_batched_cfl_dt", "wiu_batched_get_dt",
     "wiu_batched_rk3_step", "wiu_batched_status", "wiu_plan_destroy", "wiu_blocks_metrics_work_size",
-    "wiu_blocks_metrics",
+    "wiu_blocks_metrics", "wiu3_metrics_size", "wiu3_workspace_bytes", "wiu3_metrics", "wiu3_rhs", "wiu3_cfl_dt",
+    "wiu3_rk3_step",
     "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl", "wiu_step_record_bytes",
 ]
 KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3}
@@ -44,6 +45,11 @@ class WiuBlock(ctypes.Structure):
                 ("side", ctypes.c_int * 4), ("nbr", ctypes.c_int * 4), ("nbr_side", ctypes.c_int * 4),
                 ("shift", (ctypes.c_double * 2) * 4), ("fixed", (ctypes.c_double * 4) * 4),
                 ("off_X", ctypes.c_longlong)]
+
+
+class WiuGrid3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("bc", ctypes.c_int * 3),
+                ("period", ctypes.c_double * 3)]
 
 
 class WiuParams(ctypes.Structure):
@@ -76,6 +82,12 @@ def _load():
         "wiu_profile_enable": (I, [I]),
         "wiu_batched_plan": (I, [ctypes.POINTER(WiuBlock), I, I, PR, I, I, P, P, ctypes.POINTER(P)]),
         "wiu_blocks_metrics_work_size": (ctypes.c_size_t, [ctypes.POINTER(WiuBlock), I, I]),
+        "wiu3_metrics_size": (ctypes.c_size_t, [ctypes.POINTER(WiuGrid3)]),
+        "wiu3_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(WiuGrid3)]),
+        "wiu3_metrics": (I, [ctypes.POINTER(WiuGrid3), I, P, P, P, P, P, P]),
+        "wiu3_rhs": (I, [ctypes.POINTER(WiuGrid3), I, PR, P, P, P, P, P]),
+        "wiu3_cfl_dt": (I, [ctypes.POINTER(WiuGrid3), PR, P, P, ctypes.c_double, P, P, P]),
+        "wiu3_rk3_step": (I, [ctypes.POINTER(WiuGrid3), I, PR, P, P, P, P, P]),
         "wiu_blocks_metrics": (I, [ctypes.POINTER(WiuBlock), I, I, PR, P, P, P, P]),
         "wiu_batched_info": (I, [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "wiu_batched_set_dt": (I, [P, P, P]),
@@ -517,3 +529,63 @@ class BatchedPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---- three-dimensional grids (wiu3_*) -------------------------------------------
+
+def make_grid3(nx, ny, nz, bc=("periodic",) * 3, period=(0.0, 0.0, 0.0)):
+    g = WiuGrid3(int(nx), int(ny), int(nz))
+    for a in range(3):
+        g.bc[a] = BC[bc[a]] if isinstance(bc[a], str) else int(bc[a])
+        g.period[a] = float(period[a])
+    return g
+
+
+class Solver3:
+    """A 3-D grid on the device: coordinates (nz, ny, nx) arrays, metrics
+    computed once for `scheme`, a workspace; states are (5, nz, ny, nx)
+    fp64 device tensors."""
+
+    def __init__(self, x, y, z, scheme="5-2MP", bc=("periodic",) * 3, period=(0.0, 0.0, 0.0), params=None,
+                 device="cuda"):
+        nz, ny, nx = x.shape
+        self.grid = make_grid3(nx, ny, nz, bc, period)
+        self.scheme = scheme
+        self.params = params or make_params()
+        nm = lib.wiu3_metrics_size(ctypes.byref(self.grid))
+        nw = lib.wiu3_workspace_bytes(ctypes.byref(self.grid))
+        if nm == 0 or nw == 0:
+            raise WiuError("invalid 3-D grid")
+        self.M = torch.zeros(nm // 8, dtype=torch.float64, device=device)
+        self.ws = torch.zeros(nw, dtype=torch.uint8, device=device)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=device)
+        xyz = [torch.as_tensor(a, dtype=torch.float64).to(device).contiguous() for a in (x, y, z)]
+        _check(lib.wiu3_metrics(ctypes.byref(self.grid), scheme_id(scheme), *[_ptr(a) for a in xyz], _ptr(self.M),
+                                ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+        if status(self.ws):
+            raise WiuError("metrics reported a folded cell")
+
+    def planes(self):
+        g = self.grid
+        P = (g.nx + 8) * (g.ny + 8) * (g.nz + 8)
+        return self.M[:19 * P].view(19, g.nz + 8, g.ny + 8, g.nx + 8)
+
+    def rhs(self, U, out=None):
+        out = torch.empty_like(U) if out is None else out
+        _check(lib.wiu3_rhs(ctypes.byref(self.grid), scheme_id(self.scheme), ctypes.byref(self.params), _ptr(U),
+                            _ptr(self.M), _ptr(out), ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+        return out
+
+    def cfl_dt(self, U, cfl):
+        _check(lib.wiu3_cfl_dt(ctypes.byref(self.grid), ctypes.byref(self.params), _ptr(U), _ptr(self.M), float(cfl),
+                               _ptr(self.dt), ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+        return self.dt
+
+    def rk3_step(self, U, dt=None):
+        if dt is not None:
+            self.dt.fill_(float(dt))
+        _check(lib.wiu3_rk3_step(ctypes.byref(self.grid), scheme_id(self.scheme), ctypes.byref(self.params), _ptr(U),
+                                 _ptr(self.M), _ptr(self.dt), ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+
+    def status(self, clear=True):
+        return status(self.ws, clear)

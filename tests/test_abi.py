@@ -24,7 +24,7 @@ def wiu():
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(wiu_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(wiu3?_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_entry_points():
@@ -151,3 +151,22 @@ def test_block_sets_are_validated(wiu):
         rc = wiu.lib.wiu_batched_plan(d, len(b), 3, ctypes.byref(P), 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(8),
                                       ctypes.byref(plan))
         assert rc == wiu.WIU_EINVAL and not plan.value
+
+
+def test_3d_grids_and_options_are_validated(wiu):
+    """3-D grids need positive sizes (two nodes in transmissive directions,
+    positive periods in periodic ones); the 3-D path covers the paper's
+    configuration only, so other options are rejected on the host."""
+    g = wiu.make_grid3(16, 12, 10, ("periodic", "transmissive", "periodic"), (1.0, 0.0, 1.0))
+    assert wiu.lib.wiu3_metrics_size(ctypes.byref(g)) == (19 * 24 * 20 * 18 + 8) * 8
+    assert wiu.lib.wiu3_workspace_bytes(ctypes.byref(g)) > 0
+    for bad in (wiu.make_grid3(0, 12, 10), wiu.make_grid3(16, 1, 10, (1, 1, 1)),
+                wiu.make_grid3(16, 12, 10, ("periodic",) * 3, (1.0, 0.0, 1.0))):
+        assert wiu.lib.wiu3_metrics_size(ctypes.byref(bad)) == 0
+    dummy = ctypes.c_void_p(8)
+    for opts in (dict(vars="primitive"), dict(weights="z"), dict(split="sw")):
+        P = wiu.make_params(**opts)
+        rc = wiu.lib.wiu3_rhs(ctypes.byref(g), 3, ctypes.byref(P), dummy, dummy, dummy, dummy, None)
+        assert rc == wiu.WIU_EINVAL
+    P = wiu.make_params()
+    assert wiu.lib.wiu3_rhs(ctypes.byref(g), 8, ctypes.byref(P), dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL

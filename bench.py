@@ -48,6 +48,11 @@ FLOP_DIR = {  # (scheme family, interpolation variables) -> (A, B)
     ("7", "characteristic"): (2728.0, 18155.0), ("7", "conservative"): (1832.0, 11907.0),
     ("7", "primitive"): (2026.0, 13277.0),
 }
+# 3-D direction pass, per item (oracle/count_flops.py, per_item3; octant
+# Riemann state on a randomized periodic grid): nodal split flux per node
+# (nodes -4 .. n+3 of every line) and both midpoint side fluxes per midpoint
+# (midpoints -4 .. n+2): the work of the item kernel.
+FLOP_ITEM3 = {"3-1MP": (59.0, 1835.5), "5-2MP": (59.0, 2205.6), "7-2MP": (59.0, 3503.8)}
 FLOP_COMBINE = 8.0
 FLOP_RK_STAGE = 20.0
 PEAK_FP64_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
@@ -152,6 +157,52 @@ def batched_leg(steps, cfl, tune=True):
             "status": st}
 
 
+def three_d_leg(n=256, steps=8, cfl=0.5, scheme="5-2MP"):
+    """Three-dimensional path: RK3 steps with CFL of an octant Riemann state
+    on a randomized periodic n^3 grid; per-kernel times and the item
+    kernel's roofline."""
+    import torch
+    from paper_1810_11103_amd import workloads as W
+    from paper_1810_11103_amd import wenoiu
+    g = W.periodic_grid3(n, n, n, A=0.2, seed=n)
+    U0 = W.octant_state3(g)
+    sol = wenoiu.Solver3(g.x, g.y, g.z, scheme, g.bc, g.period)
+    del g
+    U = torch.as_tensor(U0).cuda().contiguous()
+    del U0
+
+    def step():
+        sol.cfl_dt(U, cfl)
+        sol.rk3_step(U)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    wenoiu.profile_enable(True)
+    for k in ("item3", "diff3"):
+        wenoiu.profile_read(k)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    kern = {k: wenoiu.profile_read(k) for k in ("item3", "diff3")}
+    wenoiu.profile_enable(False)
+    ms = e0.elapsed_time(e1) / steps
+    fn, fm = FLOP_ITEM3[scheme]
+    per_launch = n * n * ((n + 8) * fn + (n + 7) * fm)
+    achieved = per_launch / (kern["item3"][1] * 1e-3) / 1e12
+    return {"workload": f"3-D octant Riemann problem, randomized periodic {n}^3 grid (A=0.2, seed {n}), "
+                        f"WENOIU{scheme}, TVD-RK3 CFL {cfl}",
+            "ms_per_step": ms, "cell_updates_per_s": 3 * n ** 3 / (ms * 1e-3),
+            "kernels_ms": {k: round(v[1], 4) for k, v in kern.items()},
+            "roofline": {"bound": "alu", "kernel": "item3", "achieved": round(achieved, 3),
+                         "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                         "flops_per_launch": per_launch, "launches": kern["item3"][0]},
+            "status": sol.status()}
+
+
 def adjoint_leg(n=512, nsteps=400, cfl=0.5, fd_check=True):
     """Adjoint workload: isentropic vortex (strength 5) on the randomized
     periodic n x n grid of [0,10]^2, `nsteps` RK3 steps at the fixed dt of
@@ -226,6 +277,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-block leg")
     ap.add_argument("--no-rhs", action="store_true", help="skip the bare-rhs timing")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional leg")
+    ap.add_argument("--n3", type=int, default=256, help="grid size of the three-dimensional leg")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM counters)")
     args = ap.parse_args()
@@ -350,6 +403,9 @@ def main():
     if not args.no_adjoint:
         torch.cuda.empty_cache()
         out["extra"]["adjoint"] = adjoint_leg()
+    if not args.no_3d:
+        torch.cuda.empty_cache()
+        out["extra"]["three_d"] = three_d_leg(args.n3)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, U0, args.scheme, args.cfl, args.vars, args.alpha_h, args.weights,
                                            args.split)

@@ -98,6 +98,7 @@ def lib():
         L.orc3_eigenvectors.argtypes = [_P, _D, _P, _P, _P]
         L.orc3_flux_hat.restype = None
         L.orc3_flux_hat.argtypes = [_P, _D, _P, _P]
+        L.orc3_count_line_flops.argtypes = [_I, _I, _D, _P, _P, _P]
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [_I]
         L.orc_get_threads.restype = _I
@@ -545,3 +546,14 @@ def flux_hat3(Q, gamma, k):
     out = np.zeros(5)
     lib().orc3_flux_hat(_ptr(Q), gamma, _ptr(k), _ptr(out))
     return out
+
+
+def count_line_flops3(scheme, Q, K, gamma=1.4):
+    """Operation counts of one 3-D line (Q [5][n], K [6][n+8]) by phase:
+    line maximum, nodal split fluxes, midpoint split fluxes, combination."""
+    Q, K = _f64(Q), _f64(K)
+    n = Q.shape[1]
+    c = np.zeros(4, dtype=np.int64)
+    if lib().orc3_count_line_flops(scheme_id(scheme), n, gamma, _ptr(Q), _ptr(K), _ptr(c)):
+        raise ValueError("orc3_count_line_flops failed")
+    return c

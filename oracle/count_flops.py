@@ -35,7 +35,43 @@ def per_direction(scheme, vars):
     return A, B, comb
 
 
+def per_item3(scheme, n=48, lines=24, seed=3):
+    """3-D direction pass, per item: nodal split flux (per node -4 .. n+3),
+    midpoint split fluxes (per midpoint -4 .. n+2), combination and
+    difference (per interior node); averaged over `lines` sampled lines of
+    each direction of an octant Riemann state on a randomized periodic
+    n^3 grid (the counts vary slightly with the data through the mappings'
+    branches)."""
+    g = W.periodic_grid3(n, n, n, A=0.2, seed=seed)
+    U = W.octant_state3(g)
+    M = oracle.metrics3(scheme, g.x, g.y, g.z, g.bc, g.period)
+    G = oracle.G
+    rng = np.random.default_rng(seed)
+    tot = np.zeros(4)
+    cnt = 0
+    for d in range(3):
+        for _ in range(lines):
+            a, b = rng.integers(0, n, size=2)
+            # line along axis d (array axes are z, y, x)
+            ax = 2 - d
+            idx = [slice(None)] * 3
+            others = [x for x in (0, 1, 2) if x != ax]
+            idx[others[0]], idx[others[1]] = a, b
+            Q = U[(slice(None), *idx)]
+            Mi = [slice(None)] * 3
+            Mi[others[0]], Mi[others[1]] = a + G, b + G
+            K = np.concatenate([M[3 * d:3 * d + 3][(slice(None), *Mi)], M[10 + 3 * d:13 + 3 * d][(slice(None), *Mi)]])
+            tot += oracle.count_line_flops3(scheme, Q, K)
+            cnt += 1
+    tot /= cnt
+    return tot[1] / (n + 8), tot[2] / (n + 7), tot[3] / n, tot[0] / n
+
+
 if __name__ == "__main__":
+    print("3-D, per item: scheme  nodal  midpoint  difference  line-maximum")
+    for s in oracle.SCHEMES:
+        fn, fm, fd, fx = per_item3(s)
+        print(f"{s}  {fn:7.1f}  {fm:8.1f}  {fd:6.1f}  {fx:5.1f}")
     print("scheme  vars  A (per cell per direction)  B (per line)  final combination per cell")
     for s in oracle.SCHEMES:
         for v in ("characteristic", "conservative", "primitive"):

@@ -300,7 +300,8 @@ void midpoint_flux3(Scheme sc, const Params& pr, const T Qs[8][5], const double 
 // K(w, k): w = 0..2 nodal metric of this direction, 3..5 midpoint metric at
 // k+1/2.  The Lax-Friedrichs eigenvalue is alpha * max over the line's nodes.
 template <class T, class QF, class KF>
-void line_residual3(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_out) {
+void line_residual3(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam_out,
+                    void (*phase_end)(int) = nullptr) {
   T lam = T(0.0);
   for (int k = 0; k < n; ++k) {
     T Qk[5] = {Q(k, 0), Q(k, 1), Q(k, 2), Q(k, 3), Q(k, 4)};
@@ -310,6 +311,7 @@ void line_residual3(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam
   }
   lam = pr.alpha_lf * lam;
   if (lam_out) *lam_out = lam;
+  if (phase_end) phase_end(0);
   const int off = 4, len = n + 8;
   std::vector<T> fp(5 * len), fm(5 * len), Fp(5 * len), Fm(5 * len);
   for (int k = -4; k < n + 4; ++k) {
@@ -321,6 +323,7 @@ void line_residual3(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam
       fm[q * len + k + off] = 0.5 * (E[q] - lam * Qk[q]);
     }
   }
+  if (phase_end) phase_end(1);
   for (int k = -4; k < n + 3; ++k) {
     T Qs[8][5];
     for (int m = 0; m < 8; ++m)
@@ -331,6 +334,7 @@ void line_residual3(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam
     midpoint_flux3(sc, pr, Qs, k0, k1, mk, lam, a, b);
     for (int q = 0; q < 5; ++q) { Fp[q * len + k + off] = a[q]; Fm[q * len + k + off] = b[q]; }
   }
+  if (phase_end) phase_end(2);
   std::vector<T> H(5 * (n + 1));
   for (int i = -1; i < n; ++i)
     for (int q = 0; q < 5; ++q) {
@@ -342,6 +346,7 @@ void line_residual3(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam
     }
   for (int k = 0; k < n; ++k)
     for (int q = 0; q < 5; ++q) R[q * n + k] = H[q * (n + 1) + k + 1] - H[q * (n + 1) + k];
+  if (phase_end) phase_end(3);
 }
 
 // Eq. 2.2: dQ/dt = -[sum over the three directions of H_{+1/2} - H_{-1/2}] / J^{-1};

@@ -403,7 +403,7 @@ int orc_rk3_step_vjp(int scheme, int nx, int ny, int bcx, int bcy, const int* si
 // ---- operation count of one rhs evaluation ---------------------------------------
 // counts[0]: xi sweep (all rows), counts[1]: eta sweep (all columns),
 // counts[2]: final combination; single-threaded.
-static long long g_marks[3];
+static long long g_marks[4];
 static void mark(int ph) { g_marks[ph] = Counted::n(); }
 
 int orc_count_rhs_flops(int scheme, int nx, int ny, int bcx, int bcy, const int* side, const double* fixed, double gamma, double alpha, double eps,
@@ -530,5 +530,24 @@ void orc3_eigenvectors(const double* Q, double gamma, const double* nvec, double
 }
 
 void orc3_flux_hat(const double* Q, double gamma, const double* k, double* out) { flux_hat3(Q, gamma, k, out); }
+
+// Operation counts of one 3-D grid line of n nodes (line_residual3 with the
+// counting scalar), by phase: [0] line maximum, [1] nodal split fluxes
+// (nodes -4 .. n+3), [2] midpoint split fluxes (midpoints -4 .. n+2),
+// [3] upwind-biased combination and difference.  Q [5][n] (the ends repeat
+// the boundary node), K [6][n+8] (nodal and midpoint metric of the
+// direction at positions -4 .. n+3).
+int orc3_count_line_flops(int scheme, int n, double gamma, const double* Q, const double* K, long long* counts) {
+  if (bad_scheme(scheme) || n < 2) return -1;
+  Params p = make_params(gamma, 1.1, 1e-40, 1);
+  std::vector<Counted> R(5 * (size_t)n);
+  auto Qf = [&](int k, int q) { return Counted(Q[(size_t)q * n + std::min(std::max(k, 0), n - 1)]); };
+  auto Kf = [&](int w, int k) { return K[(size_t)w * (n + 8) + (k + 4)]; };
+  Counted::n() = 0;
+  line_residual3<Counted>((Scheme)scheme, p, n, Qf, Kf, R.data(), nullptr, mark);
+  counts[0] = g_marks[0];
+  for (int k = 1; k < 4; ++k) counts[k] = g_marks[k] - g_marks[k - 1];
+  return 0;
+}
 
 }  // extern "C"

@@ -466,9 +466,11 @@ __global__ void __launch_bounds__(256) s3_diff_kernel(S3Args a, int D, int mode)
 }
 
 // Line maxima of the wave speeds in all three directions and the CFL
-// maximum.  One thread per (i, j) column walks along k: zeta lines reduce in
-// registers, xi lines across the wave (threads along i), eta lines by
-// atomics.
+// maximum.  One thread per (i, j) column walks a chunk of KC3 nodes along k
+// (the third grid dimension covers the chunks): zeta lines reduce in
+// registers over the chunk, xi lines across the wave (threads along i), eta
+// lines by atomics.
+constexpr int KC3 = 16;
 __global__ void __launch_bounds__(256) w3_max_kernel(Dims3 d, const double* __restrict__ U,
                                                      const double* __restrict__ M, double gam,
                                                      unsigned long long* __restrict__ lam, int* __restrict__ status) {
@@ -481,7 +483,8 @@ __global__ void __launch_bounds__(256) w3_max_kernel(Dims3 d, const double* __re
   unsigned long long* cflm = lz + (long long)d.n[0] * d.n[1];
   double smz = 0.0, cm = 0.0;
   bool bad = false;
-  for (int k = 0; k < d.n[2]; ++k) {
+  const int k0 = blockIdx.z * KC3, k1 = min(k0 + KC3, d.n[2]);  // uniform over the block
+  for (int k = k0; k < k1; ++k) {
     double sx = 0.0;
     if (act) {
       const long long o = u3idx(d, i, j, k), mo = m3idx(d, i, j, k);
@@ -585,8 +588,12 @@ dim3 lin_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
 template <int SC>
 hipError_t launch_pass3(const S3Args& a, int D, int mode, hipStream_t st) {
   long long W = (long long)a.d.n[0] * a.d.n[1] * a.d.n[2] / a.d.n[D] * (a.d.n[D] + 2 * RG);
+  void* h = prof_open(WIU_K_ITEM3, st);
   hipLaunchKernelGGL(s3_item_kernel<SC>, lin_grid(W), dim3(256), 0, st, a, D);
+  prof_close(h);
+  h = prof_open(WIU_K_DIFF3, st);
   hipLaunchKernelGGL(s3_diff_kernel<SC>, lin_grid(a.d.np), dim3(256), 0, st, a, D, mode);
+  prof_close(h);
   return hipGetLastError();
 }
 
@@ -607,8 +614,8 @@ hipError_t pass3(int scheme, const S3Args& a, int D, int mode, hipStream_t st) {
 hipError_t maxima3(const Dims3& d, const double* U, const double* M, double gam, unsigned long long* lam,
                    long long nlam, int* status, hipStream_t st) {
   if (launch_fill_u64(lam, nlam, st) != hipSuccess) return hipErrorUnknown;
-  hipLaunchKernelGGL(w3_max_kernel, dim3((d.n[0] + 63) / 64, (d.n[1] + 3) / 4), dim3(256), 0, st, d, U, M, gam,
-                     lam, status);
+  hipLaunchKernelGGL(w3_max_kernel, dim3((d.n[0] + 63) / 64, (d.n[1] + 3) / 4, (d.n[2] + KC3 - 1) / KC3), dim3(256),
+                     0, st, d, U, M, gam, lam, status);
   return hipGetLastError();
 }
 

@@ -34,6 +34,19 @@ struct ProfScope {
   }
 };
 
+}  // namespace
+
+// Timing scopes for kernels launched from other files of the library.
+namespace wiu {
+void* prof_open(int id, hipStream_t st) {
+  if (!g_prof_on) return nullptr;
+  return new ProfScope(id, st);
+}
+void prof_close(void* h) { delete static_cast<ProfScope*>(h); }
+}  // namespace wiu
+
+namespace {
+
 // Tile shape of each sweep direction (index into the compiled variants).
 int g_variant[2] = {0, 2};  // xi 128 x 1, eta 32 x 8 (measured at 2048^2)
 

@@ -146,6 +146,10 @@ hipError_t launch_metrics_band(const Dims& d, int scheme, double ah, int B, cons
 // Maximum over each group of line maxima (lam[mem[start[g] .. start[g+1])]),
 // written back to every member.
 hipError_t launch_group_max(unsigned long long* lam, const int* start, const int* mem, int ngroups, hipStream_t st);
+// Event-timing scope of kernel `id` (WIU_K_*) on `st` while timing is
+// enabled (null otherwise); prof_close records its end.
+void* prof_open(int id, hipStream_t st);
+void prof_close(void* h);
 hipError_t launch_cfl_dt(const unsigned long long* cfl_max, double cfl, double* dt, hipStream_t st);
 hipError_t launch_lambda_out(const Dims& d, double alpha, const unsigned long long* lx, const unsigned long long* le,
                              double* ox, double* oe, hipStream_t st);

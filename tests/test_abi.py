@@ -34,7 +34,8 @@ def test_header_declares_entry_points():
 
 
 def test_library_exports_every_declared_symbol(wiu):
-    lib = ctypes.CDLL(LIB)
+    # immediate binding: every symbol the library references must resolve
+    lib = ctypes.CDLL(LIB, mode=os.RTLD_NOW)
     for n in declared_functions():
         assert hasattr(lib, n), n
     assert sorted(wiu.EXPORTS) == sorted(declared_functions())

@@ -375,9 +375,8 @@ int wiu_get_tuning(int dir);
  * clears that kernel's records. */
 enum {
   WIU_K_WAVE_MAX = 0, WIU_K_SWEEP_XI = 1, WIU_K_SWEEP_ETA = 2, WIU_K_METRICS = 3,
-  WIU_K_ITEM3 = 4,   /* 3-D direction pass: items (nodal and midpoint split fluxes) */
-  WIU_K_DIFF3 = 5,   /* 3-D direction pass: flux differences */
-  WIU_K_COUNT = 6
+  WIU_K_SWEEP3 = 4,  /* 3-D direction pass */
+  WIU_K_COUNT = 5
 };
 int wiu_profile_enable(int on);
 int wiu_profile_read(int id, long long* count, double* mean_ms);

@@ -6,13 +6,11 @@
 // every scheme, TVD-RK3.  The paper's configuration only (characteristic
 // variables, Lax-Friedrichs split, alpha = 1, Jiang-Shu weights).
 //
-// Kernels: one thread per node, threads consecutive along i (the fastest
-// memory index) for every direction, so loads and stores coalesce whatever
-// the line direction.  A direction pass is two kernels: items (nodal split
-// fluxes and both midpoint side fluxes of each node, ghost nodes included,
-// into a record box) and differences (H_{k+1/2} - H_{k-1/2} at interior
-// nodes, accumulated over the directions, with the final direction writing
-// dU/dt or the RK stage).
+// A direction pass is one LDS-tiled sweep (states staged once, one item per
+// lane, item records in LDS, the flux difference and the stage update in the
+// same kernel), with lanes along i wherever global memory is touched so
+// loads and stores coalesce whatever the line direction; the pass over the
+// last direction writes dU/dt or the RK stage.
 #include "wenoiu.h"
 #include "wiu_kernels.hpp"
 
@@ -20,8 +18,6 @@ namespace wiu {
 
 constexpr double TAG_MAGIC3 = 1810.111033;
 constexpr int NP3 = 19;   // metric planes (see wenoiu.h)
-constexpr int REC = 20;   // record values per node: f+, f-, F+, F- (5 each)
-constexpr int RG = 4;     // record box padding (nodes -4 .. n+3)
 
 struct Dims3 {
   int n[3], bc[3];
@@ -29,15 +25,10 @@ struct Dims3 {
   long long np;        // nodes
   int mp[2];           // metric box pitches nx+2G, ny+2G
   long long mplane;    // metric plane size
-  int rp[2];           // record box pitches nx+2RG, ny+2RG
-  long long rplane;    // record plane size
 };
 
 WIU_DEV long long m3idx(const Dims3& d, int i, int j, int k) {
   return ((long long)(k + GHOST) * d.mp[1] + (j + GHOST)) * d.mp[0] + (i + GHOST);
-}
-WIU_DEV long long r3idx(const Dims3& d, int i, int j, int k) {
-  return ((long long)(k + RG) * d.rp[1] + (j + RG)) * d.rp[0] + (i + RG);
 }
 WIU_DEV long long u3idx(const Dims3& d, int i, int j, int k) {
   return ((long long)k * d.n[1] + j) * d.n[0] + i;
@@ -335,7 +326,6 @@ struct S3Args {
   const unsigned long long* lam;   // line maxima: xi lines [ny nz], eta [nx nz], zeta [nx ny]
   double gamma, alpha, eps;
   int ppm;
-  double* rec;                     // record box [REC][rplane]
   double* Racc;                    // accumulated flux differences [5][np]
   double* out;                     // dU/dt (mode 2) or the new stage state (mode 3)
   const double* U0;                // RK base state
@@ -359,91 +349,144 @@ WIU_DEV bool tag3_ok(const Dims3& d, const double* M, int scheme) {
          tag[5] == (double)(d.bc[0] + 2 * d.bc[1] + 4 * d.bc[2]);
 }
 
-// Items of direction D: nodes -4 .. n+3 along D (nodal f+-), midpoints -4 ..
-// n+2 (F+-), at every position across.
-template <int SC>
-__global__ void __launch_bounds__(256) s3_item_kernel(S3Args a, int D) {
+// LDS of a 3-D sweep tile: NA items along the line by NB lines.  Per item
+// the nodal flux E^ and both midpoint side fluxes (15 values; f+- are rebuilt
+// from E^ and the staged state); the states of items k - QL .. k + QL + 1.
+// Lanes of a wave touch consecutive words: line-major for xi tiles (lanes
+// along the line), position-major otherwise (lanes across lines along i).
+template <int SC, int DIR, int NA, int NB> struct Sweep3Lds {
+  static constexpr int QL = Range<SC>::QL;
+  static constexpr int NQ = NA + 2 * QL + 1;
+  double sh[15][NA * NB];
+  double sq[5][NB * NQ];
+  static WIU_DEV int si(int tb, int ta) { return DIR == 0 ? tb * NA + ta : ta * NB + tb; }
+  static WIU_DEV int qi(int tb, int pos) { return DIR == 0 ? tb * NQ + pos : pos * NB + tb; }
+};
+
+// One direction pass.  A workgroup owns NB lines (consecutive j for xi,
+// consecutive i otherwise, at one value of the remaining index) and a
+// segment of OUT = NA - EXTRA output nodes along them: it stages the states
+// of the segment (boundary rule applied) in LDS, computes one item per lane
+// (nodal flux at k and both side fluxes at k + 1/2), then the first OUT
+// lanes of each line form H_{i+1/2} - H_{i-1/2} and, by `mode`: 0 Racc = R;
+// 1 Racc += R; 2 dU/dt = -(Racc + R)/J^{-1}; 3 the RK stage
+// U_out = ca U0 + cb (U + dt dU/dt).  Two block-wide barriers on every path.
+template <int SC, int DIR, int NA, int NB>
+__global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
+  __shared__ Sweep3Lds<SC, DIR, NA, NB> L;
+  using R_ = Range<SC>;
+  using LT = Sweep3Lds<SC, DIR, NA, NB>;
+  constexpr int OUT = NA - R_::EXTRA, QL = R_::QL, NQ = LT::NQ, NT = NA * NB;
   const Dims3& d = a.d;
-  long long W[3] = {d.n[0], d.n[1], d.n[2]};
-  W[D] += 2 * RG;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= W[0] * W[1] * W[2]) return;
-  if (!tag3_ok(d, a.M, SC)) {
-    if (t == 0) atomicOr(a.status, ST_SCHEME);
+  if (!tag3_ok(d, a.M, SC)) {  // block-uniform
+    if (threadIdx.x == 0 && threadIdx.y == 0) atomicOr(a.status, ST_SCHEME);
     return;
   }
-  int p[3] = {(int)(t % W[0]), (int)((t / W[0]) % W[1]), (int)(t / (W[0] * W[1]))};
-  p[D] -= RG;
-  const int n = d.n[D], k = p[D];
-  const double lam = a.alpha * __longlong_as_double((long long)a.lam[lam_off(d, D) + line3(d, D, p)]);
-  const double gam = a.gamma;
-  // state at line position kk (the boundary rule along D)
-  auto Qat = [&](int kk, int c) {
-    int r[3] = {p[0], p[1], p[2]};
-    r[D] = bc_index(kk, n, d.bc[D]);
-    return a.U[c * d.np + u3idx(d, r[0], r[1], r[2])];
+  const int n = d.n[DIR];
+  const int nac = DIR == 0 ? d.n[1] : d.n[0];   // grouped index across the lines
+  const int nseg = (n + OUT - 1) / OUT, ngrp = (nac + NB - 1) / NB;
+  const long long tile = blockIdx.x;
+  const int seg = (int)(tile % nseg);
+  const long long rest = tile / nseg;
+  const int grp = (int)(rest % ngrp), cb = (int)(rest / ngrp);  // cb: the remaining index
+  const int ta = DIR == 0 ? threadIdx.x : threadIdx.y;           // along
+  const int tb = DIR == 0 ? threadIdx.y : threadIdx.x;           // across
+  const int la = grp * NB + tb;
+  const bool live = la < nac;
+  const int o0 = seg * OUT;
+  const int out = min(OUT, n - o0);
+  const int k = o0 + R_::LO + ta;
+  auto node = [&](int kk, int line, int p[3]) {
+    if (DIR == 0) { p[0] = kk; p[1] = line; p[2] = cb; }
+    else if (DIR == 1) { p[0] = line; p[1] = kk; p[2] = cb; }
+    else { p[0] = line; p[1] = cb; p[2] = kk; }
   };
-  auto kn = [&](int kk, double out[3]) {
-    int r[3] = {p[0], p[1], p[2]};
-    r[D] = kk;
-    const long long o = m3idx(d, r[0], r[1], r[2]);
-    for (int c = 0; c < 3; ++c) out[c] = a.M[(3 * D + c) * d.mplane + o];
-  };
-  const long long ro = r3idx(d, p[0], p[1], p[2]);
+  // stage the states of the segment
   {
-    double Q[5], k0[3], E[5];
-    for (int c = 0; c < 5; ++c) Q[c] = Qat(k, c);
-    kn(k, k0);
-    flux3(Q, k0, gam, E);
-    for (int c = 0; c < 5; ++c) {
-      a.rec[c * d.rplane + ro] = 0.5 * (E[c] + lam * Q[c]);
-      a.rec[(5 + c) * d.rplane + ro] = 0.5 * (E[c] - lam * Q[c]);
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int k0 = o0 + R_::LO - QL;
+    for (int e = tid; e < NQ * NB; e += NT) {
+      const int pos = DIR == 0 ? e % NQ : e / NB;
+      const int lb = DIR == 0 ? e / NQ : e % NB;
+      const int ln = grp * NB + lb;
+      if (ln < nac) {
+        int p[3];
+        node(bc_index(k0 + pos, n, d.bc[DIR]), ln, p);
+        const long long o = u3idx(d, p[0], p[1], p[2]);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) L.sq[c][LT::qi(lb, pos)] = a.U[c * d.np + o];
+      }
     }
   }
-  if (k < n + RG - 1) {
-    double k0[3], k1[3], mk[3], nv[3];
-    kn(k, k0);
-    kn(k + 1, k1);
+  __syncthreads();
+  double lam = 0.0;
+  if (live) {
+    int p[3];
+    node(0, la, p);
+    lam = a.alpha * __longlong_as_double((long long)a.lam[lam_off(d, DIR) + line3(d, DIR, p)]);
+  }
+  const double gam = a.gamma;
+  const int slot = LT::si(tb, ta);
+  const bool need_node = live && k >= o0 + Traits<SC>::NLO && k < o0 + out + Traits<SC>::NHI;
+  const bool need_mid = live && k >= o0 + Traits<SC>::MLO && k < o0 + out + Traits<SC>::MHI;
+  auto kn = [&](int kk, double v[3]) {
+    int p[3];
+    node(kk, la, p);
+    const long long o = m3idx(d, p[0], p[1], p[2]);
+    for (int c = 0; c < 3; ++c) v[c] = a.M[(3 * DIR + c) * d.mplane + o];
+  };
+  if (need_node) {
+    double Q[5], k0v[3], E[5];
+    for (int c = 0; c < 5; ++c) Q[c] = L.sq[c][LT::qi(tb, ta + QL)];
+    kn(k, k0v);
+    flux3(Q, k0v, gam, E);
+    for (int c = 0; c < 5; ++c) L.sh[c][slot] = E[c];
+  }
+  if (need_mid) {
+    double k0v[3], k1v[3], mk[3], nv[3];
+    kn(k, k0v);
+    kn(k + 1, k1v);
+    int p[3];
+    node(k, la, p);
     const long long o = m3idx(d, p[0], p[1], p[2]);
     for (int c = 0; c < 3; ++c) {
-      mk[c] = a.M[(10 + 3 * D + c) * d.mplane + o];
-      nv[c] = 0.5 * (k0[c] + k1[c]);
+      mk[c] = a.M[(10 + 3 * DIR + c) * d.mplane + o];
+      nv[c] = 0.5 * (k0v[c] + k1v[c]);
     }
     const double rn = rsqrt_(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
     for (int c = 0; c < 3; ++c) nv[c] *= rn;
-    auto q = [&](int s, int c) { return Qat(k - 3 + s, c); };
+    // window slot s = 0..7 is node k - 3 + s
+    auto q = [&](int s_, int c) { return L.sq[c][LT::qi(tb, ta + QL - 3 + s_)]; };
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
+      asm volatile("" ::: "memory");  // one side at a time (register pressure)
       double F[5];
       side_flux3<Traits<SC>::R>(q, side, nv, mk, lam, gam, a.eps, a.ppm, F);
-      for (int c = 0; c < 5; ++c) a.rec[(10 + 5 * side + c) * d.rplane + ro] = F[c];
+      for (int c = 0; c < 5; ++c) L.sh[5 + 5 * side + c][slot] = F[c];
     }
   }
-}
-
-// Differences of direction D at interior nodes.  mode 0: Racc = R; 1: Racc
-// += R; 2: dU/dt = -(Racc + R)/J^{-1}; 3: stage U_out = ca U0 + cb (U + dt
-// dU/dt) with dU/dt as in mode 2.
-template <int SC>
-__global__ void __launch_bounds__(256) s3_diff_kernel(S3Args a, int D, int mode) {
-  const Dims3& d = a.d;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= d.np) return;
-  if (!tag3_ok(d, a.M, SC)) return;
-  const int p[3] = {(int)(t % d.n[0]), (int)((t / d.n[0]) % d.n[1]), (int)(t / ((long long)d.n[0] * d.n[1]))};
-  auto ridx = [&](int kk) {
-    int r[3] = {p[0], p[1], p[2]};
-    r[D] = kk;
-    return r3idx(d, r[0], r[1], r[2]);
-  };
-  const int k = p[D];
+  __syncthreads();
+  if (!live || ta >= out) return;
+  const int i = o0 + ta;
+  const int hs = LT::si(tb, i - (o0 + R_::LO));
+  const int qs = LT::qi(tb, i - (o0 + R_::LO) + QL);
+  constexpr int S = DIR == 0 ? 1 : NB;
   double Rv[5];
+#pragma unroll
   for (int c = 0; c < 5; ++c) {
-    auto fp = [&](int kk) { return a.rec[c * d.rplane + ridx(kk)]; };
-    auto fm = [&](int kk) { return a.rec[(5 + c) * d.rplane + ridx(kk)]; };
-    auto Fp = [&](int kk) { return a.rec[(10 + c) * d.rplane + ridx(kk)]; };
-    auto Fm = [&](int kk) { return a.rec[(15 + c) * d.rplane + ridx(kk)]; };
-    Rv[c] = hflux<SC>(k, 1.0, fp, fm, Fp, Fm) - hflux<SC>(k - 1, 1.0, fp, fm, Fp, Fm);
+    const double* e = &L.sh[c][hs];
+    const double* qv = &L.sq[c][qs];
+    const double* gp = &L.sh[5 + c][hs];
+    const double* gm = &L.sh[10 + c][hs];
+    auto fp = [&](int kk) { return 0.5 * (e[(kk - i) * S] + lam * qv[(kk - i) * S]); };
+    auto fm = [&](int kk) { return 0.5 * (e[(kk - i) * S] - lam * qv[(kk - i) * S]); };
+    auto Fp = [&](int kk) { return gp[(kk - i) * S]; };
+    auto Fm = [&](int kk) { return gm[(kk - i) * S]; };
+    Rv[c] = hflux<SC>(i, 1.0, fp, fm, Fp, Fm) - hflux<SC>(i - 1, 1.0, fp, fm, Fp, Fm);
   }
+  int p[3];
+  node(i, la, p);
+  const long long t = u3idx(d, p[0], p[1], p[2]);
   if (mode == 0) {
     for (int c = 0; c < 5; ++c) a.Racc[c * d.np + t] = Rv[c];
     return;
@@ -459,8 +502,8 @@ __global__ void __launch_bounds__(256) s3_diff_kernel(S3Args a, int D, int mode)
   }
   const double dt = a.dt[0];
   for (int c = 0; c < 5; ++c) {
-    const double L = (a.Racc[c * d.np + t] + Rv[c]) * rj;
-    const double us = a.U[c * d.np + t] + dt * L;
+    const double Lv = (a.Racc[c * d.np + t] + Rv[c]) * rj;
+    const double us = a.U[c * d.np + t] + dt * Lv;
     a.out[c * d.np + t] = a.ca == 0.0 ? a.cb * us : a.ca * a.U0[c * d.np + t] + a.cb * us;
   }
 }
@@ -542,16 +585,14 @@ Dims3 dims3(const wiu_grid3* g) {
   d.np = (long long)g->nx * g->ny * g->nz;
   d.mp[0] = g->nx + 2 * GHOST; d.mp[1] = g->ny + 2 * GHOST;
   d.mplane = (long long)d.mp[0] * d.mp[1] * (g->nz + 2 * GHOST);
-  d.rp[0] = g->nx + 2 * RG; d.rp[1] = g->ny + 2 * RG;
-  d.rplane = (long long)d.rp[0] * d.rp[1] * (g->nz + 2 * RG);
   return d;
 }
 
 // Workspace: [status | line maxima | dt | big area], the big area holding
 // either the metric scratch (inner derivatives, nodal band) or the stepping
-// buffers (records, Racc, U1, U2).
+// buffers (Racc, U1, U2).
 struct Ws3 {
-  size_t lam, dt, big, metric_dx, metric_t, rec, racc, u1, u2, total;
+  size_t lam, dt, big, metric_dx, metric_t, racc, u1, u2, total;
   long long nlam;
 };
 
@@ -567,8 +608,7 @@ Ws3 ws3(const wiu_grid3* g) {
   const size_t tb = al3(10 * (size_t)(g->nx + 2 * B) * (g->ny + 2 * B) * (g->nz + 2 * B) * 8);
   w.metric_dx = w.big;
   w.metric_t = w.big + dxb;
-  w.rec = w.big;
-  w.racc = w.rec + al3(REC * (size_t)d.rplane * 8);
+  w.racc = w.big;
   w.u1 = w.racc + al3(5 * (size_t)d.np * 8);
   w.u2 = w.u1 + al3(5 * (size_t)d.np * 8);
   const size_t step_end = w.u2 + al3(5 * (size_t)d.np * 8);
@@ -585,16 +625,27 @@ bool params3_ok(const wiu_params* p) {
 
 dim3 lin_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
 
-template <int SC>
-hipError_t launch_pass3(const S3Args& a, int D, int mode, hipStream_t st) {
-  long long W = (long long)a.d.n[0] * a.d.n[1] * a.d.n[2] / a.d.n[D] * (a.d.n[D] + 2 * RG);
-  void* h = prof_open(WIU_K_ITEM3, st);
-  hipLaunchKernelGGL(s3_item_kernel<SC>, lin_grid(W), dim3(256), 0, st, a, D);
-  prof_close(h);
-  h = prof_open(WIU_K_DIFF3, st);
-  hipLaunchKernelGGL(s3_diff_kernel<SC>, lin_grid(a.d.np), dim3(256), 0, st, a, D, mode);
+// Tile shapes: xi 128 items x 2 lines (lanes along the line), eta and zeta
+// 32 items x 8 lines (lanes across the lines, along i).
+template <int SC, int DIR, int NA, int NB>
+hipError_t launch_sweep3_t(const S3Args& a, int mode, hipStream_t st) {
+  constexpr int OUT = NA - Range<SC>::EXTRA;
+  const int n = a.d.n[DIR];
+  const int nac = DIR == 0 ? a.d.n[1] : a.d.n[0];
+  const int nb = DIR == 2 ? a.d.n[1] : a.d.n[2];
+  const long long tiles = (long long)((n + OUT - 1) / OUT) * ((nac + NB - 1) / NB) * nb;
+  const dim3 block = DIR == 0 ? dim3(NA, NB) : dim3(NB, NA);
+  void* h = prof_open(WIU_K_SWEEP3, st);
+  hipLaunchKernelGGL((s3_sweep_kernel<SC, DIR, NA, NB>), dim3((unsigned)tiles), block, 0, st, a, mode);
   prof_close(h);
   return hipGetLastError();
+}
+
+template <int SC>
+hipError_t launch_pass3(const S3Args& a, int D, int mode, hipStream_t st) {
+  if (D == 0) return launch_sweep3_t<SC, 0, 128, 2>(a, mode, st);
+  if (D == 1) return launch_sweep3_t<SC, 1, 32, 8>(a, mode, st);
+  return launch_sweep3_t<SC, 2, 32, 8>(a, mode, st);
 }
 
 hipError_t pass3(int scheme, const S3Args& a, int D, int mode, hipStream_t st) {
@@ -663,7 +714,7 @@ int wiu3_rhs(const wiu_grid3* g, int scheme, const wiu_params* p, const double* 
   S3Args a;
   a.d = d; a.U = U; a.M = M; a.lam = (unsigned long long*)(base + w.lam);
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
-  a.rec = (double*)(base + w.rec); a.Racc = (double*)(base + w.racc); a.out = dUdt;
+  a.Racc = (double*)(base + w.racc); a.out = dUdt;
   a.U0 = nullptr; a.dt = nullptr; a.ca = 0.0; a.cb = 1.0; a.status = (int*)base;
   if (maxima3(d, U, M, p->gamma, (unsigned long long*)a.lam, w.nlam, a.status, st) != hipSuccess) return WIU_EHIP;
   for (int D = 0; D < 3; ++D)
@@ -695,7 +746,7 @@ int wiu3_rk3_step(const wiu_grid3* g, int scheme, const wiu_params* p, double* U
   S3Args a;
   a.d = d; a.M = M; a.lam = (unsigned long long*)(base + w.lam);
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
-  a.rec = (double*)(base + w.rec); a.Racc = (double*)(base + w.racc);
+  a.Racc = (double*)(base + w.racc);
   a.U0 = U; a.dt = dt; a.status = (int*)base;
   // U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U = 1/3 U + 2/3 (U2 + dt L(U2))
   const double* src[3] = {U, U1, U2};

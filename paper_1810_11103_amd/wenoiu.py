@@ -29,7 +29,7 @@ EXPORTS = [
     "wiu3_rk3_step",
     "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl", "wiu_step_record_bytes",
 ]
-KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3, "item3": 4, "diff3": 5}
+KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3, "sweep3": 4}
 
 
 class WiuGrid(ctypes.Structure):

@@ -480,6 +480,29 @@ def bounded_grid3(nx, ny, nz, box=(0.0, 1.0, 0.0, 1.0, 0.0, 1.0), A=0.0, seed=0,
                  ("transmissive",) * 3, (0.0, 0.0, 0.0), {"A": A, "seed": seed, "layers": layers})
 
 
+def mixed_grid3(nx, ny, nz, bc=("periodic", "transmissive", "periodic"), box=(0.0, 1.0, 0.0, 1.0, 0.0, 1.0),
+                A=0.0, seed=0, layers=4):
+    """Grid with some directions periodic (distinct nodes, spacing L/n) and
+    the others bounded (nodes on both ends, spacing L/(n-1), `layers`
+    uniform node layers along those boundaries), randomized as in
+    periodic_grid3 elsewhere."""
+    n = (nx, ny, nz)
+    per = [b == "periodic" for b in bc]
+    lo, hi = box[0::2], box[1::2]
+    h = [(hi[a] - lo[a]) / (n[a] if per[a] else n[a] - 1) for a in range(3)]
+    idx = _mesh3(nx, ny, nz)
+    d = (0.0, 0.0, 0.0)
+    if A > 0:
+        mask = np.ones(idx[0].shape, dtype=bool)
+        for a in range(3):
+            if not per[a]:
+                mask &= (idx[a] >= layers) & (idx[a] < n[a] - layers)
+        d = _jitter3(idx[0].shape, A, np.random.default_rng(seed), mask.astype(np.float64))
+    c = [np.ascontiguousarray(lo[a] + (idx[a] + d[a]) * h[a]) for a in range(3)]
+    return Grid3(c[0], c[1], c[2], tuple(bc), tuple((hi[a] - lo[a]) if per[a] else 0.0 for a in range(3)),
+                 {"A": A, "seed": seed})
+
+
 def wavy_grid3(nx, ny, nz, L=1.0, amp=0.04):
     """Smooth periodic curvilinear grid on [0, L)^3: every coordinate is
     displaced by amp L sin(2 pi a) sin(2 pi b) of the two other index

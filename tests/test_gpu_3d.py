@@ -50,6 +50,10 @@ def case(kind, seed=3):
     elif kind == "bounded":
         g = W.bounded_grid3(37, 33, 29, A=0.3, seed=seed)
         U = W.octant_state3(g)
+    elif kind == "mixed":
+        g = W.mixed_grid3(38, 34, 30, ("periodic", "transmissive", "periodic"), box=(0.0, 1.0, 0.0, 0.9, 0.0, 0.75),
+                          A=0.3, seed=seed)
+        U = W.octant_state3(g)
     else:
         g = W.wavy_grid3(36, 34, 30)
         U = W.entropy_wave3(g)
@@ -57,7 +61,7 @@ def case(kind, seed=3):
 
 
 @pytest.mark.parametrize("s", ["3-1MP", "5-2MP", "7-2MP"])
-@pytest.mark.parametrize("kind", ["periodic", "bounded", "wavy"])
+@pytest.mark.parametrize("kind", ["periodic", "bounded", "mixed", "wavy"])
 def test_metrics_parity(orc, wiu, s, kind):
     say("3-D metrics", s, kind)
     g, U = case(kind)
@@ -69,7 +73,7 @@ def test_metrics_parity(orc, wiu, s, kind):
 
 
 @pytest.mark.parametrize("s", ["3-2MP", "5-1MP", "5-2MP", "7-1MP", "7-6MP"])
-@pytest.mark.parametrize("kind", ["periodic", "bounded", "wavy"])
+@pytest.mark.parametrize("kind", ["periodic", "bounded", "mixed", "wavy"])
 def test_rhs_parity(orc, wiu, s, kind):
     say("3-D rhs", s, kind)
     g, U = case(kind)
@@ -82,7 +86,8 @@ def test_rhs_parity(orc, wiu, s, kind):
     assert np.all(err <= 1e-12), err
 
 
-@pytest.mark.parametrize("s,kind", [("5-2MP", "periodic"), ("3-1MP", "bounded"), ("7-4MP", "wavy")])
+@pytest.mark.parametrize("s,kind", [("5-2MP", "periodic"), ("3-1MP", "bounded"), ("7-4MP", "wavy"),
+                                    ("5-1MP", "mixed")])
 def test_rk3_step_parity(orc, wiu, s, kind):
     say("3-D rk3", s, kind)
     g, U = case(kind, seed=5)
@@ -102,7 +107,8 @@ def test_rk3_step_parity(orc, wiu, s, kind):
 @pytest.mark.parametrize("s", ["3-1MP", "5-2MP", "7-2MP"])
 def test_free_stream_preserved(wiu, s):
     for g in (W.wavy_grid3(30, 28, 26), W.periodic_grid3(32, 30, 28, A=0.3, seed=1),
-              W.bounded_grid3(31, 29, 27, A=0.3, seed=1)):
+              W.bounded_grid3(31, 29, 27, A=0.3, seed=1),
+              W.mixed_grid3(30, 28, 26, ("transmissive", "periodic", "transmissive"), A=0.3, seed=4)):
         U = W.uniform_flow3(g)
         sol = wiu.Solver3(g.x, g.y, g.z, s, g.bc, g.period)
         d = host(sol.rhs(dev(U)))

@@ -66,7 +66,9 @@ def test_cartesian_jacobian_equals_the_2d_one():
 @pytest.mark.parametrize("s", ["3-1MP", "5-2MP", "7-2MP", "7-6MP"])
 def test_free_stream_preserved(s):
     for g in (W.wavy_grid3(20, 18, 16), W.periodic_grid3(18, 16, 14, A=0.3, seed=1),
-              W.bounded_grid3(18, 16, 14, A=0.3, seed=1)):
+              W.bounded_grid3(18, 16, 14, A=0.3, seed=1),
+              W.mixed_grid3(18, 16, 14, ("periodic", "transmissive", "periodic"), A=0.3, seed=2),
+              W.mixed_grid3(16, 18, 14, ("transmissive", "periodic", "transmissive"), A=0.3, seed=3)):
         U = W.uniform_flow3(g)
         M = orc.metrics3(s, g.x, g.y, g.z, g.bc, g.period)
         assert np.abs(orc.rhs3(s, U, M, g.bc)).max() < 1e-11

@@ -385,10 +385,20 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
   const int n = d.n[DIR];
   const int nac = DIR == 0 ? d.n[1] : d.n[0];   // grouped index across the lines
   const int nseg = (n + OUT - 1) / OUT, ngrp = (nac + NB - 1) / NB;
-  const long long tile = blockIdx.x;
-  const int seg = (int)(tile % nseg);
-  const long long rest = tile / nseg;
-  const int grp = (int)(rest % ngrp), cb = (int)(rest / ngrp);  // cb: the remaining index
+  // XCD-aware order: consecutive logical tiles share an XCD's L2; for eta
+  // and zeta the line group (along i) varies fastest, so neighbouring tiles
+  // read the same rows and pages of the k-planes
+  const long long tile = xcd_remap(blockIdx.x, gridDim.x);
+  int seg, grp, cb;
+  if (DIR == 0) {
+    seg = (int)(tile % nseg);
+    const long long rest = tile / nseg;
+    grp = (int)(rest % ngrp); cb = (int)(rest / ngrp);
+  } else {
+    grp = (int)(tile % ngrp);
+    const long long rest = tile / ngrp;
+    seg = (int)(rest % nseg); cb = (int)(rest / nseg);
+  }
   const int ta = DIR == 0 ? threadIdx.x : threadIdx.y;           // along
   const int tb = DIR == 0 ? threadIdx.y : threadIdx.x;           // across
   const int la = grp * NB + tb;

@@ -146,3 +146,30 @@ def test_options_and_mismatched_metrics_rejected(wiu):
     ok.M = other.M  # metrics of another scheme
     ok.rhs(dev(U), out)
     assert ok.status() & wiu.ST_SCHEME
+
+
+def test_properties_at_the_benchmark_size(wiu):
+    """256^3, the size the 3-D leg of the benchmark times: uniform flow on the
+    randomized periodic grid stays uniform (round-off of dU/dt grows like
+    eps |F| / h, here h = 1/256), and the flux residual of the octant
+    Riemann state sums to zero over the periodic grid (conservation)."""
+    import torch
+    n = 256
+    g = W.periodic_grid3(n, n, n, A=0.2, seed=n)
+    sol = wiu.Solver3(g.x, g.y, g.z, "5-2MP", g.bc, g.period)
+    U = dev(W.uniform_flow3(g))
+    d = sol.rhs(U)
+    fsp = float(d.abs().max())
+    say("3-D 256^3 FSP", fsp)
+    assert sol.status() == 0
+    assert fsp < 1e-10
+    U.copy_(dev(W.octant_state3(g)))
+    del g
+    sol.rhs(U, d)
+    assert sol.status() == 0
+    J = sol.planes()[9, G:-G, G:-G, G:-G]
+    f = (J * d).reshape(5, -1)
+    tot = f.sum(dim=1).abs()
+    scale = f.abs().sum(dim=1)
+    say("3-D 256^3 conservation", (tot / scale).tolist())
+    assert bool(torch.all(tot < 1e-12 * scale))

@@ -326,7 +326,8 @@ int wiu_plan_destroy(wiu_plan* plan);
  * 2-D path (Sec. 2.4), the characteristic projection of Sec. 3.4 with five
  * eigenvectors along the unit direction (shear waves along t2 and t1: t1
  * the axis of the smallest component of n, ties to the later axis, made
- * orthogonal to n; t2 = t1 x n), TVD-RK3.  The paper's configuration only:
+ * orthogonal to n; t2 = t1 x n), TVD-RK3.  J^{-1} by Eq. 2.5 or Eq. 2.6
+ * (wiu3_metrics).  The paper's configuration only:
  * wiu_params must hold characteristic variables, alpha_h = 1, Jiang-Shu
  * weights and the Lax-Friedrichs split (else WIU_EINVAL).
  *
@@ -348,8 +349,11 @@ typedef struct {
 
 size_t wiu3_metrics_size(const wiu_grid3* g);
 size_t wiu3_workspace_bytes(const wiu_grid3* g);
-int wiu3_metrics(const wiu_grid3* g, int scheme, const double* x, const double* y, const double* z, double* M,
-                 void* ws, wiu_stream_t stream);
+/* jform: 5 for J^{-1} by Eq. 2.5, 1/3 sum_{m,l} n^_{m,l} D_m x_l, or 6 for
+ * Eq. 2.6, 1/3 sum_{m,l} D_m(n^_{m,l} x_l) (the paper allows either; the
+ * nine metric components are the same).  The tag records it. */
+int wiu3_metrics(const wiu_grid3* g, int scheme, int jform, const double* x, const double* y, const double* z,
+                 double* M, void* ws, wiu_stream_t stream);
 /* dU/dt of Eq. 2.2 (one direction pass per coordinate direction). */
 int wiu3_rhs(const wiu_grid3* g, int scheme, const wiu_params* p, const double* U, const double* M, double* dUdt,
              void* ws, wiu_stream_t stream);

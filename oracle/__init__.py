@@ -89,7 +89,7 @@ def lib():
         L.orc_mb_cfl_dt.argtypes = [_I, _P, _P, _D, _P, _P, _P, _P, _D, _P]
         L.orc3_metrics_size.restype = ctypes.c_longlong
         L.orc3_metrics_size.argtypes = [_P]
-        L.orc3_metrics.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P]
+        L.orc3_metrics.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _I]
         L.orc3_rhs.argtypes = [_I, _P, _P, _D, _D, _D, _I, _P, _P, _P]
         L.orc3_cfl_dt.restype = _D
         L.orc3_cfl_dt.argtypes = [_P, _D, _P, _P, _D]
@@ -494,15 +494,17 @@ def _i3(v):
     return np.ascontiguousarray(v, dtype=np.int32)
 
 
-def metrics3(scheme, x, y, z, bc=("periodic",) * 3, period=(0.0, 0.0, 0.0)):
-    """19 metric planes with the ghost band: shape (19, nz+2G, ny+2G, nx+2G)."""
+def metrics3(scheme, x, y, z, bc=("periodic",) * 3, period=(0.0, 0.0, 0.0), jform=5):
+    """19 metric planes with the ghost band: shape (19, nz+2G, ny+2G, nx+2G);
+    jform 5 or 6: the Jacobian by Eq. 2.5 or Eq. 2.6."""
     x, y, z = _f64(x), _f64(y), _f64(z)
     nz, ny, nx = x.shape
     n = _i3([nx, ny, nz])
     b = _i3([bc_id(v) for v in bc])
     L = _f64(period)
     M = np.zeros((19, nz + 2 * G, ny + 2 * G, nx + 2 * G))
-    if lib().orc3_metrics(scheme_id(scheme), _ptr(n), _ptr(b), _ptr(L), _ptr(x), _ptr(y), _ptr(z), _ptr(M)):
+    if lib().orc3_metrics(scheme_id(scheme), _ptr(n), _ptr(b), _ptr(L), _ptr(x), _ptr(y), _ptr(z), _ptr(M),
+                          int(jform)):
         raise ValueError("orc3_metrics failed")
     return M
 

@@ -91,11 +91,17 @@ inline void step3(int d, int m, int& i, int& j, int& k) {
   if (d == 0) i += m; else if (d == 1) j += m; else k += m;
 }
 
-// Fill all 19 metric planes, ghost band included.
+// Fill all 19 metric planes, ghost band included.  jform selects the
+// Jacobian: 5 for Eq. 2.5, J^{-1} = 1/3 sum_{m,l} n^_{m,l} D_m x_l, or 6 for
+// Eq. 2.6, J^{-1} = 1/3 sum_{m,l} D_m(n^_{m,l} x_l), with x_l taken relative
+// to the node (sum_m D_m n^_{m,l} = 0 holds discretely for Eq. 2.4, so the
+// shift changes only the rounding).
 inline void compute_metrics3(Scheme sc, const Grid3& g, const double* x, const double* y, const double* z,
-                             double* M) {
+                             double* M, int jform = 5) {
   Coords3 C{g, {x, y, z}};
-  const int B = G + (seventh_order(sc) ? 4 : 3);  // nodal band for the midpoint interpolation
+  // nodal band for the midpoint interpolation, or for Eq. 2.6 around the
+  // ghost band (the operator below is evaluated on 8 nodes each side)
+  const int B = jform == 6 ? G + 8 : G + (seventh_order(sc) ? 4 : 3);
   const int EI = B + 8;                           // inner derivatives: the outer operator's reach
   // the scheme's operator along d at (i, j, k) of a function f given on nodes
   auto D = [&](int d, int i, int j, int k, auto f) {
@@ -162,6 +168,20 @@ inline void compute_metrics3(Scheme sc, const Grid3& g, const double* x, const d
       for (int i = -G; i < g.n[0] + G; ++i) {
         const size_t o = mv.off(i, j, k);
         for (int p = 0; p < 10; ++p) M[p * P + o] = (double)T[p](i, j, k);
+        if (jform == 6) {
+          int w[3] = {i, j, k};
+          for (int d = 0; d < 3; ++d)
+            if (g.bc[d] == PERIODIC) w[d] = wrap(w[d], g.n[d]);
+          long double J = 0.0L;
+          for (int m = 0; m < 3; ++m)
+            for (int l = 0; l < 3; ++l) {
+              const long double x0 = C.at(l, w[0], w[1], w[2]);
+              J += D(m, w[0], w[1], w[2], [&](int a, int b, int e) {
+                return T[3 * m + l](a, b, e) * (C.at(l, a, b, e) - x0);
+              });
+            }
+          M[9 * P + o] = (double)(J / 3.0L);
+        }
         for (int m = 0; m < 3; ++m)
           for (int l = 0; l < 3; ++l)
             M[(10 + 3 * m + l) * P + o] = interp_mid(sc, [&](int s) {

@@ -497,9 +497,9 @@ long long orc3_metrics_size(const int* n) {
 }
 
 int orc3_metrics(int scheme, const int* n, const int* bc, const double* L, const double* x, const double* y,
-                 const double* z, double* M) {
-  if (bad_scheme(scheme) || bad_grid3(n, bc)) return -1;
-  compute_metrics3((Scheme)scheme, make_grid3(n, bc, L), x, y, z, M);
+                 const double* z, double* M, int jform) {
+  if (bad_scheme(scheme) || bad_grid3(n, bc) || (jform != 5 && jform != 6)) return -1;
+  compute_metrics3((Scheme)scheme, make_grid3(n, bc, L), x, y, z, M, jform);
   return 0;
 }
 

@@ -164,14 +164,17 @@ __global__ void m3_nodal_kernel(Dims3 d, MetricStencil ms, int B, int E, Coord3 
 }
 
 // Stored metrics: nodal planes and midpoint interpolation in each metric's
-// own direction, ghost band included, plus the tag.
+// own direction, ghost band included, plus the tag.  jform 6 replaces
+// J^{-1} by Eq. 2.6, 1/3 sum_{m,l} D_m(n^_{m,l} x_l) with x_l relative to
+// the (wrapped) node, which needs the nodal band B >= GHOST + METRIC_REACH.
 __global__ void m3_band_kernel(Dims3 d, int scheme, int B, const double* __restrict__ T, double* __restrict__ M,
-                               int* __restrict__ status) {
+                               int* __restrict__ status, int jform, MetricStencil ms, Coord3 X) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
     double* tag = M + NP3 * d.mplane;
     tag[0] = TAG_MAGIC3; tag[1] = (double)scheme; tag[2] = (double)d.n[0]; tag[3] = (double)d.n[1];
-    tag[4] = (double)d.n[2]; tag[5] = (double)(d.bc[0] + 2 * d.bc[1] + 4 * d.bc[2]); tag[6] = 1.0; tag[7] = 0.0;
+    tag[4] = (double)d.n[2]; tag[5] = (double)(d.bc[0] + 2 * d.bc[1] + 4 * d.bc[2]); tag[6] = 1.0;
+    tag[7] = (double)jform;
   }
   if (t >= d.mplane) return;
   const int p[3] = {(int)(t % d.mp[0]) - GHOST, (int)((t / d.mp[0]) % d.mp[1]) - GHOST,
@@ -182,6 +185,24 @@ __global__ void m3_band_kernel(Dims3 d, int scheme, int B, const double* __restr
     return T[plane * TP + ((long long)(k + B) * V1 + (j + B)) * V0 + (i + B)];
   };
   for (int q = 0; q < 10; ++q) M[q * d.mplane + t] = tv(q, p[0], p[1], p[2]);
+  if (jform == 6) {
+    int w[3] = {p[0], p[1], p[2]};
+    for (int a = 0; a < 3; ++a)
+      if (d.bc[a] == WIU_BC_PERIODIC) w[a] = bc_index(w[a], d.n[a], 0);
+    double J = 0.0;
+    for (int m = 0; m < 3; ++m)
+      for (int l = 0; l < 3; ++l)
+        for (int k = 1; k <= METRIC_REACH; ++k) {
+          const double ck = ms.d[k - 1];
+          if (ck == 0.0) continue;
+          int p1[3] = {w[0], w[1], w[2]}, p0[3] = {w[0], w[1], w[2]};
+          p1[m] += k;
+          p0[m] -= k;
+          J += ck * (tv(3 * m + l, p1[0], p1[1], p1[2]) * c3_diff(d, X.x[l], l, p1, w) -
+                     tv(3 * m + l, p0[0], p0[1], p0[2]) * c3_diff(d, X.x[l], l, p0, w));
+        }
+    M[9 * d.mplane + t] = J * (1.0 / 3.0);
+  }
   const bool eight = scheme >= 4;
   for (int m = 0; m < 3; ++m)
     for (int l = 0; l < 3; ++l) {
@@ -197,7 +218,7 @@ __global__ void m3_band_kernel(Dims3 d, int scheme, int B, const double* __restr
                       (1.0 / 256.0);
     }
   if (p[0] >= 0 && p[0] < d.n[0] && p[1] >= 0 && p[1] < d.n[1] && p[2] >= 0 && p[2] < d.n[2]) {
-    const double j = tv(9, p[0], p[1], p[2]);
+    const double j = M[9 * d.mplane + t];
     if (!(j > 0.0) || !(j < 1.0e300)) atomicOr(status, ST_JACOBIAN);
   }
 }
@@ -613,7 +634,7 @@ Ws3 ws3(const wiu_grid3* g) {
   w.lam = A3;
   w.dt = w.lam + al3(w.nlam * 8);
   w.big = w.dt + A3;
-  const int B = GHOST + 4, E = B + 8;
+  const int B = GHOST + METRIC_REACH, E = B + 8;  // the widest band (Eq. 2.6)
   const size_t dxb = al3(9 * (size_t)(g->nx + 2 * E) * (g->ny + 2 * E) * (g->nz + 2 * E) * 8);
   const size_t tb = al3(10 * (size_t)(g->nx + 2 * B) * (g->ny + 2 * B) * (g->nz + 2 * B) * 8);
   w.metric_dx = w.big;
@@ -693,9 +714,10 @@ size_t wiu3_metrics_size(const wiu_grid3* g) {
 
 size_t wiu3_workspace_bytes(const wiu_grid3* g) { return grid3_ok(g) ? ws3(g).total : 0; }
 
-int wiu3_metrics(const wiu_grid3* g, int scheme, const double* x, const double* y, const double* z, double* M,
-                 void* ws, wiu_stream_t stream) {
-  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !x || !y || !z || !M || !ws) return WIU_EINVAL;
+int wiu3_metrics(const wiu_grid3* g, int scheme, int jform, const double* x, const double* y, const double* z,
+                 double* M, void* ws, wiu_stream_t stream) {
+  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || (jform != 5 && jform != 6) || !x || !y || !z || !M || !ws)
+    return WIU_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const Dims3 d = dims3(g);
   const Ws3 w = ws3(g);
@@ -704,13 +726,13 @@ int wiu3_metrics(const wiu_grid3* g, int scheme, const double* x, const double* 
   double* T = (double*)(base + w.metric_t);
   int* status = (int*)base;
   const MetricStencil ms = metric_stencil(scheme, 1.0);
-  const int B = metric_band(scheme), E = B + 8;
+  const int B = jform == 6 ? GHOST + METRIC_REACH : metric_band(scheme), E = B + 8;
   Coord3 X{{x, y, z}};
   const long long ND = (long long)(d.n[0] + 2 * E) * (d.n[1] + 2 * E) * (d.n[2] + 2 * E);
   const long long NT = (long long)(d.n[0] + 2 * B) * (d.n[1] + 2 * B) * (d.n[2] + 2 * B);
   hipLaunchKernelGGL(m3_inner_kernel, lin_grid(ND), dim3(256), 0, st, d, ms, E, X, Dx);
   hipLaunchKernelGGL(m3_nodal_kernel, lin_grid(NT), dim3(256), 0, st, d, ms, B, E, X, Dx, T);
-  hipLaunchKernelGGL(m3_band_kernel, lin_grid(d.mplane), dim3(256), 0, st, d, scheme, B, T, M, status);
+  hipLaunchKernelGGL(m3_band_kernel, lin_grid(d.mplane), dim3(256), 0, st, d, scheme, B, T, M, status, jform, ms, X);
   return rc3(hipGetLastError());
 }
 

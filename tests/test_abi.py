@@ -169,5 +169,7 @@ def test_3d_grids_and_options_are_validated(wiu):
         P = wiu.make_params(**opts)
         rc = wiu.lib.wiu3_rhs(ctypes.byref(g), 3, ctypes.byref(P), dummy, dummy, dummy, dummy, None)
         assert rc == wiu.WIU_EINVAL
+    # the Jacobian form is 5 or 6
+    assert wiu.lib.wiu3_metrics(ctypes.byref(g), 3, 4, dummy, dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL
     P = wiu.make_params()
     assert wiu.lib.wiu3_rhs(ctypes.byref(g), 8, ctypes.byref(P), dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL

@@ -173,3 +173,25 @@ def test_properties_at_the_benchmark_size(wiu):
     scale = f.abs().sum(dim=1)
     say("3-D 256^3 conservation", (tot / scale).tolist())
     assert bool(torch.all(tot < 1e-12 * scale))
+
+
+@pytest.mark.parametrize("s,kind", [("5-2MP", "periodic"), ("3-1MP", "bounded"), ("7-1MP", "mixed")])
+def test_jacobian_by_eq_2_6_parity(orc, wiu, s, kind):
+    # (states for which one CFL-0.5 step stays physical: the octant problem on
+    # the strongly randomized bounded grid loses positivity with 3-2MP, in the
+    # oracle as on the GPU, whatever the Jacobian)
+    say("3-D Eq. 2.6", s, kind)
+    g, U = case(kind, seed=5)
+    Mo = orc.metrics3(s, g.x, g.y, g.z, g.bc, g.period, jform=6)
+    sol = wiu.Solver3(g.x, g.y, g.z, s, g.bc, g.period, jform=6)
+    Mg = host(sol.planes())
+    for p in range(19):
+        assert np.abs(Mg[p] - Mo[p]).max() <= 1e-13 * np.abs(Mo[p]).max(), p
+    dt = orc.cfl_dt3(U, Mo, 0.5)
+    ref = orc.rk3_step3(s, U, Mo, dt, g.bc)
+    Ud = dev(U)
+    sol.rk3_step(Ud, dt)
+    assert sol.status() == 0
+    err = normwise(host(Ud) - U, ref - U)
+    assert np.all(err <= 1e-11), err
+

@@ -124,3 +124,24 @@ def test_design_order_on_a_smooth_grid(s, order):
         errs.append(np.abs(r[0] - exact).max())
     p = np.log(errs[-2] / errs[-1]) / np.log(ns[-1] / ns[-2])
     assert p > order - 0.5, (errs, p)
+
+
+def test_jacobian_by_eq_2_6():
+    """Eq. 2.6 changes J^{-1} only: exact on a Cartesian grid, the other 18
+    planes identical to Eq. 2.5's, and on a smooth grid the two forms of
+    J^{-1} approach each other as the grid is refined (both approximate the
+    same Jacobian, their difference at the operator's order)."""
+    g = W.periodic_grid3(10, 10, 10, box=(0.0, 1.0, 0.0, 2.0, 0.0, 3.0))
+    M6 = orc.metrics3("5-2MP", g.x, g.y, g.z, g.bc, g.period, jform=6)
+    assert np.allclose(M6[9], 0.1 * 0.2 * 0.3, rtol=1e-14, atol=0.0)
+    for g in (W.periodic_grid3(14, 12, 10, A=0.3, seed=1), W.bounded_grid3(14, 12, 12, A=0.3, seed=1)):
+        M5 = orc.metrics3("5-2MP", g.x, g.y, g.z, g.bc, g.period, jform=5)
+        M6 = orc.metrics3("5-2MP", g.x, g.y, g.z, g.bc, g.period, jform=6)
+        assert np.array_equal(np.delete(M5, 9, axis=0), np.delete(M6, 9, axis=0))
+    diffs = []
+    for n in (12, 24):
+        g = W.wavy_grid3(n, n, n)
+        M5 = orc.metrics3("5-2MP", g.x, g.y, g.z, g.bc, g.period, jform=5)
+        M6 = orc.metrics3("5-2MP", g.x, g.y, g.z, g.bc, g.period, jform=6)
+        diffs.append(np.abs(M5[9] - M6[9]).max() / np.abs(M5[9]).max())
+    assert np.log2(diffs[0] / diffs[1]) > 4.5, diffs

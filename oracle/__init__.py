@@ -90,10 +90,10 @@ def lib():
         L.orc3_metrics_size.restype = ctypes.c_longlong
         L.orc3_metrics_size.argtypes = [_P]
         L.orc3_metrics.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _I]
-        L.orc3_rhs.argtypes = [_I, _P, _P, _D, _D, _D, _I, _P, _P, _P]
+        L.orc3_rhs.argtypes = [_I, _P, _P, _P, _P, _D, _D, _D, _I, _P, _P, _P]
         L.orc3_cfl_dt.restype = _D
         L.orc3_cfl_dt.argtypes = [_P, _D, _P, _P, _D]
-        L.orc3_rk3_step.argtypes = [_I, _P, _P, _D, _D, _D, _I, _P, _P, _D]
+        L.orc3_rk3_step.argtypes = [_I, _P, _P, _P, _P, _D, _D, _D, _I, _P, _P, _D]
         L.orc3_eigenvectors.restype = None
         L.orc3_eigenvectors.argtypes = [_P, _D, _P, _P, _P]
         L.orc3_flux_hat.restype = None
@@ -509,12 +509,23 @@ def metrics3(scheme, x, y, z, bc=("periodic",) * 3, period=(0.0, 0.0, 0.0), jfor
     return M
 
 
-def rhs3(scheme, U, M, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+def _sides3(sides, fixed):
+    """(side kinds, fixed states) of the six sides (x lo, x hi, y lo, y hi,
+    z lo, z hi) as ctypes pointers, or nulls for all-transmissive."""
+    if sides is None:
+        return None, None
+    k = np.ascontiguousarray([SIDES[v] if isinstance(v, str) else int(v) for v in sides], dtype=np.int32)
+    f = np.zeros((6, 5)) if fixed is None else np.ascontiguousarray(fixed, dtype=np.float64).reshape(6, 5)
+    _sides3.keep = (k, f)
+    return k.ctypes.data_as(ctypes.c_void_p), f.ctypes.data_as(ctypes.c_void_p)
+
+
+def rhs3(scheme, U, M, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, sides=None, fixed=None):
     U, M = _f64(U), _f64(M)
     _, nz, ny, nx = U.shape
     out = np.zeros_like(U)
-    if lib().orc3_rhs(scheme_id(scheme), _ptr(_i3([nx, ny, nz])), _ptr(_i3([bc_id(v) for v in bc])), gamma, alpha,
-                      eps, ppm, _ptr(U), _ptr(M), _ptr(out)):
+    if lib().orc3_rhs(scheme_id(scheme), _ptr(_i3([nx, ny, nz])), _ptr(_i3([bc_id(v) for v in bc])),
+                      *_sides3(sides, fixed), gamma, alpha, eps, ppm, _ptr(U), _ptr(M), _ptr(out)):
         raise ValueError("orc3_rhs failed")
     return out
 
@@ -525,12 +536,12 @@ def cfl_dt3(U, M, cfl, gamma=1.4):
     return lib().orc3_cfl_dt(_ptr(_i3([nx, ny, nz])), gamma, _ptr(U), _ptr(M), float(cfl))
 
 
-def rk3_step3(scheme, U, M, dt, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1):
+def rk3_step3(scheme, U, M, dt, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, sides=None, fixed=None):
     U = _f64(U).copy()
     M = _f64(M)
     _, nz, ny, nx = U.shape
-    if lib().orc3_rk3_step(scheme_id(scheme), _ptr(_i3([nx, ny, nz])), _ptr(_i3([bc_id(v) for v in bc])), gamma,
-                           alpha, eps, ppm, _ptr(U), _ptr(M), float(dt)):
+    if lib().orc3_rk3_step(scheme_id(scheme), _ptr(_i3([nx, ny, nz])), _ptr(_i3([bc_id(v) for v in bc])),
+                           *_sides3(sides, fixed), gamma, alpha, eps, ppm, _ptr(U), _ptr(M), float(dt)):
         raise ValueError("orc3_rk3_step failed")
     return U
 

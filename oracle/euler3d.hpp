@@ -30,6 +30,13 @@ struct Grid3 {
   int n[3];
   Bc bc[3];
   double L[3];  // periods of periodic directions
+  // rules beyond the sides of non-periodic directions (x lo, x hi, y lo,
+  // y hi, z lo, z hi), as in 2-D: transmissive, reflecting slip wall (mirror
+  // image about the boundary node, momentum along the boundary node's unit
+  // metric direction reversed) or a fixed state
+  int side[6] = {SIDE_TRANSMISSIVE, SIDE_TRANSMISSIVE, SIDE_TRANSMISSIVE,
+                 SIDE_TRANSMISSIVE, SIDE_TRANSMISSIVE, SIDE_TRANSMISSIVE};
+  double fixed[6][5] = {};
 };
 
 // Extended coordinates X_c(i, j, k) for any integers, in extended precision:
@@ -388,16 +395,32 @@ inline void rhs3(Scheme sc, const Params& pr, const Grid3& g, const double* U, c
           p[d] = k; p[a] = la; p[b] = lb;
           i = p[0]; j = p[1]; kk = p[2];
         };
-        auto Q = [&](int k, int q) {
-          int kk2 = g.bc[d] == PERIODIC ? wrap(k, n) : std::min(std::max(k, 0), n - 1);
+        auto at = [&](int k, int q) {
           int i, j, kz;
-          node(kk2, i, j, kz);
+          node(k, i, j, kz);
           return U[q * NP + idx(i, j, kz)];
         };
         auto K = [&](int w, int k) {
           int i, j, kz;
           node(k, i, j, kz);
           return w < 3 ? mv(3 * d + w, i, j, kz) : mv(10 + 3 * d + (w - 3), i, j, kz);
+        };
+        auto Q = [&](int k, int q) -> double {
+          if (g.bc[d] == PERIODIC) return at(wrap(k, n), q);
+          if (k >= 0 && k < n) return at(k, q);
+          const int sd = 2 * d + (k < 0 ? 0 : 1);
+          const int kb = k < 0 ? 0 : n - 1;
+          if (g.side[sd] == SIDE_FIXED) return g.fixed[sd][q];
+          if (g.side[sd] == SIDE_WALL) {
+            const int km = std::min(std::max(2 * kb - k, 0), n - 1);
+            if (q == 0 || q == 4) return at(km, q);
+            double nv[3] = {K(0, kb), K(1, kb), K(2, kb)};
+            const double nn = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            for (int c = 0; c < 3; ++c) nv[c] /= nn;
+            const double mn = at(km, 1) * nv[0] + at(km, 2) * nv[1] + at(km, 3) * nv[2];
+            return at(km, q) - 2.0 * mn * nv[q - 1];
+          }
+          return at(kb, q);
         };
         std::vector<double> R(5 * n);
         line_residual3<double>(sc, pr, n, Q, K, R.data(), nullptr);

@@ -479,9 +479,15 @@ int orc_mb_cfl_dt(int nblocks, const int* idesc, const double* fdesc, double gam
 // configuration only (characteristic variables, Lax-Friedrichs, alpha = 1).
 
 namespace {
-Grid3 make_grid3(const int* n, const int* bc, const double* L) {
+// side[6] and fixed[6][5] may be null (all transmissive)
+Grid3 make_grid3(const int* n, const int* bc, const double* L, const int* side = nullptr,
+                 const double* fixed = nullptr) {
   Grid3 g;
   for (int d = 0; d < 3; ++d) { g.n[d] = n[d]; g.bc[d] = (Bc)bc[d]; g.L[d] = L[d]; }
+  for (int k = 0; k < 6; ++k) {
+    g.side[k] = side ? side[k] : SIDE_TRANSMISSIVE;
+    for (int q = 0; q < 5; ++q) g.fixed[k][q] = fixed ? fixed[5 * k + q] : 0.0;
+  }
   return g;
 }
 const double kNoPeriod[3] = {0.0, 0.0, 0.0};  // rhs3 reads no coordinates
@@ -503,10 +509,10 @@ int orc3_metrics(int scheme, const int* n, const int* bc, const double* L, const
   return 0;
 }
 
-int orc3_rhs(int scheme, const int* n, const int* bc, double gamma, double alpha, double eps, int ppm,
-             const double* U, const double* M, double* out) {
+int orc3_rhs(int scheme, const int* n, const int* bc, const int* side, const double* fixed, double gamma,
+             double alpha, double eps, int ppm, const double* U, const double* M, double* out) {
   if (bad_scheme(scheme) || bad_grid3(n, bc)) return -1;
-  rhs3((Scheme)scheme, make_params(gamma, alpha, eps, ppm), make_grid3(n, bc, kNoPeriod), U, M, out);
+  rhs3((Scheme)scheme, make_params(gamma, alpha, eps, ppm), make_grid3(n, bc, kNoPeriod, side, fixed), U, M, out);
   return 0;
 }
 
@@ -515,10 +521,11 @@ double orc3_cfl_dt(const int* n, double gamma, const double* U, const double* M,
   return cfl_dt3(make_params(gamma, 1.1, 1e-40, 1), make_grid3(n, bc, kNoPeriod), U, M, cfl);
 }
 
-int orc3_rk3_step(int scheme, const int* n, const int* bc, double gamma, double alpha, double eps, int ppm,
-                  double* U, const double* M, double dt) {
+int orc3_rk3_step(int scheme, const int* n, const int* bc, const int* side, const double* fixed, double gamma,
+                  double alpha, double eps, int ppm, double* U, const double* M, double dt) {
   if (bad_scheme(scheme) || bad_grid3(n, bc)) return -1;
-  rk3_step3((Scheme)scheme, make_params(gamma, alpha, eps, ppm), make_grid3(n, bc, kNoPeriod), U, M, dt);
+  rk3_step3((Scheme)scheme, make_params(gamma, alpha, eps, ppm), make_grid3(n, bc, kNoPeriod, side, fixed), U, M,
+            dt);
   return 0;
 }
 

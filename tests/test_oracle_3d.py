@@ -145,3 +145,81 @@ def test_jacobian_by_eq_2_6():
         M6 = orc.metrics3("5-2MP", g.x, g.y, g.z, g.bc, g.period, jform=6)
         diffs.append(np.abs(M5[9] - M6[9]).max() / np.abs(M5[9]).max())
     assert np.log2(diffs[0] / diffs[1]) > 4.5, diffs
+
+
+def _mirror_data3(x, y, z, axis):
+    """rho, p and the two tangential velocities even, the normal velocity odd
+    about both ends (0 and 1) of coordinate `axis`; periodic in the others."""
+    c = (x, y, z)
+    a = c[axis]
+    b, e = c[(axis + 1) % 3], c[(axis + 2) % 3]
+    rho = 1.0 + 0.2 * np.cos(np.pi * a) * (1.0 + 0.3 * np.sin(2 * np.pi * b) * np.cos(2 * np.pi * e))
+    un = 0.4 * np.sin(np.pi * a) + 0.1 * np.sin(3 * np.pi * a)
+    ub = 0.2 * np.cos(np.pi * a) * np.cos(2 * np.pi * b)
+    ue = 0.15 * np.cos(2 * np.pi * a) * np.sin(2 * np.pi * e)
+    p = 1.0 + 0.15 * np.cos(2 * np.pi * a) + 0.05 * np.sin(2 * np.pi * b)
+    vel = [None] * 3
+    vel[axis], vel[(axis + 1) % 3], vel[(axis + 2) % 3] = un, ub, ue
+    return W.conservative3(rho, *vel, p)
+
+
+def _box3(n, axis, two=False):
+    """Nodes along `axis`: 0..1 (n+1 nodes) or, two=True, -1 .. 1-h (2n
+    nodes); the other two axes periodic on [0, 1) with 10 and 8 nodes."""
+    counts = [10, 8, 12]
+    counts[axis] = 2 * n if two else n + 1
+    kk, jj, ii = np.meshgrid(*[np.arange(counts[d], dtype=float) for d in (2, 1, 0)], indexing="ij")
+    idx = (ii, jj, kk)
+    crd = []
+    for d in range(3):
+        if d == axis:
+            crd.append((-1.0 + idx[d] / n) if two else idx[d] / n)
+        else:
+            crd.append(idx[d] / counts[d])
+    return [np.ascontiguousarray(v) for v in crd]
+
+
+@pytest.mark.parametrize("s", ["3-1MP", "5-2MP"])
+@pytest.mark.parametrize("axis", [0, 2])
+def test_walls_equal_the_mirror_extended_periodic_problem_3d(s, axis):
+    """Walls at both ends of one axis (Sec. 6 boundaries in 3-D; the library's
+    rule, as in 2-D) give the residual and RK3 steps of the periodic problem
+    twice as long with mirror-symmetric data, on the shared nodes."""
+    N = 16
+    xw, yw, zw = _box3(N, axis)
+    bcw = ["periodic"] * 3
+    bcw[axis] = "transmissive"
+    per = [1.0, 1.0, 1.0]
+    per[axis] = 0.0
+    sides = ["transmissive"] * 6
+    sides[2 * axis] = sides[2 * axis + 1] = "wall"
+    Uw = _mirror_data3(xw, yw, zw, axis)
+    Mw = orc.metrics3(s, xw, yw, zw, bcw, per)
+    xp, yp, zp = _box3(N, axis, two=True)
+    perp = [1.0, 1.0, 1.0]
+    perp[axis] = 2.0
+    Up = _mirror_data3(xp, yp, zp, axis)
+    Mp = orc.metrics3(s, xp, yp, zp, ("periodic",) * 3, perp)
+    idx = np.r_[np.arange(N, 2 * N), 0]
+    take = lambda a: np.take(a, idx, axis=3 - axis)
+    dw = orc.rhs3(s, Uw, Mw, bcw, sides=sides)
+    dp = orc.rhs3(s, Up, Mp, ("periodic",) * 3)
+    assert np.abs(dw - take(dp)).max() <= 1e-13 * np.abs(dp).max()
+    for _ in range(3):
+        Uw = orc.rk3_step3(s, Uw, Mw, 2e-3, bcw, sides=sides)
+        Up = orc.rk3_step3(s, Up, Mp, 2e-3, ("periodic",) * 3)
+    assert np.abs(Uw - take(Up)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("s", ["3-2MP", "5-2MP", "7-1MP"])
+def test_free_stream_with_walls_and_inflow_3d(s):
+    """Mach-2 flow along x on a randomized bounded grid with uniform boundary
+    layers: walls on the y and z sides (parallel to the flow), the same state
+    fixed on x low, transmissive on x high."""
+    g = W.bounded_grid3(20, 16, 14, A=0.2, seed=6)
+    U = W.uniform_flow3(g, mach=2.0, direction=(1.0, 0.0, 0.0))
+    fixed = np.zeros((6, 5))
+    fixed[0] = U[:, 0, 0, 0]
+    M = orc.metrics3(s, g.x, g.y, g.z, g.bc, g.period)
+    d = orc.rhs3(s, U, M, g.bc, sides=("fixed", "transmissive", "wall", "wall", "wall", "wall"), fixed=fixed)
+    assert np.abs(d).max() < 1e-11

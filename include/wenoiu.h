@@ -338,13 +338,18 @@ int wiu_plan_destroy(wiu_plan* plan);
  * followed by an 8-double tag; the sweeps latch WIU_ST_SCHEME and write
  * nothing if the tag does not match.  ws: wiu3_workspace_bytes() bytes
  * (status word first, read with wiu_status); zero it once with
- * wiu_workspace_init.  Directions are periodic or transmissive (the
- * boundary node's state beyond the end, coordinates extended linearly).
+ * wiu_workspace_init.  Directions are periodic or bounded; beyond a bounded
+ * end the side's rule of wiu_grid (transmissive, reflecting wall with the
+ * momentum along the boundary node's metric direction reversed, or a fixed
+ * state; invalid rules or non-physical fixed states make the grid invalid),
+ * coordinates extended linearly.
  * All calls are asynchronous on `stream`. */
 typedef struct {
   int nx, ny, nz;
   int bc[3];            /* WIU_BC_* of x, y, z */
   double period[3];     /* periods of periodic directions */
+  int side[6];          /* WIU_SIDE_TRANSMISSIVE / _WALL / _FIXED of x low .. z high (0: transmissive) */
+  double fixed[6][5];   /* conservative state beyond a WIU_SIDE_FIXED side */
 } wiu_grid3;
 
 size_t wiu3_metrics_size(const wiu_grid3* g);

@@ -353,6 +353,10 @@ struct S3Args {
   const double* dt;                // device time step
   double ca, cb;
   int* status;
+  // rules beyond the sides of non-periodic directions (x lo .. z hi):
+  // WIU_SIDE_TRANSMISSIVE, _WALL or _FIXED with the state `fixed`
+  int side[6];
+  double fixed[6][5];
 };
 
 WIU_DEV long long lam_off(const Dims3& d, int D) {
@@ -441,11 +445,37 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
       const int lb = DIR == 0 ? e / NQ : e % NB;
       const int ln = grp * NB + lb;
       if (ln < nac) {
-        int p[3];
-        node(bc_index(k0 + pos, n, d.bc[DIR]), ln, p);
-        const long long o = u3idx(d, p[0], p[1], p[2]);
+        // beyond a non-periodic end the side's rule: transmissive (boundary
+        // node), reflecting wall (mirror node, momentum along the boundary
+        // node's unit metric direction reversed) or a fixed state
+        const int kr = k0 + pos;
+        const bool out_of = d.bc[DIR] != WIU_BC_PERIODIC && (kr < 0 || kr >= n);
+        const int sd = 2 * DIR + (kr < 0 ? 0 : 1);
+        const int rule = out_of ? a.side[sd] : WIU_SIDE_TRANSMISSIVE;
+        double Qv[5];
+        if (rule == WIU_SIDE_FIXED) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) L.sq[c][LT::qi(lb, pos)] = a.U[c * d.np + o];
+          for (int c = 0; c < 5; ++c) Qv[c] = a.fixed[sd][c];
+        } else {
+          const int kb = kr < 0 ? 0 : n - 1;
+          const int kk = rule == WIU_SIDE_WALL ? min(max(2 * kb - kr, 0), n - 1) : bc_index(kr, n, d.bc[DIR]);
+          int p[3];
+          node(kk, ln, p);
+          const long long o = u3idx(d, p[0], p[1], p[2]);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) Qv[c] = a.U[c * d.np + o];
+          if (rule == WIU_SIDE_WALL) {
+            node(kb, ln, p);
+            const long long mo = m3idx(d, p[0], p[1], p[2]);
+            double nv[3];
+            for (int c = 0; c < 3; ++c) nv[c] = a.M[(3 * DIR + c) * d.mplane + mo];
+            const double rn = rsqrt_(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            const double mn = (Qv[1] * nv[0] + Qv[2] * nv[1] + Qv[3] * nv[2]) * rn;
+            for (int c = 0; c < 3; ++c) Qv[1 + c] -= 2.0 * mn * (nv[c] * rn);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) L.sq[c][LT::qi(lb, pos)] = Qv[c];
       }
     }
   }
@@ -605,6 +635,16 @@ bool grid3_ok(const wiu_grid3* g) {
     if (g->bc[a] == WIU_BC_TRANSMISSIVE && n[a] < 2) return false;
     if (g->bc[a] == WIU_BC_PERIODIC && !(g->period[a] > 0.0 && g->period[a] < 1.0e300)) return false;
     if (n[a] > 4096) return false;
+    if (g->bc[a] == WIU_BC_PERIODIC) continue;
+    for (int e = 2 * a; e < 2 * a + 2; ++e) {
+      if (g->side[e] < WIU_SIDE_TRANSMISSIVE || g->side[e] > WIU_SIDE_FIXED) return false;
+      if (g->side[e] == WIU_SIDE_FIXED) {
+        const double* q = g->fixed[e];
+        if (!(q[0] > 0.0) || !(q[0] < 1.0e300)) return false;
+        const double p = q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];  // (gamma - 1) p
+        if (!(p > 0.0) || !(p < 1.0e300)) return false;
+      }
+    }
   }
   return (long long)n[0] * n[1] * n[2] <= (1LL << 31);
 }
@@ -652,6 +692,13 @@ bool params3_ok(const wiu_params* p) {
   return p && p->gamma > 1.0 && p->alpha_lf > 0.0 && p->eps >= 0.0 && (p->ppm == 0 || p->ppm == 1) &&
          p->vars == WIU_VARS_CHARACTERISTIC && p->alpha_h == 1.0 && p->weights == WIU_WEIGHTS_JS &&
          p->split == WIU_SPLIT_LF;
+}
+
+void sides3(const wiu_grid3* g, S3Args& a) {
+  for (int e = 0; e < 6; ++e) {
+    a.side[e] = g->bc[e / 2] == WIU_BC_PERIODIC ? WIU_SIDE_TRANSMISSIVE : g->side[e];
+    for (int c = 0; c < 5; ++c) a.fixed[e][c] = g->fixed[e][c];
+  }
 }
 
 dim3 lin_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
@@ -747,6 +794,7 @@ int wiu3_rhs(const wiu_grid3* g, int scheme, const wiu_params* p, const double* 
   a.d = d; a.U = U; a.M = M; a.lam = (unsigned long long*)(base + w.lam);
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
   a.Racc = (double*)(base + w.racc); a.out = dUdt;
+  sides3(g, a);
   a.U0 = nullptr; a.dt = nullptr; a.ca = 0.0; a.cb = 1.0; a.status = (int*)base;
   if (maxima3(d, U, M, p->gamma, (unsigned long long*)a.lam, w.nlam, a.status, st) != hipSuccess) return WIU_EHIP;
   for (int D = 0; D < 3; ++D)
@@ -780,6 +828,7 @@ int wiu3_rk3_step(const wiu_grid3* g, int scheme, const wiu_params* p, double* U
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
   a.Racc = (double*)(base + w.racc);
   a.U0 = U; a.dt = dt; a.status = (int*)base;
+  sides3(g, a);
   // U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U = 1/3 U + 2/3 (U2 + dt L(U2))
   const double* src[3] = {U, U1, U2};
   double* dst[3] = {U1, U2, U};

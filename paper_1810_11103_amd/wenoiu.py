@@ -49,7 +49,7 @@ class WiuBlock(ctypes.Structure):
 
 class WiuGrid3(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("bc", ctypes.c_int * 3),
-                ("period", ctypes.c_double * 3)]
+                ("period", ctypes.c_double * 3), ("side", ctypes.c_int * 6), ("fixed", (ctypes.c_double * 5) * 6)]
 
 
 class WiuParams(ctypes.Structure):
@@ -533,11 +533,21 @@ class BatchedPlan:
 
 # ---- three-dimensional grids (wiu3_*) -------------------------------------------
 
-def make_grid3(nx, ny, nz, bc=("periodic",) * 3, period=(0.0, 0.0, 0.0)):
+def make_grid3(nx, ny, nz, bc=("periodic",) * 3, period=(0.0, 0.0, 0.0), sides=None, fixed=None):
+    """3-D grid description; sides: rules of x low .. z high of the
+    non-periodic directions ("transmissive", "wall", "fixed"), fixed: their
+    conservative states [6][5]."""
     g = WiuGrid3(int(nx), int(ny), int(nz))
     for a in range(3):
         g.bc[a] = BC[bc[a]] if isinstance(bc[a], str) else int(bc[a])
         g.period[a] = float(period[a])
+    if sides is not None:
+        for k, v in enumerate(sides):
+            g.side[k] = SIDES[v] if isinstance(v, str) else int(v)
+    if fixed is not None:
+        for k in range(6):
+            for q in range(5):
+                g.fixed[k][q] = float(fixed[k][q])
     return g
 
 
@@ -547,9 +557,9 @@ class Solver3:
     workspace; states are (5, nz, ny, nx) fp64 device tensors."""
 
     def __init__(self, x, y, z, scheme="5-2MP", bc=("periodic",) * 3, period=(0.0, 0.0, 0.0), params=None,
-                 device="cuda", jform=5):
+                 device="cuda", jform=5, sides=None, fixed=None):
         nz, ny, nx = x.shape
-        self.grid = make_grid3(nx, ny, nz, bc, period)
+        self.grid = make_grid3(nx, ny, nz, bc, period, sides, fixed)
         self.scheme = scheme
         self.params = params or make_params()
         nm = lib.wiu3_metrics_size(ctypes.byref(self.grid))

@@ -570,3 +570,22 @@ def octant_state3(grid, gamma=GAMMA):
     w = np.array([0.0, 0.2, -0.2, 0.0, 0.4, 0.0, -0.3, 0.1])[o]
     p = np.array([1.0, 0.3, 0.3, 0.029, 0.9, 1.4, 0.6, 1.1])[o]
     return conservative3(rho, u, v, w, p, gamma)
+
+
+def smooth_state3(grid, seed=0, amp=0.15, gamma=GAMMA):
+    """Smooth random state: density, pressure and the three velocities each
+    a constant plus three sinusoids of the coordinates (wavelengths of the
+    box size) with random phases, amplitudes up to `amp`."""
+    rng = np.random.default_rng(seed)
+    L = [max(float(c.max() - c.min()), 1e-12) for c in (grid.x, grid.y, grid.z)]
+
+    def field(base):
+        f = np.full(grid.x.shape, base)
+        for _ in range(3):
+            k = rng.integers(1, 3, size=3)
+            ph = rng.uniform(0.0, 2 * np.pi)
+            f = f + amp * rng.uniform(0.3, 1.0) * np.sin(
+                2 * np.pi * (k[0] * grid.x / L[0] + k[1] * grid.y / L[1] + k[2] * grid.z / L[2]) + ph)
+        return f
+
+    return conservative3(field(1.0), field(0.3), field(-0.2), field(0.1), field(1.0), gamma)

@@ -169,6 +169,18 @@ def test_3d_grids_and_options_are_validated(wiu):
         P = wiu.make_params(**opts)
         rc = wiu.lib.wiu3_rhs(ctypes.byref(g), 3, ctypes.byref(P), dummy, dummy, dummy, dummy, None)
         assert rc == wiu.WIU_EINVAL
+    # side rules of bounded directions: 0..2, fixed states physical
+    bad = wiu.make_grid3(16, 12, 10, ("periodic", "transmissive", "periodic"), (1.0, 0.0, 1.0),
+                         sides=(0, 0, 3, 0, 0, 0))
+    assert wiu.lib.wiu3_metrics_size(ctypes.byref(bad)) == 0
+    fx = [[0.0] * 5 for _ in range(6)]
+    fx[3] = [-1.0, 0.0, 0.0, 0.0, 2.5]
+    bad = wiu.make_grid3(16, 12, 10, ("periodic", "transmissive", "periodic"), (1.0, 0.0, 1.0),
+                         sides=(0, 0, 0, 2, 0, 0), fixed=fx)
+    assert wiu.lib.wiu3_metrics_size(ctypes.byref(bad)) == 0
+    ok = wiu.make_grid3(16, 12, 10, ("periodic", "transmissive", "periodic"), (1.0, 0.0, 1.0),
+                        sides=(3, 3, 1, 0, 3, 3))  # periodic directions ignore their sides
+    assert wiu.lib.wiu3_metrics_size(ctypes.byref(ok)) > 0
     # the Jacobian form is 5 or 6
     assert wiu.lib.wiu3_metrics(ctypes.byref(g), 3, 4, dummy, dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL
     P = wiu.make_params()

@@ -195,3 +195,67 @@ def test_jacobian_by_eq_2_6_parity(orc, wiu, s, kind):
     err = normwise(host(Ud) - U, ref - U)
     assert np.all(err <= 1e-11), err
 
+
+
+FIXED6 = np.array([[1.2, 0.3, -0.1, 0.05, 2.9], [0.9, 0.1, 0.0, 0.0, 2.4], [1.0, 0.0, 0.2, 0.0, 2.6],
+                   [1.1, -0.2, 0.1, 0.1, 2.7], [1.0, 0.1, 0.0, -0.2, 2.5], [0.8, 0.0, 0.1, 0.1, 2.2]])
+SIDE_SETS3 = [("wall", "fixed", "transmissive", "wall", "fixed", "wall"),
+              ("fixed", "transmissive", "wall", "wall", "transmissive", "fixed")]
+
+
+@pytest.mark.parametrize("s", ["3-1MP", "5-2MP", "7-2MP"])
+@pytest.mark.parametrize("sides", range(len(SIDE_SETS3)))
+def test_rhs_and_rk3_parity_with_walls_and_fixed_sides(orc, wiu, s, sides):
+    say("3-D sides", s, sides)
+    g, _ = case("bounded", seed=5)
+    U = W.smooth_state3(g, seed=3)
+    sd = SIDE_SETS3[sides]
+    Mo = orc.metrics3(s, g.x, g.y, g.z, g.bc, g.period)
+    ref = orc.rhs3(s, U, Mo, g.bc, sides=sd, fixed=FIXED6)
+    sol = wiu.Solver3(g.x, g.y, g.z, s, g.bc, g.period, sides=sd, fixed=FIXED6)
+    out = host(sol.rhs(dev(U)))
+    assert sol.status() == 0
+    assert np.all(normwise(out, ref) <= 1e-12)
+    if s == "7-2MP":
+        return
+    dt = 0.5 * orc.cfl_dt3(U, Mo, 0.5)
+    ref = orc.rk3_step3(s, U, Mo, dt, g.bc, sides=sd, fixed=FIXED6)
+    Ud = dev(U)
+    sol.rk3_step(Ud, dt)
+    assert sol.status() == 0
+    assert np.all(normwise(host(Ud) - U, ref - U) <= 1e-11)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_walls_equal_the_mirror_extended_problem_on_gpu(wiu, axis):
+    from test_oracle_3d import _box3, _mirror_data3
+    N, s = 24, "5-2MP"
+    xw, yw, zw = _box3(N, axis)
+    bcw = ["periodic"] * 3
+    bcw[axis] = "transmissive"
+    per = [1.0, 1.0, 1.0]
+    per[axis] = 0.0
+    sides = ["transmissive"] * 6
+    sides[2 * axis] = sides[2 * axis + 1] = "wall"
+    sw = wiu.Solver3(xw, yw, zw, s, bcw, per, sides=sides)
+    dw = host(sw.rhs(dev(_mirror_data3(xw, yw, zw, axis))))
+    xp, yp, zp = _box3(N, axis, two=True)
+    perp = [1.0, 1.0, 1.0]
+    perp[axis] = 2.0
+    sp = wiu.Solver3(xp, yp, zp, s, ("periodic",) * 3, perp)
+    dp = host(sp.rhs(dev(_mirror_data3(xp, yp, zp, axis))))
+    idx = np.r_[np.arange(N, 2 * N), 0]
+    assert sw.status() == 0 and sp.status() == 0
+    assert np.abs(dw - np.take(dp, idx, axis=3 - axis)).max() <= 1e-12 * np.abs(dp).max()
+
+
+def test_free_stream_with_walls_and_inflow_on_gpu(wiu):
+    g = W.bounded_grid3(36, 30, 26, A=0.2, seed=6)
+    U = W.uniform_flow3(g, mach=2.0, direction=(1.0, 0.0, 0.0))
+    fixed = np.zeros((6, 5))
+    fixed[0] = U[:, 0, 0, 0]
+    sol = wiu.Solver3(g.x, g.y, g.z, "5-2MP", g.bc, g.period,
+                      sides=("fixed", "transmissive", "wall", "wall", "wall", "wall"), fixed=fixed)
+    d = host(sol.rhs(dev(U)))
+    assert sol.status() == 0
+    assert np.abs(d).max() < 1e-11

@@ -89,11 +89,11 @@ def lib():
         L.orc_mb_cfl_dt.argtypes = [_I, _P, _P, _D, _P, _P, _P, _P, _D, _P]
         L.orc3_metrics_size.restype = ctypes.c_longlong
         L.orc3_metrics_size.argtypes = [_P]
-        L.orc3_metrics.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _I]
-        L.orc3_rhs.argtypes = [_I, _P, _P, _P, _P, _D, _D, _D, _I, _P, _P, _P]
+        L.orc3_metrics.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _I, _D]
+        L.orc3_rhs.argtypes = [_I, _P, _P, _P, _P, _D, _D, _D, _I, _I, _D, _I, _P, _P, _P]
         L.orc3_cfl_dt.restype = _D
         L.orc3_cfl_dt.argtypes = [_P, _D, _P, _P, _D]
-        L.orc3_rk3_step.argtypes = [_I, _P, _P, _P, _P, _D, _D, _D, _I, _P, _P, _D]
+        L.orc3_rk3_step.argtypes = [_I, _P, _P, _P, _P, _D, _D, _D, _I, _I, _D, _I, _P, _P, _D]
         L.orc3_eigenvectors.restype = None
         L.orc3_eigenvectors.argtypes = [_P, _D, _P, _P, _P]
         L.orc3_flux_hat.restype = None
@@ -494,7 +494,7 @@ def _i3(v):
     return np.ascontiguousarray(v, dtype=np.int32)
 
 
-def metrics3(scheme, x, y, z, bc=("periodic",) * 3, period=(0.0, 0.0, 0.0), jform=5):
+def metrics3(scheme, x, y, z, bc=("periodic",) * 3, period=(0.0, 0.0, 0.0), jform=5, alpha_h=1.0):
     """19 metric planes with the ghost band: shape (19, nz+2G, ny+2G, nx+2G);
     jform 5 or 6: the Jacobian by Eq. 2.5 or Eq. 2.6."""
     x, y, z = _f64(x), _f64(y), _f64(z)
@@ -504,7 +504,7 @@ def metrics3(scheme, x, y, z, bc=("periodic",) * 3, period=(0.0, 0.0, 0.0), jfor
     L = _f64(period)
     M = np.zeros((19, nz + 2 * G, ny + 2 * G, nx + 2 * G))
     if lib().orc3_metrics(scheme_id(scheme), _ptr(n), _ptr(b), _ptr(L), _ptr(x), _ptr(y), _ptr(z), _ptr(M),
-                          int(jform)):
+                          int(jform), float(alpha_h)):
         raise ValueError("orc3_metrics failed")
     return M
 
@@ -520,12 +520,14 @@ def _sides3(sides, fixed):
     return k.ctypes.data_as(ctypes.c_void_p), f.ctypes.data_as(ctypes.c_void_p)
 
 
-def rhs3(scheme, U, M, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, sides=None, fixed=None):
+def rhs3(scheme, U, M, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, sides=None, fixed=None,
+         vars=0, alpha_h=1.0, weights=0):
     U, M = _f64(U), _f64(M)
     _, nz, ny, nx = U.shape
     out = np.zeros_like(U)
     if lib().orc3_rhs(scheme_id(scheme), _ptr(_i3([nx, ny, nz])), _ptr(_i3([bc_id(v) for v in bc])),
-                      *_sides3(sides, fixed), gamma, alpha, eps, ppm, _ptr(U), _ptr(M), _ptr(out)):
+                      *_sides3(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
+                      weights_id(weights), _ptr(U), _ptr(M), _ptr(out)):
         raise ValueError("orc3_rhs failed")
     return out
 
@@ -536,12 +538,14 @@ def cfl_dt3(U, M, cfl, gamma=1.4):
     return lib().orc3_cfl_dt(_ptr(_i3([nx, ny, nz])), gamma, _ptr(U), _ptr(M), float(cfl))
 
 
-def rk3_step3(scheme, U, M, dt, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, sides=None, fixed=None):
+def rk3_step3(scheme, U, M, dt, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, sides=None, fixed=None,
+              vars=0, alpha_h=1.0, weights=0):
     U = _f64(U).copy()
     M = _f64(M)
     _, nz, ny, nx = U.shape
     if lib().orc3_rk3_step(scheme_id(scheme), _ptr(_i3([nx, ny, nz])), _ptr(_i3([bc_id(v) for v in bc])),
-                           *_sides3(sides, fixed), gamma, alpha, eps, ppm, _ptr(U), _ptr(M), float(dt)):
+                           *_sides3(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
+                           weights_id(weights), _ptr(U), _ptr(M), float(dt)):
         raise ValueError("orc3_rk3_step failed")
     return U
 

@@ -16,8 +16,12 @@
 //     orthogonal to n and normalised, and t2 = t1 x n; for n in the x-y
 //     plane t1 = z and t2 = (-n_y, n_x, 0), the 2-D tangent, so z-uniform data
 //     reproduce the 2-D scheme;
-//   * the paper's configuration: characteristic variables, Lax-Friedrichs
-//     split, alpha = 1, Jiang-Shu weights with PPM mapping.
+//   * the scheme options of Secs. 2.4 and 3.2-3.3 and Sec. 7 as in 2-D:
+//     interpolation in characteristic, conservative or primitive variables
+//     (component-wise on deviations from the reference node), the free
+//     parameter alpha of the one-midpoint families (in h+ and, through
+//     Eq. 2.7, in the metric operator), Jiang-Shu (PPM-mapped) or WENO-Z
+//     weights; the midpoint flux keeps the Lax-Friedrichs split.
 // Arrays are [c][nz][ny][nx] with i fastest.
 // ---------------------------------------------------------------------------
 #pragma once
@@ -104,7 +108,7 @@ inline void step3(int d, int m, int& i, int& j, int& k) {
 // to the node (sum_m D_m n^_{m,l} = 0 holds discretely for Eq. 2.4, so the
 // shift changes only the rounding).
 inline void compute_metrics3(Scheme sc, const Grid3& g, const double* x, const double* y, const double* z,
-                             double* M, int jform = 5) {
+                             double* M, int jform = 5, double alpha_h = 1.0) {
   Coords3 C{g, {x, y, z}};
   // nodal band for the midpoint interpolation, or for Eq. 2.6 around the
   // ghost band (the operator below is evaluated on 8 nodes each side)
@@ -119,7 +123,7 @@ inline void compute_metrics3(Scheme sc, const Grid3& g, const double* x, const d
       step3(d, m, a, b, c);
       r[m + 8] = (double)(f(a, b, c) - f0);
     }
-    return (long double)metric_derivative(sc, 1.0, r);
+    return (long double)metric_derivative(sc, alpha_h, r);
   };
   // inner derivatives D_d x_c on [-EI, n+EI)
   std::vector<Box3> Dx;
@@ -296,23 +300,56 @@ void midpoint_flux3(Scheme sc, const Params& pr, const T Qs[8][5], const double 
   const int m0 = seventh_order(sc) ? 0 : 1, m1 = seventh_order(sc) ? 8 : 7;
   for (int side = 0; side < 2; ++side) {
     const T* Qref = Qs[3 + side];
-    T L[5][5], R[5][5];
-    eigenvectors3(Qref, pr.gamma, n, L, R);
-    T W[5];
-    for (int c = 0; c < 5; ++c) {
-      T s[8];
-      for (int m = 0; m < 8; ++m) {
-        s[m] = T(0.0);
-        if (m < m0 || m >= m1) continue;
-        for (int q = 0; q < 5; ++q) s[m] = s[m] + L[c][q] * (Qs[m][q] - Qref[q]);
-      }
-      W[c] = side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr);
-    }
     T Qm[5];
-    for (int q = 0; q < 5; ++q) {
-      Qm[q] = T(0.0);
-      for (int c = 0; c < 5; ++c) Qm[q] = Qm[q] + R[q][c] * W[c];
-      Qm[q] = Qref[q] + Qm[q];
+    if (pr.vars == 0) {
+      T L[5][5], R[5][5];
+      eigenvectors3(Qref, pr.gamma, n, L, R);
+      T W[5];
+      for (int c = 0; c < 5; ++c) {
+        T s[8];
+        for (int m = 0; m < 8; ++m) {
+          s[m] = T(0.0);
+          if (m < m0 || m >= m1) continue;
+          for (int q = 0; q < 5; ++q) s[m] = s[m] + L[c][q] * (Qs[m][q] - Qref[q]);
+        }
+        W[c] = side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr);
+      }
+      for (int q = 0; q < 5; ++q) {
+        Qm[q] = T(0.0);
+        for (int c = 0; c < 5; ++c) Qm[q] = Qm[q] + R[q][c] * W[c];
+        Qm[q] = Qref[q] + Qm[q];
+      }
+    } else {
+      // Sec. 2.4: component by component in conservative (vars 1) or
+      // primitive (vars 2: rho, u, v, w, p) variables, on deviations from
+      // the reference node's values
+      auto prim = [&](const T Q[5], T V[5]) {
+        V[0] = Q[0];
+        V[1] = Q[1] / Q[0]; V[2] = Q[2] / Q[0]; V[3] = Q[3] / Q[0];
+        V[4] = pressure3(Q, pr.gamma);
+      };
+      T V[8][5];
+      for (int m = 0; m < 8; ++m) {
+        if (m < m0 || m >= m1)
+          for (int q = 0; q < 5; ++q) V[m][q] = T(0.0);
+        else if (pr.vars == 1)
+          for (int q = 0; q < 5; ++q) V[m][q] = Qs[m][q];
+        else
+          prim(Qs[m], V[m]);
+      }
+      T Vm[5];
+      for (int c = 0; c < 5; ++c) {
+        T s[8];
+        for (int m = 0; m < 8; ++m) s[m] = (m < m0 || m >= m1) ? T(0.0) : V[m][c] - V[3 + side][c];
+        Vm[c] = V[3 + side][c] + (side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr));
+      }
+      if (pr.vars == 1) {
+        for (int q = 0; q < 5; ++q) Qm[q] = Vm[q];
+      } else {
+        Qm[0] = Vm[0];
+        for (int a = 0; a < 3; ++a) Qm[1 + a] = Vm[0] * Vm[1 + a];
+        Qm[4] = Vm[4] / (pr.gamma - 1.0) + 0.5 * Vm[0] * (Vm[1] * Vm[1] + Vm[2] * Vm[2] + Vm[3] * Vm[3]);
+      }
     }
     T E[5];
     flux_hat3(Qm, pr.gamma, mk, E);
@@ -369,7 +406,7 @@ void line_residual3(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam
       auto Fpm = [&](int m) { return Fp[q * len + i + m + off]; };
       auto fmn = [&](int m) { return fm[q * len + i + 1 - m + off]; };
       auto Fmm = [&](int m) { return Fm[q * len + i - m + off]; };
-      H[q * (n + 1) + i + 1] = h_plus<T>(sc, 1.0, fpn, Fpm) + h_plus<T>(sc, 1.0, fmn, Fmm);
+      H[q * (n + 1) + i + 1] = h_plus<T>(sc, pr.alpha_h, fpn, Fpm) + h_plus<T>(sc, pr.alpha_h, fmn, Fmm);
     }
   for (int k = 0; k < n; ++k)
     for (int q = 0; q < 5; ++q) R[q * n + k] = H[q * (n + 1) + k + 1] - H[q * (n + 1) + k];

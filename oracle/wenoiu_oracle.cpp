@@ -503,16 +503,18 @@ long long orc3_metrics_size(const int* n) {
 }
 
 int orc3_metrics(int scheme, const int* n, const int* bc, const double* L, const double* x, const double* y,
-                 const double* z, double* M, int jform) {
-  if (bad_scheme(scheme) || bad_grid3(n, bc) || (jform != 5 && jform != 6)) return -1;
-  compute_metrics3((Scheme)scheme, make_grid3(n, bc, L), x, y, z, M, jform);
+                 const double* z, double* M, int jform, double alpha_h) {
+  if (bad_options(scheme, 0, alpha_h, 0, 0) || bad_grid3(n, bc) || (jform != 5 && jform != 6)) return -1;
+  compute_metrics3((Scheme)scheme, make_grid3(n, bc, L), x, y, z, M, jform, alpha_h);
   return 0;
 }
 
 int orc3_rhs(int scheme, const int* n, const int* bc, const int* side, const double* fixed, double gamma,
-             double alpha, double eps, int ppm, const double* U, const double* M, double* out) {
-  if (bad_scheme(scheme) || bad_grid3(n, bc)) return -1;
-  rhs3((Scheme)scheme, make_params(gamma, alpha, eps, ppm), make_grid3(n, bc, kNoPeriod, side, fixed), U, M, out);
+             double alpha, double eps, int ppm, int vars, double alpha_h, int weights, const double* U,
+             const double* M, double* out) {
+  if (bad_options(scheme, vars, alpha_h, weights, 0) || bad_grid3(n, bc)) return -1;
+  rhs3((Scheme)scheme, make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights),
+       make_grid3(n, bc, kNoPeriod, side, fixed), U, M, out);
   return 0;
 }
 
@@ -522,10 +524,11 @@ double orc3_cfl_dt(const int* n, double gamma, const double* U, const double* M,
 }
 
 int orc3_rk3_step(int scheme, const int* n, const int* bc, const int* side, const double* fixed, double gamma,
-                  double alpha, double eps, int ppm, double* U, const double* M, double dt) {
-  if (bad_scheme(scheme) || bad_grid3(n, bc)) return -1;
-  rk3_step3((Scheme)scheme, make_params(gamma, alpha, eps, ppm), make_grid3(n, bc, kNoPeriod, side, fixed), U, M,
-            dt);
+                  double alpha, double eps, int ppm, int vars, double alpha_h, int weights, double* U,
+                  const double* M, double dt) {
+  if (bad_options(scheme, vars, alpha_h, weights, 0) || bad_grid3(n, bc)) return -1;
+  rk3_step3((Scheme)scheme, make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights),
+            make_grid3(n, bc, kNoPeriod, side, fixed), U, M, dt);
   return 0;
 }
 

@@ -223,3 +223,39 @@ def test_free_stream_with_walls_and_inflow_3d(s):
     M = orc.metrics3(s, g.x, g.y, g.z, g.bc, g.period)
     d = orc.rhs3(s, U, M, g.bc, sides=("fixed", "transmissive", "wall", "wall", "wall", "wall"), fixed=fixed)
     assert np.abs(d).max() < 1e-11
+
+
+OPTION_CASES = [("5-2MP", dict(vars="conservative")), ("5-1MP", dict(vars="primitive")),
+                ("3-2MP", dict(weights="z")), ("7-1MP", dict(weights="z", vars="primitive")),
+                ("3-1MP", dict(alpha_h=0.8)), ("5-1MP", dict(alpha_h=1.3, vars="conservative"))]
+
+
+@pytest.mark.parametrize("s,opts", OPTION_CASES)
+def test_z_independent_data_reduce_to_the_2d_scheme_with_options(s, opts):
+    """The scheme options of Secs. 2.4, 3.2-3.3 and 7 (interpolation
+    variables, WENO-Z weights, the free alpha) in 3-D reduce to the 2-D
+    oracle's for z-independent data (flux residual; the metrics with alpha)."""
+    g = W.periodic_grid(24, 20, box=(0.0, 2.4, 0.0, 2.0), A=0.3, seed=4)
+    U = W.random_smooth_state(g, seed=2, amp=0.2)
+    ah = opts.get("alpha_h", 1.0)
+    M2 = orc.metrics(s, g.x, g.y, g.bc, g.period, alpha_h=ah)
+    r2 = orc.rhs(s, U, M2, g.bc, **opts)
+    g3, U3 = W.extrude(g, 3, U)
+    M3 = orc.metrics3(s, g3.x, g3.y, g3.z, g3.bc, g3.period, alpha_h=ah)
+    r3 = orc.rhs3(s, U3, M3, g3.bc, **opts)
+    m = M3[:, G + 1]
+    for p2, p3 in ((0, 0), (1, 1), (2, 3), (3, 4), (5, 10), (6, 11), (7, 13), (8, 14)):
+        assert np.abs(M2[p2] - m[p3]).max() <= 1e-14 * np.abs(M2[p2]).max(), (p2, p3)
+    f2 = M2[4, G:-G, G:-G] * r2
+    f3 = _flux_residual3(M3, r3)
+    for q2, q3 in ((0, 0), (1, 1), (2, 2), (3, 4)):
+        assert np.abs(f3[q3, 1] - f2[q2]).max() <= 1e-13 * np.abs(f2[q2]).max(), q2
+    assert np.all(r3[3] == 0.0)
+
+
+@pytest.mark.parametrize("s,opts", OPTION_CASES)
+def test_free_stream_preserved_with_options(s, opts):
+    for g in (W.wavy_grid3(16, 16, 14), W.bounded_grid3(16, 15, 14, A=0.3, seed=1)):
+        U = W.uniform_flow3(g)
+        M = orc.metrics3(s, g.x, g.y, g.z, g.bc, g.period, alpha_h=opts.get("alpha_h", 1.0))
+        assert np.abs(orc.rhs3(s, U, M, g.bc, **opts)).max() < 1e-11

@@ -327,9 +327,11 @@ int wiu_plan_destroy(wiu_plan* plan);
  * eigenvectors along the unit direction (shear waves along t2 and t1: t1
  * the axis of the smallest component of n, ties to the later axis, made
  * orthogonal to n; t2 = t1 x n), TVD-RK3.  J^{-1} by Eq. 2.5 or Eq. 2.6
- * (wiu3_metrics).  The paper's configuration only:
- * wiu_params must hold characteristic variables, alpha_h = 1, Jiang-Shu
- * weights and the Lax-Friedrichs split (else WIU_EINVAL).
+ * (wiu3_metrics).  wiu_params selects the interpolation variables
+ * (component-wise on deviations for conservative or primitive (rho, u, v,
+ * w, p) variables), alpha_h of the one-midpoint schemes and the weights as
+ * in 2-D; the midpoint flux keeps the Lax-Friedrichs split (another split
+ * gives WIU_EINVAL).
  *
  * Layouts (device, caller-owned): coordinates x, y, z and each state
  * component [nz][ny][nx], i fastest; U [5][nz][ny][nx]; M 19 planes of
@@ -354,11 +356,13 @@ typedef struct {
 
 size_t wiu3_metrics_size(const wiu_grid3* g);
 size_t wiu3_workspace_bytes(const wiu_grid3* g);
-/* jform: 5 for J^{-1} by Eq. 2.5, 1/3 sum_{m,l} n^_{m,l} D_m x_l, or 6 for
+/* p may be NULL (alpha_h = 1); its alpha_h enters the metric operator of
+ * the one-midpoint schemes as in wiu_metrics and is recorded in the tag.
+ * jform: 5 for J^{-1} by Eq. 2.5, 1/3 sum_{m,l} n^_{m,l} D_m x_l, or 6 for
  * Eq. 2.6, 1/3 sum_{m,l} D_m(n^_{m,l} x_l) (the paper allows either; the
  * nine metric components are the same).  The tag records it. */
-int wiu3_metrics(const wiu_grid3* g, int scheme, int jform, const double* x, const double* y, const double* z,
-                 double* M, void* ws, wiu_stream_t stream);
+int wiu3_metrics(const wiu_grid3* g, int scheme, int jform, const wiu_params* p, const double* x, const double* y,
+                 const double* z, double* M, void* ws, wiu_stream_t stream);
 /* dU/dt of Eq. 2.2 (one direction pass per coordinate direction). */
 int wiu3_rhs(const wiu_grid3* g, int scheme, const wiu_params* p, const double* U, const double* M, double* dUdt,
              void* ws, wiu_stream_t stream);

@@ -168,12 +168,12 @@ __global__ void m3_nodal_kernel(Dims3 d, MetricStencil ms, int B, int E, Coord3 
 // J^{-1} by Eq. 2.6, 1/3 sum_{m,l} D_m(n^_{m,l} x_l) with x_l relative to
 // the (wrapped) node, which needs the nodal band B >= GHOST + METRIC_REACH.
 __global__ void m3_band_kernel(Dims3 d, int scheme, int B, const double* __restrict__ T, double* __restrict__ M,
-                               int* __restrict__ status, int jform, MetricStencil ms, Coord3 X) {
+                               int* __restrict__ status, int jform, MetricStencil ms, Coord3 X, double ah) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
     double* tag = M + NP3 * d.mplane;
     tag[0] = TAG_MAGIC3; tag[1] = (double)scheme; tag[2] = (double)d.n[0]; tag[3] = (double)d.n[1];
-    tag[4] = (double)d.n[2]; tag[5] = (double)(d.bc[0] + 2 * d.bc[1] + 4 * d.bc[2]); tag[6] = 1.0;
+    tag[4] = (double)d.n[2]; tag[5] = (double)(d.bc[0] + 2 * d.bc[1] + 4 * d.bc[2]); tag[6] = ah;
     tag[7] = (double)jform;
   }
   if (t >= d.mplane) return;
@@ -272,7 +272,7 @@ WIU_DEV void tangents3(const double n[3], double t1[3], double t2[3]) {
 // t1, q_n + c), interpolate each with WENO, map back with R, add the
 // reference, then the Lax-Friedrichs half flux with the midpoint metric.
 // q(s, c): state at window slot s = 0..7 (nodes k-3 .. k+4).
-template <int R, class QF>
+template <int R, bool ZOK = false, class QF>
 WIU_DEV void side_flux3(QF q, int side, const double n[3], const double mk[3], double lam, double gam, double eps,
                         int ppm, double F[5]) {
   double Qr[5];
@@ -320,9 +320,9 @@ WIU_DEV void side_flux3(QF q, int side, const double n[3], const double mk[3], d
   double Wf[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
-    if constexpr (R == 2) Wf[f] = weno3(w[f][0], w[f][1], w[f][3], eps, ppm);
-    else if constexpr (R == 3) Wf[f] = weno5(w[f][0], w[f][1], w[f][3], w[f][4], eps, ppm);
-    else Wf[f] = weno7(w[f][0], w[f][1], w[f][2], w[f][4], w[f][5], w[f][6], eps, ppm);
+    if constexpr (R == 2) Wf[f] = weno3<ZOK>(w[f][0], w[f][1], w[f][3], eps, ppm);
+    else if constexpr (R == 3) Wf[f] = weno5<ZOK>(w[f][0], w[f][1], w[f][3], w[f][4], eps, ppm);
+    else Wf[f] = weno7<ZOK>(w[f][0], w[f][1], w[f][2], w[f][4], w[f][5], w[f][6], eps, ppm);
   }
   // Q = Q_ref + R W
   const double s04 = Wf[0] + Wf[4], d40 = Wf[4] - Wf[0];
@@ -331,6 +331,60 @@ WIU_DEV void side_flux3(QF q, int side, const double n[3], const double mk[3], d
   r[0] = Qr[0] + sum;
   for (int a = 0; a < 3; ++a) r[1 + a] = Qr[1 + a] + (V[a] * sum + c * n[a] * d40 + t2[a] * Wf[2] + t1[a] * Wf[3]);
   r[4] = Qr[4] + (H * s04 + c * qn * d40 + 0.5 * q2 * Wf[1] + qa * Wf[2] + qb * Wf[3]);
+  double E[5];
+  flux3(r, mk, gam, E);
+  const double sl = side == 0 ? lam : -lam;
+  for (int a = 0; a < 5; ++a) F[a] = 0.5 * (E[a] + sl * r[a]);
+}
+
+// The same side flux with the interpolation component by component
+// (Sec. 2.4): vars 1 conservative, vars 2 primitive (rho, u, v, w, p), on
+// deviations from the reference node's values.
+template <int R, bool ZOK, class QF>
+WIU_DEV void side_flux3_comp(QF q, int side, int vars, const double mk[3], double lam, double gam, double eps,
+                             int ppm, double F[5]) {
+  constexpr int NS = R == 2 ? 4 : (R == 3 ? 5 : 7);
+  constexpr int C0 = R == 4 ? 3 : 2;
+  auto val = [&](int slot, double V[5]) {
+    for (int c = 0; c < 5; ++c) V[c] = q(slot, c);
+    if (vars == 2) {
+      const double ri = rcp(V[0]);
+      const double u = V[1] * ri, v = V[2] * ri, w = V[3] * ri;
+      V[4] = (gam - 1.0) * (V[4] - 0.5 * (V[1] * u + V[2] * v + V[3] * w));
+      V[1] = u; V[2] = v; V[3] = w;
+    }
+  };
+  double Vr[5];
+  val(3 + side, Vr);
+  double w[5][NS];
+#pragma unroll
+  for (int s_ = 0; s_ < NS; ++s_) {
+    if (s_ == C0) {
+      for (int f = 0; f < 5; ++f) w[f][s_] = 0.0;
+      continue;
+    }
+    const int slot = side == 0 ? 3 - C0 + s_ : 4 + C0 - s_;
+    double V[5];
+    val(slot, V);
+    for (int f = 0; f < 5; ++f) w[f][s_] = V[f] - Vr[f];
+  }
+  double Vm[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    double W;
+    if constexpr (R == 2) W = weno3<ZOK>(w[f][0], w[f][1], w[f][3], eps, ppm);
+    else if constexpr (R == 3) W = weno5<ZOK>(w[f][0], w[f][1], w[f][3], w[f][4], eps, ppm);
+    else W = weno7<ZOK>(w[f][0], w[f][1], w[f][2], w[f][4], w[f][5], w[f][6], eps, ppm);
+    Vm[f] = Vr[f] + W;
+  }
+  double r[5];
+  if (vars == 2) {
+    r[0] = Vm[0];
+    for (int a = 0; a < 3; ++a) r[1 + a] = Vm[0] * Vm[1 + a];
+    r[4] = Vm[4] / (gam - 1.0) + 0.5 * Vm[0] * (Vm[1] * Vm[1] + Vm[2] * Vm[2] + Vm[3] * Vm[3]);
+  } else {
+    for (int a = 0; a < 5; ++a) r[a] = Vm[a];
+  }
   double E[5];
   flux3(r, mk, gam, E);
   const double sl = side == 0 ? lam : -lam;
@@ -347,6 +401,9 @@ struct S3Args {
   const unsigned long long* lam;   // line maxima: xi lines [ny nz], eta [nx nz], zeta [nx ny]
   double gamma, alpha, eps;
   int ppm;
+  int vars;                        // WIU_VARS_* (interpolation variables)
+  double ah;                       // free parameter of the one-midpoint schemes
+  int weights;                     // WIU_WEIGHTS_*
   double* Racc;                    // accumulated flux differences [5][np]
   double* out;                     // dU/dt (mode 2) or the new stage state (mode 3)
   const double* U0;                // RK base state
@@ -367,11 +424,11 @@ WIU_DEV long long line3(const Dims3& d, int D, const int p[3]) {
                                                              : (long long)p[1] * d.n[0] + p[0]);
 }
 
-WIU_DEV bool tag3_ok(const Dims3& d, const double* M, int scheme) {
+WIU_DEV bool tag3_ok(const Dims3& d, const double* M, int scheme, double ah) {
   const double* tag = M + NP3 * d.mplane;
   return tag[0] == TAG_MAGIC3 && tag[1] == (double)scheme && tag[2] == (double)d.n[0] &&
          tag[3] == (double)d.n[1] && tag[4] == (double)d.n[2] &&
-         tag[5] == (double)(d.bc[0] + 2 * d.bc[1] + 4 * d.bc[2]);
+         tag[5] == (double)(d.bc[0] + 2 * d.bc[1] + 4 * d.bc[2]) && tag[6] == ah;
 }
 
 // LDS of a 3-D sweep tile: NA items along the line by NB lines.  Per item
@@ -396,14 +453,18 @@ template <int SC, int DIR, int NA, int NB> struct Sweep3Lds {
 // lanes of each line form H_{i+1/2} - H_{i-1/2} and, by `mode`: 0 Racc = R;
 // 1 Racc += R; 2 dU/dt = -(Racc + R)/J^{-1}; 3 the RK stage
 // U_out = ca U0 + cb (U + dt dU/dt).  Two block-wide barriers on every path.
-template <int SC, int DIR, int NA, int NB>
+// OPT: compiled with the scheme options (a.vars, a.ah, a.weights); without
+// it the sweep runs the paper's configuration and carries no code for them.
+template <int SC, int DIR, int NA, int NB, bool OPT>
 __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
   __shared__ Sweep3Lds<SC, DIR, NA, NB> L;
   using R_ = Range<SC>;
   using LT = Sweep3Lds<SC, DIR, NA, NB>;
   constexpr int OUT = NA - R_::EXTRA, QL = R_::QL, NQ = LT::NQ, NT = NA * NB;
   const Dims3& d = a.d;
-  if (!tag3_ok(d, a.M, SC)) {  // block-uniform
+  const double ah = OPT ? a.ah : 1.0;
+  const int ppm = OPT && a.weights != 0 ? 2 : a.ppm;  // 2: WENO-Z weights
+  if (!tag3_ok(d, a.M, SC, ah)) {  // block-uniform
     if (threadIdx.x == 0 && threadIdx.y == 0) atomicOr(a.status, ST_SCHEME);
     return;
   }
@@ -522,7 +583,10 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
     for (int side = 0; side < 2; ++side) {
       asm volatile("" ::: "memory");  // one side at a time (register pressure)
       double F[5];
-      side_flux3<Traits<SC>::R>(q, side, nv, mk, lam, gam, a.eps, a.ppm, F);
+      if (OPT && a.vars != 0)
+        side_flux3_comp<Traits<SC>::R, OPT>(q, side, a.vars, mk, lam, gam, a.eps, ppm, F);
+      else
+        side_flux3<Traits<SC>::R, OPT>(q, side, nv, mk, lam, gam, a.eps, ppm, F);
       for (int c = 0; c < 5; ++c) L.sh[5 + 5 * side + c][slot] = F[c];
     }
   }
@@ -543,7 +607,7 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
     auto fm = [&](int kk) { return 0.5 * (e[(kk - i) * S] - lam * qv[(kk - i) * S]); };
     auto Fp = [&](int kk) { return gp[(kk - i) * S]; };
     auto Fm = [&](int kk) { return gm[(kk - i) * S]; };
-    Rv[c] = hflux<SC>(i, 1.0, fp, fm, Fp, Fm) - hflux<SC>(i - 1, 1.0, fp, fm, Fp, Fm);
+    Rv[c] = hflux<SC>(i, ah, fp, fm, Fp, Fm) - hflux<SC>(i - 1, ah, fp, fm, Fp, Fm);
   }
   int p[3];
   node(i, la, p);
@@ -688,10 +752,19 @@ Ws3 ws3(const wiu_grid3* g) {
   return w;
 }
 
-bool params3_ok(const wiu_params* p) {
+bool alpha3_ok(int scheme, double a) {
+  return a > 0.0 && a < 1.0e300 && (a == 1.0 || scheme == WIU_3_1MP || scheme == WIU_5_1MP || scheme == WIU_7_1MP);
+}
+
+// the 3-D path has every option but the other midpoint splits
+bool params3_ok(const wiu_params* p, int scheme) {
   return p && p->gamma > 1.0 && p->alpha_lf > 0.0 && p->eps >= 0.0 && (p->ppm == 0 || p->ppm == 1) &&
-         p->vars == WIU_VARS_CHARACTERISTIC && p->alpha_h == 1.0 && p->weights == WIU_WEIGHTS_JS &&
-         p->split == WIU_SPLIT_LF;
+         p->vars >= WIU_VARS_CHARACTERISTIC && p->vars <= WIU_VARS_PRIMITIVE && alpha3_ok(scheme, p->alpha_h) &&
+         (p->weights == WIU_WEIGHTS_JS || p->weights == WIU_WEIGHTS_Z) && p->split == WIU_SPLIT_LF;
+}
+
+void options3(const wiu_params* p, S3Args& a) {
+  a.vars = p->vars; a.ah = p->alpha_h; a.weights = p->weights;
 }
 
 void sides3(const wiu_grid3* g, S3Args& a) {
@@ -705,7 +778,7 @@ dim3 lin_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
 
 // Tile shapes: xi 128 items x 2 lines (lanes along the line), eta and zeta
 // 32 items x 8 lines (lanes across the lines, along i).
-template <int SC, int DIR, int NA, int NB>
+template <int SC, int DIR, int NA, int NB, bool OPT>
 hipError_t launch_sweep3_t(const S3Args& a, int mode, hipStream_t st) {
   constexpr int OUT = NA - Range<SC>::EXTRA;
   const int n = a.d.n[DIR];
@@ -714,16 +787,23 @@ hipError_t launch_sweep3_t(const S3Args& a, int mode, hipStream_t st) {
   const long long tiles = (long long)((n + OUT - 1) / OUT) * ((nac + NB - 1) / NB) * nb;
   const dim3 block = DIR == 0 ? dim3(NA, NB) : dim3(NB, NA);
   void* h = prof_open(WIU_K_SWEEP3, st);
-  hipLaunchKernelGGL((s3_sweep_kernel<SC, DIR, NA, NB>), dim3((unsigned)tiles), block, 0, st, a, mode);
+  hipLaunchKernelGGL((s3_sweep_kernel<SC, DIR, NA, NB, OPT>), dim3((unsigned)tiles), block, 0, st, a, mode);
   prof_close(h);
   return hipGetLastError();
 }
 
+template <int SC, bool OPT>
+hipError_t launch_pass3_o(const S3Args& a, int D, int mode, hipStream_t st) {
+  if (D == 0) return launch_sweep3_t<SC, 0, 128, 2, OPT>(a, mode, st);
+  if (D == 1) return launch_sweep3_t<SC, 1, 32, 8, OPT>(a, mode, st);
+  return launch_sweep3_t<SC, 2, 32, 8, OPT>(a, mode, st);
+}
+
+// the options kernels only when an option is in use
 template <int SC>
 hipError_t launch_pass3(const S3Args& a, int D, int mode, hipStream_t st) {
-  if (D == 0) return launch_sweep3_t<SC, 0, 128, 2>(a, mode, st);
-  if (D == 1) return launch_sweep3_t<SC, 1, 32, 8>(a, mode, st);
-  return launch_sweep3_t<SC, 2, 32, 8>(a, mode, st);
+  if (a.vars != 0 || a.ah != 1.0 || a.weights != 0) return launch_pass3_o<SC, true>(a, D, mode, st);
+  return launch_pass3_o<SC, false>(a, D, mode, st);
 }
 
 hipError_t pass3(int scheme, const S3Args& a, int D, int mode, hipStream_t st) {
@@ -761,9 +841,11 @@ size_t wiu3_metrics_size(const wiu_grid3* g) {
 
 size_t wiu3_workspace_bytes(const wiu_grid3* g) { return grid3_ok(g) ? ws3(g).total : 0; }
 
-int wiu3_metrics(const wiu_grid3* g, int scheme, int jform, const double* x, const double* y, const double* z,
-                 double* M, void* ws, wiu_stream_t stream) {
-  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || (jform != 5 && jform != 6) || !x || !y || !z || !M || !ws)
+int wiu3_metrics(const wiu_grid3* g, int scheme, int jform, const wiu_params* p, const double* x, const double* y,
+                 const double* z, double* M, void* ws, wiu_stream_t stream) {
+  const double ah = p ? p->alpha_h : 1.0;
+  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || (jform != 5 && jform != 6) || !alpha3_ok(scheme, ah) || !x ||
+      !y || !z || !M || !ws)
     return WIU_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const Dims3 d = dims3(g);
@@ -772,20 +854,20 @@ int wiu3_metrics(const wiu_grid3* g, int scheme, int jform, const double* x, con
   double* Dx = (double*)(base + w.metric_dx);
   double* T = (double*)(base + w.metric_t);
   int* status = (int*)base;
-  const MetricStencil ms = metric_stencil(scheme, 1.0);
+  const MetricStencil ms = metric_stencil(scheme, ah);
   const int B = jform == 6 ? GHOST + METRIC_REACH : metric_band(scheme), E = B + 8;
   Coord3 X{{x, y, z}};
   const long long ND = (long long)(d.n[0] + 2 * E) * (d.n[1] + 2 * E) * (d.n[2] + 2 * E);
   const long long NT = (long long)(d.n[0] + 2 * B) * (d.n[1] + 2 * B) * (d.n[2] + 2 * B);
   hipLaunchKernelGGL(m3_inner_kernel, lin_grid(ND), dim3(256), 0, st, d, ms, E, X, Dx);
   hipLaunchKernelGGL(m3_nodal_kernel, lin_grid(NT), dim3(256), 0, st, d, ms, B, E, X, Dx, T);
-  hipLaunchKernelGGL(m3_band_kernel, lin_grid(d.mplane), dim3(256), 0, st, d, scheme, B, T, M, status, jform, ms, X);
+  hipLaunchKernelGGL(m3_band_kernel, lin_grid(d.mplane), dim3(256), 0, st, d, scheme, B, T, M, status, jform, ms, X, ah);
   return rc3(hipGetLastError());
 }
 
 int wiu3_rhs(const wiu_grid3* g, int scheme, const wiu_params* p, const double* U, const double* M, double* dUdt,
              void* ws, wiu_stream_t stream) {
-  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !params3_ok(p) || !U || !M || !dUdt || !ws) return WIU_EINVAL;
+  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !params3_ok(p, scheme) || !U || !M || !dUdt || !ws) return WIU_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const Dims3 d = dims3(g);
   const Ws3 w = ws3(g);
@@ -795,6 +877,7 @@ int wiu3_rhs(const wiu_grid3* g, int scheme, const wiu_params* p, const double* 
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
   a.Racc = (double*)(base + w.racc); a.out = dUdt;
   sides3(g, a);
+  options3(p, a);
   a.U0 = nullptr; a.dt = nullptr; a.ca = 0.0; a.cb = 1.0; a.status = (int*)base;
   if (maxima3(d, U, M, p->gamma, (unsigned long long*)a.lam, w.nlam, a.status, st) != hipSuccess) return WIU_EHIP;
   for (int D = 0; D < 3; ++D)
@@ -816,7 +899,7 @@ int wiu3_cfl_dt(const wiu_grid3* g, const wiu_params* p, const double* U, const 
 
 int wiu3_rk3_step(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, const double* dt,
                   void* ws, wiu_stream_t stream) {
-  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !params3_ok(p) || !U || !M || !dt || !ws) return WIU_EINVAL;
+  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !params3_ok(p, scheme) || !U || !M || !dt || !ws) return WIU_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const Dims3 d = dims3(g);
   const Ws3 w = ws3(g);
@@ -829,6 +912,7 @@ int wiu3_rk3_step(const wiu_grid3* g, int scheme, const wiu_params* p, double* U
   a.Racc = (double*)(base + w.racc);
   a.U0 = U; a.dt = dt; a.status = (int*)base;
   sides3(g, a);
+  options3(p, a);
   // U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U = 1/3 U + 2/3 (U2 + dt L(U2))
   const double* src[3] = {U, U1, U2};
   double* dst[3] = {U1, U2, U};

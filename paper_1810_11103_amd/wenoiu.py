@@ -84,7 +84,7 @@ def _load():
         "wiu_blocks_metrics_work_size": (ctypes.c_size_t, [ctypes.POINTER(WiuBlock), I, I]),
         "wiu3_metrics_size": (ctypes.c_size_t, [ctypes.POINTER(WiuGrid3)]),
         "wiu3_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(WiuGrid3)]),
-        "wiu3_metrics": (I, [ctypes.POINTER(WiuGrid3), I, I, P, P, P, P, P, P]),
+        "wiu3_metrics": (I, [ctypes.POINTER(WiuGrid3), I, I, PR, P, P, P, P, P, P]),
         "wiu3_rhs": (I, [ctypes.POINTER(WiuGrid3), I, PR, P, P, P, P, P]),
         "wiu3_cfl_dt": (I, [ctypes.POINTER(WiuGrid3), PR, P, P, ctypes.c_double, P, P, P]),
         "wiu3_rk3_step": (I, [ctypes.POINTER(WiuGrid3), I, PR, P, P, P, P, P]),
@@ -570,7 +570,8 @@ class Solver3:
         self.ws = torch.zeros(nw, dtype=torch.uint8, device=device)
         self.dt = torch.zeros(1, dtype=torch.float64, device=device)
         xyz = [torch.as_tensor(a, dtype=torch.float64).to(device).contiguous() for a in (x, y, z)]
-        _check(lib.wiu3_metrics(ctypes.byref(self.grid), scheme_id(scheme), int(jform), *[_ptr(a) for a in xyz],
+        _check(lib.wiu3_metrics(ctypes.byref(self.grid), scheme_id(scheme), int(jform), ctypes.byref(self.params),
+                                *[_ptr(a) for a in xyz],
                                 _ptr(self.M),
                                 ctypes.c_void_p(self.ws.data_ptr()), _stream()))
         if status(self.ws):

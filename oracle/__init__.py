@@ -90,15 +90,17 @@ def lib():
         L.orc3_metrics_size.restype = ctypes.c_longlong
         L.orc3_metrics_size.argtypes = [_P]
         L.orc3_metrics.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _I, _D]
-        L.orc3_rhs.argtypes = [_I, _P, _P, _P, _P, _D, _D, _D, _I, _I, _D, _I, _P, _P, _P]
+        L.orc3_rhs.argtypes = [_I, _P, _P, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _P]
         L.orc3_cfl_dt.restype = _D
         L.orc3_cfl_dt.argtypes = [_P, _D, _P, _P, _D]
-        L.orc3_rk3_step.argtypes = [_I, _P, _P, _P, _P, _D, _D, _D, _I, _I, _D, _I, _P, _P, _D]
+        L.orc3_rk3_step.argtypes = [_I, _P, _P, _P, _P, _D, _D, _D, _I, _I, _D, _I, _I, _P, _P, _D]
         L.orc3_eigenvectors.restype = None
         L.orc3_eigenvectors.argtypes = [_P, _D, _P, _P, _P]
         L.orc3_flux_hat.restype = None
         L.orc3_flux_hat.argtypes = [_P, _D, _P, _P]
         L.orc3_count_line_flops.argtypes = [_I, _I, _D, _P, _P, _P]
+        L.orc3_midpoint_split.restype = None
+        L.orc3_midpoint_split.argtypes = [_I, _D, _P, _P, _I, _P]
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [_I]
         L.orc_get_threads.restype = _I
@@ -521,13 +523,13 @@ def _sides3(sides, fixed):
 
 
 def rhs3(scheme, U, M, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, sides=None, fixed=None,
-         vars=0, alpha_h=1.0, weights=0):
+         vars=0, alpha_h=1.0, weights=0, split=0):
     U, M = _f64(U), _f64(M)
     _, nz, ny, nx = U.shape
     out = np.zeros_like(U)
     if lib().orc3_rhs(scheme_id(scheme), _ptr(_i3([nx, ny, nz])), _ptr(_i3([bc_id(v) for v in bc])),
                       *_sides3(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
-                      weights_id(weights), _ptr(U), _ptr(M), _ptr(out)):
+                      weights_id(weights), split_id(split), _ptr(U), _ptr(M), _ptr(out)):
         raise ValueError("orc3_rhs failed")
     return out
 
@@ -539,13 +541,13 @@ def cfl_dt3(U, M, cfl, gamma=1.4):
 
 
 def rk3_step3(scheme, U, M, dt, bc=("periodic",) * 3, gamma=1.4, alpha=1.1, eps=1e-40, ppm=1, sides=None, fixed=None,
-              vars=0, alpha_h=1.0, weights=0):
+              vars=0, alpha_h=1.0, weights=0, split=0):
     U = _f64(U).copy()
     M = _f64(M)
     _, nz, ny, nx = U.shape
     if lib().orc3_rk3_step(scheme_id(scheme), _ptr(_i3([nx, ny, nz])), _ptr(_i3([bc_id(v) for v in bc])),
                            *_sides3(sides, fixed), gamma, alpha, eps, ppm, vars_id(vars), float(alpha_h),
-                           weights_id(weights), _ptr(U), _ptr(M), float(dt)):
+                           weights_id(weights), split_id(split), _ptr(U), _ptr(M), float(dt)):
         raise ValueError("orc3_rk3_step failed")
     return U
 
@@ -574,3 +576,11 @@ def count_line_flops3(scheme, Q, K, gamma=1.4):
     if lib().orc3_count_line_flops(scheme_id(scheme), n, gamma, _ptr(Q), _ptr(K), _ptr(c)):
         raise ValueError("orc3_count_line_flops failed")
     return c
+
+
+def midpoint_split3(split, Q, k, side, gamma=1.4):
+    """F+ (side 0) or F- (side 1) of the 3-D Steger-Warming or van Leer split."""
+    Q, k = _f64(Q), _f64(k)
+    out = np.zeros(5)
+    lib().orc3_midpoint_split(split_id(split), gamma, _ptr(Q), _ptr(k), int(side), _ptr(out))
+    return out

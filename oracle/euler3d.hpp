@@ -21,7 +21,9 @@
 //     (component-wise on deviations from the reference node), the free
 //     parameter alpha of the one-midpoint families (in h+ and, through
 //     Eq. 2.7, in the metric operator), Jiang-Shu (PPM-mapped) or WENO-Z
-//     weights; the midpoint flux keeps the Lax-Friedrichs split.
+//     weights, and the Steger-Warming or van Leer split of the leading
+//     midpoint flux (Sec. 7, reading as in 2-D: H gains (F~+ - F+) +
+//     (F~- - F-) at its own midpoint, the other terms keep Lax-Friedrichs).
 // Arrays are [c][nz][ny][nx] with i fastest.
 // ---------------------------------------------------------------------------
 #pragma once
@@ -286,14 +288,68 @@ template <class T> void eigenvectors3(const T Q[5], double gam, const double n[3
   L[0][4] = 0.5 * b1; L[1][4] = -b1; L[2][4] = T(0.0); L[3][4] = T(0.0); L[4][4] = 0.5 * b1;
 }
 
+// Another split of the midpoint flux at the interpolated state Q with the
+// midpoint metric k (Sec. 7 names them; the 3-D forms of the 2-D ones):
+//   split 1 (Steger-Warming): F+- = R diag(l+-) L Q along n = k/|k|,
+//     l = |k| (q_n - c, q_n, q_n, q_n, q_n + c), l+- = (l +- |l|)/2;
+//   split 2 (van Leer): M = q_n / c; F+ = E^, F- = 0 for M >= 1 (mirrored for
+//     M <= -1), else F+- = +-|k| rho c (M +- 1)^2 / 4 (1, u + n (-q_n +- 2c)/gamma,
+//     ((gamma-1) q_n +- 2c)^2 / (2(gamma^2-1)) + (q^2 - q_n^2)/2).
+template <class T>
+void midpoint_split3(int split, double gam, const T Q[5], const double k[3], int side, T out[5]) {
+  const double kn = std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+  const double n[3] = {k[0] / kn, k[1] / kn, k[2] / kn};
+  const T rho = Q[0];
+  const T V[3] = {Q[1] / rho, Q[2] / rho, Q[3] / rho};
+  const T p = pressure3(Q, gam);
+  const T c = sqrt(gam * p / rho);
+  const T qn = V[0] * n[0] + V[1] * n[1] + V[2] * n[2];
+  if (split == 1) {
+    T L[5][5], R[5][5];
+    eigenvectors3(Q, gam, n, L, R);
+    const T lam5[5] = {kn * (qn - c), kn * qn, kn * qn, kn * qn, kn * (qn + c)};
+    T w[5];
+    for (int a = 0; a < 5; ++a) {
+      T lq = T(0.0);
+      for (int b = 0; b < 5; ++b) lq = lq + L[a][b] * Q[b];
+      const T part = side == 0 ? 0.5 * (lam5[a] + fabs(lam5[a])) : 0.5 * (lam5[a] - fabs(lam5[a]));
+      w[a] = part * lq;
+    }
+    for (int a = 0; a < 5; ++a) {
+      out[a] = T(0.0);
+      for (int b = 0; b < 5; ++b) out[a] = out[a] + R[a][b] * w[b];
+    }
+    return;
+  }
+  const T M = qn / c;
+  if ((side == 0 && T(1.0) <= M) || (side == 1 && M <= T(-1.0))) {
+    flux_hat3(Q, gam, k, out);
+    return;
+  }
+  if ((side == 0 && M <= T(-1.0)) || (side == 1 && T(1.0) <= M)) {
+    for (int q = 0; q < 5; ++q) out[q] = T(0.0);
+    return;
+  }
+  const double sg = side == 0 ? 1.0 : -1.0;
+  const T fm = sg * kn * rho * c * (M + sg) * (M + sg) / 4.0;
+  const T vt = -qn + sg * 2.0 * c;
+  const T e2 = (gam - 1.0) * qn + sg * 2.0 * c;
+  out[0] = fm;
+  for (int a = 0; a < 3; ++a) out[1 + a] = fm * (V[a] + n[a] * vt / gam);
+  out[4] = fm * (e2 * e2 / (2.0 * (gam * gam - 1.0)) + 0.5 * (V[0] * V[0] + V[1] * V[1] + V[2] * V[2] - qn * qn));
+}
+
 // Midpoint split fluxes F^+-_{k+1/2} (Secs. 2.3, 2.4, 3.4), as in 2-D: the
 // eight states Q_{k-3..k+4}, nodal metrics at k and k+1 (their normalised
 // mean is the eigenvector direction), the interpolated midpoint metric and
 // the line eigenvalue; reference state Q_k for F+, Q_{k+1} for F-, projected
 // deviations.
+// With another split (pr.split != 0) Dalt receives (F~+ - F+) + (F~- - F-).
 template <class T>
 void midpoint_flux3(Scheme sc, const Params& pr, const T Qs[8][5], const double k0[3], const double k1[3],
-                    const double mk[3], const T& lam, T Fp[5], T Fm[5]) {
+                    const double mk[3], const T& lam, T Fp[5], T Fm[5], T* Dalt = nullptr) {
+  if (Dalt)
+    for (int q = 0; q < 5; ++q) Dalt[q] = T(0.0);
   double n[3] = {0.5 * (k0[0] + k1[0]), 0.5 * (k0[1] + k1[1]), 0.5 * (k0[2] + k1[2])};
   const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
   for (int d = 0; d < 3; ++d) n[d] /= nn;
@@ -356,6 +412,11 @@ void midpoint_flux3(Scheme sc, const Params& pr, const T Qs[8][5], const double 
     const double sgn = side == 0 ? 1.0 : -1.0;
     T* out = side == 0 ? Fp : Fm;
     for (int q = 0; q < 5; ++q) out[q] = 0.5 * (E[q] + sgn * lam * Qm[q]);
+    if (Dalt && pr.split != 0) {
+      T G[5];
+      midpoint_split3(pr.split, pr.gamma, Qm, mk, side, G);
+      for (int q = 0; q < 5; ++q) Dalt[q] = Dalt[q] + (G[q] - out[q]);
+    }
   }
 }
 
@@ -388,15 +449,18 @@ void line_residual3(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam
     }
   }
   if (phase_end) phase_end(1);
+  std::vector<T> Dv(pr.split != 0 ? 5 * len : 0);
   for (int k = -4; k < n + 3; ++k) {
     T Qs[8][5];
     for (int m = 0; m < 8; ++m)
       for (int q = 0; q < 5; ++q) Qs[m][q] = Q(k - 3 + m, q);
     const double k0[3] = {K(0, k), K(1, k), K(2, k)}, k1[3] = {K(0, k + 1), K(1, k + 1), K(2, k + 1)};
     const double mk[3] = {K(3, k), K(4, k), K(5, k)};
-    T a[5], b[5];
-    midpoint_flux3(sc, pr, Qs, k0, k1, mk, lam, a, b);
+    T a[5], b[5], Da[5];
+    midpoint_flux3(sc, pr, Qs, k0, k1, mk, lam, a, b, pr.split != 0 ? Da : nullptr);
     for (int q = 0; q < 5; ++q) { Fp[q * len + k + off] = a[q]; Fm[q * len + k + off] = b[q]; }
+    if (pr.split != 0)
+      for (int q = 0; q < 5; ++q) Dv[q * len + k + off] = Da[q];
   }
   if (phase_end) phase_end(2);
   std::vector<T> H(5 * (n + 1));
@@ -407,6 +471,7 @@ void line_residual3(Scheme sc, const Params& pr, int n, QF Q, KF K, T* R, T* lam
       auto fmn = [&](int m) { return fm[q * len + i + 1 - m + off]; };
       auto Fmm = [&](int m) { return Fm[q * len + i - m + off]; };
       H[q * (n + 1) + i + 1] = h_plus<T>(sc, pr.alpha_h, fpn, Fpm) + h_plus<T>(sc, pr.alpha_h, fmn, Fmm);
+      if (pr.split != 0) H[q * (n + 1) + i + 1] = H[q * (n + 1) + i + 1] + Dv[q * len + i + off];
     }
   for (int k = 0; k < n; ++k)
     for (int q = 0; q < 5; ++q) R[q * n + k] = H[q * (n + 1) + k + 1] - H[q * (n + 1) + k];

@@ -510,10 +510,10 @@ int orc3_metrics(int scheme, const int* n, const int* bc, const double* L, const
 }
 
 int orc3_rhs(int scheme, const int* n, const int* bc, const int* side, const double* fixed, double gamma,
-             double alpha, double eps, int ppm, int vars, double alpha_h, int weights, const double* U,
+             double alpha, double eps, int ppm, int vars, double alpha_h, int weights, int split, const double* U,
              const double* M, double* out) {
-  if (bad_options(scheme, vars, alpha_h, weights, 0) || bad_grid3(n, bc)) return -1;
-  rhs3((Scheme)scheme, make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights),
+  if (bad_options(scheme, vars, alpha_h, weights, split) || bad_grid3(n, bc)) return -1;
+  rhs3((Scheme)scheme, make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split),
        make_grid3(n, bc, kNoPeriod, side, fixed), U, M, out);
   return 0;
 }
@@ -524,10 +524,10 @@ double orc3_cfl_dt(const int* n, double gamma, const double* U, const double* M,
 }
 
 int orc3_rk3_step(int scheme, const int* n, const int* bc, const int* side, const double* fixed, double gamma,
-                  double alpha, double eps, int ppm, int vars, double alpha_h, int weights, double* U,
+                  double alpha, double eps, int ppm, int vars, double alpha_h, int weights, int split, double* U,
                   const double* M, double dt) {
-  if (bad_options(scheme, vars, alpha_h, weights, 0) || bad_grid3(n, bc)) return -1;
-  rk3_step3((Scheme)scheme, make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights),
+  if (bad_options(scheme, vars, alpha_h, weights, split) || bad_grid3(n, bc)) return -1;
+  rk3_step3((Scheme)scheme, make_params(gamma, alpha, eps, ppm, vars, alpha_h, weights, split),
             make_grid3(n, bc, kNoPeriod, side, fixed), U, M, dt);
   return 0;
 }
@@ -540,6 +540,11 @@ void orc3_eigenvectors(const double* Q, double gamma, const double* nvec, double
 }
 
 void orc3_flux_hat(const double* Q, double gamma, const double* k, double* out) { flux_hat3(Q, gamma, k, out); }
+
+// Another split of the midpoint flux (split 1 Steger-Warming, 2 van Leer).
+void orc3_midpoint_split(int split, double gamma, const double* Q, const double* k, int side, double* out) {
+  midpoint_split3(split, gamma, Q, k, side, out);
+}
 
 // Operation counts of one 3-D grid line of n nodes (line_residual3 with the
 // counting scalar), by phase: [0] line maximum, [1] nodal split fluxes

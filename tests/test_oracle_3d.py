@@ -227,7 +227,9 @@ def test_free_stream_with_walls_and_inflow_3d(s):
 
 OPTION_CASES = [("5-2MP", dict(vars="conservative")), ("5-1MP", dict(vars="primitive")),
                 ("3-2MP", dict(weights="z")), ("7-1MP", dict(weights="z", vars="primitive")),
-                ("3-1MP", dict(alpha_h=0.8)), ("5-1MP", dict(alpha_h=1.3, vars="conservative"))]
+                ("3-1MP", dict(alpha_h=0.8)), ("5-1MP", dict(alpha_h=1.3, vars="conservative")),
+                ("5-2MP", dict(split="sw")), ("3-1MP", dict(split="vl")), ("7-2MP", dict(split="sw", weights="z")),
+                ("5-1MP", dict(split="vl", vars="primitive"))]
 
 
 @pytest.mark.parametrize("s,opts", OPTION_CASES)
@@ -259,3 +261,24 @@ def test_free_stream_preserved_with_options(s, opts):
         U = W.uniform_flow3(g)
         M = orc.metrics3(s, g.x, g.y, g.z, g.bc, g.period, alpha_h=opts.get("alpha_h", 1.0))
         assert np.abs(orc.rhs3(s, U, M, g.bc, **opts)).max() < 1e-11
+
+
+def test_3d_splits_sum_to_the_flux_and_van_leer_limits():
+    """Both 3-D splits satisfy F+ + F- = E^(Q; k) (E^ is homogeneous of
+    degree one); van Leer's F+ is E^ and F- zero for M >= 1 (mirrored for
+    M <= -1); for random 3-D states and directions."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        vel = rng.standard_normal(3) * 0.8
+        Q = W.conservative3(0.5 + rng.random(), *vel, 0.5 + rng.random())
+        k = rng.standard_normal(3) * (0.5 + rng.random())
+        E = orc.flux_hat3(Q, 1.4, k)
+        for sp in ("sw", "vl"):
+            tot = orc.midpoint_split3(sp, Q, k, 0) + orc.midpoint_split3(sp, Q, k, 1)
+            assert np.allclose(tot, E, rtol=1e-13, atol=1e-13 * np.abs(E).max()), sp
+    # supersonic along k
+    Q = W.conservative3(1.0, 2.0, 0.3, -0.4, 0.5)
+    k = np.array([1.0, 0.1, -0.2])
+    assert np.allclose(orc.midpoint_split3("vl", Q, k, 0), orc.flux_hat3(Q, 1.4, k), rtol=1e-14)
+    assert np.all(orc.midpoint_split3("vl", Q, k, 1) == 0.0)
+    assert np.allclose(orc.midpoint_split3("vl", Q, -k, 1), orc.flux_hat3(Q, 1.4, -k), rtol=1e-14)

@@ -327,11 +327,11 @@ int wiu_plan_destroy(wiu_plan* plan);
  * eigenvectors along the unit direction (shear waves along t2 and t1: t1
  * the axis of the smallest component of n, ties to the later axis, made
  * orthogonal to n; t2 = t1 x n), TVD-RK3.  J^{-1} by Eq. 2.5 or Eq. 2.6
- * (wiu3_metrics).  wiu_params selects the interpolation variables
- * (component-wise on deviations for conservative or primitive (rho, u, v,
- * w, p) variables), alpha_h of the one-midpoint schemes and the weights as
- * in 2-D; the midpoint flux keeps the Lax-Friedrichs split (another split
- * gives WIU_EINVAL).
+ * (wiu3_metrics).  wiu_params selects the options as in 2-D: the
+ * interpolation variables (component-wise on deviations for conservative
+ * or primitive (rho, u, v, w, p) variables), alpha_h of the one-midpoint
+ * schemes, the weights, and the Steger-Warming or van Leer split of the
+ * leading midpoint flux (the 3-D forms of the 2-D splits).
  *
  * Layouts (device, caller-owned): coordinates x, y, z and each state
  * component [nz][ny][nx], i fastest; U [5][nz][ny][nx]; M 19 planes of

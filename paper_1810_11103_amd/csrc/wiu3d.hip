@@ -266,15 +266,67 @@ WIU_DEV void tangents3(const double n[3], double t1[3], double t2[3]) {
   t2[2] = t1[0] * n[1] - t1[1] * n[0];
 }
 
+// Another split of the midpoint flux at the interpolated state Q with the
+// midpoint metric k (Sec. 7; the 3-D forms of the 2-D ones).
+//   split 1, Steger-Warming: F+- = R diag(l+-) L Q along n = k/|k| at Q, with
+//     l = |k| (q_n - c, q_n, q_n, q_n, q_n + c), l+- = (l +- |l|)/2; the
+//     shear rows of L annihilate Q, so only the acoustic and entropy fields
+//     contribute;
+//   split 2, van Leer: the Mach-number split along n.
+WIU_DEV void mid_split_alt3(int split, const double Q[5], const double k[3], int side, double gam, double G[5]) {
+  const double kn = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+  const double rkn = rcp(kn);
+  const double n[3] = {k[0] * rkn, k[1] * rkn, k[2] * rkn};
+  const double ri = rcp(Q[0]);
+  const double V[3] = {Q[1] * ri, Q[2] * ri, Q[3] * ri};
+  const double q2 = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+  const double p = (gam - 1.0) * (Q[4] - 0.5 * Q[0] * q2);
+  const double c2 = gam * p * ri;
+  const double rc = rsqrt_(c2);
+  const double c = c2 * rc;
+  const double qn = V[0] * n[0] + V[1] * n[1] + V[2] * n[2];
+  if (split == 1) {
+    const double H = (Q[4] + p) * ri;
+    const double b1 = (gam - 1.0) * (rc * rc);
+    const double b2 = 0.5 * b1 * q2;
+    const double A = b2 * Q[0] - b1 * (V[0] * Q[1] + V[1] * Q[2] + V[2] * Q[3] - Q[4]);
+    const double Bn = rc * (qn * Q[0] - (n[0] * Q[1] + n[1] * Q[2] + n[2] * Q[3]));
+    const double l0 = kn * (qn - c), l1 = kn * qn, l4 = kn * (qn + c);
+    auto part = [&](double l) { return side == 0 ? 0.5 * (l + fabs(l)) : 0.5 * (l - fabs(l)); };
+    const double w0 = part(l0) * 0.5 * (A + Bn), w1 = part(l1) * (Q[0] - A), w4 = part(l4) * 0.5 * (A - Bn);
+    G[0] = w0 + w1 + w4;
+    for (int a = 0; a < 3; ++a) G[1 + a] = (w0 + w1 + w4) * V[a] + c * n[a] * (w4 - w0);
+    G[4] = H * (w0 + w4) + c * qn * (w4 - w0) + 0.5 * q2 * w1;
+    return;
+  }
+  const double M = qn * rc;
+  if ((side == 0 && 1.0 <= M) || (side == 1 && M <= -1.0)) {
+    flux3(Q, k, gam, G);
+    return;
+  }
+  if ((side == 0 && M <= -1.0) || (side == 1 && 1.0 <= M)) {
+    for (int a = 0; a < 5; ++a) G[a] = 0.0;
+    return;
+  }
+  const double sg = side == 0 ? 1.0 : -1.0;
+  const double fm = sg * kn * Q[0] * c * (M + sg) * (M + sg) * 0.25;
+  const double vt = -qn + sg * 2.0 * c;
+  const double e2 = (gam - 1.0) * qn + sg * 2.0 * c;
+  G[0] = fm;
+  for (int a = 0; a < 3; ++a) G[1 + a] = fm * (V[a] + n[a] * vt / gam);
+  G[4] = fm * (e2 * e2 / (2.0 * (gam * gam - 1.0)) + 0.5 * (q2 - qn * qn));
+}
+
 // One side of the midpoint k+1/2 (side 0: F+, reference Q_k; side 1: F-,
 // reference Q_{k+1}): project the stencil's deviations from the reference
 // on the characteristic fields (rows of L for q_n - c, q_n, shear t2, shear
 // t1, q_n + c), interpolate each with WENO, map back with R, add the
 // reference, then the Lax-Friedrichs half flux with the midpoint metric.
 // q(s, c): state at window slot s = 0..7 (nodes k-3 .. k+4).
+// With split != 0, Dacc accumulates the other split's difference G - F.
 template <int R, bool ZOK = false, class QF>
 WIU_DEV void side_flux3(QF q, int side, const double n[3], const double mk[3], double lam, double gam, double eps,
-                        int ppm, double F[5]) {
+                        int ppm, double F[5], int split = 0, double* Dacc = nullptr) {
   double Qr[5];
   for (int c = 0; c < 5; ++c) Qr[c] = q(3 + side, c);
   double t1[3], t2[3];
@@ -335,6 +387,11 @@ WIU_DEV void side_flux3(QF q, int side, const double n[3], const double mk[3], d
   flux3(r, mk, gam, E);
   const double sl = side == 0 ? lam : -lam;
   for (int a = 0; a < 5; ++a) F[a] = 0.5 * (E[a] + sl * r[a]);
+  if (split != 0) {
+    double G[5];
+    mid_split_alt3(split, r, mk, side, gam, G);
+    for (int a = 0; a < 5; ++a) Dacc[a] += G[a] - F[a];
+  }
 }
 
 // The same side flux with the interpolation component by component
@@ -342,7 +399,7 @@ WIU_DEV void side_flux3(QF q, int side, const double n[3], const double mk[3], d
 // deviations from the reference node's values.
 template <int R, bool ZOK, class QF>
 WIU_DEV void side_flux3_comp(QF q, int side, int vars, const double mk[3], double lam, double gam, double eps,
-                             int ppm, double F[5]) {
+                             int ppm, double F[5], int split = 0, double* Dacc = nullptr) {
   constexpr int NS = R == 2 ? 4 : (R == 3 ? 5 : 7);
   constexpr int C0 = R == 4 ? 3 : 2;
   auto val = [&](int slot, double V[5]) {
@@ -389,6 +446,11 @@ WIU_DEV void side_flux3_comp(QF q, int side, int vars, const double mk[3], doubl
   flux3(r, mk, gam, E);
   const double sl = side == 0 ? lam : -lam;
   for (int a = 0; a < 5; ++a) F[a] = 0.5 * (E[a] + sl * r[a]);
+  if (split != 0) {
+    double G[5];
+    mid_split_alt3(split, r, mk, side, gam, G);
+    for (int a = 0; a < 5; ++a) Dacc[a] += G[a] - F[a];
+  }
 }
 
 // ===========================================================================
@@ -404,6 +466,7 @@ struct S3Args {
   int vars;                        // WIU_VARS_* (interpolation variables)
   double ah;                       // free parameter of the one-midpoint schemes
   int weights;                     // WIU_WEIGHTS_*
+  int split;                       // WIU_SPLIT_* of the leading midpoint flux
   double* Racc;                    // accumulated flux differences [5][np]
   double* out;                     // dU/dt (mode 2) or the new stage state (mode 3)
   const double* U0;                // RK base state
@@ -436,10 +499,13 @@ WIU_DEV bool tag3_ok(const Dims3& d, const double* M, int scheme, double ah) {
 // from E^ and the staged state); the states of items k - QL .. k + QL + 1.
 // Lanes of a wave touch consecutive words: line-major for xi tiles (lanes
 // along the line), position-major otherwise (lanes across lines along i).
-template <int SC, int DIR, int NA, int NB> struct Sweep3Lds {
+template <int SC, int DIR, int NA, int NB, bool OPT = false> struct Sweep3Lds {
   static constexpr int QL = Range<SC>::QL;
   static constexpr int NQ = NA + 2 * QL + 1;
-  double sh[15][NA * NB];
+  // with the options, 5 more per item: D, the difference another midpoint
+  // split makes to H at the item's midpoint
+  static constexpr int NREC = OPT ? 20 : 15;
+  double sh[NREC][NA * NB];
   double sq[5][NB * NQ];
   static WIU_DEV int si(int tb, int ta) { return DIR == 0 ? tb * NA + ta : ta * NB + tb; }
   static WIU_DEV int qi(int tb, int pos) { return DIR == 0 ? tb * NQ + pos : pos * NB + tb; }
@@ -457,13 +523,14 @@ template <int SC, int DIR, int NA, int NB> struct Sweep3Lds {
 // it the sweep runs the paper's configuration and carries no code for them.
 template <int SC, int DIR, int NA, int NB, bool OPT>
 __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
-  __shared__ Sweep3Lds<SC, DIR, NA, NB> L;
+  __shared__ Sweep3Lds<SC, DIR, NA, NB, OPT> L;
   using R_ = Range<SC>;
-  using LT = Sweep3Lds<SC, DIR, NA, NB>;
+  using LT = Sweep3Lds<SC, DIR, NA, NB, OPT>;
   constexpr int OUT = NA - R_::EXTRA, QL = R_::QL, NQ = LT::NQ, NT = NA * NB;
   const Dims3& d = a.d;
   const double ah = OPT ? a.ah : 1.0;
   const int ppm = OPT && a.weights != 0 ? 2 : a.ppm;  // 2: WENO-Z weights
+  const int split = OPT ? a.split : 0;                 // another split of the leading midpoint flux
   if (!tag3_ok(d, a.M, SC, ah)) {  // block-uniform
     if (threadIdx.x == 0 && threadIdx.y == 0) atomicOr(a.status, ST_SCHEME);
     return;
@@ -579,15 +646,19 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
     for (int c = 0; c < 3; ++c) nv[c] *= rn;
     // window slot s = 0..7 is node k - 3 + s
     auto q = [&](int s_, int c) { return L.sq[c][LT::qi(tb, ta + QL - 3 + s_)]; };
+    double D[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       asm volatile("" ::: "memory");  // one side at a time (register pressure)
       double F[5];
       if (OPT && a.vars != 0)
-        side_flux3_comp<Traits<SC>::R, OPT>(q, side, a.vars, mk, lam, gam, a.eps, ppm, F);
+        side_flux3_comp<Traits<SC>::R, OPT>(q, side, a.vars, mk, lam, gam, a.eps, ppm, F, split, D);
       else
-        side_flux3<Traits<SC>::R, OPT>(q, side, nv, mk, lam, gam, a.eps, ppm, F);
+        side_flux3<Traits<SC>::R, OPT>(q, side, nv, mk, lam, gam, a.eps, ppm, F, split, D);
       for (int c = 0; c < 5; ++c) L.sh[5 + 5 * side + c][slot] = F[c];
+    }
+    if constexpr (OPT) {
+      for (int c = 0; c < 5; ++c) L.sh[LT::NREC - 5 + c][slot] = D[c];
     }
   }
   __syncthreads();
@@ -608,6 +679,10 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
     auto Fp = [&](int kk) { return gp[(kk - i) * S]; };
     auto Fm = [&](int kk) { return gm[(kk - i) * S]; };
     Rv[c] = hflux<SC>(i, ah, fp, fm, Fp, Fm) - hflux<SC>(i - 1, ah, fp, fm, Fp, Fm);
+    if constexpr (OPT) {
+      const double* dd = &L.sh[LT::NREC - 5 + c][hs];
+      if (split != 0) Rv[c] += dd[0] - dd[-S];
+    }
   }
   int p[3];
   node(i, la, p);
@@ -756,15 +831,15 @@ bool alpha3_ok(int scheme, double a) {
   return a > 0.0 && a < 1.0e300 && (a == 1.0 || scheme == WIU_3_1MP || scheme == WIU_5_1MP || scheme == WIU_7_1MP);
 }
 
-// the 3-D path has every option but the other midpoint splits
 bool params3_ok(const wiu_params* p, int scheme) {
   return p && p->gamma > 1.0 && p->alpha_lf > 0.0 && p->eps >= 0.0 && (p->ppm == 0 || p->ppm == 1) &&
          p->vars >= WIU_VARS_CHARACTERISTIC && p->vars <= WIU_VARS_PRIMITIVE && alpha3_ok(scheme, p->alpha_h) &&
-         (p->weights == WIU_WEIGHTS_JS || p->weights == WIU_WEIGHTS_Z) && p->split == WIU_SPLIT_LF;
+         (p->weights == WIU_WEIGHTS_JS || p->weights == WIU_WEIGHTS_Z) && p->split >= WIU_SPLIT_LF &&
+         p->split <= WIU_SPLIT_VL;
 }
 
 void options3(const wiu_params* p, S3Args& a) {
-  a.vars = p->vars; a.ah = p->alpha_h; a.weights = p->weights;
+  a.vars = p->vars; a.ah = p->alpha_h; a.weights = p->weights; a.split = p->split;
 }
 
 void sides3(const wiu_grid3* g, S3Args& a) {
@@ -802,7 +877,7 @@ hipError_t launch_pass3_o(const S3Args& a, int D, int mode, hipStream_t st) {
 // the options kernels only when an option is in use
 template <int SC>
 hipError_t launch_pass3(const S3Args& a, int D, int mode, hipStream_t st) {
-  if (a.vars != 0 || a.ah != 1.0 || a.weights != 0) return launch_pass3_o<SC, true>(a, D, mode, st);
+  if (a.vars != 0 || a.ah != 1.0 || a.weights != 0 || a.split != 0) return launch_pass3_o<SC, true>(a, D, mode, st);
   return launch_pass3_o<SC, false>(a, D, mode, st);
 }
 

@@ -156,8 +156,8 @@ def test_block_sets_are_validated(wiu):
 
 def test_3d_grids_and_options_are_validated(wiu):
     """3-D grids need positive sizes (two nodes in transmissive directions,
-    positive periods in periodic ones); the 3-D path has every scheme option
-    but the other midpoint splits, which are rejected on the host."""
+    positive periods in periodic ones); out-of-range options are rejected on
+    the host."""
     g = wiu.make_grid3(16, 12, 10, ("periodic", "transmissive", "periodic"), (1.0, 0.0, 1.0))
     assert wiu.lib.wiu3_metrics_size(ctypes.byref(g)) == (19 * 24 * 20 * 18 + 8) * 8
     assert wiu.lib.wiu3_workspace_bytes(ctypes.byref(g)) > 0
@@ -165,8 +165,8 @@ def test_3d_grids_and_options_are_validated(wiu):
                 wiu.make_grid3(16, 12, 10, ("periodic",) * 3, (1.0, 0.0, 1.0))):
         assert wiu.lib.wiu3_metrics_size(ctypes.byref(bad)) == 0
     dummy = ctypes.c_void_p(8)
-    # every option but the other midpoint splits; alpha_h only for one-midpoint schemes
-    for scheme, opts in ((3, dict(split="sw")), (3, dict(split="vl")), (3, dict(alpha_h=0.9))):
+    # options as in 2-D: alpha_h only for one-midpoint schemes, enums in range
+    for scheme, opts in ((3, dict(split=3)), (3, dict(vars=3)), (3, dict(alpha_h=0.9))):
         P = wiu.make_params(**opts)
         rc = wiu.lib.wiu3_rhs(ctypes.byref(g), scheme, ctypes.byref(P), dummy, dummy, dummy, dummy, None)
         assert rc == wiu.WIU_EINVAL

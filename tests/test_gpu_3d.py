@@ -137,7 +137,7 @@ def test_z_independent_data_give_the_2d_flux_residual(wiu):
 def test_options_and_mismatched_metrics_rejected(wiu):
     import torch
     g, U = case("periodic")
-    sol = wiu.Solver3(g.x, g.y, g.z, "5-2MP", g.bc, g.period, params=wiu.make_params(split="sw"))
+    sol = wiu.Solver3(g.x, g.y, g.z, "5-2MP", g.bc, g.period, params=wiu.make_params(vars=3))
     with pytest.raises(RuntimeError):
         sol.rhs(dev(U))
     other = wiu.Solver3(g.x, g.y, g.z, "3-1MP", g.bc, g.period)
@@ -263,10 +263,13 @@ def test_free_stream_with_walls_and_inflow_on_gpu(wiu):
 
 # (scheme, options, state): the octant Riemann state where one CFL-0.25 step
 # stays physical; 3-2MP with WENO-Z loses positivity on it (in the oracle as
-# on the GPU), so that case runs on a smooth state
+# on the GPU), so those cases run on a smooth state (also 3-1MP with the van
+# Leer split)
 OPTION_CASES3 = [("5-2MP", dict(vars="conservative"), "octant"), ("5-1MP", dict(vars="primitive"), "octant"),
                  ("3-2MP", dict(weights="z"), "smooth"), ("7-1MP", dict(weights="z", vars="primitive"), "octant"),
-                 ("3-1MP", dict(alpha_h=0.8), "octant"), ("5-1MP", dict(alpha_h=1.3, vars="conservative"), "octant")]
+                 ("3-1MP", dict(alpha_h=0.8), "octant"), ("5-1MP", dict(alpha_h=1.3, vars="conservative"), "octant"),
+                 ("5-2MP", dict(split="sw"), "octant"), ("3-1MP", dict(split="vl"), "smooth"),
+                 ("7-2MP", dict(split="sw", weights="z"), "smooth"), ("5-1MP", dict(split="vl", vars="primitive"), "octant")]
 
 
 @pytest.mark.parametrize("s,opts,state", OPTION_CASES3)

@@ -309,3 +309,30 @@ def test_metrics_tag_records_alpha_3d(wiu):
     assert sol.status() & wiu.ST_SCHEME
     assert bool(torch.all(out == 7.0))
 
+
+
+@pytest.mark.parametrize("shape,bc", [((1, 5, 7), ("periodic", "periodic", "periodic")),
+                                      ((4, 9, 2), ("transmissive", "periodic", "periodic")),
+                                      ((17, 1, 33), ("periodic", "periodic", "transmissive")),
+                                      ((3, 2, 2), ("transmissive", "transmissive", "transmissive"))])
+def test_degenerate_shapes(orc, wiu, shape, bc):
+    """One node along a periodic direction, two along a bounded one, and
+    tiny grids: rhs and an RK3 step against the oracle."""
+    say("3-D degenerate", shape, bc)
+    nz, ny, nx = shape
+    g = W.mixed_grid3(nx, ny, nz, bc, A=0.1, seed=4, layers=1)
+    U = W.smooth_state3(g, seed=1)
+    for s in ("3-1MP", "5-2MP"):
+        Mo = orc.metrics3(s, g.x, g.y, g.z, g.bc, g.period)
+        sol = wiu.Solver3(g.x, g.y, g.z, s, g.bc, g.period)
+        assert np.allclose(host(sol.planes()), Mo, rtol=0.0, atol=1e-13 * np.abs(Mo).max())
+        ref = orc.rhs3(s, U, Mo, g.bc)
+        out = host(sol.rhs(dev(U)))
+        assert sol.status() == 0
+        scale = np.abs(ref).max() + 1e-300
+        assert np.abs(out - ref).max() <= 1e-12 * max(scale, 1.0)
+        dt = 0.5 * orc.cfl_dt3(U, Mo, 0.5)
+        ref = orc.rk3_step3(s, U, Mo, dt, g.bc)
+        Ud = dev(U)
+        sol.rk3_step(Ud, dt)
+        assert np.abs(host(Ud) - ref).max() <= 1e-12

@@ -61,26 +61,32 @@ PEAK_FP64_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
 
-# HBM traffic of the dominant kernel, from the committed rocprofv3 counter
-# summary; used only while the kernel sources are the ones profiled.
+# HBM traffic of the dominant kernels, from the committed rocprofv3 counter
+# summaries; used only while the kernel sources are the ones profiled.
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_eta_riemann2048_hbm.md")
 KERNEL_SOURCES = ("paper_1810_11103_amd/csrc/wiu_device.hpp", "paper_1810_11103_amd/csrc/wiu_kernels.hpp",
                   "paper_1810_11103_amd/csrc/wiu_sweep.hpp",
                   "paper_1810_11103_amd/csrc/wiu_kernels.hip")
+TRAFFIC_SUMMARY3 = os.path.join(ROOT, "profiles", "sweep3_octant256_counters.md")
+KERNEL_SOURCES3 = ("paper_1810_11103_amd/csrc/wiu_device.hpp", "paper_1810_11103_amd/csrc/wiu_kernels.hpp",
+                   "paper_1810_11103_amd/csrc/wiu3d.hip")
 
 
-def profiled_traffic(n):
+def profiled_traffic(n, summary=TRAFFIC_SUMMARY, sources=KERNEL_SOURCES, n_profiled=None):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch recorded in `summary`,
+    or None when the workload or the kernel sources differ from the
+    profiled ones."""
     import hashlib
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(summary).read()
     except OSError:
         return None
     fields = dict(line.strip().split(": ", 1) for line in text.splitlines()
                   if line.startswith("    ") and ": " in line)
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if n != N_DEFAULT or fields.get("source_sha") != h.hexdigest()[:16]:
+    if n != (N_DEFAULT if n_profiled is None else n_profiled) or fields.get("source_sha") != h.hexdigest()[:16]:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -200,7 +206,9 @@ def three_d_leg(n=256, steps=8, cfl=0.5, scheme="5-2MP"):
             "kernels_ms": {k: round(v[1], 4) for k, v in kern.items()},
             "roofline": {"bound": "alu", "kernel": "sweep3", "achieved": round(achieved, 3),
                          "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                         "flops_per_launch": per_launch, "launches": kern["sweep3"][0]},
+                         "flops_per_launch": per_launch, "launches": kern["sweep3"][0],
+                         "traffic": (profiled_traffic(n, TRAFFIC_SUMMARY3, KERNEL_SOURCES3, 256)
+                                     if scheme == "5-2MP" else None)},
             "status": sol.status()}
 
 

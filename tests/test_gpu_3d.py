@@ -336,3 +336,33 @@ def test_degenerate_shapes(orc, wiu, shape, bc):
         Ud = dev(U)
         sol.rk3_step(Ud, dt)
         assert np.abs(host(Ud) - ref).max() <= 1e-12
+
+
+def test_status_flags_3d(wiu):
+    """Device-latched errors of the 3-D path: a non-physical state, metrics
+    of another scheme (nothing written) and a folded grid (J^{-1} <= 0)."""
+    import ctypes
+    import torch
+    say("3-D status flags")
+    g = W.periodic_grid3(24, 20, 16, box=(0.0, 1.2, 0.0, 1.0, 0.0, 0.8), A=0.2, seed=2)
+    U = W.smooth_state3(g, seed=2)
+    sol = wiu.Solver3(g.x, g.y, g.z, "5-2MP", g.bc, g.period)
+    assert sol.status() == 0
+    Ub = U.copy()
+    Ub[4, 5, 6, 7] = 0.1 * Ub[4, 5, 6, 7] - 5.0   # negative pressure at one node
+    sol.rhs(dev(Ub))
+    assert sol.status() & wiu.ST_NONPHYS
+    other = wiu.Solver3(g.x, g.y, g.z, "3-1MP", g.bc, g.period)
+    out = torch.full(U.shape, 7.0, dtype=torch.float64, device="cuda")
+    Ud = dev(U)
+    rc = wiu.lib.wiu3_rhs(ctypes.byref(sol.grid), wiu.scheme_id("5-2MP"), ctypes.byref(sol.params),
+                          ctypes.c_void_p(Ud.data_ptr()), ctypes.c_void_p(other.M.data_ptr()),
+                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(sol.ws.data_ptr()), wiu._stream())
+    assert rc == 0
+    assert sol.status() & wiu.ST_SCHEME
+    assert float(out.min()) == 7.0 and float(out.max()) == 7.0
+    gf = W.periodic_grid3(24, 24, 24, box=(0.0, 10.0, 0.0, 10.0, 0.0, 10.0))
+    x = gf.x.copy()
+    x[10, 10, 10] += 3.0 * 10.0 / 24    # node pushed past its neighbours: J^{-1} < 0
+    with pytest.raises(wiu.WiuError):
+        wiu.Solver3(x, gf.y, gf.z, "5-2MP", gf.bc, gf.period)

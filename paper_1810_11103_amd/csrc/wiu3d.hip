@@ -518,7 +518,7 @@ template <int SC, int DIR, int NA, int NB, bool OPT = false> struct Sweep3Lds {
 // (nodal flux at k and both side fluxes at k + 1/2), then the first OUT
 // lanes of each line form H_{i+1/2} - H_{i-1/2} and, by `mode`: 0 Racc = R;
 // 1 Racc += R; 2 dU/dt = -(Racc + R)/J^{-1}; 3 the RK stage
-// U_out = ca U0 + cb (U + dt dU/dt).  Two block-wide barriers on every path.
+// U_out = ca U0 + cb (U + dt dU/dt).  Four block-wide barriers on every path.
 // OPT: compiled with the scheme options (a.vars, a.ah, a.weights); without
 // it the sweep runs the paper's configuration and carries no code for them.
 template <int SC, int DIR, int NA, int NB, bool OPT>
@@ -662,28 +662,49 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
     }
   }
   __syncthreads();
+  constexpr int S = DIR == 0 ? 1 : NB;
+  // H_{k+1/2} once per item, for the midpoints k + 1/2 of k in [o0 - 1,
+  // o0 + out), into the item's nodal-flux slots once every record is read;
+  // each midpoint's H is then read by both of its nodes (exact telescoping)
+  {
+    const bool hact = live && k >= o0 - 1 && k < o0 + out;
+    double Hk[5];
+    if (hact) {
+      const int qs = LT::qi(tb, ta + QL);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const double* e = &L.sh[c][slot];
+        const double* qv = &L.sq[c][qs];
+        const double* gp = &L.sh[5 + c][slot];
+        const double* gm = &L.sh[10 + c][slot];
+        if constexpr (SC == 3) {
+          Hk[c] = hsum52(lam, [&](int m) { return e[m * S]; }, [&](int m) { return qv[m * S]; },
+                         [&](int m) { return gp[m * S]; }, [&](int m) { return gm[m * S]; });
+        } else {
+          auto fp = [&](int kk) { return 0.5 * (e[(kk - k) * S] + lam * qv[(kk - k) * S]); };
+          auto fm = [&](int kk) { return 0.5 * (e[(kk - k) * S] - lam * qv[(kk - k) * S]); };
+          auto Fp = [&](int kk) { return gp[(kk - k) * S]; };
+          auto Fm = [&](int kk) { return gm[(kk - k) * S]; };
+          Hk[c] = hflux<SC>(k, ah, fp, fm, Fp, Fm);
+        }
+        if constexpr (OPT) {
+          if (split != 0) Hk[c] += L.sh[LT::NREC - 5 + c][slot];
+        }
+      }
+    }
+    __syncthreads();
+    if (hact) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) L.sh[c][slot] = Hk[c];
+    }
+    __syncthreads();
+  }
   if (!live || ta >= out) return;
   const int i = o0 + ta;
   const int hs = LT::si(tb, i - (o0 + R_::LO));
-  const int qs = LT::qi(tb, i - (o0 + R_::LO) + QL);
-  constexpr int S = DIR == 0 ? 1 : NB;
   double Rv[5];
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    const double* e = &L.sh[c][hs];
-    const double* qv = &L.sq[c][qs];
-    const double* gp = &L.sh[5 + c][hs];
-    const double* gm = &L.sh[10 + c][hs];
-    auto fp = [&](int kk) { return 0.5 * (e[(kk - i) * S] + lam * qv[(kk - i) * S]); };
-    auto fm = [&](int kk) { return 0.5 * (e[(kk - i) * S] - lam * qv[(kk - i) * S]); };
-    auto Fp = [&](int kk) { return gp[(kk - i) * S]; };
-    auto Fm = [&](int kk) { return gm[(kk - i) * S]; };
-    Rv[c] = hflux<SC>(i, ah, fp, fm, Fp, Fm) - hflux<SC>(i - 1, ah, fp, fm, Fp, Fm);
-    if constexpr (OPT) {
-      const double* dd = &L.sh[LT::NREC - 5 + c][hs];
-      if (split != 0) Rv[c] += dd[0] - dd[-S];
-    }
-  }
+  for (int c = 0; c < 5; ++c) Rv[c] = L.sh[c][hs] - L.sh[c][hs - S];
   int p[3];
   node(i, la, p);
   const long long t = u3idx(d, p[0], p[1], p[2]);

@@ -743,6 +743,23 @@ WIU_DEV double h1mp_plus(double a, NF f, MF F) {
   }
 }
 
+// H_{k+1/2} = h^+_{k+1/2} + h^-_{k+1/2} of WENOIU5-2MP (Eq. 3.20 and its
+// mirror image) with the nodal split fluxes written as f^+- = (E +- lam Q)/2.
+// Collecting the terms of both halves gives
+//   H = 6/5 (F^+_k + F^-_k) - 2/15 (F^+_{k-1} + F^-_{k+1})
+//     + 1/60 [E_{k-1} + E_{k+2} - 3 (E_k + E_{k+1})]
+//     + lam/60 [Q_{k-1} - Q_{k+2} + 5 (Q_k - Q_{k+1})],
+// the linear map of hflux<3> in eleven operations instead of about twenty;
+// for a uniform state the lam Q terms vanish exactly.  E(m), Q(m): nodal
+// flux and state at k + m; Fp(m), Fm(m): midpoint split fluxes at k + m + 1/2.
+template <class EF, class QF, class GP, class GM>
+WIU_DEV double hsum52(double lam, EF E, QF Q, GP Fp, GM Fm) {
+  const double g0 = Fp(0) + Fm(0), g1 = Fp(-1) + Fm(1);
+  const double ep = fma(-3.0, E(0) + E(1), E(-1) + E(2));
+  const double qp = fma(5.0, Q(0) - Q(1), Q(-1) - Q(2));
+  return fma(1.0 / 60.0, fma(lam, qp, ep), fma(-2.0 / 15.0, g1, 1.2 * g0));
+}
+
 template <int SC, class FP, class FM, class GP, class GM>
 WIU_DEV double hflux(int i, double ah, FP fp, FM fm, GP Fp, GM Fm) {
   if constexpr (SC == 0 || SC == 2 || SC == 4) {

@@ -93,34 +93,45 @@ template <int SC, int DIR, int NA, int NB, bool OPT = false> struct SweepLds {
   static WIU_DEV int qi(int tb, int pos) { return DIR == 0 ? tb * NQ + pos : pos * NB + tb; }
 };
 
-// H_{i+1/2} - H_{i-1/2} at output node i of line tb from the items in LDS.
+// H_{k+1/2} of component c at the midpoint of item k (slot hs, its state at
+// slot qs) from the records in LDS; with another split of the leading
+// midpoint flux, plus that split's difference D at the same midpoint.
 template <int SC, int DIR, int NA, int NB, bool OPT>
-WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB, OPT>& L, int tb, int o0, int i, double lam, double ah,
-                           bool alt, double R[4]) {
-  using R_ = Range<SC>;
-  using LT = SweepLds<SC, DIR, NA, NB, OPT>;
-  // one base slot per array at node i; the stencil's nodes are then constant
-  // offsets from it (stride 1 along a xi line, NB across eta lines)
+WIU_DEV double tile_hsum(const SweepLds<SC, DIR, NA, NB, OPT>& L, int c, int hs, int qs, int k, double lam,
+                         double ah, bool alt) {
+  // stencil nodes at constant offsets from the item (stride 1 along a xi
+  // line, NB across eta lines)
   constexpr int S = DIR == 0 ? 1 : NB;
-  const int hs = LT::si(tb, i - (o0 + R_::LO));
-  const int qs = LT::qi(tb, i - (o0 + R_::LO) + R_::QL);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    asm volatile("" ::: "memory");  // one component at a time (register pressure)
-    const double* e = &L.sh[c][hs];
-    const double* q = &L.sq[c][qs];
-    const double* gp = &L.sh[4 + c][hs];
-    const double* gm = &L.sh[8 + c][hs];
-    auto fp = [&](int kk) { return 0.5 * (e[(kk - i) * S] + lam * q[(kk - i) * S]); };
-    auto fm = [&](int kk) { return 0.5 * (e[(kk - i) * S] - lam * q[(kk - i) * S]); };
-    auto Fp = [&](int kk) { return gp[(kk - i) * S]; };
-    auto Fm = [&](int kk) { return gm[(kk - i) * S]; };
-    R[c] = hflux<SC>(i, ah, fp, fm, Fp, Fm) - hflux<SC>(i - 1, ah, fp, fm, Fp, Fm);
-    if constexpr (OPT) {
-      const double* dd = &L.sh[12 + c][hs];
-      if (alt) R[c] += dd[0] - dd[-S];
-    }
+  const double* e = &L.sh[c][hs];
+  const double* q = &L.sq[c][qs];
+  const double* gp = &L.sh[4 + c][hs];
+  const double* gm = &L.sh[8 + c][hs];
+  double H;
+  if constexpr (SC == 3) {
+    H = hsum52(lam, [&](int m) { return e[m * S]; }, [&](int m) { return q[m * S]; },
+               [&](int m) { return gp[m * S]; }, [&](int m) { return gm[m * S]; });
+  } else {
+    auto fp = [&](int kk) { return 0.5 * (e[(kk - k) * S] + lam * q[(kk - k) * S]); };
+    auto fm = [&](int kk) { return 0.5 * (e[(kk - k) * S] - lam * q[(kk - k) * S]); };
+    auto Fp = [&](int kk) { return gp[(kk - k) * S]; };
+    auto Fm = [&](int kk) { return gm[(kk - k) * S]; };
+    H = hflux<SC>(k, ah, fp, fm, Fp, Fm);
   }
+  if constexpr (OPT) {
+    if (alt) H += L.sh[12 + c][hs];
+  }
+  return H;
+}
+
+// H_{i+1/2} - H_{i-1/2} at output node i of line tb, once the items' H have
+// replaced their nodal fluxes in LDS (sweep_tile): each midpoint's H is formed
+// once and read by both of its nodes, so the differences telescope exactly.
+template <int SC, int DIR, int NA, int NB, bool OPT>
+WIU_DEV void tile_residual(const SweepLds<SC, DIR, NA, NB, OPT>& L, int tb, int o0, int i, double R[4]) {
+  constexpr int S = DIR == 0 ? 1 : NB;
+  const int hs = SweepLds<SC, DIR, NA, NB, OPT>::si(tb, i - (o0 + Range<SC>::LO));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) R[c] = L.sh[c][hs] - L.sh[c][hs - S];
 }
 
 // Epilogue operands of one output node, loaded before the tile's last
@@ -141,14 +152,14 @@ struct OutOperands {
 // separate pass, so the maxima are bit-identical to it.
 template <int SC, int NA, int NB, bool OPT>
 WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB, OPT>& L, bool act, int line, int i, int o0,
-                             int tb, double lam, double ah, bool alt, const OutOperands& op) {
+                             int tb, const OutOperands& op) {
   static_assert(64 % NB == 0 && (NA * NB) % 64 == 0, "eta tile must pack whole waves");
   const Dims& d = s.d;
   double sx = 0.0, se = 0.0;
   bool bad = false;
   if (act) {
     double R[4];
-    tile_residual<SC, 1, NA, NB, OPT>(L, tb, o0, i, lam, ah, alt, R);
+    tile_residual<SC, 1, NA, NB, OPT>(L, tb, o0, i, R);
     const long long o = (long long)i * d.nx + line;
     const double rj = -rcp(op.jinv);
     const double dt = s.dt[0];
@@ -177,7 +188,7 @@ WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB, OPT>& L
 
 // One tile of a sweep: logical tile (bxl, byl) = (segment along the line,
 // group of lines) for xi, (group of lines, segment) for eta.  Every thread of
-// the block calls it with the same tile; it contains three block-wide
+// the block calls it with the same tile; it contains five block-wide
 // barriers on every path that reaches the output phase, and none after.
 // OPT: compiled with the scheme options (interpolation variables s.vars and
 // the free parameter s.ah); without it the tile runs the paper's
@@ -362,15 +373,33 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   }
   __syncthreads();
 
+  // H_{k+1/2} once per item, for the midpoints k + 1/2 of k in [o0 - 1,
+  // o0 + out), into the item's nodal-flux slots once every record is read
+  {
+    const bool hact = live && k >= o0 - 1 && k < o0 + out;
+    double Hk[4];
+    if (hact) {
+      const int qs = LT::qi(tb, ta + QL);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Hk[c] = tile_hsum<SC, DIR, NA, NB, OPT>(L, c, slot, qs, k, lam, ah, alt);
+    }
+    __syncthreads();
+    if (hact) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sh[c][slot] = Hk[c];
+    }
+    __syncthreads();
+  }
+
   if constexpr (DIR == 1) {
     if (fused) {  // whole waves take part in the reductions
-      fused_stage_out<SC, NA, NB, OPT>(s, L, act, line, i, o0, tb, lam, ah, alt, op);
+      fused_stage_out<SC, NA, NB, OPT>(s, L, act, line, i, o0, tb, op);
       return;
     }
   }
   if (!act) return;  // no barrier follows
   double R[4];
-  tile_residual<SC, DIR, NA, NB, OPT>(L, tb, o0, i, lam, ah, alt, R);
+  tile_residual<SC, DIR, NA, NB, OPT>(L, tb, o0, i, R);
   if (s.mode == 0) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) s.Rxi[c * d.np + o] = R[c];

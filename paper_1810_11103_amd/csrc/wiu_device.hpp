@@ -92,6 +92,14 @@ WIU_DEV double rcp(double x) {
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
 }
+// One Newton step only (about 2e-15 relative): for the normalisations of
+// the WENO weights, where the error scales the interpolated deviation from
+// the reference state and nothing else (that deviation is exactly zero for a
+// uniform state, so free-stream preservation is untouched).
+WIU_DEV double rcp_w(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
 WIU_DEV double rsqrt_(double x) {
   double y = __builtin_amdgcn_rsq(x);
   double h = 0.5 * y;
@@ -225,22 +233,22 @@ WIU_DEV double weno5(double a, double b, double d, double e, double eps, int ppm
   if constexpr (ZOK) {
     if (ppm == 2) {
       // tau = |IS_0 - IS_2|; q_k = tau / (eps + IS_k) from one reciprocal
-      const double P01 = D0 * D1, R = rcp(P01 * D2), tau = fabs(D0 - D2);
+      const double P01 = D0 * D1, R = rcp_w(P01 * D2), tau = fabs(D0 - D2);
       const double q0 = tau * (D1 * D2 * R), q1 = tau * (D0 * D2 * R), q2 = tau * (P01 * R);
       const double a0 = fma(q0, q0, 1.0), a1 = 10.0 * fma(q1, q1, 1.0), a2 = 5.0 * fma(q2, q2, 1.0);
-      return (a0 * p0 + a1 * p1 + a2 * p2) * rcp(a0 + a1 + a2);
+      return (a0 * p0 + a1 * p1 + a2 * p2) * rcp_w(a0 + a1 + a2);
     }
   }
   D0 *= D0; D1 *= D1; D2 *= D2;
   const double a0 = D1 * D2, a1 = 10.0 * (D0 * D2), a2 = 5.0 * (D0 * D1);
-  const double r = rcp(a0 + a1 + a2);
+  const double r = rcp_w(a0 + a1 + a2);
   double w0 = a0 * r, w1 = a1 * r, w2 = a2 * r;
   if (ppm) {
     w0 = map3(w0, 0.0625, WIU_M3L0, WIU_M3H0);
     w1 = map3(w1, 0.625, WIU_M3L1, WIU_M3H1);
     w2 = map3(w2, 0.3125, WIU_M3L2, WIU_M3H2);
   }
-  return (w0 * p0 + w1 * p1 + w2 * p2) * rcp(w0 + w1 + w2);
+  return (w0 * p0 + w1 * p1 + w2 * p2) * rcp_w(w0 + w1 + w2);
 }
 
 // r = 2: left-biased value at k+1/2 from v_{k-2}, v_{k-1}, v_k = 0, v_{k+1}
@@ -258,21 +266,21 @@ WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
   double D1 = fma(13.0 / 12.0, t1 * t1, fma(u1, u1, eps));
   if constexpr (ZOK) {
     if (ppm == 2) {  // WENO-Z, tau = |IS_0 - IS_1|
-      const double R = rcp(D0 * D1), tau = fabs(D0 - D1);
+      const double R = rcp_w(D0 * D1), tau = fabs(D0 - D1);
       const double q0 = tau * (D1 * R), q1 = tau * (D0 * R);
       const double a0 = fma(q0, q0, 1.0), a1 = 3.0 * fma(q1, q1, 1.0);
-      return (a0 * p0 + a1 * p1) * rcp(a0 + a1);
+      return (a0 * p0 + a1 * p1) * rcp_w(a0 + a1);
     }
   }
   D0 *= D0; D1 *= D1;
   const double a0 = D1, a1 = 3.0 * D0;
-  const double r = rcp(a0 + a1);
+  const double r = rcp_w(a0 + a1);
   double w0 = a0 * r, w1 = a1 * r;
   if (ppm) {
     w0 = map2(w0, 0.25, WIU_M2L0, WIU_M2H0);
     w1 = map2(w1, 0.75, WIU_M2L1, WIU_M2H1);
   }
-  return (w0 * p0 + w1 * p1) * rcp(w0 + w1);
+  return (w0 * p0 + w1 * p1) * rcp_w(w0 + w1);
 }
 
 // Fourth-order mapping of the Appendix, g = C (1 - (w/C - 1)^4) below C and
@@ -320,19 +328,19 @@ WIU_DEV double weno7(double a, double b, double c, double e, double f, double g,
                  (3.0 * (e - f) + g) * (1.0 / 6.0));
   if constexpr (ZOK) {
     if (ppm == 2) {  // WENO-Z, tau = |IS_0 + 3 IS_1 - 3 IS_2 - IS_3|
-      const double P01 = D0 * D1, P23 = D2 * D3, R = rcp(P01 * P23);
+      const double P01 = D0 * D1, P23 = D2 * D3, R = rcp_w(P01 * P23);
       const double tau = fabs(fma(3.0, D1 - D2, D0 - D3));
       const double q0 = tau * (D1 * P23 * R), q1 = tau * (D0 * P23 * R);
       const double q2 = tau * (D3 * P01 * R), q3 = tau * (D2 * P01 * R);
       const double a0 = fma(q0, q0, 1.0), a1 = 21.0 * fma(q1, q1, 1.0);
       const double a2 = 35.0 * fma(q2, q2, 1.0), a3 = 7.0 * fma(q3, q3, 1.0);
-      return (a0 * p0 + a1 * p1 + a2 * p2 + a3 * p3) * rcp((a0 + a1) + (a2 + a3));
+      return (a0 * p0 + a1 * p1 + a2 * p2 + a3 * p3) * rcp_w((a0 + a1) + (a2 + a3));
     }
   }
   D0 *= D0; D1 *= D1; D2 *= D2; D3 *= D3;
   const double P01 = D0 * D1, P23 = D2 * D3;
   const double a0 = (D1 * P23), a1 = 21.0 * (D0 * P23), a2 = 35.0 * (D3 * P01), a3 = 7.0 * (D2 * P01);
-  const double r = rcp((a0 + a1) + (a2 + a3));
+  const double r = rcp_w((a0 + a1) + (a2 + a3));
   double w0 = a0 * r, w1 = a1 * r, w2 = a2 * r, w3 = a3 * r;
   if (ppm) {
     w0 = map4(w0, 1.0 / 64.0, WIU_M4L0, WIU_M4H0);
@@ -340,7 +348,7 @@ WIU_DEV double weno7(double a, double b, double c, double e, double f, double g,
     w2 = map4(w2, 35.0 / 64.0, WIU_M4L2, WIU_M4H2);
     w3 = map4(w3, 7.0 / 64.0, WIU_M4L3, WIU_M4H3);
   }
-  return (w0 * p0 + w1 * p1 + w2 * p2 + w3 * p3) * rcp((w0 + w1) + (w2 + w3));
+  return (w0 * p0 + w1 * p1 + w2 * p2 + w3 * p3) * rcp_w((w0 + w1) + (w2 + w3));
 }
 
 // Steger-Warming (split 1) or van Leer (split 2) split of a midpoint flux at

@@ -661,6 +661,26 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
       for (int c = 0; c < 5; ++c) L.sh[LT::NREC - 5 + c][slot] = D[c];
     }
   }
+  // epilogue operands of this lane's output node, issued before the
+  // barriers so that their latency overlaps them and the flux difference
+  const bool act = live && ta < out;
+  const int i = o0 + ta;
+  double xr[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, x0[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, jv = 1.0;
+  long long t = 0;
+  if (act) {
+    int p[3];
+    node(i, la, p);
+    t = u3idx(d, p[0], p[1], p[2]);
+    if (mode != 0) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) xr[c] = a.Racc[c * d.np + t];
+    }
+    if (mode >= 2) jv = a.M[9 * d.mplane + m3idx(d, p[0], p[1], p[2])];
+    if (mode == 3 && a.ca != 0.0) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) x0[c] = a.U0[c * d.np + t];
+    }
+  }
   __syncthreads();
   constexpr int S = DIR == 0 ? 1 : NB;
   // H_{k+1/2} once per item, for the midpoints k + 1/2 of k in [o0 - 1,
@@ -699,33 +719,33 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
     }
     __syncthreads();
   }
-  if (!live || ta >= out) return;
-  const int i = o0 + ta;
+  if (!act) return;
   const int hs = LT::si(tb, i - (o0 + R_::LO));
   double Rv[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) Rv[c] = L.sh[c][hs] - L.sh[c][hs - S];
-  int p[3];
-  node(i, la, p);
-  const long long t = u3idx(d, p[0], p[1], p[2]);
   if (mode == 0) {
     for (int c = 0; c < 5; ++c) a.Racc[c * d.np + t] = Rv[c];
     return;
   }
   if (mode == 1) {
-    for (int c = 0; c < 5; ++c) a.Racc[c * d.np + t] += Rv[c];
+    for (int c = 0; c < 5; ++c) a.Racc[c * d.np + t] = xr[c] + Rv[c];
     return;
   }
-  const double rj = -rcp(a.M[9 * d.mplane + m3idx(d, p[0], p[1], p[2])]);
+  const double rj = -rcp(jv);
   if (mode == 2) {
-    for (int c = 0; c < 5; ++c) a.out[c * d.np + t] = (a.Racc[c * d.np + t] + Rv[c]) * rj;
+    for (int c = 0; c < 5; ++c) a.out[c * d.np + t] = (xr[c] + Rv[c]) * rj;
     return;
   }
+  // the stage state at the output node is the staged tile entry (an interior
+  // node, untouched by the side rules); U0 is not read when its coefficient
+  // is zero (first stage)
   const double dt = a.dt[0];
+  const int pq = LT::qi(tb, ta - R_::LO + QL);
   for (int c = 0; c < 5; ++c) {
-    const double Lv = (a.Racc[c * d.np + t] + Rv[c]) * rj;
-    const double us = a.U[c * d.np + t] + dt * Lv;
-    a.out[c * d.np + t] = a.ca == 0.0 ? a.cb * us : a.ca * a.U0[c * d.np + t] + a.cb * us;
+    const double Lv = (xr[c] + Rv[c]) * rj;
+    const double us = L.sq[c][pq] + dt * Lv;
+    a.out[c * d.np + t] = a.ca == 0.0 ? a.cb * us : a.ca * x0[c] + a.cb * us;
   }
 }
 

@@ -316,6 +316,8 @@ int wiu_batched_get_dt(const wiu_plan* plan, double* dt_host, wiu_stream_t strea
  * of the step (captured on first use, bound to the plan's pointers). */
 int wiu_batched_rk3_step(wiu_plan* plan, int use_graph, wiu_stream_t stream);
 int wiu_batched_status(wiu_plan* plan, wiu_stream_t stream, int* status, int clear);
+/* Waits for the device, then frees the plan (also when the wait fails, which
+ * returns WIU_EHIP). */
 int wiu_plan_destroy(wiu_plan* plan);
 
 /* ---- Three-dimensional grids ----------------------------------------------

@@ -22,15 +22,24 @@ std::vector<ProfRec> g_prof;
 struct ProfScope {
   int id; hipStream_t st; hipEvent_t a = nullptr, b = nullptr; bool on;
   ProfScope(int id_, hipStream_t st_) : id(id_), st(st_) {
-    on = g_prof_on;
-    if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) hipEventRecord(a, st);
-    else on = false;
+    on = g_prof_on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
+         hipEventRecord(a, st) == hipSuccess;
+    if (!on) drop();
   }
   ~ProfScope() {
     if (!on) return;
-    hipEventRecord(b, st);
+    if (hipEventRecord(b, st) != hipSuccess) {
+      drop();
+      return;
+    }
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof.push_back({id, a, b});
+  }
+  // a scope that cannot be timed keeps no events
+  void drop() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    a = b = nullptr;
   }
 };
 
@@ -501,8 +510,8 @@ int wiu_profile_read(int id, long long* count, double* mean_ms) {
     if (r.id != id) { keep.push_back(r); continue; }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) { tot += ms; ++n; }
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
   g_prof.swap(keep);
   *count = n;

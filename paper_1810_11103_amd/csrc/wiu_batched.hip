@@ -127,12 +127,13 @@ bool line_groups(const wiu_block* blocks, int n, const std::vector<size_t>& off_
 
 void free_plan(wiu_plan* p) {
   if (!p) return;
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
-  if (p->d_blocks) hipFree(p->d_blocks);
-  if (p->d_tiles) hipFree(p->d_tiles);
-  if (p->d_ws) hipFree(p->d_ws);
-  if (p->d_gstart) hipFree(p->d_gstart);
+  // teardown: nothing useful can be done with a failure here
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->d_blocks) (void)hipFree(p->d_blocks);
+  if (p->d_tiles) (void)hipFree(p->d_tiles);
+  if (p->d_ws) (void)hipFree(p->d_ws);
+  if (p->d_gstart) (void)hipFree(p->d_gstart);
   delete p;
 }
 
@@ -363,10 +364,10 @@ int wiu_batched_rk3_step(wiu_plan* p, int use_graph, wiu_stream_t stream) {
         p->graph = g;
         if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) rc = WIU_EHIP;
       } else if (g) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
       }
     }
-    hipStreamDestroy(cap);
+    if (hipStreamDestroy(cap) != hipSuccess) rc = WIU_EHIP;
     if (rc != WIU_OK) return rc;
   }
   return hipGraphLaunch(p->exec, st) == hipSuccess ? WIU_OK : WIU_EHIP;
@@ -379,9 +380,11 @@ int wiu_batched_status(wiu_plan* p, wiu_stream_t stream, int* status, int clear)
 
 int wiu_plan_destroy(wiu_plan* p) {
   if (!p) return WIU_EINVAL;
-  hipDeviceSynchronize();
+  // work queued on the plan's buffers ends before they are freed; a failed
+  // wait is reported, the plan is freed either way
+  const bool ok = hipDeviceSynchronize() == hipSuccess;
   free_plan(p);
-  return WIU_OK;
+  return ok ? WIU_OK : WIU_EHIP;
 }
 
 }  // extern "C"

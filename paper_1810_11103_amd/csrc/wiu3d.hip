@@ -892,8 +892,8 @@ void sides3(const wiu_grid3* g, S3Args& a) {
 
 dim3 lin_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
 
-// Tile shapes: xi 128 items x 2 lines (lanes along the line), eta and zeta
-// 32 items x 8 lines (lanes across the lines, along i).
+// Tile shapes: xi 64 items x 4 lines (lanes along the line, one line per
+// wave), eta and zeta 32 items x 8 lines (lanes across the lines, along i).
 template <int SC, int DIR, int NA, int NB, bool OPT>
 hipError_t launch_sweep3_t(const S3Args& a, int mode, hipStream_t st) {
   constexpr int OUT = NA - Range<SC>::EXTRA;
@@ -910,7 +910,7 @@ hipError_t launch_sweep3_t(const S3Args& a, int mode, hipStream_t st) {
 
 template <int SC, bool OPT>
 hipError_t launch_pass3_o(const S3Args& a, int D, int mode, hipStream_t st) {
-  if (D == 0) return launch_sweep3_t<SC, 0, 128, 2, OPT>(a, mode, st);
+  if (D == 0) return launch_sweep3_t<SC, 0, 64, 4, OPT>(a, mode, st);
   if (D == 1) return launch_sweep3_t<SC, 1, 32, 8, OPT>(a, mode, st);
   return launch_sweep3_t<SC, 2, 32, 8, OPT>(a, mode, st);
 }

@@ -461,6 +461,7 @@ struct S3Args {
   const double* U;                 // state the fluxes are built from
   const double* M;
   const unsigned long long* lam;   // line maxima: xi lines [ny nz], eta [nx nz], zeta [nx ny]
+  unsigned long long* nlam;        // zeta pass of an RK stage: the next stage's maxima (or null)
   double gamma, alpha, eps;
   int ppm;
   int vars;                        // WIU_VARS_* (interpolation variables)
@@ -681,6 +682,18 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
       for (int c = 0; c < 5; ++c) x0[c] = a.U0[c * d.np + t];
     }
   }
+  // nodal metrics of all three directions, for the next stage's maxima
+  double km[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) km[c] = 0.0;
+  const bool fused = DIR == 2 && mode == 3 && a.nlam != nullptr;  // uniform over the grid
+  if (fused && act) {
+    int p[3];
+    node(i, la, p);
+    const long long mo = m3idx(d, p[0], p[1], p[2]);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) km[c] = a.M[c * d.mplane + mo];
+  }
   __syncthreads();
   constexpr int S = DIR == 0 ? 1 : NB;
   // H_{k+1/2} once per item, for the midpoints k + 1/2 of k in [o0 - 1,
@@ -718,6 +731,59 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
       for (int c = 0; c < 5; ++c) L.sh[c][slot] = Hk[c];
     }
     __syncthreads();
+  }
+  if constexpr (DIR == 2) {
+    if (fused) {
+      // RK stage with the next stage's line maxima (Sec. 2.3), every lane
+      // taking part in the reductions: lanes of a wave are NB lines along i
+      // (fast) by 64/NB positions along k.  Wave speeds as in the separate
+      // maxima pass (same routine, clamped at zero), so the maxima are
+      // bit-identical to it.
+      static_assert(64 % NB == 0 && (NA * NB) % 64 == 0, "zeta tile must pack whole waves");
+      double sx = 0.0, se = 0.0, sz = 0.0;
+      bool bad = false;
+      if (act) {
+        const int hs = LT::si(tb, i - (o0 + R_::LO));
+        const double rj = -rcp(jv);
+        const double dt = a.dt[0];
+        const int pq = LT::qi(tb, ta - R_::LO + QL);
+        double Qn[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          const double Lv = (xr[c] + (L.sh[c][hs] - L.sh[c][hs - S])) * rj;
+          const double us = L.sq[c][pq] + dt * Lv;
+          Qn[c] = a.ca == 0.0 ? a.cb * us : a.ca * x0[c] + a.cb * us;
+          a.out[c * d.np + t] = Qn[c];
+        }
+        double sp[3];
+#pragma unroll
+        for (int D = 0; D < 3; ++D) {
+          const double kk[3] = {km[3 * D], km[3 * D + 1], km[3 * D + 2]};
+          bool b;
+          sp[D] = speed3(Qn, kk, a.gamma, b);
+          bad |= b;
+        }
+        sx = fmax(0.0, sp[0]);
+        se = fmax(0.0, sp[1]);
+        sz = fmax(0.0, sp[2]);
+      }
+      if (bad) atomicOr(a.status, ST_NONPHYS);
+      const int j = cb;
+      unsigned long long* lx = a.nlam;
+      unsigned long long* le = lx + (long long)d.n[1] * d.n[2];
+      unsigned long long* lz = le + (long long)d.n[0] * d.n[2];
+      // eta lines (i, k): one node of the tile each
+      if (act) atomicMax(&le[(long long)i * d.n[0] + la], (unsigned long long)__double_as_longlong(se));
+      // xi lines (j, k): reduce over the lines of the wave (along i)
+      for (int off = 1; off < NB; off <<= 1) sx = fmax(sx, __shfl_xor(sx, off, 64));
+      if (tb == 0 && live && ta < out)
+        atomicMax(&lx[(long long)i * d.n[1] + j], (unsigned long long)__double_as_longlong(sx));
+      // zeta lines (i, j): reduce over the positions of the wave (along k)
+      for (int off = NB; off < 64; off <<= 1) sz = fmax(sz, __shfl_xor(sz, off, 64));
+      const int lane = (threadIdx.x + NB * threadIdx.y) & 63;
+      if (lane < NB && live) atomicMax(&lz[(long long)j * d.n[0] + la], (unsigned long long)__double_as_longlong(sz));
+      return;
+    }
   }
   if (!act) return;
   const int hs = LT::si(tb, i - (o0 + R_::LO));
@@ -843,7 +909,7 @@ Dims3 dims3(const wiu_grid3* g) {
 // either the metric scratch (inner derivatives, nodal band) or the stepping
 // buffers (Racc, U1, U2).
 struct Ws3 {
-  size_t lam, dt, big, metric_dx, metric_t, racc, u1, u2, total;
+  size_t lam, lam2, dt, big, metric_dx, metric_t, racc, u1, u2, total;
   long long nlam;
 };
 
@@ -852,7 +918,8 @@ Ws3 ws3(const wiu_grid3* g) {
   Ws3 w;
   w.nlam = (long long)g->ny * g->nz + (long long)g->nx * g->nz + (long long)g->nx * g->ny + 1;
   w.lam = A3;
-  w.dt = w.lam + al3(w.nlam * 8);
+  w.lam2 = w.lam + al3(w.nlam * 8);  // the next RK stage's maxima
+  w.dt = w.lam2 + al3(w.nlam * 8);
   w.big = w.dt + A3;
   const int B = GHOST + METRIC_REACH, E = B + 8;  // the widest band (Eq. 2.6)
   const size_t dxb = al3(9 * (size_t)(g->nx + 2 * E) * (g->ny + 2 * E) * (g->nz + 2 * E) * 8);
@@ -989,6 +1056,7 @@ int wiu3_rhs(const wiu_grid3* g, int scheme, const wiu_params* p, const double* 
   const Ws3 w = ws3(g);
   char* base = (char*)ws;
   S3Args a;
+  a.nlam = nullptr;
   a.d = d; a.U = U; a.M = M; a.lam = (unsigned long long*)(base + w.lam);
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
   a.Racc = (double*)(base + w.racc); a.out = dUdt;
@@ -1023,6 +1091,7 @@ int wiu3_rk3_step(const wiu_grid3* g, int scheme, const wiu_params* p, double* U
   double* U1 = (double*)(base + w.u1);
   double* U2 = (double*)(base + w.u2);
   S3Args a;
+  a.nlam = nullptr;
   a.d = d; a.M = M; a.lam = (unsigned long long*)(base + w.lam);
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
   a.Racc = (double*)(base + w.racc);
@@ -1033,12 +1102,19 @@ int wiu3_rk3_step(const wiu_grid3* g, int scheme, const wiu_params* p, double* U
   const double* src[3] = {U, U1, U2};
   double* dst[3] = {U1, U2, U};
   const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  // the first stage's maxima from a separate pass; the zeta pass of stages 1
+  // and 2 accumulates the next stage's into the other buffer
+  unsigned long long* lbuf[2] = {(unsigned long long*)(base + w.lam), (unsigned long long*)(base + w.lam2)};
+  if (maxima3(d, U, M, p->gamma, lbuf[0], w.nlam, a.status, st) != hipSuccess) return WIU_EHIP;
   for (int s = 0; s < 3; ++s) {
     a.U = src[s]; a.out = dst[s]; a.ca = ca[s]; a.cb = cb[s];
-    if (maxima3(d, a.U, M, p->gamma, (unsigned long long*)a.lam, w.nlam, a.status, st) != hipSuccess)
-      return WIU_EHIP;
-    for (int D = 0; D < 3; ++D)
+    a.lam = lbuf[s & 1];
+    unsigned long long* next = s < 2 ? lbuf[(s + 1) & 1] : nullptr;
+    if (next && launch_fill_u64(next, w.nlam, st) != hipSuccess) return WIU_EHIP;
+    for (int D = 0; D < 3; ++D) {
+      a.nlam = D == 2 ? next : nullptr;
       if (pass3(scheme, a, D, D == 0 ? 0 : (D == 1 ? 1 : 3), st) != hipSuccess) return WIU_EHIP;
+    }
   }
   return WIU_OK;
 }

@@ -180,8 +180,7 @@ def three_d_leg(n=256, steps=8, cfl=0.5, scheme="5-2MP"):
     del U0
 
     def step():
-        sol.cfl_dt(U, cfl)
-        sol.rk3_step(U)
+        sol.rk3_step_cfl(U, cfl)
 
     for _ in range(2):
         step()

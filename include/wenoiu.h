@@ -374,6 +374,12 @@ int wiu3_cfl_dt(const wiu_grid3* g, const wiu_params* p, const double* U, const 
 /* One TVD-RK3 step of U in place with the device scalar time step dt (Sec. 6). */
 int wiu3_rk3_step(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, const double* dt,
                   void* ws, wiu_stream_t stream);
+/* wiu3_cfl_dt followed by wiu3_rk3_step, sharing one pass over U for the
+ * CFL maximum and the first stage's line maxima: *dt (device scalar)
+ * receives the CFL time step of U, then U advances by it.  Same results as
+ * the two calls.  WIU_EINVAL unless cfl > 0. */
+int wiu3_rk3_step_cfl(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
+                      double* dt, void* ws, wiu_stream_t stream);
 
 /* Tile shapes of the two sweep kernels (dir 0 = xi, 1 = eta).  Several
  * shapes are compiled; the choice is process-wide and affects speed only,

@@ -1015,6 +1015,49 @@ int rc3(hipError_t e) { return e == hipSuccess ? WIU_OK : WIU_EHIP; }
 
 }  // namespace
 
+// One TVD-RK3 step; with cfl > 0 the first stage's maxima pass also yields
+// the CFL time step, written to *dt before the stages read it (dt is then
+// written, otherwise only read).
+static int rk3_3d(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl, double* dt,
+           void* ws, wiu_stream_t stream) {
+  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !params3_ok(p, scheme) || !U || !M || !dt || !ws) return WIU_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const Dims3 d = dims3(g);
+  const Ws3 w = ws3(g);
+  char* base = (char*)ws;
+  double* U1 = (double*)(base + w.u1);
+  double* U2 = (double*)(base + w.u2);
+  S3Args a;
+  a.nlam = nullptr;
+  a.d = d; a.M = M; a.lam = (unsigned long long*)(base + w.lam);
+  a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
+  a.Racc = (double*)(base + w.racc);
+  a.U0 = U; a.dt = dt; a.status = (int*)base;
+  sides3(g, a);
+  options3(p, a);
+  // U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U = 1/3 U + 2/3 (U2 + dt L(U2))
+  const double* src[3] = {U, U1, U2};
+  double* dst[3] = {U1, U2, U};
+  const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  // the first stage's maxima from a separate pass; the zeta pass of stages 1
+  // and 2 accumulates the next stage's into the other buffer
+  unsigned long long* lbuf[2] = {(unsigned long long*)(base + w.lam), (unsigned long long*)(base + w.lam2)};
+  if (maxima3(d, U, M, p->gamma, lbuf[0], w.nlam, a.status, st) != hipSuccess) return WIU_EHIP;
+  if (cfl > 0.0 && launch_cfl_dt(lbuf[0] + w.nlam - 1, cfl, dt, st) != hipSuccess) return WIU_EHIP;
+  for (int s = 0; s < 3; ++s) {
+    a.U = src[s]; a.out = dst[s]; a.ca = ca[s]; a.cb = cb[s];
+    a.lam = lbuf[s & 1];
+    unsigned long long* next = s < 2 ? lbuf[(s + 1) & 1] : nullptr;
+    if (next && launch_fill_u64(next, w.nlam, st) != hipSuccess) return WIU_EHIP;
+    for (int D = 0; D < 3; ++D) {
+      a.nlam = D == 2 ? next : nullptr;
+      if (pass3(scheme, a, D, D == 0 ? 0 : (D == 1 ? 1 : 3), st) != hipSuccess) return WIU_EHIP;
+    }
+  }
+  return WIU_OK;
+}
+
+
 extern "C" {
 
 size_t wiu3_metrics_size(const wiu_grid3* g) {
@@ -1083,40 +1126,13 @@ int wiu3_cfl_dt(const wiu_grid3* g, const wiu_params* p, const double* U, const 
 
 int wiu3_rk3_step(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, const double* dt,
                   void* ws, wiu_stream_t stream) {
-  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !params3_ok(p, scheme) || !U || !M || !dt || !ws) return WIU_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
-  const Dims3 d = dims3(g);
-  const Ws3 w = ws3(g);
-  char* base = (char*)ws;
-  double* U1 = (double*)(base + w.u1);
-  double* U2 = (double*)(base + w.u2);
-  S3Args a;
-  a.nlam = nullptr;
-  a.d = d; a.M = M; a.lam = (unsigned long long*)(base + w.lam);
-  a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
-  a.Racc = (double*)(base + w.racc);
-  a.U0 = U; a.dt = dt; a.status = (int*)base;
-  sides3(g, a);
-  options3(p, a);
-  // U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U = 1/3 U + 2/3 (U2 + dt L(U2))
-  const double* src[3] = {U, U1, U2};
-  double* dst[3] = {U1, U2, U};
-  const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0};
-  // the first stage's maxima from a separate pass; the zeta pass of stages 1
-  // and 2 accumulates the next stage's into the other buffer
-  unsigned long long* lbuf[2] = {(unsigned long long*)(base + w.lam), (unsigned long long*)(base + w.lam2)};
-  if (maxima3(d, U, M, p->gamma, lbuf[0], w.nlam, a.status, st) != hipSuccess) return WIU_EHIP;
-  for (int s = 0; s < 3; ++s) {
-    a.U = src[s]; a.out = dst[s]; a.ca = ca[s]; a.cb = cb[s];
-    a.lam = lbuf[s & 1];
-    unsigned long long* next = s < 2 ? lbuf[(s + 1) & 1] : nullptr;
-    if (next && launch_fill_u64(next, w.nlam, st) != hipSuccess) return WIU_EHIP;
-    for (int D = 0; D < 3; ++D) {
-      a.nlam = D == 2 ? next : nullptr;
-      if (pass3(scheme, a, D, D == 0 ? 0 : (D == 1 ? 1 : 3), st) != hipSuccess) return WIU_EHIP;
-    }
-  }
-  return WIU_OK;
+  return rk3_3d(g, scheme, p, U, M, 0.0, const_cast<double*>(dt), ws, stream);
+}
+
+int wiu3_rk3_step_cfl(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
+                      double* dt, void* ws, wiu_stream_t stream) {
+  if (!(cfl > 0.0)) return WIU_EINVAL;
+  return rk3_3d(g, scheme, p, U, M, cfl, dt, ws, stream);
 }
 
 }  // extern "C"

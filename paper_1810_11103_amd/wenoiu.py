@@ -26,7 +26,7 @@ EXPORTS = [
     "wiu_batched_plan", "wiu_batched_info", "wiu_batched_set_dt", "wiu_batched_cfl_dt", "wiu_batched_get_dt",
     "wiu_batched_rk3_step", "wiu_batched_status", "wiu_plan_destroy", "wiu_blocks_metrics_work_size",
     "wiu_blocks_metrics", "wiu3_metrics_size", "wiu3_workspace_bytes", "wiu3_metrics", "wiu3_rhs", "wiu3_cfl_dt",
-    "wiu3_rk3_step",
+    "wiu3_rk3_step", "wiu3_rk3_step_cfl",
     "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl", "wiu_step_record_bytes",
 ]
 KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3, "sweep3": 4}
@@ -88,6 +88,7 @@ def _load():
         "wiu3_rhs": (I, [ctypes.POINTER(WiuGrid3), I, PR, P, P, P, P, P]),
         "wiu3_cfl_dt": (I, [ctypes.POINTER(WiuGrid3), PR, P, P, ctypes.c_double, P, P, P]),
         "wiu3_rk3_step": (I, [ctypes.POINTER(WiuGrid3), I, PR, P, P, P, P, P]),
+        "wiu3_rk3_step_cfl": (I, [ctypes.POINTER(WiuGrid3), I, PR, P, P, ctypes.c_double, P, P, P]),
         "wiu_blocks_metrics": (I, [ctypes.POINTER(WiuBlock), I, I, PR, P, P, P, P]),
         "wiu_batched_info": (I, [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "wiu_batched_set_dt": (I, [P, P, P]),
@@ -598,6 +599,14 @@ class Solver3:
             self.dt.fill_(float(dt))
         _check(lib.wiu3_rk3_step(ctypes.byref(self.grid), scheme_id(self.scheme), ctypes.byref(self.params), _ptr(U),
                                  _ptr(self.M), _ptr(self.dt), ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+
+    def rk3_step_cfl(self, U, cfl):
+        """cfl_dt then rk3_step with one shared pass over U; returns the
+        device time step."""
+        _check(lib.wiu3_rk3_step_cfl(ctypes.byref(self.grid), scheme_id(self.scheme), ctypes.byref(self.params),
+                                     _ptr(U), _ptr(self.M), float(cfl), _ptr(self.dt),
+                                     ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+        return self.dt
 
     def status(self, clear=True):
         return status(self.ws, clear)

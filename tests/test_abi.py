@@ -189,3 +189,7 @@ def test_3d_grids_and_options_are_validated(wiu):
                                 None) == wiu.WIU_EINVAL
     P = wiu.make_params()
     assert wiu.lib.wiu3_rhs(ctypes.byref(g), 8, ctypes.byref(P), dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL
+    # the combined CFL step needs a positive CFL number and the step's own checks
+    for cfl, scheme in ((0.0, 3), (-0.5, 3), (float("nan"), 3), (0.5, 8)):
+        assert wiu.lib.wiu3_rk3_step_cfl(ctypes.byref(g), scheme, ctypes.byref(P), dummy, dummy, cfl, dummy, dummy,
+                                         None) == wiu.WIU_EINVAL

@@ -366,3 +366,26 @@ def test_status_flags_3d(wiu):
     x[10, 10, 10] += 3.0 * 10.0 / 24    # node pushed past its neighbours: J^{-1} < 0
     with pytest.raises(wiu.WiuError):
         wiu.Solver3(x, gf.y, gf.z, "5-2MP", gf.bc, gf.period)
+
+
+@pytest.mark.parametrize("kind", ["periodic", "mixed"])
+def test_rk3_step_cfl_equals_cfl_dt_then_step_3d(wiu, kind):
+    """wiu3_rk3_step_cfl shares the first stage's maxima pass with the CFL
+    rule: the same time step and state as wiu3_cfl_dt then wiu3_rk3_step,
+    bit for bit, over two steps (CFL 0.3: the octant state on these rough
+    grids loses positivity at 0.5 in the oracle too)."""
+    import torch
+    say("3-D rk3_step_cfl", kind)
+    g, U = case(kind)
+    a = wiu.Solver3(g.x, g.y, g.z, "5-2MP", g.bc, g.period)
+    b = wiu.Solver3(g.x, g.y, g.z, "5-2MP", g.bc, g.period)
+    Ua, Ub = dev(U), dev(U)
+    for _ in range(2):
+        a.cfl_dt(Ua, 0.3)
+        a.rk3_step(Ua)
+        b.rk3_step_cfl(Ub, 0.3)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(Ua).all())
+        assert torch.equal(a.dt, b.dt)
+        assert torch.equal(Ua, Ub)
+    assert a.status() == 0 and b.status() == 0

@@ -905,9 +905,9 @@ Dims3 dims3(const wiu_grid3* g) {
   return d;
 }
 
-// Workspace: [status | line maxima | dt | big area], the big area holding
-// either the metric scratch (inner derivatives, nodal band) or the stepping
-// buffers (Racc, U1, U2).
+// Workspace: [status | line maxima, two buffers (this and the next RK
+// stage) | dt | big area], the big area holding either the metric scratch
+// (inner derivatives, nodal band) or the stepping buffers (Racc, U1, U2).
 struct Ws3 {
   size_t lam, lam2, dt, big, metric_dx, metric_t, racc, u1, u2, total;
   long long nlam;

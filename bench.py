@@ -32,21 +32,24 @@ sys.path.insert(0, ROOT)
 # (A + B/n) per sweep direction (midpoint fluxes, nodal splits, line wave
 # speeds, H and its difference) plus 8 for the final -(R_xi + R_eta)/J^{-1},
 # counted by instantiating the oracle with an operation-counting scalar (add,
-# sub, mul, div, sqrt = 1 each) on the Riemann workload (oracle/count_flops.py;
-# B includes the oracle's uniform four-node ghost band, under 0.4 % of the
+# sub, mul, div, sqrt = 1 each) on the Riemann workload (oracle/count_flops.py).
+# The count is the method's own work: each side projects the window entries
+# its interpolation reads (five for r = 3, four for r = 2, seven for r = 4),
+# each deviation Q_m - Q_ref is formed once, sums start from their first term
+# (B includes the oracle's uniform four-node ghost band, under 0.4 % of the
 # total at n = 2048).  The RK stage update adds 5 per component.  The
 # one-midpoint forms with alpha != 1 add a few operations per cell that the
 # table leaves out.
 N_DEFAULT = 2048
 FLOP_DIR = {  # (scheme family, interpolation variables) -> (A, B)
-    ("3", "characteristic"): (1392.0, 9355.0), ("3", "conservative"): (672.0, 4321.0),
-    ("3", "primitive"): (822.0, 5374.0),
-    ("5-1MP", "characteristic"): (1728.0, 11475.0), ("5-1MP", "conservative"): (1008.0, 6439.0),
+    ("3", "characteristic"): (1072.0, 7115.0), ("3", "conservative"): (664.0, 4265.0),
+    ("3", "primitive"): (814.0, 5318.0),
+    ("5-1MP", "characteristic"): (1472.0, 9683.0), ("5-1MP", "conservative"): (1008.0, 6439.0),
     ("5-1MP", "primitive"): (1158.0, 7491.0),
-    ("5-2MP", "characteristic"): (1720.0, 11467.0), ("5-2MP", "conservative"): (1000.0, 6431.0),
+    ("5-2MP", "characteristic"): (1464.0, 9675.0), ("5-2MP", "conservative"): (1000.0, 6431.0),
     ("5-2MP", "primitive"): (1150.0, 7483.0),
-    ("7", "characteristic"): (2728.0, 18155.0), ("7", "conservative"): (1832.0, 11907.0),
-    ("7", "primitive"): (2026.0, 13277.0),
+    ("7", "characteristic"): (2440.0, 16139.0), ("7", "conservative"): (1864.0, 12131.0),
+    ("7", "primitive"): (2058.0, 13501.0),
 }
 # 3-D direction pass, per item (oracle/count_flops.py, per_item3; octant
 # Riemann state on a randomized periodic grid): nodal split flux per node
@@ -54,7 +57,7 @@ FLOP_DIR = {  # (scheme family, interpolation variables) -> (A, B)
 # (midpoints -4 .. n+2), and the upwind-biased combination and difference
 # per interior node: the algorithmic work of one sweep launch (the tiles'
 # recomputed halo items are not counted).
-FLOP_ITEM3 = {"3-1MP": (59.0, 1835.5, 61.1), "5-2MP": (59.0, 2205.6, 102.0), "7-2MP": (59.0, 3503.8, 163.2)}
+FLOP_ITEM3 = {"3-1MP": (59.0, 1325.5, 61.1), "5-2MP": (59.0, 1795.6, 102.0), "7-2MP": (59.0, 2993.8, 163.2)}
 FLOP_COMBINE = 8.0
 FLOP_RK_STAGE = 20.0
 PEAK_FP64_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz

@@ -5,9 +5,15 @@ The oracle is instantiated with an operation-counting scalar (add, sub,
 mul, div and sqrt count one each; metric-only work is not counted).  A
 sweep of one direction costs A per cell plus B per grid line (the line's
 wave-speed maximum and the boundary stencils), so on lines of n nodes it is
-A + B / n per cell.  A and B come from two line lengths on a smooth periodic
-state; the count does not depend on the data (no data-dependent branches in
-the counted arithmetic).
+A + B / n per cell.  A and B come from two line lengths on the Riemann
+state; the count depends on the data only through the two branches of each
+weight mapping (a few hundredths of an operation per cell).
+
+What is counted is the method's own work as the oracle performs it: each
+side projects only the window entries its interpolation reads, each
+deviation Q_m - Q_ref is formed once per side, and sums of products start
+from their first term (no additions of zero).  The dense eigenvector
+products still include the structural zeros of L and R.
 
 Usage: python oracle/count_flops.py
 """

@@ -356,23 +356,30 @@ void midpoint_flux3(Scheme sc, const Params& pr, const T Qs[8][5], const double 
   const int m0 = seventh_order(sc) ? 0 : 1, m1 = seventh_order(sc) ? 8 : 7;
   for (int side = 0; side < 2; ++side) {
     const T* Qref = Qs[3 + side];
+    // the entries this side's interpolation reads, each deviation formed once
+    int lo, hi;
+    side_window(sc, side, lo, hi);
     T Qm[5];
     if (pr.vars == 0) {
       T L[5][5], R[5][5];
       eigenvectors3(Qref, pr.gamma, n, L, R);
+      T dQ[8][5];
+      for (int m = lo; m < hi; ++m)
+        for (int q = 0; q < 5; ++q) dQ[m][q] = Qs[m][q] - Qref[q];
       T W[5];
       for (int c = 0; c < 5; ++c) {
         T s[8];
         for (int m = 0; m < 8; ++m) {
           s[m] = T(0.0);
-          if (m < m0 || m >= m1) continue;
-          for (int q = 0; q < 5; ++q) s[m] = s[m] + L[c][q] * (Qs[m][q] - Qref[q]);
+          if (m < lo || m >= hi) continue;
+          s[m] = L[c][0] * dQ[m][0];
+          for (int q = 1; q < 5; ++q) s[m] = s[m] + L[c][q] * dQ[m][q];
         }
         W[c] = side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr);
       }
       for (int q = 0; q < 5; ++q) {
-        Qm[q] = T(0.0);
-        for (int c = 0; c < 5; ++c) Qm[q] = Qm[q] + R[q][c] * W[c];
+        Qm[q] = R[q][0] * W[0];
+        for (int c = 1; c < 5; ++c) Qm[q] = Qm[q] + R[q][c] * W[c];
         Qm[q] = Qref[q] + Qm[q];
       }
     } else {
@@ -396,7 +403,7 @@ void midpoint_flux3(Scheme sc, const Params& pr, const T Qs[8][5], const double 
       T Vm[5];
       for (int c = 0; c < 5; ++c) {
         T s[8];
-        for (int m = 0; m < 8; ++m) s[m] = (m < m0 || m >= m1) ? T(0.0) : V[m][c] - V[3 + side][c];
+        for (int m = 0; m < 8; ++m) s[m] = (m < lo || m >= hi) ? T(0.0) : V[m][c] - V[3 + side][c];
         Vm[c] = V[3 + side][c] + (side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr));
       }
       if (pr.vars == 1) {

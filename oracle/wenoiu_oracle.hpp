@@ -216,6 +216,15 @@ template <class T> T weno_right(Scheme sc, const T s[8], const Params& pr) {
   return weno_left(sc, m, pr);
 }
 
+// Window entries [lo, hi) of Q_{k-3..k+4} that the interpolation of one side
+// reads: k-2..k+2 (r = 3), k-2..k+1 (r = 2), k-3..k+3 (r = 4) for the
+// left-biased side, the mirror images about k+1/2 for the right-biased one.
+inline void side_window(Scheme sc, int side, int& lo, int& hi) {
+  const int r4 = seventh_order(sc), r3 = fifth_order(sc);
+  if (side == 0) { lo = r4 ? 0 : 1; hi = r4 ? 7 : (r3 ? 6 : 5); }
+  else { lo = r4 ? 1 : (r3 ? 2 : 3); hi = r4 ? 8 : 7; }
+}
+
 // ===========================================================================
 // Sec. 3.2 / 3.3: upwind-biased numerical flux h^+_{i+1/2} from nodal values
 // f(m) = f_{i+m} and midpoint values F(m) = f_{i+1/2+m}, with alpha = 1
@@ -680,28 +689,35 @@ void midpoint_flux(Scheme sc, const Params& pr, const T Qs[8][4], double kx0, do
   double nbx = 0.5 * (kx0 + kx1), nby = 0.5 * (ky0 + ky1);
   double nn = std::sqrt(nbx * nbx + nby * nby);
   double nx_ = nbx / nn, ny_ = nby / nn;
-  // window entries the interpolation reads: Q_{k-3..k+4} for r = 4, Q_{k-2..k+3}
+  // window entries either side reads: Q_{k-3..k+4} for r = 4, Q_{k-2..k+3}
   // otherwise (the others are left out, and set to zero where passed on)
   const int m0 = seventh_order(sc) ? 0 : 1, m1 = seventh_order(sc) ? 8 : 7;
   for (int side = 0; side < 2; ++side) {
     const T* Qref = Qs[3 + side];  // Q_k for +, Q_{k+1} for -
+    // the entries this side's interpolation reads, each deviation formed once
+    int lo, hi;
+    side_window(sc, side, lo, hi);
     T Qm[4];
     if (pr.vars == 0) {
       T L[4][4], R[4][4];
       eigenvectors(Qref, pr.gamma, nx_, ny_, L, R);
+      T dQ[8][4];
+      for (int m = lo; m < hi; ++m)
+        for (int q = 0; q < 4; ++q) dQ[m][q] = Qs[m][q] - Qref[q];
       T W[4];
       for (int c = 0; c < 4; ++c) {
         T s[8];
         for (int m = 0; m < 8; ++m) {
           s[m] = T(0.0);
-          if (m < m0 || m >= m1) continue;
-          for (int q = 0; q < 4; ++q) s[m] = s[m] + L[c][q] * (Qs[m][q] - Qref[q]);
+          if (m < lo || m >= hi) continue;
+          s[m] = L[c][0] * dQ[m][0];
+          for (int q = 1; q < 4; ++q) s[m] = s[m] + L[c][q] * dQ[m][q];
         }
         W[c] = side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr);
       }
       for (int q = 0; q < 4; ++q) {
-        Qm[q] = T(0.0);
-        for (int c = 0; c < 4; ++c) Qm[q] = Qm[q] + R[q][c] * W[c];
+        Qm[q] = R[q][0] * W[0];
+        for (int c = 1; c < 4; ++c) Qm[q] = Qm[q] + R[q][c] * W[c];
         Qm[q] = Qref[q] + Qm[q];
       }
     } else {
@@ -720,7 +736,7 @@ void midpoint_flux(Scheme sc, const Params& pr, const T Qs[8][4], double kx0, do
       T Vm[4];
       for (int c = 0; c < 4; ++c) {
         T s[8];
-        for (int m = 0; m < 8; ++m) s[m] = (m < m0 || m >= m1) ? T(0.0) : V[m][c] - V[3 + side][c];
+        for (int m = 0; m < 8; ++m) s[m] = (m < lo || m >= hi) ? T(0.0) : V[m][c] - V[3 + side][c];
         Vm[c] = V[3 + side][c] + (side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr));
       }
       if (pr.vars == 1)

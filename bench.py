@@ -33,23 +33,24 @@ sys.path.insert(0, ROOT)
 # speeds, H and its difference) plus 8 for the final -(R_xi + R_eta)/J^{-1},
 # counted by instantiating the oracle with an operation-counting scalar (add,
 # sub, mul, div, sqrt = 1 each) on the Riemann workload (oracle/count_flops.py).
-# The count is the method's own work: each side projects the window entries
-# its interpolation reads (five for r = 3, four for r = 2, seven for r = 4),
-# each deviation Q_m - Q_ref is formed once, sums start from their first term
+# The count is the method's own work: each side projects the deviations
+# Q_m - Q_ref of the window entries its interpolation reads (five for r = 3,
+# four for r = 2, seven for r = 4) except the reference node's own, which is
+# zero, each deviation is formed once and sums start from their first term
 # (B includes the oracle's uniform four-node ghost band, under 0.4 % of the
 # total at n = 2048).  The RK stage update adds 5 per component.  The
 # one-midpoint forms with alpha != 1 add a few operations per cell that the
 # table leaves out.
 N_DEFAULT = 2048
 FLOP_DIR = {  # (scheme family, interpolation variables) -> (A, B)
-    ("3", "characteristic"): (1072.0, 7115.0), ("3", "conservative"): (664.0, 4265.0),
-    ("3", "primitive"): (814.0, 5318.0),
-    ("5-1MP", "characteristic"): (1472.0, 9683.0), ("5-1MP", "conservative"): (1008.0, 6439.0),
-    ("5-1MP", "primitive"): (1158.0, 7491.0),
-    ("5-2MP", "characteristic"): (1464.0, 9675.0), ("5-2MP", "conservative"): (1000.0, 6431.0),
-    ("5-2MP", "primitive"): (1150.0, 7483.0),
-    ("7", "characteristic"): (2440.0, 16139.0), ("7", "conservative"): (1864.0, 12131.0),
-    ("7", "primitive"): (2058.0, 13501.0),
+    ("3", "characteristic"): (1008.0, 6667.0), ("3", "conservative"): (656.0, 4209.0),
+    ("3", "primitive"): (806.0, 5262.0),
+    ("5-1MP", "characteristic"): (1408.0, 9235.0), ("5-1MP", "conservative"): (1000.0, 6383.0),
+    ("5-1MP", "primitive"): (1150.0, 7435.0),
+    ("5-2MP", "characteristic"): (1400.0, 9227.0), ("5-2MP", "conservative"): (992.0, 6375.0),
+    ("5-2MP", "primitive"): (1142.0, 7427.0),
+    ("7", "characteristic"): (2376.0, 15691.0), ("7", "conservative"): (1856.0, 12075.0),
+    ("7", "primitive"): (2050.0, 13445.0),
 }
 # 3-D direction pass, per item (oracle/count_flops.py, per_item3; octant
 # Riemann state on a randomized periodic grid): nodal split flux per node
@@ -57,7 +58,7 @@ FLOP_DIR = {  # (scheme family, interpolation variables) -> (A, B)
 # (midpoints -4 .. n+2), and the upwind-biased combination and difference
 # per interior node: the algorithmic work of one sweep launch (the tiles'
 # recomputed halo items are not counted).
-FLOP_ITEM3 = {"3-1MP": (59.0, 1325.5, 61.1), "5-2MP": (59.0, 1795.6, 102.0), "7-2MP": (59.0, 2993.8, 163.2)}
+FLOP_ITEM3 = {"3-1MP": (59.0, 1225.5, 61.1), "5-2MP": (59.0, 1695.6, 102.0), "7-2MP": (59.0, 2893.8, 163.2)}
 FLOP_COMBINE = 8.0
 FLOP_RK_STAGE = 20.0
 PEAK_FP64_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
@@ -100,20 +101,82 @@ def flops_per_cell_dir(n, scheme="5-2MP", vars="characteristic"):
     return A + B / n
 
 
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, U, scheme, cfl, vars="characteristic", alpha_h=1.0, weights="js", split="lf"):
-    """The oracle, as it stands, timed on the host cores: one TVD-RK3 step of
-    the full workload (3 rhs evaluations)."""
+    """The oracle, as it stands, timed on the host: one rhs and one TVD-RK3
+    step (3 rhs) of the full workload, each with OpenMP over grid lines on
+    all host threads and single-threaded.  The headline figure is the
+    all-thread RK3 step."""
     import oracle
     oracle.build.build(force=False)
     M = oracle.metrics(scheme, g.x, g.y, g.bc, g.period, alpha_h=alpha_h)
     dt = oracle.cfl_dt(U, M, cfl)
-    t0 = time.perf_counter()
-    oracle.rk3_step(scheme, U, M, dt, g.bc, vars=vars, alpha_h=alpha_h, weights=weights, split=split)
-    t = time.perf_counter() - t0
+    kw = dict(vars=vars, alpha_h=alpha_h, weights=weights, split=split)
     n = g.x.size
-    return {"value": 3 * n / t, "unit": "cell-updates/s", "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": f"one TVD-RK3 step (3 rhs) of the full {g.x.shape[1]}x{g.x.shape[0]} workload, "
-                      f"{t:.2f} s"}
+    threads = oracle.get_threads()
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    t_step = timed(lambda: oracle.rk3_step(scheme, U, M, dt, g.bc, **kw))
+    t_rhs = timed(lambda: oracle.rhs(scheme, U, M, g.bc, **kw))
+    # single thread on a bounded sample: the first `rows` grid rows (full
+    # xi lines, a grid of its own with the same boundary rule)
+    rows = min(g.x.shape[0], 512)
+    gs = type(g)(np.ascontiguousarray(g.x[:rows]), np.ascontiguousarray(g.y[:rows]), g.bc, g.period)
+    Us = np.ascontiguousarray(U[:, :rows])
+    Ms = oracle.metrics(scheme, gs.x, gs.y, gs.bc, gs.period, alpha_h=alpha_h)
+    ns = gs.x.size
+    oracle.set_threads(1)
+    try:
+        t_rhs1 = timed(lambda: oracle.rhs(scheme, Us, Ms, gs.bc, **kw))
+        t_step1 = timed(lambda: oracle.rk3_step(scheme, Us, Ms, dt, gs.bc, **kw))
+    finally:
+        oracle.set_threads(threads)
+    shape = f"{g.x.shape[1]}x{g.x.shape[0]}"
+    return {"value": 3 * n / t_step, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one TVD-RK3 step (3 rhs) of the full {shape} workload on {threads} threads, {t_step:.2f} s",
+            "cpu_model": host_cpu_model(), "host_cpus": os.cpu_count(),
+            "rhs_cells_per_s": n / t_rhs,
+            "single_thread": {"rk3_cell_updates_per_s": 3 * ns / t_step1, "rhs_cells_per_s": ns / t_rhs1,
+                              "sample": f"the first {rows} rows ({g.x.shape[1]}x{rows}) of the workload, "
+                                        f"one rhs {t_rhs1:.2f} s, one RK3 step {t_step1:.2f} s"},
+            "timings_s": {"rk3_step": t_step, "rhs": t_rhs}}
+
+
+def uniform_grid_leg(n, scheme, cfl, params, steps):
+    """The same Riemann workload on the uniform (unjittered) 2048^2 grid of
+    [0,1]^2: RK3 steps with CFL, whole-step time."""
+    import torch
+    from paper_1810_11103_amd import workloads as W
+    from paper_1810_11103_amd import wenoiu
+    g, U0 = W.riemann_problem(n, A=0.0)
+    sol = wenoiu.Solver(g.x, g.y, scheme, g.bc, g.period, params=params)
+    U = torch.as_tensor(U0).cuda().contiguous()
+    for _ in range(3):
+        sol.rk3_step_cfl(U, cfl)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        sol.rk3_step_cfl(U, cfl)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"workload": f"2-D Riemann problem, uniform {n}x{n} grid on [0,1]^2, WENOIU{scheme}, transmissive, "
+                        f"TVD-RK3 CFL {cfl}", "ms_per_step": ms, "cell_updates_per_s": 3 * n * n / (ms * 1e-3),
+            "status": sol.status()}
 
 
 def batched_leg(steps, cfl, tune=True):
@@ -407,6 +470,7 @@ def main():
             "device_status": st,
         },
     }
+    out["extra"]["uniform_grid"] = uniform_grid_leg(n, args.scheme, args.cfl, params, args.steps)
     if not args.no_batched:
         del sol, U
         torch.cuda.empty_cache()

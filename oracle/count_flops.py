@@ -10,7 +10,8 @@ state; the count depends on the data only through the two branches of each
 weight mapping (a few hundredths of an operation per cell).
 
 What is counted is the method's own work as the oracle performs it: each
-side projects only the window entries its interpolation reads, each
+side projects only the window entries its interpolation reads, less the
+reference node itself (its deviation, and so its projection, is zero), each
 deviation Q_m - Q_ref is formed once per side, and sums of products start
 from their first term (no additions of zero).  The dense eigenvector
 products still include the structural zeros of L and R.

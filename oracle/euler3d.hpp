@@ -365,13 +365,14 @@ void midpoint_flux3(Scheme sc, const Params& pr, const T Qs[8][5], const double 
       eigenvectors3(Qref, pr.gamma, n, L, R);
       T dQ[8][5];
       for (int m = lo; m < hi; ++m)
-        for (int q = 0; q < 5; ++q) dQ[m][q] = Qs[m][q] - Qref[q];
+        for (int q = 0; q < 5; ++q) dQ[m][q] = m == 3 + side ? T(0.0) : Qs[m][q] - Qref[q];
       T W[5];
       for (int c = 0; c < 5; ++c) {
         T s[8];
         for (int m = 0; m < 8; ++m) {
           s[m] = T(0.0);
-          if (m < lo || m >= hi) continue;
+          // the reference node's own deviation is zero, and so is its projection
+          if (m < lo || m >= hi || m == 3 + side) continue;
           s[m] = L[c][0] * dQ[m][0];
           for (int q = 1; q < 5; ++q) s[m] = s[m] + L[c][q] * dQ[m][q];
         }
@@ -403,7 +404,8 @@ void midpoint_flux3(Scheme sc, const Params& pr, const T Qs[8][5], const double 
       T Vm[5];
       for (int c = 0; c < 5; ++c) {
         T s[8];
-        for (int m = 0; m < 8; ++m) s[m] = (m < lo || m >= hi) ? T(0.0) : V[m][c] - V[3 + side][c];
+        for (int m = 0; m < 8; ++m)
+          s[m] = (m < lo || m >= hi || m == 3 + side) ? T(0.0) : V[m][c] - V[3 + side][c];
         Vm[c] = V[3 + side][c] + (side == 0 ? weno_left(sc, s, pr) : weno_right(sc, s, pr));
       }
       if (pr.vars == 1) {

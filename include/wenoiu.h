@@ -192,6 +192,32 @@ int wiu_rk3_step(const wiu_grid* g, int scheme, const wiu_params* p, double* U, 
 int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
                      double* dt_dev, void* ws, wiu_stream_t stream);
 
+/* ---- Allocation-free RK3 step ------------------------------------------------
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same step and same results as wiu_rk3_step (the same
+ * kernels), with its scratch (two sets of line maxima and two stage buffers,
+ * wiu_noalloc_bytes() bytes) in one static device array of
+ * WIU_NOALLOC_SCRATCH_BYTES per device, which each device the library runs
+ * on holds from the first call until the process ends; the call itself
+ * allocates nothing.  Grids whose scratch exceeds the array (beyond about
+ * 1.1 million nodes, e.g. 1024 x 1024 fits) are rejected with WIU_EINVAL
+ * before anything is launched.  The current device must be the one `stream`
+ * belongs to; the first call on a device looks up the array's address there
+ * (make that first call outside graph capture).  Every call on one device
+ * shares its array: calls that overlap in time on one device (other streams,
+ * other threads) race and must be serialised by the caller.  Device-side
+ * conditions latch the WIU_ST_* bits into the caller's device int
+ * *status_dev (bits are OR-ed in, never cleared). */
+#define WIU_NOALLOC_SCRATCH_BYTES ((size_t)72 << 20)
+
+/* Scratch bytes wiu_rk3_step_noalloc needs for this grid (0 for an invalid
+ * grid); a grid is accepted when this is at most WIU_NOALLOC_SCRATCH_BYTES. */
+size_t wiu_noalloc_bytes(const wiu_grid* g);
+
+int wiu_rk3_step_noalloc(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
+                         const double* dt_dev, int* status_dev, wiu_stream_t stream);
+
 /* ---- Adjoints (metrics held fixed) ------------------------------------------
  * Reverse-mode derivatives of the residual and of one RK3 step with respect
  * to the state, for gradients through time integration.  Third- and

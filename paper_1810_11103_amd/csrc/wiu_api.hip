@@ -300,26 +300,82 @@ int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U
 // accumulate the maxima of U1 and U2 in their eta sweeps.
 // rec (optional, a step record): the three maxima sets go there instead of
 // the workspace, U's at rec[0], U1's at rec[1], U2's at rec[2].
+//
+// inplace: two buffers instead of three.  The eta sweep of a stage reads
+// the partial update P only at its own output node, so it may write the new
+// stage state over P: stage 1 puts P and then U1 in U1's buffer, stage 2 P
+// and U2 in U2's, and stage 3 its P in U1's buffer (U1 is no longer read).
 int rk3_stages(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M, const double* dt,
                double* U1, double* U2, const Ws& w, hipStream_t st, bool have_max,
-               unsigned long long* rec = nullptr) {
+               unsigned long long* rec = nullptr, bool inplace = false) {
   const long long ns = (long long)g->nx + g->ny + 1;
   unsigned long long* m0 = rec ? rec : w.lx;              // maxima of U
   unsigned long long* mA = rec ? rec + ns : w.lx2;        // of U1
   unsigned long long* mB = rec ? rec + 2 * ns : w.lx;     // of U2
+  Ws w1 = w, w2 = w, w3 = w;
+  if (inplace) { w1.rxi = U1; w2.rxi = U2; w3.rxi = U1; }
   Maxima m1;
   if (have_max) { m1.lx_in = w.lx; m1.le_in = w.le; }
   m1.wm = m0;
   m1.nlx = mA; m1.nle = mA + g->ny;
-  int rc = residual(g, scheme, p, U, M, w, 2, U1, U, dt, 0.0, 1.0, st, m1);
+  int rc = residual(g, scheme, p, U, M, w1, 2, U1, U, dt, 0.0, 1.0, st, m1);
   if (rc) return rc;
   Maxima m2;
   m2.lx_in = mA; m2.le_in = mA + g->ny; m2.nlx = mB; m2.nle = mB + g->ny;
-  rc = residual(g, scheme, p, U1, M, w, 2, U2, U, dt, 0.75, 0.25, st, m2);
+  rc = residual(g, scheme, p, U1, M, w2, 2, U2, U, dt, 0.75, 0.25, st, m2);
   if (rc) return rc;
   Maxima m3;
   m3.lx_in = mB; m3.le_in = mB + g->ny;
-  return residual(g, scheme, p, U2, M, w, 2, U, U, dt, 1.0 / 3.0, 2.0 / 3.0, st, m3);
+  return residual(g, scheme, p, U2, M, w3, 2, U, U, dt, 1.0 / 3.0, 2.0 / 3.0, st, m3);
+}
+
+// ---- allocation-free RK3 step ------------------------------------------------
+// Scratch of wiu_rk3_step_noalloc: one array per device, resident from the
+// library's first use on that device until the process ends.  Host code never
+// uses the array's name as an address (it is a host-side stand-in): the
+// device address is taken once per device with hipGetSymbolAddress.
+constexpr size_t NOALLOC_BYTES = WIU_NOALLOC_SCRATCH_BYTES;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Layout in the scratch: two sets of line maxima, then the two stage
+// buffers (P / U1 and P / U2, see rk3_stages).
+struct NoallocLayout {
+  size_t lam, lam2, a, b, total;
+};
+NoallocLayout noalloc_layout(const wiu_grid* g) {
+  NoallocLayout L;
+  const size_t np = (size_t)g->nx * g->ny;
+  const size_t lam = align_up(((size_t)g->nx + g->ny + 1) * 8);
+  L.lam = 0;
+  L.lam2 = lam;
+  L.a = 2 * lam;
+  L.b = L.a + align_up(4 * np * 8);
+  L.total = L.b + align_up(4 * np * 8);
+  return L;
+}
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[WIU_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of this device's scratch (the current device), taken on
+// the first call on the device; WIU_EHIP when the runtime cannot give it.
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return WIU_EHIP;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return WIU_EINVAL;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return WIU_EHIP;
+    g_noalloc_ptr[dev] = ptr;
+  }
+  *out = g_noalloc_ptr[dev];
+  return WIU_OK;
 }
 
 }  // namespace
@@ -402,6 +458,33 @@ int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double*
   }
   if (launch_cfl_dt(w.cfl, cfl, dt_dev, st) != hipSuccess) return WIU_EHIP;
   return rk3_stages(g, scheme, p, U, M, dt_dev, w.u1, w.u2, w, st, true);
+}
+
+size_t wiu_noalloc_bytes(const wiu_grid* g) {
+  if (!grid_ok(g)) return 0;
+  return noalloc_layout(g).total;
+}
+
+int wiu_rk3_step_noalloc(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
+                         const double* dt_dev, int* status_dev, wiu_stream_t stream) {
+  if (!grid_ok(g) || !options_ok(scheme, p) || !U || !M || !dt_dev || !status_dev) return WIU_EINVAL;
+  const NoallocLayout L = noalloc_layout(g);
+  if (L.total > NOALLOC_BYTES) return WIU_EINVAL;  // beyond the scratch, checked before any device call
+  void* base = nullptr;
+  if (const int rc = noalloc_scratch(&base)) return rc;
+  char* b = (char*)base;
+  Ws w{};
+  w.status = status_dev;
+  w.lx = (unsigned long long*)(b + L.lam);
+  w.le = w.lx + g->ny;
+  w.cfl = w.le + g->nx;
+  w.lx2 = (unsigned long long*)(b + L.lam2);
+  w.le2 = w.lx2 + g->ny;
+  double* A = (double*)(b + L.a);
+  double* B = (double*)(b + L.b);
+  // every maxima set is cleared by a fill kernel before it is accumulated,
+  // and both stage buffers are written before they are read
+  return rk3_stages(g, scheme, p, U, M, dt_dev, A, B, w, (hipStream_t)stream, false, nullptr, true);
 }
 
 int wiu_rhs_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U, const double* M,

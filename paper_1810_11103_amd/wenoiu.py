@@ -28,6 +28,7 @@ EXPORTS = [
     "wiu_blocks_metrics", "wiu3_metrics_size", "wiu3_workspace_bytes", "wiu3_metrics", "wiu3_rhs", "wiu3_cfl_dt",
     "wiu3_rk3_step", "wiu3_rk3_step_cfl",
     "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl", "wiu_step_record_bytes",
+    "wiu_noalloc_bytes", "wiu_rk3_step_noalloc",
 ]
 KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3, "sweep3": 4}
 
@@ -77,6 +78,8 @@ def _load():
         "wiu_cfl_dt": (I, [G, PR, P, P, ctypes.c_double, P, P, P]),
         "wiu_rk3_step": (I, [G, I, PR, P, P, P, P, P]),
         "wiu_rk3_step_cfl": (I, [G, I, PR, P, P, ctypes.c_double, P, P, P]),
+        "wiu_noalloc_bytes": (ctypes.c_size_t, [G]),
+        "wiu_rk3_step_noalloc": (I, [G, I, PR, P, P, P, P, P]),
         "wiu_status": (I, [P, P, ctypes.POINTER(I), I]),
         "wiu_strerror": (ctypes.c_char_p, [I]),
         "wiu_profile_enable": (I, [I]),
@@ -255,6 +258,19 @@ def rk3_step(grid, scheme, params, U, M, dt_dev, ws, stream=None):
 def rk3_step_cfl(grid, scheme, params, U, M, cfl, dt_dev, ws, stream=None):
     _check(lib.wiu_rk3_step_cfl(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U), _ptr(M),
                                 float(cfl), _ptr(dt_dev), ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+    return U
+
+
+def noalloc_bytes(grid):
+    return lib.wiu_noalloc_bytes(ctypes.byref(grid))
+
+
+def rk3_step_noalloc(grid, scheme, params, U, M, dt_dev, status_dev, stream=None):
+    """wiu_rk3_step without a workspace: scratch in the library's static
+    device array; device-side status bits are OR-ed into status_dev (int32)."""
+    assert status_dev.is_cuda and status_dev.dtype == torch.int32, "int32 device tensor expected"
+    _check(lib.wiu_rk3_step_noalloc(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U), _ptr(M),
+                                    _ptr(dt_dev), ctypes.c_void_p(status_dev.data_ptr()), _stream(stream)))
     return U
 
 

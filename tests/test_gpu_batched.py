@@ -143,3 +143,31 @@ def test_batched_plan_rejects_bad_blocks(wiu):
     rc = wiu.lib.wiu_batched_plan(blk, 1, 3, ctypes.byref(prm), 0, 0, ctypes.c_void_p(256), ctypes.c_void_p(256),
                                   ctypes.byref(p))
     assert rc == wiu.WIU_EINVAL and not p.value
+
+
+def test_batched_d4_workload_largest_blocks_match_oracle(orc, wiu):
+    """The full 64-block batched workload (sides 64..1024, 24.4 M cells), one
+    step replayed from a captured graph; the three largest blocks, which
+    include sides of 1024 nodes, are checked against the oracle's RK3 step
+    with the same per-block time step."""
+    say("batched D4 workload vs oracle")
+    blocks = W.batched_blocks()
+    sizes = [g.x.size for g, _ in blocks]
+    pick = sorted(range(len(blocks)), key=lambda b: -sizes[b])[:3]
+    assert any(max(blocks[b][0].x.shape) == 1024 for b in pick)
+    plan = _plan(wiu, blocks, "5-2MP")
+    plan.cfl_dt(0.5)
+    dts = plan.get_dt()
+    plan.step(graph=True)
+    assert plan.status() == 0
+    for b in pick:
+        g, U = blocks[b]
+        say("  block", b, g.x.shape)
+        M = orc.metrics("5-2MP", g.x, g.y, g.bc, g.period)
+        assert orc.cfl_dt(U, M, 0.5) == pytest.approx(dts[b], rel=1e-13)
+        ref = orc.rk3_step("5-2MP", U, M, dts[b], g.bc)
+        out = plan.state(b).cpu().numpy()
+        for c in range(4):
+            scale = np.abs(ref[c] - U[c]).max()
+            assert np.abs((out[c] - U[c]) - (ref[c] - U[c])).max() <= 1e-11 * scale, (b, c)
+    plan.close()

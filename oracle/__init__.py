@@ -26,8 +26,10 @@ _P = ctypes.c_void_p
 def lib():
     global _lib
     if _lib is None:
-        path = _build.LIB
-        if not os.path.exists(path):
+        # ORACLE_LIB: another build of the same source (the sanitizer build of
+        # tests/test_oracle_sanitizers.py); otherwise the regular library
+        path = os.environ.get("ORACLE_LIB") or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
         L = ctypes.CDLL(path)
         L.orc_weno.restype = _D

@@ -30,5 +30,16 @@ def build(force=True):
     return LIB
 
 
+def build_sanitized(out):
+    """The same library with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code only; every undefined-behaviour report is fatal), written to
+    `out`.  Loaded into a Python process with the ASan runtime preloaded."""
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas", "-o", out, SRC]
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     print(build())

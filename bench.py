@@ -357,6 +357,7 @@ def main():
     ap.add_argument("--no-rhs", action="store_true", help="skip the bare-rhs timing")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional leg")
+    ap.add_argument("--adjoint-steps", type=int, default=400, help="RK3 steps of the adjoint leg")
     ap.add_argument("--n3", type=int, default=256, help="grid size of the three-dimensional leg")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM counters)")
@@ -482,7 +483,7 @@ def main():
         out["extra"]["batched"] = batched_leg(max(3, args.steps // 4), args.cfl)
     if not args.no_adjoint:
         torch.cuda.empty_cache()
-        out["extra"]["adjoint"] = adjoint_leg()
+        out["extra"]["adjoint"] = adjoint_leg(nsteps=args.adjoint_steps)
     if not args.no_3d:
         torch.cuda.empty_cache()
         out["extra"]["three_d"] = three_d_leg(args.n3)

@@ -8,7 +8,10 @@ Two ways to have the stage states at hand in the backward pass:
   every = k   forward keeps U_n every k steps (checkpoints); backward walks
               the segments in reverse, recomputes each segment forward with
               its stage states (wiu_rk3_step_stages), then applies the step
-              adjoints in reverse order (N/k checkpoints + 3 k states).
+              adjoints in reverse order (N/k checkpoints + 3 k states).  The
+              last segment's stage states are the forward pass's own (kept
+              as it runs them), so the backward pass starts with adjoints
+              while the next segment is recomputed beside it.
 rollout(every="auto") stores everything when 3 N states fit in the given
 fraction of free device memory, else checkpoints every ~sqrt(N/3) steps,
 which minimises N/k + 3k.  Metrics and the time step are held fixed (no
@@ -30,6 +33,10 @@ class RK3Rollout(torch.autograd.Function):
         if every == 0:  # one allocation for all (U_n, U1, U2), and their step records
             stages = torch.empty((nsteps, 3) + tuple(U.shape), dtype=U.dtype, device=U.device)
             recs = solver.step_record(nsteps)
+        else:  # the last segment's stages and step records
+            first_last = (nsteps - 1) // every * every
+            stages = torch.empty((nsteps - first_last, 3) + tuple(U.shape), dtype=U.dtype, device=U.device)
+            recs = solver.step_record(nsteps - first_last)
         for s in range(nsteps):
             if every == 0:
                 stages[s, 0].copy_(U)
@@ -37,7 +44,12 @@ class RK3Rollout(torch.autograd.Function):
             else:
                 if s % every == 0:
                     ckpts.append(U.clone())
-                solver.rk3_step(U)
+                if s >= first_last:
+                    i = s - first_last
+                    stages[i, 0].copy_(U)
+                    solver.rk3_step_stages(U, stages[i, 1], stages[i, 2], rec=recs[i])
+                else:
+                    solver.rk3_step(U)
         ctx.solver, ctx.nsteps, ctx.dt, ctx.every = solver, nsteps, float(dt), every
         ctx.ckpts, ctx.stages, ctx.recs = ckpts, stages, recs
         return U
@@ -58,9 +70,10 @@ class RK3Rollout(torch.autograd.Function):
 
 
 def _checkpointed_backward(ctx, Ub):
-    """Segments in reverse order; the forward recomputation of segment k-1
-    runs on a second stream (its own workspace, one of two stage buffers)
-    while the step adjoints of segment k run on the caller's stream."""
+    """Segments in reverse order: the last one from the stages the forward
+    pass kept; for the others, the forward recomputation of segment k-1 runs
+    on a second stream (its own workspace, one of two stage buffers) while
+    the step adjoints of segment k run on the caller's stream."""
     solver, nsteps, every, ckpts = ctx.solver, ctx.nsteps, ctx.every, ctx.ckpts
     nseg = len(ckpts)
     main = torch.cuda.current_stream()
@@ -84,12 +97,14 @@ def _checkpointed_backward(ctx, Ub):
                 solver.rk3_step_stages(U, B[i, 1], B[i, 2], ws=ws2, rec=recs[seg % 2, i])
             ready[seg].record(side)
 
-    recompute(nseg - 1)
     for seg in reversed(range(nseg)):
         if seg > 0:
             recompute(seg - 1)
-        main.wait_event(ready[seg])
-        B, R = bufs[seg % 2], recs[seg % 2]
+        if seg == nseg - 1:
+            B, R = ctx.stages, ctx.recs
+        else:
+            main.wait_event(ready[seg])
+            B, R = bufs[seg % 2], recs[seg % 2]
         for i in reversed(range(min(nsteps, (seg + 1) * every) - seg * every)):
             solver.rk3_step_vjp(B[i, 0], Ub, B[i, 1], B[i, 2], out=Ub, rec=R[i])
         freed[seg].record(main)

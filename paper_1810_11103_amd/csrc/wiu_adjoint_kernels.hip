@@ -62,37 +62,66 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
   const bool live = line < n_ac;
   const int tid = threadIdx.x + blockDim.x * threadIdx.y;
 
-  // stage states (boundary rule applied) and Rbar = -Gbar / J^{-1} (zero off the line)
+  // stage states (boundary rule applied) and Rbar = -Gbar / J^{-1} (zero off
+  // the line); every load of the thread's elements is issued before any is
+  // stored, so their latencies overlap
   {
     const int k0 = o0 + LO - 2;
-    for (int e = tid; e < NQ * NB; e += NT) {
+    const int r0 = o0 + LO - 3;
+    constexpr int NR = NA + 6;
+    constexpr int IQ = (NQ * NB + NT - 1) / NT, IR = (NR * NB + NT - 1) / NT;
+    double qv[IQ][4], gv[IR][4], jv[IR];
+#pragma unroll
+    for (int it = 0; it < IQ; ++it) {
+      const int e = tid + it * NT;
       const int pos = DIR == 0 ? e % NQ : e / NB;
       const int lb_ = DIR == 0 ? e / NQ : e % NB;
       const int ln = lgrp * NB + lb_;
-      if (ln < n_ac) {
+      if (e < NQ * NB && ln < n_ac) {
         const int kk = bc_index(k0 + pos, n_al, bc_al);
         const long long o = DIR == 0 ? (long long)ln * d.nx + kk : (long long)kk * d.nx + ln;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) L.sq[c][LT::qi(lb_, pos)] = s.U[c * d.np + o];
+        for (int c = 0; c < 4; ++c) qv[it][c] = s.U[c * d.np + o];
       }
     }
-    const int r0 = o0 + LO - 3;
-    constexpr int NR = NA + 6;
-    for (int e = tid; e < NR * NB; e += NT) {
+#pragma unroll
+    for (int it = 0; it < IR; ++it) {
+      const int e = tid + it * NT;
       const int pos = DIR == 0 ? e % NR : e / NB;
       const int lb_ = DIR == 0 ? e / NR : e % NB;
       const int ln = lgrp * NB + lb_;
       const int p = r0 + pos;
-      double v[4] = {0.0, 0.0, 0.0, 0.0};
-      if (ln < n_ac && p >= 0 && p < n_al) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gv[it][c] = 0.0;
+      jv[it] = -1.0;
+      if (e < NR * NB && ln < n_ac && p >= 0 && p < n_al) {
         const int ii = DIR == 0 ? p : ln, jj = DIR == 0 ? ln : p;
         const long long o = (long long)jj * d.nx + ii;
-        const double rj = -1.0 / s.M[4 * d.mplane + (long long)(jj + GHOST) * d.mpitch + (ii + GHOST)];
+        jv[it] = s.M[4 * d.mplane + (long long)(jj + GHOST) * d.mpitch + (ii + GHOST)];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = s.Gbar[c * d.np + o] * rj;
+        for (int c = 0; c < 4; ++c) gv[it][c] = s.Gbar[c * d.np + o];
       }
+    }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) L.rb[c][LT::ri(lb_, pos)] = v[c];
+    for (int it = 0; it < IQ; ++it) {
+      const int e = tid + it * NT;
+      const int pos = DIR == 0 ? e % NQ : e / NB;
+      const int lb_ = DIR == 0 ? e / NQ : e % NB;
+      if (e < NQ * NB && lgrp * NB + lb_ < n_ac) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) L.sq[c][LT::qi(lb_, pos)] = qv[it][c];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IR; ++it) {
+      const int e = tid + it * NT;
+      const int pos = DIR == 0 ? e % NR : e / NB;
+      const int lb_ = DIR == 0 ? e / NR : e % NB;
+      if (e < NR * NB) {
+        const double rj = -1.0 / jv[it];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) L.rb[c][LT::ri(lb_, pos)] = gv[it][c] * rj;
+      }
     }
   }
   __syncthreads();

@@ -249,6 +249,16 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   const bool need_node = live && k >= o0 + Traits<SC>::NLO && k < o0 + out + Traits<SC>::NHI;
   const bool need_mid = live && k >= o0 + Traits<SC>::MLO && k < o0 + out + Traits<SC>::MHI;
 
+  // metrics of this thread's item, issued before the staging so that their
+  // latency overlaps it
+  const long long mo_k = mline + mstride * k;
+  double kx0 = 0.0, ky0 = 0.0, kx1 = 0.0, ky1 = 0.0, mmx = 0.0, mmy = 0.0;
+  if (need_node || need_mid) { kx0 = Mk[mo_k]; ky0 = Mk[d.mplane + mo_k]; }
+  if (need_mid) {
+    kx1 = Mk[mo_k + mstride]; ky1 = Mk[d.mplane + mo_k + mstride];
+    mmx = Mm[mo_k]; mmy = Mm[d.mplane + mo_k];
+  }
+
   // Stage the states of the tile (with the boundary rule applied) in LDS,
   // consecutive threads reading consecutive addresses.  Beyond the ends of a
   // non-periodic line the side's rule applies: transmissive (copy of the
@@ -262,45 +272,67 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
     // tiles whose window stays inside the line, or with no wall or fixed
     // side at the ends it reaches, load plainly (block-uniform test)
     const bool edge = bc_al != 0 && ((k0 < 0 && s.side[S0] != 0) || (k0 + NQ > n_al && s.side[S0 + 1] != 0));
-    for (int e = tid; e < NQ * NB; e += NT) {
-      const int pos = DIR == 0 ? e % NQ : e / NB;
-      const int lb = DIR == 0 ? e / NQ : e % NB;
-      const int ln = (DIR == 0 ? byl : bxl) * NB + lb;
-      if (ln < n_ac) {
-        const int kr = k0 + pos;
-        const bool lo = kr < 0;
-        const int rule = (edge && (lo || kr >= n_al)) ? (lo ? s.side[S0] : s.side[S0 + 1]) : 0;
-        double Qv[4];
-        if (rule == 2) {
+    // the thread's elements, NIT at most; in the paper's configuration every
+    // load is issued before any is stored, so their latencies overlap (the
+    // option kernels, short of registers, load and store one at a time)
+    constexpr int NIT = (NQ * NB + NT - 1) / NT;
+    constexpr int GRP = OPT ? 1 : NIT;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) Qv[c] = lo ? s.fixed[S0][c] : s.fixed[S0 + 1][c];
-        } else if (rule == 3) {
-          // interface: the neighbour's node; layers deeper than any stencil
-          // reaches are clamped (staged but never used)
-          const int sd = lo ? S0 : S0 + 1;
-          const int m = min(lo ? -kr : kr - n_al + 1, WIU_MB_REACH - 1);
-          const long long o = s.g0[sd] + m * s.gm[sd] + ln * s.gl[sd];
+    for (int g0 = 0; g0 < NIT; g0 += GRP) {
+      double Qs_[GRP][4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) Qv[c] = s.nbU[sd][c * s.nbnp[sd] + o];
-        } else {
-          const int kb = lo ? 0 : n_al - 1;
-          const int kk = rule == 1 ? min(max(2 * kb - kr, 0), n_al - 1) : bc_index(kr, n_al, bc_al);
-          const long long o = DIR == 0 ? (long long)ln * d.nx + kk : (long long)kk * d.nx + ln;
+      for (int it = 0; it < GRP; ++it) {
+        const int e = tid + (g0 + it) * NT;
+        if (e >= NQ * NB) break;
+        const int pos = DIR == 0 ? e % NQ : e / NB;
+        const int lb = DIR == 0 ? e / NQ : e % NB;
+        const int ln = (DIR == 0 ? byl : bxl) * NB + lb;
+        double* Qv = Qs_[it];
+        if (ln < n_ac) {
+          const int kr = k0 + pos;
+          const bool lo = kr < 0;
+          const int rule = (edge && (lo || kr >= n_al)) ? (lo ? s.side[S0] : s.side[S0 + 1]) : 0;
+          if (rule == 2) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) Qv[c] = s.U[c * d.np + o];
-          if (rule == 1) {
-            const long long mb = DIR == 0 ? (long long)(ln + GHOST) * d.mpitch + (kb + GHOST)
-                                          : (long long)(kb + GHOST) * d.mpitch + (ln + GHOST);
-            const double bx = Mk[mb], by = Mk[d.mplane + mb];
-            const double rn = rsqrt_(bx * bx + by * by);
-            const double nbx = bx * rn, nby = by * rn;
-            const double mn = Qv[1] * nbx + Qv[2] * nby;
-            Qv[1] -= 2.0 * mn * nbx;
-            Qv[2] -= 2.0 * mn * nby;
+            for (int c = 0; c < 4; ++c) Qv[c] = lo ? s.fixed[S0][c] : s.fixed[S0 + 1][c];
+          } else if (rule == 3) {
+            // interface: the neighbour's node; layers deeper than any stencil
+            // reaches are clamped (staged but never used)
+            const int sd = lo ? S0 : S0 + 1;
+            const int m = min(lo ? -kr : kr - n_al + 1, WIU_MB_REACH - 1);
+            const long long o = s.g0[sd] + m * s.gm[sd] + ln * s.gl[sd];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Qv[c] = s.nbU[sd][c * s.nbnp[sd] + o];
+          } else {
+            const int kb = lo ? 0 : n_al - 1;
+            const int kk = rule == 1 ? min(max(2 * kb - kr, 0), n_al - 1) : bc_index(kr, n_al, bc_al);
+            const long long o = DIR == 0 ? (long long)ln * d.nx + kk : (long long)kk * d.nx + ln;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Qv[c] = s.U[c * d.np + o];
+            if (rule == 1) {
+              const long long mb = DIR == 0 ? (long long)(ln + GHOST) * d.mpitch + (kb + GHOST)
+                                            : (long long)(kb + GHOST) * d.mpitch + (ln + GHOST);
+              const double bx = Mk[mb], by = Mk[d.mplane + mb];
+              const double rn = rsqrt_(bx * bx + by * by);
+              const double nbx = bx * rn, nby = by * rn;
+              const double mn = Qv[1] * nbx + Qv[2] * nby;
+              Qv[1] -= 2.0 * mn * nbx;
+              Qv[2] -= 2.0 * mn * nby;
+            }
           }
         }
+      }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sq[c][LT::qi(lb, pos)] = Qv[c];
+      for (int it = 0; it < GRP; ++it) {
+        const int e = tid + (g0 + it) * NT;
+        if (e >= NQ * NB) break;
+        const int pos = DIR == 0 ? e % NQ : e / NB;
+        const int lb = DIR == 0 ? e / NQ : e % NB;
+        const int ln = (DIR == 0 ? byl : bxl) * NB + lb;
+        if (ln < n_ac) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) sq[c][LT::qi(lb, pos)] = Qs_[it][c];
+        }
       }
     }
   }
@@ -309,8 +341,6 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
   if (need_node || need_mid) {
     // stencil states Q_{k-QL..k+QL+1}, read from LDS where they are used
     auto q = [&](int m, int c) { return sq[c][LT::qi(tb, ta + m)]; };
-    const long long mo = mline + mstride * k;
-    const double kx0 = Mk[mo], ky0 = Mk[d.mplane + mo];
     if (need_node) {
       const double qk[4] = {q(QL, 0), q(QL, 1), q(QL, 2), q(QL, 3)};
       double E[4];
@@ -319,8 +349,7 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
       for (int c = 0; c < 4; ++c) sh[c][slot] = E[c];
     }
     if (need_mid) {
-      const double kx1 = Mk[mo + mstride], ky1 = Mk[d.mplane + mo + mstride];
-      const double mx = Mm[mo], my = Mm[d.mplane + mo];
+      const double mx = mmx, my = mmy;
       const double nbx = 0.5 * (kx0 + kx1), nby = 0.5 * (ky0 + ky1);
       const double rn = rsqrt_(nbx * nbx + nby * nby);
       const double nx_ = nbx * rn, ny_ = nby * rn;

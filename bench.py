@@ -236,6 +236,43 @@ def batched_leg(steps, cfl, tune=True):
             "status": st}
 
 
+def batched_small_leg(steps, cfl, nblocks=64, nmin=24, nmax=64):
+    """The batched step where launches, not kernels, set the time: 64
+    periodic randomized blocks with sides 24..64 (the same generator as the
+    64-block workload at smaller sizes).  Graph replay against eager
+    launches of the same batched kernels, alternating, medians."""
+    import torch
+    from paper_1810_11103_amd import wenoiu
+    from paper_1810_11103_amd import workloads as W
+
+    blocks = W.batched_blocks(nblocks=nblocks, seed=65, nmin=nmin, nmax=nmax)
+    plan = wenoiu.BatchedPlan([(g.x, g.y, g.bc, g.period) for g, _ in blocks], "5-2MP")
+    for b, (_, U) in enumerate(blocks):
+        plan.state(b).copy_(torch.as_tensor(U))
+    plan.cfl_dt(cfl)
+    plan.set_dt([0.5 * t for t in plan.get_dt()])
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    tg, te = [], []
+    for _ in range(3):
+        tg.append(timed(lambda: plan.step(graph=True), steps))
+        te.append(timed(lambda: plan.step(graph=False), steps))
+    out = {"blocks": len(blocks), "cells": plan.info()[0], "graph_ms_per_step": float(np.median(tg)),
+           "eager_batched_ms_per_step": float(np.median(te)), "status": plan.status()}
+    plan.close()
+    return out
+
+
 def three_d_leg(n=256, steps=8, cfl=0.5, scheme="5-2MP"):
     """Three-dimensional path: RK3 steps with CFL of an octant Riemann state
     on a randomized periodic n^3 grid; per-kernel times and the item
@@ -481,6 +518,7 @@ def main():
         del sol, U
         torch.cuda.empty_cache()
         out["extra"]["batched"] = batched_leg(max(3, args.steps // 4), args.cfl)
+        out["extra"]["batched_small"] = batched_small_leg(max(20, args.steps), args.cfl)
     if not args.no_adjoint:
         torch.cuda.empty_cache()
         out["extra"]["adjoint"] = adjoint_leg(nsteps=args.adjoint_steps)

@@ -316,53 +316,69 @@ __global__ void __launch_bounds__(256) adj_fixup_kernel(AdjArgs s, int dir, int 
   const int n_ac = dir == 0 ? d.ny : d.nx;
   const int bc_al = dir == 0 ? d.bcx : d.bcy;
   if (line >= n_ac) return;
-  // eigenvalue adjoint and first maximal node over the line's segments
-  double lb = 0.0;
-  int ks = INT_MAX;
-  for (int t = lane; t < nseg; t += 64) {
-    lb += s.lam_part[(long long)line * nseg + t];
-    ks = min(ks, s.arg_part[(long long)line * nseg + t]);
-  }
-  for (int off = 32; off > 0; off >>= 1) {  // symmetric butterfly: every lane gets the same bits
-    lb += __shfl_xor(lb, off, 64);
-    ks = min(ks, __shfl_xor(ks, off, 64));
-  }
   constexpr int NG = 2 * NGHOST_ADJ;
   auto target = [&](int g) {
     const int p = g < NGHOST_ADJ ? -1 - g : n_al + (g - NGHOST_ADJ);
     return bc_index(p, n_al, bc_al);
   };
-  // lanes 0 .. NG-1: the ghost targets; lane NG: the maximal node if no ghost maps there
+  // Lanes 0 .. NG-1 own the ghost targets (the first lane of each distinct
+  // target).  Their ghost contributions and the current Ubar there are
+  // loaded first, so those loads overlap the reduction below.
   int t = -1;
   bool own = false;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0}, ub[4] = {0.0, 0.0, 0.0, 0.0};
   if (lane < NG) {
     t = target(lane);
     own = true;
     for (int g = 0; g < lane; ++g) own = own && target(g) != t;
-  } else if (lane == NG && ks < n_al) {
+    if (own) {
+      for (int g = 0; g < NG; ++g) {
+        if (target(g) != t) continue;
+        const double* gb =
+            s.ghost + (((long long)line * 2 + (g < NGHOST_ADJ ? 0 : 1)) * NGHOST_ADJ + g % NGHOST_ADJ) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += gb[c];
+      }
+      const long long o = dir == 0 ? (long long)line * d.nx + t : (long long)t * d.nx + line;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ub[c] = s.Ubar[c * d.np + o];
+    }
+  }
+  // eigenvalue adjoint and first maximal node over the line's segments
+  double lb = 0.0;
+  int ks = INT_MAX;
+  for (int q = lane; q < nseg; q += 64) {
+    lb += s.lam_part[(long long)line * nseg + q];
+    ks = min(ks, s.arg_part[(long long)line * nseg + q]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {  // symmetric butterfly: every lane gets the same bits
+    lb += __shfl_xor(lb, off, 64);
+    ks = min(ks, __shfl_xor(ks, off, 64));
+  }
+  // lane NG: the maximal node if no ghost maps there
+  if (lane == NG && ks < n_al) {
     t = ks;
     own = true;
     for (int g = 0; g < NG; ++g) own = own && target(g) != t;
-  }
-  if (!own) return;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int g = 0; g < NG; ++g) {
-    if (target(g) != t) continue;
-    const double* gb = s.ghost + (((long long)line * 2 + (g < NGHOST_ADJ ? 0 : 1)) * NGHOST_ADJ + g % NGHOST_ADJ) * 4;
+    if (own) {
+      const long long o = dir == 0 ? (long long)line * d.nx + t : (long long)t * d.nx + line;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] += gb[c];
+      for (int c = 0; c < 4; ++c) ub[c] = s.Ubar[c * d.np + o];
+    }
   }
-  const long long o = dir == 0 ? (long long)line * d.nx + t : (long long)t * d.nx + line;
-  if (t == ks && lb != 0.0) {
-    const double Q[4] = {s.U[o], s.U[d.np + o], s.U[2 * d.np + o], s.U[3 * d.np + o]};
-    const int ii = dir == 0 ? t : line, jj = dir == 0 ? line : t;
-    const long long mo = (long long)(jj + GHOST) * d.mpitch + (ii + GHOST);
-    const double* Mk = s.M + (dir == 0 ? 0 : 2) * d.mplane;
-    wave_speed_vjp(Q, Mk[mo], Mk[d.mplane + mo], s.gamma, s.alpha * lb, acc);
-  }
-  const double coef = s.coef_c * (s.coef_dt ? s.coef_dt[0] : 1.0);
+  if (own) {
+    const long long o = dir == 0 ? (long long)line * d.nx + t : (long long)t * d.nx + line;
+    if (t == ks && lb != 0.0) {
+      const double Q[4] = {s.U[o], s.U[d.np + o], s.U[2 * d.np + o], s.U[3 * d.np + o]};
+      const int ii = dir == 0 ? t : line, jj = dir == 0 ? line : t;
+      const long long mo = (long long)(jj + GHOST) * d.mpitch + (ii + GHOST);
+      const double* Mk = s.M + (dir == 0 ? 0 : 2) * d.mplane;
+      wave_speed_vjp(Q, Mk[mo], Mk[d.mplane + mo], s.gamma, s.alpha * lb, acc);
+    }
+    const double coef = s.coef_c * (s.coef_dt ? s.coef_dt[0] : 1.0);
 #pragma unroll
-  for (int c = 0; c < 4; ++c) s.Ubar[c * d.np + o] += coef * acc[c];
+    for (int c = 0; c < 4; ++c) s.Ubar[c * d.np + o] = ub[c] + coef * acc[c];
+  }
   if (lane == 0 && ks >= n_al && lb != 0.0) atomicOr(s.status, ST_ARGMAX);
 }
 

@@ -164,13 +164,12 @@ def uniform_grid_leg(n, scheme, cfl, params, steps):
     g, U0 = W.riemann_problem(n, A=0.0)
     sol = wenoiu.Solver(g.x, g.y, scheme, g.bc, g.period, params=params)
     U = torch.as_tensor(U0).cuda().contiguous()
-    for _ in range(3):
-        sol.rk3_step_cfl(U, cfl)
+    dts = torch.empty(max(steps, 3), dtype=torch.float64, device="cuda")
+    sol.rk3_steps_cfl(U, cfl, 3, dts)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(steps):
-        sol.rk3_step_cfl(U, cfl)
+    sol.rk3_steps_cfl(U, cfl, steps, dts)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
@@ -293,17 +292,20 @@ def three_d_leg(n=256, steps=8, cfl=0.5, scheme="5-2MP"):
     for _ in range(2):
         step()
     torch.cuda.synchronize()
-    wenoiu.profile_enable(True)
-    wenoiu.profile_read("sweep3")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(steps):
+    for _ in range(steps):  # bare steps
         step()
     e1.record()
     torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    wenoiu.profile_enable(True)  # again, every launch bracketed by events
+    wenoiu.profile_read("sweep3")
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
     kern = {"sweep3": wenoiu.profile_read("sweep3")}
     wenoiu.profile_enable(False)
-    ms = e0.elapsed_time(e1) / steps
     fn, fm, fd = FLOP_ITEM3[scheme]
     per_launch = n * n * ((n + 8) * fn + (n + 7) * fm + n * fd)
     achieved = per_launch / (kern["sweep3"][1] * 1e-3) / 1e12
@@ -423,33 +425,52 @@ def main():
     U = torch.as_tensor(U0).cuda().contiguous()
     torch.cuda.synchronize()
 
-    def step():
-        sol.rk3_step_cfl(U, args.cfl)
+    # time marching: K CFL-limited RK3 steps per call (each step's line
+    # eigenvalues and CFL maximum come from the previous step's last sweep)
+    dts = torch.empty(max(args.steps, args.warmup, 1), dtype=torch.float64, device="cuda")
 
-    for _ in range(args.warmup):
-        step()
+    def steps(k):
+        if k > 0:
+            sol.rk3_steps_cfl(U, args.cfl, k, dts)
+
+    steps(args.warmup)
     torch.cuda.synchronize()
     st = sol.status()
     if st:
         raise SystemExit(f"device status {st} after warm-up")
 
-    # timed region: K steps between two synchronisations, kernel timing on
-    wenoiu.profile_enable(True)
-    for k in ("wave_max", "sweep_xi", "sweep_eta"):
-        wenoiu.profile_read(k)
+    # timed region: K bare steps between two synchronisations
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_host = time.perf_counter()
     e0.record()
-    for _ in range(args.steps):
-        step()
+    steps(args.steps)
     e1.record()
     torch.cuda.synchronize()
     t_host = time.perf_counter() - t_host
     ms_total = e0.elapsed_time(e1)
+    ms_per_step = ms_total / args.steps
+    # the same K steps again with every launch bracketed by HIP events on the
+    # library's stream: mean duration of each kernel
+    wenoiu.profile_enable(True)
+    for k in ("wave_max", "sweep_xi", "sweep_eta"):
+        wenoiu.profile_read(k)
+    torch.cuda.synchronize()
+    e0.record()
+    steps(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_evented = e0.elapsed_time(e1) / args.steps
+    # one call per step (a separate maxima pass in every step), for comparison
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        sol.rk3_step_cfl(U, args.cfl)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_single_calls = e0.elapsed_time(e1) / args.steps
     kern = {k: wenoiu.profile_read(k) for k in ("wave_max", "sweep_xi", "sweep_eta")}
     wenoiu.profile_enable(False)
-    ms_per_step = ms_total / args.steps
     cells = n * n
     value = 3 * cells * args.steps / (ms_total * 1e-3)
 
@@ -509,6 +530,8 @@ def main():
             "rhs_ms": rhs_ms,
             "rhs_cells_per_s": rhs_ms and cells / (rhs_ms * 1e-3),
             "kernels_ms": {k: round(v[1], 4) for k, v in kern.items()},
+            "ms_per_step_with_kernel_events": ms_evented,
+            "ms_per_step_one_call_per_step": ms_single_calls,
             "host_wall_s": t_host,
             "device_status": st,
         },

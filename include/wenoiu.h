@@ -192,6 +192,17 @@ int wiu_rk3_step(const wiu_grid* g, int scheme, const wiu_params* p, double* U, 
 int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
                      double* dt_dev, void* ws, wiu_stream_t stream);
 
+/* nsteps (>= 1) CFL-limited RK3 steps in one call, the time marching of
+ * Sec. 6: dt_dev[s] (device array of nsteps doubles, caller-owned) receives
+ * step s's time step, computed on the device from the state it starts from.
+ * Results are those of nsteps wiu_rk3_step_cfl calls, bit for bit; only the
+ * first step has a separate maxima pass over U, later steps take the line
+ * eigenvalues and the CFL maximum of their state from the last stage of the
+ * step before, which accumulates them as it writes that state.  WIU_EINVAL
+ * for nsteps < 1 or invalid arguments, before anything is launched. */
+int wiu_rk3_steps_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
+                      int nsteps, double* dt_dev, void* ws, wiu_stream_t stream);
+
 /* ---- Allocation-free RK3 step ------------------------------------------------
  * For callers that cannot allocate device memory or pass a workspace: code
  * under HIP graph capture, tight serving loops, harnesses that forbid

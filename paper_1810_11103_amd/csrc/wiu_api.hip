@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <utility>
 #include <vector>
 
 using namespace wiu;
@@ -64,8 +65,9 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Workspace layout (byte offsets):
 //   0            header: int status, padding
-//   HDR          lam_xi[ny], lam_eta[nx], cfl_max[1]   (uint64 bit patterns)
-//   lam2         a second lam_xi, lam_eta, cfl_max set (maxima of an RK stage state)
+//   HDR          lam_xi[ny], lam_eta[nx], cfl_max[1], cfl per eta line[nx]
+//                (uint64 bit patterns)
+//   lam2         a second such set (maxima of an RK stage state)
 //   off_scratch  R^xi[4 np], U1[4 np], U2[4 np]  -- or the metric band temp
 //   then the adjoint region: Ubar2, Ubar1 (4 planes each), eigenvalue
 //   partials [max lines x segments] (double) and first maximal nodes (int),
@@ -80,9 +82,12 @@ WsLayout layout(const wiu_grid* g) {
   const int B = GHOST + 4;  // widest nodal-metric band (eight-point interpolation)
   const size_t band = 5 * (size_t)(g->nx + 2 * B) * (g->ny + 2 * B);
   const size_t plane4 = align_up(4 * np * 8);
+  // a maxima set: lam_xi[ny], lam_eta[nx], cfl[1], then per eta line the
+  // CFL maxima[nx] that wiu_rk3_steps_cfl accumulates in a step's last stage
+  const size_t set = align_up(((size_t)2 * g->nx + g->ny + 1) * 8);
   L.lam = ALIGN;
-  L.lam2 = L.lam + align_up(((size_t)g->nx + g->ny + 1) * 8);
-  L.scratch = L.lam2 + align_up(((size_t)g->nx + g->ny + 1) * 8);
+  L.lam2 = L.lam + set;
+  L.scratch = L.lam2 + set;
   L.rxi = L.scratch;
   L.u1 = L.rxi + plane4;
   L.u2 = L.u1 + plane4;
@@ -247,6 +252,7 @@ int hip_rc(hipError_t e) { return e == hipSuccess ? WIU_OK : WIU_EHIP; }
 struct Maxima {
   const unsigned long long *lx_in = nullptr, *le_in = nullptr;
   unsigned long long *nlx = nullptr, *nle = nullptr;
+  unsigned long long* ncfl = nullptr;  // with nlx: per eta line CFL maxima of the new state (nlx + nx + ny + 1)
   unsigned long long* wm = nullptr;  // target of the separate pass (lx[ny], le[nx], cfl[1]); default the workspace's
 };
 
@@ -274,7 +280,7 @@ int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U
   }
   a.mode = mode == 2 ? 3 : 0; a.Rxi = w.rxi; a.out = out; a.U0 = U0; a.dt = dt; a.ca = ca; a.cb = cb;
   a.status = w.status;
-  a.nlam_xi = nullptr; a.nlam_eta = nullptr;
+  a.nlam_xi = nullptr; a.nlam_eta = nullptr; a.ncfl = nullptr;
   {
     ProfScope ps(WIU_K_SWEEP_XI, st);
     e = launch_sweep(scheme, 0, g_variant[0], a, st);
@@ -282,9 +288,11 @@ int residual(const wiu_grid* g, int scheme, const wiu_params* p, const double* U
   if (e != hipSuccess) return WIU_EHIP;
   a.mode = mode;
   if (mode == 2 && mx.nlx) {
-    // lx/le and cfl of one set are contiguous: lam_xi[ny], lam_eta[nx], cfl[1]
-    if (launch_fill_u64(mx.nlx, (long long)d.nx + d.ny + 1, st) != hipSuccess) return WIU_EHIP;
-    a.nlam_xi = mx.nlx; a.nlam_eta = mx.nle;
+    // one set is contiguous: lam_xi[ny], lam_eta[nx], cfl[1] (and the per-line
+    // CFL maxima[nx] when they are accumulated too)
+    const long long len = (long long)d.nx + d.ny + 1 + (mx.ncfl ? d.nx : 0);
+    if (launch_fill_u64(mx.nlx, len, st) != hipSuccess) return WIU_EHIP;
+    a.nlam_xi = mx.nlx; a.nlam_eta = mx.nle; a.ncfl = mx.ncfl;
   }
   {
     ProfScope ps(WIU_K_SWEEP_ETA, st);
@@ -458,6 +466,46 @@ int wiu_rk3_step_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double*
   }
   if (launch_cfl_dt(w.cfl, cfl, dt_dev, st) != hipSuccess) return WIU_EHIP;
   return rk3_stages(g, scheme, p, U, M, dt_dev, w.u1, w.u2, w, st, true);
+}
+
+int wiu_rk3_steps_cfl(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
+                      int nsteps, double* dt_dev, void* ws, wiu_stream_t stream) {
+  if (!grid_ok(g) || !options_ok(scheme, p) || !U || !M || !dt_dev || !ws || !(cfl > 0.0) || nsteps < 1)
+    return WIU_EINVAL;
+  Ws w = carve(g, ws);
+  hipStream_t st = (hipStream_t)stream;
+  const long long ny = g->ny, nxy = (long long)g->nx + g->ny;
+  // two maxima sets (lam_xi[ny], lam_eta[nx], cfl[1], cfl per eta line[nx]):
+  // sa holds the current state's, sb receives the next stage's; they swap
+  // roles stage by stage.  The first step's come from the separate pass (one
+  // CFL maximum), later steps' from the step before (per-line CFL maxima).
+  unsigned long long* sa = w.lx;
+  unsigned long long* sb = w.lx2;
+  {
+    ProfScope ps(WIU_K_WAVE_MAX, st);
+    if (launch_wave_max(dims(g), U, M, p->gamma, sa, sa + ny, sa + nxy, w.status, st) != hipSuccess) return WIU_EHIP;
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    double* dt = dt_dev + s;
+    if ((s == 0 ? launch_cfl_dt(sa + nxy, cfl, dt, st) : launch_cfl_dt_lines(sa + nxy + 1, g->nx, cfl, dt, st)) !=
+        hipSuccess)
+      return WIU_EHIP;
+    Maxima m1;  // U in, U1 out
+    m1.lx_in = sa; m1.le_in = sa + ny; m1.nlx = sb; m1.nle = sb + ny;
+    int rc = residual(g, scheme, p, U, M, w, 2, w.u1, U, dt, 0.0, 1.0, st, m1);
+    if (rc) return rc;
+    Maxima m2;  // U1 in, U2 out
+    m2.lx_in = sb; m2.le_in = sb + ny; m2.nlx = sa; m2.nle = sa + ny;
+    rc = residual(g, scheme, p, w.u1, M, w, 2, w.u2, U, dt, 0.75, 0.25, st, m2);
+    if (rc) return rc;
+    Maxima m3;  // U2 in; the new state's maxima and CFL maximum out, unless last
+    m3.lx_in = sa; m3.le_in = sa + ny;
+    if (s + 1 < nsteps) { m3.nlx = sb; m3.nle = sb + ny; m3.ncfl = sb + nxy + 1; }
+    rc = residual(g, scheme, p, w.u2, M, w, 2, U, U, dt, 1.0 / 3.0, 2.0 / 3.0, st, m3);
+    if (rc) return rc;
+    std::swap(sa, sb);
+  }
+  return WIU_OK;
 }
 
 size_t wiu_noalloc_bytes(const wiu_grid* g) {

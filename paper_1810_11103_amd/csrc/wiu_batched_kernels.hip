@@ -46,6 +46,7 @@ __global__ void __launch_bounds__(NA * NB, (sweep_waves<SC, OPT>())) batched_swe
     s.lam_xi = lam; s.lam_eta = lam + s.d.ny;
     unsigned long long* nlam = (DIR == 1 && st < 2) ? b.lam + ufirst(st == 0 ? B.oLam2 : B.oLam) : nullptr;
     s.nlam_xi = nlam; s.nlam_eta = nlam ? nlam + s.d.ny : nullptr;
+    s.ncfl = nullptr;
     s.gamma = b.gamma; s.alpha = b.alpha; s.eps = b.eps; s.ppm = b.ppm; s.vars = b.vars; s.ah = b.ah;
     s.weights = b.weights; s.split = b.split;
     // the block's side rules; an interface reads the neighbour's state of

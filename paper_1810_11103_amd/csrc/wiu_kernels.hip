@@ -360,6 +360,28 @@ hipError_t launch_metrics_band(const Dims& d, int scheme, double ah, int B, cons
   return hipGetLastError();
 }
 
+// One block: the maximum of n per-line CFL maxima (non-negative, so their
+// bit patterns order as the values), then dt = cfl / max.
+__global__ void __launch_bounds__(256) cfl_dt_lines_kernel(const unsigned long long* cfl_lines, int n, double cfl,
+                                                            double* dt) {
+  __shared__ unsigned long long part[4];
+  unsigned long long m = 0;
+  for (int k = threadIdx.x; k < n; k += 256) m = max(m, cfl_lines[k]);
+  for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) m = max(m, part[w]);
+    m = max(m, part[0]);
+    dt[0] = cfl / __longlong_as_double((long long)m);
+  }
+}
+
+hipError_t launch_cfl_dt_lines(const unsigned long long* cfl_lines, int n, double cfl, double* dt, hipStream_t st) {
+  hipLaunchKernelGGL(cfl_dt_lines_kernel, dim3(1), dim3(256), 0, st, cfl_lines, n, cfl, dt);
+  return hipGetLastError();
+}
+
 hipError_t launch_cfl_dt(const unsigned long long* cfl_max, double cfl, double* dt, hipStream_t st) {
   hipLaunchKernelGGL(cfl_dt_kernel, dim3(1), dim3(64), 0, st, cfl_max, cfl, dt);
   return hipGetLastError();

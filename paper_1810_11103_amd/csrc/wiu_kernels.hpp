@@ -47,6 +47,10 @@ struct SweepArgs {
   // state are accumulated here (cleared beforehand) for the next stage
   unsigned long long* nlam_xi;
   unsigned long long* nlam_eta;
+  // with them, when set: per eta line (column i, nx entries, cleared
+  // beforehand) the CFL maximum of the new state, max over the line's nodes
+  // of (s_xi + s_eta) / J^{-1} as the separate maxima pass forms it
+  unsigned long long* ncfl;
 };
 
 // One block of a batched multi-block problem (device table entry).  The
@@ -151,6 +155,8 @@ hipError_t launch_group_max(unsigned long long* lam, const int* start, const int
 void* prof_open(int id, hipStream_t st);
 void prof_close(void* h);
 hipError_t launch_cfl_dt(const unsigned long long* cfl_max, double cfl, double* dt, hipStream_t st);
+// dt = cfl / max of n per-line CFL maxima
+hipError_t launch_cfl_dt_lines(const unsigned long long* cfl_lines, int n, double cfl, double* dt, hipStream_t st);
 hipError_t launch_lambda_out(const Dims& d, double alpha, const unsigned long long* lx, const unsigned long long* le,
                              double* ox, double* oe, hipStream_t st);
 hipError_t launch_set_tag(const Dims& d, int scheme, double ah, double* M, hipStream_t st);

@@ -155,7 +155,7 @@ WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB, OPT>& L
                              int tb, const OutOperands& op) {
   static_assert(64 % NB == 0 && (NA * NB) % 64 == 0, "eta tile must pack whole waves");
   const Dims& d = s.d;
-  double sx = 0.0, se = 0.0;
+  double sx = 0.0, se = 0.0, cf = 0.0;
   bool bad = false;
   if (act) {
     double R[4];
@@ -175,6 +175,7 @@ WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB, OPT>& L
     bad = w.bad || !(sxr < 1.0e300) || !(ser < 1.0e300);
     sx = fmax(0.0, sxr);
     se = fmax(0.0, ser);
+    if (s.ncfl) cf = fmax(0.0, (sx + ser) / op.jinv);
   }
   if (bad) atomicOr(s.status, ST_NONPHYS);
   // eta line (column) maxima: reduce over the positions of the wave
@@ -184,6 +185,10 @@ WIU_DEV void fused_stage_out(const SweepArgs& s, SweepLds<SC, 1, NA, NB, OPT>& L
   const int lane = (threadIdx.x + NB * threadIdx.y) & 63;
   if (lane < NB && line < d.nx) atomicMax(&s.nlam_eta[line], (unsigned long long)__double_as_longlong(se));
   if (tb == 0 && act) atomicMax(&s.nlam_xi[i], (unsigned long long)__double_as_longlong(sx));
+  if (s.ncfl) {  // CFL maximum per eta line, reduced as the eta maxima
+    for (int off = NB; off < 64; off <<= 1) cf = fmax(cf, __shfl_xor(cf, off, 64));
+    if (lane < NB && line < d.nx) atomicMax(&s.ncfl[line], (unsigned long long)__double_as_longlong(cf));
+  }
 }
 
 // One tile of a sweep: logical tile (bxl, byl) = (segment along the line,

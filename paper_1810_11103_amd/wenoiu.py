@@ -27,7 +27,7 @@ EXPORTS = [
     "wiu_batched_rk3_step", "wiu_batched_status", "wiu_plan_destroy", "wiu_blocks_metrics_work_size",
     "wiu_blocks_metrics", "wiu3_metrics_size", "wiu3_workspace_bytes", "wiu3_metrics", "wiu3_rhs", "wiu3_cfl_dt",
     "wiu3_rk3_step", "wiu3_rk3_step_cfl",
-    "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl", "wiu_step_record_bytes",
+    "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl", "wiu_rk3_steps_cfl", "wiu_step_record_bytes",
     "wiu_noalloc_bytes", "wiu_rk3_step_noalloc",
 ]
 KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3, "sweep3": 4}
@@ -78,6 +78,7 @@ def _load():
         "wiu_cfl_dt": (I, [G, PR, P, P, ctypes.c_double, P, P, P]),
         "wiu_rk3_step": (I, [G, I, PR, P, P, P, P, P]),
         "wiu_rk3_step_cfl": (I, [G, I, PR, P, P, ctypes.c_double, P, P, P]),
+        "wiu_rk3_steps_cfl": (I, [G, I, PR, P, P, ctypes.c_double, I, P, P, P]),
         "wiu_noalloc_bytes": (ctypes.c_size_t, [G]),
         "wiu_rk3_step_noalloc": (I, [G, I, PR, P, P, P, P, P]),
         "wiu_status": (I, [P, P, ctypes.POINTER(I), I]),
@@ -261,6 +262,17 @@ def rk3_step_cfl(grid, scheme, params, U, M, cfl, dt_dev, ws, stream=None):
     return U
 
 
+def rk3_steps_cfl(grid, scheme, params, U, M, cfl, nsteps, dt_dev, ws, stream=None):
+    """nsteps RK3 steps, each at the CFL time step of its state; dt_dev
+    (float64, >= nsteps entries) receives the step sizes."""
+    if dt_dev.numel() < nsteps or dt_dev.dtype != torch.float64 or not dt_dev.is_contiguous():
+        raise ValueError("dt_dev: a contiguous float64 tensor of at least nsteps entries")
+    _check(lib.wiu_rk3_steps_cfl(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U), _ptr(M),
+                                 float(cfl), int(nsteps), _ptr(dt_dev), ctypes.c_void_p(ws.data_ptr()),
+                                 _stream(stream)))
+    return U
+
+
 def noalloc_bytes(grid):
     return lib.wiu_noalloc_bytes(ctypes.byref(grid))
 
@@ -370,6 +382,13 @@ class Solver:
     def rk3_step_cfl(self, U, cfl):
         """CFL time step of U (into self.dt) and one RK3 step of that size."""
         return rk3_step_cfl(self.grid, self.scheme, self.params, U, self.M, cfl, self.dt, self.ws)
+
+    def rk3_steps_cfl(self, U, cfl, nsteps, dts=None):
+        """nsteps CFL-limited RK3 steps in one call; returns the device
+        tensor of the step sizes (dts, or a new one)."""
+        dts = torch.empty(int(nsteps), dtype=torch.float64, device=self.device) if dts is None else dts
+        rk3_steps_cfl(self.grid, self.scheme, self.params, U, self.M, cfl, int(nsteps), dts, self.ws)
+        return dts
 
     def rhs_vjp(self, U, Gbar, out=None):
         out = torch.empty_like(U) if out is None else out

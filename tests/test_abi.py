@@ -94,6 +94,10 @@ def test_bad_scheme_params_and_pointers_rejected(wiu):
     assert wiu.lib.wiu_metrics(ctypes.byref(g), -1, None, dummy, dummy, dummy, dummy, None) == wiu.WIU_EINVAL
     assert wiu.lib.wiu_cfl_dt(ctypes.byref(g), ctypes.byref(p), dummy, dummy, ctypes.c_double(-1.0), dummy, dummy,
                               None) == wiu.WIU_EINVAL
+    # several CFL-limited steps: at least one step, a positive CFL number
+    for n, c in ((0, 0.5), (-3, 0.5), (2, 0.0)):
+        assert wiu.lib.wiu_rk3_steps_cfl(ctypes.byref(g), 3, ctypes.byref(p), dummy, other, ctypes.c_double(c), n,
+                                         ctypes.c_void_p(768), ctypes.c_void_p(1024), None) == wiu.WIU_EINVAL
     assert wiu.lib.wiu_strerror(wiu.WIU_EINVAL) == b"invalid argument"
 
 

@@ -312,6 +312,81 @@ def test_rk3_step_cfl_equals_cfl_dt_then_step(wiu):
     assert sol.status() == 0
 
 
+STEPS_CASES = [
+    ("5-2MP", "riemann", None, {}),
+    ("3-1MP", "vortex", None, {}),
+    ("7-4MP", "riemann", None, {}),
+    ("5-2MP", "riemann", ("wall", "transmissive", "wall", "wall"), {}),
+    ("5-1MP", "riemann", None, dict(vars="conservative", alpha_h=0.8)),
+]
+
+
+@pytest.mark.parametrize("s,kind,sides,opts", STEPS_CASES)
+def test_rk3_steps_cfl_equals_single_steps(wiu, s, kind, sides, opts):
+    """Several CFL-limited steps in one call give bitwise the states and time
+    steps of as many wiu_rk3_step_cfl calls: the line eigenvalues and CFL
+    maximum that the last stage's eta sweep accumulates for the next step
+    equal those of the separate maxima pass."""
+    say("rk3_steps_cfl vs single steps", s, kind, sides, opts)
+    g, U = make_case(kind, 301, 203, seed=8) if kind == "riemann" else make_case(kind, 300, 70, seed=8)
+    sol = wiu.Solver(g.x, g.y, s, g.bc, g.period, params=wiu.make_params(**opts), sides=sides)
+    Ua, Ub = _dev(U), _dev(U)
+    dts = []
+    for _ in range(4):
+        sol.rk3_step_cfl(Ua, 0.5)
+        dts.append(float(sol.dt.item()))
+    got = _host(sol.rk3_steps_cfl(Ub, 0.5, 4)).tolist()
+    assert sol.status() == 0
+    assert got == dts
+    assert np.array_equal(_host(Ua), _host(Ub))
+    one = sol.rk3_steps_cfl(Ub, 0.5, 1)  # a single step: the separate pass only
+    sol.rk3_step_cfl(Ua, 0.5)
+    assert float(one[0].item()) == float(sol.dt.item())
+    assert np.array_equal(_host(Ua), _host(Ub))
+
+
+def test_rk3_steps_cfl_across_tile_shapes(wiu):
+    """The CFL maximum reduced in the eta tiles does not depend on their
+    lane layout (2 to 16 lines per wave): same steps for every eta shape."""
+    g, U = make_case("riemann", 301, 203, seed=9)
+    saved = wiu.get_tuning(1)
+    try:
+        sol = wiu.Solver(g.x, g.y, "5-2MP", g.bc, g.period)
+        ref = None
+        for ve in range(wiu.tuning_variants(1)):
+            wiu.set_tuning(1, ve)
+            Ud = _dev(U)
+            dts = _host(sol.rk3_steps_cfl(Ud, 0.5, 3))
+            out = (_host(Ud), dts)
+            if ref is None:
+                ref = out
+            else:
+                assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), ve
+        assert sol.status() == 0
+    finally:
+        wiu.set_tuning(1, saved)
+
+
+def test_rk3_steps_cfl_track_oracle(orc, wiu):
+    """Three CFL-limited steps in one call against the oracle's CFL rule and
+    RK3 step applied three times (ragged transmissive Riemann grid)."""
+    g, U = make_case("riemann", 260, 90, seed=10)
+    Mo = orc.metrics("5-2MP", g.x, g.y, g.bc, g.period)
+    ref = U.copy()
+    ref_dts = []
+    for _ in range(3):
+        dt = orc.cfl_dt(ref, Mo, 0.5)
+        ref_dts.append(dt)
+        ref = orc.rk3_step("5-2MP", ref, Mo, dt, g.bc)
+    sol = wiu.Solver(g.x, g.y, "5-2MP", g.bc, g.period)
+    Ud = _dev(U)
+    dts = _host(sol.rk3_steps_cfl(Ud, 0.5, 3))
+    assert sol.status() == 0
+    assert np.allclose(dts, ref_dts, rtol=1e-12, atol=0.0), (dts, ref_dts)
+    err = normwise(_host(Ud) - U, ref - U)
+    assert np.all(err <= 1e-11), err
+
+
 def test_rk3_step_identical_across_tile_shapes(wiu):
     """RK3 steps are bitwise the same for every pair of tile shapes: the eta
     tiles reduce the next stage's line maxima over their own lane layout

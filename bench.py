@@ -375,6 +375,25 @@ def adjoint_leg(n=512, nsteps=400, cfl=0.5, fd_check=True):
         fd = (run(eps0 + h, False, 20)[0] - run(eps0 - h, False, 20)[0]) / (2 * h)
         res["fd_dJ_deps"] = fd
         res["fd_rel_err"] = abs(fd - res["stored"]["dJ_deps"]) / abs(fd)
+        # gradient in the initial state against central differences along
+        # three seeded Gaussian bumps centred within r <= 3 of the vortex
+        U0 = AG.vortex_state_torch(x, y, torch.tensor(eps0, dtype=torch.float64, device="cuda")).detach()
+        Ud = U0.clone().requires_grad_(True)
+        AG.density_objective(AG.rollout(Ud, sol, nsteps, dt, every=20)).backward()
+        rng = np.random.default_rng(524)
+        errs = []
+        for _ in range(3):
+            r, th = 3.0 * math.sqrt(rng.uniform()), rng.uniform(0.0, 2.0 * math.pi)
+            cx, cy = 5.0 + r * math.cos(th), 5.0 + r * math.sin(th)
+            b = torch.exp(-((x - cx) ** 2 + (y - cy) ** 2) / 0.8)
+            V = torch.stack([b, 0.3 * b, -0.2 * b, 1.5 * b]).contiguous()
+            Jp = AG.density_objective(AG.rollout(U0 + h * V, sol, nsteps, dt, every=20)).item()
+            Jm = AG.density_objective(AG.rollout(U0 - h * V, sol, nsteps, dt, every=20)).item()
+            fdv = (Jp - Jm) / (2 * h)
+            an = float((Ud.grad * V).sum())
+            errs.append(abs(an - fdv) / abs(fdv))
+        res["fd_bumps_rel_err"] = errs
+        res["status"] |= sol.status()
     return res
 
 

@@ -35,8 +35,8 @@ WIU_DEV void weno5_vjp(double a, double b, double d, double e, double eps, int p
   for (int k = 0; k < 3; ++k) {
     w[k] = al[k] * r;
     dw[k] = w[k] - C[k];
-    h[k] = (dw[k] > 0.0 ? KH[k] : KL[k]) * dw[k];  // K d
-    g[k] = ppm ? fma(dw[k] * dw[k], h[k], C[k]) : w[k];
+    h[k] = kd(dw[k], KL[k], KH[k]);  // K d, as the forward sweep forms it
+    g[k] = ppm ? fma(dw[k], fma(dw[k], h[k], -1.0), w[k]) : w[k];  // C + K d^3
   }
   const double sg = g[0] + g[1] + g[2];
   const double rs = rcp(sg);
@@ -100,8 +100,8 @@ WIU_DEV void weno3_vjp(double a, double b, double d, double eps, int ppm, double
   for (int k = 0; k < 2; ++k) {
     w[k] = al[k] * r;
     dw[k] = w[k] - C[k];
-    h[k] = (dw[k] > 0.0 ? KH[k] : KL[k]) * dw[k];  // K d
-    g[k] = ppm ? fma(dw[k], h[k], C[k]) : w[k];
+    h[k] = kd(dw[k], KL[k], KH[k]);  // K d, as the forward sweep forms it
+    g[k] = ppm ? fma(dw[k], h[k] - 1.0, w[k]) : w[k];  // C + K d^2
   }
   const double sg = g[0] + g[1];
   const double rs = rcp(sg);

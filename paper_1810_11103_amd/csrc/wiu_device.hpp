@@ -42,8 +42,13 @@ WIU_DEV void two_sum(double a, double b, double& s, double& e) {
 
 WIU_DEV int bc_index(int k, int n, int bc) {
   if (bc == 0) {
-    while (k < 0) k += n;
-    while (k >= n) k -= n;
+    // one period covers every stencil reach on lines at least as long as
+    // it; shorter periodic lines take the remainder
+    k = k < 0 ? k + n : (k >= n ? k - n : k);
+    if (k < 0 || k >= n) {
+      k %= n;
+      if (k < 0) k += n;
+    }
     return k;
   }
   return k < 0 ? 0 : (k >= n ? n - 1 : k);
@@ -184,13 +189,15 @@ WIU_DEV double kd(double d, double Klo, double Khi) {
   if (fabs(Klo) >= fabs(Khi)) return fma(Klo - Khi, fmin(d, 0.0), Khi * d);
   return fma(Khi - Klo, fmax(d, 0.0), Klo * d);
 }
+// Each mapping returns C + K d^n as w + d (K d^(n-1) - 1), which needs no
+// copy of C beside -C (the -1 is an inline constant).
 WIU_DEV double map3(double w, double C, double Klo, double Khi) {
   const double d = w - C;
-  return fma(d * d, kd(d, Klo, Khi), C);
+  return fma(d, fma(d, kd(d, Klo, Khi), -1.0), w);
 }
 WIU_DEV double map2(double w, double C, double Klo, double Khi) {
   const double d = w - C;
-  return fma(d, kd(d, Klo, Khi), C);
+  return fma(d, kd(d, Klo, Khi) - 1.0, w);
 }
 
 // (K_lo, K_hi) of the mappings for the linear weights of Table 1.
@@ -288,7 +295,7 @@ WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
 // d <= 0 and 1/(1-C)^3 above.
 WIU_DEV double map4(double w, double C, double Klo, double Khi) {
   const double d = w - C;
-  return fma(d * d, kd(d, Klo, Khi) * d, C);
+  return fma(d, fma(d * d, kd(d, Klo, Khi), -1.0), w);
 }
 //   C = 1/64, 21/64, 35/64, 7/64: K_lo = -(64/(64 C))^3, K_hi = (64/(64 - 64 C))^3
 #define WIU_M4L0 (-262144.0)

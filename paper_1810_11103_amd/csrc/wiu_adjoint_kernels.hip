@@ -206,11 +206,25 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
   const bool xfold = DIR == 1 && s.x_lam_part != nullptr;
   if (xfold && tb == 0 && ta < out) {
     const int row = o0 + ta;
+    const double* lp = s.x_lam_part + (long long)row * s.x_nseg;
+    const int* ap = s.x_arg_part + (long long)row * s.x_nseg;
     double sum = 0.0;
     int kf = INT_MAX;
-    for (int t = 0; t < s.x_nseg; ++t) {
-      sum += s.x_lam_part[(long long)row * s.x_nseg + t];
-      kf = min(kf, s.x_arg_part[(long long)row * s.x_nseg + t]);
+    // eight segments' loads in flight at a time, then their sum in order
+    for (int t0 = 0; t0 < s.x_nseg; t0 += 8) {
+      double v[8];
+      int a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = t0 + u < s.x_nseg;
+        v[u] = in ? lp[t0 + u] : 0.0;
+        a[u] = in ? ap[t0 + u] : INT_MAX;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (t0 + u < s.x_nseg) sum += v[u];
+        kf = min(kf, a[u]);
+      }
     }
     L.xlb[ta] = sum;
     L.xks[ta] = kf;
@@ -222,12 +236,15 @@ __global__ void __launch_bounds__(NA * NB, 2) adj_sweep_kernel(AdjArgs s) {
   // line-eigenvalue adjoint of this tile (fixed-order sum over its items) and
   // its first node attaining the line maximum
   if (ta == 0) {
-    double sum = 0.0;
+    // four interleaved partial sums (fixed association, shorter dependence chain)
+    double sum4[4] = {0.0, 0.0, 0.0, 0.0};
     int kf = INT_MAX;
+#pragma unroll
     for (int t = 0; t < NA; ++t) {
-      sum += L.lb[LT::si(tb, t)];
+      sum4[t & 3] += L.lb[LT::si(tb, t)];
       kf = min(kf, L.ka[LT::si(tb, t)]);
     }
+    const double sum = (sum4[0] + sum4[1]) + (sum4[2] + sum4[3]);
     s.lam_part[(long long)line * nseg + seg] = sum;
     s.arg_part[(long long)line * nseg + seg] = kf;
   }

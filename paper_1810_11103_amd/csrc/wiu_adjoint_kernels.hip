@@ -338,28 +338,44 @@ __global__ void __launch_bounds__(256) adj_fixup_kernel(AdjArgs s, int dir, int 
     const int p = g < NGHOST_ADJ ? -1 - g : n_al + (g - NGHOST_ADJ);
     return bc_index(p, n_al, bc_al);
   };
-  // Lanes 0 .. NG-1 own the ghost targets (the first lane of each distinct
-  // target).  Their ghost contributions and the current Ubar there are
-  // loaded first, so those loads overlap the reduction below.
-  int t = -1;
-  bool own = false;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0}, ub[4] = {0.0, 0.0, 0.0, 0.0};
+  // Lane g < NG holds ghost position g: its target node tg and contribution
+  // gv (all loaded at once).  The first lane of each distinct target owns
+  // it and sums the contributions of every lane with that target in lane
+  // order, read across the wave; the owners' current Ubar is loaded at once
+  // too, so these loads overlap the reduction below.
+  int tg = -1;
+  double gv[4] = {0.0, 0.0, 0.0, 0.0};
   if (lane < NG) {
-    t = target(lane);
-    own = true;
-    for (int g = 0; g < lane; ++g) own = own && target(g) != t;
-    if (own) {
-      for (int g = 0; g < NG; ++g) {
-        if (target(g) != t) continue;
-        const double* gb =
-            s.ghost + (((long long)line * 2 + (g < NGHOST_ADJ ? 0 : 1)) * NGHOST_ADJ + g % NGHOST_ADJ) * 4;
+    tg = target(lane);
+    const double* gb =
+        s.ghost + (((long long)line * 2 + (lane < NGHOST_ADJ ? 0 : 1)) * NGHOST_ADJ + lane % NGHOST_ADJ) * 4;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] += gb[c];
-      }
-      const long long o = dir == 0 ? (long long)line * d.nx + t : (long long)t * d.nx + line;
+    for (int c = 0; c < 4; ++c) gv[c] = gb[c];
+  }
+  int t = lane < NG ? tg : -1;
+  bool own = lane < NG;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0}, ub[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int c = 0; c < 4; ++c) ub[c] = s.Ubar[c * d.np + o];
+  for (int g = 0; g < NG; ++g) {  // lane g's values, read into scalar registers
+    const int tgg = __builtin_amdgcn_readlane(tg, g);
+    double gg[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const long long bits = __double_as_longlong(gv[c]);
+      const unsigned lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), g);
+      const unsigned hi = __builtin_amdgcn_readlane((int)(bits >> 32), g);
+      gg[c] = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
     }
+    if (lane < NG && tgg == t) {
+      if (g < lane) own = false;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] += gg[c];
+    }
+  }
+  if (own) {
+    const long long o = dir == 0 ? (long long)line * d.nx + t : (long long)t * d.nx + line;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ub[c] = s.Ubar[c * d.np + o];
   }
   // eigenvalue adjoint and first maximal node over the line's segments
   double lb = 0.0;

@@ -251,6 +251,24 @@ def test_full_size_riemann_parity(orc, wiu):
     assert sol.status() == 0
 
 
+def test_full_size_steps_cfl_equal_single_steps(wiu):
+    """The timed configuration: several CFL-limited steps per call on the
+    2048^2 randomized Riemann workload (A = 0.2, seed 2048), bitwise equal to
+    one wiu_rk3_step_cfl call per step, states and time steps."""
+    say("full-size: rk3_steps_cfl against single steps")
+    g, U = W.riemann_problem(2048, A=0.2, seed=2048)
+    sol = wiu.Solver(g.x, g.y, "5-2MP", g.bc, g.period)
+    Ua, Ub = _dev(U), _dev(U)
+    dts = []
+    for _ in range(3):
+        sol.rk3_step_cfl(Ua, 0.5)
+        dts.append(float(sol.dt.item()))
+    got = _host(sol.rk3_steps_cfl(Ub, 0.5, 3)).tolist()
+    assert sol.status() == 0
+    assert got == dts
+    assert np.array_equal(_host(Ua), _host(Ub))
+
+
 def test_tile_shapes_give_identical_results(wiu):
     """Every compiled tile shape of both sweeps gives bitwise the same rhs
     (each item is computed by the same code whatever the tiling)."""

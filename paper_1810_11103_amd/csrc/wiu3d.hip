@@ -9,8 +9,9 @@
 // A direction pass is one LDS-tiled sweep (states staged once, one item per
 // lane, item records in LDS, the flux difference and the stage update in the
 // same kernel), with lanes along i wherever global memory is touched so
-// loads and stores coalesce whatever the line direction; the pass over the
-// last direction writes dU/dt or the RK stage.
+// loads and stores coalesce whatever the line direction.  The passes run
+// zeta, eta, xi: the xi pass, whose lines are contiguous in memory, writes
+// dU/dt or the RK stage (and, in stages 1 and 2, the next stage's maxima).
 #include "wenoiu.h"
 #include "wiu_kernels.hpp"
 
@@ -461,7 +462,7 @@ struct S3Args {
   const double* U;                 // state the fluxes are built from
   const double* M;
   const unsigned long long* lam;   // line maxima: xi lines [ny nz], eta [nx nz], zeta [nx ny]
-  unsigned long long* nlam;        // zeta pass of an RK stage: the next stage's maxima (or null)
+  unsigned long long* nlam;        // xi pass of an RK stage: the next stage's maxima (or null)
   double gamma, alpha, eps;
   int ppm;
   int vars;                        // WIU_VARS_* (interpolation variables)
@@ -508,6 +509,7 @@ template <int SC, int DIR, int NA, int NB, bool OPT = false> struct Sweep3Lds {
   static constexpr int NREC = OPT ? 20 : 15;
   double sh[NREC][NA * NB];
   double sq[5][NB * NQ];
+  double red[DIR == 0 ? NA * NB : 1];  // xi tiles: the next stage's eta speeds, reduced over the lines
   static WIU_DEV int si(int tb, int ta) { return DIR == 0 ? tb * NA + ta : ta * NB + tb; }
   static WIU_DEV int qi(int tb, int pos) { return DIR == 0 ? tb * NQ + pos : pos * NB + tb; }
 };
@@ -519,7 +521,8 @@ template <int SC, int DIR, int NA, int NB, bool OPT = false> struct Sweep3Lds {
 // (nodal flux at k and both side fluxes at k + 1/2), then the first OUT
 // lanes of each line form H_{i+1/2} - H_{i-1/2} and, by `mode`: 0 Racc = R;
 // 1 Racc += R; 2 dU/dt = -(Racc + R)/J^{-1}; 3 the RK stage
-// U_out = ca U0 + cb (U + dt dU/dt).  Four block-wide barriers on every path.
+// U_out = ca U0 + cb (U + dt dU/dt).  Four block-wide barriers on every path
+// (five in an xi pass that accumulates the next stage's maxima).
 // OPT: compiled with the scheme options (a.vars, a.ah, a.weights); without
 // it the sweep runs the paper's configuration and carries no code for them.
 template <int SC, int DIR, int NA, int NB, bool OPT>
@@ -686,7 +689,7 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
   double km[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) km[c] = 0.0;
-  const bool fused = DIR == 2 && mode == 3 && a.nlam != nullptr;  // uniform over the grid
+  const bool fused = DIR == 0 && mode == 3 && a.nlam != nullptr;  // uniform over the grid
   if (fused && act) {
     int p[3];
     node(i, la, p);
@@ -732,14 +735,14 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
     }
     __syncthreads();
   }
-  if constexpr (DIR == 2) {
+  if constexpr (DIR == 0) {
     if (fused) {
       // RK stage with the next stage's line maxima (Sec. 2.3), every lane
-      // taking part in the reductions: lanes of a wave are NB lines along i
-      // (fast) by 64/NB positions along k.  Wave speeds as in the separate
-      // maxima pass (same routine, clamped at zero), so the maxima are
-      // bit-identical to it.
-      static_assert(64 % NB == 0 && (NA * NB) % 64 == 0, "zeta tile must pack whole waves");
+      // taking part in the reductions: a wave is one line (j, k) along i, the
+      // tile's NB lines are consecutive j at one k.  Wave speeds as in the
+      // separate maxima pass (same routine, clamped at zero), so the maxima
+      // are bit-identical to it.
+      static_assert(NA == 64, "xi tile: one line per wave");
       double sx = 0.0, se = 0.0, sz = 0.0;
       bool bad = false;
       if (act) {
@@ -768,20 +771,23 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
         sz = fmax(0.0, sp[2]);
       }
       if (bad) atomicOr(a.status, ST_NONPHYS);
-      const int j = cb;
       unsigned long long* lx = a.nlam;
       unsigned long long* le = lx + (long long)d.n[1] * d.n[2];
       unsigned long long* lz = le + (long long)d.n[0] * d.n[2];
-      // eta lines (i, k): one node of the tile each
-      if (act) atomicMax(&le[(long long)i * d.n[0] + la], (unsigned long long)__double_as_longlong(se));
-      // xi lines (j, k): reduce over the lines of the wave (along i)
-      for (int off = 1; off < NB; off <<= 1) sx = fmax(sx, __shfl_xor(sx, off, 64));
-      if (tb == 0 && live && ta < out)
-        atomicMax(&lx[(long long)i * d.n[1] + j], (unsigned long long)__double_as_longlong(sx));
-      // zeta lines (i, j): reduce over the positions of the wave (along k)
-      for (int off = NB; off < 64; off <<= 1) sz = fmax(sz, __shfl_xor(sz, off, 64));
-      const int lane = (threadIdx.x + NB * threadIdx.y) & 63;
-      if (lane < NB && live) atomicMax(&lz[(long long)j * d.n[0] + la], (unsigned long long)__double_as_longlong(sz));
+      // xi lines (j, k): reduce over the wave (along i)
+      for (int off = 32; off > 0; off >>= 1) sx = fmax(sx, __shfl_xor(sx, off, 64));
+      if (ta == 0 && live) atomicMax(&lx[(long long)cb * d.n[1] + la], (unsigned long long)__double_as_longlong(sx));
+      // zeta lines (i, j): one node of the tile each
+      if (act) atomicMax(&lz[(long long)la * d.n[0] + i], (unsigned long long)__double_as_longlong(sz));
+      // eta lines (i, k): reduce over the tile's lines
+      L.red[LT::si(tb, ta)] = se;
+      __syncthreads();
+      if (tb == 0 && ta < out) {
+        double m = L.red[LT::si(0, ta)];
+#pragma unroll
+        for (int l = 1; l < NB; ++l) m = fmax(m, L.red[LT::si(l, ta)]);
+        atomicMax(&le[(long long)cb * d.n[0] + i], (unsigned long long)__double_as_longlong(m));
+      }
       return;
     }
   }
@@ -1039,7 +1045,7 @@ static int rk3_3d(const wiu_grid3* g, int scheme, const wiu_params* p, double* U
   const double* src[3] = {U, U1, U2};
   double* dst[3] = {U1, U2, U};
   const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0};
-  // the first stage's maxima from a separate pass; the zeta pass of stages 1
+  // the first stage's maxima from a separate pass; the xi pass of stages 1
   // and 2 accumulates the next stage's into the other buffer
   unsigned long long* lbuf[2] = {(unsigned long long*)(base + w.lam), (unsigned long long*)(base + w.lam2)};
   if (maxima3(d, U, M, p->gamma, lbuf[0], w.nlam, a.status, st) != hipSuccess) return WIU_EHIP;
@@ -1049,9 +1055,10 @@ static int rk3_3d(const wiu_grid3* g, int scheme, const wiu_params* p, double* U
     a.lam = lbuf[s & 1];
     unsigned long long* next = s < 2 ? lbuf[(s + 1) & 1] : nullptr;
     if (next && launch_fill_u64(next, w.nlam, st) != hipSuccess) return WIU_EHIP;
-    for (int D = 0; D < 3; ++D) {
-      a.nlam = D == 2 ? next : nullptr;
-      if (pass3(scheme, a, D, D == 0 ? 0 : (D == 1 ? 1 : 3), st) != hipSuccess) return WIU_EHIP;
+    for (int q = 0; q < 3; ++q) {  // zeta, eta, then xi, which writes the stage state
+      const int D = 2 - q;
+      a.nlam = D == 0 ? next : nullptr;
+      if (pass3(scheme, a, D, q == 0 ? 0 : (q == 1 ? 1 : 3), st) != hipSuccess) return WIU_EHIP;
     }
   }
   return WIU_OK;
@@ -1107,8 +1114,8 @@ int wiu3_rhs(const wiu_grid3* g, int scheme, const wiu_params* p, const double* 
   options3(p, a);
   a.U0 = nullptr; a.dt = nullptr; a.ca = 0.0; a.cb = 1.0; a.status = (int*)base;
   if (maxima3(d, U, M, p->gamma, (unsigned long long*)a.lam, w.nlam, a.status, st) != hipSuccess) return WIU_EHIP;
-  for (int D = 0; D < 3; ++D)
-    if (pass3(scheme, a, D, D == 0 ? 0 : (D == 1 ? 1 : 2), st) != hipSuccess) return WIU_EHIP;
+  for (int q = 0; q < 3; ++q)  // zeta, eta, then xi, which writes dU/dt
+    if (pass3(scheme, a, 2 - q, q == 0 ? 0 : (q == 1 ? 1 : 2), st) != hipSuccess) return WIU_EHIP;
   return WIU_OK;
 }
 

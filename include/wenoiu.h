@@ -255,6 +255,18 @@ size_t wiu_step_record_bytes(const wiu_grid* g);
 int wiu_rk3_step_stages(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
                         const double* dt_dev, double* U1, double* U2, void* rec, void* ws, wiu_stream_t stream);
 
+/* nsteps (>= 1) steps of wiu_rk3_step_stages in one call, for the stored
+ * stages of a differentiated time integration: step s copies its U_n to
+ * stages[s][0] and writes U1, U2 to stages[s][1], stages[s][2] (stages:
+ * caller-owned [nsteps][3][4][ny][nx]) and its step record to recs[s]
+ * (caller-owned, nsteps records of wiu_step_record_bytes, required); U
+ * advances in place by nsteps steps of size *dt_dev.  States and the line
+ * maxima of the records are those of nsteps wiu_rk3_step_stages calls bit
+ * for bit; only the first step has a separate maxima pass, later steps take
+ * the line maxima of their U_n from the last stage of the step before. */
+int wiu_rk3_steps_stages(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
+                         const double* dt_dev, int nsteps, double* stages, void* recs, void* ws, wiu_stream_t stream);
+
 /* Ubar_n = (d U^{n+1} / d U^n)^T Ubar_np1 for one RK3 step of size *dt_dev
  * from U_n.  U1, U2: the stored stage states, or both NULL to recompute them;
  * rec: the step record written with them, or NULL (requires U1, U2 when set;

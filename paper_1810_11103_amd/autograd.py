@@ -12,6 +12,9 @@ Two ways to have the stage states at hand in the backward pass:
               last segment's stage states are the forward pass's own (kept
               as it runs them), so the backward pass starts with adjoints
               while the next segment is recomputed beside it.
+The stage-storing steps of a segment (or of the whole rollout) run as one
+library call (wiu_rk3_steps_stages), whose steps after the first take their
+line maxima from the step before.
 rollout(every="auto") stores everything when 3 N states fit in the given
 fraction of free device memory, else checkpoints every ~sqrt(N/3) steps,
 which minimises N/k + 3k.  Metrics and the time step are held fixed (no
@@ -30,26 +33,25 @@ class RK3Rollout(torch.autograd.Function):
         U = U0.detach().clone().contiguous()
         solver.dt.fill_(float(dt))
         ckpts, stages, recs = [], None, None
+        if nsteps <= 0:
+            every = 0
         if every == 0:  # one allocation for all (U_n, U1, U2), and their step records
-            stages = torch.empty((nsteps, 3) + tuple(U.shape), dtype=U.dtype, device=U.device)
-            recs = solver.step_record(nsteps)
+            stages = torch.empty((max(nsteps, 0), 3) + tuple(U.shape), dtype=U.dtype, device=U.device)
+            recs = solver.step_record(max(nsteps, 0))
         else:  # the last segment's stages and step records
             first_last = (nsteps - 1) // every * every
             stages = torch.empty((nsteps - first_last, 3) + tuple(U.shape), dtype=U.dtype, device=U.device)
             recs = solver.step_record(nsteps - first_last)
-        for s in range(nsteps):
-            if every == 0:
-                stages[s, 0].copy_(U)
-                solver.rk3_step_stages(U, stages[s, 1], stages[s, 2], rec=recs[s])
-            else:
+        if every == 0:
+            if nsteps > 0:
+                solver.rk3_steps_stages(U, stages, recs)  # all steps in one call
+        else:
+            for s in range(first_last):
                 if s % every == 0:
                     ckpts.append(U.clone())
-                if s >= first_last:
-                    i = s - first_last
-                    stages[i, 0].copy_(U)
-                    solver.rk3_step_stages(U, stages[i, 1], stages[i, 2], rec=recs[i])
-                else:
-                    solver.rk3_step(U)
+                solver.rk3_step(U)
+            ckpts.append(U.clone())  # the last segment's start, kept with its stages
+            solver.rk3_steps_stages(U, stages, recs)
         ctx.solver, ctx.nsteps, ctx.dt, ctx.every = solver, nsteps, float(dt), every
         ctx.ckpts, ctx.stages, ctx.recs = ckpts, stages, recs
         return U
@@ -92,9 +94,8 @@ def _checkpointed_backward(ctx, Ub):
                 side.wait_event(freed[seg + 2])  # its buffer set was last used by segment seg+2
             B, U = bufs[seg % 2], work[seg % 2]
             U.copy_(ckpts[seg])
-            for i in range(min(nsteps, (seg + 1) * every) - seg * every):
-                B[i, 0].copy_(U)
-                solver.rk3_step_stages(U, B[i, 1], B[i, 2], ws=ws2, rec=recs[seg % 2, i])
+            n = min(nsteps, (seg + 1) * every) - seg * every
+            solver.rk3_steps_stages(U, B[:n], recs[seg % 2, :n], ws=ws2)
             ready[seg].record(side)
 
     for seg in reversed(range(nseg)):

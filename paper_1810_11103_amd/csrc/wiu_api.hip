@@ -557,6 +557,44 @@ int wiu_rk3_step_stages(const wiu_grid* g, int scheme, const wiu_params* p, doub
   return rk3_stages(g, scheme, p, U, M, dt_dev, U1, U2, w, (hipStream_t)stream, false, (unsigned long long*)rec);
 }
 
+int wiu_rk3_steps_stages(const wiu_grid* g, int scheme, const wiu_params* p, double* U, const double* M,
+                         const double* dt_dev, int nsteps, double* stages, void* recs, void* ws, wiu_stream_t stream) {
+  if (!grid_ok(g) || !options_ok(scheme, p) || !U || !M || !dt_dev || nsteps < 1 || !stages || !recs || !ws)
+    return WIU_EINVAL;
+  Ws w = carve(g, ws);
+  hipStream_t st = (hipStream_t)stream;
+  const long long ny = g->ny, ns = (long long)g->nx + g->ny + 1;
+  const size_t plane4 = (size_t)4 * g->nx * g->ny;
+  unsigned long long* r = (unsigned long long*)recs;
+  // the first step's maxima of U from a separate pass, into its record;
+  // later steps' from the last stage of the step before
+  {
+    ProfScope ps(WIU_K_WAVE_MAX, st);
+    if (launch_wave_max(dims(g), U, M, p->gamma, r, r + ny, r + ns - 1, w.status, st) != hipSuccess) return WIU_EHIP;
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    double* S0 = stages + (size_t)s * 3 * plane4;
+    double* S1 = S0 + plane4;
+    double* S2 = S1 + plane4;
+    unsigned long long* rs = r + (long long)s * 3 * ns;
+    if (hipMemcpyAsync(S0, U, plane4 * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) return WIU_EHIP;
+    Maxima m1;  // U in, U1 out
+    m1.lx_in = rs; m1.le_in = rs + ny; m1.nlx = rs + ns; m1.nle = rs + ns + ny;
+    int rc = residual(g, scheme, p, U, M, w, 2, S1, U, dt_dev, 0.0, 1.0, st, m1);
+    if (rc) return rc;
+    Maxima m2;  // U1 in, U2 out
+    m2.lx_in = rs + ns; m2.le_in = rs + ns + ny; m2.nlx = rs + 2 * ns; m2.nle = rs + 2 * ns + ny;
+    rc = residual(g, scheme, p, S1, M, w, 2, S2, U, dt_dev, 0.75, 0.25, st, m2);
+    if (rc) return rc;
+    Maxima m3;  // U2 in; the new state's maxima into the next step's record
+    m3.lx_in = rs + 2 * ns; m3.le_in = rs + 2 * ns + ny;
+    if (s + 1 < nsteps) { m3.nlx = rs + 3 * ns; m3.nle = rs + 3 * ns + ny; }
+    rc = residual(g, scheme, p, S2, M, w, 2, U, U, dt_dev, 1.0 / 3.0, 2.0 / 3.0, st, m3);
+    if (rc) return rc;
+  }
+  return WIU_OK;
+}
+
 int wiu_rk3_step_vjp(const wiu_grid* g, int scheme, const wiu_params* p, const double* U_n, const double* U1,
                      const double* U2, const void* rec, const double* M, const double* dt_dev,
                      const double* Ubar_np1, double* Ubar_n, void* ws, wiu_stream_t stream) {

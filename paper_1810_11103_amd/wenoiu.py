@@ -27,7 +27,7 @@ EXPORTS = [
     "wiu_batched_rk3_step", "wiu_batched_status", "wiu_plan_destroy", "wiu_blocks_metrics_work_size",
     "wiu_blocks_metrics", "wiu3_metrics_size", "wiu3_workspace_bytes", "wiu3_metrics", "wiu3_rhs", "wiu3_cfl_dt",
     "wiu3_rk3_step", "wiu3_rk3_step_cfl",
-    "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl", "wiu_rk3_steps_cfl", "wiu_step_record_bytes",
+    "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl", "wiu_rk3_steps_cfl", "wiu_rk3_steps_stages", "wiu_step_record_bytes",
     "wiu_noalloc_bytes", "wiu_rk3_step_noalloc",
 ]
 KERNELS = {"wave_max": 0, "sweep_xi": 1, "sweep_eta": 2, "metrics": 3, "sweep3": 4}
@@ -103,6 +103,7 @@ def _load():
         "wiu_plan_destroy": (I, [P]),
         "wiu_rhs_vjp": (I, [G, I, PR, P, P, P, P, P, P]),
         "wiu_rk3_step_stages": (I, [G, I, PR, P, P, P, P, P, P, P, P]),
+        "wiu_rk3_steps_stages": (I, [G, I, PR, P, P, P, I, P, P, P, P]),
         "wiu_rk3_step_vjp": (I, [G, I, PR, P, P, P, P, P, P, P, P, P, P]),
         "wiu_step_record_bytes": (ctypes.c_size_t, [G]),
         "wiu_tuning_variants": (I, [I]),
@@ -310,6 +311,22 @@ def rk3_step_stages(grid, scheme, params, U, M, dt_dev, U1, U2, ws, rec=None, st
     return U
 
 
+def rk3_steps_stages(grid, scheme, params, U, M, dt_dev, stages, recs, ws, stream=None):
+    """len(stages) steps of rk3_step_stages in one call: stages [n, 3, 4, ny, nx]
+    (U_n, U1, U2 of each step), recs [n, record words] (step records)."""
+    n = int(stages.shape[0])
+    if (stages.dim() != 5 or tuple(stages.shape[1:]) != (3,) + tuple(U.shape) or stages.dtype != torch.float64
+            or not stages.is_contiguous()):
+        raise ValueError("stages: a contiguous float64 tensor [n, 3, 4, ny, nx]")
+    if (recs.dim() != 2 or recs.shape[0] < n or recs.shape[1] * recs.element_size() < step_record_bytes(grid)
+            or not recs.is_contiguous() or not recs.is_cuda):
+        raise ValueError("recs: a contiguous device tensor of at least n step records")
+    _check(lib.wiu_rk3_steps_stages(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U), _ptr(M),
+                                    _ptr(dt_dev), n, _ptr(stages), ctypes.c_void_p(recs.data_ptr()),
+                                    ctypes.c_void_p(ws.data_ptr()), _stream(stream)))
+    return U
+
+
 def rk3_step_vjp(grid, scheme, params, U_n, U1, U2, M, dt_dev, Ubar_np1, Ubar_n, ws, rec=None, stream=None):
     _check(lib.wiu_rk3_step_vjp(ctypes.byref(grid), scheme_id(scheme), ctypes.byref(params), _ptr(U_n), _ptr(U1),
                                 _ptr(U2), _rec(rec), _ptr(M), _ptr(dt_dev), _ptr(Ubar_np1), _ptr(Ubar_n),
@@ -397,6 +414,10 @@ class Solver:
     def rk3_step_stages(self, U, U1, U2, ws=None, rec=None):
         return rk3_step_stages(self.grid, self.scheme, self.params, U, self.M, self.dt, U1, U2,
                                self.ws if ws is None else ws, rec)
+
+    def rk3_steps_stages(self, U, stages, recs, ws=None):
+        return rk3_steps_stages(self.grid, self.scheme, self.params, U, self.M, self.dt, stages, recs,
+                                self.ws if ws is None else ws)
 
     def step_record(self, n=None):
         """Device buffer for one step record (or `n` of them, as rows)."""

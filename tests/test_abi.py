@@ -98,6 +98,10 @@ def test_bad_scheme_params_and_pointers_rejected(wiu):
     for n, c in ((0, 0.5), (-3, 0.5), (2, 0.0)):
         assert wiu.lib.wiu_rk3_steps_cfl(ctypes.byref(g), 3, ctypes.byref(p), dummy, other, ctypes.c_double(c), n,
                                          ctypes.c_void_p(768), ctypes.c_void_p(1024), None) == wiu.WIU_EINVAL
+    # several stage-storing steps: at least one step, stages and records required
+    for n, st, rc in ((0, dummy, dummy), (2, None, dummy), (2, dummy, None)):
+        assert wiu.lib.wiu_rk3_steps_stages(ctypes.byref(g), 3, ctypes.byref(p), dummy, other, ctypes.c_void_p(768),
+                                            n, st, rc, ctypes.c_void_p(1024), None) == wiu.WIU_EINVAL
     assert wiu.lib.wiu_strerror(wiu.WIU_EINVAL) == b"invalid argument"
 
 

@@ -50,6 +50,33 @@ def test_rollout_forward_equals_plain_steps(mods, every):
     assert torch.equal(out, U)
 
 
+@pytest.mark.parametrize("s,n,nsteps", [("5-2MP", 48, 7), ("3-1MP", 37, 5), ("5-1MP", 48, 1)])
+def test_steps_stages_equal_single_stage_steps(mods, s, n, nsteps):
+    """wiu_rk3_steps_stages: the stored U_n, U1, U2 and the final state equal
+    those of one wiu_rk3_step_stages call per step bit for bit, and so do the
+    line maxima of the step records (the later steps' come from the step
+    before, not from a separate pass)."""
+    torch, wenoiu, AG = mods
+    say("steps_stages", s, n, nsteps)
+    g, sol, x, y = _setup(wenoiu, torch, n=n, scheme=s)
+    U0 = AG.vortex_state_torch(x, y, torch.tensor(5 / (2 * math.pi), dtype=torch.float64, device="cuda"))
+    sol.dt.fill_(0.02)
+    Ua, Ub = U0.clone(), U0.clone()
+    Sa = torch.empty((nsteps, 3) + tuple(U0.shape), dtype=torch.float64, device="cuda")
+    Sb = torch.empty_like(Sa)
+    Ra, Rb = sol.step_record(nsteps), sol.step_record(nsteps)
+    for k in range(nsteps):
+        Sa[k, 0].copy_(Ua)
+        sol.rk3_step_stages(Ua, Sa[k, 1], Sa[k, 2], rec=Ra[k])
+    sol.rk3_steps_stages(Ub, Sb, Rb)
+    assert sol.status() == 0
+    assert torch.equal(Ua, Ub) and torch.equal(Sa, Sb)
+    ns = g.x.shape[0] + g.x.shape[1] + 1
+    ra, rb = Ra.cpu().numpy().reshape(nsteps, 3, -1), Rb.cpu().numpy().reshape(nsteps, 3, -1)
+    assert np.array_equal(ra[:, :, :ns - 1], rb[:, :, :ns - 1])  # line maxima of U_n, U1, U2
+    assert np.array_equal(ra[0], rb[0])  # the first step's record entirely (its CFL entry included)
+
+
 def test_rollout_gradient_matches_oracle_adjoint_chain(orc, mods):
     torch, wenoiu, AG = mods
     s = "5-2MP"

@@ -429,6 +429,15 @@ int wiu3_rk3_step(const wiu_grid3* g, int scheme, const wiu_params* p, double* U
  * the two calls.  WIU_EINVAL unless cfl > 0. */
 int wiu3_rk3_step_cfl(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
                       double* dt, void* ws, wiu_stream_t stream);
+/* nsteps (>= 1) successive wiu3_rk3_step_cfl steps of U in place (Sec. 6,
+ * each at the CFL time step of the state it starts from); dt points to
+ * nsteps device doubles, dt[s] receiving the size of step s.  Same results,
+ * bit for bit, as nsteps wiu3_rk3_step_cfl calls: only the first step has a
+ * separate pass over U for the maxima; the last stage of each step forms
+ * the next step's line maxima and CFL maximum as it writes the state.
+ * WIU_EINVAL unless cfl > 0 and nsteps >= 1. */
+int wiu3_rk3_steps_cfl(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
+                       int nsteps, double* dt, void* ws, wiu_stream_t stream);
 
 /* Tile shapes of the two sweep kernels (dir 0 = xi, 1 = eta).  Several
  * shapes are compiled; the choice is process-wide and affects speed only,

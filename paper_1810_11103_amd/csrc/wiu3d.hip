@@ -13,6 +13,8 @@
 // zeta, eta, xi: the xi pass, whose lines are contiguous in memory, writes
 // dU/dt or the RK stage (and, in stages 1 and 2, the next stage's maxima).
 #include "wenoiu.h"
+
+#include <utility>
 #include "wiu_kernels.hpp"
 
 namespace wiu {
@@ -463,6 +465,7 @@ struct S3Args {
   const double* M;
   const unsigned long long* lam;   // line maxima: xi lines [ny nz], eta [nx nz], zeta [nx ny]
   unsigned long long* nlam;        // xi pass of an RK stage: the next stage's maxima (or null)
+  unsigned long long* ncfl;        // with nlam, when set: the next state's CFL maximum per j [ny]
   double gamma, alpha, eps;
   int ppm;
   int vars;                        // WIU_VARS_* (interpolation variables)
@@ -774,6 +777,14 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
       unsigned long long* lx = a.nlam;
       unsigned long long* le = lx + (long long)d.n[1] * d.n[2];
       unsigned long long* lz = le + (long long)d.n[0] * d.n[2];
+      if (a.ncfl) {
+        // CFL maximum, formed as the separate maxima pass forms it, in
+        // partial maxima per j: the tiles of one k plane run together, so
+        // their atomics spread over ny addresses
+        double cf = act ? (sx + se + sz) / jv : 0.0;
+        for (int off = 32; off > 0; off >>= 1) cf = fmax(cf, __shfl_xor(cf, off, 64));
+        if (ta == 0 && live) atomicMax(&a.ncfl[la], (unsigned long long)__double_as_longlong(cf));
+      }
       // xi lines (j, k): reduce over the wave (along i)
       for (int off = 32; off > 0; off >>= 1) sx = fmax(sx, __shfl_xor(sx, off, 64));
       if (ta == 0 && live) atomicMax(&lx[(long long)cb * d.n[1] + la], (unsigned long long)__double_as_longlong(sx));
@@ -924,8 +935,11 @@ Ws3 ws3(const wiu_grid3* g) {
   Ws3 w;
   w.nlam = (long long)g->ny * g->nz + (long long)g->nx * g->nz + (long long)g->nx * g->ny + 1;
   w.lam = A3;
-  w.lam2 = w.lam + al3(w.nlam * 8);  // the next RK stage's maxima
-  w.dt = w.lam2 + al3(w.nlam * 8);
+  // a maxima set: the line maxima and the CFL maximum (nlam entries), then
+  // the partial CFL maxima per j [ny] that several steps per call carry
+  const size_t set = al3((w.nlam + g->ny) * 8);
+  w.lam2 = w.lam + set;  // the next RK stage's maxima
+  w.dt = w.lam2 + set;
   w.big = w.dt + A3;
   const int B = GHOST + METRIC_REACH, E = B + 8;  // the widest band (Eq. 2.6)
   const size_t dxb = al3(9 * (size_t)(g->nx + 2 * E) * (g->ny + 2 * E) * (g->nz + 2 * E) * 8);
@@ -1021,12 +1035,15 @@ int rc3(hipError_t e) { return e == hipSuccess ? WIU_OK : WIU_EHIP; }
 
 }  // namespace
 
-// One TVD-RK3 step; with cfl > 0 the first stage's maxima pass also yields
-// the CFL time step, written to *dt before the stages read it (dt is then
-// written, otherwise only read).
+// nsteps TVD-RK3 steps; with cfl > 0 each at the CFL time step of its state,
+// written to dt[step] before the stages read it, otherwise all at the device
+// scalar *dt, only read.  Only the first step has a separate maxima pass: the
+// xi pass of each stage accumulates the next stage's maxima (that of the last
+// stage, for the next step, also the partial CFL maxima per j).
 static int rk3_3d(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl, double* dt,
-           void* ws, wiu_stream_t stream) {
-  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !params3_ok(p, scheme) || !U || !M || !dt || !ws) return WIU_EINVAL;
+           void* ws, wiu_stream_t stream, int nsteps = 1) {
+  if (!grid3_ok(g) || scheme < 0 || scheme > 7 || !params3_ok(p, scheme) || !U || !M || !dt || !ws || nsteps < 1)
+    return WIU_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const Dims3 d = dims3(g);
   const Ws3 w = ws3(g);
@@ -1035,35 +1052,47 @@ static int rk3_3d(const wiu_grid3* g, int scheme, const wiu_params* p, double* U
   double* U2 = (double*)(base + w.u2);
   S3Args a;
   a.nlam = nullptr;
+  a.ncfl = nullptr;
   a.d = d; a.M = M; a.lam = (unsigned long long*)(base + w.lam);
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
   a.Racc = (double*)(base + w.racc);
-  a.U0 = U; a.dt = dt; a.status = (int*)base;
+  a.U0 = U; a.status = (int*)base;
   sides3(g, a);
   options3(p, a);
   // U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U = 1/3 U + 2/3 (U2 + dt L(U2))
   const double* src[3] = {U, U1, U2};
   double* dst[3] = {U1, U2, U};
   const double ca[3] = {0.0, 0.75, 1.0 / 3.0}, cb[3] = {1.0, 0.25, 2.0 / 3.0};
-  // the first stage's maxima from a separate pass; the xi pass of stages 1
-  // and 2 accumulates the next stage's into the other buffer
-  unsigned long long* lbuf[2] = {(unsigned long long*)(base + w.lam), (unsigned long long*)(base + w.lam2)};
-  if (maxima3(d, U, M, p->gamma, lbuf[0], w.nlam, a.status, st) != hipSuccess) return WIU_EHIP;
-  if (cfl > 0.0 && launch_cfl_dt(lbuf[0] + w.nlam - 1, cfl, dt, st) != hipSuccess) return WIU_EHIP;
-  for (int s = 0; s < 3; ++s) {
-    a.U = src[s]; a.out = dst[s]; a.ca = ca[s]; a.cb = cb[s];
-    a.lam = lbuf[s & 1];
-    unsigned long long* next = s < 2 ? lbuf[(s + 1) & 1] : nullptr;
-    if (next && launch_fill_u64(next, w.nlam, st) != hipSuccess) return WIU_EHIP;
-    for (int q = 0; q < 3; ++q) {  // zeta, eta, then xi, which writes the stage state
-      const int D = 2 - q;
-      a.nlam = D == 0 ? next : nullptr;
-      if (pass3(scheme, a, D, q == 0 ? 0 : (q == 1 ? 1 : 3), st) != hipSuccess) return WIU_EHIP;
+  // two maxima sets: sa holds the current state's, sb receives the next
+  // stage's; the first step's come from a separate pass
+  unsigned long long* sa = (unsigned long long*)(base + w.lam);
+  unsigned long long* sb = (unsigned long long*)(base + w.lam2);
+  if (maxima3(d, U, M, p->gamma, sa, w.nlam, a.status, st) != hipSuccess) return WIU_EHIP;
+  for (int step = 0; step < nsteps; ++step) {
+    double* dts = cfl > 0.0 ? dt + step : dt;
+    if (cfl > 0.0) {
+      const hipError_t e = step == 0 ? launch_cfl_dt(sa + w.nlam - 1, cfl, dts, st)
+                                     : launch_cfl_dt_lines(sa + w.nlam, d.n[1], cfl, dts, st);
+      if (e != hipSuccess) return WIU_EHIP;
     }
+    a.dt = dts;
+    for (int s = 0; s < 3; ++s) {
+      a.U = src[s]; a.out = dst[s]; a.ca = ca[s]; a.cb = cb[s];
+      a.lam = s == 1 ? sb : sa;  // the maxima of U, U1, U2
+      unsigned long long* next = s == 0 ? sb : (s == 1 ? sa : (step + 1 < nsteps ? sb : nullptr));
+      const bool with_cfl = s == 2 && next;
+      if (next && launch_fill_u64(next, w.nlam + (with_cfl ? d.n[1] : 0), st) != hipSuccess) return WIU_EHIP;
+      for (int q = 0; q < 3; ++q) {  // zeta, eta, then xi, which writes the stage state
+        const int D = 2 - q;
+        a.nlam = D == 0 ? next : nullptr;
+        a.ncfl = D == 0 && with_cfl ? next + w.nlam : nullptr;
+        if (pass3(scheme, a, D, q == 0 ? 0 : (q == 1 ? 1 : 3), st) != hipSuccess) return WIU_EHIP;
+      }
+    }
+    std::swap(sa, sb);
   }
   return WIU_OK;
 }
-
 
 extern "C" {
 
@@ -1107,6 +1136,7 @@ int wiu3_rhs(const wiu_grid3* g, int scheme, const wiu_params* p, const double* 
   char* base = (char*)ws;
   S3Args a;
   a.nlam = nullptr;
+  a.ncfl = nullptr;
   a.d = d; a.U = U; a.M = M; a.lam = (unsigned long long*)(base + w.lam);
   a.gamma = p->gamma; a.alpha = p->alpha_lf; a.eps = p->eps; a.ppm = p->ppm;
   a.Racc = (double*)(base + w.racc); a.out = dUdt;
@@ -1140,6 +1170,12 @@ int wiu3_rk3_step_cfl(const wiu_grid3* g, int scheme, const wiu_params* p, doubl
                       double* dt, void* ws, wiu_stream_t stream) {
   if (!(cfl > 0.0)) return WIU_EINVAL;
   return rk3_3d(g, scheme, p, U, M, cfl, dt, ws, stream);
+}
+
+int wiu3_rk3_steps_cfl(const wiu_grid3* g, int scheme, const wiu_params* p, double* U, const double* M, double cfl,
+                       int nsteps, double* dt, void* ws, wiu_stream_t stream) {
+  if (!(cfl > 0.0) || nsteps < 1) return WIU_EINVAL;
+  return rk3_3d(g, scheme, p, U, M, cfl, dt, ws, stream, nsteps);
 }
 
 }  // extern "C"

@@ -26,7 +26,7 @@ EXPORTS = [
     "wiu_batched_plan", "wiu_batched_info", "wiu_batched_set_dt", "wiu_batched_cfl_dt", "wiu_batched_get_dt",
     "wiu_batched_rk3_step", "wiu_batched_status", "wiu_plan_destroy", "wiu_blocks_metrics_work_size",
     "wiu_blocks_metrics", "wiu3_metrics_size", "wiu3_workspace_bytes", "wiu3_metrics", "wiu3_rhs", "wiu3_cfl_dt",
-    "wiu3_rk3_step", "wiu3_rk3_step_cfl",
+    "wiu3_rk3_step", "wiu3_rk3_step_cfl", "wiu3_rk3_steps_cfl",
     "wiu_rhs_vjp", "wiu_rk3_step_stages", "wiu_rk3_step_vjp", "wiu_rk3_step_cfl", "wiu_rk3_steps_cfl", "wiu_rk3_steps_stages", "wiu_step_record_bytes",
     "wiu_noalloc_bytes", "wiu_rk3_step_noalloc",
 ]
@@ -93,6 +93,7 @@ def _load():
         "wiu3_cfl_dt": (I, [ctypes.POINTER(WiuGrid3), PR, P, P, ctypes.c_double, P, P, P]),
         "wiu3_rk3_step": (I, [ctypes.POINTER(WiuGrid3), I, PR, P, P, P, P, P]),
         "wiu3_rk3_step_cfl": (I, [ctypes.POINTER(WiuGrid3), I, PR, P, P, ctypes.c_double, P, P, P]),
+        "wiu3_rk3_steps_cfl": (I, [ctypes.POINTER(WiuGrid3), I, PR, P, P, ctypes.c_double, I, P, P, P]),
         "wiu_blocks_metrics": (I, [ctypes.POINTER(WiuBlock), I, I, PR, P, P, P, P]),
         "wiu_batched_info": (I, [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "wiu_batched_set_dt": (I, [P, P, P]),
@@ -663,6 +664,17 @@ class Solver3:
                                      _ptr(U), _ptr(self.M), float(cfl), _ptr(self.dt),
                                      ctypes.c_void_p(self.ws.data_ptr()), _stream()))
         return self.dt
+
+    def rk3_steps_cfl(self, U, cfl, nsteps, dts=None):
+        """nsteps CFL-limited RK3 steps in one call; returns the device
+        tensor of the step sizes (dts, or a new one)."""
+        dts = torch.empty(int(nsteps), dtype=torch.float64, device=self.M.device) if dts is None else dts
+        if dts.numel() < nsteps or dts.dtype != torch.float64 or not dts.is_contiguous():
+            raise ValueError("dts: a contiguous float64 tensor of at least nsteps entries")
+        _check(lib.wiu3_rk3_steps_cfl(ctypes.byref(self.grid), scheme_id(self.scheme), ctypes.byref(self.params),
+                                      _ptr(U), _ptr(self.M), float(cfl), int(nsteps), _ptr(dts),
+                                      ctypes.c_void_p(self.ws.data_ptr()), _stream()))
+        return dts
 
     def status(self, clear=True):
         return status(self.ws, clear)

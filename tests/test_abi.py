@@ -201,3 +201,7 @@ def test_3d_grids_and_options_are_validated(wiu):
     for cfl, scheme in ((0.0, 3), (-0.5, 3), (float("nan"), 3), (0.5, 8)):
         assert wiu.lib.wiu3_rk3_step_cfl(ctypes.byref(g), scheme, ctypes.byref(P), dummy, dummy, cfl, dummy, dummy,
                                          None) == wiu.WIU_EINVAL
+    # several steps per call: also at least one step
+    for cfl, scheme, n in ((0.0, 3, 2), (float("nan"), 3, 2), (0.5, 8, 2), (0.5, 3, 0), (0.5, 3, -1)):
+        assert wiu.lib.wiu3_rk3_steps_cfl(ctypes.byref(g), scheme, ctypes.byref(P), dummy, dummy, cfl, n, dummy,
+                                          dummy, None) == wiu.WIU_EINVAL

@@ -389,3 +389,106 @@ def test_rk3_step_cfl_equals_cfl_dt_then_step_3d(wiu, kind):
         assert torch.equal(a.dt, b.dt)
         assert torch.equal(Ua, Ub)
     assert a.status() == 0 and b.status() == 0
+
+
+STEPS_CASES3 = [("5-2MP", "periodic", None, {}), ("3-1MP", "bounded", None, {}), ("7-2MP", "mixed", None, {}),
+                ("5-2MP", "wavy", None, {}), ("5-2MP", "bounded", 0, {}), ("3-1MP", "bounded", 1, {}),
+                ("5-1MP", "periodic", None, dict(vars="primitive", weights="z")),
+                ("5-2MP", "mixed", None, dict(split="sw"))]
+
+
+@pytest.mark.parametrize("s,kind,sides,opts", STEPS_CASES3)
+def test_rk3_steps_cfl_equal_single_steps_3d(wiu, s, kind, sides, opts):
+    """wiu3_rk3_steps_cfl: the last stage of each step forms the next step's
+    line maxima and its CFL maximum (partial maxima per j) in place of a
+    separate pass; states and time steps equal those of as many
+    wiu3_rk3_step_cfl calls, bit for bit."""
+    import torch
+    say("3-D rk3_steps_cfl vs single steps", s, kind, sides, opts)
+    g, U = case(kind, seed=5)
+    kw = {}
+    if sides is not None:
+        kw = dict(sides=SIDE_SETS3[sides], fixed=FIXED6)
+    if sides is not None or "split" in opts:
+        # the octant state loses positivity within four steps with the
+        # Steger-Warming split (single steps too), so those run on a smooth one
+        U = W.smooth_state3(g, seed=3)
+    params = wiu.make_params(**opts)
+    a = wiu.Solver3(g.x, g.y, g.z, s, g.bc, g.period, params=params, **kw)
+    b = wiu.Solver3(g.x, g.y, g.z, s, g.bc, g.period, params=params, **kw)
+    Ua, Ub = dev(U), dev(U)
+    ref = []
+    for _ in range(4):
+        a.rk3_step_cfl(Ua, 0.3)
+        ref.append(float(a.dt[0]))
+    got = host(b.rk3_steps_cfl(Ub, 0.3, 4)).tolist()
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(Ua).all())
+    assert got == ref
+    assert torch.equal(Ua, Ub)
+    assert a.status() == 0 and b.status() == 0
+    one = b.rk3_steps_cfl(Ub, 0.3, 1)  # one step: the separate pass only
+    a.rk3_step_cfl(Ua, 0.3)
+    assert float(one[0]) == float(a.dt[0])
+    assert torch.equal(Ua, Ub)
+
+
+@pytest.mark.parametrize("shape,bc", [((1, 5, 7), ("periodic", "periodic", "periodic")),
+                                      ((17, 1, 33), ("periodic", "periodic", "transmissive")),
+                                      ((3, 2, 2), ("transmissive", "transmissive", "transmissive"))])
+def test_rk3_steps_cfl_degenerate_shapes_3d(wiu, shape, bc):
+    """Several steps per call on one-node and two-node directions."""
+    import torch
+    say("3-D rk3_steps_cfl degenerate", shape, bc)
+    nz, ny, nx = shape
+    g = W.mixed_grid3(nx, ny, nz, bc, A=0.1, seed=4, layers=1)
+    U = W.smooth_state3(g, seed=1)
+    a = wiu.Solver3(g.x, g.y, g.z, "5-2MP", g.bc, g.period)
+    b = wiu.Solver3(g.x, g.y, g.z, "5-2MP", g.bc, g.period)
+    Ua, Ub = dev(U), dev(U)
+    ref = []
+    for _ in range(3):
+        a.rk3_step_cfl(Ua, 0.5)
+        ref.append(float(a.dt[0]))
+    assert host(b.rk3_steps_cfl(Ub, 0.5, 3)).tolist() == ref
+    assert torch.equal(Ua, Ub)
+
+
+def test_rk3_steps_cfl_track_oracle_3d(orc, wiu):
+    """Three CFL-limited steps in one call against the oracle's CFL rule and
+    RK3 step applied three times."""
+    say("3-D rk3_steps_cfl vs oracle")
+    g, U = case("mixed", seed=5)
+    s = "5-2MP"
+    Mo = orc.metrics3(s, g.x, g.y, g.z, g.bc, g.period)
+    sol = wiu.Solver3(g.x, g.y, g.z, s, g.bc, g.period)
+    Ud = dev(U)
+    dts = host(sol.rk3_steps_cfl(Ud, 0.3, 3))
+    assert sol.status() == 0
+    ref = U.copy()
+    for n in range(3):
+        dt = orc.cfl_dt3(ref, Mo, 0.3)
+        assert abs(dts[n] - dt) <= 1e-12 * dt, (n, dts[n], dt)
+        ref = orc.rk3_step3(s, ref, Mo, dt, g.bc)
+    assert np.all(normwise(host(Ud) - U, ref - U) <= 1e-10)
+
+
+def test_rk3_steps_cfl_at_the_benchmark_size_3d(wiu):
+    """256^3 octant problem: two steps in one call equal two single CFL
+    steps, bit for bit, in the launch shapes the benchmark times."""
+    import torch
+    say("3-D rk3_steps_cfl at 256^3")
+    n = 256
+    g = W.periodic_grid3(n, n, n, A=0.2, seed=n)
+    sol = wiu.Solver3(g.x, g.y, g.z, "5-2MP", g.bc, g.period)
+    Ua = dev(W.octant_state3(g))
+    del g
+    Ub = Ua.clone()
+    ref = []
+    for _ in range(2):
+        sol.rk3_step_cfl(Ua, 0.5)
+        ref.append(float(sol.dt[0]))
+    got = host(sol.rk3_steps_cfl(Ub, 0.5, 2)).tolist()
+    assert got == ref
+    assert torch.equal(Ua, Ub)
+    assert sol.status() == 0

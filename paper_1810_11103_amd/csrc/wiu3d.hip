@@ -571,15 +571,31 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
     else if (DIR == 1) { p[0] = line; p[1] = kk; p[2] = cb; }
     else { p[0] = line; p[1] = cb; p[2] = kk; }
   };
-  // stage the states of the segment
+  // stage the states of the segment: each thread's elements (NIT at most)
+  // are all loaded before any is stored, so their latencies overlap; a
+  // segment whose window lies inside the line needs no index mapping
   {
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int k0 = o0 + R_::LO - QL;
-    for (int e = tid; e < NQ * NB; e += NT) {
+    const bool inside = k0 >= 0 && k0 + NQ <= n;  // uniform over the block
+    constexpr int NIT = (NQ * NB + NT - 1) / NT;
+    double Qs[NIT][5];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = tid + it * NT;
+      if (e >= NQ * NB) break;
       const int pos = DIR == 0 ? e % NQ : e / NB;
       const int lb = DIR == 0 ? e / NQ : e % NB;
       const int ln = grp * NB + lb;
-      if (ln < nac) {
+      double* Qv = Qs[it];
+      if (ln >= nac) continue;
+      if (inside) {
+        int p[3];
+        node(k0 + pos, ln, p);
+        const long long o = u3idx(d, p[0], p[1], p[2]);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) Qv[c] = a.U[c * d.np + o];
+      } else {
         // beyond a non-periodic end the side's rule: transmissive (boundary
         // node), reflecting wall (mirror node, momentum along the boundary
         // node's unit metric direction reversed) or a fixed state
@@ -587,7 +603,6 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
         const bool out_of = d.bc[DIR] != WIU_BC_PERIODIC && (kr < 0 || kr >= n);
         const int sd = 2 * DIR + (kr < 0 ? 0 : 1);
         const int rule = out_of ? a.side[sd] : WIU_SIDE_TRANSMISSIVE;
-        double Qv[5];
         if (rule == WIU_SIDE_FIXED) {
 #pragma unroll
           for (int c = 0; c < 5; ++c) Qv[c] = a.fixed[sd][c];
@@ -609,9 +624,17 @@ __global__ void __launch_bounds__(NA * NB) s3_sweep_kernel(S3Args a, int mode) {
             for (int c = 0; c < 3; ++c) Qv[1 + c] -= 2.0 * mn * (nv[c] * rn);
           }
         }
-#pragma unroll
-        for (int c = 0; c < 5; ++c) L.sq[c][LT::qi(lb, pos)] = Qv[c];
       }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = tid + it * NT;
+      if (e >= NQ * NB) break;
+      const int pos = DIR == 0 ? e % NQ : e / NB;
+      const int lb = DIR == 0 ? e / NQ : e % NB;
+      if (grp * NB + lb >= nac) continue;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) L.sq[c][LT::qi(lb, pos)] = Qs[it][c];
     }
   }
   __syncthreads();

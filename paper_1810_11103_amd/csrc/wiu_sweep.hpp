@@ -277,6 +277,8 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
     // tiles whose window stays inside the line, or with no wall or fixed
     // side at the ends it reaches, load plainly (block-uniform test)
     const bool edge = bc_al != 0 && ((k0 < 0 && s.side[S0] != 0) || (k0 + NQ > n_al && s.side[S0 + 1] != 0));
+    // tiles whose window lies inside the line need no index mapping at all
+    const bool inside = k0 >= 0 && k0 + NQ <= n_al;
     // the thread's elements, NIT at most; in the paper's configuration every
     // load is issued before any is stored, so their latencies overlap (the
     // option kernels, short of registers, load and store one at a time)
@@ -293,7 +295,14 @@ WIU_DEV void sweep_tile(const SweepArgs& s, int bxl, int byl, SweepLds<SC, DIR, 
         const int lb = DIR == 0 ? e / NQ : e % NB;
         const int ln = (DIR == 0 ? byl : bxl) * NB + lb;
         double* Qv = Qs_[it];
-        if (ln < n_ac) {
+        if (inside) {
+          if (ln < n_ac) {
+            const int kr = k0 + pos;
+            const long long o = DIR == 0 ? (long long)ln * d.nx + kr : (long long)kr * d.nx + ln;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Qv[c] = s.U[c * d.np + o];
+          }
+        } else if (ln < n_ac) {
           const int kr = k0 + pos;
           const bool lo = kr < 0;
           const int rule = (edge && (lo || kr >= n_al)) ? (lo ? s.side[S0] : s.side[S0 + 1]) : 0;

@@ -427,8 +427,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(domain decomposition is described in DESIGN.md but not built).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
+              "(no domain decomposition across GPUs is implemented).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -363,6 +363,37 @@ def test_rk3_steps_cfl_equals_single_steps(wiu, s, kind, sides, opts):
     assert np.array_equal(_host(Ua), _host(Ub))
 
 
+
+DEGENERATE_STEPS = [("strip", 203, 1), ("smooth", 7, 5), ("bounded", 3, 2), ("periodic1", 9, 1)]
+
+
+@pytest.mark.parametrize("kind,nx,ny", DEGENERATE_STEPS)
+def test_rk3_steps_cfl_degenerate_shapes(wiu, kind, nx, ny):
+    """Several steps per call on a one-row strip, a one-node periodic
+    direction and grids of a few nodes, where the per-line CFL partials
+    cover only a handful of lines: states and time steps equal those of
+    single wiu_rk3_step_cfl calls, bit for bit."""
+    say("rk3_steps_cfl degenerate", kind, nx, ny)
+    if kind == "bounded":
+        g = W.bounded_grid(nx, ny, (0, 1, 0, 1), A=0.1, seed=4, layers=1)
+        U = W.random_smooth_state(g, seed=4)
+    elif kind == "periodic1":
+        g = W.periodic_grid(nx, ny, (0, 10, 0, 10), A=0.0, seed=3)
+        U = W.random_smooth_state(g, seed=3)
+    else:
+        g, U = make_case(kind, nx, ny, seed=4)
+    a = wiu.Solver(g.x, g.y, "5-2MP", g.bc, g.period)
+    b = wiu.Solver(g.x, g.y, "5-2MP", g.bc, g.period)
+    Ua, Ub = _dev(U), _dev(U)
+    dts = []
+    for _ in range(3):
+        a.rk3_step_cfl(Ua, 0.5)
+        dts.append(float(a.dt.item()))
+    got = _host(b.rk3_steps_cfl(Ub, 0.5, 3)).tolist()
+    assert a.status() == 0 and b.status() == 0
+    assert got == dts
+    assert np.array_equal(_host(Ua), _host(Ub))
+
 def test_rk3_steps_cfl_across_tile_shapes(wiu):
     """The CFL maximum reduced in the eta tiles does not depend on their
     lane layout (2 to 16 lines per wave): same steps for every eta shape."""

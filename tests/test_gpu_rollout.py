@@ -77,6 +77,36 @@ def test_steps_stages_equal_single_stage_steps(mods, s, n, nsteps):
     assert np.array_equal(ra[0], rb[0])  # the first step's record entirely (its CFL entry included)
 
 
+
+@pytest.mark.parametrize("s,sides", [("5-2MP", ("wall", "transmissive", "wall", "wall")),
+                                     ("3-2MP", ("transmissive", "wall", "transmissive", "transmissive"))])
+def test_steps_stages_with_walls_on_a_ragged_bounded_grid(mods, s, sides):
+    """The stage-storing steps in one call on a bounded 61 x 45 Riemann grid
+    with reflecting walls (tiles cut by the grid's ends): stored stages,
+    final state and the records' line maxima equal one stage-storing call
+    per step bit for bit."""
+    torch, wenoiu, AG = mods
+    say("steps_stages walls", s, sides)
+    g = W.bounded_grid(61, 45, (0, 1, 0, 1), A=0.2, seed=6)
+    U0 = torch.as_tensor(W.riemann_state(g)).cuda().contiguous()
+    sol = wenoiu.Solver(g.x, g.y, s, g.bc, g.period, sides=sides)
+    sol.cfl_dt(U0, 0.4)
+    nsteps = 6
+    Ua, Ub = U0.clone(), U0.clone()
+    Sa = torch.empty((nsteps, 3) + tuple(U0.shape), dtype=torch.float64, device="cuda")
+    Sb = torch.empty_like(Sa)
+    Ra, Rb = sol.step_record(nsteps), sol.step_record(nsteps)
+    for k in range(nsteps):
+        Sa[k, 0].copy_(Ua)
+        sol.rk3_step_stages(Ua, Sa[k, 1], Sa[k, 2], rec=Ra[k])
+    sol.rk3_steps_stages(Ub, Sb, Rb)
+    assert sol.status() == 0
+    assert bool(torch.isfinite(Ua).all())
+    assert torch.equal(Ua, Ub) and torch.equal(Sa, Sb)
+    ns = g.x.shape[0] + g.x.shape[1] + 1
+    ra, rb = Ra.cpu().numpy().reshape(nsteps, 3, -1), Rb.cpu().numpy().reshape(nsteps, 3, -1)
+    assert np.array_equal(ra[:, :, :ns - 1], rb[:, :, :ns - 1])
+
 def test_rollout_gradient_matches_oracle_adjoint_chain(orc, mods):
     torch, wenoiu, AG = mods
     s = "5-2MP"

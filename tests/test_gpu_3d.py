@@ -492,3 +492,39 @@ def test_rk3_steps_cfl_at_the_benchmark_size_3d(wiu):
     assert got == ref
     assert torch.equal(Ua, Ub)
     assert sol.status() == 0
+
+
+
+def test_steps_cfl_replayed_from_a_captured_graph_3d(wiu):
+    """3-D steps in one call captured in a HIP graph and replayed three
+    times, eager calls between: each replay equals the eager call."""
+    import torch
+    say("3-D rk3_steps_cfl graph replays")
+    g, U = case("mixed", seed=5)
+    sol = wiu.Solver3(g.x, g.y, g.z, "5-2MP", g.bc, g.period)
+    U0 = dev(U)
+    K = 3
+    Ue = U0.clone()
+    dte = sol.rk3_steps_cfl(Ue, 0.3, K)
+    torch.cuda.synchronize()
+    Ug = U0.clone()
+    dtg = torch.empty(K, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        sol.rk3_steps_cfl(Ug, 0.3, K, dtg)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        sol.rk3_steps_cfl(Ug, 0.3, K, dtg)
+    for r in range(3):
+        Ug.copy_(U0)
+        dtg.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Ug, Ue), r
+        assert torch.equal(dtg, dte), r
+        Uw = U0.clone()
+        sol.rk3_steps_cfl(Uw, 0.3, 2)
+        torch.cuda.synchronize()
+    assert sol.status() == 0

@@ -367,6 +367,43 @@ def test_rk3_steps_cfl_equals_single_steps(wiu, s, kind, sides, opts):
 DEGENERATE_STEPS = [("strip", 203, 1), ("smooth", 7, 5), ("bounded", 3, 2), ("periodic1", 9, 1)]
 
 
+
+def test_steps_cfl_replayed_from_a_captured_graph(wiu):
+    """Several CFL steps per call captured once in a HIP graph (the library
+    clears its maxima with fill kernels, never memsets) and replayed three
+    times, with eager steps and synchronisations between the replays: every
+    replay gives the eager call's states and time steps bit for bit."""
+    import torch
+    say("rk3_steps_cfl graph replays")
+    g, U = make_case("riemann", 301, 203, seed=8)
+    sol = wiu.Solver(g.x, g.y, "5-2MP", g.bc, g.period)
+    U0 = _dev(U)
+    K = 4
+    Ue = U0.clone()
+    dte = sol.rk3_steps_cfl(Ue, 0.5, K)
+    torch.cuda.synchronize()
+    Ug = U0.clone()
+    dtg = torch.empty(K, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # one call before capture, as torch asks
+        sol.rk3_steps_cfl(Ug, 0.5, K, dtg)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        sol.rk3_steps_cfl(Ug, 0.5, K, dtg)
+    for r in range(3):
+        Ug.copy_(U0)
+        dtg.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Ug, Ue), r
+        assert torch.equal(dtg, dte), r
+        Uw = U0.clone()  # eager work between the replays
+        sol.rk3_steps_cfl(Uw, 0.5, 2)
+        torch.cuda.synchronize()
+    assert sol.status() == 0
+
 @pytest.mark.parametrize("kind,nx,ny", DEGENERATE_STEPS)
 def test_rk3_steps_cfl_degenerate_shapes(wiu, kind, nx, ny):
     """Several steps per call on a one-row strip, a one-node periodic

@@ -218,8 +218,8 @@ WIU_DEV double map2(double w, double C, double Klo, double Khi) {
 // v_{k+2} = (a, b, 0, d, e).  Candidates from Table 1 (b_{k,l}), linear
 // weights (1, 10, 5)/16, Jiang-Shu indicators (Eq. 3.22)
 //   IS = 13/12 t^2 + 1/4 s^2 = 13/12 t^2 + u^2,  u = s/2,
-// with t, u formed directly from the values (t0 = a - 2b, u0 = a/2 - 2b;
-// t1 = b + d, u1 = (b - d)/2; t2 = e - 2d, u2 = e/2 - 2d), weights
+// with t, u formed directly from the values (t0 = a - 2b, u0 = a/2 - 2b
+// = t0 - a/2; t1 = b + d, u1 = (b - d)/2; t2 = e - 2d, u2 = t2 - e/2), weights
 // alpha_k / sum alpha with alpha_k = C_k / (eps + IS_k)^2 formed with one
 // reciprocal (w_k = C_k prod_{l != k} D_l / sum_m C_m prod_{l != m} D_l; the
 // common factor 1/16 of the C_k cancels), mapping Eq. 3.23 and
@@ -233,7 +233,7 @@ WIU_DEV double weno5(double a, double b, double d, double e, double eps, int ppm
   const double p1 = 0.375 * d - 0.125 * b;
   const double p2 = 0.75 * d - 0.125 * e;
   const double t0 = fma(-2.0, b, a), t1 = b + d, t2 = fma(-2.0, d, e);
-  const double u0 = fma(-2.0, b, 0.5 * a), u1 = 0.5 * (b - d), u2 = fma(-2.0, d, 0.5 * e);
+  const double u0 = fma(-0.5, a, t0), u1 = 0.5 * (b - d), u2 = fma(-0.5, e, t2);
   double D0 = fma(13.0 / 12.0, t0 * t0, fma(u0, u0, eps));
   double D1 = fma(13.0 / 12.0, t1 * t1, fma(u1, u1, eps));
   double D2 = fma(13.0 / 12.0, t2 * t2, fma(u2, u2, eps));
@@ -268,7 +268,7 @@ WIU_DEV double weno3(double a, double b, double d, double eps, int ppm) {
   const double p1 = 0.5 * d;
   // the first two r = 3 indicators, in the form of weno5
   const double t0 = fma(-2.0, b, a), t1 = b + d;
-  const double u0 = fma(-2.0, b, 0.5 * a), u1 = 0.5 * (b - d);
+  const double u0 = fma(-0.5, a, t0), u1 = 0.5 * (b - d);
   double D0 = fma(13.0 / 12.0, t0 * t0, fma(u0, u0, eps));
   double D1 = fma(13.0 / 12.0, t1 * t1, fma(u1, u1, eps));
   if constexpr (ZOK) {

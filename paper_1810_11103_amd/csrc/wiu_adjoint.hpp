@@ -22,14 +22,18 @@ WIU_DEV void weno5_vjp(double a, double b, double d, double e, double eps, int p
   const double d1 = b - a, d2 = -b, d3 = d, d4 = e - d;
   const double t[3] = {d2 - d1, d3 - d2, d4 - d3};
   const double s[3] = {fma(3.0, d2, -d1), -(d2 + d3), fma(-3.0, d3, d4)};
+  // IS_k = 13/12 t^2 + 1/4 s^2 (Eq. 3.22), E = eps + IS, D = E^2
   double E[3], D[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    E[k] = eps + fma(13.0 / 12.0, t[k] * t[k], 0.25 * (s[k] * s[k]));
+    const double u = 0.5 * s[k];
+    E[k] = fma(13.0 / 12.0, t[k] * t[k], fma(u, u, eps));
     D[k] = E[k] * E[k];
   }
-  const double al[3] = {C[0] * (D[1] * D[2]), C[1] * (D[0] * D[2]), C[2] * (D[0] * D[1])};
-  const double r = rcp(al[0] + al[1] + al[2]);
+  // alpha_k = C_k prod_{l != k} D_l (the common factor of the products cancels)
+  const double P[3] = {D[1] * D[2], D[0] * D[2], D[0] * D[1]};
+  const double al[3] = {C[0] * P[0], C[1] * P[1], C[2] * P[2]};
+  const double r = rcp_w(al[0] + al[1] + al[2]);
   double w[3], g[3], h[3], dw[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -38,34 +42,33 @@ WIU_DEV void weno5_vjp(double a, double b, double d, double e, double eps, int p
     h[k] = kd(dw[k], KL[k], KH[k]);  // K d, as the forward sweep forms it
     g[k] = ppm ? fma(dw[k], fma(dw[k], h[k], -1.0), w[k]) : w[k];  // C + K d^3
   }
-  const double sg = g[0] + g[1] + g[2];
-  const double rs = rcp(sg);
+  const double rs = rcp_w(g[0] + g[1] + g[2]);
   const double N = g[0] * p[0] + g[1] * p[1] + g[2] * p[2];
-  // out = N / sg
+  // out = N / sum g
   const double Nb = ob * rs;
-  const double sgb = -ob * N * rs * rs;
-  double pb[3], ab_[3], Db[3] = {0.0, 0.0, 0.0};
+  const double sgb = -(Nb * N) * rs;
+  double pb[3], cb[3];
   double rb = 0.0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     pb[k] = Nb * g[k];
-    const double gb = Nb * p[k] + sgb;
-    const double wb = ppm ? gb * 3.0 * (dw[k] * h[k]) : gb;  // dg/dw = 3 K d^2
-    ab_[k] = wb * r;
-    rb += wb * al[k];
+    const double gb = fma(Nb, p[k], sgb);
+    const double wb = ppm ? gb * (3.0 * (dw[k] * h[k])) : gb;  // dg/dw = 3 K d^2
+    cb[k] = wb * r;
+    rb = fma(wb, al[k], rb);
   }
-  const double Sb = -rb * r * r;
+  const double Sb = -(rb * r) * r;
+  // adjoints of alpha_k times C_k, then of D_l
 #pragma unroll
-  for (int k = 0; k < 3; ++k) ab_[k] += Sb;
-  Db[0] = ab_[1] * C[1] * D[2] + ab_[2] * C[2] * D[1];
-  Db[1] = ab_[0] * C[0] * D[2] + ab_[2] * C[2] * D[0];
-  Db[2] = ab_[0] * C[0] * D[1] + ab_[1] * C[1] * D[0];
+  for (int k = 0; k < 3; ++k) cb[k] = (cb[k] + Sb) * C[k];
+  const double Db[3] = {fma(cb[1], D[2], cb[2] * D[1]), fma(cb[0], D[2], cb[2] * D[0]),
+                        fma(cb[0], D[1], cb[1] * D[0])};
   double tb[3], sb[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double Ib = 2.0 * E[k] * Db[k];
-    tb[k] = Ib * (13.0 / 6.0) * t[k];
-    sb[k] = Ib * 0.5 * s[k];
+    const double q = E[k] * Db[k];  // dIS = 2 E dD
+    tb[k] = (13.0 / 3.0) * q * t[k];
+    sb[k] = q * s[k];
   }
   const double d1b = -tb[0] - sb[0];
   const double d2b = tb[0] - tb[1] + 3.0 * sb[0] - sb[1];

@@ -93,11 +93,12 @@ WIU_DEV void weno3_vjp(double a, double b, double d, double eps, int ppm, double
   double E[2], D[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    E[k] = eps + fma(13.0 / 12.0, t[k] * t[k], 0.25 * (s[k] * s[k]));
+    const double u = 0.5 * s[k];
+    E[k] = fma(13.0 / 12.0, t[k] * t[k], fma(u, u, eps));
     D[k] = E[k] * E[k];
   }
   const double al[2] = {C[0] * D[1], C[1] * D[0]};
-  const double r = rcp(al[0] + al[1]);
+  const double r = rcp_w(al[0] + al[1]);
   double w[2], g[2], h[2], dw[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -106,30 +107,26 @@ WIU_DEV void weno3_vjp(double a, double b, double d, double eps, int ppm, double
     h[k] = kd(dw[k], KL[k], KH[k]);  // K d, as the forward sweep forms it
     g[k] = ppm ? fma(dw[k], h[k] - 1.0, w[k]) : w[k];  // C + K d^2
   }
-  const double sg = g[0] + g[1];
-  const double rs = rcp(sg);
+  const double rs = rcp_w(g[0] + g[1]);
   const double N = g[0] * p[0] + g[1] * p[1];
+  // out = N / sum g
   const double Nb = ob * rs;
-  const double sgb = -ob * N * rs * rs;
-  double pb[2], ab_[2], rb = 0.0;
+  const double sgb = -(Nb * N) * rs;
+  double pb[2], cb[2], rb = 0.0;
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     pb[k] = Nb * g[k];
-    const double gb = Nb * p[k] + sgb;
-    const double wb = ppm ? gb * 2.0 * h[k] : gb;  // dg/dw = 2 K d
-    ab_[k] = wb * r;
-    rb += wb * al[k];
+    const double gb = fma(Nb, p[k], sgb);
+    const double wb = ppm ? gb * (2.0 * h[k]) : gb;  // dg/dw = 2 K d
+    cb[k] = wb * r;
+    rb = fma(wb, al[k], rb);
   }
-  const double Sb = -rb * r * r;
-  ab_[0] += Sb;
-  ab_[1] += Sb;
-  const double Db0 = ab_[1] * C[1], Db1 = ab_[0] * C[0];
+  const double Sb = -(rb * r) * r;
+  // alpha_0 = C_0 D_1, alpha_1 = C_1 D_0; dIS = 2 E dD
+  const double q0 = E[0] * ((cb[1] + Sb) * C[1]), q1 = E[1] * ((cb[0] + Sb) * C[0]);
   double tb[2], sb[2];
-  {
-    const double Ib0 = 2.0 * E[0] * Db0, Ib1 = 2.0 * E[1] * Db1;
-    tb[0] = Ib0 * (13.0 / 6.0) * t[0]; sb[0] = Ib0 * 0.5 * s[0];
-    tb[1] = Ib1 * (13.0 / 6.0) * t[1]; sb[1] = Ib1 * 0.5 * s[1];
-  }
+  tb[0] = (13.0 / 3.0) * q0 * t[0]; sb[0] = q0 * s[0];
+  tb[1] = (13.0 / 3.0) * q1 * t[1]; sb[1] = q1 * s[1];
   const double d1b = -tb[0] - sb[0];
   const double d2b = tb[0] - tb[1] + 3.0 * sb[0] - sb[1];
   const double d3b = tb[1] - sb[1];
